@@ -1,0 +1,211 @@
+/*
+ * isdf.h - C ABI of the MI355X multigrid-ISDF exchange library.
+ *
+ * Method: Smyser, White, Sharma, "Use of multigrids to reduce the cost of
+ * performing interpolative separable density fitting" (arXiv 2404.09373).
+ *
+ *   isdf_plan      geometry -> grid levels, atom-centred windows and the
+ *                  local / global / non-local function sets
+ *                  (section "Computational details", Eqs. rcut, Ggrid and
+ *                  "mg product density")
+ *   isdf_fit       per domain: basis values, pair-density Gram (Eq. M(R,R)),
+ *                  pivoted-Cholesky interpolation points, least-squares
+ *                  fitting functions (Eq. lsqr); then the Coulomb metric
+ *                  (xi|xi') by FFT Poisson solves (Eq. (xi|xi'))
+ *   isdf_exchange  the four-term THC exchange matrix (Eq. ints) and
+ *                  E_x = tr(D K), once per SCF iteration
+ *
+ * Conventions
+ *   Units: Bohr and Hartree.  Basis functions are ordered atom-major as the
+ *   shells are given, p components x, y, z.  Matrices crossing the ABI are
+ *   dense FP64; N x N matrices (D, K) are symmetric so row- and column-major
+ *   coincide.  Grid points are flat indices i1 + n1 (i2 + n2 i3) of the level
+ *   grid.  Domain order: the universal level-0 domain first, then one window
+ *   per atom for level 1, level 2, ...; interpolation points xi are ordered
+ *   by domain, then by selection order.
+ *
+ *   Ownership: every array passed in is caller-owned and only read during
+ *   the call (isdf_plan copies what it needs).  Handles are library-owned;
+ *   destroy fits before their plan.  Device pointers (D, K) must be
+ *   allocations on the current HIP device; the library never frees them.
+ *
+ *   Streams and errors: all device work is ordered on options.stream (a
+ *   hipStream_t, NULL for the default stream).  No call throws.  Argument
+ *   errors are returned synchronously; errors raised by kernels surface at
+ *   the next call that synchronises (isdf_fit, isdf_exchange, isdf_sync and
+ *   the copy-out calls all synchronise).  isdf_last_error() gives a message
+ *   for the last non-OK status of the calling thread.
+ *
+ *   Threading: a plan and its fits must not be used from two threads at once.
+ */
+#ifndef ISDF_H
+#define ISDF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  ISDF_OK = 0,
+  ISDF_E_ARG = -1,         /* bad argument (null, NaN, out of range)            */
+  ISDF_E_NOMEM = -2,       /* device or host allocation failed                  */
+  ISDF_E_HIP = -3,         /* HIP runtime or kernel error                       */
+  ISDF_E_NOT_SPD = -4,     /* interpolation metric not positive definite        */
+  ISDF_E_RANK = -5,        /* fewer independent points than requested           */
+  ISDF_E_STATE = -6,       /* handle used in the wrong state                    */
+  ISDF_E_UNSUPPORTED = -7  /* grid or shell outside what the kernels support    */
+} isdf_status;
+
+typedef struct isdf_plan_s* isdf_plan_t; /* opaque, library-owned */
+typedef struct isdf_fit_s* isdf_fit_t;   /* opaque, library-owned */
+
+/* Precision of the fit / exchange contractions. */
+enum { ISDF_FP64 = 0, ISDF_MIXED_X3 = 1, ISDF_MIXED_X6 = 2 };
+/* Candidate selection before pivoted Cholesky. */
+enum { ISDF_SEL_FULL = 0, ISDF_SEL_MLP = 1 };
+
+/* System description (section "Computational details"; the thresholds of
+ * its threshold table).  All pointers are host pointers, read only. */
+typedef struct {
+  double lattice[9];          /* rows a1, a2, a3 (Bohr)                                  */
+  int32_t n_atoms;
+  const double* xyz;          /* [n_atoms][3] Cartesian positions (Bohr)                 */
+  int32_t n_shells;
+  const int32_t* shell_atom;  /* [n_shells] atom of each shell, atom-major order         */
+  const int32_t* shell_l;     /* [n_shells] 0 (s) or 1 (p); uncontracted, normalised     */
+  const double* shell_alpha;  /* [n_shells] exponent (Bohr^-2)                           */
+  int32_t n_levels;           /* 1..8                                                     */
+  const int32_t* grid;        /* [n_levels][3] points per axis, coarse -> fine, each axis
+                                 2^a 3^b 5^c and at most 256                               */
+  const double* alpha_bound;  /* [n_levels-1] a shell lives on the coarsest level l with
+                                 alpha < alpha_bound[l], else on the finest               */
+  double image_tol;           /* periodic-image cutoff tau (e.g. 1e-10)                  */
+  double eps_r;               /* window accuracy of Eq. rcut (e.g. 1e-5)                 */
+  double n_mu_ratio;          /* points per owned function; <= 0: threshold only         */
+  double eps_isdf;            /* relative stop of the pivoted Cholesky (e.g. 1e-14)      */
+  double tie_tol;             /* relative tie window of the pivot argmax (e.g. 1e-8)     */
+} isdf_system;
+
+typedef struct {
+  int32_t precision;          /* ISDF_FP64 (default) or a mixed mode                     */
+  int32_t selector;           /* ISDF_SEL_FULL (default) or ISDF_SEL_MLP                 */
+  double mlp_keep;            /* MLP: keep ceil(mlp_keep * n_mu_d) candidates per domain */
+  const float* mlp_weights;   /* MLP: host array of ISDF_MLP_NPARAM floats, copied       */
+  void* stream;               /* hipStream_t or NULL                                      */
+  int32_t w_batch;            /* fitting functions per Poisson batch (0: automatic)      */
+  int32_t reserved[7];
+} isdf_options;
+
+/* Build the multigrid plan (host only, no device work).
+ * Reads sys and opts; on success *out owns copies of everything it needs.
+ * Errors: ISDF_E_ARG for null pointers, non-positive grids, NaN exponents;
+ * ISDF_E_UNSUPPORTED for grids that are not 2,3,5-smooth, axes above 256,
+ * levels that are not strictly finer, or l > 1. */
+isdf_status isdf_plan(const isdf_system* sys, const isdf_options* opts, isdf_plan_t* out);
+
+/* Sizes: number of basis functions N, total requested points N_mu, domains. */
+isdf_status isdf_plan_info(isdf_plan_t plan, int64_t* n_basis, int64_t* n_mu, int32_t* n_domains);
+
+/* Domain d: level, centre atom (-1 for the universal domain), point count,
+ * |L|, |N| and requested point count n_mu_d. */
+isdf_status isdf_plan_domain(isdf_plan_t plan, int32_t d, int32_t* level, int32_t* atom,
+                             int64_t* n_points, int32_t* n_L, int32_t* n_N, int32_t* n_mu);
+
+/* Copy domain d's flat grid indices (ascending, n_points entries) and its
+ * function indices (n_L local then n_N non-local, basis order) to host
+ * arrays of the stated sizes. */
+isdf_status isdf_plan_domain_points(isdf_plan_t plan, int32_t d, int64_t* points);
+isdf_status isdf_plan_domain_functions(isdf_plan_t plan, int32_t d, int32_t* functions);
+
+/* Fit (interpolative decomposition + Coulomb metric), once per geometry
+ * (section "Using multiple grids for exchange", item 1).  Allocates the
+ * fit's device buffers, runs every stage on the plan's stream and
+ * synchronises.  Errors: ISDF_E_NOMEM, ISDF_E_HIP, ISDF_E_NOT_SPD (a local
+ * interpolation metric failed its Cholesky), ISDF_E_RANK (a domain stopped
+ * early by eps_isdf while n_mu_ratio > 0; the fit is still usable). */
+isdf_status isdf_fit(isdf_plan_t plan, isdf_fit_t* out);
+
+/* Same with the points of every domain given instead of selected:
+ * local_points holds, domain after domain, n_mu_d local point indices
+ * (positions in the domain's point list).  Duplicate points make the
+ * metric singular and return ISDF_E_NOT_SPD. */
+isdf_status isdf_fit_with_points(isdf_plan_t plan, const int64_t* local_points, isdf_fit_t* out);
+
+/* Exchange build, once per SCF iteration (Eq. ints):
+ *   K = -[X^L'((X^G D X^G') o W)X^L + X^L'((X^G D X^L') o W)X^N
+ *         + X^N'((X^L D X^G') o W)X^L + X^N'((X^L D X^L') o W)X^N],
+ *   e_x = tr(D K).
+ * D_dev, K_dev: device pointers to N x N FP64 (D symmetric, per spin).
+ * e_x: host pointer or NULL.  Synchronises the stream.
+ * Errors: ISDF_E_ARG (null D/K, NaN found in D), ISDF_E_STATE (fit not from
+ * this plan), ISDF_E_HIP. */
+isdf_status isdf_exchange(isdf_plan_t plan, isdf_fit_t fit, const double* D_dev, double* K_dev,
+                          double* e_x);
+
+/* Stage outputs for checks, copied to host (synchronises).
+ *   ISDF_FIELD_PHI    domain d: basis values, n_points x (n_L + n_N), column-major
+ *   ISDF_FIELD_DIAG   domain d: Gram diagonal, n_points
+ *   ISDF_FIELD_POINTS domain d: chosen local point indices (int64), count from COUNT
+ *   ISDF_FIELD_COUNT  all: chosen point count per domain (int64, n_domains)
+ *   ISDF_FIELD_THETA  domain d: Theta = M(P_d, xi), n_points x n, column-major
+ *   ISDF_FIELD_F      domain d: fitting functions, n_points x n, column-major
+ *   ISDF_FIELD_XL / ISDF_FIELD_XN  all: N_mu x N column-major
+ *   ISDF_FIELD_W      all: N_mu x N_mu column-major (symmetric)
+ * `bytes` must equal the size of the field or ISDF_E_ARG is returned. */
+enum {
+  ISDF_FIELD_PHI = 0, ISDF_FIELD_DIAG = 1, ISDF_FIELD_POINTS = 2, ISDF_FIELD_COUNT = 3,
+  ISDF_FIELD_THETA = 4, ISDF_FIELD_F = 5, ISDF_FIELD_XL = 6, ISDF_FIELD_XN = 7, ISDF_FIELD_W = 8
+};
+isdf_status isdf_fit_get(isdf_fit_t fit, int32_t field, int32_t d, void* host_out, size_t bytes);
+
+/* Total fitted points (after any early stop). */
+isdf_status isdf_fit_info(isdf_fit_t fit, int64_t* n_mu);
+
+/* Per-stage device times of the last isdf_fit / isdf_exchange (ms), measured
+ * with HIP events on the plan's stream:
+ *   t[0] basis+diag, t[1] selection, t[2] gather X, t[3] Theta GEMM,
+ *   t[4] Cholesky + triangular solves, t[5] Coulomb metric (FFT + GEMM),
+ *   t[6] exchange total, t[7] exchange GEMM part. */
+isdf_status isdf_stage_times(isdf_plan_t plan, double* t_ms, int32_t n);
+
+/* Per-kernel instrumentation.  isdf_profile(plan, 1) resets the counters
+ * and brackets every launch of the kernel families below with HIP events on
+ * the plan's stream (0 turns it off).  isdf_kernel_stats returns, for one
+ * family, the summed device time (ms), the launch count and the algorithmic
+ * HBM bytes and flops of those launches (what the method must move or
+ * compute: basis columns, factor columns and residuals for the selection
+ * column kernel; 2 M N K per GEMM).
+ *   ISDF_K_SELECT_COLUMN  pivoted-Cholesky column + residual update
+ *   ISDF_K_SELECT_PICK    tie-rule pivot pick
+ *   ISDF_K_GEMM_FIT       Theta, Cholesky/solve and W products
+ *   ISDF_K_GEMM_EXCHANGE  exchange products (Eq. ints)
+ *   ISDF_K_FFT            FFT passes of the Poisson solves
+ *   ISDF_K_BASIS          basis values + Gram diagonal */
+enum {
+  ISDF_K_SELECT_COLUMN = 0, ISDF_K_SELECT_PICK = 1, ISDF_K_GEMM_FIT = 2,
+  ISDF_K_GEMM_EXCHANGE = 3, ISDF_K_FFT = 4, ISDF_K_BASIS = 5, ISDF_K_NFAMILY = 6
+};
+isdf_status isdf_profile(isdf_plan_t plan, int32_t enable);
+isdf_status isdf_kernel_stats(isdf_plan_t plan, int32_t family, double* ms, int64_t* launches,
+                              double* bytes, double* flops);
+
+/* Wait for the plan's stream; report deferred device errors. */
+isdf_status isdf_sync(isdf_plan_t plan);
+
+void isdf_fit_destroy(isdf_fit_t fit);
+void isdf_plan_destroy(isdf_plan_t plan);
+
+/* Message for the last non-OK status on this thread (never NULL). */
+const char* isdf_last_error(void);
+
+/* Library version string. */
+const char* isdf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ISDF_H */

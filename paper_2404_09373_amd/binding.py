@@ -1,0 +1,288 @@
+"""ctypes binding of include/isdf.h (argument marshalling only).
+
+Every step of the fit and of the exchange build runs inside libisdf.so; this
+module converts NumPy/torch arguments into the C structs and pointers the
+library expects.  torch is used only for device buffers and the stream.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libisdf.so")
+
+ISDF_OK = 0
+STATUS = {
+    0: "ISDF_OK", -1: "ISDF_E_ARG", -2: "ISDF_E_NOMEM", -3: "ISDF_E_HIP",
+    -4: "ISDF_E_NOT_SPD", -5: "ISDF_E_RANK", -6: "ISDF_E_STATE", -7: "ISDF_E_UNSUPPORTED",
+}
+FIELD = {"phi": 0, "diag": 1, "points": 2, "count": 3, "theta": 4, "F": 5, "XL": 6, "XN": 7, "W": 8}
+FP64, MIXED_X3, MIXED_X6 = 0, 1, 2
+SEL_FULL, SEL_MLP = 0, 1
+
+EXPORTED = [
+    "isdf_plan", "isdf_plan_info", "isdf_plan_domain", "isdf_plan_domain_points",
+    "isdf_plan_domain_functions", "isdf_fit", "isdf_fit_with_points", "isdf_exchange",
+    "isdf_fit_get", "isdf_fit_info", "isdf_stage_times", "isdf_sync", "isdf_fit_destroy",
+    "isdf_plan_destroy", "isdf_last_error", "isdf_version",
+]
+
+
+class IsdfError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class _System(C.Structure):
+    _fields_ = [
+        ("lattice", C.c_double * 9),
+        ("n_atoms", C.c_int32),
+        ("xyz", C.POINTER(C.c_double)),
+        ("n_shells", C.c_int32),
+        ("shell_atom", C.POINTER(C.c_int32)),
+        ("shell_l", C.POINTER(C.c_int32)),
+        ("shell_alpha", C.POINTER(C.c_double)),
+        ("n_levels", C.c_int32),
+        ("grid", C.POINTER(C.c_int32)),
+        ("alpha_bound", C.POINTER(C.c_double)),
+        ("image_tol", C.c_double),
+        ("eps_r", C.c_double),
+        ("n_mu_ratio", C.c_double),
+        ("eps_isdf", C.c_double),
+        ("tie_tol", C.c_double),
+    ]
+
+
+class _Options(C.Structure):
+    _fields_ = [
+        ("precision", C.c_int32),
+        ("selector", C.c_int32),
+        ("mlp_keep", C.c_double),
+        ("mlp_weights", C.POINTER(C.c_float)),
+        ("stream", C.c_void_p),
+        ("w_batch", C.c_int32),
+        ("reserved", C.c_int32 * 7),
+    ]
+
+
+_lib = None
+
+
+def load(required: bool = True):
+    """Load libisdf.so from the package directory (never builds it)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        if required:
+            raise RuntimeError(
+                f"{LIB_PATH} is missing: build the HIP library first (__graft_entry__.build())"
+            )
+        return None
+    lib = C.CDLL(LIB_PATH)
+    vp = C.c_void_p
+    lib.isdf_plan.argtypes = [C.POINTER(_System), C.POINTER(_Options), C.POINTER(vp)]
+    lib.isdf_plan_info.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int32)]
+    lib.isdf_plan_domain.argtypes = [vp, C.c_int32] + [C.POINTER(C.c_int32)] * 2 + [C.POINTER(C.c_int64)] + [C.POINTER(C.c_int32)] * 3
+    lib.isdf_plan_domain_points.argtypes = [vp, C.c_int32, C.POINTER(C.c_int64)]
+    lib.isdf_plan_domain_functions.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32)]
+    lib.isdf_fit.argtypes = [vp, C.POINTER(vp)]
+    lib.isdf_fit_with_points.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(vp)]
+    lib.isdf_exchange.argtypes = [vp, vp, vp, vp, C.POINTER(C.c_double)]
+    lib.isdf_fit_get.argtypes = [vp, C.c_int32, C.c_int32, vp, C.c_size_t]
+    lib.isdf_fit_info.argtypes = [vp, C.POINTER(C.c_int64)]
+    lib.isdf_stage_times.argtypes = [vp, C.POINTER(C.c_double), C.c_int32]
+    lib.isdf_sync.argtypes = [vp]
+    lib.isdf_fit_destroy.argtypes = [vp]
+    lib.isdf_fit_destroy.restype = None
+    lib.isdf_plan_destroy.argtypes = [vp]
+    lib.isdf_plan_destroy.restype = None
+    lib.isdf_last_error.restype = C.c_char_p
+    lib.isdf_version.restype = C.c_char_p
+    for name in EXPORTED:
+        f = getattr(lib, name)
+        if f.restype is None and name not in ("isdf_fit_destroy", "isdf_plan_destroy"):
+            pass
+    for name in ("isdf_plan", "isdf_plan_info", "isdf_plan_domain", "isdf_plan_domain_points",
+                 "isdf_plan_domain_functions", "isdf_fit", "isdf_fit_with_points",
+                 "isdf_exchange", "isdf_fit_get", "isdf_fit_info", "isdf_stage_times", "isdf_sync"):
+        getattr(lib, name).restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def _check(st: int, what: str, allow=()):
+    if st != ISDF_OK and st not in allow:
+        raise IsdfError(st, f"{what}: {load().isdf_last_error().decode()}")
+    return st
+
+
+def _ptr(a: np.ndarray, ctype):
+    return a.ctypes.data_as(C.POINTER(ctype))
+
+
+class Plan:
+    """A multigrid-ISDF plan for one system (see include/isdf.h)."""
+
+    def __init__(self, sysm, precision: int = FP64, selector: int = SEL_FULL, stream=None,
+                 w_batch: int = 0):
+        lib = load()
+        self._keep = []
+        s = _System()
+        for i, v in enumerate(np.asarray(sysm.lattice, dtype=np.float64).ravel()):
+            s.lattice[i] = float(v)
+        xyz = np.ascontiguousarray(sysm.xyz, dtype=np.float64)
+        sa = np.ascontiguousarray(sysm.shell_atom, dtype=np.int32)
+        sl = np.ascontiguousarray(sysm.shell_l, dtype=np.int32)
+        sal = np.ascontiguousarray(sysm.shell_alpha, dtype=np.float64)
+        grid = np.ascontiguousarray(sysm.grids, dtype=np.int32)
+        ab = np.ascontiguousarray(np.asarray(sysm.alpha_bound, dtype=np.float64).reshape(-1))
+        if ab.size == 0:
+            ab = np.zeros(1)
+        self._keep += [xyz, sa, sl, sal, grid, ab]
+        s.n_atoms = xyz.shape[0]
+        s.xyz = _ptr(xyz, C.c_double)
+        s.n_shells = sa.size
+        s.shell_atom = _ptr(sa, C.c_int32)
+        s.shell_l = _ptr(sl, C.c_int32)
+        s.shell_alpha = _ptr(sal, C.c_double)
+        s.n_levels = grid.shape[0]
+        s.grid = _ptr(grid, C.c_int32)
+        s.alpha_bound = _ptr(ab, C.c_double)
+        s.image_tol = float(sysm.image_tol)
+        s.eps_r = float(sysm.eps_r)
+        s.n_mu_ratio = float(sysm.n_mu_ratio)
+        s.eps_isdf = float(sysm.eps_isdf)
+        s.tie_tol = float(sysm.tie_tol)
+        o = _Options()
+        o.precision = precision
+        o.selector = selector
+        o.stream = C.c_void_p(stream) if stream else None
+        o.w_batch = w_batch
+        h = C.c_void_p()
+        _check(lib.isdf_plan(C.byref(s), C.byref(o), C.byref(h)), "isdf_plan")
+        self.handle = h
+        n_basis, n_mu, nd = C.c_int64(), C.c_int64(), C.c_int32()
+        _check(lib.isdf_plan_info(h, C.byref(n_basis), C.byref(n_mu), C.byref(nd)), "isdf_plan_info")
+        self.n_basis, self.n_mu, self.n_domains = n_basis.value, n_mu.value, nd.value
+
+    def domain(self, d: int) -> dict:
+        lib = load()
+        lev, atom, nL, nN, nmu = (C.c_int32() for _ in range(5))
+        npts = C.c_int64()
+        _check(lib.isdf_plan_domain(self.handle, d, C.byref(lev), C.byref(atom), C.byref(npts),
+                                    C.byref(nL), C.byref(nN), C.byref(nmu)), "isdf_plan_domain")
+        pts = np.zeros(npts.value, dtype=np.int64)
+        funcs = np.zeros(nL.value + nN.value, dtype=np.int32)
+        _check(lib.isdf_plan_domain_points(self.handle, d, _ptr(pts, C.c_int64)), "points")
+        _check(lib.isdf_plan_domain_functions(self.handle, d, _ptr(funcs, C.c_int32)), "functions")
+        return dict(level=lev.value, atom=atom.value, points=pts, nL=nL.value, nN=nN.value,
+                    n_mu=nmu.value, funcs=funcs)
+
+    def fit(self, points=None, allow_rank=True) -> "Fit":
+        lib = load()
+        h = C.c_void_p()
+        allow = (-5,) if allow_rank else ()
+        if points is None:
+            st = lib.isdf_fit(self.handle, C.byref(h))
+        else:
+            flat = np.ascontiguousarray(np.concatenate([np.asarray(p, dtype=np.int64) for p in points]))
+            st = lib.isdf_fit_with_points(self.handle, _ptr(flat, C.c_int64), C.byref(h))
+        if h.value:
+            fit = Fit(self, h)
+            _check(st, "isdf_fit", allow)
+            fit.status = st
+            return fit
+        _check(st, "isdf_fit")
+        raise IsdfError(-3, "isdf_fit returned no handle")
+
+    def stage_times(self) -> np.ndarray:
+        t = np.zeros(8)
+        _check(load().isdf_stage_times(self.handle, _ptr(t, C.c_double), 8), "isdf_stage_times")
+        return t
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            load().isdf_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Fit:
+    def __init__(self, plan: Plan, handle):
+        self.plan = plan
+        self.handle = handle
+        n = C.c_int64()
+        _check(load().isdf_fit_info(handle, C.byref(n)), "isdf_fit_info")
+        self.n_mu = n.value
+        self.status = 0
+
+    def counts(self) -> np.ndarray:
+        out = np.zeros(self.plan.n_domains, dtype=np.int64)
+        self._get("count", 0, out)
+        return out
+
+    def _get(self, field: str, d: int, out: np.ndarray):
+        _check(load().isdf_fit_get(self.handle, FIELD[field], d, out.ctypes.data_as(C.c_void_p),
+                                   out.nbytes), f"isdf_fit_get({field})")
+        return out
+
+    def get(self, field: str, d: int = 0) -> np.ndarray:
+        """Copy a stage output to the host (column-major arrays are returned as
+        (rows, cols) NumPy arrays)."""
+        p = self.plan
+        if field in ("XL", "XN"):
+            return self._get(field, 0, np.zeros((p.n_basis, self.n_mu))).T
+        if field == "W":
+            return self._get(field, 0, np.zeros((self.n_mu, self.n_mu))).T
+        if field == "count":
+            return self.counts()
+        dom = p.domain(d)
+        npts = dom["points"].size
+        cnt = int(self.counts()[d])
+        if field == "phi":
+            return self._get(field, d, np.zeros((dom["nL"] + dom["nN"], npts))).T
+        if field == "diag":
+            return self._get(field, d, np.zeros(npts))
+        if field == "points":
+            return self._get(field, d, np.zeros(cnt, dtype=np.int64))
+        if field in ("theta", "F"):
+            return self._get(field, d, np.zeros((cnt, npts))).T
+        raise KeyError(field)
+
+    def exchange(self, D, K=None):
+        """K and E_x for a density D (torch CUDA tensors; K allocated if None).
+        Returns (K, e_x)."""
+        import torch
+
+        if not isinstance(D, torch.Tensor) or not D.is_cuda or D.dtype != torch.float64:
+            raise TypeError("D must be a float64 CUDA tensor")
+        D = D.contiguous()
+        n = self.plan.n_basis
+        if K is None:
+            K = torch.empty((n, n), dtype=torch.float64, device=D.device)
+        ex = C.c_double()
+        _check(load().isdf_exchange(self.plan.handle, self.handle, C.c_void_p(D.data_ptr()),
+                                    C.c_void_p(K.data_ptr()), C.byref(ex)), "isdf_exchange")
+        return K, ex.value
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            load().isdf_fit_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

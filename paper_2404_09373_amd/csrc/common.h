@@ -1,0 +1,212 @@
+// Internal declarations shared by the host runtime and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/isdf.h"
+
+namespace isdf {
+
+// ------------------------------------------------------------------ errors
+void set_error(const std::string& msg);
+#define ISDF_HIP_TRY(expr)                                                        \
+  do {                                                                            \
+    hipError_t _e = (expr);                                                       \
+    if (_e != hipSuccess) {                                                       \
+      ::isdf::set_error(std::string(#expr) + ": " + hipGetErrorString(_e));       \
+      return _e == hipErrorOutOfMemory ? ISDF_E_NOMEM : ISDF_E_HIP;               \
+    }                                                                             \
+  } while (0)
+
+// ------------------------------------------------------------ host plan
+struct HostDomain {
+  int level = 0;
+  int atom = -1;                 // -1: universal domain
+  std::vector<int32_t> points;   // ascending flat grid indices
+  std::vector<int32_t> funcs;    // L then N, basis order
+  int nL = 0, nN = 0, n_mu = 0;
+  double r_max = 0.0;
+};
+
+struct ShellDev {                // one periodic shell as the basis kernel sees it
+  double alpha;
+  double norm;
+  int32_t l;
+  int32_t img_off;
+  int32_t img_cnt;
+  int32_t pad;
+};
+
+struct ColShell {                // a shell occupying columns [col, col + ncomp) of a domain
+  int32_t shell;
+  int32_t col;
+};
+
+struct HostPlan {
+  double lattice[9];             // rows a_i
+  double inv[9];                 // inverse lattice, frac = r @ inv
+  double volume;
+  double ln_inv_tau;
+  int n_atoms = 0;
+  std::vector<double> xyz;
+  int n_shells = 0;
+  std::vector<int32_t> shell_atom, shell_l, shell_level;
+  std::vector<double> shell_alpha;
+  std::vector<int32_t> img_off, img_cnt;
+  std::vector<double> img_xyz;   // image centres A + T
+  int n_basis = 0;
+  std::vector<int32_t> f_shell, f_atom, f_comp, f_level;
+  int n_levels = 0;
+  int grid[8][3];
+  std::vector<double> alpha_bound;
+  double eps_r, n_mu_ratio, eps_isdf, tie_tol;
+  std::vector<HostDomain> domains;
+  int64_t n_mu_total = 0;
+};
+
+// Builds the plan on the host (validates the system).  Returns ISDF_OK or an
+// error status with set_error() called.
+isdf_status build_host_plan(const isdf_system* sys, HostPlan& hp);
+
+// -------------------------------------------------------------- GEMM engine
+// Column-major FP64 GEMM problem:  C(m,n) = epi( sum_k opA(m,k) opB(k,n) ).
+//   opA(m,k) = transA ? A[k + m*lda] : A[m + k*lda]
+//   opB(k,n) = transB ? B[n + k*ldb] : B[(bidx ? bidx[k] : k) + n*ldb]
+// Epilogues: EPI_AXPBY  C = alpha*acc + beta*C
+//            EPI_THETA  acc split at k = kL: C = aL*(aL + 2*aN)
+//            EPI_HADAMARD C = alpha*acc*E(m,n) (+ beta*C)
+enum { EPI_AXPBY = 0, EPI_THETA = 1, EPI_HADAMARD = 2 };
+struct GemmProblem {
+  const double* A;
+  const double* B;
+  double* C;
+  const double* E;
+  const int32_t* bidx;
+  int64_t lda, ldb, ldc, lde;
+  int32_t M, N, K, kL;
+  int32_t transA, transB;
+  double alpha, beta;
+  int32_t tile_start;            // first flat tile of this problem in a grouped launch
+  int32_t pad;
+};
+
+// Launch one problem or a group (device array of problems, tile_start
+// filled by the caller, total_tiles = sum of tiles).
+isdf_status gemm_f64(hipStream_t s, int epi, const GemmProblem& p);
+isdf_status gemm_f64_grouped(hipStream_t s, int epi, const GemmProblem* d_probs, int nprob,
+                             int total_tiles);
+int gemm_tiles(int M, int N);
+
+// ------------------------------------------------------------ other kernels
+struct BasisTile {
+  int32_t domain;
+  int32_t start;
+};
+struct DomainDev {
+  int64_t pts_off;               // into the points pool
+  int64_t phi_off;               // into the Phi pool (pts x nG, column-major)
+  int64_t diag_off;              // into the diag pool
+  int32_t pts, nG, nL, n_mu;
+  int32_t colshell_off, colshell_cnt;
+  int32_t level;
+  int32_t pad;
+};
+struct LatticeArg {
+  double a[9];
+  double ln_inv_tau;
+  int32_t grid[8][3];
+};
+isdf_status launch_basis_eval(hipStream_t s, const LatticeArg& lat, const ShellDev* shells,
+                              const double* img, const ColShell* colshells,
+                              const DomainDev* doms, const int32_t* points,
+                              const BasisTile* tiles, int ntiles, double* phi, double* diag);
+
+// Selection (pivoted Cholesky) over a batch of domains.
+struct SelDomain {
+  int64_t phi_off, lfac_off, diag_off, prow_off;
+  int32_t pts, nG, nL, n_mu;
+  int32_t tile_off, ntiles;
+  int32_t piv_off, pad;
+};
+struct SelState {
+  double d0max;
+  double dpiv;
+  int32_t cur;
+  int32_t done;
+  int32_t count;
+  int32_t pad;
+};
+constexpr int SEL_TILE = 64;
+isdf_status launch_sel_init(hipStream_t s, const SelDomain* doms, const int32_t* tile_dom,
+                            int tile_base, int ntiles, const double* diag, double* tmax,
+                            int32_t* tidx, double tau);
+isdf_status launch_sel_select(hipStream_t s, const SelDomain* doms, int dom_base, int ndom,
+                              int k, SelState* st, const double* phi, const double* lfac,
+                              double* diag, const double* tmax, const int32_t* tidx, double* prow,
+                              int32_t* piv, double tau, double eps);
+isdf_status launch_sel_column(hipStream_t s, const SelDomain* doms, const int32_t* tile_dom,
+                              int tile_base, int ntiles, int k, const SelState* st,
+                              const double* phi, double* lfac, double* diag, const double* prow,
+                              double* tmax, int32_t* tidx, double tau);
+
+// Gather of the pivot rows of Phi into per-domain X rows and the global
+// X^L / X^N (column-major N_mu x N).
+struct GatherDom {
+  int64_t phi_off;
+  int64_t xrow_off;              // into Xrows pool (count x nG, column-major nG x count)
+  int32_t pts, nG, nL, count;
+  int32_t xoff;                  // first global xi index
+  int32_t piv_off;
+  int32_t func_off;              // into the per-domain function list pool
+  int32_t pad;
+};
+isdf_status launch_gather_x(hipStream_t s, const GatherDom* doms, int ndom, int max_rows,
+                            const double* phi, const int32_t* piv, const int32_t* funcs,
+                            double* xrows, double* XL, double* XN, int64_t nmu);
+
+isdf_status launch_fill(hipStream_t s, double* p, int64_t n, double v);
+isdf_status launch_gather_square(hipStream_t s, const double* theta, int64_t pts, int n,
+                                 const int32_t* piv, double* M);
+// small domains (n <= 64): Cholesky of M = Theta[piv,:] and F = Theta M^-1 per row
+struct SmallFitDom {
+  int64_t theta_off;             // Theta and F share the layout (pts x n column-major)
+  int32_t pts, n, piv_off, row_tile_off;
+};
+isdf_status launch_small_fit(hipStream_t s, const SmallFitDom* doms, const int32_t* tile_dom,
+                             int ntiles, const double* theta, const int32_t* piv, double* F,
+                             int32_t* status, int nmax);
+// 64 x 64 diagonal-block Cholesky + inverse of the factor (blocked path)
+isdf_status launch_potrf_diag(hipStream_t s, double* M, int64_t ldm, double* Cf, int64_t ldc,
+                              double* inv, int w, int32_t* status);
+
+// FFT: batched 3D complex transforms, in place, sign -1 forward / +1 inverse
+// (unnormalised).  z holds `batch` complex arrays of n1 n2 n3 (x fastest).
+isdf_status fft3d(hipStream_t s, double* z, int batch, const int grid[3], int sign,
+                  const double** unused);
+// allocate the twiddle table of an axis length ahead of any stream work
+isdf_status fft_prepare(int n);
+// out[b] (grid gc, complex) = v(m) * zf[b](m) / Ng_fine for m in J_gc \ {0}, else 0;
+// B[i*3 + j] = component j of reciprocal vector b_i (a_i . b_j = 2 pi delta_ij)
+isdf_status launch_poisson_restrict(hipStream_t s, const double* zf, const int gf[3], double* zc,
+                                    const int gc[3], int batch, const double B[9]);
+// scatter domain columns into complex pair arrays: z[slot/2][2 pts[i] + slot%2] = src[i]
+struct ScatterCol {
+  const double* src;
+  const int32_t* pts;
+  int32_t n;
+  int32_t slot;
+};
+isdf_status launch_scatter_cols(hipStream_t s, const ScatterCol* cols, int ncols, int max_n,
+                                double* z, int64_t ng);
+// V[c][R] = component c%2 of z[c/2][R], c < ncols
+isdf_status launch_split_planar(hipStream_t s, const double* z, int64_t ng, int ncols, double* V);
+isdf_status launch_symmetrize_w(hipStream_t s, double* W, int64_t nmu, const int8_t* lev);
+isdf_status launch_add(hipStream_t s, const double* a, const double* b, double* c, int64_t n);
+isdf_status launch_trace_dot(hipStream_t s, const double* a, const double* b, int64_t n,
+                             double* partial, int nblk, double* out);
+
+}  // namespace isdf

@@ -1,0 +1,340 @@
+// Batched 3D complex FFTs and the FFT Poisson solve of the Coulomb metric
+// (Eq. (xi|xi'); "Computational details": one FFT per local fitting function,
+// potentials needed on the function's own and on every coarser grid).
+//
+// Transform: three passes of 1D transforms (x, y, z), each line held in LDS
+// and transformed by a Stockham autosort sequence of radix-4/2/3/5 stages.
+// Lines of one workgroup are neighbours along x, so every global access is a
+// run of consecutive complex values.  Two real fitting functions travel in
+// one complex array (re, im): the Coulomb kernel is real and even in m, so
+// the potentials come back as the real and imaginary parts.
+//
+// Poisson step: a spectrum on grid l' is multiplied by v(m) = 4 pi / |G_m|^2
+// on the band J_l = {|m_i| < n_l,i / 2} \ {0} of a grid l <= l' and written
+// into grid l's index space (zero elsewhere), ready for the inverse pass.
+#include <cmath>
+
+#include "common.h"
+
+namespace isdf {
+
+struct FftRadices {
+  int32_t n;
+  int32_t nrad;
+  int32_t r[12];
+};
+
+static FftRadices make_radices(int n) {
+  FftRadices f{};
+  f.n = n;
+  int m = n;
+  while (m % 4 == 0) { f.r[f.nrad++] = 4; m /= 4; }
+  while (m % 2 == 0) { f.r[f.nrad++] = 2; m /= 2; }
+  while (m % 3 == 0) { f.r[f.nrad++] = 3; m /= 3; }
+  while (m % 5 == 0) { f.r[f.nrad++] = 5; m /= 5; }
+  return f;
+}
+
+__device__ inline double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ inline double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ inline double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+// multiply by sign * i
+__device__ inline double2 mul_si(double2 a, double sign) { return make_double2(-sign * a.y, sign * a.x); }
+
+// one radix-R butterfly of a Stockham stage
+template <int R>
+__device__ inline void butterfly(const double2* src, double2* dst, int n, int j, int Ns,
+                                 const double2* tw, double sign) {
+  const int k = j % Ns;
+  const int stride_in = n / R;
+  double2 v[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) v[r] = src[j + r * stride_in];
+  const int step = n / (Ns * R);
+#pragma unroll
+  for (int r = 1; r < R; ++r) {
+    double2 w = tw[(r * k * step) % n];
+    if (sign > 0.0) w.y = -w.y;  // the table holds e^{-2 pi i t/n}
+    v[r] = cmul(v[r], w);
+  }
+  double2 y[R];
+  if (R == 2) {
+    y[0] = cadd(v[0], v[1]);
+    y[1] = csub(v[0], v[1]);
+  } else if (R == 4) {
+    const double2 a = cadd(v[0], v[2]), b = csub(v[0], v[2]);
+    const double2 c = cadd(v[1], v[3]), d = mul_si(csub(v[1], v[3]), sign);
+    y[0] = cadd(a, c);
+    y[2] = csub(a, c);
+    y[1] = cadd(b, d);
+    y[3] = csub(b, d);
+  } else if (R == 3) {
+    const double h = 0.86602540378443864676;  // sqrt(3)/2
+    const double2 s = cadd(v[1], v[2]);
+    const double2 d = mul_si(csub(v[1], v[2]), sign * h);
+    const double2 m = make_double2(v[0].x - 0.5 * s.x, v[0].y - 0.5 * s.y);
+    y[0] = cadd(v[0], s);
+    y[1] = cadd(m, d);
+    y[2] = csub(m, d);
+  } else if (R == 5) {
+    const double c1 = 0.30901699437494742410, c2 = -0.80901699437494742410;
+    const double s1 = 0.95105651629515357212, s2 = 0.58778525229247312917;
+    const double2 p1 = cadd(v[1], v[4]), m1 = csub(v[1], v[4]);
+    const double2 p2 = cadd(v[2], v[3]), m2 = csub(v[2], v[3]);
+    const double2 a1 = make_double2(v[0].x + c1 * p1.x + c2 * p2.x, v[0].y + c1 * p1.y + c2 * p2.y);
+    const double2 a2 = make_double2(v[0].x + c2 * p1.x + c1 * p2.x, v[0].y + c2 * p1.y + c1 * p2.y);
+    const double2 b1 = mul_si(make_double2(s1 * m1.x + s2 * m2.x, s1 * m1.y + s2 * m2.y), sign);
+    const double2 b2 = mul_si(make_double2(s2 * m1.x - s1 * m2.x, s2 * m1.y - s1 * m2.y), sign);
+    y[0] = make_double2(v[0].x + p1.x + p2.x, v[0].y + p1.y + p2.y);
+    y[1] = cadd(a1, b1);
+    y[4] = csub(a1, b1);
+    y[2] = cadd(a2, b2);
+    y[3] = csub(a2, b2);
+  }
+  const int idxD = (j / Ns) * Ns * R + k;
+#pragma unroll
+  for (int r = 0; r < R; ++r) dst[idxD + r * Ns] = y[r];
+}
+
+__global__ void __launch_bounds__(256)
+fft_pass_kernel(double2* __restrict__ z, int batch, int n1, int n2, int n3, int axis, double sign,
+                const double2* __restrict__ tw, FftRadices rad, int lpw) {
+  extern __shared__ double2 lds[];
+  const int n = rad.n;
+  double2* bufA = lds;
+  double2* bufB = lds + lpw * n;
+  const int64_t ng = (int64_t)n1 * n2 * n3;
+  const int tid = threadIdx.x;
+  const int g = blockIdx.x;
+  // element (j, i): line j of the group, position i along the axis
+  int64_t base;
+  int64_t estride;   // stride between positions along the axis
+  int64_t lstride;   // stride between lines of the group
+  int nlines_here = lpw;
+  if (axis == 0) {
+    const int64_t nl = (int64_t)n2 * n3 * batch;
+    const int64_t L0 = (int64_t)g * lpw;
+    if (L0 + lpw > nl) nlines_here = (int)(nl - L0);
+    base = L0 * n1;
+    estride = 1;
+    lstride = n1;
+  } else {
+    const int groups_x = n1 / lpw;
+    const int i10 = (g % groups_x) * lpw;
+    const int rest = g / groups_x;
+    if (axis == 1) {
+      const int i3 = rest % n3, b = rest / n3;
+      base = (int64_t)b * ng + i10 + (int64_t)n1 * n2 * i3;
+      estride = n1;
+    } else {
+      const int i2 = rest % n2, b = rest / n2;
+      base = (int64_t)b * ng + i10 + (int64_t)n1 * i2;
+      estride = (int64_t)n1 * n2;
+    }
+    lstride = 1;
+  }
+  const int tot = nlines_here * n;
+  if (axis == 0) {
+    for (int e = tid; e < tot; e += 256) bufA[e] = z[base + e];
+  } else {
+    for (int e = tid; e < tot; e += 256) {
+      const int j = e % lpw, i = e / lpw;
+      bufA[j * n + i] = z[base + j * lstride + i * estride];
+    }
+  }
+  __syncthreads();
+  double2* src = bufA;
+  double2* dst = bufB;
+  int Ns = 1;
+  for (int s = 0; s < rad.nrad; ++s) {
+    const int R = rad.r[s];
+    const int nb = n / R;
+    for (int u = tid; u < nlines_here * nb; u += 256) {
+      const int line = u / nb, j = u % nb;
+      const double2* sl = src + line * n;
+      double2* dl = dst + line * n;
+      if (R == 4) butterfly<4>(sl, dl, n, j, Ns, tw, sign);
+      else if (R == 2) butterfly<2>(sl, dl, n, j, Ns, tw, sign);
+      else if (R == 3) butterfly<3>(sl, dl, n, j, Ns, tw, sign);
+      else butterfly<5>(sl, dl, n, j, Ns, tw, sign);
+    }
+    __syncthreads();
+    double2* t = src;
+    src = dst;
+    dst = t;
+    Ns *= R;
+  }
+  if (axis == 0) {
+    for (int e = tid; e < tot; e += 256) z[base + e] = src[e];
+  } else {
+    for (int e = tid; e < tot; e += 256) {
+      const int j = e % lpw, i = e / lpw;
+      z[base + j * lstride + i * estride] = src[j * n + i];
+    }
+  }
+}
+
+// host twiddle tables e^{-2 pi i t / n}, cached per n
+struct TwCache {
+  int n = 0;
+  double2* dev = nullptr;
+};
+static TwCache g_tw[64];
+static int g_ntw = 0;
+
+static const double2* twiddles(int n) {
+  for (int i = 0; i < g_ntw; ++i)
+    if (g_tw[i].n == n) return g_tw[i].dev;
+  std::vector<double2> h(n);
+  for (int t = 0; t < n; ++t) {
+    long double ang = -2.0L * 3.141592653589793238462643383279502884L * (long double)t / n;
+    h[t] = make_double2((double)cosl(ang), (double)sinl(ang));
+  }
+  double2* d = nullptr;
+  if (hipMalloc(&d, sizeof(double2) * n) != hipSuccess) return nullptr;
+  if (hipMemcpy(d, h.data(), sizeof(double2) * n, hipMemcpyHostToDevice) != hipSuccess) return nullptr;
+  if (g_ntw < 64) g_tw[g_ntw++] = TwCache{n, d};
+  return d;
+}
+
+isdf_status fft_prepare(int n) {
+  if (!twiddles(n)) {
+    set_error("fft: twiddle allocation failed");
+    return ISDF_E_NOMEM;
+  }
+  return ISDF_OK;
+}
+
+isdf_status fft3d(hipStream_t s, double* zr, int batch, const int grid[3], int sign,
+                  const double** /*unused*/) {
+  double2* z = reinterpret_cast<double2*>(zr);
+  const int n1 = grid[0], n2 = grid[1], n3 = grid[2];
+  for (int axis = 0; axis < 3; ++axis) {
+    const int n = grid[axis];
+    if (n == 1) continue;
+    const double2* tw = twiddles(n);
+    if (!tw) {
+      set_error("fft: twiddle allocation failed");
+      return ISDF_E_NOMEM;
+    }
+    FftRadices rad = make_radices(n);
+    int lpw;
+    int64_t groups;
+    if (axis == 0) {
+      lpw = n <= 64 ? 16 : 8;
+      const int64_t nl = (int64_t)n2 * n3 * batch;
+      groups = (nl + lpw - 1) / lpw;
+    } else {
+      lpw = (n1 % 8 == 0) ? 8 : (n1 % 4 == 0) ? 4 : (n1 % 2 == 0) ? 2 : 1;
+      groups = (int64_t)(n1 / lpw) * (axis == 1 ? n3 : n2) * batch;
+    }
+    const size_t shmem = sizeof(double2) * 2 * (size_t)lpw * n;
+    hipLaunchKernelGGL(fft_pass_kernel, dim3((unsigned)groups), dim3(256), shmem, s, z, batch, n1,
+                       n2, n3, axis, (double)sign, tw, rad, lpw);
+    ISDF_HIP_TRY(hipGetLastError());
+  }
+  return ISDF_OK;
+}
+
+// ---------------------------------------------------------------- Poisson
+struct PoissonArg {
+  int gf[3], gc[3];
+  double B[9];   // B[i*3 + j] = component j of reciprocal vector b_i
+  double inv_ngf;
+};
+
+__global__ void __launch_bounds__(256)
+poisson_restrict_kernel(const double2* __restrict__ zf, double2* __restrict__ zc, int batch,
+                        PoissonArg a) {
+  const int64_t ngc = (int64_t)a.gc[0] * a.gc[1] * a.gc[2];
+  const int64_t ngf = (int64_t)a.gf[0] * a.gf[1] * a.gf[2];
+  const int b = blockIdx.y;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < ngc;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    int j[3];
+    j[0] = (int)(e % a.gc[0]);
+    const int64_t r = e / a.gc[0];
+    j[1] = (int)(r % a.gc[1]);
+    j[2] = (int)(r / a.gc[1]);
+    int m[3];
+    bool inband = true;
+    for (int i = 0; i < 3; ++i) {
+      m[i] = (j[i] <= (a.gc[i] - 1) / 2) ? j[i] : j[i] - a.gc[i];
+      if (2 * abs(m[i]) >= a.gc[i]) inband = false;
+    }
+    double2 out = make_double2(0.0, 0.0);
+    if (inband && (m[0] | m[1] | m[2]) != 0) {
+      double G[3];
+      for (int c = 0; c < 3; ++c) G[c] = m[0] * a.B[c] + m[1] * a.B[3 + c] + m[2] * a.B[6 + c];
+      const double g2 = G[0] * G[0] + G[1] * G[1] + G[2] * G[2];
+      const double v = 4.0 * 3.14159265358979323846 / g2 * a.inv_ngf;
+      int jf[3];
+      for (int i = 0; i < 3; ++i) jf[i] = m[i] < 0 ? m[i] + a.gf[i] : m[i];
+      const int64_t f = jf[0] + (int64_t)a.gf[0] * (jf[1] + (int64_t)a.gf[1] * jf[2]);
+      const double2 zv = zf[(int64_t)b * ngf + f];
+      out = make_double2(v * zv.x, v * zv.y);
+    }
+    zc[(int64_t)b * ngc + e] = out;
+  }
+}
+
+isdf_status launch_poisson_restrict(hipStream_t s, const double* zf, const int gf[3], double* zc,
+                                    const int gc[3], int batch, const double B[9]) {
+  if (batch <= 0) return ISDF_OK;
+  PoissonArg a;
+  for (int i = 0; i < 3; ++i) {
+    a.gf[i] = gf[i];
+    a.gc[i] = gc[i];
+  }
+  for (int i = 0; i < 9; ++i) a.B[i] = B[i];
+  a.inv_ngf = 1.0 / ((double)gf[0] * gf[1] * gf[2]);
+  const int64_t ngc = (int64_t)gc[0] * gc[1] * gc[2];
+  int64_t blocks = (ngc + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(poisson_restrict_kernel, dim3((unsigned)blocks, batch), dim3(256), 0, s,
+                     reinterpret_cast<const double2*>(zf), reinterpret_cast<double2*>(zc), batch, a);
+  ISDF_HIP_TRY(hipGetLastError());
+  return ISDF_OK;
+}
+
+// ------------------------------------------------------- scatter / split
+__global__ void scatter_cols_kernel(const ScatterCol* __restrict__ cols, double* __restrict__ z,
+                                    int64_t ng) {
+  const ScatterCol c = cols[blockIdx.y];
+  double* zp = z + (int64_t)(c.slot >> 1) * 2 * ng + (c.slot & 1);
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < c.n; i += gridDim.x * blockDim.x)
+    zp[2 * (int64_t)c.pts[i]] = c.src[i];
+}
+isdf_status launch_scatter_cols(hipStream_t s, const ScatterCol* cols, int ncols, int max_n,
+                                double* z, int64_t ng) {
+  if (ncols <= 0) return ISDF_OK;
+  int blocks = (max_n + 255) / 256;
+  if (blocks > 1024) blocks = 1024;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(scatter_cols_kernel, dim3(blocks, ncols), dim3(256), 0, s, cols, z, ng);
+  ISDF_HIP_TRY(hipGetLastError());
+  return ISDF_OK;
+}
+
+__global__ void split_planar_kernel(const double* __restrict__ z, int64_t ng, int ncols,
+                                    double* __restrict__ V) {
+  const int c = blockIdx.y;
+  const double* zp = z + (int64_t)(c >> 1) * 2 * ng + (c & 1);
+  double* vp = V + (int64_t)c * ng;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < ng;
+       i += (int64_t)gridDim.x * blockDim.x)
+    vp[i] = zp[2 * i];
+}
+isdf_status launch_split_planar(hipStream_t s, const double* z, int64_t ng, int ncols, double* V) {
+  if (ncols <= 0) return ISDF_OK;
+  int64_t blocks = (ng + 255) / 256;
+  if (blocks > 2048) blocks = 2048;
+  hipLaunchKernelGGL(split_planar_kernel, dim3((unsigned)blocks, ncols), dim3(256), 0, s, z, ng,
+                     ncols, V);
+  ISDF_HIP_TRY(hipGetLastError());
+  return ISDF_OK;
+}
+
+}  // namespace isdf

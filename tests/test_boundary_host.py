@@ -1,0 +1,93 @@
+"""Host-side checks of the C ABI (no GPU): the library loads, exports every
+declared symbol, builds the same multigrid plan as the oracle, and returns the
+documented status codes for bad input."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import plan as oplan
+from paper_2404_09373_amd import binding
+from workloads import batched_cells, config, tiny_system
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = binding.load()
+    hdr = open(os.path.join(ROOT, "include", "isdf.h")).read()
+    names = set(re.findall(r"\b(isdf_[a-z_]+)\s*\(", hdr))
+    assert names, "no declarations found"
+    for n in sorted(names):
+        assert hasattr(lib, n), f"{n} declared in isdf.h but not exported"
+    assert set(binding.EXPORTED) <= names
+
+
+def _compare_plan(sysm):
+    p = binding.Plan(sysm)
+    op = oplan.build_plan(sysm)
+    assert p.n_basis == op.n_basis
+    assert p.n_domains == len(op.domains)
+    assert p.n_mu == op.n_mu
+    for d in range(p.n_domains):
+        g = p.domain(d)
+        od = op.domains[d]
+        assert g["level"] == od.level and g["atom"] == od.atom
+        assert g["nL"] == od.L.size and g["nN"] == od.N.size and g["n_mu"] == od.n_mu
+        assert np.array_equal(g["points"], od.points), f"domain {d} points"
+        assert np.array_equal(g["funcs"], od.G), f"domain {d} functions"
+    p.close()
+
+
+@pytest.mark.parametrize("which", ["cfg1", "tiny1", "tiny2", "strained"])
+def test_plan_matches_oracle(which):
+    if which == "cfg1":
+        s = config(1, with_density=False)
+    elif which == "tiny1":
+        s = tiny_system("one_atom")
+    elif which == "tiny2":
+        s = tiny_system("two_atom")
+    else:
+        s = batched_cells(4)[3]  # 2x2x2 strained cell, uneven grids
+        s.grids = np.array([[24, 48, 40], [48, 96, 80]])
+    _compare_plan(s)
+
+
+@pytest.mark.slow
+def test_plan_matches_oracle_cfg2():
+    _compare_plan(config(2, with_density=False))
+
+
+def _status(sysm, **over):
+    for k, v in over.items():
+        setattr(sysm, k, v)
+    with pytest.raises(binding.IsdfError) as e:
+        binding.Plan(sysm)
+    return e.value.status
+
+
+def test_plan_errors():
+    assert _status(tiny_system("one_atom"), grids=np.array([[12, 12, 12], [26, 24, 24]])) == -7
+    assert _status(tiny_system("one_atom"), grids=np.array([[24, 24, 24], [12, 12, 12]])) == -7
+    s = tiny_system("one_atom")
+    s.shell_alpha = s.shell_alpha.copy()
+    s.shell_alpha[1] = np.nan
+    assert _status(s) == -1
+    s = tiny_system("one_atom")
+    s.shell_l = s.shell_l.copy()
+    s.shell_l[0] = 2
+    assert _status(s) == -7
+    assert _status(tiny_system("one_atom"), lattice=np.zeros((3, 3))) == -1
+    assert _status(tiny_system("one_atom"), image_tol=0.0) == -1
+
+
+def test_null_arguments():
+    lib = binding.load()
+    h = C.c_void_p()
+    assert lib.isdf_plan(None, None, C.byref(h)) == -1
+    assert lib.isdf_plan_info(None, None, None, None) == -1
+    assert lib.isdf_fit(None, C.byref(h)) == -1
+    assert lib.isdf_exchange(None, None, None, None, None) == -1
+    assert lib.isdf_last_error()

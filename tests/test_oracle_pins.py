@@ -340,7 +340,7 @@ def test_exchange_invariants_cfg1(cfg1_oracle):
 def test_single_level_textbook_thc():
     """One level, one universal domain: the four-term formula reduces to the
     textbook K = -X^T [(X D X^T) o W] X."""
-    s = tiny_system("one_atom", grids=((14, 14, 14),), alpha_bound=())
+    s = tiny_system("one_atom", grids=((15, 15, 15),), alpha_bound=())
     r = pipeline.run(s)
     assert np.all(r.XN == 0)
     X = r.XL

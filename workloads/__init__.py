@@ -15,4 +15,5 @@ from .diamond import (  # noqa: F401
     periodic_overlap,
     random_density,
     level_bounds,
+    batched_cells,
 )
