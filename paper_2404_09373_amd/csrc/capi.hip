@@ -30,6 +30,8 @@ using namespace isdf;
 namespace {
 
 constexpr int NSTAGE = 8;
+constexpr int RL_MIN_PIVOTS = 128;  // right-looking selection above this many pivots
+constexpr int RL_BLOCK = 128;       // pivots between residual (SYRK) updates
 
 struct DevBuf {
   void* p = nullptr;
@@ -278,6 +280,7 @@ isdf_status run_selection(isdf_plan_s* pl, isdf_fit_s* f, const int64_t* pinned)
     x.tile_off = (int)tile_dom.size();
     x.ntiles = (x.pts + SEL_TILE - 1) / SEL_TILE;
     x.piv_off = (int)pv;
+    x.mres_off = -1;
     for (int t = 0; t < x.ntiles; ++t) tile_dom.push_back(d);
     f->lfac_off[d] = lf;
     f->piv_off[d] = pv;
@@ -312,6 +315,26 @@ isdf_status run_selection(isdf_plan_s* pl, isdf_fit_s* f, const int64_t* pinned)
     ISDF_HIP_TRY(hipMemcpy(f->piv.p, hp_piv.data(), sizeof(int32_t) * pv, hipMemcpyHostToDevice));
     return ISDF_OK;
   }
+  // Large single-domain batches (the universal grid) use the right-looking
+  // form: residual Gram kept in HBM, SYRK update every RL_BLOCK pivots.
+  size_t free_b = 0, total_b = 0;
+  ISDF_HIP_TRY(hipMemGetInfo(&free_b, &total_b));
+  std::vector<char> right(nd, 0);
+  int64_t mres_max = 0;
+  for (int d = 0; d < nd; ++d) {
+    const int lev = hp.domains[d].level;
+    int nlev = 0;
+    for (int e = 0; e < nd; ++e) nlev += hp.domains[e].level == lev;
+    const double P = (double)sd[d].pts;
+    if (nlev == 1 && sd[d].n_mu > RL_MIN_PIVOTS && P * P * 8.0 <= 0.4 * (double)free_b) {
+      right[d] = 1;
+      sd[d].mres_off = 0;
+      mres_max = std::max<int64_t>(mres_max, (int64_t)sd[d].pts * sd[d].pts);
+    }
+  }
+  DevBuf mres;
+  if (mres_max > 0)
+    if ((st = mres.alloc(sizeof(double) * mres_max)) != ISDF_OK) return st;
   DevBuf d_sd, d_tile_dom;
   if ((st = upload(d_sd, sd)) != ISDF_OK) return st;
   if ((st = upload(d_tile_dom, tile_dom)) != ISDF_OK) return st;
@@ -339,6 +362,26 @@ isdf_status run_selection(isdf_plan_s* pl, isdf_fit_s* f, const int64_t* pinned)
     if ((st = launch_sel_init(s, D, d_tile_dom.as<int32_t>(), t0, t1 - t0, f->dwork.as<double>(),
                               f->tmax.as<double>(), f->tidx.as<int32_t>(), tau)) != ISDF_OK)
       return st;
+    const bool rl = right[d0] != 0;
+    const int64_t P = sd[d0].pts;
+    if (rl) {
+      // residual Gram = full pair Gram A_L o (A_L + 2 A_N), lower triangle
+      GemmProblem g{};
+      g.A = f->phi.as<double>() + pl->phi_off[d0];
+      g.lda = P;
+      g.B = g.A;
+      g.ldb = P;
+      g.transB = 1;
+      g.C = mres.as<double>();
+      g.ldc = P;
+      g.M = (int)P;
+      g.N = (int)P;
+      g.K = sd[d0].nG;
+      g.kL = sd[d0].nL;
+      g.lower = 1;
+      if ((st = gemm_prof(pl, ISDF_K_GEMM_FIT, EPI_THETA, g)) != ISDF_OK) return st;
+    }
+    int kb = 0;
     for (int k = 0; k <= kmax; ++k) {
       double col_bytes = 0.0, col_flops = 0.0, pick_bytes = 0.0;
       for (int d = d0; d < d1; ++d) {
@@ -355,12 +398,37 @@ isdf_status run_selection(isdf_plan_s* pl, isdf_fit_s* f, const int64_t* pinned)
         return st;
       ps_pick.finish();
       if (k == kmax) break;
-      ProfScope ps_col(pl, ISDF_K_SELECT_COLUMN, col_bytes, col_flops);
-      if ((st = launch_sel_column(s, D, d_tile_dom.as<int32_t>(), t0, t1 - t0, k, S,
-                                  f->phi.as<double>(), f->lfac.as<double>(),
-                                  f->dwork.as<double>(), f->prow.as<double>(),
-                                  f->tmax.as<double>(), f->tidx.as<int32_t>(), tau)) != ISDF_OK)
-        return st;
+      if (rl) {  // residual column + block columns instead of basis + all columns
+        col_bytes = 8.0 * P * ((double)(k - kb) + 4.0);
+        col_flops = 2.0 * P * (double)(k - kb);
+      }
+      {
+        ProfScope ps_col(pl, ISDF_K_SELECT_COLUMN, col_bytes, col_flops);
+        if ((st = launch_sel_column(s, D, d_tile_dom.as<int32_t>(), t0, t1 - t0, k, rl ? kb : 0, S,
+                                    f->phi.as<double>(), mres.as<double>(), f->lfac.as<double>(),
+                                    f->dwork.as<double>(), f->prow.as<double>(),
+                                    f->tmax.as<double>(), f->tidx.as<int32_t>(), tau)) != ISDF_OK)
+          return st;
+      }
+      if (rl && (k + 1 - kb == RL_BLOCK) && k + 1 < kmax) {
+        // Mres -= L[:, kb..k] L[:, kb..k]^T on the lower triangle
+        GemmProblem g{};
+        g.A = f->lfac.as<double>() + sd[d0].lfac_off + (int64_t)kb * P;
+        g.lda = P;
+        g.B = g.A;
+        g.ldb = P;
+        g.transB = 1;
+        g.C = mres.as<double>();
+        g.ldc = P;
+        g.M = (int)P;
+        g.N = (int)P;
+        g.K = k + 1 - kb;
+        g.alpha = -1.0;
+        g.beta = 1.0;
+        g.lower = 1;
+        if ((st = gemm_prof(pl, ISDF_K_GEMM_FIT, EPI_AXPBY, g)) != ISDF_OK) return st;
+        kb = k + 1;
+      }
     }
     d0 = d1;
   }
@@ -463,26 +531,23 @@ isdf_status blocked_fit(isdf_plan_s* pl, const double* theta, int64_t pts, int n
 }
 
 // ------------------------------------------------------------- Coulomb metric
+// Columns (fitting functions xi') are processed level by level in chunks.  For
+// a chunk on level l' every function is transformed on its own grid, and its
+// potential is formed on every grid l <= l' through that grid's band.  The
+// potentials of the whole chunk stay in HBM (one slab per grid), so that
+// W[rows of level l, chunk] = dV_l F_d^T V_l[P_d, chunk] is one wide grouped
+// GEMM per grid.  Chunk widths follow a memory budget; FFT batches follow the
+// size of the complex work buffers.
 isdf_status run_coulomb(isdf_plan_s* pl, isdf_fit_s* f) {
   HostPlan& hp = pl->hp;
   hipStream_t s = pl->stream;
   const int nd = (int)hp.domains.size();
   const int64_t nmu = f->nmu;
+  const int L = hp.n_levels;
   isdf_status st;
   if ((st = f->W.alloc(sizeof(double) * nmu * nmu)) != ISDF_OK) return st;
   if ((st = launch_fill(s, f->W.as<double>(), nmu * nmu, 0.0)) != ISDF_OK) return st;
-  // columns per batch
-  int wb = pl->opts.w_batch > 0 ? pl->opts.w_batch : 0;
-  const int L = hp.n_levels;
-  int64_t ng_max = 0;
-  for (int l = 0; l < L; ++l) ng_max = std::max(ng_max, level_ng(hp, l));
-  if (wb <= 0) {
-    // about 1.5 GB of complex work buffers on the finest grid
-    int64_t cap = (int64_t)(1.5e9 / (16.0 * ng_max)) * 2;
-    wb = (int)std::max<int64_t>(2, std::min<int64_t>(256, cap));
-  }
-  wb += wb & 1;
-  // per-level column lists (global xi indices are contiguous per level)
+  // global xi indices are contiguous per level
   std::vector<int64_t> lev_begin(L, -1), lev_end(L, -1);
   std::vector<int> col_dom(nmu), col_j(nmu);
   for (int d = 0; d < nd; ++d) {
@@ -495,115 +560,133 @@ isdf_status run_coulomb(isdf_plan_s* pl, isdf_fit_s* f) {
       col_j[f->xoff[d] + j] = j;
     }
   }
-  // descriptors for every batch, uploaded once
-  std::vector<ScatterCol> scat;
-  std::vector<GemmProblem> probs;
-  struct Launch {
-    int lp;           // column level
-    int64_t c0;       // first column
-    int ncols;
-    int scat_off;
-    int max_n;
-    int prob_off[8], prob_cnt[8], tiles[8];
+  // memory budget for the potential slabs and the complex work buffers
+  size_t free_b = 0, total_b = 0;
+  ISDF_HIP_TRY(hipMemGetInfo(&free_b, &total_b));
+  const double v_budget = std::max(2e9, 0.45 * (double)free_b);
+  const double z_budget = std::min(4e9, std::max(2.5e8, 0.05 * (double)free_b));
+  struct Chunk {
+    int lp;
+    int64_t c0, c1;
   };
-  std::vector<Launch> launches;
+  std::vector<Chunk> chunks;
+  int64_t vmax = 0;  // doubles of V needed by the widest chunk
   for (int lp = 0; lp < L; ++lp) {
     if (lev_begin[lp] < 0) continue;
-    for (int64_t c0 = lev_begin[lp]; c0 < lev_end[lp]; c0 += wb) {
-      Launch ln{};
-      ln.lp = lp;
-      ln.c0 = c0;
-      ln.ncols = (int)std::min<int64_t>(wb, lev_end[lp] - c0);
-      ln.scat_off = (int)scat.size();
-      ln.max_n = 0;
-      for (int c = 0; c < ln.ncols; ++c) {
-        const int d = col_dom[c0 + c];
-        const int j = col_j[c0 + c];
-        const int64_t pts = (int64_t)hp.domains[d].points.size();
-        ScatterCol sc;
-        sc.src = f->F.as<double>() + f->th_off[d] + (int64_t)j * pts;
-        sc.pts = pl->d_points.as<int32_t>() + pl->pts_off[d];
-        sc.n = (int)pts;
-        sc.slot = c;
-        scat.push_back(sc);
-        ln.max_n = std::max(ln.max_n, (int)pts);
-      }
-      for (int l = 0; l <= lp; ++l) {
-        ln.prob_off[l] = (int)probs.size();
-        int tiles = 0;
-        const double dV = hp.volume / (double)level_ng(hp, l);
-        for (int d = 0; d < nd; ++d) {
-          if (hp.domains[d].level != l || f->count[d] == 0) continue;
-          const HostDomain& D = hp.domains[d];
-          GemmProblem p{};
-          p.A = f->F.as<double>() + f->th_off[d];
-          p.lda = (int64_t)D.points.size();
-          p.transA = 1;
-          p.B = nullptr;  // the V buffer of level l, patched at launch time
-          p.ldb = level_ng(hp, l);
-          p.bidx = ((int64_t)D.points.size() == level_ng(hp, l) && D.atom < 0)
-                       ? nullptr
-                       : pl->d_points.as<int32_t>() + pl->pts_off[d];
-          p.C = f->W.as<double>() + f->xoff[d] + c0 * nmu;
-          p.ldc = nmu;
-          p.M = f->count[d];
-          p.N = ln.ncols;
-          p.K = (int)D.points.size();
-          p.alpha = dV;
-          p.beta = 0.0;
-          p.tile_start = tiles;
-          tiles += gemm_tiles(p.M, p.N);
-          probs.push_back(p);
-        }
-        ln.prob_cnt[l] = (int)probs.size() - ln.prob_off[l];
-        ln.tiles[l] = tiles;
-      }
-      launches.push_back(ln);
+    double per_col = 0.0;
+    for (int l = 0; l <= lp; ++l) per_col += 8.0 * level_ng(hp, l);
+    int64_t w = std::max<int64_t>(2, (int64_t)(v_budget / per_col));
+    w -= w & 1;
+    for (int64_t c0 = lev_begin[lp]; c0 < lev_end[lp]; c0 += w) {
+      Chunk c{lp, c0, std::min(c0 + w, lev_end[lp])};
+      chunks.push_back(c);
+      vmax = std::max<int64_t>(vmax, (int64_t)(per_col / 8.0) * (c.c1 - c.c0));
     }
   }
-  // work buffers
-  const int npairs_max = wb / 2;
+  // descriptors: scatter per column, GEMM problems per (chunk, row level)
+  std::vector<ScatterCol> scat(nmu);
+  for (int64_t c = 0; c < nmu; ++c) {
+    const int d = col_dom[c];
+    const int64_t pts = (int64_t)hp.domains[d].points.size();
+    scat[c].src = f->F.as<double>() + f->th_off[d] + (int64_t)col_j[c] * pts;
+    scat[c].pts = pl->d_points.as<int32_t>() + pl->pts_off[d];
+    scat[c].n = (int)pts;
+    scat[c].slot = 0;  // set per batch below
+  }
   DevBuf zf, zc, V, d_scat, d_probs;
-  if ((st = zf.alloc(sizeof(double) * 2 * ng_max * npairs_max)) != ISDF_OK) return st;
-  if ((st = zc.alloc(sizeof(double) * 2 * ng_max * npairs_max)) != ISDF_OK) return st;
-  std::vector<int64_t> voff(L + 1, 0);
-  for (int l = 0; l < L; ++l) voff[l + 1] = voff[l] + level_ng(hp, l) * wb;
-  if ((st = V.alloc(sizeof(double) * voff[L])) != ISDF_OK) return st;
-  // patch B pointers per level: each launch uses the same V layout
-  for (auto& ln : launches)
-    for (int l = 0; l <= ln.lp; ++l)
-      for (int i = 0; i < ln.prob_cnt[l]; ++i) probs[ln.prob_off[l] + i].B = V.as<double>() + voff[l];
-  if ((st = upload(d_scat, scat)) != ISDF_OK) return st;
-  if ((st = upload(d_probs, probs)) != ISDF_OK) return st;
-  for (auto& ln : launches) {
-    const int lp = ln.lp;
-    const int npairs = (ln.ncols + 1) / 2;
-    const int64_t ngp = level_ng(hp, lp);
-    if ((st = launch_fill(s, zf.as<double>(), 2 * ngp * npairs, 0.0)) != ISDF_OK) return st;
-    if ((st = launch_scatter_cols(s, d_scat.as<ScatterCol>() + ln.scat_off, ln.ncols, ln.max_n,
-                                  zf.as<double>(), ngp)) != ISDF_OK)
-      return st;
-    if ((st = fft_prof(pl, zf.as<double>(), npairs, hp.grid[lp], -1)) != ISDF_OK) return st;
-    for (int l = 0; l <= lp; ++l) {
-      const int64_t ng = level_ng(hp, l);
-      if ((st = launch_poisson_restrict(s, zf.as<double>(), hp.grid[lp], zc.as<double>(),
-                                        hp.grid[l], npairs, pl->recip)) != ISDF_OK)
-        return st;
-      if ((st = fft_prof(pl, zc.as<double>(), npairs, hp.grid[l], +1)) != ISDF_OK) return st;
-      if ((st = launch_split_planar(s, zc.as<double>(), ng, ln.ncols, V.as<double>() + voff[l])) !=
-          ISDF_OK)
-        return st;
-      if (ln.prob_cnt[l] > 0) {
-        double by = 0.0, fl = 0.0;
-        for (int i = 0; i < ln.prob_cnt[l]; ++i) {
-          by += gemm_bytes(probs[ln.prob_off[l] + i]);
-          fl += gemm_flops(probs[ln.prob_off[l] + i]);
-        }
-        ProfScope ps(pl, ISDF_K_GEMM_FIT, by, fl);
-        if ((st = gemm_f64_grouped(s, EPI_AXPBY, d_probs.as<GemmProblem>() + ln.prob_off[l],
-                                   ln.prob_cnt[l], ln.tiles[l])) != ISDF_OK)
-          return st;
+  int64_t ngz_max = 0;
+  for (auto& c : chunks) ngz_max = std::max(ngz_max, level_ng(hp, c.lp));
+  int64_t fft_pairs = std::max<int64_t>(1, (int64_t)(z_budget / (16.0 * ngz_max)));
+  if ((st = zf.alloc(sizeof(double) * 2 * ngz_max * fft_pairs)) != ISDF_OK) return st;
+  if ((st = zc.alloc(sizeof(double) * 2 * ngz_max * fft_pairs)) != ISDF_OK) return st;
+  if ((st = V.alloc(sizeof(double) * std::max<int64_t>(vmax, 1))) != ISDF_OK) return st;
+  std::vector<GemmProblem> probs;
+  struct GemmLaunch {
+    int off, cnt, tiles;
+    double bytes, flops;
+  };
+  std::vector<std::vector<GemmLaunch>> glaunch(chunks.size());
+  for (size_t ci = 0; ci < chunks.size(); ++ci) {
+    const Chunk& ch = chunks[ci];
+    int64_t voff = 0;
+    for (int l = 0; l <= ch.lp; ++l) {
+      GemmLaunch gl{(int)probs.size(), 0, 0, 0.0, 0.0};
+      const double dV = hp.volume / (double)level_ng(hp, l);
+      for (int d = 0; d < nd; ++d) {
+        if (hp.domains[d].level != l || f->count[d] == 0) continue;
+        const HostDomain& D = hp.domains[d];
+        GemmProblem p{};
+        p.A = f->F.as<double>() + f->th_off[d];
+        p.lda = (int64_t)D.points.size();
+        p.transA = 1;
+        p.B = V.as<double>() + voff;
+        p.ldb = level_ng(hp, l);
+        p.bidx = ((int64_t)D.points.size() == level_ng(hp, l) && D.atom < 0)
+                     ? nullptr
+                     : pl->d_points.as<int32_t>() + pl->pts_off[d];
+        p.C = f->W.as<double>() + f->xoff[d] + ch.c0 * nmu;
+        p.ldc = nmu;
+        p.M = f->count[d];
+        p.N = (int)(ch.c1 - ch.c0);
+        p.K = (int)D.points.size();
+        p.alpha = dV;
+        p.beta = 0.0;
+        p.tile_start = gl.tiles;
+        gl.tiles += gemm_tiles(p.M, p.N);
+        gl.bytes += gemm_bytes(p);
+        gl.flops += gemm_flops(p);
+        probs.push_back(p);
       }
+      gl.cnt = (int)probs.size() - gl.off;
+      glaunch[ci].push_back(gl);
+      voff += level_ng(hp, l) * (ch.c1 - ch.c0);
+    }
+  }
+  if ((st = upload(d_probs, probs)) != ISDF_OK) return st;
+  // the scatter slot of a column is its position within its FFT batch
+  for (auto& ch : chunks) {
+    const int64_t pairs_max = std::max<int64_t>(1, (ngz_max * fft_pairs) / level_ng(hp, ch.lp));
+    const int64_t bw = std::max<int64_t>(2, 2 * pairs_max);
+    for (int64_t b0 = ch.c0; b0 < ch.c1; b0 += bw)
+      for (int64_t c = b0; c < std::min(b0 + bw, ch.c1); ++c) scat[c].slot = (int)(c - b0);
+  }
+  if ((st = upload(d_scat, scat)) != ISDF_OK) return st;
+  for (size_t ci = 0; ci < chunks.size(); ++ci) {
+    const Chunk& ch = chunks[ci];
+    const int lp = ch.lp;
+    const int64_t ngp = level_ng(hp, lp);
+    const int64_t pairs_max = std::max<int64_t>(1, (ngz_max * fft_pairs) / ngp);
+    const int64_t bw = std::max<int64_t>(2, 2 * pairs_max);
+    for (int64_t b0 = ch.c0; b0 < ch.c1; b0 += bw) {
+      const int ncols = (int)std::min<int64_t>(bw, ch.c1 - b0);
+      const int npairs = (ncols + 1) / 2;
+      int max_n = 0;
+      for (int64_t c = b0; c < b0 + ncols; ++c) max_n = std::max(max_n, scat[c].n);
+      if ((st = launch_fill(s, zf.as<double>(), 2 * ngp * npairs, 0.0)) != ISDF_OK) return st;
+      if ((st = launch_scatter_cols(s, d_scat.as<ScatterCol>() + b0, ncols, max_n, zf.as<double>(),
+                                    ngp)) != ISDF_OK)
+        return st;
+      if ((st = fft_prof(pl, zf.as<double>(), npairs, hp.grid[lp], -1)) != ISDF_OK) return st;
+      int64_t voff = 0;
+      for (int l = 0; l <= lp; ++l) {
+        const int64_t ng = level_ng(hp, l);
+        if ((st = launch_poisson_restrict(s, zf.as<double>(), hp.grid[lp], zc.as<double>(),
+                                          hp.grid[l], npairs, pl->recip)) != ISDF_OK)
+          return st;
+        if ((st = fft_prof(pl, zc.as<double>(), npairs, hp.grid[l], +1)) != ISDF_OK) return st;
+        if ((st = launch_split_planar(s, zc.as<double>(), ng, ncols,
+                                      V.as<double>() + voff + (b0 - ch.c0) * ng)) != ISDF_OK)
+          return st;
+        voff += ng * (ch.c1 - ch.c0);
+      }
+    }
+    for (int l = 0; l <= lp; ++l) {
+      const GemmLaunch& gl = glaunch[ci][l];
+      if (gl.cnt == 0) continue;
+      ProfScope ps(pl, ISDF_K_GEMM_FIT, gl.bytes, gl.flops);
+      if ((st = gemm_f64_grouped(s, EPI_AXPBY, d_probs.as<GemmProblem>() + gl.off, gl.cnt,
+                                 gl.tiles)) != ISDF_OK)
+        return st;
     }
   }
   // level of each xi, then symmetrise

@@ -91,7 +91,7 @@ struct GemmProblem {
   int32_t transA, transB;
   double alpha, beta;
   int32_t tile_start;            // first flat tile of this problem in a grouped launch
-  int32_t pad;
+  int32_t lower;                 // 1: only tiles touching the lower triangle (m >= n)
 };
 
 // Launch one problem or a group (device array of problems, tile_start
@@ -128,6 +128,7 @@ isdf_status launch_basis_eval(hipStream_t s, const LatticeArg& lat, const ShellD
 // Selection (pivoted Cholesky) over a batch of domains.
 struct SelDomain {
   int64_t phi_off, lfac_off, diag_off, prow_off;
+  int64_t mres_off;              // >= 0: right-looking, residual Gram (lower) at this offset
   int32_t pts, nG, nL, n_mu;
   int32_t tile_off, ntiles;
   int32_t piv_off, pad;
@@ -148,10 +149,13 @@ isdf_status launch_sel_select(hipStream_t s, const SelDomain* doms, int dom_base
                               int k, SelState* st, const double* phi, const double* lfac,
                               double* diag, const double* tmax, const int32_t* tidx, double* prow,
                               int32_t* piv, double tau, double eps);
+// Left-looking (mres == nullptr): column from the basis values and all k
+// previous factor columns.  Right-looking: column from the residual Gram
+// (lower triangle, updated up to column kb) and the factor columns kb..k-1.
 isdf_status launch_sel_column(hipStream_t s, const SelDomain* doms, const int32_t* tile_dom,
-                              int tile_base, int ntiles, int k, const SelState* st,
-                              const double* phi, double* lfac, double* diag, const double* prow,
-                              double* tmax, int32_t* tidx, double tau);
+                              int tile_base, int ntiles, int k, int kb, const SelState* st,
+                              const double* phi, const double* mres, double* lfac, double* diag,
+                              const double* prow, double* tmax, int32_t* tidx, double tau);
 
 // Gather of the pivot rows of Phi into per-domain X rows and the global
 // X^L / X^N (column-major N_mu x N).

@@ -47,6 +47,7 @@ gemm_f64_kernel(GemmProblem single, const GemmProblem* __restrict__ probs, int n
   const int tn = local / tilesM;
   const int m0 = tm * BM, n0 = tn * BN;
   if (n0 >= p.N) return;
+  if (p.lower && m0 + BM <= n0) return;  // tile strictly above the diagonal
 
   __shared__ double As[BK][BM + PAD];
   __shared__ double Bs[BK][BN + PAD];

@@ -253,7 +253,8 @@ isdf_status launch_sel_select(hipStream_t s, const SelDomain* doms, int dom_base
 // factor columns, then wave 0 finishes the points.
 __global__ void __launch_bounds__(256)
 sel_column_kernel(const SelDomain* __restrict__ doms, const int32_t* __restrict__ tile_dom,
-                  int tile_base, int k, const SelState* __restrict__ st, const double* __restrict__ phi,
+                  int tile_base, int k, int kb, const SelState* __restrict__ st,
+                  const double* __restrict__ phi, const double* __restrict__ mres,
                   double* __restrict__ lfac, double* __restrict__ diag,
                   const double* __restrict__ prow, double* __restrict__ tmax,
                   int32_t* __restrict__ tidx, double tau) {
@@ -270,11 +271,36 @@ sel_column_kernel(const SelDomain* __restrict__ doms, const int32_t* __restrict_
   const double* pr = prow + D.prow_off;
   const double* ph = phi + D.phi_off + ii;
   double sL = 0.0, sN = 0.0, sc = 0.0;
-  int c = w;
-  for (; c < D.nL; c += 4) sL += ph[c * P] * pr[c];
-  for (; c < D.nG; c += 4) sN += ph[c * P] * pr[c];
+  const bool right = D.mres_off >= 0;
+  int j0 = 0;
+  if (right) {
+    // residual Gram entry (ii, p) from the stored lower triangle
+    if (w == 0) {
+      const int p = st[dom].cur;
+      const double* m = mres + D.mres_off;
+      sL = (ii >= p) ? m[ii + (int64_t)p * P] : m[p + (int64_t)ii * P];
+    }
+    j0 = kb;
+  } else {
+    int c = w;
+    for (; c + 12 < D.nL; c += 16) {
+      const double a0 = ph[c * P], a1 = ph[(c + 4) * P], a2 = ph[(c + 8) * P], a3 = ph[(c + 12) * P];
+      sL += a0 * pr[c] + a1 * pr[c + 4] + a2 * pr[c + 8] + a3 * pr[c + 12];
+    }
+    for (; c < D.nL; c += 4) sL += ph[c * P] * pr[c];
+    for (; c + 12 < D.nG; c += 16) {
+      const double a0 = ph[c * P], a1 = ph[(c + 4) * P], a2 = ph[(c + 8) * P], a3 = ph[(c + 12) * P];
+      sN += a0 * pr[c] + a1 * pr[c + 4] + a2 * pr[c + 8] + a3 * pr[c + 12];
+    }
+    for (; c < D.nG; c += 4) sN += ph[c * P] * pr[c];
+  }
   const double* lf = lfac + D.lfac_off + ii;
-  for (int j = w; j < k; j += 4) sc += lf[j * P] * pr[D.nG + j];
+  int j = j0 + w;
+  for (; j + 12 < k; j += 16) {
+    const double b0 = lf[j * P], b1 = lf[(j + 4) * P], b2 = lf[(j + 8) * P], b3 = lf[(j + 12) * P];
+    sc += b0 * pr[D.nG + j] + b1 * pr[D.nG + j + 4] + b2 * pr[D.nG + j + 8] + b3 * pr[D.nG + j + 12];
+  }
+  for (; j < k; j += 4) sc += lf[j * P] * pr[D.nG + j];
   __shared__ double red[3][4][64];
   red[0][w][lane] = sL;
   red[1][w][lane] = sN;
@@ -284,7 +310,7 @@ sel_column_kernel(const SelDomain* __restrict__ doms, const int32_t* __restrict_
   sL = (red[0][0][lane] + red[0][1][lane]) + (red[0][2][lane] + red[0][3][lane]);
   sN = (red[1][0][lane] + red[1][1][lane]) + (red[1][2][lane] + red[1][3][lane]);
   sc = (red[2][0][lane] + red[2][1][lane]) + (red[2][2][lane] + red[2][3][lane]);
-  const double col = sL * (sL + 2.0 * sN) - sc;
+  const double col = (right ? sL : sL * (sL + 2.0 * sN)) - sc;
   const double ell = col / sqrt(st[dom].dpiv);
   double dv = -1.0;
   if (valid) {
@@ -299,12 +325,12 @@ sel_column_kernel(const SelDomain* __restrict__ doms, const int32_t* __restrict_
 }
 
 isdf_status launch_sel_column(hipStream_t s, const SelDomain* doms, const int32_t* tile_dom,
-                              int tile_base, int ntiles, int k, const SelState* st,
-                              const double* phi, double* lfac, double* diag, const double* prow,
-                              double* tmax, int32_t* tidx, double tau) {
+                              int tile_base, int ntiles, int k, int kb, const SelState* st,
+                              const double* phi, const double* mres, double* lfac, double* diag,
+                              const double* prow, double* tmax, int32_t* tidx, double tau) {
   if (ntiles <= 0) return ISDF_OK;
   hipLaunchKernelGGL(sel_column_kernel, dim3(ntiles), dim3(256), 0, s, doms, tile_dom, tile_base,
-                     k, st, phi, lfac, diag, prow, tmax, tidx, tau);
+                     k, kb, st, phi, mres, lfac, diag, prow, tmax, tidx, tau);
   ISDF_HIP_TRY(hipGetLastError());
   return ISDF_OK;
 }
