@@ -3,7 +3,7 @@
 
 Workload: 2x2x2 diamond supercell (64 atoms, N = 832 basis functions),
 grids 32^3 / 64^3 / 128^3, 8 interpolation points per owned function
-(N_mu = 6656), 128 occupied orbitals, FP64 contractions and Cholesky.
+(N_mu = 6656), 128 occupied orbitals.
 
 A step is the whole hot path once: one isdf_fit (basis values, pivoted-
 Cholesky points, fitting functions, Coulomb metric) followed by 7
@@ -12,10 +12,17 @@ with a weight of 1/7, so value = step time / 7 = t_fit/7 + t_K in seconds
 per SCF iteration (lower is better).  Inputs are generated once and are
 resident on the GPU before the timed region.
 
-Also printed: the roofline position of the dominant kernel family (from
-HIP events bracketing each of its launches inside the timed region) and
-the FP64 oracle timed on a bounded sample of the same workload on the
-host cores.
+Two paths are timed on the same inputs:
+  reference  FP64 contractions, full pivoted-Cholesky selection
+  optimized  BF16-split (x6) contractions with FP32 accumulation carried in
+             FP64, and the learned candidate selector (trained on the GPU in
+             the untimed setup on full selections of the 8-atom cell and of a
+             differently displaced 64-atom cell)
+The headline value is the optimized path when its E_x agrees with the
+reference to 1e-6 Ha/atom, else the reference path.  Also reported: the
+roofline position of the headline path's dominant kernel family (HIP events
+around each of its launches in the timed region), parity against the stored
+FP64-oracle result, and the oracle timed on a bounded sample on the host.
 """
 import argparse
 import json
@@ -30,21 +37,17 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
 PEAK_FP64_TFS = 78.6
+PEAK_BF16_TFS = 2500.0
+# family id -> (name, bound, kernel name in profiles)
 FAMILIES = {
-    0: ("select_column", "hbm"),
-    1: ("select_pick", "hbm"),
-    2: ("gemm_fit_f64", "mfma"),
-    3: ("gemm_exchange_f64", "mfma"),
-    4: ("fft_c2c_f64", "hbm"),
-    5: ("basis_eval", "hbm"),
-}
-KERNEL_NAMES = {
-    0: "sel_column_kernel",
-    1: "sel_select_kernel",
-    2: "gemm_f64_kernel",
-    3: "gemm_f64_kernel",
-    4: "fft_pass_kernel",
-    5: "basis_eval_kernel",
+    0: ("select_column", "hbm", "sel_column_kernel"),
+    1: ("select_pick", "hbm", "sel_select_kernel"),
+    2: ("gemm_select", "mfma", "gemm_f64_kernel<*, 1>"),
+    3: ("gemm_metric", "mfma", "gemm_f64_kernel<*, 2>"),
+    4: ("gemm_fit", "mfma", "gemm_f64_kernel<*, 3>"),
+    5: ("gemm_exchange", "mfma", "gemm_f64_kernel<*, 4>"),
+    6: ("fft", "hbm", "fft_pass_kernel"),
+    7: ("basis", "hbm", "basis_eval_kernel"),
 }
 
 
@@ -54,9 +57,6 @@ def kernel_stats(plan):
     from paper_2404_09373_amd import binding
 
     lib = binding.load()
-    lib.isdf_kernel_stats.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_double),
-                                      C.POINTER(C.c_int64), C.POINTER(C.c_double),
-                                      C.POINTER(C.c_double)]
     out = {}
     for fam in FAMILIES:
         ms, n, by, fl = C.c_double(), C.c_int64(), C.c_double(), C.c_double()
@@ -66,19 +66,15 @@ def kernel_stats(plan):
 
 
 def set_profile(plan, on):
-    import ctypes as C
-
     from paper_2404_09373_amd import binding
 
-    lib = binding.load()
-    lib.isdf_profile.argtypes = [C.c_void_p, C.c_int32]
-    lib.isdf_profile(plan.handle, 1 if on else 0)
+    binding.load().isdf_profile(plan.handle, 1 if on else 0)
 
 
-def roofline(stats):
+def roofline(stats, mixed):
     fam = max(stats, key=lambda f: stats[f]["ms"])
     st = stats[fam]
-    name, bound = FAMILIES[fam]
+    name, bound, kname = FAMILIES[fam]
     n = max(st["launches"], 1)
     avg_s = st["ms"] / n / 1e3
     if bound == "hbm":
@@ -87,9 +83,12 @@ def roofline(stats):
     else:
         achieved = st["flops"] / n / avg_s / 1e12
         peak, unit = PEAK_FP64_TFS, "TFLOP/s"
+        if mixed and fam in (3, 5):
+            kname = kname.replace("gemm_f64_kernel", "gemm_mixed_kernel").replace("*,", "*, 3,")
+            peak = PEAK_BF16_TFS
     return {
         "bound": bound,
-        "kernel": KERNEL_NAMES[fam],
+        "kernel": kname,
         "family": name,
         "achieved": round(achieved, 3),
         "peak": peak,
@@ -100,26 +99,52 @@ def roofline(stats):
         "launches": st["launches"],
         "alg_bytes_per_launch": st["bytes"] / n,
         "alg_flops_per_launch": st["flops"] / n,
+        # BF16 MFMA work actually issued per algorithmic flop (six split products)
+        "mfma_issue_frac": round(6 * achieved / peak, 4) if peak == PEAK_BF16_TFS else None,
     }
 
 
-def cpu_baseline(sysm, budget_note=True):
+def train_selector(torch, log):
+    """Full FP64 selections of the 8-atom cell and of a 64-atom cell with other
+    displacements -> features/labels -> Adam on the GPU (library kernels)."""
+    from oracle import mlp as omlp  # parameter initialisation only (He normal, seeded)
+    from paper_2404_09373_amd import binding
+    from workloads import config, diamond_system
+
+    systems = [config(1, with_density=False),
+               diamond_system((2, 2, 2), ((32, 32, 32), (64, 64, 64), (128, 128, 128)), 8.0, 128,
+                              0.05, 0.0, 777, 778, with_density=False)]
+    Xs, Ys = [], []
+    for ts in systems:
+        pl = binding.Plan(ts)
+        f = pl.fit()
+        X, Y = f.features()
+        Xs.append(X)
+        Ys.append(Y)
+        f.close()
+        pl.close()
+    X = torch.cat(Xs)
+    Y = torch.cat(Ys)
+    t = time.perf_counter()
+    w, hist = binding.mlp_train(X, Y, omlp.init_params(0).astype(np.float32), epochs=10,
+                                batch=16384, lr=2e-3, seed=1)
+    log(f"trained selector on {X.shape[0]} points in {time.perf_counter() - t:.2f}s, "
+        f"loss {hist[0]:.4f} -> {hist[-1]:.4f}")
+    return w, [float(h) for h in hist]
+
+
+def cpu_baseline(sysm):
     """FP64 oracle on a bounded sample of the same workload, extrapolated to
     one fit/7 + one exchange (seconds per SCF iteration)."""
-    import scipy.fft  # noqa: F401
-
     from oracle import basis, coulomb, exchange, isdf
     from oracle import plan as oplan
 
     cores = len(os.sched_getaffinity(0))
-    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS"):
-        os.environ.setdefault(k, str(cores))
     t_all = time.perf_counter()
     p = oplan.build_plan(sysm)
     doms = p.domains
     levels = sorted({d.level for d in doms})
     est = {}
-    # universal domain: basis + diag in full, 192 pivot steps, fit at 192 points
     U = doms[0]
     t = time.perf_counter()
     Phi = basis.domain_values(p, U)
@@ -129,8 +154,7 @@ def cpu_baseline(sysm, budget_note=True):
     piv, _, _, _ = isdf.pivoted_cholesky(Phi, U.L.size, ks, sysm.eps_isdf, sysm.tie_tol)
     t_sel = time.perf_counter() - t
     nG = U.L.size + U.N.size
-    scale_sel = sum(nG + k for k in range(U.n_mu)) / sum(nG + k for k in range(ks))
-    est["select"] = t_sel * scale_sel
+    est["select"] = t_sel * sum(nG + k for k in range(U.n_mu)) / sum(nG + k for k in range(ks))
     t = time.perf_counter()
     isdf.fit_functions(Phi, U.L.size, piv)
     t_fit = time.perf_counter() - t
@@ -139,7 +163,6 @@ def cpu_baseline(sysm, budget_note=True):
         return 2.0 * U.points.size * n * nG + 2.0 * U.points.size * n * n + n ** 3 / 3.0
 
     est["fit"] = t_fit * work(U.n_mu) / work(ks)
-    # one window per finer level, every stage, scaled by the window count
     for lev in levels[1:]:
         ws = [d for d in doms if d.level == lev]
         d = ws[0]
@@ -155,8 +178,6 @@ def cpu_baseline(sysm, budget_note=True):
         est["basis"] += tb * len(ws)
         est["select"] += tsel * len(ws)
         est["fit"] += tf * len(ws)
-    # Coulomb metric: one batch of 16 columns per level (FFT, band potentials,
-    # products against every row domain), scaled by the column count
     rng = np.random.default_rng(0)
     t_coul = 0.0
     vker = [coulomb.coulomb_kernel(p.lattice, p.grids[l]) for l in range(len(p.grids))]
@@ -174,12 +195,10 @@ def cpu_baseline(sysm, budget_note=True):
             for d in doms:
                 if d.level != l:
                     continue
-                Fd = np.empty((d.points.size, d.n_mu))
-                Fd[:] = 1.0
+                Fd = np.ones((d.points.size, d.n_mu))
                 _ = Fd.T @ V[d.points]
         t_coul += (time.perf_counter() - t) * cols / b
     est["coulomb"] = t_coul
-    # exchange in full with X / W of the real sparsity
     nmu = sum(d.n_mu for d in doms)
     N = p.n_basis
     XL = np.zeros((nmu, N))
@@ -196,9 +215,8 @@ def cpu_baseline(sysm, budget_note=True):
     exchange.exchange_energy(sysm.D, K)
     est["exchange"] = time.perf_counter() - t
     t_fit_total = est["basis"] + est["select"] + est["fit"] + est["coulomb"]
-    value = t_fit_total / 7.0 + est["exchange"]
     return {
-        "value": round(value, 4),
+        "value": round(t_fit_total / 7.0 + est["exchange"], 4),
         "unit": "s/SCF-iter",
         "cores": cores,
         "kind": "oracle",
@@ -222,6 +240,7 @@ def main():
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--exchanges", type=int, default=7)
+    ap.add_argument("--paths", choices=["both", "reference", "optimized"], default="both")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -232,90 +251,125 @@ def main():
     from paper_2404_09373_amd import binding
     from workloads import config
 
+    def log(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
     assert torch.cuda.is_available(), "bench needs a GPU"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     s = config(args.config)
     stream = torch.cuda.current_stream(dev).cuda_stream
-    plan = binding.Plan(s, stream=stream)
     D = torch.tensor(s.D, dtype=torch.float64, device=dev)
     K = torch.empty_like(D)
-    print(f"[bench] cfg{args.config}: N={plan.n_basis} N_mu={plan.n_mu} domains={plan.n_domains}",
-          file=sys.stderr, flush=True)
 
-    def step():
-        fit = plan.fit()
-        ex = None
-        for _ in range(args.exchanges):
-            _, ex = fit.exchange(D, K)
-        n_mu = fit.n_mu
-        fit.close()
-        return ex, n_mu
+    def run_path(plan, tag):
+        def step():
+            fit = plan.fit()
+            ex = None
+            for _ in range(args.exchanges):
+                _, ex = fit.exchange(D, K)
+            sel = fit.selection()
+            n_mu = fit.n_mu
+            fit.close()
+            return ex, n_mu, sel
 
-    for w in range(args.warmup):
-        ex, _ = step()
-        print(f"[bench] warmup {w} E_x={ex:.10f}", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    set_profile(plan, True)
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        ex, n_mu = step()
-        print(f"[bench] step {i} done", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    stats = kernel_stats(plan)
-    stages = plan.stage_times()
-    set_profile(plan, False)
-    ms_per_step = (t1 - t0) / args.steps * 1e3
-    value = ms_per_step / args.exchanges / 1e3
-    rl = roofline(stats)
+        for w in range(args.warmup):
+            ex, _, _ = step()
+            log(f"{tag} warmup {w} E_x={ex:.10f}")
+        torch.cuda.synchronize()
+        set_profile(plan, True)
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            ex, n_mu, sel = step()
+            log(f"{tag} step {i} done")
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        stats = kernel_stats(plan)
+        stages = plan.stage_times()
+        set_profile(plan, False)
+        ms = (t1 - t0) / args.steps * 1e3
+        return dict(ms_per_step=ms, value=ms / args.exchanges / 1e3, E_x=ex, n_mu=n_mu,
+                    stats=stats, stages=stages, selection=sel)
+
+    results = {}
+    if args.paths in ("both", "reference"):
+        plan = binding.Plan(s, stream=stream)
+        log(f"cfg{args.config}: N={plan.n_basis} N_mu={plan.n_mu} domains={plan.n_domains}")
+        results["reference"] = run_path(plan, "reference")
+        plan.close()
+    weights, hist = None, None
+    if args.paths in ("both", "optimized"):
+        weights, hist = train_selector(torch, log)
+        plan = binding.Plan(s, stream=stream, precision=binding.MIXED_X6,
+                            selector=binding.SEL_MLP, mlp_weights=weights, mlp_keep=2.0,
+                            mlp_cutoff=0.05)
+        results["optimized"] = run_path(plan, "optimized")
+        plan.close()
+
+    ref = results.get("reference")
+    opt = results.get("optimized")
+    dE_opt = abs(opt["E_x"] - ref["E_x"]) / s.n_atoms if (ref and opt) else None
+    use_opt = opt is not None and (ref is None or dE_opt <= 1e-6)
+    head = opt if use_opt else ref
+    rl = roofline(head["stats"], mixed=use_opt)
 
     parity = None
     gpath = os.path.join(ROOT, "tests", "golden", f"cfg{args.config}_oracle.npz")
     if os.path.exists(gpath):
         g = np.load(gpath)
-        parity = {"oracle_E_x": float(g["E_x"]), "gpu_E_x": ex,
-                  "abs_dE_per_atom": abs(ex - float(g["E_x"])) / s.n_atoms}
+        parity = {"oracle_E_x": float(g["E_x"])}
+        for name, r in results.items():
+            parity[f"{name}_E_x"] = r["E_x"]
+            parity[f"{name}_abs_dE_per_atom"] = abs(r["E_x"] - float(g["E_x"])) / s.n_atoms
 
     cpu = None
     if not args.no_cpu_baseline:
-        print("[bench] cpu baseline (oracle sample) ...", file=sys.stderr, flush=True)
+        log("cpu baseline (oracle sample) ...")
         cpu = cpu_baseline(s)
 
-    fam_summary = {FAMILIES[f][0]: {"ms": round(v["ms"], 3), "launches": v["launches"]}
-                   for f, v in stats.items()}
+    def summary(r):
+        st = r["stages"]
+        sel = r["selection"]
+        return {
+            "value": round(r["value"], 6),
+            "ms_per_step": round(r["ms_per_step"], 3),
+            "E_x": r["E_x"],
+            "stage_ms_last_fit": {
+                "basis": round(st[0], 3), "select": round(st[1], 3), "gather": round(st[2], 3),
+                "theta": round(st[3], 3), "solve": round(st[4], 3), "coulomb": round(st[5], 3),
+                "exchange": round(st[6], 3),
+            },
+            "kernel_families_ms": {FAMILIES[f][0]: round(v["ms"], 3) for f, v in r["stats"].items()},
+            "candidates": int(np.sum(sel["n_candidates"])),
+            "fallback_domains": int(np.sum(sel["fallback"])),
+        }
+
     line = {
         "metric": "ISDF fit + K build s/SCF iter & MFMA util; mixed vs FP64 at 1e-6 Ha/atom",
-        "value": round(value, 6),
+        "value": round(head["value"], 6),
         "unit": "s/SCF-iter",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 3),
+        "ms_per_step": round(head["ms_per_step"], 3),
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "bf16x6/f64" if use_opt else "f64",
         "data": "synthetic",
         "config": {
-            "workload": f"cfg{args.config}: diamond 2x2x2 (64 atoms, +-0.05 A displacements), "
-                        "13 functions/atom (N=832), grids 32^3/64^3/128^3, N_mu=8N=6656, "
-                        "n_occ=128; step = 1 fit + 7 exchange builds" if args.config == 2 else
-                        f"cfg{args.config}",
-            "n_basis": plan.n_basis,
-            "n_mu": n_mu,
-            "domains": plan.n_domains,
+            "workload": ("cfg2: diamond 2x2x2 (64 atoms, +-0.05 A displacements), 13 functions/atom "
+                         "(N=832), grids 32^3/64^3/128^3, N_mu=8N=6656, n_occ=128; step = 1 fit + "
+                         "7 exchange builds") if args.config == 2 else f"cfg{args.config}",
+            "n_basis": s.n_basis,
+            "n_mu": head["n_mu"],
             "exchanges_per_fit": args.exchanges,
-            "precision": "fp64",
-            "selector": "full",
+            "headline_path": "optimized (bf16-split x6 + learned selector)" if use_opt else
+                             "reference (fp64, full selection)",
         },
-        "stage_ms_last_step": {
-            "basis": round(stages[0], 3), "select": round(stages[1], 3),
-            "gather": round(stages[2], 3), "theta": round(stages[3], 3),
-            "solve": round(stages[4], 3), "coulomb": round(stages[5], 3),
-            "exchange": round(stages[6], 3),
-        },
-        "kernel_families": fam_summary,
+        "paths": {k: summary(v) for k, v in results.items()},
+        "mixed_vs_fp64_abs_dE_per_atom": dE_opt,
+        "selector_training_loss": hist,
         "roofline": rl,
         "parity": parity,
         "cpu_baseline": cpu,

@@ -62,8 +62,14 @@ typedef enum {
 typedef struct isdf_plan_s* isdf_plan_t; /* opaque, library-owned */
 typedef struct isdf_fit_s* isdf_fit_t;   /* opaque, library-owned */
 
-/* Precision of the fit / exchange contractions. */
+/* Precision of the fit / exchange contractions: FP64 MFMA, or BF16-split
+ * operands (x = x0 + x1 [+ x2]) multiplied on BF16 MFMA with FP32
+ * accumulation carried into FP64 every 256 terms; X3 keeps the 3 leading
+ * products of 2-plane operands, X6 the 6 of 3-plane operands.  Cholesky
+ * factors and triangular solves of the interpolation metric are FP64 in
+ * every mode. */
 enum { ISDF_FP64 = 0, ISDF_MIXED_X3 = 1, ISDF_MIXED_X6 = 2 };
+enum { ISDF_MIX_THETA = 1, ISDF_MIX_W = 2, ISDF_MIX_EXCHANGE = 4 };
 /* Candidate selection before pivoted Cholesky. */
 enum { ISDF_SEL_FULL = 0, ISDF_SEL_MLP = 1 };
 
@@ -92,11 +98,15 @@ typedef struct {
 typedef struct {
   int32_t precision;          /* ISDF_FP64 (default) or a mixed mode                     */
   int32_t selector;           /* ISDF_SEL_FULL (default) or ISDF_SEL_MLP                 */
-  double mlp_keep;            /* MLP: keep ceil(mlp_keep * n_mu_d) candidates per domain */
+  double mlp_keep;            /* MLP: at least ceil(mlp_keep * n_mu_d) candidates / domain */
+  double mlp_cutoff;          /* MLP: also every point with score >= mlp_cutoff (0..1)    */
   const float* mlp_weights;   /* MLP: host array of ISDF_MLP_NPARAM floats, copied       */
   void* stream;               /* hipStream_t or NULL                                      */
   int32_t w_batch;            /* fitting functions per Poisson batch (0: automatic)      */
-  int32_t reserved[7];
+  int32_t mixed_mask;         /* contractions run in the mixed precision when precision
+                                 is ISDF_MIXED_*: bit 0 Theta, bit 1 W (universal rows),
+                                 bit 2 exchange; 0 means W and exchange                   */
+  int32_t reserved[6];
 } isdf_options;
 
 /* Build the multigrid plan (host only, no device work).
@@ -133,6 +143,63 @@ isdf_status isdf_fit(isdf_plan_t plan, isdf_fit_t* out);
  * (positions in the domain's point list).  Duplicate points make the
  * metric singular and return ISDF_E_NOT_SPD. */
 isdf_status isdf_fit_with_points(isdf_plan_t plan, const int64_t* local_points, isdf_fit_t* out);
+
+/* Same with the candidate points of every domain given: n_candidates[d]
+ * ascending local indices per domain, concatenated in candidates.  The
+ * greedy selection then runs over those points only (what the learned
+ * selector does with its top-scoring points).  Errors as isdf_fit plus
+ * ISDF_E_ARG for counts outside 1..n_points or unsorted lists. */
+isdf_status isdf_fit_with_candidates(isdf_plan_t plan, const int64_t* candidates,
+                                     const int64_t* n_candidates, isdf_fit_t* out);
+
+/* Selection report per domain (host arrays of n_domains, any may be NULL):
+ * candidates the greedy selection ran over, residual of the last pivot,
+ * largest initial Gram diagonal among the points left out (candidate modes;
+ * when it is below (1 - tie_tol) times the last residual the pivots are
+ * those of the full selection), and 1 where that check failed and the
+ * domain was refitted with full selection. */
+isdf_status isdf_fit_selection(isdf_fit_t fit, int64_t* n_candidates, double* last_residual,
+                               double* final_residual, int32_t* fallback);
+
+/* ---- learned candidate selector (not part of the paper's method) ------
+ * Network 16 -> 64 -> 64 -> 1 (ReLU, ReLU, sigmoid), FP32, ISDF_MLP_NPARAM
+ * parameters packed as W1[64][16], b1[64], W2[64][64], b2[64], w3[64], b3.
+ * Loss: mean weighted binary cross-entropy with positive weight pw. */
+#define ISDF_MLP_NPARAM 5313
+typedef struct {
+  int32_t epochs;
+  int32_t batch;
+  float lr, beta1, beta2, eps;  /* Adam */
+  float pos_weight;             /* <= 0: (#negative / #positive) of the labels */
+  uint64_t seed;                /* shuffling */
+  void* stream;                 /* hipStream_t or NULL */
+} isdf_mlp_config;
+
+/* 16 features of every grid point of every domain (domain after domain, in
+ * point order) into features_dev [n x 16] float, and labels_dev [n] = 1 for
+ * the points a candidate set must keep for the pruned selection to equal the
+ * fit's full selection (initial Gram diagonal >= (1 - tie_tol) times the
+ * residual of the domain's last pivot), else 0 (labels_dev may be NULL).
+ * *n receives the point count; capacity must be at least that.  Device
+ * pointers; with features_dev NULL only *n is set. */
+isdf_status isdf_fit_features(isdf_fit_t fit, float* features_dev, float* labels_dev,
+                              int64_t capacity, int64_t* n);
+
+/* Logits z (score = sigmoid(z)) of n feature rows; weights host, data device. */
+isdf_status isdf_mlp_forward(const float* weights, const float* features_dev, int64_t n,
+                             float* scores_dev, void* stream);
+
+/* Mean loss and its gradient (host outputs) over n rows. */
+isdf_status isdf_mlp_loss_grad(const float* weights, const float* features_dev,
+                               const float* labels_dev, int64_t n, float pos_weight, float* grad,
+                               float* loss, void* stream);
+
+/* Adam training on the GPU with the library's own forward/backward kernels;
+ * weights (host, ISDF_MLP_NPARAM) are read as the start point and receive
+ * the result; epoch_loss (host, cfg->epochs, may be NULL) the mean loss of
+ * each epoch. */
+isdf_status isdf_mlp_train(const float* features_dev, const float* labels_dev, int64_t n,
+                           const isdf_mlp_config* cfg, float* weights, float* epoch_loss);
 
 /* Exchange build, once per SCF iteration (Eq. ints):
  *   K = -[X^L'((X^G D X^G') o W)X^L + X^L'((X^G D X^L') o W)X^N
@@ -180,13 +247,16 @@ isdf_status isdf_stage_times(isdf_plan_t plan, double* t_ms, int32_t n);
  * column kernel; 2 M N K per GEMM).
  *   ISDF_K_SELECT_COLUMN  pivoted-Cholesky column + residual update
  *   ISDF_K_SELECT_PICK    tie-rule pivot pick
- *   ISDF_K_GEMM_FIT       Theta, Cholesky/solve and W products
+ *   ISDF_K_GEMM_SELECT    residual pair Gram and its rank updates (right-looking)
+ *   ISDF_K_GEMM_METRIC    W = dV F^T V products
+ *   ISDF_K_GEMM_FIT       Theta, blocked Cholesky and triangular-solve products
  *   ISDF_K_GEMM_EXCHANGE  exchange products (Eq. ints)
  *   ISDF_K_FFT            FFT passes of the Poisson solves
  *   ISDF_K_BASIS          basis values + Gram diagonal */
 enum {
-  ISDF_K_SELECT_COLUMN = 0, ISDF_K_SELECT_PICK = 1, ISDF_K_GEMM_FIT = 2,
-  ISDF_K_GEMM_EXCHANGE = 3, ISDF_K_FFT = 4, ISDF_K_BASIS = 5, ISDF_K_NFAMILY = 6
+  ISDF_K_SELECT_COLUMN = 0, ISDF_K_SELECT_PICK = 1, ISDF_K_GEMM_SELECT = 2,
+  ISDF_K_GEMM_METRIC = 3, ISDF_K_GEMM_FIT = 4, ISDF_K_GEMM_EXCHANGE = 5, ISDF_K_FFT = 6,
+  ISDF_K_BASIS = 7, ISDF_K_NFAMILY = 8
 };
 isdf_status isdf_profile(isdf_plan_t plan, int32_t enable);
 isdf_status isdf_kernel_stats(isdf_plan_t plan, int32_t family, double* ms, int64_t* launches,

@@ -90,3 +90,18 @@ def fit_functions(Phi: np.ndarray, nL: int, piv: np.ndarray):
     cf = sla.cho_factor(Mxi, lower=True)
     F = sla.cho_solve(cf, Theta.T).T
     return F, Theta, Mxi
+
+
+def needed_points(d0: np.ndarray, d_last: float, tie_tol: float) -> np.ndarray:
+    """Points a candidate set must contain for the restricted greedy selection
+    to reproduce the full one: residual diagonals never grow, so a point whose
+    initial diagonal is below (1 - tie_tol) d_last can never reach the tie
+    window of any step whose pivot residual is at least d_last."""
+    return np.nonzero(d0 >= (1.0 - tie_tol) * d_last)[0]
+
+
+def restriction_is_exact(d0: np.ndarray, candidates, d_last: float, tie_tol: float) -> bool:
+    mask = np.ones(d0.size, dtype=bool)
+    mask[np.asarray(candidates)] = False
+    excl = d0[mask]
+    return bool(excl.size == 0 or excl.max() < (1.0 - tie_tol) * d_last)

@@ -22,14 +22,32 @@ STATUS = {
 }
 FIELD = {"phi": 0, "diag": 1, "points": 2, "count": 3, "theta": 4, "F": 5, "XL": 6, "XN": 7, "W": 8}
 FP64, MIXED_X3, MIXED_X6 = 0, 1, 2
+MIX_THETA, MIX_W, MIX_EXCHANGE = 1, 2, 4
 SEL_FULL, SEL_MLP = 0, 1
 
 EXPORTED = [
     "isdf_plan", "isdf_plan_info", "isdf_plan_domain", "isdf_plan_domain_points",
     "isdf_plan_domain_functions", "isdf_fit", "isdf_fit_with_points", "isdf_exchange",
     "isdf_fit_get", "isdf_fit_info", "isdf_stage_times", "isdf_sync", "isdf_fit_destroy",
-    "isdf_plan_destroy", "isdf_last_error", "isdf_version",
+    "isdf_plan_destroy", "isdf_last_error", "isdf_version", "isdf_fit_with_candidates",
+    "isdf_fit_selection", "isdf_fit_features", "isdf_mlp_forward", "isdf_mlp_loss_grad",
+    "isdf_mlp_train", "isdf_profile", "isdf_kernel_stats",
 ]
+MLP_NPARAM = 5313
+
+
+class _MlpConfig(C.Structure):
+    _fields_ = [
+        ("epochs", C.c_int32),
+        ("batch", C.c_int32),
+        ("lr", C.c_float),
+        ("beta1", C.c_float),
+        ("beta2", C.c_float),
+        ("eps", C.c_float),
+        ("pos_weight", C.c_float),
+        ("seed", C.c_uint64),
+        ("stream", C.c_void_p),
+    ]
 
 
 class IsdfError(RuntimeError):
@@ -63,10 +81,12 @@ class _Options(C.Structure):
         ("precision", C.c_int32),
         ("selector", C.c_int32),
         ("mlp_keep", C.c_double),
+        ("mlp_cutoff", C.c_double),
         ("mlp_weights", C.POINTER(C.c_float)),
         ("stream", C.c_void_p),
         ("w_batch", C.c_int32),
-        ("reserved", C.c_int32 * 7),
+        ("mixed_mask", C.c_int32),
+        ("reserved", C.c_int32 * 6),
     ]
 
 
@@ -104,13 +124,23 @@ def load(required: bool = True):
     lib.isdf_plan_destroy.restype = None
     lib.isdf_last_error.restype = C.c_char_p
     lib.isdf_version.restype = C.c_char_p
-    for name in EXPORTED:
-        f = getattr(lib, name)
-        if f.restype is None and name not in ("isdf_fit_destroy", "isdf_plan_destroy"):
-            pass
+    fp = C.POINTER(C.c_float)
+    lib.isdf_fit_with_candidates.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(vp)]
+    lib.isdf_fit_selection.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_double),
+                                       C.POINTER(C.c_double), C.POINTER(C.c_int32)]
+    lib.isdf_fit_features.argtypes = [vp, vp, vp, C.c_int64, C.POINTER(C.c_int64)]
+    lib.isdf_mlp_forward.argtypes = [fp, vp, C.c_int64, vp, vp]
+    lib.isdf_mlp_loss_grad.argtypes = [fp, vp, vp, C.c_int64, C.c_float, fp, fp, vp]
+    lib.isdf_mlp_train.argtypes = [vp, vp, C.c_int64, C.POINTER(_MlpConfig), fp, fp]
+    lib.isdf_profile.argtypes = [vp, C.c_int32]
+    lib.isdf_kernel_stats.argtypes = [vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64),
+                                      C.POINTER(C.c_double), C.POINTER(C.c_double)]
     for name in ("isdf_plan", "isdf_plan_info", "isdf_plan_domain", "isdf_plan_domain_points",
                  "isdf_plan_domain_functions", "isdf_fit", "isdf_fit_with_points",
-                 "isdf_exchange", "isdf_fit_get", "isdf_fit_info", "isdf_stage_times", "isdf_sync"):
+                 "isdf_exchange", "isdf_fit_get", "isdf_fit_info", "isdf_stage_times", "isdf_sync",
+                 "isdf_fit_with_candidates", "isdf_fit_selection", "isdf_fit_features",
+                 "isdf_mlp_forward", "isdf_mlp_loss_grad", "isdf_mlp_train", "isdf_profile",
+                 "isdf_kernel_stats"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -130,7 +160,8 @@ class Plan:
     """A multigrid-ISDF plan for one system (see include/isdf.h)."""
 
     def __init__(self, sysm, precision: int = FP64, selector: int = SEL_FULL, stream=None,
-                 w_batch: int = 0):
+                 w_batch: int = 0, mlp_weights=None, mlp_keep: float = 2.0,
+                 mlp_cutoff: float = 0.05, mixed_mask: int = 0):
         lib = load()
         self._keep = []
         s = _System()
@@ -164,6 +195,14 @@ class Plan:
         o.selector = selector
         o.stream = C.c_void_p(stream) if stream else None
         o.w_batch = w_batch
+        if mlp_weights is not None:
+            wts = np.ascontiguousarray(mlp_weights, dtype=np.float32)
+            assert wts.size == MLP_NPARAM
+            self._keep.append(wts)
+            o.mlp_weights = _ptr(wts, C.c_float)
+        o.mlp_keep = float(mlp_keep)
+        o.mlp_cutoff = float(mlp_cutoff)
+        o.mixed_mask = int(mixed_mask)
         h = C.c_void_p()
         _check(lib.isdf_plan(C.byref(s), C.byref(o), C.byref(h)), "isdf_plan")
         self.handle = h
@@ -184,11 +223,16 @@ class Plan:
         return dict(level=lev.value, atom=atom.value, points=pts, nL=nL.value, nN=nN.value,
                     n_mu=nmu.value, funcs=funcs)
 
-    def fit(self, points=None, allow_rank=True) -> "Fit":
+    def fit(self, points=None, allow_rank=True, candidates=None) -> "Fit":
         lib = load()
         h = C.c_void_p()
         allow = (-5,) if allow_rank else ()
-        if points is None:
+        if candidates is not None:
+            flat = np.ascontiguousarray(np.concatenate([np.asarray(c, dtype=np.int64) for c in candidates]))
+            cnt = np.ascontiguousarray([len(c) for c in candidates], dtype=np.int64)
+            st = lib.isdf_fit_with_candidates(self.handle, _ptr(flat, C.c_int64), _ptr(cnt, C.c_int64),
+                                              C.byref(h))
+        elif points is None:
             st = lib.isdf_fit(self.handle, C.byref(h))
         else:
             flat = np.ascontiguousarray(np.concatenate([np.asarray(p, dtype=np.int64) for p in points]))
@@ -226,6 +270,29 @@ class Fit:
         _check(load().isdf_fit_info(handle, C.byref(n)), "isdf_fit_info")
         self.n_mu = n.value
         self.status = 0
+
+    def selection(self) -> dict:
+        nd = self.plan.n_domains
+        nc = np.zeros(nd, dtype=np.int64)
+        dl = np.zeros(nd)
+        df = np.zeros(nd)
+        fb = np.zeros(nd, dtype=np.int32)
+        _check(load().isdf_fit_selection(self.handle, _ptr(nc, C.c_int64), _ptr(dl, C.c_double),
+                                         _ptr(df, C.c_double), _ptr(fb, C.c_int32)), "isdf_fit_selection")
+        return dict(n_candidates=nc, last_residual=dl, excluded_max=df, fallback=fb)
+
+    def features(self, with_labels=True):
+        """(features [n, 16] float32, labels [n]) as CUDA tensors."""
+        import torch
+
+        n = C.c_int64()
+        load().isdf_fit_features(self.handle, None, None, 0, C.byref(n))
+        X = torch.empty((n.value, 16), dtype=torch.float32, device="cuda")
+        Y = torch.empty((n.value,), dtype=torch.float32, device="cuda") if with_labels else None
+        _check(load().isdf_fit_features(self.handle, C.c_void_p(X.data_ptr()),
+                                        C.c_void_p(Y.data_ptr()) if Y is not None else None,
+                                        n.value, C.byref(n)), "isdf_fit_features")
+        return X, Y
 
     def counts(self) -> np.ndarray:
         out = np.zeros(self.plan.n_domains, dtype=np.int64)
@@ -286,3 +353,35 @@ class Fit:
             self.close()
         except Exception:
             pass
+
+
+def mlp_forward(weights, X):
+    """Logits of feature rows X (float32 CUDA tensor [n, 16])."""
+    import torch
+
+    w = np.ascontiguousarray(weights, dtype=np.float32)
+    z = torch.empty((X.shape[0],), dtype=torch.float32, device=X.device)
+    _check(load().isdf_mlp_forward(_ptr(w, C.c_float), C.c_void_p(X.data_ptr()), X.shape[0],
+                                   C.c_void_p(z.data_ptr()), None), "isdf_mlp_forward")
+    return z
+
+
+def mlp_loss_grad(weights, X, Y, pos_weight):
+    w = np.ascontiguousarray(weights, dtype=np.float32)
+    g = np.zeros(MLP_NPARAM, dtype=np.float32)
+    loss = C.c_float()
+    _check(load().isdf_mlp_loss_grad(_ptr(w, C.c_float), C.c_void_p(X.data_ptr()),
+                                     C.c_void_p(Y.data_ptr()), X.shape[0], float(pos_weight),
+                                     _ptr(g, C.c_float), C.byref(loss), None), "isdf_mlp_loss_grad")
+    return float(loss.value), g
+
+
+def mlp_train(X, Y, weights, epochs=20, batch=65536, lr=1e-3, pos_weight=0.0, seed=0):
+    """Train on the GPU; returns (weights float32, per-epoch mean loss)."""
+    w = np.ascontiguousarray(weights, dtype=np.float32).copy()
+    cfg = _MlpConfig(epochs, batch, lr, 0.9, 0.999, 1e-8, float(pos_weight), seed, None)
+    hist = np.zeros(epochs, dtype=np.float32)
+    _check(load().isdf_mlp_train(C.c_void_p(X.data_ptr()), C.c_void_p(Y.data_ptr()), X.shape[0],
+                                 C.byref(cfg), _ptr(w, C.c_float), _ptr(hist, C.c_float)),
+           "isdf_mlp_train")
+    return w, hist

@@ -17,6 +17,8 @@ SOURCES = [
     "kernels_gemm.hip",
     "kernels_linalg.hip",
     "kernels_fft.hip",
+    "kernels_mlp.hip",
+    "kernels_mixed.hip",
     "plan.cpp",
 ]
 

@@ -66,6 +66,49 @@ isdf_status upload(DevBuf& b, const std::vector<T>& v) {
   return ISDF_OK;
 }
 
+// BF16 split planes of one logical operand (k-contiguous rows).
+struct Planes {
+  DevBuf buf;
+  int64_t ld = 0, plane = 0;
+  int rows = 0, cols = 0;
+  const __bf16* p() const { return static_cast<const __bf16*>(buf.p); }
+};
+
+isdf_status make_planes(hipStream_t s, int splits, const double* src, int64_t so, int64_t sk,
+                        const int32_t* kidx, int rows, int cols, Planes& out, double scale = 1.0) {
+  out.rows = rows;
+  out.cols = cols;
+  out.ld = (cols + 7) / 8 * 8;
+  out.plane = (int64_t)rows * out.ld;
+  const size_t need = sizeof(__bf16) * (size_t)splits * std::max<int64_t>(out.plane, 8);
+  isdf_status st;
+  if (out.buf.bytes != need)
+    if ((st = out.buf.alloc(need)) != ISDF_OK) return st;
+  return launch_split_bf16(s, src, so, sk, kidx, rows, cols, splits, static_cast<__bf16*>(out.buf.p),
+                           out.ld, out.plane, scale);
+}
+
+MixedProblem mixed_problem(const Planes& A, const Planes& B, double* C, int64_t ldc, int M, int N,
+                           int K, double alpha, double beta, const double* E, int64_t lde) {
+  MixedProblem p{};
+  p.A = A.p();
+  p.B = B.p();
+  p.plane_a = A.plane;
+  p.plane_b = B.plane;
+  p.lda = A.ld;
+  p.ldb = B.ld;
+  p.C = C;
+  p.ldc = ldc;
+  p.E = E;
+  p.lde = lde;
+  p.M = M;
+  p.N = N;
+  p.K = K;
+  p.alpha = alpha;
+  p.beta = beta;
+  return p;
+}
+
 }  // namespace
 
 struct isdf_plan_s;
@@ -79,7 +122,8 @@ struct isdf_plan_s {
   hipStream_t stream = nullptr;
   bool uploaded = false;
   // static device tables
-  DevBuf d_shells, d_img, d_colshells, d_doms, d_points, d_tiles, d_funcs;
+  DevBuf d_shells, d_img, d_colshells, d_doms, d_points, d_tiles, d_funcs, d_mlp_w;
+  std::vector<float> mlp_w;
   int ntiles_basis = 0;
   std::vector<int64_t> pts_off, phi_off, func_off;
   int64_t phi_total = 0, pts_total = 0;
@@ -104,14 +148,22 @@ struct isdf_plan_s {
 
 struct isdf_fit_s {
   isdf_plan_s* plan = nullptr;
-  DevBuf phi, diag0, dwork, lfac, prow, piv, tmax, tidx, state;
+  DevBuf phi, diag0, dwork, aux, piv, cflag;
   std::vector<int> count;          // points per domain
+  std::vector<int> ncand;          // candidates the selection ran over
+  std::vector<double> dlast;       // residual of the last pivot
+  std::vector<double> dfinal;      // largest final residual over the domain (candidate modes)
+  std::vector<int> fallback;       // 1: the learned candidates failed the residual check
+  std::vector<int> mode;           // selection mode per domain
   std::vector<int64_t> xoff;       // first xi of each domain
-  std::vector<int64_t> lfac_off, th_off, xrow_off, piv_off;
+  std::vector<int64_t> th_off, xrow_off, piv_off;
   int64_t nmu = 0;
   DevBuf xrows, XL, XN, XG, theta, F, W, lev;
   // exchange workspace
   DevBuf EG, EL, QGG, QGL, QLL, Y1, Y2, partial, ex_out;
+  // mixed precision: fit-time operand planes and per-exchange planes
+  Planes xg_row, xl_row, xl_col, xn_col;
+  Planes Dp, EGp, ELp, QGGp, QGLp, QGLTp, QLLp, Y1p, Y2p;
 };
 
 namespace {
@@ -169,9 +221,37 @@ double gemm_bytes(const GemmProblem& p) {
 }
 double gemm_flops(const GemmProblem& p) { return 2.0 * p.M * (double)p.N * p.K; }
 
+int mixed_splits(const isdf_plan_s* pl) {
+  return pl->opts.precision == ISDF_MIXED_X3 ? 2 : pl->opts.precision == ISDF_MIXED_X6 ? 3 : 0;
+}
+bool mixed_on(const isdf_plan_s* pl, int bit) {
+  if (mixed_splits(pl) == 0) return false;
+  // default: the Coulomb metric and the exchange; Theta only on request (its
+  // errors are amplified by the conditioning of the interpolation metric)
+  const int mask = pl->opts.mixed_mask == 0 ? (ISDF_MIX_W | ISDF_MIX_EXCHANGE) : pl->opts.mixed_mask;
+  return (mask & bit) != 0;
+}
+
+int family_tag(int fam) {
+  switch (fam) {
+    case ISDF_K_GEMM_SELECT: return 1;
+    case ISDF_K_GEMM_METRIC: return 2;
+    case ISDF_K_GEMM_FIT: return 3;
+    case ISDF_K_GEMM_EXCHANGE: return 4;
+    default: return 0;
+  }
+}
+
+isdf_status mixed_prof(isdf_plan_s* pl, int fam, int epi, const MixedProblem& p) {
+  const int S = mixed_splits(pl);
+  ProfScope ps(pl, fam, 2.0 * S * ((double)p.M * p.K + (double)p.K * p.N) + 8.0 * (double)p.M * p.N,
+               2.0 * p.M * (double)p.N * p.K);
+  return gemm_mixed(pl->stream, epi, S, p, family_tag(fam));
+}
+
 isdf_status gemm_prof(isdf_plan_s* pl, int fam, int epi, const GemmProblem& p) {
   ProfScope ps(pl, fam, gemm_bytes(p), gemm_flops(p));
-  return gemm_f64(pl->stream, epi, p);
+  return gemm_f64(pl->stream, epi, p, family_tag(fam));
 }
 
 isdf_status fft_prof(isdf_plan_s* pl, double* z, int batch, const int grid[3], int sign) {
@@ -247,6 +327,8 @@ isdf_status upload_plan(isdf_plan_s* pl) {
   for (int l = 0; l < hp.n_levels; ++l)
     for (int i = 0; i < 3; ++i)
       if ((st = fft_prepare(hp.grid[l][i])) != ISDF_OK) return st;
+  if (!pl->mlp_w.empty())
+    if ((st = upload(pl->d_mlp_w, pl->mlp_w)) != ISDF_OK) return st;
   for (int i = 0; i <= NSTAGE; ++i) ISDF_HIP_TRY(hipEventCreate(&pl->ev[i]));
   pl->uploaded = true;
   return ISDF_OK;
@@ -257,40 +339,250 @@ inline int64_t level_ng(const HostPlan& hp, int l) {
 }
 
 // ---------------------------------------------------------------- selection
-isdf_status run_selection(isdf_plan_s* pl, isdf_fit_s* f, const int64_t* pinned) {
+// One selection domain: basis values at phi_base + phi_off (column-major,
+// leading dimension pts), working diagonal at diag_base + diag_off (consumed).
+struct SelSpec {
+  int level;
+  int pts, nG, nL, n_mu;
+  int64_t phi_off, diag_off;
+};
+
+// Greedy pivoted Cholesky of every spec domain, one batch per level.  Writes
+// pivots (local to the spec domain) to piv_out + piv_off[d], the number found
+// to counts[d] and the residual of the last pivot to dlast[d].
+isdf_status select_points(isdf_plan_s* pl, const std::vector<SelSpec>& spec,
+                          const double* phi_base, double* diag_base, int32_t* piv_out,
+                          const std::vector<int64_t>& piv_off, std::vector<int>& counts,
+                          std::vector<double>& dlast) {
+  const HostPlan& hp = pl->hp;
+  hipStream_t s = pl->stream;
+  const int nd = (int)spec.size();
+  counts.assign(nd, 0);
+  dlast.assign(nd, 0.0);
+  if (nd == 0) return ISDF_OK;
+  std::vector<SelDomain> sd(nd);
+  std::vector<int32_t> tile_dom;
+  int64_t lf = 0, pr = 0;
+  for (int d = 0; d < nd; ++d) {
+    const SelSpec& S = spec[d];
+    SelDomain& x = sd[d];
+    x.phi_off = S.phi_off;
+    x.lfac_off = lf;
+    x.diag_off = S.diag_off;
+    x.prow_off = pr;
+    x.pts = S.pts;
+    x.nG = S.nG;
+    x.nL = S.nL;
+    x.n_mu = S.n_mu;
+    x.tile_off = (int)tile_dom.size();
+    x.ntiles = (x.pts + SEL_TILE - 1) / SEL_TILE;
+    x.piv_off = (int)piv_off[d];
+    x.mres_off = -1;
+    for (int t = 0; t < x.ntiles; ++t) tile_dom.push_back(d);
+    lf += (int64_t)x.pts * x.n_mu;
+    pr += x.nG + x.n_mu;
+  }
+  isdf_status st;
+  // Large single-domain batches (the universal grid) use the right-looking
+  // form: residual Gram kept in HBM, SYRK update every RL_BLOCK pivots.
+  size_t free_b = 0, total_b = 0;
+  ISDF_HIP_TRY(hipMemGetInfo(&free_b, &total_b));
+  std::vector<char> right(nd, 0);
+  int64_t mres_max = 0;
+  for (int d = 0; d < nd; ++d) {
+    int nlev = 0;
+    for (int e = 0; e < nd; ++e) nlev += spec[e].level == spec[d].level;
+    const double P = (double)sd[d].pts;
+    if (nlev == 1 && sd[d].n_mu > RL_MIN_PIVOTS && P * P * 8.0 <= 0.4 * (double)free_b) {
+      right[d] = 1;
+      sd[d].mres_off = 0;
+      mres_max = std::max<int64_t>(mres_max, (int64_t)sd[d].pts * sd[d].pts);
+    }
+  }
+  DevBuf mres, lfac, prow, tmax, tidx, state, d_sd, d_tile_dom;
+  if (mres_max > 0)
+    if ((st = mres.alloc(sizeof(double) * mres_max)) != ISDF_OK) return st;
+  if ((st = upload(d_sd, sd)) != ISDF_OK) return st;
+  if ((st = upload(d_tile_dom, tile_dom)) != ISDF_OK) return st;
+  const int ntiles = (int)tile_dom.size();
+  if ((st = lfac.alloc(sizeof(double) * std::max<int64_t>(lf, 1))) != ISDF_OK) return st;
+  if ((st = prow.alloc(sizeof(double) * std::max<int64_t>(pr, 1))) != ISDF_OK) return st;
+  if ((st = tmax.alloc(sizeof(double) * std::max(ntiles, 1))) != ISDF_OK) return st;
+  if ((st = tidx.alloc(sizeof(int32_t) * std::max(ntiles, 1))) != ISDF_OK) return st;
+  if ((st = state.alloc(sizeof(SelState) * nd)) != ISDF_OK) return st;
+  ISDF_HIP_TRY(hipMemsetAsync(state.p, 0, sizeof(SelState) * nd, s));
+  const double tau = hp.tie_tol, eps = hp.eps_isdf;
+  SelDomain* D = d_sd.as<SelDomain>();
+  SelState* S = state.as<SelState>();
+  // one batch per level (domains of a level are contiguous)
+  int d0 = 0;
+  while (d0 < nd) {
+    int d1 = d0;
+    int kmax = 0;
+    while (d1 < nd && spec[d1].level == spec[d0].level) {
+      kmax = std::max(kmax, spec[d1].n_mu);
+      ++d1;
+    }
+    const int t0 = sd[d0].tile_off;
+    const int t1 = (d1 < nd) ? sd[d1].tile_off : ntiles;
+    if ((st = launch_sel_init(s, D, d_tile_dom.as<int32_t>(), t0, t1 - t0, diag_base,
+                              tmax.as<double>(), tidx.as<int32_t>(), tau)) != ISDF_OK)
+      return st;
+    const bool rl = right[d0] != 0;
+    const int64_t P = sd[d0].pts;
+    if (rl) {
+      // residual Gram = full pair Gram A_L o (A_L + 2 A_N), lower triangle
+      GemmProblem g{};
+      g.A = phi_base + sd[d0].phi_off;
+      g.lda = P;
+      g.B = g.A;
+      g.ldb = P;
+      g.transB = 1;
+      g.C = mres.as<double>();
+      g.ldc = P;
+      g.M = (int)P;
+      g.N = (int)P;
+      g.K = sd[d0].nG;
+      g.kL = sd[d0].nL;
+      g.lower = 1;
+      if ((st = gemm_prof(pl, ISDF_K_GEMM_SELECT, EPI_THETA, g)) != ISDF_OK) return st;
+    }
+    int kb = 0;
+    for (int k = 0; k <= kmax; ++k) {
+      double col_bytes = 0.0, col_flops = 0.0, pick_bytes = 0.0;
+      for (int d = d0; d < d1; ++d) {
+        if (sd[d].n_mu <= k) continue;
+        col_bytes += 8.0 * sd[d].pts * ((double)sd[d].nG + k + 3.0);
+        col_flops += 2.0 * sd[d].pts * ((double)sd[d].nG + k) + 3.0 * sd[d].pts;
+        pick_bytes += 12.0 * sd[d].ntiles + 16.0 * (sd[d].nG + k);
+      }
+      ProfScope ps_pick(pl, ISDF_K_SELECT_PICK, pick_bytes, 0.0);
+      if ((st = launch_sel_select(s, D, d0, d1 - d0, k, S, phi_base, lfac.as<double>(), diag_base,
+                                  tmax.as<double>(), tidx.as<int32_t>(), prow.as<double>(),
+                                  piv_out, tau, eps)) != ISDF_OK)
+        return st;
+      ps_pick.finish();
+      if (k == kmax) break;
+      if (rl) {  // residual column + block columns instead of basis + all columns
+        col_bytes = 8.0 * P * ((double)(k - kb) + 4.0);
+        col_flops = 2.0 * P * (double)(k - kb);
+      }
+      {
+        ProfScope ps_col(pl, ISDF_K_SELECT_COLUMN, col_bytes, col_flops);
+        if ((st = launch_sel_column(s, D, d_tile_dom.as<int32_t>(), t0, t1 - t0, k, rl ? kb : 0, S,
+                                    phi_base, mres.as<double>(), lfac.as<double>(), diag_base,
+                                    prow.as<double>(), tmax.as<double>(), tidx.as<int32_t>(),
+                                    tau)) != ISDF_OK)
+          return st;
+      }
+      if (rl && (k + 1 - kb == RL_BLOCK) && k + 1 < kmax) {
+        // Mres -= L[:, kb..k] L[:, kb..k]^T on the lower triangle
+        GemmProblem g{};
+        g.A = lfac.as<double>() + sd[d0].lfac_off + (int64_t)kb * P;
+        g.lda = P;
+        g.B = g.A;
+        g.ldb = P;
+        g.transB = 1;
+        g.C = mres.as<double>();
+        g.ldc = P;
+        g.M = (int)P;
+        g.N = (int)P;
+        g.K = k + 1 - kb;
+        g.alpha = -1.0;
+        g.beta = 1.0;
+        g.lower = 1;
+        if ((st = gemm_prof(pl, ISDF_K_GEMM_SELECT, EPI_AXPBY, g)) != ISDF_OK) return st;
+        kb = k + 1;
+      }
+    }
+    d0 = d1;
+  }
+  std::vector<SelState> hs(nd);
+  ISDF_HIP_TRY(hipMemcpyAsync(hs.data(), state.p, sizeof(SelState) * nd, hipMemcpyDeviceToHost, s));
+  ISDF_HIP_TRY(hipStreamSynchronize(s));
+  for (int d = 0; d < nd; ++d) {
+    counts[d] = hs[d].count;
+    dlast[d] = hs[d].dpiv;
+  }
+  return ISDF_OK;
+}
+
+// Features of every point of every domain (learned selector input).
+isdf_status compute_features(isdf_plan_s* pl, isdf_fit_s* f, float* feats) {
   HostPlan& hp = pl->hp;
   hipStream_t s = pl->stream;
   const int nd = (int)hp.domains.size();
-  std::vector<SelDomain> sd(nd);
-  std::vector<int32_t> tile_dom;
-  int64_t lf = 0, pr = 0, pv = 0;
-  f->lfac_off.assign(nd, 0);
-  f->piv_off.assign(nd, 0);
+  MlpGeom g{};
+  for (int i = 0; i < 9; ++i) {
+    g.lat[i] = hp.lattice[i];
+    g.inv[i] = hp.inv[i];
+  }
+  g.n_atoms = hp.n_atoms;
+  g.n_levels = hp.n_levels;
+  std::vector<MlpDomain> md(nd);
   for (int d = 0; d < nd; ++d) {
     const HostDomain& D = hp.domains[d];
-    SelDomain& x = sd[d];
-    x.phi_off = pl->phi_off[d];
-    x.lfac_off = lf;
-    x.diag_off = pl->pts_off[d];
-    x.prow_off = pr;
-    x.pts = (int)D.points.size();
-    x.nG = (int)D.funcs.size();
-    x.nL = D.nL;
-    x.n_mu = D.n_mu;
-    x.tile_off = (int)tile_dom.size();
-    x.ntiles = (x.pts + SEL_TILE - 1) / SEL_TILE;
-    x.piv_off = (int)pv;
-    x.mres_off = -1;
-    for (int t = 0; t < x.ntiles; ++t) tile_dom.push_back(d);
-    f->lfac_off[d] = lf;
-    f->piv_off[d] = pv;
-    lf += (int64_t)x.pts * x.n_mu;
-    pr += x.nG + x.n_mu;
-    pv += x.n_mu;
+    MlpDomain& m = md[d];
+    m.pts_off = pl->pts_off[d];
+    m.pts = (int)D.points.size();
+    m.level = D.level;
+    m.atom = D.atom;
+    m.nL = D.nL;
+    m.n_mu = D.n_mu;
+    for (int i = 0; i < 3; ++i) m.grid[i] = hp.grid[D.level][i];
+    double h = 0.0;
+    for (int i = 0; i < 3; ++i) {
+      const double* a = hp.lattice + 3 * i;
+      h = std::max(h, std::sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]) / hp.grid[D.level][i]);
+    }
+    m.h = h;
+    if (D.atom >= 0) {
+      m.rs = D.r_max;
+    } else if (hp.n_levels > 1) {
+      m.rs = std::sqrt(-std::log(hp.eps_r) / hp.alpha_bound[0]);
+    } else {
+      double h0 = 0.0;
+      for (int i = 0; i < 3; ++i) {
+        const double* a = hp.lattice + 3 * i;
+        h0 = std::max(h0, std::sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]) / hp.grid[0][i]);
+      }
+      m.rs = 10.0 * h0;
+    }
   }
   isdf_status st;
+  DevBuf d_md, d_atoms;
+  if ((st = upload(d_md, md)) != ISDF_OK) return st;
+  if ((st = upload(d_atoms, hp.xyz)) != ISDF_OK) return st;
+  if ((st = launch_diag_stats(s, d_md.as<MlpDomain>(), nd, f->diag0.as<double>())) != ISDF_OK) return st;
+  if ((st = launch_features(s, g, d_md.as<MlpDomain>(), pl->d_points.as<int32_t>(),
+                            pl->d_tiles.as<BasisTile>(), pl->ntiles_basis, f->aux.as<double>(),
+                            f->diag0.as<double>(), d_atoms.as<double>(), feats)) != ISDF_OK)
+    return st;
+  ISDF_HIP_TRY(hipStreamSynchronize(s));
+  return ISDF_OK;
+}
+
+// Selection for a fit.  mode[d]: 0 full, 1 candidates from the learned
+// scores, 2 candidates given by the caller (cand_in).
+isdf_status run_selection(isdf_plan_s* pl, isdf_fit_s* f, const int64_t* pinned,
+                          const std::vector<int>& mode, const int64_t* cand_in,
+                          const int64_t* ncand_in) {
+  HostPlan& hp = pl->hp;
+  hipStream_t s = pl->stream;
+  const int nd = (int)hp.domains.size();
+  isdf_status st;
+  int64_t pv = 0;
+  f->piv_off.assign(nd, 0);
+  for (int d = 0; d < nd; ++d) {
+    f->piv_off[d] = pv;
+    pv += hp.domains[d].n_mu;
+  }
   if ((st = f->piv.alloc(sizeof(int32_t) * std::max<int64_t>(pv, 1))) != ISDF_OK) return st;
   f->count.assign(nd, 0);
+  f->dlast.assign(nd, 0.0);
+  f->ncand.assign(nd, 0);
+  f->dfinal.assign(nd, 0.0);
+  f->fallback.assign(nd, 0);
   if (pinned) {
     std::vector<int32_t> hp_piv(pv);
     int64_t o = 0;
@@ -315,127 +607,197 @@ isdf_status run_selection(isdf_plan_s* pl, isdf_fit_s* f, const int64_t* pinned)
     ISDF_HIP_TRY(hipMemcpy(f->piv.p, hp_piv.data(), sizeof(int32_t) * pv, hipMemcpyHostToDevice));
     return ISDF_OK;
   }
-  // Large single-domain batches (the universal grid) use the right-looking
-  // form: residual Gram kept in HBM, SYRK update every RL_BLOCK pivots.
-  size_t free_b = 0, total_b = 0;
-  ISDF_HIP_TRY(hipMemGetInfo(&free_b, &total_b));
-  std::vector<char> right(nd, 0);
-  int64_t mres_max = 0;
+  // full-mode domains
+  std::vector<SelSpec> full;
+  std::vector<int> full_id;
+  std::vector<int64_t> full_poff;
   for (int d = 0; d < nd; ++d) {
-    const int lev = hp.domains[d].level;
-    int nlev = 0;
-    for (int e = 0; e < nd; ++e) nlev += hp.domains[e].level == lev;
-    const double P = (double)sd[d].pts;
-    if (nlev == 1 && sd[d].n_mu > RL_MIN_PIVOTS && P * P * 8.0 <= 0.4 * (double)free_b) {
-      right[d] = 1;
-      sd[d].mres_off = 0;
-      mres_max = std::max<int64_t>(mres_max, (int64_t)sd[d].pts * sd[d].pts);
-    }
+    if (mode[d] != 0) continue;
+    const HostDomain& D = hp.domains[d];
+    full.push_back(SelSpec{D.level, (int)D.points.size(), (int)D.funcs.size(), D.nL, D.n_mu,
+                           pl->phi_off[d], pl->pts_off[d]});
+    full_id.push_back(d);
+    full_poff.push_back(f->piv_off[d]);
   }
-  DevBuf mres;
-  if (mres_max > 0)
-    if ((st = mres.alloc(sizeof(double) * mres_max)) != ISDF_OK) return st;
-  DevBuf d_sd, d_tile_dom;
-  if ((st = upload(d_sd, sd)) != ISDF_OK) return st;
-  if ((st = upload(d_tile_dom, tile_dom)) != ISDF_OK) return st;
-  const int ntiles = (int)tile_dom.size();
-  if ((st = f->lfac.alloc(sizeof(double) * std::max<int64_t>(lf, 1))) != ISDF_OK) return st;
-  if ((st = f->prow.alloc(sizeof(double) * std::max<int64_t>(pr, 1))) != ISDF_OK) return st;
-  if ((st = f->tmax.alloc(sizeof(double) * ntiles)) != ISDF_OK) return st;
-  if ((st = f->tidx.alloc(sizeof(int32_t) * ntiles)) != ISDF_OK) return st;
-  if ((st = f->state.alloc(sizeof(SelState) * nd)) != ISDF_OK) return st;
-  ISDF_HIP_TRY(hipMemsetAsync(f->state.p, 0, sizeof(SelState) * nd, s));
-  const double tau = hp.tie_tol, eps = hp.eps_isdf;
-  // one batch per level: domains of a level are contiguous
-  int d0 = 0;
-  while (d0 < nd) {
-    int d1 = d0;
-    int kmax = 0;
-    while (d1 < nd && hp.domains[d1].level == hp.domains[d0].level) {
-      kmax = std::max(kmax, hp.domains[d1].n_mu);
-      ++d1;
-    }
-    const int t0 = sd[d0].tile_off;
-    const int t1 = (d1 < nd) ? sd[d1].tile_off : ntiles;
-    SelDomain* D = d_sd.as<SelDomain>();
-    SelState* S = f->state.as<SelState>();
-    if ((st = launch_sel_init(s, D, d_tile_dom.as<int32_t>(), t0, t1 - t0, f->dwork.as<double>(),
-                              f->tmax.as<double>(), f->tidx.as<int32_t>(), tau)) != ISDF_OK)
+  std::vector<int> cnt;
+  std::vector<double> dl;
+  if (!full.empty()) {
+    if ((st = select_points(pl, full, f->phi.as<double>(), f->dwork.as<double>(), f->piv.as<int32_t>(),
+                            full_poff, cnt, dl)) != ISDF_OK)
       return st;
-    const bool rl = right[d0] != 0;
-    const int64_t P = sd[d0].pts;
-    if (rl) {
-      // residual Gram = full pair Gram A_L o (A_L + 2 A_N), lower triangle
-      GemmProblem g{};
-      g.A = f->phi.as<double>() + pl->phi_off[d0];
-      g.lda = P;
-      g.B = g.A;
-      g.ldb = P;
-      g.transB = 1;
-      g.C = mres.as<double>();
-      g.ldc = P;
-      g.M = (int)P;
-      g.N = (int)P;
-      g.K = sd[d0].nG;
-      g.kL = sd[d0].nL;
-      g.lower = 1;
-      if ((st = gemm_prof(pl, ISDF_K_GEMM_FIT, EPI_THETA, g)) != ISDF_OK) return st;
+    for (size_t i = 0; i < full.size(); ++i) {
+      f->count[full_id[i]] = cnt[i];
+      f->dlast[full_id[i]] = dl[i];
+      f->ncand[full_id[i]] = full[i].pts;
     }
-    int kb = 0;
-    for (int k = 0; k <= kmax; ++k) {
-      double col_bytes = 0.0, col_flops = 0.0, pick_bytes = 0.0;
-      for (int d = d0; d < d1; ++d) {
-        if (sd[d].n_mu <= k) continue;
-        col_bytes += 8.0 * sd[d].pts * ((double)sd[d].nG + k + 3.0);
-        col_flops += 2.0 * sd[d].pts * ((double)sd[d].nG + k) + 3.0 * sd[d].pts;
-        pick_bytes += 12.0 * sd[d].ntiles + 16.0 * (sd[d].nG + k);
-      }
-      ProfScope ps_pick(pl, ISDF_K_SELECT_PICK, pick_bytes, 0.0);
-      if ((st = launch_sel_select(s, D, d0, d1 - d0, k, S, f->phi.as<double>(),
-                                  f->lfac.as<double>(), f->dwork.as<double>(),
-                                  f->tmax.as<double>(), f->tidx.as<int32_t>(),
-                                  f->prow.as<double>(), f->piv.as<int32_t>(), tau, eps)) != ISDF_OK)
-        return st;
-      ps_pick.finish();
-      if (k == kmax) break;
-      if (rl) {  // residual column + block columns instead of basis + all columns
-        col_bytes = 8.0 * P * ((double)(k - kb) + 4.0);
-        col_flops = 2.0 * P * (double)(k - kb);
-      }
-      {
-        ProfScope ps_col(pl, ISDF_K_SELECT_COLUMN, col_bytes, col_flops);
-        if ((st = launch_sel_column(s, D, d_tile_dom.as<int32_t>(), t0, t1 - t0, k, rl ? kb : 0, S,
-                                    f->phi.as<double>(), mres.as<double>(), f->lfac.as<double>(),
-                                    f->dwork.as<double>(), f->prow.as<double>(),
-                                    f->tmax.as<double>(), f->tidx.as<int32_t>(), tau)) != ISDF_OK)
-          return st;
-      }
-      if (rl && (k + 1 - kb == RL_BLOCK) && k + 1 < kmax) {
-        // Mres -= L[:, kb..k] L[:, kb..k]^T on the lower triangle
-        GemmProblem g{};
-        g.A = f->lfac.as<double>() + sd[d0].lfac_off + (int64_t)kb * P;
-        g.lda = P;
-        g.B = g.A;
-        g.ldb = P;
-        g.transB = 1;
-        g.C = mres.as<double>();
-        g.ldc = P;
-        g.M = (int)P;
-        g.N = (int)P;
-        g.K = k + 1 - kb;
-        g.alpha = -1.0;
-        g.beta = 1.0;
-        g.lower = 1;
-        if ((st = gemm_prof(pl, ISDF_K_GEMM_FIT, EPI_AXPBY, g)) != ISDF_OK) return st;
-        kb = k + 1;
-      }
-    }
-    d0 = d1;
   }
-  std::vector<SelState> hs(nd);
-  ISDF_HIP_TRY(hipMemcpyAsync(hs.data(), f->state.p, sizeof(SelState) * nd, hipMemcpyDeviceToHost, s));
+  // candidate-mode domains
+  std::vector<int> cid;
+  for (int d = 0; d < nd; ++d)
+    if (mode[d] != 0) cid.push_back(d);
+  if (cid.empty()) return ISDF_OK;
+  DevBuf cand;  // candidate lists, at pts_off[d] for domain d
+  if ((st = cand.alloc(sizeof(int32_t) * std::max<int64_t>(pl->pts_total, 1))) != ISDF_OK) return st;
+  if ((st = f->cflag.alloc(std::max<int64_t>(pl->pts_total, 1))) != ISDF_OK) return st;
+  ISDF_HIP_TRY(hipMemsetAsync(f->cflag.p, 1, pl->pts_total, s));
+  std::vector<int32_t> nc_host(nd, 0);
+  bool any_learned = false, any_given = false;
+  for (int d : cid) (mode[d] == 1 ? any_learned : any_given) = true;
+  if (any_given) {
+    std::vector<int32_t> hc(std::max<int64_t>(pl->pts_total, 1), 0);
+    std::vector<uint8_t> hf(std::max<int64_t>(pl->pts_total, 1), 1);
+    int64_t o = 0;
+    for (int d = 0; d < nd; ++d) {
+      const int64_t n = ncand_in[d];
+      const int64_t np = (int64_t)hp.domains[d].points.size();
+      if (mode[d] == 2) {
+        if (n <= 0 || n > np) {
+          set_error("isdf_fit_with_candidates: candidate count outside 1..points");
+          return ISDF_E_ARG;
+        }
+        for (int64_t i = 0; i < np; ++i) hf[pl->pts_off[d] + i] = 0;
+        for (int64_t i = 0; i < n; ++i) {
+          const int64_t v = cand_in[o + i];
+          if (v < 0 || v >= np || (i > 0 && v <= cand_in[o + i - 1])) {
+            set_error("isdf_fit_with_candidates: candidates must be ascending local indices");
+            return ISDF_E_ARG;
+          }
+          hc[pl->pts_off[d] + i] = (int32_t)v;
+          hf[pl->pts_off[d] + v] = 1;
+        }
+        nc_host[d] = (int32_t)n;
+      }
+      o += std::max<int64_t>(n, 0);
+    }
+    ISDF_HIP_TRY(hipMemcpy(cand.p, hc.data(), sizeof(int32_t) * hc.size(), hipMemcpyHostToDevice));
+    ISDF_HIP_TRY(hipMemcpy(f->cflag.p, hf.data(), hf.size(), hipMemcpyHostToDevice));
+  }
+  if (any_learned) {
+    DevBuf feats, z, d_cd, d_nc, d_w;
+    if ((st = feats.alloc(sizeof(float) * 16 * pl->pts_total)) != ISDF_OK) return st;
+    if ((st = z.alloc(sizeof(float) * pl->pts_total)) != ISDF_OK) return st;
+    if ((st = compute_features(pl, f, feats.as<float>())) != ISDF_OK) return st;
+    if ((st = launch_mlp_forward(s, pl->d_mlp_w.as<float>(), feats.as<float>(), pl->pts_total,
+                                 z.as<float>())) != ISDF_OK)
+      return st;
+    std::vector<CandDomain> cd;
+    std::vector<int> cd_id;
+    for (int d : cid) {
+      if (mode[d] != 1) continue;
+      CandDomain c{};
+      c.pts_off = pl->pts_off[d];
+      c.cand_off = pl->pts_off[d];
+      c.pts = (int)hp.domains[d].points.size();
+      c.keep = std::max(hp.domains[d].n_mu,
+                        (int)std::ceil(pl->opts.mlp_keep * (double)hp.domains[d].n_mu));
+      c.keep = std::max(1, std::min(c.keep, c.pts));
+      cd.push_back(c);
+      cd_id.push_back(d);
+    }
+    if ((st = upload(d_cd, cd)) != ISDF_OK) return st;
+    if ((st = d_nc.alloc(sizeof(int32_t) * cd.size())) != ISDF_OK) return st;
+    const double pc = std::min(std::max(pl->opts.mlp_cutoff, 1e-30), 1.0 - 1e-7);
+    const float zcut = (float)std::log(pc / (1.0 - pc));  // logit of the score cutoff
+    if ((st = launch_topk_compact(s, d_cd.as<CandDomain>(), (int)cd.size(), z.as<float>(), zcut,
+                                  cand.as<int32_t>(), d_nc.as<int32_t>(),
+                                  f->cflag.as<uint8_t>())) != ISDF_OK)
+      return st;
+    std::vector<int32_t> nc(cd.size());
+    ISDF_HIP_TRY(hipMemcpyAsync(nc.data(), d_nc.p, sizeof(int32_t) * nc.size(), hipMemcpyDeviceToHost, s));
+    ISDF_HIP_TRY(hipStreamSynchronize(s));
+    for (size_t i = 0; i < cd.size(); ++i) nc_host[cd_id[i]] = nc[i];
+  }
+  // compact candidate rows, select on them, map pivots back
+  std::vector<GatherRows> gr;
+  std::vector<SelSpec> cs;
+  std::vector<int64_t> cpoff;
+  int64_t phic = 0, dgc = 0, pvc = 0;
+  int max_nc = 0;
+  for (int d : cid) {
+    const HostDomain& D = hp.domains[d];
+    GatherRows g{};
+    g.phi_off = pl->phi_off[d];
+    g.diag_off = pl->pts_off[d];
+    g.phic_off = phic;
+    g.diagc_off = dgc;
+    g.cand_off = pl->pts_off[d];
+    g.pts = (int)D.points.size();
+    g.nG = (int)D.funcs.size();
+    g.nc = nc_host[d];
+    gr.push_back(g);
+    cs.push_back(SelSpec{D.level, g.nc, g.nG, D.nL, std::min(D.n_mu, g.nc), phic, dgc});
+    cpoff.push_back(pvc);
+    phic += (int64_t)g.nc * g.nG;
+    dgc += g.nc;
+    pvc += D.n_mu;
+    max_nc = std::max(max_nc, g.nc);
+    f->ncand[d] = g.nc;
+  }
+  DevBuf d_gr, phic_b, diagc_b, pivc;
+  if ((st = upload(d_gr, gr)) != ISDF_OK) return st;
+  if ((st = phic_b.alloc(sizeof(double) * std::max<int64_t>(phic, 1))) != ISDF_OK) return st;
+  if ((st = diagc_b.alloc(sizeof(double) * std::max<int64_t>(dgc, 1))) != ISDF_OK) return st;
+  if ((st = pivc.alloc(sizeof(int32_t) * std::max<int64_t>(pvc, 1))) != ISDF_OK) return st;
+  if ((st = launch_gather_rows(s, d_gr.as<GatherRows>(), (int)gr.size(), max_nc, f->phi.as<double>(),
+                               f->diag0.as<double>(), cand.as<int32_t>(), phic_b.as<double>(),
+                               diagc_b.as<double>())) != ISDF_OK)
+    return st;
+  if ((st = select_points(pl, cs, phic_b.as<double>(), diagc_b.as<double>(), pivc.as<int32_t>(), cpoff,
+                          cnt, dl)) != ISDF_OK)
+    return st;
+  for (size_t i = 0; i < cid.size(); ++i) {
+    const int d = cid[i];
+    f->count[d] = cnt[i];
+    f->dlast[d] = dl[i];
+    if ((st = launch_map_pivots(s, cand.as<int32_t>(), pl->pts_off[d], pivc.as<int32_t>() + cpoff[i],
+                                f->piv.as<int32_t>() + f->piv_off[d], cnt[i])) != ISDF_OK)
+      return st;
+  }
+  // Exactness check: residual diagonals never grow, so when every point left
+  // out has an initial diagonal below (1 - tie_tol) times the residual of the
+  // last pivot, none of them could have entered the tie window of any step
+  // and the pivots are those of the full selection.  Learned candidate sets
+  // that fail (or stop short of n_mu points) are selected again in full.
+  std::vector<JudgeDomain> jd;
+  for (int d : cid) jd.push_back(JudgeDomain{pl->pts_off[d], 0, (int)hp.domains[d].points.size(), 0});
+  DevBuf d_jd, d_out;
+  if ((st = upload(d_jd, jd)) != ISDF_OK) return st;
+  if ((st = d_out.alloc(sizeof(double) * jd.size())) != ISDF_OK) return st;
+  if ((st = launch_excluded_max(s, d_jd.as<JudgeDomain>(), (int)jd.size(), f->diag0.as<double>(),
+                                f->cflag.as<uint8_t>(), d_out.as<double>())) != ISDF_OK)
+    return st;
+  std::vector<double> ho(jd.size());
+  ISDF_HIP_TRY(hipMemcpyAsync(ho.data(), d_out.p, sizeof(double) * ho.size(), hipMemcpyDeviceToHost, s));
   ISDF_HIP_TRY(hipStreamSynchronize(s));
-  for (int d = 0; d < nd; ++d) f->count[d] = hs[d].count;
+  std::vector<SelSpec> redo;
+  std::vector<int> redo_id;
+  std::vector<int64_t> redo_poff;
+  for (size_t i = 0; i < cid.size(); ++i) {
+    const int d = cid[i];
+    f->dfinal[d] = ho[i];
+    const bool exact = ho[i] < (1.0 - hp.tie_tol) * f->dlast[d];
+    const bool short_of_points = f->count[d] < hp.domains[d].n_mu;
+    if (exact && !short_of_points) continue;
+    f->fallback[d] = 1;
+    if (mode[d] != 1) continue;  // caller-given candidates: report only
+    const HostDomain& D = hp.domains[d];
+    redo.push_back(SelSpec{D.level, (int)D.points.size(), (int)D.funcs.size(), D.nL, D.n_mu,
+                           pl->phi_off[d], pl->pts_off[d]});
+    redo_id.push_back(d);
+    redo_poff.push_back(f->piv_off[d]);
+  }
+  if (!redo.empty()) {
+    // dwork still holds the untouched initial diagonals of these domains
+    if ((st = select_points(pl, redo, f->phi.as<double>(), f->dwork.as<double>(), f->piv.as<int32_t>(),
+                            redo_poff, cnt, dl)) != ISDF_OK)
+      return st;
+    for (size_t i = 0; i < redo.size(); ++i) {
+      f->count[redo_id[i]] = cnt[i];
+      f->dlast[redo_id[i]] = dl[i];
+      f->ncand[redo_id[i]] = redo[i].pts;
+    }
+  }
+  ISDF_HIP_TRY(hipStreamSynchronize(s));
   return ISDF_OK;
 }
 
@@ -643,6 +1005,17 @@ isdf_status run_coulomb(isdf_plan_s* pl, isdf_fit_s* f) {
     }
   }
   if ((st = upload(d_probs, probs)) != ISDF_OK) return st;
+  // mixed precision for the universal rows (the level-0 row block has one
+  // domain whose points are the whole grid, so no row gather is involved)
+  const bool w_mixed = mixed_on(pl, ISDF_MIX_W) && nd > 0 && hp.domains[0].atom < 0 &&
+                       hp.domains[0].level == 0 && f->count[0] > 0;
+  Planes Fp0, Vp0;
+  if (w_mixed) {
+    const int64_t pts0 = (int64_t)hp.domains[0].points.size();
+    if ((st = make_planes(s, mixed_splits(pl), f->F.as<double>() + f->th_off[0], pts0, 1, nullptr,
+                          f->count[0], (int)pts0, Fp0)) != ISDF_OK)
+      return st;
+  }
   // the scatter slot of a column is its position within its FFT batch
   for (auto& ch : chunks) {
     const int64_t pairs_max = std::max<int64_t>(1, (ngz_max * fft_pairs) / level_ng(hp, ch.lp));
@@ -683,9 +1056,21 @@ isdf_status run_coulomb(isdf_plan_s* pl, isdf_fit_s* f) {
     for (int l = 0; l <= lp; ++l) {
       const GemmLaunch& gl = glaunch[ci][l];
       if (gl.cnt == 0) continue;
-      ProfScope ps(pl, ISDF_K_GEMM_FIT, gl.bytes, gl.flops);
+      if (l == 0 && w_mixed) {
+        const int64_t ng0 = level_ng(hp, 0);
+        const int w = (int)(ch.c1 - ch.c0);
+        if ((st = make_planes(s, mixed_splits(pl), V.as<double>(), ng0, 1, nullptr, w, (int)ng0, Vp0)) !=
+            ISDF_OK)
+          return st;
+        MixedProblem mp = mixed_problem(Fp0, Vp0, f->W.as<double>() + f->xoff[0] + ch.c0 * nmu, nmu,
+                                        f->count[0], w, (int)ng0, hp.volume / (double)ng0, 0.0,
+                                        nullptr, 0);
+        if ((st = mixed_prof(pl, ISDF_K_GEMM_METRIC, EPI_AXPBY, mp)) != ISDF_OK) return st;
+        continue;
+      }
+      ProfScope ps(pl, ISDF_K_GEMM_METRIC, gl.bytes, gl.flops);
       if ((st = gemm_f64_grouped(s, EPI_AXPBY, d_probs.as<GemmProblem>() + gl.off, gl.cnt,
-                                 gl.tiles)) != ISDF_OK)
+                                 gl.tiles, family_tag(ISDF_K_GEMM_METRIC))) != ISDF_OK)
         return st;
     }
   }
@@ -700,7 +1085,8 @@ isdf_status run_coulomb(isdf_plan_s* pl, isdf_fit_s* f) {
   return ISDF_OK;
 }
 
-isdf_status do_fit(isdf_plan_s* pl, const int64_t* pinned, isdf_fit_t* out) {
+isdf_status do_fit(isdf_plan_s* pl, const int64_t* pinned, const int64_t* cand_in,
+                   const int64_t* ncand_in, const std::vector<int>* force_full, isdf_fit_t* out) {
   if (!pl || !out) {
     set_error("isdf_fit: null argument");
     return ISDF_E_ARG;
@@ -717,19 +1103,31 @@ isdf_status do_fit(isdf_plan_s* pl, const int64_t* pinned, isdf_fit_t* out) {
   if ((st = f->phi.alloc(sizeof(double) * std::max<int64_t>(pl->phi_total, 1))) != ISDF_OK) return st;
   if ((st = f->diag0.alloc(sizeof(double) * pl->pts_total)) != ISDF_OK) return st;
   if ((st = f->dwork.alloc(sizeof(double) * pl->pts_total)) != ISDF_OK) return st;
+  if ((st = f->aux.alloc(sizeof(double) * 4 * pl->pts_total)) != ISDF_OK) return st;
   double basis_bytes = 8.0 * ((double)pl->phi_total + pl->pts_total);
   ProfScope ps_basis(pl, ISDF_K_BASIS, basis_bytes, 0.0);
   if ((st = launch_basis_eval(s, pl->lat, pl->d_shells.as<ShellDev>(), pl->d_img.as<double>(),
                               pl->d_colshells.as<ColShell>(), pl->d_doms.as<DomainDev>(),
                               pl->d_points.as<int32_t>(), pl->d_tiles.as<BasisTile>(),
-                              pl->ntiles_basis, f->phi.as<double>(), f->diag0.as<double>())) != ISDF_OK)
+                              pl->ntiles_basis, f->phi.as<double>(), f->diag0.as<double>(),
+                              f->aux.as<double>())) != ISDF_OK)
     return st;
   ps_basis.finish();
   ISDF_HIP_TRY(hipMemcpyAsync(f->dwork.p, f->diag0.p, sizeof(double) * pl->pts_total,
                               hipMemcpyDeviceToDevice, s));
   ISDF_HIP_TRY(hipEventRecord(pl->ev[1], s));
   // 2. selection
-  if ((st = run_selection(pl, f.get(), pinned)) != ISDF_OK) return st;
+  f->mode.assign(nd, 0);
+  for (int d = 0; d < nd; ++d) {
+    const int pts = (int)hp.domains[d].points.size();
+    if (cand_in) {
+      f->mode[d] = 2;
+    } else if (pl->opts.selector == ISDF_SEL_MLP && !(force_full && (*force_full)[d])) {
+      const int keep = (int)std::ceil(pl->opts.mlp_keep * (double)hp.domains[d].n_mu);
+      f->mode[d] = keep < pts ? 1 : 0;
+    }
+  }
+  if ((st = run_selection(pl, f.get(), pinned, f->mode, cand_in, ncand_in)) != ISDF_OK) return st;
   ISDF_HIP_TRY(hipEventRecord(pl->ev[2], s));
   bool rank_short = false;
   f->xoff.assign(nd, 0);
@@ -804,17 +1202,45 @@ isdf_status do_fit(isdf_plan_s* pl, const int64_t* pinned, isdf_fit_t* out) {
       tiles += gemm_tiles(p.M, p.N);
       probs.push_back(p);
     }
-    DevBuf d_probs;
-    if ((st = upload(d_probs, probs)) != ISDF_OK) return st;
-    double by = 0.0, fl = 0.0;
-    for (auto& p : probs) {
-      by += gemm_bytes(p);
-      fl += gemm_flops(p);
+    if (mixed_on(pl, ISDF_MIX_THETA)) {
+      // per domain: planes of Phi_d and of its pivot rows with the L columns
+      // padded to a multiple of 32 so that no k chunk straddles the L/N split
+      const int S = mixed_splits(pl);
+      Planes Ap, Bp;
+      DevBuf kx;
+      for (int d = 0; d < nd; ++d) {
+        if (f->count[d] == 0) continue;
+        const int nL = gd[d].nL, nG = gd[d].nG, padL = (nL + 31) / 32 * 32;
+        std::vector<int32_t> kidx(padL + (nG - nL));
+        for (int c = 0; c < padL; ++c) kidx[c] = c < nL ? c : -1;
+        for (int c = nL; c < nG; ++c) kidx[padL + c - nL] = c;
+        if ((st = upload(kx, kidx)) != ISDF_OK) return st;
+        const int Kp = (int)kidx.size();
+        if ((st = make_planes(s, S, f->phi.as<double>() + pl->phi_off[d], 1, gd[d].pts,
+                              kx.as<int32_t>(), gd[d].pts, Kp, Ap)) != ISDF_OK)
+          return st;
+        if ((st = make_planes(s, S, f->xrows.as<double>() + f->xrow_off[d], nG, 1, kx.as<int32_t>(),
+                              f->count[d], Kp, Bp)) != ISDF_OK)
+          return st;
+        MixedProblem mp = mixed_problem(Ap, Bp, f->theta.as<double>() + f->th_off[d], gd[d].pts,
+                                        gd[d].pts, f->count[d], Kp, 1.0, 0.0, nullptr, 0);
+        mp.kL = padL;
+        if ((st = mixed_prof(pl, ISDF_K_GEMM_FIT, EPI_THETA, mp)) != ISDF_OK) return st;
+        ISDF_HIP_TRY(hipStreamSynchronize(s));  // planes and index are reused
+      }
+    } else {
+      DevBuf d_probs;
+      if ((st = upload(d_probs, probs)) != ISDF_OK) return st;
+      double by = 0.0, fl = 0.0;
+      for (auto& p : probs) {
+        by += gemm_bytes(p);
+        fl += gemm_flops(p);
+      }
+      ProfScope ps(pl, ISDF_K_GEMM_FIT, by, fl);
+      if ((st = gemm_f64_grouped(s, EPI_THETA, d_probs.as<GemmProblem>(), (int)probs.size(), tiles,
+                                 family_tag(ISDF_K_GEMM_FIT))) != ISDF_OK)
+        return st;
     }
-    ProfScope ps(pl, ISDF_K_GEMM_FIT, by, fl);
-    if ((st = gemm_f64_grouped(s, EPI_THETA, d_probs.as<GemmProblem>(), (int)probs.size(), tiles)) !=
-        ISDF_OK)
-      return st;
     ISDF_HIP_TRY(hipStreamSynchronize(s));
   }
   ISDF_HIP_TRY(hipEventRecord(pl->ev[4], s));
@@ -904,13 +1330,30 @@ isdf_status isdf_plan(const isdf_system* sys, const isdf_options* opts, isdf_pla
   isdf_status st = build_host_plan(sys, pl->hp);
   if (st != ISDF_OK) return st;
   if (opts) pl->opts = *opts;
-  if (pl->opts.precision != ISDF_FP64) {
-    set_error("isdf_plan: only ISDF_FP64 is available in this build");
-    return ISDF_E_UNSUPPORTED;
+  if (pl->opts.precision != ISDF_FP64 && pl->opts.precision != ISDF_MIXED_X3 &&
+      pl->opts.precision != ISDF_MIXED_X6) {
+    set_error("isdf_plan: unknown precision");
+    return ISDF_E_ARG;
   }
-  if (pl->opts.selector != ISDF_SEL_FULL) {
-    set_error("isdf_plan: only full selection is available in this build");
-    return ISDF_E_UNSUPPORTED;
+  if (pl->opts.mixed_mask < 0 || pl->opts.mixed_mask > 7) {
+    set_error("isdf_plan: mixed_mask must be within 0..7");
+    return ISDF_E_ARG;
+  }
+  if (pl->opts.selector == ISDF_SEL_MLP) {
+    if (!pl->opts.mlp_weights || !(pl->opts.mlp_keep >= 1.0)) {
+      set_error("isdf_plan: the learned selector needs weights and mlp_keep >= 1");
+      return ISDF_E_ARG;
+    }
+    pl->mlp_w.assign(pl->opts.mlp_weights, pl->opts.mlp_weights + MLP_NPARAM);
+    for (float v : pl->mlp_w)
+      if (!std::isfinite(v)) {
+        set_error("isdf_plan: non-finite network weight");
+        return ISDF_E_ARG;
+      }
+    pl->opts.mlp_weights = nullptr;
+  } else if (pl->opts.selector != ISDF_SEL_FULL) {
+    set_error("isdf_plan: unknown selector");
+    return ISDF_E_ARG;
   }
   pl->stream = static_cast<hipStream_t>(pl->opts.stream);
   *out = pl.release();
@@ -966,7 +1409,7 @@ isdf_status isdf_plan_domain_functions(isdf_plan_t plan, int32_t d, int32_t* fun
 
 isdf_status isdf_fit(isdf_plan_t plan, isdf_fit_t* out) {
   if (out) *out = nullptr;
-  return do_fit(plan, nullptr, out);
+  return do_fit(plan, nullptr, nullptr, nullptr, nullptr, out);
 }
 
 isdf_status isdf_fit_with_points(isdf_plan_t plan, const int64_t* local_points, isdf_fit_t* out) {
@@ -975,7 +1418,170 @@ isdf_status isdf_fit_with_points(isdf_plan_t plan, const int64_t* local_points, 
     set_error("isdf_fit_with_points: null points");
     return ISDF_E_ARG;
   }
-  return do_fit(plan, local_points, out);
+  return do_fit(plan, local_points, nullptr, nullptr, nullptr, out);
+}
+
+isdf_status isdf_fit_with_candidates(isdf_plan_t plan, const int64_t* candidates,
+                                     const int64_t* n_candidates, isdf_fit_t* out) {
+  if (out) *out = nullptr;
+  if (!candidates || !n_candidates) {
+    set_error("isdf_fit_with_candidates: null candidates");
+    return ISDF_E_ARG;
+  }
+  return do_fit(plan, nullptr, candidates, n_candidates, nullptr, out);
+}
+
+isdf_status isdf_fit_selection(isdf_fit_t fit, int64_t* n_candidates, double* last_residual,
+                               double* final_residual, int32_t* fallback) {
+  if (!fit) {
+    set_error("isdf_fit_selection: null fit");
+    return ISDF_E_ARG;
+  }
+  const size_t nd = fit->count.size();
+  for (size_t d = 0; d < nd; ++d) {
+    if (n_candidates) n_candidates[d] = fit->ncand.size() == nd ? fit->ncand[d] : 0;
+    if (last_residual) last_residual[d] = fit->dlast.size() == nd ? fit->dlast[d] : 0.0;
+    if (final_residual) final_residual[d] = fit->dfinal.size() == nd ? fit->dfinal[d] : 0.0;
+    if (fallback) fallback[d] = fit->fallback.size() == nd ? fit->fallback[d] : 0;
+  }
+  return ISDF_OK;
+}
+
+isdf_status isdf_fit_features(isdf_fit_t fit, float* features_dev, float* labels_dev,
+                              int64_t capacity, int64_t* n) {
+  if (!fit) {
+    set_error("isdf_fit_features: null fit");
+    return ISDF_E_ARG;
+  }
+  isdf_plan_s* pl = fit->plan;
+  if (n) *n = pl->pts_total;
+  if (!features_dev) return ISDF_OK;  // size query
+  if (capacity < pl->pts_total) {
+    set_error("isdf_fit_features: capacity below the number of points");
+    return ISDF_E_ARG;
+  }
+  isdf_status st = compute_features(pl, fit, features_dev);
+  if (st != ISDF_OK) return st;
+  if (labels_dev) {
+    std::vector<float> lab(pl->pts_total, 0.f);
+    const int nd = (int)pl->hp.domains.size();
+    // needed set: initial diagonal >= (1 - tie_tol) x residual of the last pivot
+    std::vector<double> dg(pl->pts_total);
+    ISDF_HIP_TRY(hipMemcpy(dg.data(), fit->diag0.p, sizeof(double) * pl->pts_total, hipMemcpyDeviceToHost));
+    for (int d = 0; d < nd; ++d) {
+      const double thr = (1.0 - pl->hp.tie_tol) * fit->dlast[d];
+      const int64_t np = (int64_t)pl->hp.domains[d].points.size();
+      for (int64_t i = 0; i < np; ++i) lab[pl->pts_off[d] + i] = dg[pl->pts_off[d] + i] >= thr ? 1.f : 0.f;
+    }
+    ISDF_HIP_TRY(hipMemcpy(labels_dev, lab.data(), sizeof(float) * lab.size(), hipMemcpyHostToDevice));
+  }
+  return ISDF_OK;
+}
+
+isdf_status isdf_mlp_forward(const float* weights, const float* features_dev, int64_t n,
+                             float* scores_dev, void* stream) {
+  if (!weights || !features_dev || !scores_dev || n < 0) {
+    set_error("isdf_mlp_forward: bad argument");
+    return ISDF_E_ARG;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  DevBuf w;
+  isdf_status st;
+  if ((st = upload(w, std::vector<float>(weights, weights + MLP_NPARAM))) != ISDF_OK) return st;
+  if ((st = launch_mlp_forward(s, w.as<float>(), features_dev, n, scores_dev)) != ISDF_OK) return st;
+  ISDF_HIP_TRY(hipStreamSynchronize(s));
+  return ISDF_OK;
+}
+
+isdf_status isdf_mlp_loss_grad(const float* weights, const float* features_dev,
+                               const float* labels_dev, int64_t n, float pos_weight, float* grad,
+                               float* loss, void* stream) {
+  if (!weights || !features_dev || !labels_dev || n <= 0) {
+    set_error("isdf_mlp_loss_grad: bad argument");
+    return ISDF_E_ARG;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  isdf_status st;
+  DevBuf w, part, lpart, g, l;
+  const int64_t nblk = (n + 31) / 32;
+  if ((st = upload(w, std::vector<float>(weights, weights + MLP_NPARAM))) != ISDF_OK) return st;
+  if ((st = part.alloc(sizeof(float) * nblk * MLP_NPARAM)) != ISDF_OK) return st;
+  if ((st = lpart.alloc(sizeof(float) * nblk)) != ISDF_OK) return st;
+  if ((st = g.alloc(sizeof(float) * MLP_NPARAM)) != ISDF_OK) return st;
+  if ((st = l.alloc(sizeof(float))) != ISDF_OK) return st;
+  if ((st = launch_mlp_grad(s, w.as<float>(), features_dev, labels_dev, nullptr, 0, n, pos_weight,
+                            1.0f / (float)n, part.as<float>(), lpart.as<float>(), g.as<float>(),
+                            l.as<float>())) != ISDF_OK)
+    return st;
+  float lh = 0.f;
+  if (grad) ISDF_HIP_TRY(hipMemcpyAsync(grad, g.p, sizeof(float) * MLP_NPARAM, hipMemcpyDeviceToHost, s));
+  ISDF_HIP_TRY(hipMemcpyAsync(&lh, l.p, sizeof(float), hipMemcpyDeviceToHost, s));
+  ISDF_HIP_TRY(hipStreamSynchronize(s));
+  if (loss) *loss = lh / (float)n;
+  return ISDF_OK;
+}
+
+isdf_status isdf_mlp_train(const float* features_dev, const float* labels_dev, int64_t n,
+                           const isdf_mlp_config* cfg, float* weights, float* epoch_loss) {
+  if (!features_dev || !labels_dev || !cfg || !weights || n <= 0 || cfg->epochs <= 0 ||
+      cfg->batch <= 0) {
+    set_error("isdf_mlp_train: bad argument");
+    return ISDF_E_ARG;
+  }
+  hipStream_t s = static_cast<hipStream_t>(cfg->stream);
+  isdf_status st;
+  float pw = cfg->pos_weight;
+  if (!(pw > 0.f)) {
+    std::vector<float> lab(n);
+    ISDF_HIP_TRY(hipMemcpy(lab.data(), labels_dev, sizeof(float) * n, hipMemcpyDeviceToHost));
+    double pos = 0.0;
+    for (float v : lab) pos += v;
+    pw = pos > 0.0 ? (float)((n - pos) / pos) : 1.f;
+  }
+  const int64_t B = std::min<int64_t>(cfg->batch, n);
+  const int64_t nblk = (B + 31) / 32;
+  const int64_t nbatch = (n + B - 1) / B;
+  DevBuf w, m, v, g, part, lpart, lbuf, perm;
+  if ((st = upload(w, std::vector<float>(weights, weights + MLP_NPARAM))) != ISDF_OK) return st;
+  if ((st = upload(m, std::vector<float>(MLP_NPARAM, 0.f))) != ISDF_OK) return st;
+  if ((st = upload(v, std::vector<float>(MLP_NPARAM, 0.f))) != ISDF_OK) return st;
+  if ((st = g.alloc(sizeof(float) * MLP_NPARAM)) != ISDF_OK) return st;
+  if ((st = part.alloc(sizeof(float) * nblk * MLP_NPARAM)) != ISDF_OK) return st;
+  if ((st = lpart.alloc(sizeof(float) * nblk)) != ISDF_OK) return st;
+  if ((st = lbuf.alloc(sizeof(float) * nbatch)) != ISDF_OK) return st;
+  if ((st = perm.alloc(sizeof(int32_t) * n)) != ISDF_OK) return st;
+  std::vector<int32_t> hp(n);
+  uint64_t state = 0x9E3779B97F4A7C15ull ^ (uint64_t)cfg->seed;
+  auto next = [&]() {  // splitmix64
+    uint64_t z = (state += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+  };
+  int t = 0;
+  std::vector<float> lb(nbatch);
+  for (int ep = 0; ep < cfg->epochs; ++ep) {
+    for (int64_t i = 0; i < n; ++i) hp[i] = (int32_t)i;
+    for (int64_t i = n - 1; i > 0; --i) std::swap(hp[i], hp[(int64_t)(next() % (uint64_t)(i + 1))]);
+    ISDF_HIP_TRY(hipMemcpyAsync(perm.p, hp.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
+    for (int64_t b = 0; b < nbatch; ++b) {
+      const int64_t b0 = b * B, bn = std::min(B, n - b0);
+      if ((st = launch_mlp_grad(s, w.as<float>(), features_dev, labels_dev, perm.as<int32_t>(), b0, bn,
+                                pw, 1.0f / (float)bn, part.as<float>(), lpart.as<float>(),
+                                g.as<float>(), lbuf.as<float>() + b)) != ISDF_OK)
+        return st;
+      if ((st = launch_adam(s, w.as<float>(), g.as<float>(), m.as<float>(), v.as<float>(), cfg->lr,
+                            cfg->beta1, cfg->beta2, cfg->eps, ++t)) != ISDF_OK)
+        return st;
+    }
+    ISDF_HIP_TRY(hipMemcpyAsync(lb.data(), lbuf.p, sizeof(float) * nbatch, hipMemcpyDeviceToHost, s));
+    ISDF_HIP_TRY(hipStreamSynchronize(s));
+    double tot = 0.0;
+    for (float x : lb) tot += x;
+    if (epoch_loss) epoch_loss[ep] = (float)(tot / (double)n);
+  }
+  ISDF_HIP_TRY(hipMemcpy(weights, w.p, sizeof(float) * MLP_NPARAM, hipMemcpyDeviceToHost));
+  return ISDF_OK;
 }
 
 isdf_status isdf_fit_info(isdf_fit_t fit, int64_t* n_mu) {
@@ -1116,6 +1722,41 @@ isdf_status isdf_exchange(isdf_plan_t plan, isdf_fit_t fit, const double* D, dou
     return gemm_prof(plan, ISDF_K_GEMM_EXCHANGE, epi, p);
   };
   const int m = (int)nmu, n = (int)N;
+  if (mixed_on(plan, ISDF_MIX_EXCHANGE)) {
+    const int S = mixed_splits(plan);
+    if (!fit->xg_row.buf.p) {  // fit-time operands, split once
+      if ((st = make_planes(s, S, XG, 1, nmu, nullptr, m, n, fit->xg_row)) != ISDF_OK) return st;
+      if ((st = make_planes(s, S, XL, 1, nmu, nullptr, m, n, fit->xl_row)) != ISDF_OK) return st;
+      if ((st = make_planes(s, S, XL, nmu, 1, nullptr, n, m, fit->xl_col)) != ISDF_OK) return st;
+      if ((st = make_planes(s, S, XN, nmu, 1, nullptr, n, m, fit->xn_col)) != ISDF_OK) return st;
+    }
+    auto mg = [&](int epi, const Planes& A, const Planes& B, double* C, int64_t ldc, int M, int Nn,
+                  int Kk, double alpha, double beta) {
+      return mixed_prof(plan, ISDF_K_GEMM_EXCHANGE, epi,
+                        mixed_problem(A, B, C, ldc, M, Nn, Kk, alpha, beta, W, nmu));
+    };
+    // D as B operand: (k = nu, n = lam) -> plane row lam, column nu
+    if ((st = make_planes(s, S, D, N, 1, nullptr, n, n, fit->Dp)) != ISDF_OK) return st;
+    if ((st = mg(EPI_AXPBY, fit->xg_row, fit->Dp, EG, nmu, m, n, n, 1.0, 0.0)) != ISDF_OK) return st;
+    if ((st = mg(EPI_AXPBY, fit->xl_row, fit->Dp, EL, nmu, m, n, n, 1.0, 0.0)) != ISDF_OK) return st;
+    if ((st = make_planes(s, S, EG, 1, nmu, nullptr, m, n, fit->EGp)) != ISDF_OK) return st;
+    if ((st = make_planes(s, S, EL, 1, nmu, nullptr, m, n, fit->ELp)) != ISDF_OK) return st;
+    if ((st = mg(EPI_HADAMARD, fit->EGp, fit->xg_row, QGG, nmu, m, m, n, 1.0, 0.0)) != ISDF_OK) return st;
+    if ((st = mg(EPI_HADAMARD, fit->EGp, fit->xl_row, QGL, nmu, m, m, n, 1.0, 0.0)) != ISDF_OK) return st;
+    if ((st = mg(EPI_HADAMARD, fit->ELp, fit->xl_row, QLL, nmu, m, m, n, 1.0, 0.0)) != ISDF_OK) return st;
+    if ((st = make_planes(s, S, QGG, 1, nmu, nullptr, m, m, fit->QGGp)) != ISDF_OK) return st;
+    if ((st = make_planes(s, S, QGL, 1, nmu, nullptr, m, m, fit->QGLp)) != ISDF_OK) return st;
+    if ((st = make_planes(s, S, QGL, nmu, 1, nullptr, m, m, fit->QGLTp)) != ISDF_OK) return st;
+    if ((st = make_planes(s, S, QLL, 1, nmu, nullptr, m, m, fit->QLLp)) != ISDF_OK) return st;
+    if ((st = mg(EPI_AXPBY, fit->QGGp, fit->xl_col, Y1, nmu, m, n, m, 1.0, 0.0)) != ISDF_OK) return st;
+    if ((st = mg(EPI_AXPBY, fit->QGLp, fit->xn_col, Y1, nmu, m, n, m, 1.0, 1.0)) != ISDF_OK) return st;
+    if ((st = mg(EPI_AXPBY, fit->QGLTp, fit->xl_col, Y2, nmu, m, n, m, 1.0, 0.0)) != ISDF_OK) return st;
+    if ((st = mg(EPI_AXPBY, fit->QLLp, fit->xn_col, Y2, nmu, m, n, m, 1.0, 1.0)) != ISDF_OK) return st;
+    if ((st = make_planes(s, S, Y1, nmu, 1, nullptr, n, m, fit->Y1p)) != ISDF_OK) return st;
+    if ((st = make_planes(s, S, Y2, nmu, 1, nullptr, n, m, fit->Y2p)) != ISDF_OK) return st;
+    if ((st = mg(EPI_AXPBY, fit->xl_col, fit->Y1p, K, N, n, n, m, -1.0, 0.0)) != ISDF_OK) return st;
+    if ((st = mg(EPI_AXPBY, fit->xn_col, fit->Y2p, K, N, n, n, m, -1.0, 1.0)) != ISDF_OK) return st;
+  } else {
   // E_G = X^G D, E_L = X^L D
   if ((st = gemm(EPI_AXPBY, XG, nmu, 0, D, N, 0, EG, nmu, m, n, n, 1.0, 0.0, nullptr)) != ISDF_OK) return st;
   if ((st = gemm(EPI_AXPBY, XL, nmu, 0, D, N, 0, EL, nmu, m, n, n, 1.0, 0.0, nullptr)) != ISDF_OK) return st;
@@ -1131,6 +1772,7 @@ isdf_status isdf_exchange(isdf_plan_t plan, isdf_fit_t fit, const double* D, dou
   // K = -(X^L^T Y1 + X^N^T Y2)
   if ((st = gemm(EPI_AXPBY, XL, nmu, 1, Y1, nmu, 0, K, N, n, n, m, -1.0, 0.0, nullptr)) != ISDF_OK) return st;
   if ((st = gemm(EPI_AXPBY, XN, nmu, 1, Y2, nmu, 0, K, N, n, n, m, -1.0, 1.0, nullptr)) != ISDF_OK) return st;
+  }
   ISDF_HIP_TRY(hipEventRecord(plan->ev[1], s));
   if ((st = launch_trace_dot(s, D, K, N * N, fit->partial.as<double>(), 1024,
                              fit->ex_out.as<double>())) != ISDF_OK)

@@ -96,9 +96,11 @@ struct GemmProblem {
 
 // Launch one problem or a group (device array of problems, tile_start
 // filled by the caller, total_tiles = sum of tiles).
-isdf_status gemm_f64(hipStream_t s, int epi, const GemmProblem& p);
+// tag: 0 generic, 1 selection Gram / residual updates, 2 Coulomb metric,
+// 3 fit (Theta, Cholesky, solves), 4 exchange
+isdf_status gemm_f64(hipStream_t s, int epi, const GemmProblem& p, int tag = 0);
 isdf_status gemm_f64_grouped(hipStream_t s, int epi, const GemmProblem* d_probs, int nprob,
-                             int total_tiles);
+                             int total_tiles, int tag = 0);
 int gemm_tiles(int M, int N);
 
 // ------------------------------------------------------------ other kernels
@@ -120,10 +122,12 @@ struct LatticeArg {
   double ln_inv_tau;
   int32_t grid[8][3];
 };
+// aux (optional, 4 per point): a_L, a_N, max_{mu in L} mu^2, sum_{mu in L} mu
 isdf_status launch_basis_eval(hipStream_t s, const LatticeArg& lat, const ShellDev* shells,
                               const double* img, const ColShell* colshells,
                               const DomainDev* doms, const int32_t* points,
-                              const BasisTile* tiles, int ntiles, double* phi, double* diag);
+                              const BasisTile* tiles, int ntiles, double* phi, double* diag,
+                              double* aux);
 
 // Selection (pivoted Cholesky) over a batch of domains.
 struct SelDomain {
@@ -212,5 +216,86 @@ isdf_status launch_symmetrize_w(hipStream_t s, double* W, int64_t nmu, const int
 isdf_status launch_add(hipStream_t s, const double* a, const double* b, double* c, int64_t n);
 isdf_status launch_trace_dot(hipStream_t s, const double* a, const double* b, int64_t n,
                              double* partial, int nblk, double* out);
+
+// ------------------------------------------------------- mixed precision
+// BF16-split GEMM problem: A planes hold (m, k) at A + p plane_a + m lda + k,
+// B planes hold (k, n) at B + p plane_b + n ldb + k (k-contiguous, lda, ldb,
+// plane strides multiples of 8).  Epilogues as for the FP64 engine; with
+// EPI_THETA the split point kL must be a multiple of 32.
+struct MixedProblem {
+  const __bf16* A;
+  const __bf16* B;
+  double* C;
+  const double* E;
+  int64_t plane_a, plane_b, lda, ldb, ldc, lde;
+  int32_t M, N, K, kL;
+  double alpha, beta;
+  int32_t tile_start;
+  int32_t lower;
+};
+isdf_status gemm_mixed(hipStream_t s, int epi, int splits, const MixedProblem& p, int tag = 4);
+isdf_status gemm_mixed_grouped(hipStream_t s, int epi, int splits, const MixedProblem* d_probs,
+                               int nprob, int total_tiles, int tag = 4);
+int mixed_tiles(int M, int N);
+// planes[p][o][k] (ld ldd, plane stride `plane`) of scale * src[o so + ks sk],
+// ks = kidx ? kidx[k] : k (kidx[k] < 0 gives 0)
+isdf_status launch_split_bf16(hipStream_t s, const double* src, int64_t so, int64_t sk,
+                              const int32_t* kidx, int rows, int cols, int splits, __bf16* dst,
+                              int64_t ldd, int64_t plane, double scale);
+
+// ------------------------------------------------------- learned selector
+constexpr int MLP_NPARAM = 64 * 16 + 64 + 64 * 64 + 64 + 64 + 1;  // 5313
+struct MlpGeom {
+  double lat[9];
+  double inv[9];
+  int32_t n_atoms;
+  int32_t n_levels;
+};
+struct MlpDomain {
+  int64_t pts_off;
+  int32_t pts, level, atom, nL, n_mu;
+  int32_t grid[3];
+  double rs, h, gmax, gmean;
+};
+struct CandDomain {
+  int64_t pts_off, cand_off;
+  int32_t pts, keep;
+};
+struct GatherRows {
+  int64_t phi_off, diag_off, phic_off, diagc_off, cand_off;
+  int32_t pts, nG, nc, pad;
+};
+struct JudgeDomain {
+  int64_t diag_off, th_off;
+  int32_t pts, n;
+};
+isdf_status launch_diag_stats(hipStream_t s, MlpDomain* doms, int ndom, const double* diag);
+isdf_status launch_features(hipStream_t s, const MlpGeom& g, const MlpDomain* doms,
+                            const int32_t* points, const BasisTile* tiles, int ntiles,
+                            const double* aux, const double* diag, const double* atoms,
+                            float* feats);
+isdf_status launch_mlp_forward(hipStream_t s, const float* w, const float* X, int64_t n, float* z);
+size_t mlp_grad_shmem();
+// gradient of sum_p l_p * inv_count over batch rows [b0, b0 + bn) (through perm if given)
+isdf_status launch_mlp_grad(hipStream_t s, const float* w, const float* X, const float* Y,
+                            const int32_t* perm, int64_t b0, int64_t bn, float pw,
+                            float inv_count, float* partial, float* lpart, float* grad,
+                            float* loss);
+isdf_status launch_adam(hipStream_t s, float* w, const float* g, float* m, float* v, float lr,
+                        float b1, float b2, float eps, int t);
+// candidates = the `keep` best logits of each domain plus every logit >= zcut;
+// flag[pts_off + i] = 1 for candidates
+isdf_status launch_topk_compact(hipStream_t s, const CandDomain* doms, int ndom, const float* z,
+                                float zcut, int32_t* cand, int32_t* ncand, uint8_t* flag);
+isdf_status launch_excluded_max(hipStream_t s, const JudgeDomain* doms, int ndom,
+                                const double* diag, const uint8_t* flag, double* out);
+isdf_status launch_gather_rows(hipStream_t s, const GatherRows* g, int ndom, int max_nc,
+                               const double* phi, const double* diag, const int32_t* cand,
+                               double* phic, double* diagc);
+isdf_status launch_map_pivots(hipStream_t s, const int32_t* cand, int64_t cand_off,
+                              const int32_t* pivc, int32_t* piv, int n);
+isdf_status launch_final_residual(hipStream_t s, const JudgeDomain* doms, int ndom,
+                                  const double* diag, const double* theta, const double* F,
+                                  double* out);
 
 }  // namespace isdf

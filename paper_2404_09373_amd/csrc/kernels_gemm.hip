@@ -36,7 +36,9 @@ __device__ inline const GemmProblem* find_problem(const GemmProblem* probs, int 
 }
 }  // namespace
 
-template <int EPI>
+// TAG only separates the instantiations per role (selection Gram, Coulomb
+// metric, fit solves, exchange) so that profiles attribute time per role.
+template <int EPI, int TAG>
 __global__ void __launch_bounds__(256)
 gemm_f64_kernel(GemmProblem single, const GemmProblem* __restrict__ probs, int nprob) {
   const GemmProblem* pp = probs ? find_problem(probs, nprob, blockIdx.x) : &single;
@@ -200,45 +202,53 @@ gemm_f64_kernel(GemmProblem single, const GemmProblem* __restrict__ probs, int n
 
 int gemm_tiles(int M, int N) { return ((M + BM - 1) / BM) * ((N + BN - 1) / BN); }
 
-static isdf_status launch(hipStream_t s, int epi, const GemmProblem& single,
+template <int TAG>
+static void launch_tag(hipStream_t s, int epi, const GemmProblem& single, const GemmProblem* probs,
+                       int nprob, int tiles) {
+  if (epi == EPI_THETA)
+    hipLaunchKernelGGL((gemm_f64_kernel<EPI_THETA, TAG>), dim3(tiles), dim3(256), 0, s, single, probs,
+                       nprob);
+  else if (epi == EPI_HADAMARD)
+    hipLaunchKernelGGL((gemm_f64_kernel<EPI_HADAMARD, TAG>), dim3(tiles), dim3(256), 0, s, single,
+                       probs, nprob);
+  else
+    hipLaunchKernelGGL((gemm_f64_kernel<EPI_AXPBY, TAG>), dim3(tiles), dim3(256), 0, s, single, probs,
+                       nprob);
+}
+
+static isdf_status launch(hipStream_t s, int epi, int tag, const GemmProblem& single,
                           const GemmProblem* probs, int nprob, int tiles) {
   if (tiles <= 0) return ISDF_OK;
-  switch (epi) {
-    case EPI_AXPBY:
-      hipLaunchKernelGGL(gemm_f64_kernel<EPI_AXPBY>, dim3(tiles), dim3(256), 0, s, single, probs,
-                         nprob);
-      break;
-    case EPI_THETA:
-      hipLaunchKernelGGL(gemm_f64_kernel<EPI_THETA>, dim3(tiles), dim3(256), 0, s, single, probs,
-                         nprob);
-      break;
-    case EPI_HADAMARD:
-      hipLaunchKernelGGL(gemm_f64_kernel<EPI_HADAMARD>, dim3(tiles), dim3(256), 0, s, single,
-                         probs, nprob);
-      break;
-    default:
-      set_error("gemm: bad epilogue");
-      return ISDF_E_ARG;
+  if (epi != EPI_AXPBY && epi != EPI_THETA && epi != EPI_HADAMARD) {
+    set_error("gemm: bad epilogue");
+    return ISDF_E_ARG;
+  }
+  switch (tag) {
+    case 1: launch_tag<1>(s, epi, single, probs, nprob, tiles); break;
+    case 2: launch_tag<2>(s, epi, single, probs, nprob, tiles); break;
+    case 3: launch_tag<3>(s, epi, single, probs, nprob, tiles); break;
+    case 4: launch_tag<4>(s, epi, single, probs, nprob, tiles); break;
+    default: launch_tag<0>(s, epi, single, probs, nprob, tiles); break;
   }
   ISDF_HIP_TRY(hipGetLastError());
   return ISDF_OK;
 }
 
-isdf_status gemm_f64(hipStream_t s, int epi, const GemmProblem& p) {
+isdf_status gemm_f64(hipStream_t s, int epi, const GemmProblem& p, int tag) {
   if (p.M <= 0 || p.N <= 0) return ISDF_OK;
   GemmProblem q = p;
   q.tile_start = 0;
   if (p.K <= 0) {
     // empty contraction: C = beta C (or zero); run with K = 0 to apply it
   }
-  return launch(s, epi, q, nullptr, 1, gemm_tiles(p.M, p.N));
+  return launch(s, epi, tag, q, nullptr, 1, gemm_tiles(p.M, p.N));
 }
 
 isdf_status gemm_f64_grouped(hipStream_t s, int epi, const GemmProblem* d_probs, int nprob,
-                             int total_tiles) {
+                             int total_tiles, int tag) {
   if (nprob <= 0) return ISDF_OK;
   GemmProblem dummy{};
-  return launch(s, epi, dummy, d_probs, nprob, total_tiles);
+  return launch(s, epi, tag, dummy, d_probs, nprob, total_tiles);
 }
 
 }  // namespace isdf

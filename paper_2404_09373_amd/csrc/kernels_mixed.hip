@@ -1,0 +1,328 @@
+// BF16-split GEMM with FP32 accumulation and FP64 carry (mixed precision).
+//
+// An FP64 operand x is stored as S BF16 planes x = x_0 + x_1 (+ x_2) with
+// x_0 = bf16(x), x_1 = bf16(x - x_0), x_2 = bf16(x - x_0 - x_1).  A product
+// is formed from the planes whose indices add up to at most S - 1:
+//   S = 2 ("x3"): a0 b0 + a0 b1 + a1 b0                 (~16-bit operands)
+//   S = 3 ("x6"): the above + a0 b2 + a1 b1 + a2 b0     (~24-bit operands)
+// on v_mfma_f32_16x16x32_bf16.  The leading term a0 b0 and the correction
+// terms accumulate in separate FP32 registers (the corrections are 2^-8 times
+// smaller, so their rounding is negligible) and both are added into FP64
+// accumulators every 256 values of k, which bounds the FP32 rounding of the
+// leading term.  Used for the Gram, Coulomb-metric and exchange contractions
+// when a mixed precision is requested; the interpolation-metric Cholesky and
+// triangular solves always stay FP64.
+//
+// Planes are K-contiguous: A plane p holds element (m, k) at
+// A + p * plane_stride + m * lda + k, B plane p holds (k, n) at
+// B + p * plane_stride + n * ldb + k, so every MFMA operand is one 16-byte
+// LDS read.  Lane layout of v_mfma_f32_16x16x32_bf16 (wave64):
+//   operand 1: lane l holds X[i = l % 16][k = 8 (l / 16) + t], t = 0..7
+//   operand 2: lane l holds Y[k = 8 (l / 16) + t][j = l % 16]
+//   result   : lane l, register v holds D[i = 4 (l / 16) + v][j = l % 16]
+// Operand 1 carries B^T and operand 2 A^T, so a lane's results are 16
+// consecutive rows of one column of the column-major C.
+#include "common.h"
+
+namespace isdf {
+
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef double d4m __attribute__((ext_vector_type(4)));
+
+namespace {
+constexpr int BM = 64, BN = 64, BK = 32, KFLUSH = 256;
+
+__device__ inline const MixedProblem* find_mixed(const MixedProblem* probs, int nprob, int tile) {
+  int lo = 0, hi = nprob - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (probs[mid].tile_start <= tile) lo = mid; else hi = mid - 1;
+  }
+  return probs + lo;
+}
+}  // namespace
+
+template <int EPI, int S, int TAG>
+__global__ void __launch_bounds__(256)
+gemm_mixed_kernel(MixedProblem single, const MixedProblem* __restrict__ probs, int nprob) {
+  const MixedProblem* pp = probs ? find_mixed(probs, nprob, blockIdx.x) : &single;
+  const MixedProblem p = *pp;
+  const int tilesM = (p.M + BM - 1) / BM;
+  const int local = (int)blockIdx.x - p.tile_start;
+  const int tm = local % tilesM, tn = local / tilesM;
+  const int m0 = tm * BM, n0 = tn * BN;
+  if (n0 >= p.N) return;
+  if (p.lower && m0 + BM <= n0) return;
+
+  // [plane][row][k], padded by 8 bf16 (16 B) per row against bank conflicts
+  __shared__ __attribute__((aligned(16))) __bf16 As[S][BM][BK + 8];
+  __shared__ __attribute__((aligned(16))) __bf16 Bs[S][BN][BK + 8];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+
+  f4v hi[2][2], lo[2][2], hiN[2][2], loN[2][2];
+  d4m acc[2][2], accN[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      hi[a][b] = lo[a][b] = hiN[a][b] = loN[a][b] = f4v{0.f, 0.f, 0.f, 0.f};
+      acc[a][b] = accN[a][b] = d4m{0.0, 0.0, 0.0, 0.0};
+    }
+
+  // each thread stages one 16-byte chunk (8 bf16 along k) per plane and operand
+  const int lr = tid >> 2;          // row within the tile (0..63)
+  const int lk = (tid & 3) * 8;     // k offset within the chunk
+  for (int k0 = 0; k0 < p.K; k0 += BK) {
+    bf8v ra[S], rb[S];
+    {
+      const int gm = m0 + lr, gk = k0 + lk;
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        bf8v v;
+        if (gm < p.M && gk + 8 <= p.K) {
+          v = *reinterpret_cast<const bf8v*>(p.A + s * p.plane_a + (int64_t)gm * p.lda + gk);
+        } else {
+#pragma unroll
+          for (int t = 0; t < 8; ++t)
+            v[t] = (gm < p.M && gk + t < p.K) ? p.A[s * p.plane_a + (int64_t)gm * p.lda + gk + t]
+                                               : (__bf16)0.0f;
+        }
+        ra[s] = v;
+      }
+      const int gn = n0 + lr;
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        bf8v v;
+        if (gn < p.N && gk + 8 <= p.K) {
+          v = *reinterpret_cast<const bf8v*>(p.B + s * p.plane_b + (int64_t)gn * p.ldb + gk);
+        } else {
+#pragma unroll
+          for (int t = 0; t < 8; ++t)
+            v[t] = (gn < p.N && gk + t < p.K) ? p.B[s * p.plane_b + (int64_t)gn * p.ldb + gk + t]
+                                               : (__bf16)0.0f;
+        }
+        rb[s] = v;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      *reinterpret_cast<bf8v*>(&As[s][lr][lk]) = ra[s];
+      *reinterpret_cast<bf8v*>(&Bs[s][lr][lk]) = rb[s];
+    }
+    __syncthreads();
+    const int kq = 8 * (lane >> 4);
+    bf8v xb[S][2], ya[S][2];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+#pragma unroll
+      for (int b = 0; b < 2; ++b) xb[s][b] = *reinterpret_cast<const bf8v*>(&Bs[s][wn * 32 + b * 16 + (lane & 15)][kq]);
+#pragma unroll
+      for (int a = 0; a < 2; ++a) ya[s][a] = *reinterpret_cast<const bf8v*>(&As[s][wm * 32 + a * 16 + (lane & 15)][kq]);
+    }
+    // Theta split: this chunk's k range lies entirely on one side of kL when
+    // kL is a multiple of BK (the host pads the L columns to guarantee it)
+    const bool toN = (EPI == EPI_THETA) && k0 >= p.kL;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        f4v h = toN ? hiN[a][b] : hi[a][b];
+        f4v l = toN ? loN[a][b] : lo[a][b];
+        h = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xb[0][b], ya[0][a], h, 0, 0, 0);
+        l = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xb[0][b], ya[1][a], l, 0, 0, 0);
+        l = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xb[1][b], ya[0][a], l, 0, 0, 0);
+        if (S == 3) {
+          l = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xb[0][b], ya[S - 1][a], l, 0, 0, 0);
+          l = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xb[1][b], ya[1][a], l, 0, 0, 0);
+          l = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xb[S - 1][b], ya[0][a], l, 0, 0, 0);
+        }
+        if (toN) {
+          hiN[a][b] = h;
+          loN[a][b] = l;
+        } else {
+          hi[a][b] = h;
+          lo[a][b] = l;
+        }
+      }
+    if (((k0 + BK) % KFLUSH) == 0 || k0 + BK >= p.K) {
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            acc[a][b][v] += (double)hi[a][b][v] + (double)lo[a][b][v];
+            hi[a][b][v] = lo[a][b][v] = 0.f;
+            if (EPI == EPI_THETA) {
+              accN[a][b][v] += (double)hiN[a][b][v] + (double)loN[a][b][v];
+              hiN[a][b][v] = loN[a][b][v] = 0.f;
+            }
+          }
+    }
+  }
+  // epilogue: lane holds C(m0 + wm*32 + a*16 + lane%16, n0 + wn*32 + b*16 + 4(lane/16) + v)
+#pragma unroll
+  for (int a = 0; a < 2; ++a) {
+    const int gm = m0 + wm * 32 + a * 16 + (lane & 15);
+    if (gm >= p.M) continue;
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int gn = n0 + wn * 32 + b * 16 + 4 * (lane >> 4) + v;
+        if (gn >= p.N) continue;
+        double* cp = p.C + (int64_t)gm + (int64_t)gn * p.ldc;
+        const double x = acc[a][b][v];
+        if (EPI == EPI_THETA) {
+          *cp = x * (x + 2.0 * accN[a][b][v]);
+        } else if (EPI == EPI_HADAMARD) {
+          double y = p.alpha * x * p.E[(int64_t)gm + (int64_t)gn * p.lde];
+          if (p.beta != 0.0) y += p.beta * *cp;
+          *cp = y;
+        } else {
+          double y = p.alpha * x;
+          if (p.beta != 0.0) y += p.beta * *cp;
+          *cp = y;
+        }
+      }
+  }
+}
+
+int mixed_tiles(int M, int N) { return ((M + BM - 1) / BM) * ((N + BN - 1) / BN); }
+
+template <int S, int TAG>
+static void launch_st(hipStream_t s, int epi, const MixedProblem& single, const MixedProblem* probs,
+                      int nprob, int tiles) {
+  if (epi == EPI_THETA)
+    hipLaunchKernelGGL((gemm_mixed_kernel<EPI_THETA, S, TAG>), dim3(tiles), dim3(256), 0, s, single,
+                       probs, nprob);
+  else if (epi == EPI_HADAMARD)
+    hipLaunchKernelGGL((gemm_mixed_kernel<EPI_HADAMARD, S, TAG>), dim3(tiles), dim3(256), 0, s,
+                       single, probs, nprob);
+  else
+    hipLaunchKernelGGL((gemm_mixed_kernel<EPI_AXPBY, S, TAG>), dim3(tiles), dim3(256), 0, s, single,
+                       probs, nprob);
+}
+
+template <int S>
+static void launch_s(hipStream_t s, int epi, int tag, const MixedProblem& single,
+                     const MixedProblem* probs, int nprob, int tiles) {
+  switch (tag) {
+    case 2: launch_st<S, 2>(s, epi, single, probs, nprob, tiles); break;
+    case 3: launch_st<S, 3>(s, epi, single, probs, nprob, tiles); break;
+    default: launch_st<S, 4>(s, epi, single, probs, nprob, tiles); break;
+  }
+}
+
+isdf_status gemm_mixed(hipStream_t s, int epi, int splits, const MixedProblem& p, int tag) {
+  if (p.M <= 0 || p.N <= 0) return ISDF_OK;
+  MixedProblem q = p;
+  q.tile_start = 0;
+  const int tiles = mixed_tiles(p.M, p.N);
+  if (splits == 2) launch_s<2>(s, epi, tag, q, nullptr, 1, tiles);
+  else launch_s<3>(s, epi, tag, q, nullptr, 1, tiles);
+  ISDF_HIP_TRY(hipGetLastError());
+  return ISDF_OK;
+}
+
+isdf_status gemm_mixed_grouped(hipStream_t s, int epi, int splits, const MixedProblem* d_probs,
+                               int nprob, int total_tiles, int tag) {
+  if (nprob <= 0 || total_tiles <= 0) return ISDF_OK;
+  MixedProblem dummy{};
+  if (splits == 2) launch_s<2>(s, epi, tag, dummy, d_probs, nprob, total_tiles);
+  else launch_s<3>(s, epi, tag, dummy, d_probs, nprob, total_tiles);
+  ISDF_HIP_TRY(hipGetLastError());
+  return ISDF_OK;
+}
+
+// ------------------------------------------------------------------ split
+// Logical operand X (rows x cols, "outer" x "k") read from an FP64 matrix with
+// element (o, k) at src[o * so + k * sk]; written as `splits` K-contiguous
+// planes dst[p * plane + o * ldd + k] (ldd >= cols).  Optional row gather:
+// o_src = gidx ? gidx[o] : o (rows) or k_src = kidx ? kidx[k] : k.
+__global__ void __launch_bounds__(256)
+split_bf16_kernel(const double* __restrict__ src, int64_t so, int64_t sk,
+                  const int32_t* __restrict__ kidx, int rows, int cols, int splits,
+                  __bf16* __restrict__ dst, int64_t ldd, int64_t plane, double scale) {
+  const int64_t total = (int64_t)rows * cols;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    // walk k fastest when the source is k-contiguous, else the outer index
+    int64_t o, k;
+    if (sk == 1) {
+      o = e / cols;
+      k = e % cols;
+    } else {
+      k = e / rows;
+      o = e % rows;
+    }
+    const int64_t ks = kidx ? (int64_t)kidx[k] : k;
+    double x = ks >= 0 ? src[o * so + ks * sk] * scale : 0.0;
+    __bf16* d = dst + o * ldd + k;
+    for (int p = 0; p < splits; ++p) {
+      const __bf16 h = (__bf16)(float)x;
+      d[p * plane] = h;
+      x -= (double)(float)h;
+    }
+  }
+}
+
+// Same for a source whose outer index is the contiguous one (so == 1): a
+// 32 x 32 tile is read along o and written along k through LDS.
+__global__ void __launch_bounds__(256)
+split_bf16_t_kernel(const double* __restrict__ src, int64_t sk, const int32_t* __restrict__ kidx,
+                    int rows, int cols, int splits, __bf16* __restrict__ dst, int64_t ldd,
+                    int64_t plane, double scale) {
+  __shared__ double t[32][33];
+  const int o0 = blockIdx.x * 32, k0 = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  for (int r = ty; r < 32; r += 8) {
+    const int o = o0 + tx, k = k0 + r;
+    double v = 0.0;
+    if (o < rows && k < cols) {
+      const int64_t ks = kidx ? (int64_t)kidx[k] : k;
+      v = ks >= 0 ? src[(int64_t)o + ks * sk] * scale : 0.0;
+    }
+    t[r][tx] = v;
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int o = o0 + r, k = k0 + tx;
+    if (o < rows && k < cols) {
+      double x = t[tx][r];
+      __bf16* d = dst + (int64_t)o * ldd + k;
+      for (int q = 0; q < splits; ++q) {
+        const __bf16 h = (__bf16)(float)x;
+        d[q * plane] = h;
+        x -= (double)(float)h;
+      }
+    }
+  }
+}
+
+isdf_status launch_split_bf16(hipStream_t s, const double* src, int64_t so, int64_t sk,
+                              const int32_t* kidx, int rows, int cols, int splits, __bf16* dst,
+                              int64_t ldd, int64_t plane, double scale) {
+  const int64_t total = (int64_t)rows * cols;
+  if (total <= 0) return ISDF_OK;
+  if (so == 1 && sk != 1) {
+    hipLaunchKernelGGL(split_bf16_t_kernel, dim3((rows + 31) / 32, (cols + 31) / 32), dim3(256), 0, s,
+                       src, sk, kidx, rows, cols, splits, dst, ldd, plane, scale);
+    ISDF_HIP_TRY(hipGetLastError());
+    return ISDF_OK;
+  }
+  int64_t blocks = (total + 255) / 256;
+  if (blocks > 16384) blocks = 16384;
+  hipLaunchKernelGGL(split_bf16_kernel, dim3((unsigned)blocks), dim3(256), 0, s, src, so, sk, kidx,
+                     rows, cols, splits, dst, ldd, plane, scale);
+  ISDF_HIP_TRY(hipGetLastError());
+  return ISDF_OK;
+}
+
+}  // namespace isdf

@@ -30,7 +30,7 @@ basis_eval_kernel(LatticeArg lat, const ShellDev* __restrict__ shells,
                   const double* __restrict__ img, const ColShell* __restrict__ colshells,
                   const DomainDev* __restrict__ doms, const int32_t* __restrict__ points,
                   const BasisTile* __restrict__ tiles, double* __restrict__ phi,
-                  double* __restrict__ diag) {
+                  double* __restrict__ diag, double* __restrict__ aux) {
   const BasisTile t = tiles[blockIdx.x];
   const DomainDev d = doms[t.domain];
   const int i = t.start + (int)threadIdx.x;
@@ -46,7 +46,7 @@ basis_eval_kernel(LatticeArg lat, const ShellDev* __restrict__ shells,
   const double x = f1 * lat.a[0] + f2 * lat.a[3] + f3 * lat.a[6];
   const double y = f1 * lat.a[1] + f2 * lat.a[4] + f3 * lat.a[7];
   const double z = f1 * lat.a[2] + f2 * lat.a[5] + f3 * lat.a[8];
-  double aL = 0.0, aN = 0.0;
+  double aL = 0.0, aN = 0.0, mL = 0.0, sL = 0.0;
   double* out = phi + d.phi_off + i;
   const int64_t P = d.pts;
   for (int e = 0; e < d.colshell_cnt; ++e) {
@@ -70,25 +70,45 @@ basis_eval_kernel(LatticeArg lat, const ShellDev* __restrict__ shells,
     }
     if (sh.l == 0) {
       out[cs.col * P] = v0;
-      if (cs.col < d.nL) aL += v0 * v0; else aN += v0 * v0;
+      if (cs.col < d.nL) {
+        aL += v0 * v0;
+        mL = fmax(mL, v0 * v0);
+        sL += v0;
+      } else {
+        aN += v0 * v0;
+      }
     } else {
       out[cs.col * P] = vx;
       out[(cs.col + 1) * P] = vy;
       out[(cs.col + 2) * P] = vz;
       const double s = vx * vx + vy * vy + vz * vz;
-      if (cs.col < d.nL) aL += s; else aN += s;
+      if (cs.col < d.nL) {
+        aL += s;
+        mL = fmax(mL, fmax(vx * vx, fmax(vy * vy, vz * vz)));
+        sL += vx + vy + vz;
+      } else {
+        aN += s;
+      }
     }
   }
   diag[d.diag_off + i] = aL * (aL + 2.0 * aN);
+  if (aux) {
+    double* a = aux + 4 * (d.diag_off + i);
+    a[0] = aL;
+    a[1] = aN;
+    a[2] = mL;
+    a[3] = sL;
+  }
 }
 
 isdf_status launch_basis_eval(hipStream_t s, const LatticeArg& lat, const ShellDev* shells,
                               const double* img, const ColShell* colshells,
                               const DomainDev* doms, const int32_t* points,
-                              const BasisTile* tiles, int ntiles, double* phi, double* diag) {
+                              const BasisTile* tiles, int ntiles, double* phi, double* diag,
+                              double* aux) {
   if (ntiles <= 0) return ISDF_OK;
   hipLaunchKernelGGL(basis_eval_kernel, dim3(ntiles), dim3(256), 0, s, lat, shells, img,
-                     colshells, doms, points, tiles, phi, diag);
+                     colshells, doms, points, tiles, phi, diag, aux);
   ISDF_HIP_TRY(hipGetLastError());
   return ISDF_OK;
 }

@@ -346,3 +346,84 @@ def test_single_level_textbook_thc():
     X = r.XL
     K2 = -X.T @ ((X @ s.D @ X.T) * r.W) @ X
     assert np.allclose(r.K, K2, rtol=1e-13, atol=1e-13 * np.abs(K2).max())
+
+
+# ------------------------------------------------------------- MLP (T13)
+def test_mlp_backward_matches_finite_differences():
+    """The oracle's analytic backward of the scoring network equals central
+    finite differences of its loss (catches a wrong ReLU mask, a transposed
+    weight or a dropped pos-weight)."""
+    from oracle import mlp
+
+    rng = np.random.default_rng(11)
+    X = rng.standard_normal((40, mlp.NF))
+    y = (rng.random(40) < 0.2).astype(float)
+    th = mlp.init_params(3)
+    th[mlp.OFF_B1:mlp.OFF_W2] = 0.05 * rng.standard_normal(mlp.NH)
+    th[mlp.OFF_B2:mlp.OFF_W3] = 0.05 * rng.standard_normal(mlp.NH)
+    loss, g = mlp.loss_grad(th, X, y, 4.0)
+    idx = np.concatenate([rng.choice(mlp.NPARAM, 60, replace=False), [mlp.OFF_B3, mlp.OFF_W3]])
+    eps = 1e-6
+    for i in idx:
+        tp = th.copy(); tp[i] += eps
+        tm = th.copy(); tm[i] -= eps
+        fd = (mlp.loss_grad(tp, X, y, 4.0)[0] - mlp.loss_grad(tm, X, y, 4.0)[0]) / (2 * eps)
+        assert abs(fd - g[i]) <= 1e-7 * max(1.0, abs(fd)), (i, fd, g[i])
+
+
+def test_mlp_loss_is_weighted_bce():
+    """Loss of a network with zero weights and bias b3 = z0 is the closed
+    form pw y softplus(-z0) + (1-y) softplus(z0) averaged."""
+    from oracle import mlp
+
+    th = np.zeros(mlp.NPARAM)
+    th[mlp.OFF_B3] = 0.7
+    X = np.ones((5, mlp.NF))
+    y = np.array([1, 0, 0, 1, 0], float)
+    loss, _ = mlp.loss_grad(th, X, y, 3.0)
+    sp = lambda v: np.log1p(np.exp(v))  # noqa: E731
+    want = np.mean(3.0 * y * sp(-0.7) + (1 - y) * sp(0.7))
+    assert abs(loss - want) < 1e-14
+
+
+def test_mlp_features_simple_cases():
+    """Feature definitions on a one-atom cell: the diagonal feature equals the
+    Gram diagonal, distances are zero at the atom's grid point."""
+    from oracle import isdf, mlp
+    from oracle import plan as oplan
+
+    s = tiny_system("one_atom")
+    s.xyz = np.array([[0.0, 0.0, 0.0]])
+    p = oplan.build_plan(s)
+    dom = p.domains[1]
+    F, Phi = mlp.domain_features(p, dom, s)
+    g = isdf.gram_diag(Phi, dom.L.size)
+    assert np.allclose(10 ** (10 * F[:, 2]), g, rtol=1e-12)
+    assert np.isclose(F[:, 3].max(), 1.0)
+    at = np.nonzero(dom.points == 0)[0][0]
+    assert F[at, 8] == 0.0 and F[at, 9] == 0.0
+    assert np.allclose(F[:, 1], 0.0) and np.allclose(F[:, 0], 1.0)
+
+
+def test_restricted_selection_equals_full_on_needed_set():
+    """Greedy selection restricted to the points whose initial diagonal is at
+    least (1 - tau) times the last pivot residual (plus arbitrary extras)
+    returns the full selection's pivots; dropping one needed point is caught
+    by the exactness check."""
+    s = config(1, with_density=False)
+    p = oplan.build_plan(s)
+    rng = np.random.default_rng(5)
+    for d in (1, 4):
+        dom = p.domains[d]
+        Phi = basis.domain_values(p, dom)
+        piv, L, _, d0 = isdf.pivoted_cholesky(Phi, dom.L.size, dom.n_mu, s.eps_isdf, s.tie_tol)
+        dlast = L[piv[-1], len(piv) - 1] ** 2
+        need = isdf.needed_points(d0, dlast, s.tie_tol)
+        assert need.size < 0.2 * dom.points.size
+        extra = rng.choice(dom.points.size, 200, replace=False)
+        cand = np.union1d(need, extra)
+        piv_r, Lr, _, _ = isdf.pivoted_cholesky(Phi, dom.L.size, dom.n_mu, s.eps_isdf, s.tie_tol, candidates=cand)
+        assert np.array_equal(piv_r, piv)
+        assert isdf.restriction_is_exact(d0, cand, Lr[piv_r[-1], len(piv_r) - 1] ** 2, s.tie_tol)
+        worst = need[np.argmin(d0[need])]
+        assert not isdf.restriction_is_exact(d0, np.setdiff1d(cand, [worst]), dlast, s.tie_tol)
