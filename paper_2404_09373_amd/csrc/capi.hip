@@ -15,6 +15,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <memory>
 #include <numeric>
 
@@ -33,21 +34,135 @@ constexpr int NSTAGE = 8;
 constexpr int RL_MIN_PIVOTS = 128;  // right-looking selection above this many pivots
 constexpr int RL_BLOCK = 128;       // pivots between residual (SYRK) updates
 
+// Device memory of one plan.  A block that a buffer gives back is kept and
+// handed to a later buffer of the same plan, with no hipFree/hipMalloc (both
+// of which stall the host, and freeing multi-GB blocks costs the driver
+// hundreds of milliseconds): every kernel and copy of a plan is enqueued on
+// the plan's stream, so the stream orders the old uses of a block before the
+// new ones.  For the same reason host data reaches the device through a
+// pinned staging ring as copies on that stream, never as a synchronous copy
+// that could overtake kernels still reading a reused block.
+struct MemCtx {
+  static constexpr size_t STAGE_BYTES = 64u << 20;
+  hipStream_t stream = nullptr;
+  std::multimap<size_t, void*> free_blocks;
+  size_t cached = 0;
+  char* stage = nullptr;
+  size_t stage_off = 0;
+
+  ~MemCtx() {
+    trim();
+    if (stage) (void)hipHostFree(stage);
+  }
+  static size_t round(size_t b) {
+    const size_t g = b >= (1u << 20) ? (2u << 20) : 512;
+    return (b + g - 1) / g * g;
+  }
+  void trim() {
+    for (auto& kv : free_blocks) (void)hipFree(kv.second);
+    free_blocks.clear();
+    cached = 0;
+  }
+  // A cached block of at least `b` bytes (at most 1/8 larger for big ones),
+  // else a new one; on an allocation failure the cache is released first.
+  void* get(size_t b, size_t* cap) {
+    const size_t r = round(b);
+    auto it = free_blocks.lower_bound(r);
+    if (it != free_blocks.end() && it->first <= r + std::max<size_t>(r / 8, 4096)) {
+      void* p = it->second;
+      *cap = it->first;
+      cached -= it->first;
+      free_blocks.erase(it);
+      return p;
+    }
+    void* p = nullptr;
+    if (hipMalloc(&p, r) != hipSuccess) {
+      (void)hipGetLastError();
+      trim();
+      if (hipMalloc(&p, r) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+      }
+    }
+    *cap = r;
+    return p;
+  }
+  void put(void* p, size_t cap) {
+    free_blocks.emplace(cap, p);
+    cached += cap;
+  }
+  // Host -> device copy ordered on the plan's stream.
+  isdf_status copy_in(void* dst, const void* src, size_t n) {
+    if (n == 0) return ISDF_OK;
+    if (!stage && hipHostMalloc((void**)&stage, STAGE_BYTES) != hipSuccess) {
+      (void)hipGetLastError();
+      stage = nullptr;
+    }
+    if (!stage || n > STAGE_BYTES) {
+      ISDF_HIP_TRY(hipStreamSynchronize(stream));
+      ISDF_HIP_TRY(hipMemcpy(dst, src, n, hipMemcpyHostToDevice));
+      return ISDF_OK;
+    }
+    if (stage_off + n > STAGE_BYTES) {  // ring full: the earlier copies must have run
+      ISDF_HIP_TRY(hipStreamSynchronize(stream));
+      stage_off = 0;
+    }
+    std::memcpy(stage + stage_off, src, n);
+    ISDF_HIP_TRY(hipMemcpyAsync(dst, stage + stage_off, n, hipMemcpyHostToDevice, stream));
+    stage_off += (n + 255) / 256 * 256;
+    return ISDF_OK;
+  }
+};
+
+// The memory context of the plan whose API call is running on this thread
+// (empty outside plan calls: buffers then use hipMalloc/hipFree directly).
+thread_local std::shared_ptr<MemCtx> t_mem;
+
+struct MemScope {
+  std::shared_ptr<MemCtx> prev;
+  explicit MemScope(const std::shared_ptr<MemCtx>& m) : prev(t_mem) { t_mem = m; }
+  ~MemScope() { t_mem = prev; }
+};
+
 struct DevBuf {
   void* p = nullptr;
-  size_t bytes = 0;
-  ~DevBuf() {
-    if (p) (void)hipFree(p);
+  size_t bytes = 0, cap = 0;
+  std::shared_ptr<MemCtx> mem;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) {
+      if (mem)
+        mem->put(p, cap);
+      else
+        (void)hipFree(p);
+    }
+    p = nullptr;
+    bytes = cap = 0;
+    mem.reset();
   }
   isdf_status alloc(size_t b) {
-    if (p) (void)hipFree(p);
-    p = nullptr;
+    if (p && mem && mem == t_mem && b <= cap && MemCtx::round(b) + (cap >> 3) >= cap) {
+      bytes = b;  // the block held already fits
+      return ISDF_OK;
+    }
+    release();
     bytes = b;
     if (b == 0) return ISDF_OK;
-    hipError_t e = hipMalloc(&p, b);
-    if (e != hipSuccess) {
+    if (t_mem) {
+      p = t_mem->get(b, &cap);
+      if (p) mem = t_mem;
+    } else if (hipMalloc(&p, b) == hipSuccess) {
+      cap = b;
+    } else {
+      (void)hipGetLastError();
       p = nullptr;
-      set_error(std::string("hipMalloc of ") + std::to_string(b) + " bytes: " + hipGetErrorString(e));
+    }
+    if (!p) {
+      bytes = 0;
+      set_error("device allocation of " + std::to_string(b) + " bytes failed");
       return ISDF_E_NOMEM;
     }
     return ISDF_OK;
@@ -58,12 +173,19 @@ struct DevBuf {
   }
 };
 
+// Host -> device copy: stream-ordered through the plan's staging ring inside
+// plan calls, synchronous otherwise.
+isdf_status copy_in(void* dst, const void* src, size_t n) {
+  if (t_mem) return t_mem->copy_in(dst, src, n);
+  if (n) ISDF_HIP_TRY(hipMemcpy(dst, src, n, hipMemcpyHostToDevice));
+  return ISDF_OK;
+}
+
 template <class T>
 isdf_status upload(DevBuf& b, const std::vector<T>& v) {
   isdf_status st = b.alloc(sizeof(T) * std::max<size_t>(v.size(), 1));
   if (st != ISDF_OK) return st;
-  if (!v.empty()) ISDF_HIP_TRY(hipMemcpy(b.p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice));
-  return ISDF_OK;
+  return copy_in(b.p, v.data(), sizeof(T) * v.size());
 }
 
 // BF16 split planes of one logical operand (k-contiguous rows).
@@ -118,6 +240,7 @@ hipEvent_t prof_event(isdf_plan_s* pl);
 
 struct isdf_plan_s {
   HostPlan hp;
+  std::shared_ptr<MemCtx> mem;  // device block cache + upload staging
   isdf_options opts{};
   hipStream_t stream = nullptr;
   bool uploaded = false;
@@ -604,7 +727,7 @@ isdf_status run_selection(isdf_plan_s* pl, isdf_fit_s* f, const int64_t* pinned,
       }
       f->count[d] = hp.domains[d].n_mu;
     }
-    ISDF_HIP_TRY(hipMemcpy(f->piv.p, hp_piv.data(), sizeof(int32_t) * pv, hipMemcpyHostToDevice));
+    if ((st = copy_in(f->piv.p, hp_piv.data(), sizeof(int32_t) * pv)) != ISDF_OK) return st;
     return ISDF_OK;
   }
   // full-mode domains
@@ -669,8 +792,8 @@ isdf_status run_selection(isdf_plan_s* pl, isdf_fit_s* f, const int64_t* pinned,
       }
       o += std::max<int64_t>(n, 0);
     }
-    ISDF_HIP_TRY(hipMemcpy(cand.p, hc.data(), sizeof(int32_t) * hc.size(), hipMemcpyHostToDevice));
-    ISDF_HIP_TRY(hipMemcpy(f->cflag.p, hf.data(), hf.size(), hipMemcpyHostToDevice));
+    if ((st = copy_in(cand.p, hc.data(), sizeof(int32_t) * hc.size())) != ISDF_OK) return st;
+    if ((st = copy_in(f->cflag.p, hf.data(), hf.size())) != ISDF_OK) return st;
   }
   if (any_learned) {
     DevBuf feats, z, d_cd, d_nc, d_w;
@@ -923,10 +1046,13 @@ isdf_status run_coulomb(isdf_plan_s* pl, isdf_fit_s* f) {
     }
   }
   // memory budget for the potential slabs and the complex work buffers
+  // (free memory plus the plan's cached blocks, so that repeated fits size
+  // their buffers alike and take them back from the cache)
   size_t free_b = 0, total_b = 0;
   ISDF_HIP_TRY(hipMemGetInfo(&free_b, &total_b));
-  const double v_budget = std::max(2e9, 0.45 * (double)free_b);
-  const double z_budget = std::min(4e9, std::max(2.5e8, 0.05 * (double)free_b));
+  const double avail = (double)free_b + (double)(pl->mem ? pl->mem->cached : 0);
+  const double v_budget = std::min(24e9, std::max(2e9, 0.45 * avail));
+  const double z_budget = std::min(4e9, std::max(2.5e8, 0.05 * avail));
   struct Chunk {
     int lp;
     int64_t c0, c1;
@@ -1091,6 +1217,7 @@ isdf_status do_fit(isdf_plan_s* pl, const int64_t* pinned, const int64_t* cand_i
     set_error("isdf_fit: null argument");
     return ISDF_E_ARG;
   }
+  MemScope mscope(pl->mem);
   isdf_status st;
   if ((st = upload_plan(pl)) != ISDF_OK) return st;
   HostPlan& hp = pl->hp;
@@ -1356,6 +1483,8 @@ isdf_status isdf_plan(const isdf_system* sys, const isdf_options* opts, isdf_pla
     return ISDF_E_ARG;
   }
   pl->stream = static_cast<hipStream_t>(pl->opts.stream);
+  pl->mem = std::make_shared<MemCtx>();
+  pl->mem->stream = pl->stream;
   *out = pl.release();
   return ISDF_OK;
 }
@@ -1456,6 +1585,7 @@ isdf_status isdf_fit_features(isdf_fit_t fit, float* features_dev, float* labels
   isdf_plan_s* pl = fit->plan;
   if (n) *n = pl->pts_total;
   if (!features_dev) return ISDF_OK;  // size query
+  MemScope mscope(pl->mem);
   if (capacity < pl->pts_total) {
     set_error("isdf_fit_features: capacity below the number of points");
     return ISDF_E_ARG;
@@ -1467,6 +1597,7 @@ isdf_status isdf_fit_features(isdf_fit_t fit, float* features_dev, float* labels
     const int nd = (int)pl->hp.domains.size();
     // needed set: initial diagonal >= (1 - tie_tol) x residual of the last pivot
     std::vector<double> dg(pl->pts_total);
+    ISDF_HIP_TRY(hipStreamSynchronize(pl->stream));
     ISDF_HIP_TRY(hipMemcpy(dg.data(), fit->diag0.p, sizeof(double) * pl->pts_total, hipMemcpyDeviceToHost));
     for (int d = 0; d < nd; ++d) {
       const double thr = (1.0 - pl->hp.tie_tol) * fit->dlast[d];
@@ -1652,6 +1783,7 @@ isdf_status isdf_fit_get(isdf_fit_t fit, int32_t field, int32_t d, void* host_ou
       need = sizeof(int64_t) * fit->count[d];
       if (bytes != need) break;
       tmp32.resize(std::max(fit->count[d], 1));
+      ISDF_HIP_TRY(hipStreamSynchronize(pl->stream));
       if (fit->count[d] > 0)
         ISDF_HIP_TRY(hipMemcpy(tmp32.data(), fit->piv.as<int32_t>() + fit->piv_off[d],
                                sizeof(int32_t) * fit->count[d], hipMemcpyDeviceToHost));
@@ -1683,6 +1815,7 @@ isdf_status isdf_exchange(isdf_plan_t plan, isdf_fit_t fit, const double* D, dou
     set_error("isdf_exchange: fit belongs to another plan");
     return ISDF_E_STATE;
   }
+  MemScope mscope(plan->mem);
   hipStream_t s = plan->stream;
   const int64_t nmu = fit->nmu, N = plan->hp.n_basis;
   isdf_status st;
