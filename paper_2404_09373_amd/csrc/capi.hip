@@ -339,10 +339,16 @@ void prof_collect(isdf_plan_s* pl) {
   pl->evnext = 0;
 }
 
-double gemm_bytes(const GemmProblem& p) {
-  return 8.0 * ((double)p.M * p.K + (double)p.K * p.N + (double)p.M * p.N * (p.beta != 0.0 ? 2 : 1));
+// Algorithmic counts; a lower-triangle (symmetric) update counts only the
+// N(N+1)/2 entries it has to produce.
+double gemm_outputs(const GemmProblem& p) {
+  return p.lower ? 0.5 * (double)p.N * (p.N + 1.0) : (double)p.M * p.N;
 }
-double gemm_flops(const GemmProblem& p) { return 2.0 * p.M * (double)p.N * p.K; }
+double gemm_bytes(const GemmProblem& p) {
+  return 8.0 * ((double)p.M * p.K + (p.lower ? 0.0 : (double)p.K * p.N) +
+                gemm_outputs(p) * (p.beta != 0.0 ? 2 : 1));
+}
+double gemm_flops(const GemmProblem& p) { return 2.0 * gemm_outputs(p) * p.K; }
 
 int mixed_splits(const isdf_plan_s* pl) {
   return pl->opts.precision == ISDF_MIXED_X3 ? 2 : pl->opts.precision == ISDF_MIXED_X6 ? 3 : 0;
@@ -1090,15 +1096,16 @@ isdf_status run_coulomb(isdf_plan_s* pl, isdf_fit_s* f) {
   if ((st = V.alloc(sizeof(double) * std::max<int64_t>(vmax, 1))) != ISDF_OK) return st;
   std::vector<GemmProblem> probs;
   struct GemmLaunch {
-    int off, cnt, tiles;
+    int level, off, cnt, tiles, shape;
     double bytes, flops;
   };
+  // per chunk: one grouped launch per (row level, tile shape)
   std::vector<std::vector<GemmLaunch>> glaunch(chunks.size());
   for (size_t ci = 0; ci < chunks.size(); ++ci) {
     const Chunk& ch = chunks[ci];
     int64_t voff = 0;
     for (int l = 0; l <= ch.lp; ++l) {
-      GemmLaunch gl{(int)probs.size(), 0, 0, 0.0, 0.0};
+      std::vector<GemmProblem> lp_probs;
       const double dV = hp.volume / (double)level_ng(hp, l);
       for (int d = 0; d < nd; ++d) {
         if (hp.domains[d].level != l || f->count[d] == 0) continue;
@@ -1119,14 +1126,21 @@ isdf_status run_coulomb(isdf_plan_s* pl, isdf_fit_s* f) {
         p.K = (int)D.points.size();
         p.alpha = dV;
         p.beta = 0.0;
-        p.tile_start = gl.tiles;
-        gl.tiles += gemm_tiles(p.M, p.N);
-        gl.bytes += gemm_bytes(p);
-        gl.flops += gemm_flops(p);
-        probs.push_back(p);
+        lp_probs.push_back(p);
       }
-      gl.cnt = (int)probs.size() - gl.off;
-      glaunch[ci].push_back(gl);
+      for (int shape = 0; shape < GEMM_NSHAPE; ++shape) {
+        GemmLaunch gl{l, (int)probs.size(), 0, 0, shape, 0.0, 0.0};
+        for (GemmProblem p : lp_probs) {
+          if (gemm_default_shape(EPI_AXPBY, p.M, p.N, p.K) != shape) continue;
+          p.tile_start = gl.tiles;
+          gl.tiles += gemm_tiles(p.M, p.N, shape);
+          gl.bytes += gemm_bytes(p);
+          gl.flops += gemm_flops(p);
+          probs.push_back(p);
+        }
+        gl.cnt = (int)probs.size() - gl.off;
+        if (gl.cnt > 0) glaunch[ci].push_back(gl);
+      }
       voff += level_ng(hp, l) * (ch.c1 - ch.c0);
     }
   }
@@ -1179,10 +1193,8 @@ isdf_status run_coulomb(isdf_plan_s* pl, isdf_fit_s* f) {
         voff += ng * (ch.c1 - ch.c0);
       }
     }
-    for (int l = 0; l <= lp; ++l) {
-      const GemmLaunch& gl = glaunch[ci][l];
-      if (gl.cnt == 0) continue;
-      if (l == 0 && w_mixed) {
+    for (const GemmLaunch& gl : glaunch[ci]) {
+      if (gl.level == 0 && w_mixed) {
         const int64_t ng0 = level_ng(hp, 0);
         const int w = (int)(ch.c1 - ch.c0);
         if ((st = make_planes(s, mixed_splits(pl), V.as<double>(), ng0, 1, nullptr, w, (int)ng0, Vp0)) !=
@@ -1196,7 +1208,7 @@ isdf_status run_coulomb(isdf_plan_s* pl, isdf_fit_s* f) {
       }
       ProfScope ps(pl, ISDF_K_GEMM_METRIC, gl.bytes, gl.flops);
       if ((st = gemm_f64_grouped(s, EPI_AXPBY, d_probs.as<GemmProblem>() + gl.off, gl.cnt,
-                                 gl.tiles, family_tag(ISDF_K_GEMM_METRIC))) != ISDF_OK)
+                                 gl.tiles, family_tag(ISDF_K_GEMM_METRIC), gl.shape)) != ISDF_OK)
         return st;
     }
   }
@@ -1311,7 +1323,6 @@ isdf_status do_fit(isdf_plan_s* pl, const int64_t* pinned, const int64_t* cand_i
   if ((st = f->F.alloc(sizeof(double) * std::max<int64_t>(th, 1))) != ISDF_OK) return st;
   {
     std::vector<GemmProblem> probs;
-    int tiles = 0;
     for (int d = 0; d < nd; ++d) {
       if (f->count[d] == 0) continue;
       GemmProblem p{};
@@ -1325,8 +1336,6 @@ isdf_status do_fit(isdf_plan_s* pl, const int64_t* pinned, const int64_t* cand_i
       p.N = f->count[d];
       p.K = gd[d].nG;
       p.kL = gd[d].nL;
-      p.tile_start = tiles;
-      tiles += gemm_tiles(p.M, p.N);
       probs.push_back(p);
     }
     if (mixed_on(pl, ISDF_MIX_THETA)) {
@@ -1356,17 +1365,31 @@ isdf_status do_fit(isdf_plan_s* pl, const int64_t* pinned, const int64_t* cand_i
         ISDF_HIP_TRY(hipStreamSynchronize(s));  // planes and index are reused
       }
     } else {
-      DevBuf d_probs;
-      if ((st = upload(d_probs, probs)) != ISDF_OK) return st;
+      // one grouped launch per tile shape (the universal domain is big, the
+      // windows are skinny)
+      std::vector<GemmProblem> grouped;
+      int tiles[GEMM_NSHAPE] = {}, first[GEMM_NSHAPE] = {}, cnt[GEMM_NSHAPE] = {};
       double by = 0.0, fl = 0.0;
-      for (auto& p : probs) {
-        by += gemm_bytes(p);
-        fl += gemm_flops(p);
+      for (int shape = 0; shape < GEMM_NSHAPE; ++shape) {
+        first[shape] = (int)grouped.size();
+        for (GemmProblem p : probs) {
+          if (gemm_default_shape(EPI_THETA, p.M, p.N, p.K) != shape) continue;
+          p.tile_start = tiles[shape];
+          tiles[shape] += gemm_tiles(p.M, p.N, shape);
+          by += gemm_bytes(p);
+          fl += gemm_flops(p);
+          grouped.push_back(p);
+        }
+        cnt[shape] = (int)grouped.size() - first[shape];
       }
+      DevBuf d_probs;
+      if ((st = upload(d_probs, grouped)) != ISDF_OK) return st;
       ProfScope ps(pl, ISDF_K_GEMM_FIT, by, fl);
-      if ((st = gemm_f64_grouped(s, EPI_THETA, d_probs.as<GemmProblem>(), (int)probs.size(), tiles,
-                                 family_tag(ISDF_K_GEMM_FIT))) != ISDF_OK)
-        return st;
+      for (int shape = 0; shape < GEMM_NSHAPE; ++shape)
+        if (cnt[shape] > 0 &&
+            (st = gemm_f64_grouped(s, EPI_THETA, d_probs.as<GemmProblem>() + first[shape], cnt[shape],
+                                   tiles[shape], family_tag(ISDF_K_GEMM_FIT), shape)) != ISDF_OK)
+          return st;
     }
     ISDF_HIP_TRY(hipStreamSynchronize(s));
   }

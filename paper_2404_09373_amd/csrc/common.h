@@ -98,10 +98,20 @@ struct GemmProblem {
 // filled by the caller, total_tiles = sum of tiles).
 // tag: 0 generic, 1 selection Gram / residual updates, 2 Coulomb metric,
 // 3 fit (Theta, Cholesky, solves), 4 exchange
-isdf_status gemm_f64(hipStream_t s, int epi, const GemmProblem& p, int tag = 0);
+// Tile shapes of the FP64 GEMM (index into kShapes).  Single problems take
+// `shape` < 0 to mean the default for their size; a grouped launch names its
+// shape, and its tile_start/total_tiles must be counted with gemm_tiles of
+// that shape.
+struct GemmShape {
+  int bm, bn, wm, wn;
+};
+constexpr int GEMM_NSHAPE = 5;
+extern const GemmShape kShapes[GEMM_NSHAPE];
+isdf_status gemm_f64(hipStream_t s, int epi, const GemmProblem& p, int tag = 0, int shape = -1);
 isdf_status gemm_f64_grouped(hipStream_t s, int epi, const GemmProblem* d_probs, int nprob,
-                             int total_tiles, int tag = 0);
-int gemm_tiles(int M, int N);
+                             int total_tiles, int tag = 0, int shape = 0);
+int gemm_tiles(int M, int N, int shape = 0, bool lower = false);
+int gemm_default_shape(int epi, int M, int N, int K, bool lower = false);
 
 // ------------------------------------------------------------ other kernels
 struct BasisTile {

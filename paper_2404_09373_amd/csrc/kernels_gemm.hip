@@ -2,16 +2,24 @@
 //
 // One kernel serves every dense contraction of the path: the Hadamard Gram
 // Theta = A_L o (A_L + 2 A_N) (Eq. M(R,R) restricted to the pivots), the
-// triangular-solve updates of the least-squares fit (Eq. lsqr), the
-// Coulomb-metric products W = dV F^T V (Eq. (xi|xi')) and the exchange
-// products of Eq. ints.  Problems are column-major; a launch may carry a
-// group of independent problems of different sizes (one per domain).
+// residual updates of the pivoted Cholesky, the triangular-solve updates of
+// the least-squares fit (Eq. lsqr), the Coulomb-metric products
+// W = dV F^T V (Eq. (xi|xi')) and the exchange products of Eq. ints.
+// Problems are column-major; a launch may carry a group of independent
+// problems of different sizes (one per domain).
 //
-// Tiling: 64 x 64 output tile per 256-thread workgroup, 4 waves in 2 x 2,
-// each wave 32 x 32 = 2 x 2 MFMA blocks of 16 x 16, K staged through LDS in
-// chunks of 16.  The MFMA is fed B^T as its first operand and A^T as its
-// second, so a lane's accumulators hold 16 consecutive rows of one C column:
-// stores are contiguous along the column-major leading dimension.
+// Tiling: a BM x BN output tile per workgroup of WM x WN waves, each wave
+// (BM/WM) x (BN/WN) = FM x FN MFMA blocks of 16 x 16 (shapes in kShapes).
+// K is staged through two LDS buffers in chunks of 16: the next chunk's
+// global loads are issued into registers before the current chunk's MFMAs
+// and land in the other buffer afterwards, one barrier per chunk.  The MFMA
+// is fed B^T as its first operand and A^T as its second, so a lane's
+// accumulators hold 16 consecutive rows of one C column: stores are
+// contiguous along the column-major leading dimension.
+//
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own
+// L2; the flat tile index is remapped so that every XCD walks a contiguous
+// range of tiles (neighbouring tiles share A rows or B columns in its L2).
 //
 // Lane layouts of v_mfma_f64_16x16x4f64 (wave64):
 //   operand 1: lane l holds X[i = l % 16][k = l / 16]
@@ -24,7 +32,7 @@ namespace isdf {
 typedef double d4v __attribute__((ext_vector_type(4)));
 
 namespace {
-constexpr int BM = 64, BN = 64, BK = 16, PAD = 2;
+constexpr int BK = 16, PAD = 2, NXCD = 8;
 
 __device__ inline const GemmProblem* find_problem(const GemmProblem* probs, int nprob, int tile) {
   int lo = 0, hi = nprob - 1;
@@ -34,221 +42,385 @@ __device__ inline const GemmProblem* find_problem(const GemmProblem* probs, int 
   }
   return probs + lo;
 }
+
+// Bijection of [0, nb): dispatch slot b (XCD b % 8) -> contiguous tile range.
+__device__ inline int xcd_tile(int b, int nb) {
+  const int x = b % NXCD, q = b / NXCD, per = nb / NXCD, rem = nb % NXCD;
+  return (x < rem ? x * (per + 1) : rem * (per + 1) + (x - rem) * per) + q;
+}
+
+// Per-thread global -> register loads of one K chunk.  Each thread owns
+// fixed (row, column) slots of the A and B tiles; their addresses are formed
+// once and advanced by a constant stride per chunk.  Interior chunks of
+// interior tiles skip all bounds tests.
+template <int BM_, int BN_, int NT>
+struct TileLoader {
+  static constexpr int NA = BM_ * BK / NT, NB = BN_ * BK / NT;
+  static_assert(NT % BM_ == 0 && NT % BN_ == 0 && NT % BK == 0 && NA >= 1 && NB >= 1, "tile");
+  double ra[NA], rb[NB];
+  const double* pa;  // slot r = 0 of A at the current chunk
+  const double* pb;  // slot r = 0 of B (rows gathered: column base only)
+  int64_t sa, sb;    // pointer step between slots r and r + 1
+  int64_t ca, cb;    // pointer step per chunk
+  int am, ak, bn, bk;  // this thread's tile coordinates of slot 0
+  bool a_ok[NA], b_ok[NB];  // row/column inside the problem (slot-wise)
+
+  __device__ void init(const GemmProblem& p, int m0, int n0, int tid) {
+    if (!p.transA) {  // A(m, k) at m + k lda: m fastest
+      am = tid % BM_;
+      ak = tid / BM_;
+      pa = p.A + (int64_t)(m0 + am) + (int64_t)ak * p.lda;
+      sa = (int64_t)(NT / BM_) * p.lda;
+      ca = (int64_t)BK * p.lda;
+#pragma unroll
+      for (int r = 0; r < NA; ++r) a_ok[r] = m0 + am < p.M;
+    } else {  // A(m, k) at k + m lda: k fastest
+      ak = tid % BK;
+      am = tid / BK;
+      pa = p.A + (int64_t)ak + (int64_t)(m0 + am) * p.lda;
+      sa = (int64_t)(NT / BK) * p.lda;
+      ca = BK;
+#pragma unroll
+      for (int r = 0; r < NA; ++r) a_ok[r] = m0 + am + (NT / BK) * r < p.M;
+    }
+    if (!p.transB) {  // B(k, n) at row(k) + n ldb: k fastest
+      bk = tid % BK;
+      bn = tid / BK;
+      pb = p.B + (int64_t)(n0 + bn) * p.ldb;
+      sb = (int64_t)(NT / BK) * p.ldb;
+      cb = BK;
+#pragma unroll
+      for (int r = 0; r < NB; ++r) b_ok[r] = n0 + bn + (NT / BK) * r < p.N;
+    } else {  // B(k, n) at n + k ldb: n fastest
+      bn = tid % BN_;
+      bk = tid / BN_;
+      pb = p.B + (int64_t)(n0 + bn) + (int64_t)bk * p.ldb;
+      sb = (int64_t)(NT / BN_) * p.ldb;
+      cb = (int64_t)BK * p.ldb;
+#pragma unroll
+      for (int r = 0; r < NB; ++r) b_ok[r] = n0 + bn < p.N;
+    }
+  }
+
+  // chunk starting at k0 (the pointers sit at k0)
+  __device__ void load(const GemmProblem& p, int k0) {
+    const bool kfull = k0 + BK <= p.K;
+    if (!p.transA) {
+#pragma unroll
+      for (int r = 0; r < NA; ++r) {
+        const bool ok = a_ok[r] && (kfull || k0 + ak + (NT / BM_) * r < p.K);
+        ra[r] = ok ? pa[r * sa] : 0.0;
+      }
+    } else {
+      const bool kok = kfull || k0 + ak < p.K;
+#pragma unroll
+      for (int r = 0; r < NA; ++r) ra[r] = (a_ok[r] && kok) ? pa[r * sa] : 0.0;
+    }
+    if (!p.transB) {
+      const bool kok = kfull || k0 + bk < p.K;
+      int64_t row = k0 + bk;
+      if (p.bidx && kok) row = p.bidx[k0 + bk];
+#pragma unroll
+      for (int r = 0; r < NB; ++r) rb[r] = (b_ok[r] && kok) ? pb[row + r * sb] : 0.0;
+    } else {
+#pragma unroll
+      for (int r = 0; r < NB; ++r) {
+        const bool ok = b_ok[r] && (kfull || k0 + bk + (NT / BN_) * r < p.K);
+        rb[r] = ok ? pb[r * sb] : 0.0;
+      }
+    }
+  }
+
+  __device__ void advance(const GemmProblem& p) {
+    pa += ca;
+    if (p.transB) pb += cb;  // gathered rows index from the column base
+  }
+
+  __device__ void store(const GemmProblem& p, double (*As)[BM_ + PAD], double (*Bs)[BN_ + PAD]) const {
+    if (!p.transA) {
+#pragma unroll
+      for (int r = 0; r < NA; ++r) As[ak + (NT / BM_) * r][am] = ra[r];
+    } else {
+#pragma unroll
+      for (int r = 0; r < NA; ++r) As[ak][am + (NT / BK) * r] = ra[r];
+    }
+    if (!p.transB) {
+#pragma unroll
+      for (int r = 0; r < NB; ++r) Bs[bk][bn + (NT / BK) * r] = rb[r];
+    } else {
+#pragma unroll
+      for (int r = 0; r < NB; ++r) Bs[bk + (NT / BN_) * r][bn] = rb[r];
+    }
+  }
+};
 }  // namespace
 
 // TAG only separates the instantiations per role (selection Gram, Coulomb
 // metric, fit solves, exchange) so that profiles attribute time per role.
-template <int EPI, int TAG>
-__global__ void __launch_bounds__(256)
+template <int EPI, int TAG, int BM_, int BN_, int WM_, int WN_>
+__global__ void __launch_bounds__(64 * WM_ * WN_)
 gemm_f64_kernel(GemmProblem single, const GemmProblem* __restrict__ probs, int nprob) {
-  const GemmProblem* pp = probs ? find_problem(probs, nprob, blockIdx.x) : &single;
+  constexpr int NT = 64 * WM_ * WN_;
+  constexpr int TM = BM_ / WM_, TN = BN_ / WN_;  // wave tile
+  constexpr int FM = TM / 16, FN = TN / 16;
+  constexpr bool TWO = EPI == EPI_THETA;
+  const int tile = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+  const GemmProblem* pp = probs ? find_problem(probs, nprob, tile) : &single;
   const GemmProblem p = *pp;
-  const int tilesM = (p.M + BM - 1) / BM;
-  const int local = (int)blockIdx.x - p.tile_start;
-  const int tm = local % tilesM;
-  const int tn = local / tilesM;
-  const int m0 = tm * BM, n0 = tn * BN;
+  const int tilesM = (p.M + BM_ - 1) / BM_;
+  const int local = tile - p.tile_start;
+  int tm, tn;
+  if (BM_ == BN_ && p.lower) {
+    // lower triangle of square tiles only, row by row: local = tm (tm + 1) / 2 + tn
+    int r = (int)((sqrt(8.0 * (double)local + 1.0) - 1.0) * 0.5);
+    while ((int64_t)(r + 1) * (r + 2) / 2 <= local) ++r;
+    while ((int64_t)r * (r + 1) / 2 > local) --r;
+    tm = r;
+    tn = local - r * (r + 1) / 2;
+  } else {
+    tm = local % tilesM;
+    tn = local / tilesM;
+  }
+  const int m0 = tm * BM_, n0 = tn * BN_;
   if (n0 >= p.N) return;
-  if (p.lower && m0 + BM <= n0) return;  // tile strictly above the diagonal
+  if (p.lower && m0 + BM_ <= n0) return;  // tile strictly above the diagonal
 
-  __shared__ double As[BK][BM + PAD];
-  __shared__ double Bs[BK][BN + PAD];
+  // two LDS stages: chunk c is read from stage c & 1 while chunk c + 1 is
+  // written to the other, one barrier per chunk
+  __shared__ double As[2][BK][BM_ + PAD];
+  __shared__ double Bs[2][BK][BN_ + PAD];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int wm = wave & 1, wn = wave >> 1;
+  const int wm = wave % WM_, wn = wave / WM_;
 
-  d4v acc[2][2], accN[2][2];
+  d4v acc[FM][FN], accN[TWO ? FM : 1][TWO ? FN : 1];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < FM; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      acc[a][b] = d4v{0.0, 0.0, 0.0, 0.0};
-      accN[a][b] = d4v{0.0, 0.0, 0.0, 0.0};
-    }
+    for (int b = 0; b < FN; ++b) acc[a][b] = d4v{0.0, 0.0, 0.0, 0.0};
+  if (TWO) {
+#pragma unroll
+    for (int a = 0; a < (TWO ? FM : 1); ++a)
+#pragma unroll
+      for (int b = 0; b < (TWO ? FN : 1); ++b) accN[a][b] = d4v{0.0, 0.0, 0.0, 0.0};
+  }
 
-  double ra[4], rb[4];
+  TileLoader<BM_, BN_, NT> ld;
+  ld.init(p, m0, n0, tid);
+  if (p.K > 0) {
+    ld.load(p, 0);
+    ld.store(p, As[0], Bs[0]);
+  }
+  __syncthreads();
+  int stage = 0;
   for (int k0 = 0; k0 < p.K; k0 += BK) {
-    // ---- global -> registers
-    if (!p.transA) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int m = tid & 63, k = (tid >> 6) + 4 * r;
-        const int gm = m0 + m, gk = k0 + k;
-        ra[r] = (gm < p.M && gk < p.K) ? p.A[(int64_t)gm + (int64_t)gk * p.lda] : 0.0;
-      }
-    } else {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int k = tid & 15, m = (tid >> 4) + 16 * r;
-        const int gm = m0 + m, gk = k0 + k;
-        ra[r] = (gm < p.M && gk < p.K) ? p.A[(int64_t)gk + (int64_t)gm * p.lda] : 0.0;
-      }
+    const bool more = k0 + BK < p.K;
+    if (more) {
+      ld.advance(p);
+      ld.load(p, k0 + BK);  // in flight during the MFMAs below
     }
-    if (!p.transB) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int k = tid & 15, n = (tid >> 4) + 16 * r;
-        const int gn = n0 + n, gk = k0 + k;
-        double v = 0.0;
-        if (gn < p.N && gk < p.K) {
-          const int64_t kr = p.bidx ? (int64_t)p.bidx[gk] : (int64_t)gk;
-          v = p.B[kr + (int64_t)gn * p.ldb];
-        }
-        rb[r] = v;
-      }
-    } else {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int n = tid & 63, k = (tid >> 6) + 4 * r;
-        const int gn = n0 + n, gk = k0 + k;
-        rb[r] = (gn < p.N && gk < p.K) ? p.B[(int64_t)gn + (int64_t)gk * p.ldb] : 0.0;
-      }
-    }
-    __syncthreads();
-    // ---- registers -> LDS
-    if (!p.transA) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) As[(tid >> 6) + 4 * r][tid & 63] = ra[r];
-    } else {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) As[tid & 15][(tid >> 4) + 16 * r] = ra[r];
-    }
-    if (!p.transB) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) Bs[tid & 15][(tid >> 4) + 16 * r] = rb[r];
-    } else {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) Bs[(tid >> 6) + 4 * r][tid & 63] = rb[r];
-    }
-    __syncthreads();
-    // ---- MFMA
 #pragma unroll
     for (int kk = 0; kk < BK / 4; ++kk) {
       const int kr = kk * 4 + (lane >> 4);
-      double xb[2], ya[2];
+      double xb[FN], ya[FM];
 #pragma unroll
-      for (int b = 0; b < 2; ++b) xb[b] = Bs[kr][wn * 32 + b * 16 + (lane & 15)];
+      for (int b = 0; b < FN; ++b) xb[b] = Bs[stage][kr][wn * TN + b * 16 + (lane & 15)];
 #pragma unroll
-      for (int a = 0; a < 2; ++a) ya[a] = As[kr][wm * 32 + a * 16 + (lane & 15)];
-      if (EPI == EPI_THETA) {
+      for (int a = 0; a < FM; ++a) ya[a] = As[stage][kr][wm * TM + a * 16 + (lane & 15)];
+      if constexpr (TWO) {
         const int kb = k0 + kk * 4;
         if (kb + 4 <= p.kL) {
 #pragma unroll
-          for (int a = 0; a < 2; ++a)
+          for (int a = 0; a < FM; ++a)
 #pragma unroll
-            for (int b = 0; b < 2; ++b)
+            for (int b = 0; b < FN; ++b)
               acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(xb[b], ya[a], acc[a][b], 0, 0, 0);
         } else if (kb >= p.kL) {
 #pragma unroll
-          for (int a = 0; a < 2; ++a)
+          for (int a = 0; a < FM; ++a)
 #pragma unroll
-            for (int b = 0; b < 2; ++b)
+            for (int b = 0; b < FN; ++b)
               accN[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(xb[b], ya[a], accN[a][b], 0, 0, 0);
         } else {
           const bool inL = (kb + (lane >> 4)) < p.kL;
-          double xL[2], xN[2];
+          double xL[FN], xN[FN];
 #pragma unroll
-          for (int b = 0; b < 2; ++b) {
+          for (int b = 0; b < FN; ++b) {
             xL[b] = inL ? xb[b] : 0.0;
             xN[b] = inL ? 0.0 : xb[b];
           }
 #pragma unroll
-          for (int a = 0; a < 2; ++a)
+          for (int a = 0; a < FM; ++a)
 #pragma unroll
-            for (int b = 0; b < 2; ++b) {
+            for (int b = 0; b < FN; ++b) {
               acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(xL[b], ya[a], acc[a][b], 0, 0, 0);
               accN[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(xN[b], ya[a], accN[a][b], 0, 0, 0);
             }
         }
       } else {
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+        for (int a = 0; a < FM; ++a)
 #pragma unroll
-          for (int b = 0; b < 2; ++b)
+          for (int b = 0; b < FN; ++b)
             acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(xb[b], ya[a], acc[a][b], 0, 0, 0);
       }
     }
+    if (more) ld.store(p, As[stage ^ 1], Bs[stage ^ 1]);
+    __syncthreads();
+    stage ^= 1;
   }
-  // ---- epilogue: lane holds C(m0 + wm*32 + a*16 + lane%16, n0 + wn*32 + b*16 + lane/16 + 4v)
+  // ---- epilogue: lane holds C(m0 + wm*TM + a*16 + lane%16, n0 + wn*TN + b*16 + lane/16 + 4v).
+  // Per row block a, every read (C when beta != 0, E for the Hadamard) is
+  // issued before any store, so the reads overlap instead of each waiting
+  // out the previous store.
+  const bool rd_c = !TWO && p.beta != 0.0;
 #pragma unroll
-  for (int a = 0; a < 2; ++a) {
-    const int gm = m0 + wm * 32 + a * 16 + (lane & 15);
+  for (int a = 0; a < FM; ++a) {
+    const int gm = m0 + wm * TM + a * 16 + (lane & 15);
     if (gm >= p.M) continue;
+    double cin[FN][4], ein[EPI == EPI_HADAMARD ? FN : 1][4];
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
+    for (int b = 0; b < FN; ++b)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int gn = n0 + wn * 32 + b * 16 + (lane >> 4) + 4 * v;
-        if (gn >= p.N) continue;
-        double* cp = p.C + (int64_t)gm + (int64_t)gn * p.ldc;
-        const double x = acc[a][b][v];
-        if (EPI == EPI_THETA) {
-          *cp = x * (x + 2.0 * accN[a][b][v]);
-        } else if (EPI == EPI_HADAMARD) {
-          double y = p.alpha * x * p.E[(int64_t)gm + (int64_t)gn * p.lde];
-          if (p.beta != 0.0) y += p.beta * *cp;
-          *cp = y;
-        } else {
-          double y = p.alpha * x;
-          if (p.beta != 0.0) y += p.beta * *cp;
-          *cp = y;
-        }
+        const int gn = n0 + wn * TN + b * 16 + (lane >> 4) + 4 * v;
+        const bool ok = gn < p.N;
+        cin[b][v] = (rd_c && ok) ? p.C[(int64_t)gm + (int64_t)gn * p.ldc] : 0.0;
+        if constexpr (EPI == EPI_HADAMARD)
+          ein[b][v] = ok ? p.E[(int64_t)gm + (int64_t)gn * p.lde] : 0.0;
       }
-    }
+#pragma unroll
+    for (int b = 0; b < FN; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int gn = n0 + wn * TN + b * 16 + (lane >> 4) + 4 * v;
+        if (gn >= p.N) continue;
+        const double x = acc[a][b][v];
+        double y;
+        if constexpr (TWO) {
+          y = x * (x + 2.0 * accN[TWO ? a : 0][TWO ? b : 0][v]);
+        } else if constexpr (EPI == EPI_HADAMARD) {
+          y = p.alpha * x * ein[EPI == EPI_HADAMARD ? b : 0][v] + p.beta * cin[b][v];
+        } else {
+          y = p.alpha * x + p.beta * cin[b][v];
+        }
+        p.C[(int64_t)gm + (int64_t)gn * p.ldc] = y;
+      }
   }
 }
 
-int gemm_tiles(int M, int N) { return ((M + BM - 1) / BM) * ((N + BN - 1) / BN); }
+// Tile shapes (BM x BN, waves WM x WN).  Shape 0 suits skinny and grouped
+// window problems; the others trade registers per wave against operand reuse.
+const GemmShape kShapes[GEMM_NSHAPE] = {
+    {64, 64, 2, 2}, {128, 64, 2, 2}, {128, 128, 2, 4}, {128, 128, 4, 4}, {64, 128, 2, 2}};
 
-template <int TAG>
-static void launch_tag(hipStream_t s, int epi, const GemmProblem& single, const GemmProblem* probs,
-                       int nprob, int tiles) {
-  if (epi == EPI_THETA)
-    hipLaunchKernelGGL((gemm_f64_kernel<EPI_THETA, TAG>), dim3(tiles), dim3(256), 0, s, single, probs,
-                       nprob);
-  else if (epi == EPI_HADAMARD)
-    hipLaunchKernelGGL((gemm_f64_kernel<EPI_HADAMARD, TAG>), dim3(tiles), dim3(256), 0, s, single,
-                       probs, nprob);
+namespace {
+template <int EPI, int TAG, int SH>
+void launch_shape(hipStream_t s, const GemmProblem& single, const GemmProblem* probs, int nprob,
+                  int tiles) {
+  if constexpr (SH == 0)
+    hipLaunchKernelGGL((gemm_f64_kernel<EPI, TAG, 64, 64, 2, 2>), dim3(tiles), dim3(256), 0, s,
+                       single, probs, nprob);
+  else if constexpr (SH == 1)
+    hipLaunchKernelGGL((gemm_f64_kernel<EPI, TAG, 128, 64, 2, 2>), dim3(tiles), dim3(256), 0, s,
+                       single, probs, nprob);
+  else if constexpr (SH == 2)
+    hipLaunchKernelGGL((gemm_f64_kernel<EPI, TAG, 128, 128, 2, 4>), dim3(tiles), dim3(512), 0, s,
+                       single, probs, nprob);
+  else if constexpr (SH == 3)
+    hipLaunchKernelGGL((gemm_f64_kernel<EPI, TAG, 128, 128, 4, 4>), dim3(tiles), dim3(1024), 0, s,
+                       single, probs, nprob);
   else
-    hipLaunchKernelGGL((gemm_f64_kernel<EPI_AXPBY, TAG>), dim3(tiles), dim3(256), 0, s, single, probs,
-                       nprob);
+    hipLaunchKernelGGL((gemm_f64_kernel<EPI, TAG, 64, 128, 2, 2>), dim3(tiles), dim3(256), 0, s,
+                       single, probs, nprob);
 }
 
-static isdf_status launch(hipStream_t s, int epi, int tag, const GemmProblem& single,
-                          const GemmProblem* probs, int nprob, int tiles) {
+template <int EPI, int TAG>
+void launch_epi(hipStream_t s, int shape, const GemmProblem& single, const GemmProblem* probs,
+                int nprob, int tiles) {
+  switch (shape) {
+    case 1: launch_shape<EPI, TAG, 1>(s, single, probs, nprob, tiles); break;
+    case 2: launch_shape<EPI, TAG, 2>(s, single, probs, nprob, tiles); break;
+    case 3: launch_shape<EPI, TAG, 3>(s, single, probs, nprob, tiles); break;
+    case 4: launch_shape<EPI, TAG, 4>(s, single, probs, nprob, tiles); break;
+    default: launch_shape<EPI, TAG, 0>(s, single, probs, nprob, tiles); break;
+  }
+}
+
+template <int TAG>
+void launch_tag(hipStream_t s, int epi, int shape, const GemmProblem& single,
+                const GemmProblem* probs, int nprob, int tiles) {
+  if (epi == EPI_THETA)
+    launch_epi<EPI_THETA, TAG>(s, shape, single, probs, nprob, tiles);
+  else if (epi == EPI_HADAMARD)
+    launch_epi<EPI_HADAMARD, TAG>(s, shape, single, probs, nprob, tiles);
+  else
+    launch_epi<EPI_AXPBY, TAG>(s, shape, single, probs, nprob, tiles);
+}
+
+isdf_status launch(hipStream_t s, int epi, int tag, int shape, const GemmProblem& single,
+                   const GemmProblem* probs, int nprob, int tiles) {
   if (tiles <= 0) return ISDF_OK;
   if (epi != EPI_AXPBY && epi != EPI_THETA && epi != EPI_HADAMARD) {
     set_error("gemm: bad epilogue");
     return ISDF_E_ARG;
   }
+  if (shape < 0 || shape >= GEMM_NSHAPE) {
+    set_error("gemm: bad tile shape");
+    return ISDF_E_ARG;
+  }
   switch (tag) {
-    case 1: launch_tag<1>(s, epi, single, probs, nprob, tiles); break;
-    case 2: launch_tag<2>(s, epi, single, probs, nprob, tiles); break;
-    case 3: launch_tag<3>(s, epi, single, probs, nprob, tiles); break;
-    case 4: launch_tag<4>(s, epi, single, probs, nprob, tiles); break;
-    default: launch_tag<0>(s, epi, single, probs, nprob, tiles); break;
+    case 1: launch_tag<1>(s, epi, shape, single, probs, nprob, tiles); break;
+    case 2: launch_tag<2>(s, epi, shape, single, probs, nprob, tiles); break;
+    case 3: launch_tag<3>(s, epi, shape, single, probs, nprob, tiles); break;
+    case 4: launch_tag<4>(s, epi, shape, single, probs, nprob, tiles); break;
+    default: launch_tag<0>(s, epi, shape, single, probs, nprob, tiles); break;
   }
   ISDF_HIP_TRY(hipGetLastError());
   return ISDF_OK;
 }
+}  // namespace
 
-isdf_status gemm_f64(hipStream_t s, int epi, const GemmProblem& p, int tag) {
+// Measured on MI355X over the path's problem shapes: the 16-wave 128 x 128
+// tile wins once there are enough tiles to fill the chip (or a long K keeps
+// fewer tiles busy); skinny and mid-sized outputs keep the 64 x 64 tile.
+int gemm_default_shape(int epi, int M, int N, int K, bool lower) {
+  (void)epi;
+  if (lower) return 3;
+  const int64_t t128 = (int64_t)((M + 127) / 128) * ((N + 127) / 128);
+  if (t128 >= 1024 || (t128 >= 128 && K >= 16384)) return 3;
+  return 0;
+}
+
+int gemm_tiles(int M, int N, int shape, bool lower) {
+  const GemmShape& g = kShapes[shape < 0 || shape >= GEMM_NSHAPE ? 0 : shape];
+  if (lower && g.bm == g.bn) {  // square lower-triangle problems list only tiles with tm >= tn
+    const int t = (N + g.bn - 1) / g.bn;
+    return t * (t + 1) / 2;
+  }
+  return ((M + g.bm - 1) / g.bm) * ((N + g.bn - 1) / g.bn);
+}
+
+isdf_status gemm_f64(hipStream_t s, int epi, const GemmProblem& p, int tag, int shape) {
   if (p.M <= 0 || p.N <= 0) return ISDF_OK;
   GemmProblem q = p;
   q.tile_start = 0;
-  if (p.K <= 0) {
-    // empty contraction: C = beta C (or zero); run with K = 0 to apply it
+  // K <= 0 runs the epilogue alone: C = beta C
+  if (p.lower && p.M != p.N) {
+    set_error("gemm: a lower-triangle update must be square");
+    return ISDF_E_ARG;
   }
-  return launch(s, epi, tag, q, nullptr, 1, gemm_tiles(p.M, p.N));
+  if (shape < 0) shape = gemm_default_shape(epi, p.M, p.N, p.K, p.lower != 0);
+  return launch(s, epi, tag, shape, q, nullptr, 1, gemm_tiles(p.M, p.N, shape, p.lower != 0));
 }
 
 isdf_status gemm_f64_grouped(hipStream_t s, int epi, const GemmProblem* d_probs, int nprob,
-                             int total_tiles, int tag) {
+                             int total_tiles, int tag, int shape) {
   if (nprob <= 0) return ISDF_OK;
   GemmProblem dummy{};
-  return launch(s, epi, tag, dummy, d_probs, nprob, total_tiles);
+  return launch(s, epi, tag, shape, dummy, d_probs, nprob, total_tiles);
 }
 
 }  // namespace isdf
