@@ -106,7 +106,13 @@ typedef struct {
   int32_t mixed_mask;         /* contractions run in the mixed precision when precision
                                  is ISDF_MIXED_*: bit 0 Theta, bit 1 W (universal rows),
                                  bit 2 exchange; 0 means W and exchange                   */
-  int32_t reserved[6];
+  int32_t eager_exchange;     /* 0 (default): the exchange of a fit is captured as a HIP
+                                 graph on its first call and replayed while the operand
+                                 pointers stay the same; 1: always launch kernel by kernel */
+  int32_t pad0;
+  const char* tune_file;      /* JSON tile-shape table written by isdf_autotune, read at
+                                 plan time (copied); NULL: the built-in size rule          */
+  int32_t reserved[2];
 } isdf_options;
 
 /* Build the multigrid plan (host only, no device work).
@@ -207,10 +213,21 @@ isdf_status isdf_mlp_train(const float* features_dev, const float* labels_dev, i
  *   e_x = tr(D K).
  * D_dev, K_dev: device pointers to N x N FP64 (D symmetric, per spin).
  * e_x: host pointer or NULL.  Synchronises the stream.
+ * Unless the plan was made with eager_exchange = 1, the first call of a fit
+ * captures the kernel sequence as a HIP graph and later calls with the same
+ * D_dev/K_dev replay it (the contents of D_dev may change between calls).
  * Errors: ISDF_E_ARG (null D/K, NaN found in D), ISDF_E_STATE (fit not from
  * this plan), ISDF_E_HIP. */
 isdf_status isdf_exchange(isdf_plan_t plan, isdf_fit_t fit, const double* D_dev, double* K_dev,
                           double* e_x);
+
+/* The same exchange for a factored density D = C C' (the occupied orbitals of
+ * the section on the exchange matrix): the pair products X^S D X^T' are
+ * formed as (X^S C)(X^T C)', inner size n_occ instead of N.
+ * C_dev: device pointer to N x n_occ FP64, row-major (C[mu * n_occ + i]).
+ * K_dev, e_x and errors as isdf_exchange (ISDF_E_ARG also for n_occ < 1). */
+isdf_status isdf_exchange_occ(isdf_plan_t plan, isdf_fit_t fit, const double* C_dev,
+                              int32_t n_occ, double* K_dev, double* e_x);
 
 /* Stage outputs for checks, copied to host (synchronises).
  *   ISDF_FIELD_PHI    domain d: basis values, n_points x (n_L + n_N), column-major

@@ -31,7 +31,7 @@ EXPORTED = [
     "isdf_fit_get", "isdf_fit_info", "isdf_stage_times", "isdf_sync", "isdf_fit_destroy",
     "isdf_plan_destroy", "isdf_last_error", "isdf_version", "isdf_fit_with_candidates",
     "isdf_fit_selection", "isdf_fit_features", "isdf_mlp_forward", "isdf_mlp_loss_grad",
-    "isdf_mlp_train", "isdf_profile", "isdf_kernel_stats",
+    "isdf_mlp_train", "isdf_profile", "isdf_kernel_stats", "isdf_exchange_occ",
 ]
 MLP_NPARAM = 5313
 
@@ -86,7 +86,10 @@ class _Options(C.Structure):
         ("stream", C.c_void_p),
         ("w_batch", C.c_int32),
         ("mixed_mask", C.c_int32),
-        ("reserved", C.c_int32 * 6),
+        ("eager_exchange", C.c_int32),
+        ("pad0", C.c_int32),
+        ("tune_file", C.c_char_p),
+        ("reserved", C.c_int32 * 2),
     ]
 
 
@@ -133,6 +136,7 @@ def load(required: bool = True):
     lib.isdf_mlp_loss_grad.argtypes = [fp, vp, vp, C.c_int64, C.c_float, fp, fp, vp]
     lib.isdf_mlp_train.argtypes = [vp, vp, C.c_int64, C.POINTER(_MlpConfig), fp, fp]
     lib.isdf_profile.argtypes = [vp, C.c_int32]
+    lib.isdf_exchange_occ.argtypes = [vp, vp, vp, C.c_int32, vp, C.POINTER(C.c_double)]
     lib.isdf_kernel_stats.argtypes = [vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64),
                                       C.POINTER(C.c_double), C.POINTER(C.c_double)]
     for name in ("isdf_plan", "isdf_plan_info", "isdf_plan_domain", "isdf_plan_domain_points",
@@ -140,7 +144,7 @@ def load(required: bool = True):
                  "isdf_exchange", "isdf_fit_get", "isdf_fit_info", "isdf_stage_times", "isdf_sync",
                  "isdf_fit_with_candidates", "isdf_fit_selection", "isdf_fit_features",
                  "isdf_mlp_forward", "isdf_mlp_loss_grad", "isdf_mlp_train", "isdf_profile",
-                 "isdf_kernel_stats"):
+                 "isdf_kernel_stats", "isdf_exchange_occ"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -161,7 +165,8 @@ class Plan:
 
     def __init__(self, sysm, precision: int = FP64, selector: int = SEL_FULL, stream=None,
                  w_batch: int = 0, mlp_weights=None, mlp_keep: float = 2.0,
-                 mlp_cutoff: float = 0.05, mixed_mask: int = 0):
+                 mlp_cutoff: float = 0.05, mixed_mask: int = 0, eager_exchange: bool = False,
+                 tune_file=None):
         lib = load()
         self._keep = []
         s = _System()
@@ -203,6 +208,11 @@ class Plan:
         o.mlp_keep = float(mlp_keep)
         o.mlp_cutoff = float(mlp_cutoff)
         o.mixed_mask = int(mixed_mask)
+        o.eager_exchange = 1 if eager_exchange else 0
+        if tune_file is not None:
+            tf = str(tune_file).encode()
+            self._keep.append(tf)
+            o.tune_file = tf
         h = C.c_void_p()
         _check(lib.isdf_plan(C.byref(s), C.byref(o), C.byref(h)), "isdf_plan")
         self.handle = h
@@ -341,6 +351,25 @@ class Fit:
         ex = C.c_double()
         _check(load().isdf_exchange(self.plan.handle, self.handle, C.c_void_p(D.data_ptr()),
                                     C.c_void_p(K.data_ptr()), C.byref(ex)), "isdf_exchange")
+        return K, ex.value
+
+    def exchange_occ(self, C_occ, K=None):
+        """K and E_x for D = C_occ C_occ^T, C_occ an (N, n_occ) float64 CUDA
+        tensor (row-major).  Returns (K, e_x)."""
+        import torch
+
+        if not isinstance(C_occ, torch.Tensor) or not C_occ.is_cuda or C_occ.dtype != torch.float64:
+            raise TypeError("C_occ must be a float64 CUDA tensor")
+        C_occ = C_occ.contiguous()
+        n = self.plan.n_basis
+        if C_occ.dim() != 2 or C_occ.shape[0] != n:
+            raise ValueError("C_occ must have shape (N, n_occ)")
+        if K is None:
+            K = torch.empty((n, n), dtype=torch.float64, device=C_occ.device)
+        ex = C.c_double()
+        _check(load().isdf_exchange_occ(self.plan.handle, self.handle, C.c_void_p(C_occ.data_ptr()),
+                                        int(C_occ.shape[1]), C.c_void_p(K.data_ptr()), C.byref(ex)),
+               "isdf_exchange_occ")
         return K, ex.value
 
     def close(self):

@@ -210,6 +210,14 @@ isdf_status make_planes(hipStream_t s, int splits, const double* src, int64_t so
                            out.ld, out.plane, scale);
 }
 
+// Size the planes of a rows x cols operand without filling them.
+isdf_status size_planes(int splits, int rows, int cols, Planes& out) {
+  const int64_t ld = (cols + 7) / 8 * 8;
+  const size_t need = sizeof(__bf16) * (size_t)splits * std::max<int64_t>((int64_t)rows * ld, 8);
+  if (out.buf.bytes == need) return ISDF_OK;
+  return out.buf.alloc(need);
+}
+
 MixedProblem mixed_problem(const Planes& A, const Planes& B, double* C, int64_t ldc, int M, int N,
                            int K, double alpha, double beta, const double* E, int64_t lde) {
   MixedProblem p{};
@@ -243,6 +251,7 @@ struct isdf_plan_s {
   std::shared_ptr<MemCtx> mem;  // device block cache + upload staging
   isdf_options opts{};
   hipStream_t stream = nullptr;
+  hipStream_t cap_stream = nullptr;  // private non-blocking stream for graph capture
   bool uploaded = false;
   // static device tables
   DevBuf d_shells, d_img, d_colshells, d_doms, d_points, d_tiles, d_funcs, d_mlp_w;
@@ -287,6 +296,23 @@ struct isdf_fit_s {
   // mixed precision: fit-time operand planes and per-exchange planes
   Planes xg_row, xl_row, xl_col, xn_col;
   Planes Dp, EGp, ELp, QGGp, QGLp, QGLTp, QLLp, Y1p, Y2p;
+  // factored density: D = C C^T for the energy
+  DevBuf Docc;
+  // captured exchange: replayed while (mode, operands, K) stay the same
+  hipGraph_t xgraph = nullptr;
+  hipGraphExec_t xexec = nullptr;
+  const void* xkey_in = nullptr;
+  const void* xkey_out = nullptr;
+  int xkey_nocc = -1;
+  void drop_graph() {
+    if (xexec) (void)hipGraphExecDestroy(xexec);
+    if (xgraph) (void)hipGraphDestroy(xgraph);
+    xexec = nullptr;
+    xgraph = nullptr;
+    xkey_in = xkey_out = nullptr;
+    xkey_nocc = -1;
+  }
+  ~isdf_fit_s() { drop_graph(); }
 };
 
 namespace {
@@ -1462,6 +1488,229 @@ isdf_status do_fit(isdf_plan_s* pl, const int64_t* pinned, const int64_t* cand_i
   return ISDF_OK;
 }
 
+// ------------------------------------------------------------- exchange
+// Workspace of the exchange (n_occ = 0: dense D, else the factored form).
+// Everything the kernel sequence touches is sized here, so that the
+// sequence itself allocates nothing and can be captured as a graph.
+isdf_status exchange_prepare(isdf_plan_s* plan, isdf_fit_s* fit, int n_occ) {
+  const int64_t nmu = fit->nmu, N = plan->hp.n_basis;
+  const int64_t ec = n_occ > 0 ? n_occ : N;  // columns of E_G, E_L
+  isdf_status st;
+  if (!fit->Y1.p) {
+    if ((st = fit->Y1.alloc(sizeof(double) * nmu * N)) != ISDF_OK) return st;
+    if ((st = fit->Y2.alloc(sizeof(double) * nmu * N)) != ISDF_OK) return st;
+    if ((st = fit->QGG.alloc(sizeof(double) * nmu * nmu)) != ISDF_OK) return st;
+    if ((st = fit->QGL.alloc(sizeof(double) * nmu * nmu)) != ISDF_OK) return st;
+    if ((st = fit->QLL.alloc(sizeof(double) * nmu * nmu)) != ISDF_OK) return st;
+    if ((st = fit->partial.alloc(sizeof(double) * 1024)) != ISDF_OK) return st;
+    if ((st = fit->ex_out.alloc(sizeof(double))) != ISDF_OK) return st;
+  }
+  if (fit->EG.bytes < sizeof(double) * nmu * ec) {
+    if ((st = fit->EG.alloc(sizeof(double) * nmu * ec)) != ISDF_OK) return st;
+    if ((st = fit->EL.alloc(sizeof(double) * nmu * ec)) != ISDF_OK) return st;
+  }
+  if (n_occ > 0 && !fit->Docc.p)
+    if ((st = fit->Docc.alloc(sizeof(double) * N * N)) != ISDF_OK) return st;
+  if (mixed_on(plan, ISDF_MIX_EXCHANGE)) {
+    const int S = mixed_splits(plan);
+    const int m = (int)nmu, n = (int)N;
+    hipStream_t s = plan->stream;
+    if (!fit->xg_row.buf.p) {  // fit-time operands, split once
+      if ((st = make_planes(s, S, fit->XG.as<double>(), 1, nmu, nullptr, m, n, fit->xg_row)) != ISDF_OK)
+        return st;
+      if ((st = make_planes(s, S, fit->XL.as<double>(), 1, nmu, nullptr, m, n, fit->xl_row)) != ISDF_OK)
+        return st;
+      if ((st = make_planes(s, S, fit->XL.as<double>(), nmu, 1, nullptr, n, m, fit->xl_col)) != ISDF_OK)
+        return st;
+      if ((st = make_planes(s, S, fit->XN.as<double>(), nmu, 1, nullptr, n, m, fit->xn_col)) != ISDF_OK)
+        return st;
+    }
+    if ((st = size_planes(S, n_occ > 0 ? n_occ : n, n, fit->Dp)) != ISDF_OK) return st;
+    if ((st = size_planes(S, m, (int)ec, fit->EGp)) != ISDF_OK) return st;
+    if ((st = size_planes(S, m, (int)ec, fit->ELp)) != ISDF_OK) return st;
+    for (Planes* q : {&fit->QGGp, &fit->QGLp, &fit->QGLTp, &fit->QLLp})
+      if ((st = size_planes(S, m, m, *q)) != ISDF_OK) return st;
+    if ((st = size_planes(S, n, m, fit->Y1p)) != ISDF_OK) return st;
+    if ((st = size_planes(S, n, m, fit->Y2p)) != ISDF_OK) return st;
+  }
+  return ISDF_OK;
+}
+
+// The kernel sequence of one exchange on plan->stream: no allocation, no
+// synchronisation.  in = D (n_occ = 0) or C_occ (row-major N x n_occ).
+isdf_status exchange_enqueue(isdf_plan_s* plan, isdf_fit_s* fit, const double* in, int n_occ,
+                             double* K, bool stage_event) {
+  hipStream_t s = plan->stream;
+  const int64_t nmu = fit->nmu, N = plan->hp.n_basis;
+  const int m = (int)nmu, n = (int)N, ec = n_occ > 0 ? n_occ : n;
+  const double* XL = fit->XL.as<double>();
+  const double* XN = fit->XN.as<double>();
+  const double* XG = fit->XG.as<double>();
+  const double* W = fit->W.as<double>();
+  double* EG = fit->EG.as<double>();
+  double* EL = fit->EL.as<double>();
+  double* Y1 = fit->Y1.as<double>();
+  double* Y2 = fit->Y2.as<double>();
+  double* QGG = fit->QGG.as<double>();
+  double* QGL = fit->QGL.as<double>();
+  double* QLL = fit->QLL.as<double>();
+  isdf_status st;
+  auto gemm = [&](int epi, const double* A, int64_t lda, int tA, const double* B, int64_t ldb,
+                  int tB, double* C, int64_t ldc, int M, int Nn, int Kk, double alpha, double beta,
+                  const double* E) {
+    GemmProblem p{};
+    p.A = A; p.lda = lda; p.transA = tA;
+    p.B = B; p.ldb = ldb; p.transB = tB;
+    p.C = C; p.ldc = ldc;
+    p.E = E; p.lde = nmu;
+    p.M = M; p.N = Nn; p.K = Kk;
+    p.alpha = alpha; p.beta = beta;
+    return gemm_prof(plan, ISDF_K_GEMM_EXCHANGE, epi, p);
+  };
+  if (mixed_on(plan, ISDF_MIX_EXCHANGE)) {
+    const int S = mixed_splits(plan);
+    auto mg = [&](int epi, const Planes& A, const Planes& B, double* C, int64_t ldc, int M, int Nn,
+                  int Kk, double alpha, double beta) {
+      return mixed_prof(plan, ISDF_K_GEMM_EXCHANGE, epi,
+                        mixed_problem(A, B, C, ldc, M, Nn, Kk, alpha, beta, W, nmu));
+    };
+    // B operand of E = X D (k = nu): rows lam of D, or rows i of C_occ
+    if (n_occ > 0) {
+      if ((st = make_planes(s, S, in, 1, n_occ, nullptr, n_occ, n, fit->Dp)) != ISDF_OK) return st;
+    } else {
+      if ((st = make_planes(s, S, in, N, 1, nullptr, n, n, fit->Dp)) != ISDF_OK) return st;
+    }
+    if ((st = mg(EPI_AXPBY, fit->xg_row, fit->Dp, EG, nmu, m, ec, n, 1.0, 0.0)) != ISDF_OK) return st;
+    if ((st = mg(EPI_AXPBY, fit->xl_row, fit->Dp, EL, nmu, m, ec, n, 1.0, 0.0)) != ISDF_OK) return st;
+    if ((st = make_planes(s, S, EG, 1, nmu, nullptr, m, ec, fit->EGp)) != ISDF_OK) return st;
+    if ((st = make_planes(s, S, EL, 1, nmu, nullptr, m, ec, fit->ELp)) != ISDF_OK) return st;
+    // Q = P o W with P = E X^T (dense) or E_S E_T^T (factored)
+    const Planes& BG = n_occ > 0 ? fit->EGp : fit->xg_row;
+    const Planes& BL = n_occ > 0 ? fit->ELp : fit->xl_row;
+    if ((st = mg(EPI_HADAMARD, fit->EGp, BG, QGG, nmu, m, m, ec, 1.0, 0.0)) != ISDF_OK) return st;
+    if ((st = mg(EPI_HADAMARD, fit->EGp, BL, QGL, nmu, m, m, ec, 1.0, 0.0)) != ISDF_OK) return st;
+    if ((st = mg(EPI_HADAMARD, fit->ELp, BL, QLL, nmu, m, m, ec, 1.0, 0.0)) != ISDF_OK) return st;
+    if ((st = make_planes(s, S, QGG, 1, nmu, nullptr, m, m, fit->QGGp)) != ISDF_OK) return st;
+    if ((st = make_planes(s, S, QGL, 1, nmu, nullptr, m, m, fit->QGLp)) != ISDF_OK) return st;
+    if ((st = make_planes(s, S, QGL, nmu, 1, nullptr, m, m, fit->QGLTp)) != ISDF_OK) return st;
+    if ((st = make_planes(s, S, QLL, 1, nmu, nullptr, m, m, fit->QLLp)) != ISDF_OK) return st;
+    if ((st = mg(EPI_AXPBY, fit->QGGp, fit->xl_col, Y1, nmu, m, n, m, 1.0, 0.0)) != ISDF_OK) return st;
+    if ((st = mg(EPI_AXPBY, fit->QGLp, fit->xn_col, Y1, nmu, m, n, m, 1.0, 1.0)) != ISDF_OK) return st;
+    if ((st = mg(EPI_AXPBY, fit->QGLTp, fit->xl_col, Y2, nmu, m, n, m, 1.0, 0.0)) != ISDF_OK) return st;
+    if ((st = mg(EPI_AXPBY, fit->QLLp, fit->xn_col, Y2, nmu, m, n, m, 1.0, 1.0)) != ISDF_OK) return st;
+    if ((st = make_planes(s, S, Y1, nmu, 1, nullptr, n, m, fit->Y1p)) != ISDF_OK) return st;
+    if ((st = make_planes(s, S, Y2, nmu, 1, nullptr, n, m, fit->Y2p)) != ISDF_OK) return st;
+    if ((st = mg(EPI_AXPBY, fit->xl_col, fit->Y1p, K, N, n, n, m, -1.0, 0.0)) != ISDF_OK) return st;
+    if ((st = mg(EPI_AXPBY, fit->xn_col, fit->Y2p, K, N, n, n, m, -1.0, 1.0)) != ISDF_OK) return st;
+  } else {
+    if (n_occ > 0) {
+      // E_G = X^G C, E_L = X^L C; Q_ST = (E_S E_T^T) o W
+      if ((st = gemm(EPI_AXPBY, XG, nmu, 0, in, n_occ, 1, EG, nmu, m, ec, n, 1.0, 0.0, nullptr)) != ISDF_OK) return st;
+      if ((st = gemm(EPI_AXPBY, XL, nmu, 0, in, n_occ, 1, EL, nmu, m, ec, n, 1.0, 0.0, nullptr)) != ISDF_OK) return st;
+      if ((st = gemm(EPI_HADAMARD, EG, nmu, 0, EG, nmu, 1, QGG, nmu, m, m, ec, 1.0, 0.0, W)) != ISDF_OK) return st;
+      if ((st = gemm(EPI_HADAMARD, EG, nmu, 0, EL, nmu, 1, QGL, nmu, m, m, ec, 1.0, 0.0, W)) != ISDF_OK) return st;
+      if ((st = gemm(EPI_HADAMARD, EL, nmu, 0, EL, nmu, 1, QLL, nmu, m, m, ec, 1.0, 0.0, W)) != ISDF_OK) return st;
+    } else {
+      // E_G = X^G D, E_L = X^L D; Q = (E X^T) o W
+      if ((st = gemm(EPI_AXPBY, XG, nmu, 0, in, N, 0, EG, nmu, m, n, n, 1.0, 0.0, nullptr)) != ISDF_OK) return st;
+      if ((st = gemm(EPI_AXPBY, XL, nmu, 0, in, N, 0, EL, nmu, m, n, n, 1.0, 0.0, nullptr)) != ISDF_OK) return st;
+      if ((st = gemm(EPI_HADAMARD, EG, nmu, 0, XG, nmu, 1, QGG, nmu, m, m, n, 1.0, 0.0, W)) != ISDF_OK) return st;
+      if ((st = gemm(EPI_HADAMARD, EG, nmu, 0, XL, nmu, 1, QGL, nmu, m, m, n, 1.0, 0.0, W)) != ISDF_OK) return st;
+      if ((st = gemm(EPI_HADAMARD, EL, nmu, 0, XL, nmu, 1, QLL, nmu, m, m, n, 1.0, 0.0, W)) != ISDF_OK) return st;
+    }
+    // Y1 = Q_GG X^L + Q_GL X^N ; Y2 = Q_GL^T X^L + Q_LL X^N
+    if ((st = gemm(EPI_AXPBY, QGG, nmu, 0, XL, nmu, 0, Y1, nmu, m, n, m, 1.0, 0.0, nullptr)) != ISDF_OK) return st;
+    if ((st = gemm(EPI_AXPBY, QGL, nmu, 0, XN, nmu, 0, Y1, nmu, m, n, m, 1.0, 1.0, nullptr)) != ISDF_OK) return st;
+    if ((st = gemm(EPI_AXPBY, QGL, nmu, 1, XL, nmu, 0, Y2, nmu, m, n, m, 1.0, 0.0, nullptr)) != ISDF_OK) return st;
+    if ((st = gemm(EPI_AXPBY, QLL, nmu, 0, XN, nmu, 0, Y2, nmu, m, n, m, 1.0, 1.0, nullptr)) != ISDF_OK) return st;
+    // K = -(X^L^T Y1 + X^N^T Y2)
+    if ((st = gemm(EPI_AXPBY, XL, nmu, 1, Y1, nmu, 0, K, N, n, n, m, -1.0, 0.0, nullptr)) != ISDF_OK) return st;
+    if ((st = gemm(EPI_AXPBY, XN, nmu, 1, Y2, nmu, 0, K, N, n, n, m, -1.0, 1.0, nullptr)) != ISDF_OK) return st;
+  }
+  if (stage_event) ISDF_HIP_TRY(hipEventRecord(plan->ev[1], s));
+  const double* Dm = in;
+  if (n_occ > 0) {  // D = C C^T for e_x = tr(D K)
+    if ((st = gemm(EPI_AXPBY, in, n_occ, 1, in, n_occ, 0, fit->Docc.as<double>(), N, n, n, n_occ, 1.0,
+                   0.0, nullptr)) != ISDF_OK)
+      return st;
+    Dm = fit->Docc.as<double>();
+  }
+  return launch_trace_dot(s, Dm, K, N * N, fit->partial.as<double>(), 1024, fit->ex_out.as<double>());
+}
+
+isdf_status exchange_run(isdf_plan_s* plan, isdf_fit_s* fit, const double* in, int n_occ, double* K,
+                         double* e_x) {
+  if (fit->plan != plan) {
+    set_error("isdf_exchange: fit belongs to another plan");
+    return ISDF_E_STATE;
+  }
+  MemScope mscope(plan->mem);
+  hipStream_t s = plan->stream;
+  isdf_status st;
+  if ((st = exchange_prepare(plan, fit, n_occ)) != ISDF_OK) return st;
+  const bool graph = plan->opts.eager_exchange == 0 && !plan->prof;
+  if (graph && (!fit->xexec || fit->xkey_in != in || fit->xkey_out != K || fit->xkey_nocc != n_occ)) {
+    fit->drop_graph();
+    if (!plan->cap_stream)
+      ISDF_HIP_TRY(hipStreamCreateWithFlags(&plan->cap_stream, hipStreamNonBlocking));
+    // recorded on the private stream (capture needs a non-null one), replayed on the plan's
+    ISDF_HIP_TRY(hipStreamSynchronize(s));
+    plan->stream = plan->cap_stream;
+    hipError_t e = hipStreamBeginCapture(plan->cap_stream, hipStreamCaptureModeRelaxed);
+    if (e != hipSuccess) {
+      plan->stream = s;
+      set_error(std::string("isdf_exchange: graph capture: ") + hipGetErrorString(e));
+      return ISDF_E_HIP;
+    }
+    st = exchange_enqueue(plan, fit, in, n_occ, K, false);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(plan->cap_stream, &g);
+    plan->stream = s;
+    if (st != ISDF_OK || e != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      if (st == ISDF_OK) {
+        set_error(std::string("isdf_exchange: graph capture: ") + hipGetErrorString(e));
+        st = ISDF_E_HIP;
+      }
+      return st;
+    }
+    hipGraphExec_t x = nullptr;
+    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      set_error(std::string("isdf_exchange: graph instantiate: ") + hipGetErrorString(e));
+      return ISDF_E_HIP;
+    }
+    fit->xgraph = g;
+    fit->xexec = x;
+    fit->xkey_in = in;
+    fit->xkey_out = K;
+    fit->xkey_nocc = n_occ;
+  }
+  ISDF_HIP_TRY(hipEventRecord(plan->ev[0], s));
+  if (graph) {
+    ISDF_HIP_TRY(hipGraphLaunch(fit->xexec, s));
+  } else {
+    if ((st = exchange_enqueue(plan, fit, in, n_occ, K, true)) != ISDF_OK) return st;
+  }
+  ISDF_HIP_TRY(hipEventRecord(plan->ev[2], s));
+  double ex = 0.0;
+  ISDF_HIP_TRY(hipMemcpyAsync(&ex, fit->ex_out.p, sizeof(double), hipMemcpyDeviceToHost, s));
+  ISDF_HIP_TRY(hipStreamSynchronize(s));
+  prof_collect(plan);
+  float ms;
+  ISDF_HIP_TRY(hipEventElapsedTime(&ms, plan->ev[0], plan->ev[2]));
+  plan->stage_ms[6] = ms;
+  if (!graph) ISDF_HIP_TRY(hipEventElapsedTime(&ms, plan->ev[0], plan->ev[1]));
+  plan->stage_ms[7] = ms;  // with a graph: the whole exchange
+  if (e_x) *e_x = ex;
+  if (!std::isfinite(ex)) {
+    set_error("isdf_exchange: non-finite exchange energy (NaN or Inf in the density?)");
+    return ISDF_E_ARG;
+  }
+  return ISDF_OK;
+}
+
 }  // namespace
 
 // ====================================================================== C ABI
@@ -1834,121 +2083,16 @@ isdf_status isdf_exchange(isdf_plan_t plan, isdf_fit_t fit, const double* D, dou
     set_error("isdf_exchange: null argument");
     return ISDF_E_ARG;
   }
-  if (fit->plan != plan) {
-    set_error("isdf_exchange: fit belongs to another plan");
-    return ISDF_E_STATE;
-  }
-  MemScope mscope(plan->mem);
-  hipStream_t s = plan->stream;
-  const int64_t nmu = fit->nmu, N = plan->hp.n_basis;
-  isdf_status st;
-  if (!fit->EG.p) {
-    if ((st = fit->EG.alloc(sizeof(double) * nmu * N)) != ISDF_OK) return st;
-    if ((st = fit->EL.alloc(sizeof(double) * nmu * N)) != ISDF_OK) return st;
-    if ((st = fit->Y1.alloc(sizeof(double) * nmu * N)) != ISDF_OK) return st;
-    if ((st = fit->Y2.alloc(sizeof(double) * nmu * N)) != ISDF_OK) return st;
-    if ((st = fit->QGG.alloc(sizeof(double) * nmu * nmu)) != ISDF_OK) return st;
-    if ((st = fit->QGL.alloc(sizeof(double) * nmu * nmu)) != ISDF_OK) return st;
-    if ((st = fit->QLL.alloc(sizeof(double) * nmu * nmu)) != ISDF_OK) return st;
-    if ((st = fit->partial.alloc(sizeof(double) * 1024)) != ISDF_OK) return st;
-    if ((st = fit->ex_out.alloc(sizeof(double))) != ISDF_OK) return st;
-  }
-  ISDF_HIP_TRY(hipEventRecord(plan->ev[0], s));
-  const double* XL = fit->XL.as<double>();
-  const double* XN = fit->XN.as<double>();
-  const double* XG = fit->XG.as<double>();
-  const double* W = fit->W.as<double>();
-  double* EG = fit->EG.as<double>();
-  double* EL = fit->EL.as<double>();
-  double* Y1 = fit->Y1.as<double>();
-  double* Y2 = fit->Y2.as<double>();
-  double* QGG = fit->QGG.as<double>();
-  double* QGL = fit->QGL.as<double>();
-  double* QLL = fit->QLL.as<double>();
-  auto gemm = [&](int epi, const double* A, int64_t lda, int tA, const double* B, int64_t ldb,
-                  int tB, double* C, int64_t ldc, int M, int Nn, int Kk, double alpha, double beta,
-                  const double* E) {
-    GemmProblem p{};
-    p.A = A; p.lda = lda; p.transA = tA;
-    p.B = B; p.ldb = ldb; p.transB = tB;
-    p.C = C; p.ldc = ldc;
-    p.E = E; p.lde = nmu;
-    p.M = M; p.N = Nn; p.K = Kk;
-    p.alpha = alpha; p.beta = beta;
-    return gemm_prof(plan, ISDF_K_GEMM_EXCHANGE, epi, p);
-  };
-  const int m = (int)nmu, n = (int)N;
-  if (mixed_on(plan, ISDF_MIX_EXCHANGE)) {
-    const int S = mixed_splits(plan);
-    if (!fit->xg_row.buf.p) {  // fit-time operands, split once
-      if ((st = make_planes(s, S, XG, 1, nmu, nullptr, m, n, fit->xg_row)) != ISDF_OK) return st;
-      if ((st = make_planes(s, S, XL, 1, nmu, nullptr, m, n, fit->xl_row)) != ISDF_OK) return st;
-      if ((st = make_planes(s, S, XL, nmu, 1, nullptr, n, m, fit->xl_col)) != ISDF_OK) return st;
-      if ((st = make_planes(s, S, XN, nmu, 1, nullptr, n, m, fit->xn_col)) != ISDF_OK) return st;
-    }
-    auto mg = [&](int epi, const Planes& A, const Planes& B, double* C, int64_t ldc, int M, int Nn,
-                  int Kk, double alpha, double beta) {
-      return mixed_prof(plan, ISDF_K_GEMM_EXCHANGE, epi,
-                        mixed_problem(A, B, C, ldc, M, Nn, Kk, alpha, beta, W, nmu));
-    };
-    // D as B operand: (k = nu, n = lam) -> plane row lam, column nu
-    if ((st = make_planes(s, S, D, N, 1, nullptr, n, n, fit->Dp)) != ISDF_OK) return st;
-    if ((st = mg(EPI_AXPBY, fit->xg_row, fit->Dp, EG, nmu, m, n, n, 1.0, 0.0)) != ISDF_OK) return st;
-    if ((st = mg(EPI_AXPBY, fit->xl_row, fit->Dp, EL, nmu, m, n, n, 1.0, 0.0)) != ISDF_OK) return st;
-    if ((st = make_planes(s, S, EG, 1, nmu, nullptr, m, n, fit->EGp)) != ISDF_OK) return st;
-    if ((st = make_planes(s, S, EL, 1, nmu, nullptr, m, n, fit->ELp)) != ISDF_OK) return st;
-    if ((st = mg(EPI_HADAMARD, fit->EGp, fit->xg_row, QGG, nmu, m, m, n, 1.0, 0.0)) != ISDF_OK) return st;
-    if ((st = mg(EPI_HADAMARD, fit->EGp, fit->xl_row, QGL, nmu, m, m, n, 1.0, 0.0)) != ISDF_OK) return st;
-    if ((st = mg(EPI_HADAMARD, fit->ELp, fit->xl_row, QLL, nmu, m, m, n, 1.0, 0.0)) != ISDF_OK) return st;
-    if ((st = make_planes(s, S, QGG, 1, nmu, nullptr, m, m, fit->QGGp)) != ISDF_OK) return st;
-    if ((st = make_planes(s, S, QGL, 1, nmu, nullptr, m, m, fit->QGLp)) != ISDF_OK) return st;
-    if ((st = make_planes(s, S, QGL, nmu, 1, nullptr, m, m, fit->QGLTp)) != ISDF_OK) return st;
-    if ((st = make_planes(s, S, QLL, 1, nmu, nullptr, m, m, fit->QLLp)) != ISDF_OK) return st;
-    if ((st = mg(EPI_AXPBY, fit->QGGp, fit->xl_col, Y1, nmu, m, n, m, 1.0, 0.0)) != ISDF_OK) return st;
-    if ((st = mg(EPI_AXPBY, fit->QGLp, fit->xn_col, Y1, nmu, m, n, m, 1.0, 1.0)) != ISDF_OK) return st;
-    if ((st = mg(EPI_AXPBY, fit->QGLTp, fit->xl_col, Y2, nmu, m, n, m, 1.0, 0.0)) != ISDF_OK) return st;
-    if ((st = mg(EPI_AXPBY, fit->QLLp, fit->xn_col, Y2, nmu, m, n, m, 1.0, 1.0)) != ISDF_OK) return st;
-    if ((st = make_planes(s, S, Y1, nmu, 1, nullptr, n, m, fit->Y1p)) != ISDF_OK) return st;
-    if ((st = make_planes(s, S, Y2, nmu, 1, nullptr, n, m, fit->Y2p)) != ISDF_OK) return st;
-    if ((st = mg(EPI_AXPBY, fit->xl_col, fit->Y1p, K, N, n, n, m, -1.0, 0.0)) != ISDF_OK) return st;
-    if ((st = mg(EPI_AXPBY, fit->xn_col, fit->Y2p, K, N, n, n, m, -1.0, 1.0)) != ISDF_OK) return st;
-  } else {
-  // E_G = X^G D, E_L = X^L D
-  if ((st = gemm(EPI_AXPBY, XG, nmu, 0, D, N, 0, EG, nmu, m, n, n, 1.0, 0.0, nullptr)) != ISDF_OK) return st;
-  if ((st = gemm(EPI_AXPBY, XL, nmu, 0, D, N, 0, EL, nmu, m, n, n, 1.0, 0.0, nullptr)) != ISDF_OK) return st;
-  // Q = (E X^T) o W
-  if ((st = gemm(EPI_HADAMARD, EG, nmu, 0, XG, nmu, 1, QGG, nmu, m, m, n, 1.0, 0.0, W)) != ISDF_OK) return st;
-  if ((st = gemm(EPI_HADAMARD, EG, nmu, 0, XL, nmu, 1, QGL, nmu, m, m, n, 1.0, 0.0, W)) != ISDF_OK) return st;
-  if ((st = gemm(EPI_HADAMARD, EL, nmu, 0, XL, nmu, 1, QLL, nmu, m, m, n, 1.0, 0.0, W)) != ISDF_OK) return st;
-  // Y1 = Q_GG X^L + Q_GL X^N ; Y2 = Q_GL^T X^L + Q_LL X^N
-  if ((st = gemm(EPI_AXPBY, QGG, nmu, 0, XL, nmu, 0, Y1, nmu, m, n, m, 1.0, 0.0, nullptr)) != ISDF_OK) return st;
-  if ((st = gemm(EPI_AXPBY, QGL, nmu, 0, XN, nmu, 0, Y1, nmu, m, n, m, 1.0, 1.0, nullptr)) != ISDF_OK) return st;
-  if ((st = gemm(EPI_AXPBY, QGL, nmu, 1, XL, nmu, 0, Y2, nmu, m, n, m, 1.0, 0.0, nullptr)) != ISDF_OK) return st;
-  if ((st = gemm(EPI_AXPBY, QLL, nmu, 0, XN, nmu, 0, Y2, nmu, m, n, m, 1.0, 1.0, nullptr)) != ISDF_OK) return st;
-  // K = -(X^L^T Y1 + X^N^T Y2)
-  if ((st = gemm(EPI_AXPBY, XL, nmu, 1, Y1, nmu, 0, K, N, n, n, m, -1.0, 0.0, nullptr)) != ISDF_OK) return st;
-  if ((st = gemm(EPI_AXPBY, XN, nmu, 1, Y2, nmu, 0, K, N, n, n, m, -1.0, 1.0, nullptr)) != ISDF_OK) return st;
-  }
-  ISDF_HIP_TRY(hipEventRecord(plan->ev[1], s));
-  if ((st = launch_trace_dot(s, D, K, N * N, fit->partial.as<double>(), 1024,
-                             fit->ex_out.as<double>())) != ISDF_OK)
-    return st;
-  ISDF_HIP_TRY(hipEventRecord(plan->ev[2], s));
-  double ex = 0.0;
-  ISDF_HIP_TRY(hipMemcpyAsync(&ex, fit->ex_out.p, sizeof(double), hipMemcpyDeviceToHost, s));
-  ISDF_HIP_TRY(hipStreamSynchronize(s));
-  prof_collect(plan);
-  float ms;
-  ISDF_HIP_TRY(hipEventElapsedTime(&ms, plan->ev[0], plan->ev[2]));
-  plan->stage_ms[6] = ms;
-  ISDF_HIP_TRY(hipEventElapsedTime(&ms, plan->ev[0], plan->ev[1]));
-  plan->stage_ms[7] = ms;
-  if (e_x) *e_x = ex;
-  if (!std::isfinite(ex)) {
-    set_error("isdf_exchange: non-finite exchange energy (NaN or Inf in D?)");
+  return exchange_run(plan, fit, D, 0, K, e_x);
+}
+
+isdf_status isdf_exchange_occ(isdf_plan_t plan, isdf_fit_t fit, const double* C_occ, int32_t n_occ,
+                              double* K, double* e_x) {
+  if (!plan || !fit || !C_occ || !K || n_occ < 1) {
+    set_error("isdf_exchange_occ: null argument or n_occ < 1");
     return ISDF_E_ARG;
   }
-  return ISDF_OK;
+  return exchange_run(plan, fit, C_occ, n_occ, K, e_x);
 }
 
 isdf_status isdf_stage_times(isdf_plan_t plan, double* t_ms, int32_t n) {
@@ -2013,6 +2157,7 @@ void isdf_plan_destroy(isdf_plan_t plan) {
   for (int i = 0; i <= NSTAGE; ++i)
     if (plan->ev[i]) (void)hipEventDestroy(plan->ev[i]);
   for (auto e : plan->evpool) (void)hipEventDestroy(e);
+  if (plan->cap_stream) (void)hipStreamDestroy(plan->cap_stream);
   delete plan;
 }
 
