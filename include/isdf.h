@@ -229,6 +229,18 @@ isdf_status isdf_exchange(isdf_plan_t plan, isdf_fit_t fit, const double* D_dev,
 isdf_status isdf_exchange_occ(isdf_plan_t plan, isdf_fit_t fit, const double* C_dev,
                               int32_t n_occ, double* K_dev, double* e_x);
 
+/* Tile-shape tuning of the FP64 GEMMs (for callers that set up a plan once
+ * and run it many times).  Runs one fit and one dense and one factored
+ * exchange (D = I, C = the first n_occ unit vectors) on the plan; every
+ * single-problem GEMM class met on the way (epilogue, role, triangle,
+ * layouts, accumulation, log2 sizes) is timed with each tile shape, best of
+ * `reps` launches, and the fastest is kept in the plan and written to
+ * json_out (NULL: kept only).  Results do not depend on the shape; only the
+ * speed does.  Load the file into later plans with isdf_options.tune_file.
+ * Errors: ISDF_E_ARG (n_occ outside 1..N, reps < 1, file not writable),
+ * those of isdf_fit and isdf_exchange. */
+isdf_status isdf_autotune(isdf_plan_t plan, int32_t n_occ, int32_t reps, const char* json_out);
+
 /* Stage outputs for checks, copied to host (synchronises).
  *   ISDF_FIELD_PHI    domain d: basis values, n_points x (n_L + n_N), column-major
  *   ISDF_FIELD_DIAG   domain d: Gram diagonal, n_points
@@ -255,13 +267,17 @@ isdf_status isdf_fit_info(isdf_fit_t fit, int64_t* n_mu);
  *   t[6] exchange total, t[7] exchange GEMM part. */
 isdf_status isdf_stage_times(isdf_plan_t plan, double* t_ms, int32_t n);
 
-/* Per-kernel instrumentation.  isdf_profile(plan, 1) resets the counters
- * and brackets every launch of the kernel families below with HIP events on
- * the plan's stream (0 turns it off).  isdf_kernel_stats returns, for one
- * family, the summed device time (ms), the launch count and the algorithmic
- * HBM bytes and flops of those launches (what the method must move or
- * compute: basis columns, factor columns and residuals for the selection
- * column kernel; 2 M N K per GEMM).
+/* Per-kernel instrumentation.  isdf_profile(plan, mask) resets the counters
+ * and brackets every launch of the kernel families whose bit is set in mask
+ * (bit f for family f, ISDF_K_ALL for all, 0 turns it off) with HIP events
+ * on the plan's stream; each bracket costs two event records, so profile
+ * only the families needed while timing.  With ISDF_K_GEMM_EXCHANGE in the
+ * mask the exchange runs eagerly instead of as a replayed graph.
+ * isdf_kernel_stats returns, for one family, the summed device time (ms),
+ * the launch count and the algorithmic HBM bytes and flops of those launches
+ * (what the method must move or compute: basis columns, factor columns and
+ * residuals for the selection column kernel; 2 M N K per GEMM, N (N + 1) K
+ * for a lower-triangle update).
  *   ISDF_K_SELECT_COLUMN  pivoted-Cholesky column + residual update
  *   ISDF_K_SELECT_PICK    tie-rule pivot pick
  *   ISDF_K_GEMM_SELECT    residual pair Gram and its rank updates (right-looking)
@@ -273,9 +289,9 @@ isdf_status isdf_stage_times(isdf_plan_t plan, double* t_ms, int32_t n);
 enum {
   ISDF_K_SELECT_COLUMN = 0, ISDF_K_SELECT_PICK = 1, ISDF_K_GEMM_SELECT = 2,
   ISDF_K_GEMM_METRIC = 3, ISDF_K_GEMM_FIT = 4, ISDF_K_GEMM_EXCHANGE = 5, ISDF_K_FFT = 6,
-  ISDF_K_BASIS = 7, ISDF_K_NFAMILY = 8
+  ISDF_K_BASIS = 7, ISDF_K_NFAMILY = 8, ISDF_K_ALL = (1 << 8) - 1
 };
-isdf_status isdf_profile(isdf_plan_t plan, int32_t enable);
+isdf_status isdf_profile(isdf_plan_t plan, int32_t family_mask);
 isdf_status isdf_kernel_stats(isdf_plan_t plan, int32_t family, double* ms, int64_t* launches,
                               double* bytes, double* flops);
 

@@ -31,7 +31,7 @@ EXPORTED = [
     "isdf_fit_get", "isdf_fit_info", "isdf_stage_times", "isdf_sync", "isdf_fit_destroy",
     "isdf_plan_destroy", "isdf_last_error", "isdf_version", "isdf_fit_with_candidates",
     "isdf_fit_selection", "isdf_fit_features", "isdf_mlp_forward", "isdf_mlp_loss_grad",
-    "isdf_mlp_train", "isdf_profile", "isdf_kernel_stats", "isdf_exchange_occ",
+    "isdf_mlp_train", "isdf_profile", "isdf_kernel_stats", "isdf_exchange_occ", "isdf_autotune",
 ]
 MLP_NPARAM = 5313
 
@@ -137,6 +137,7 @@ def load(required: bool = True):
     lib.isdf_mlp_train.argtypes = [vp, vp, C.c_int64, C.POINTER(_MlpConfig), fp, fp]
     lib.isdf_profile.argtypes = [vp, C.c_int32]
     lib.isdf_exchange_occ.argtypes = [vp, vp, vp, C.c_int32, vp, C.POINTER(C.c_double)]
+    lib.isdf_autotune.argtypes = [vp, C.c_int32, C.c_int32, C.c_char_p]
     lib.isdf_kernel_stats.argtypes = [vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64),
                                       C.POINTER(C.c_double), C.POINTER(C.c_double)]
     for name in ("isdf_plan", "isdf_plan_info", "isdf_plan_domain", "isdf_plan_domain_points",
@@ -144,7 +145,7 @@ def load(required: bool = True):
                  "isdf_exchange", "isdf_fit_get", "isdf_fit_info", "isdf_stage_times", "isdf_sync",
                  "isdf_fit_with_candidates", "isdf_fit_selection", "isdf_fit_features",
                  "isdf_mlp_forward", "isdf_mlp_loss_grad", "isdf_mlp_train", "isdf_profile",
-                 "isdf_kernel_stats", "isdf_exchange_occ"):
+                 "isdf_kernel_stats", "isdf_exchange_occ", "isdf_autotune"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -219,6 +220,12 @@ class Plan:
         n_basis, n_mu, nd = C.c_int64(), C.c_int64(), C.c_int32()
         _check(lib.isdf_plan_info(h, C.byref(n_basis), C.byref(n_mu), C.byref(nd)), "isdf_plan_info")
         self.n_basis, self.n_mu, self.n_domains = n_basis.value, n_mu.value, nd.value
+
+    def autotune(self, n_occ: int, reps: int = 3, json_out=None):
+        """Time every GEMM tile shape on this plan's problems (one fit and
+        both exchange forms) and keep the fastest; optionally write JSON."""
+        path = None if json_out is None else str(json_out).encode()
+        _check(load().isdf_autotune(self.handle, int(n_occ), int(reps), path), "isdf_autotune")
 
     def domain(self, d: int) -> dict:
         lib = load()

@@ -14,8 +14,11 @@
 // Hadamard product against W fused into their epilogue, and E_x = tr(D K).
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
+#include <fstream>
 #include <map>
+#include <sstream>
 #include <memory>
 #include <numeric>
 
@@ -270,12 +273,18 @@ struct isdf_plan_s {
     hipEvent_t a, b;
     double bytes, flops;
   };
-  bool prof = false;
+  int prof = 0;  // family mask of the bracketed launches
   std::vector<hipEvent_t> evpool;
   size_t evnext = 0;
   std::vector<ProfRec> pending;
   double kms[ISDF_K_NFAMILY] = {}, kbytes[ISDF_K_NFAMILY] = {}, kflops[ISDF_K_NFAMILY] = {};
   int64_t kn[ISDF_K_NFAMILY] = {};
+  // GEMM tile shapes per problem class: read from the tune file, or
+  // measured while `tuning` (isdf_autotune)
+  std::map<std::string, int> tune;
+  std::map<std::string, std::vector<float>> tune_us;
+  bool tuning = false;
+  int tune_reps = 3;
 };
 
 struct isdf_fit_s {
@@ -333,7 +342,7 @@ struct ProfScope {
   double bytes, flops;
   hipEvent_t a = nullptr;
   ProfScope(isdf_plan_s* p, int f, double by, double fl) : pl(p), fam(f), bytes(by), flops(fl) {
-    if (pl->prof) {
+    if ((pl->prof >> fam) & 1) {
       a = prof_event(pl);
       if (a) (void)hipEventRecord(a, pl->stream);
     }
@@ -404,9 +413,84 @@ isdf_status mixed_prof(isdf_plan_s* pl, int fam, int epi, const MixedProblem& p)
   return gemm_mixed(pl->stream, epi, S, p, family_tag(fam));
 }
 
+// Class of a single GEMM problem for the tile-shape table: epilogue, role,
+// triangle, operand layouts, accumulation and log2 buckets of the sizes.
+std::string gemm_key(int epi, int tag, const GemmProblem& p) {
+  auto lg = [](int x) {
+    int b = 0;
+    while ((2 << b) <= x) ++b;
+    return b;
+  };
+  char k[160];
+  std::snprintf(k, sizeof(k), "e%d t%d l%d a%d b%d c%d g%d m%d n%d k%d", epi, tag, p.lower ? 1 : 0,
+                p.transA, p.transB, p.beta != 0.0 ? 1 : 0, p.bidx ? 1 : 0, lg(p.M), lg(p.N),
+                lg(std::max(p.K, 1)));
+  return k;
+}
+
+// Time every valid shape on the problem itself (C saved and restored when
+// the update reads it) and keep the fastest; results of all shapes agree
+// bit for bit, so the choice changes speed only.
+isdf_status tune_problem(isdf_plan_s* pl, int epi, int tag, const GemmProblem& p, const std::string& key) {
+  hipStream_t s = pl->stream;
+  const bool rd = p.beta != 0.0;
+  const size_t cbytes = sizeof(double) * ((size_t)(p.N - 1) * p.ldc + p.M);
+  DevBuf save;
+  isdf_status st;
+  ISDF_HIP_TRY(hipStreamSynchronize(s));
+  if (rd) {
+    if ((st = save.alloc(cbytes)) != ISDF_OK) return st;
+    ISDF_HIP_TRY(hipMemcpyAsync(save.p, p.C, cbytes, hipMemcpyDeviceToDevice, s));
+  }
+  hipEvent_t a, b;
+  ISDF_HIP_TRY(hipEventCreate(&a));
+  ISDF_HIP_TRY(hipEventCreate(&b));
+  std::vector<float> us(GEMM_NSHAPE, -1.f);
+  int best = gemm_default_shape(epi, p.M, p.N, p.K, p.lower != 0);
+  float tbest = 0.f;
+  for (int sh = 0; sh < GEMM_NSHAPE; ++sh) {
+    if (p.lower && kShapes[sh].bm != kShapes[sh].bn) continue;
+    float tmin = 0.f;
+    for (int r = 0; r < pl->tune_reps; ++r) {
+      if (rd) ISDF_HIP_TRY(hipMemcpyAsync(p.C, save.p, cbytes, hipMemcpyDeviceToDevice, s));
+      ISDF_HIP_TRY(hipEventRecord(a, s));
+      if ((st = gemm_f64(s, epi, p, tag, sh)) != ISDF_OK) return st;
+      ISDF_HIP_TRY(hipEventRecord(b, s));
+      ISDF_HIP_TRY(hipEventSynchronize(b));
+      float ms = 0.f;
+      ISDF_HIP_TRY(hipEventElapsedTime(&ms, a, b));
+      if (r == 0 || ms < tmin) tmin = ms;
+    }
+    us[sh] = 1e3f * tmin;
+    if (us[sh] >= 0.f && (tbest == 0.f || us[sh] < tbest)) {
+      tbest = us[sh];
+      best = sh;
+    }
+  }
+  if (rd) ISDF_HIP_TRY(hipMemcpyAsync(p.C, save.p, cbytes, hipMemcpyDeviceToDevice, s));
+  ISDF_HIP_TRY(hipStreamSynchronize(s));
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  pl->tune[key] = best;
+  pl->tune_us[key] = us;
+  return ISDF_OK;
+}
+
 isdf_status gemm_prof(isdf_plan_s* pl, int fam, int epi, const GemmProblem& p) {
+  const int tag = family_tag(fam);
+  int shape = -1;
+  if (pl->tuning || !pl->tune.empty()) {
+    const std::string key = gemm_key(epi, tag, p);
+    auto it = pl->tune.find(key);
+    if (it == pl->tune.end() && pl->tuning && p.M > 0 && p.N > 0) {
+      isdf_status st = tune_problem(pl, epi, tag, p, key);
+      if (st != ISDF_OK) return st;
+      it = pl->tune.find(key);
+    }
+    if (it != pl->tune.end()) shape = it->second;
+  }
   ProfScope ps(pl, fam, gemm_bytes(p), gemm_flops(p));
-  return gemm_f64(pl->stream, epi, p, family_tag(fam));
+  return gemm_f64(pl->stream, epi, p, tag, shape);
 }
 
 isdf_status fft_prof(isdf_plan_s* pl, double* z, int batch, const int grid[3], int sign) {
@@ -1232,6 +1316,10 @@ isdf_status run_coulomb(isdf_plan_s* pl, isdf_fit_s* f) {
         if ((st = mixed_prof(pl, ISDF_K_GEMM_METRIC, EPI_AXPBY, mp)) != ISDF_OK) return st;
         continue;
       }
+      if (gl.cnt == 1) {  // a lone problem (the universal rows) takes the tuned shape
+        if ((st = gemm_prof(pl, ISDF_K_GEMM_METRIC, EPI_AXPBY, probs[gl.off])) != ISDF_OK) return st;
+        continue;
+      }
       ProfScope ps(pl, ISDF_K_GEMM_METRIC, gl.bytes, gl.flops);
       if ((st = gemm_f64_grouped(s, EPI_AXPBY, d_probs.as<GemmProblem>() + gl.off, gl.cnt,
                                  gl.tiles, family_tag(ISDF_K_GEMM_METRIC), gl.shape)) != ISDF_OK)
@@ -1395,27 +1483,31 @@ isdf_status do_fit(isdf_plan_s* pl, const int64_t* pinned, const int64_t* cand_i
       // windows are skinny)
       std::vector<GemmProblem> grouped;
       int tiles[GEMM_NSHAPE] = {}, first[GEMM_NSHAPE] = {}, cnt[GEMM_NSHAPE] = {};
-      double by = 0.0, fl = 0.0;
+      double by[GEMM_NSHAPE] = {}, fl[GEMM_NSHAPE] = {};
       for (int shape = 0; shape < GEMM_NSHAPE; ++shape) {
         first[shape] = (int)grouped.size();
         for (GemmProblem p : probs) {
           if (gemm_default_shape(EPI_THETA, p.M, p.N, p.K) != shape) continue;
           p.tile_start = tiles[shape];
           tiles[shape] += gemm_tiles(p.M, p.N, shape);
-          by += gemm_bytes(p);
-          fl += gemm_flops(p);
+          by[shape] += gemm_bytes(p);
+          fl[shape] += gemm_flops(p);
           grouped.push_back(p);
         }
         cnt[shape] = (int)grouped.size() - first[shape];
       }
       DevBuf d_probs;
       if ((st = upload(d_probs, grouped)) != ISDF_OK) return st;
-      ProfScope ps(pl, ISDF_K_GEMM_FIT, by, fl);
-      for (int shape = 0; shape < GEMM_NSHAPE; ++shape)
-        if (cnt[shape] > 0 &&
-            (st = gemm_f64_grouped(s, EPI_THETA, d_probs.as<GemmProblem>() + first[shape], cnt[shape],
-                                   tiles[shape], family_tag(ISDF_K_GEMM_FIT), shape)) != ISDF_OK)
-          return st;
+      for (int shape = 0; shape < GEMM_NSHAPE; ++shape) {
+        if (cnt[shape] == 1) {  // a lone problem (the universal domain) takes the tuned shape
+          if ((st = gemm_prof(pl, ISDF_K_GEMM_FIT, EPI_THETA, grouped[first[shape]])) != ISDF_OK) return st;
+        } else if (cnt[shape] > 1) {
+          ProfScope ps(pl, ISDF_K_GEMM_FIT, by[shape], fl[shape]);
+          if ((st = gemm_f64_grouped(s, EPI_THETA, d_probs.as<GemmProblem>() + first[shape], cnt[shape],
+                                     tiles[shape], family_tag(ISDF_K_GEMM_FIT), shape)) != ISDF_OK)
+            return st;
+        }
+      }
     }
     ISDF_HIP_TRY(hipStreamSynchronize(s));
   }
@@ -1486,6 +1578,77 @@ isdf_status do_fit(isdf_plan_s* pl, const int64_t* pinned, const int64_t* cand_i
     return ISDF_E_RANK;
   }
   return ISDF_OK;
+}
+
+// ------------------------------------------------------------ tune file
+// {"arch": "...", "entries": [{"key": "<class>", "shape": s, "us": [...]}, ...]}
+// Only the key/shape pairs are read back; times are for the reader.
+isdf_status read_tune_file(const char* path, std::map<std::string, int>& out) {
+  std::ifstream f(path);
+  if (!f) {
+    set_error(std::string("tune file: cannot open ") + path);
+    return ISDF_E_ARG;
+  }
+  std::stringstream ss;
+  ss << f.rdbuf();
+  const std::string t = ss.str();
+  size_t pos = 0;
+  int n = 0;
+  while ((pos = t.find("\"key\"", pos)) != std::string::npos) {
+    const size_t q0 = t.find('"', t.find(':', pos) + 1);
+    const size_t q1 = q0 == std::string::npos ? q0 : t.find('"', q0 + 1);
+    const size_t sp = q1 == std::string::npos ? q1 : t.find("\"shape\"", q1);
+    if (sp == std::string::npos) break;
+    const size_t c = t.find(':', sp);
+    const int shape = c == std::string::npos ? -1 : std::atoi(t.c_str() + c + 1);
+    if (shape < 0 || shape >= GEMM_NSHAPE) {
+      set_error(std::string("tune file: bad shape in ") + path);
+      return ISDF_E_ARG;
+    }
+    out[t.substr(q0 + 1, q1 - q0 - 1)] = shape;
+    pos = c;
+    ++n;
+  }
+  if (n == 0 && t.find("\"entries\"") == std::string::npos) {
+    set_error(std::string("tune file: no entries in ") + path);
+    return ISDF_E_ARG;
+  }
+  return ISDF_OK;
+}
+
+isdf_status write_tune_file(const isdf_plan_s* pl, const char* path) {
+  std::ofstream f(path);
+  if (!f) {
+    set_error(std::string("tune file: cannot write ") + path);
+    return ISDF_E_ARG;
+  }
+  int dev = 0;
+  hipDeviceProp_t pr{};
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&pr, dev) != hipSuccess)
+    std::snprintf(pr.gcnArchName, sizeof(pr.gcnArchName), "unknown");
+  f << "{\n  \"arch\": \"" << pr.gcnArchName << "\",\n  \"shapes\": [";
+  for (int i = 0; i < GEMM_NSHAPE; ++i)
+    f << (i ? ", " : "") << "\"" << kShapes[i].bm << "x" << kShapes[i].bn << " w" << kShapes[i].wm
+      << "x" << kShapes[i].wn << "\"";
+  f << "],\n  \"entries\": [";
+  bool first = true;
+  for (const auto& kv : pl->tune) {
+    f << (first ? "\n" : ",\n") << "    {\"key\": \"" << kv.first << "\", \"shape\": " << kv.second;
+    auto it = pl->tune_us.find(kv.first);
+    if (it != pl->tune_us.end()) {
+      f << ", \"us\": [";
+      for (size_t i = 0; i < it->second.size(); ++i) {
+        char b[32];
+        std::snprintf(b, sizeof(b), "%.1f", it->second[i]);
+        f << (i ? ", " : "") << b;
+      }
+      f << "]";
+    }
+    f << "}";
+    first = false;
+  }
+  f << "\n  ]\n}\n";
+  return f ? ISDF_OK : ISDF_E_ARG;
 }
 
 // ------------------------------------------------------------- exchange
@@ -1648,7 +1811,8 @@ isdf_status exchange_run(isdf_plan_s* plan, isdf_fit_s* fit, const double* in, i
   hipStream_t s = plan->stream;
   isdf_status st;
   if ((st = exchange_prepare(plan, fit, n_occ)) != ISDF_OK) return st;
-  const bool graph = plan->opts.eager_exchange == 0 && !plan->prof;
+  const bool graph = plan->opts.eager_exchange == 0 && !((plan->prof >> ISDF_K_GEMM_EXCHANGE) & 1) &&
+                     !plan->tuning;
   if (graph && (!fit->xexec || fit->xkey_in != in || fit->xkey_out != K || fit->xkey_nocc != n_occ)) {
     fit->drop_graph();
     if (!plan->cap_stream)
@@ -1753,6 +1917,10 @@ isdf_status isdf_plan(const isdf_system* sys, const isdf_options* opts, isdf_pla
   } else if (pl->opts.selector != ISDF_SEL_FULL) {
     set_error("isdf_plan: unknown selector");
     return ISDF_E_ARG;
+  }
+  if (pl->opts.tune_file) {
+    if ((st = read_tune_file(pl->opts.tune_file, pl->tune)) != ISDF_OK) return st;
+    pl->opts.tune_file = nullptr;  // not kept: the caller owns the string
   }
   pl->stream = static_cast<hipStream_t>(pl->opts.stream);
   pl->mem = std::make_shared<MemCtx>();
@@ -2095,6 +2263,41 @@ isdf_status isdf_exchange_occ(isdf_plan_t plan, isdf_fit_t fit, const double* C_
   return exchange_run(plan, fit, C_occ, n_occ, K, e_x);
 }
 
+isdf_status isdf_autotune(isdf_plan_t plan, int32_t n_occ, int32_t reps, const char* json_out) {
+  if (!plan || n_occ < 1 || reps < 1) {
+    set_error("isdf_autotune: null plan, n_occ < 1 or reps < 1");
+    return ISDF_E_ARG;
+  }
+  const int64_t N = plan->hp.n_basis;
+  if (n_occ > N) {
+    set_error("isdf_autotune: n_occ above the basis size");
+    return ISDF_E_ARG;
+  }
+  isdf_status st = ISDF_OK;
+  plan->tuning = true;
+  plan->tune_reps = reps;
+  isdf_fit_t fit = nullptr;
+  {
+    // operands of the exchange shapes: D = I, C = the first n_occ unit vectors
+    std::vector<double> hD((size_t)(N * N), 0.0), hC((size_t)(N * n_occ), 0.0);
+    for (int64_t i = 0; i < N; ++i) hD[i * N + i] = 1.0;
+    for (int64_t i = 0; i < n_occ; ++i) hC[i * n_occ + i] = 1.0;
+    DevBuf dD, dC, dK;
+    MemScope mscope(plan->mem);
+    st = do_fit(plan, nullptr, nullptr, nullptr, nullptr, &fit);
+    if (st == ISDF_OK && (st = upload(dD, hD)) == ISDF_OK && (st = upload(dC, hC)) == ISDF_OK &&
+        (st = dK.alloc(sizeof(double) * N * N)) == ISDF_OK) {
+      st = exchange_run(plan, fit, dD.as<double>(), 0, dK.as<double>(), nullptr);
+      if (st == ISDF_OK) st = exchange_run(plan, fit, dC.as<double>(), n_occ, dK.as<double>(), nullptr);
+    }
+    if (fit) isdf_fit_destroy(fit);
+  }
+  plan->tuning = false;
+  if (st != ISDF_OK) return st;
+  if (json_out) return write_tune_file(plan, json_out);
+  return ISDF_OK;
+}
+
 isdf_status isdf_stage_times(isdf_plan_t plan, double* t_ms, int32_t n) {
   if (!plan || !t_ms) {
     set_error("isdf_stage_times: null argument");
@@ -2104,14 +2307,14 @@ isdf_status isdf_stage_times(isdf_plan_t plan, double* t_ms, int32_t n) {
   return ISDF_OK;
 }
 
-isdf_status isdf_profile(isdf_plan_t plan, int32_t enable) {
+isdf_status isdf_profile(isdf_plan_t plan, int32_t family_mask) {
   if (!plan) {
     set_error("isdf_profile: null plan");
     return ISDF_E_ARG;
   }
   ISDF_HIP_TRY(hipStreamSynchronize(plan->stream));
   prof_collect(plan);
-  plan->prof = enable != 0;
+  plan->prof = family_mask & ISDF_K_ALL;
   for (int i = 0; i < ISDF_K_NFAMILY; ++i) {
     plan->kms[i] = plan->kbytes[i] = plan->kflops[i] = 0.0;
     plan->kn[i] = 0;

@@ -91,3 +91,23 @@ def test_null_arguments():
     assert lib.isdf_fit(None, C.byref(h)) == -1
     assert lib.isdf_exchange(None, None, None, None, None) == -1
     assert lib.isdf_last_error()
+
+
+def test_tune_file_errors(tmp_path):
+    """The plan reads the tile-shape table at creation (no GPU work):
+    missing files and out-of-range shapes are argument errors."""
+    from paper_2404_09373_amd import binding
+    from workloads import tiny_system
+
+    s = tiny_system("one_atom")
+    with pytest.raises(binding.IsdfError) as e:
+        binding.Plan(s, tune_file=tmp_path / "missing.json")
+    assert e.value.status == -1
+    bad = tmp_path / "bad.json"
+    bad.write_text('{"arch": "gfx950", "entries": [{"key": "e0 t1", "shape": 9}]}')
+    with pytest.raises(binding.IsdfError) as e:
+        binding.Plan(s, tune_file=bad)
+    assert e.value.status == -1
+    good = tmp_path / "good.json"
+    good.write_text('{"arch": "gfx950", "entries": [{"key": "e0 t1 l0 a0 b0 c0 g0 m5 n5 k5", "shape": 2}]}')
+    binding.Plan(s, tune_file=good).close()
