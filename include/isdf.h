@@ -144,6 +144,21 @@ isdf_status isdf_plan_domain_functions(isdf_plan_t plan, int32_t d, int32_t* fun
  * early by eps_isdf while n_mu_ratio > 0; the fit is still usable). */
 isdf_status isdf_fit(isdf_plan_t plan, isdf_fit_t* out);
 
+/* Fits of several plans (independent cells of a batch) at once: up to
+ * max_concurrent (<= 0: 4) host threads each take the next plan, largest
+ * N_mu first, and run isdf_fit on it, so that the cells' kernels and host
+ * decisions overlap on the GPU.  Plans made with a NULL stream get a
+ * private stream for the duration of the call; give plans their own
+ * streams otherwise (fits of plans that share a stream serialise).  The
+ * plans must be distinct and must not be used by other threads meanwhile.
+ * fits[i] receives the fit of plans[i] (NULL where it failed);
+ * statuses[i] (may be NULL) its status.  Returns ISDF_OK or the status of
+ * the first failed plan in index order (message names the plan); the
+ * caller destroys every non-NULL fit either way.  Results equal those of
+ * isdf_fit on each plan alone. */
+isdf_status isdf_fit_batch(const isdf_plan_t* plans, int32_t n, int32_t max_concurrent,
+                           isdf_fit_t* fits, isdf_status* statuses);
+
 /* Same with the points of every domain given instead of selected:
  * local_points holds, domain after domain, n_mu_d local point indices
  * (positions in the domain's point list).  Duplicate points make the

@@ -32,6 +32,7 @@ EXPORTED = [
     "isdf_plan_destroy", "isdf_last_error", "isdf_version", "isdf_fit_with_candidates",
     "isdf_fit_selection", "isdf_fit_features", "isdf_mlp_forward", "isdf_mlp_loss_grad",
     "isdf_mlp_train", "isdf_profile", "isdf_kernel_stats", "isdf_exchange_occ", "isdf_autotune",
+    "isdf_fit_batch",
 ]
 MLP_NPARAM = 5313
 
@@ -138,6 +139,8 @@ def load(required: bool = True):
     lib.isdf_profile.argtypes = [vp, C.c_int32]
     lib.isdf_exchange_occ.argtypes = [vp, vp, vp, C.c_int32, vp, C.POINTER(C.c_double)]
     lib.isdf_autotune.argtypes = [vp, C.c_int32, C.c_int32, C.c_char_p]
+    lib.isdf_fit_batch.argtypes = [C.POINTER(vp), C.c_int32, C.c_int32, C.POINTER(vp),
+                                   C.POINTER(C.c_int)]
     lib.isdf_kernel_stats.argtypes = [vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64),
                                       C.POINTER(C.c_double), C.POINTER(C.c_double)]
     for name in ("isdf_plan", "isdf_plan_info", "isdf_plan_domain", "isdf_plan_domain_points",
@@ -145,7 +148,7 @@ def load(required: bool = True):
                  "isdf_exchange", "isdf_fit_get", "isdf_fit_info", "isdf_stage_times", "isdf_sync",
                  "isdf_fit_with_candidates", "isdf_fit_selection", "isdf_fit_features",
                  "isdf_mlp_forward", "isdf_mlp_loss_grad", "isdf_mlp_train", "isdf_profile",
-                 "isdf_kernel_stats", "isdf_exchange_occ", "isdf_autotune"):
+                 "isdf_kernel_stats", "isdf_exchange_occ", "isdf_autotune", "isdf_fit_batch"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -277,6 +280,30 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def fit_batch(plans, max_concurrent: int = 4, allow_rank: bool = True):
+    """Fits of several plans at once (isdf_fit_batch); returns the list of
+    Fit objects in plan order.  Raises on the first failed plan after
+    destroying every fit the call made."""
+    lib = load()
+    n = len(plans)
+    hp = (C.c_void_p * n)(*[p.handle.value for p in plans])
+    hf = (C.c_void_p * n)()
+    sts = (C.c_int * n)()
+    st = lib.isdf_fit_batch(hp, n, int(max_concurrent), hf, sts)
+    fits = [Fit(p, C.c_void_p(h)) if h else None for p, h in zip(plans, hf)]
+    allow = (-5,) if allow_rank else ()
+    if st != ISDF_OK and (all(x == ISDF_OK for x in sts) or
+                          any(x != ISDF_OK and x not in allow for x in sts)):
+        for f in fits:
+            if f is not None:
+                f.close()
+        _check(st, "isdf_fit_batch")
+    for f, x in zip(fits, sts):
+        if f is not None:
+            f.status = x
+    return fits
 
 
 class Fit:

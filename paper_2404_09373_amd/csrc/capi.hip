@@ -13,6 +13,7 @@
 // isdf_exchange runs the four-term K of Eq. ints as MFMA GEMMs with the
 // Hadamard product against W fused into their epilogue, and E_x = tr(D K).
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -20,7 +21,9 @@
 #include <map>
 #include <sstream>
 #include <memory>
+#include <mutex>
 #include <numeric>
+#include <thread>
 
 #include "common.h"
 
@@ -34,6 +37,7 @@ using namespace isdf;
 namespace {
 
 constexpr int NSTAGE = 8;
+std::mutex g_big_alloc_mu;  // see select_points
 constexpr int RL_MIN_PIVOTS = 128;  // right-looking selection above this many pivots
 constexpr int RL_BLOCK = 128;       // pivots between residual (SYRK) updates
 
@@ -624,23 +628,30 @@ isdf_status select_points(isdf_plan_s* pl, const std::vector<SelSpec>& spec,
   isdf_status st;
   // Large single-domain batches (the universal grid) use the right-looking
   // form: residual Gram kept in HBM, SYRK update every RL_BLOCK pivots.
-  size_t free_b = 0, total_b = 0;
-  ISDF_HIP_TRY(hipMemGetInfo(&free_b, &total_b));
+  // The memory test and the allocation of the residual Gram are one step
+  // under a process-wide lock, so plans fitted concurrently (isdf_fit_batch)
+  // see each other's residual Grams.
   std::vector<char> right(nd, 0);
   int64_t mres_max = 0;
-  for (int d = 0; d < nd; ++d) {
-    int nlev = 0;
-    for (int e = 0; e < nd; ++e) nlev += spec[e].level == spec[d].level;
-    const double P = (double)sd[d].pts;
-    if (nlev == 1 && sd[d].n_mu > RL_MIN_PIVOTS && P * P * 8.0 <= 0.4 * (double)free_b) {
-      right[d] = 1;
-      sd[d].mres_off = 0;
-      mres_max = std::max<int64_t>(mres_max, (int64_t)sd[d].pts * sd[d].pts);
-    }
-  }
   DevBuf mres, lfac, prow, tmax, tidx, state, d_sd, d_tile_dom;
-  if (mres_max > 0)
-    if ((st = mres.alloc(sizeof(double) * mres_max)) != ISDF_OK) return st;
+  {
+    std::lock_guard<std::mutex> lock(g_big_alloc_mu);
+    size_t free_b = 0, total_b = 0;
+    ISDF_HIP_TRY(hipMemGetInfo(&free_b, &total_b));
+    const double avail = (double)free_b + (double)(pl->mem ? pl->mem->cached : 0);
+    for (int d = 0; d < nd; ++d) {
+      int nlev = 0;
+      for (int e = 0; e < nd; ++e) nlev += spec[e].level == spec[d].level;
+      const double P = (double)sd[d].pts;
+      if (nlev == 1 && sd[d].n_mu > RL_MIN_PIVOTS && P * P * 8.0 <= 0.4 * avail) {
+        right[d] = 1;
+        sd[d].mres_off = 0;
+        mres_max = std::max<int64_t>(mres_max, (int64_t)sd[d].pts * sd[d].pts);
+      }
+    }
+    if (mres_max > 0)
+      if ((st = mres.alloc(sizeof(double) * mres_max)) != ISDF_OK) return st;
+  }
   if ((st = upload(d_sd, sd)) != ISDF_OK) return st;
   if ((st = upload(d_tile_dom, tile_dom)) != ISDF_OK) return st;
   const int ntiles = (int)tile_dom.size();
@@ -1979,6 +1990,88 @@ isdf_status isdf_plan_domain_functions(isdf_plan_t plan, int32_t d, int32_t* fun
 isdf_status isdf_fit(isdf_plan_t plan, isdf_fit_t* out) {
   if (out) *out = nullptr;
   return do_fit(plan, nullptr, nullptr, nullptr, nullptr, out);
+}
+
+isdf_status isdf_fit_batch(const isdf_plan_t* plans, int32_t n, int32_t max_concurrent,
+                           isdf_fit_t* fits, isdf_status* statuses) {
+  if (!plans || !fits || n < 0) {
+    set_error("isdf_fit_batch: null plans/fits or n < 0");
+    return ISDF_E_ARG;
+  }
+  for (int i = 0; i < n; ++i) {
+    fits[i] = nullptr;
+    if (statuses) statuses[i] = ISDF_OK;
+  }
+  for (int i = 0; i < n; ++i) {
+    if (!plans[i]) {
+      set_error("isdf_fit_batch: null plan " + std::to_string(i));
+      return ISDF_E_ARG;
+    }
+    for (int j = 0; j < i; ++j)
+      if (plans[j] == plans[i]) {
+        set_error("isdf_fit_batch: plan " + std::to_string(i) + " appears twice");
+        return ISDF_E_ARG;
+      }
+  }
+  if (n == 0) return ISDF_OK;
+  int dev = 0;
+  ISDF_HIP_TRY(hipGetDevice(&dev));
+  // plans on the null stream get a private stream for the call (the null
+  // stream would serialise them)
+  std::vector<hipStream_t> own(n, nullptr);
+  for (int i = 0; i < n; ++i)
+    if (!plans[i]->stream) {
+      hipError_t e = hipStreamCreateWithFlags(&own[i], hipStreamNonBlocking);
+      if (e != hipSuccess) {
+        for (int j = 0; j < i; ++j)
+          if (own[j]) {
+            plans[j]->stream = nullptr;
+            plans[j]->mem->stream = nullptr;
+            (void)hipStreamDestroy(own[j]);
+          }
+        set_error(std::string("isdf_fit_batch: stream: ") + hipGetErrorString(e));
+        return ISDF_E_HIP;
+      }
+      plans[i]->stream = own[i];
+      plans[i]->mem->stream = own[i];
+    }
+  // largest first, so that the long fits start early
+  std::vector<int> order(n);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return plans[a]->hp.n_mu_total > plans[b]->hp.n_mu_total;
+  });
+  std::vector<isdf_status> sts(n, ISDF_OK);
+  std::vector<std::string> msg(n);
+  std::atomic<int> next(0);
+  auto worker = [&]() {
+    if (hipSetDevice(dev) != hipSuccess) return;
+    for (int k; (k = next.fetch_add(1)) < n;) {
+      const int i = order[k];
+      sts[i] = do_fit(plans[i], nullptr, nullptr, nullptr, nullptr, &fits[i]);
+      if (sts[i] != ISDF_OK) msg[i] = g_err;
+    }
+  };
+  const int nt = std::max(1, std::min(n, max_concurrent > 0 ? (int)max_concurrent : 4));
+  std::vector<std::thread> pool;
+  for (int t = 0; t < nt; ++t) pool.emplace_back(worker);
+  for (auto& t : pool) t.join();
+  for (int i = 0; i < n; ++i)
+    if (own[i]) {
+      (void)hipStreamSynchronize(own[i]);
+      plans[i]->stream = nullptr;
+      plans[i]->mem->stream = nullptr;
+      (void)hipStreamDestroy(own[i]);
+    }
+  isdf_status first = ISDF_OK;
+  for (int i = 0; i < n; ++i) {
+    if (statuses) statuses[i] = sts[i];
+    if (sts[i] != ISDF_OK && first == ISDF_OK) {
+      first = sts[i];
+      set_error("isdf_fit_batch: plan " + std::to_string(i) + ": " + msg[i]);
+    }
+  }
+  return first;
 }
 
 isdf_status isdf_fit_with_points(isdf_plan_t plan, const int64_t* local_points, isdf_fit_t* out) {

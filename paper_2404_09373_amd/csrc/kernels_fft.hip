@@ -14,6 +14,8 @@
 // into grid l's index space (zero elsewhere), ready for the inverse pass.
 #include <cmath>
 
+#include <mutex>
+
 #include "common.h"
 
 namespace isdf {
@@ -176,17 +178,24 @@ fft_pass_kernel(double2* __restrict__ z, int batch, int n1, int n2, int n3, int 
   }
 }
 
-// host twiddle tables e^{-2 pi i t / n}, cached per n
+// host twiddle tables e^{-2 pi i t / n}, cached per (device, n) for the
+// life of the process; a mutex keeps concurrent plans (isdf_fit_batch) safe
 struct TwCache {
-  int n = 0;
-  double2* dev = nullptr;
+  int dev = -1, n = 0;
+  double2* ptr = nullptr;
 };
-static TwCache g_tw[64];
+constexpr int TW_MAX = 128;
+static TwCache g_tw[TW_MAX];
 static int g_ntw = 0;
+static std::mutex g_tw_mu;
 
 static const double2* twiddles(int n) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  std::lock_guard<std::mutex> lock(g_tw_mu);
   for (int i = 0; i < g_ntw; ++i)
-    if (g_tw[i].n == n) return g_tw[i].dev;
+    if (g_tw[i].dev == dev && g_tw[i].n == n) return g_tw[i].ptr;
+  if (g_ntw == TW_MAX) return nullptr;
   std::vector<double2> h(n);
   for (int t = 0; t < n; ++t) {
     long double ang = -2.0L * 3.141592653589793238462643383279502884L * (long double)t / n;
@@ -194,8 +203,11 @@ static const double2* twiddles(int n) {
   }
   double2* d = nullptr;
   if (hipMalloc(&d, sizeof(double2) * n) != hipSuccess) return nullptr;
-  if (hipMemcpy(d, h.data(), sizeof(double2) * n, hipMemcpyHostToDevice) != hipSuccess) return nullptr;
-  if (g_ntw < 64) g_tw[g_ntw++] = TwCache{n, d};
+  if (hipMemcpy(d, h.data(), sizeof(double2) * n, hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(d);
+    return nullptr;
+  }
+  g_tw[g_ntw++] = TwCache{dev, n, d};
   return d;
 }
 

@@ -299,14 +299,16 @@ def config(k: int, with_density: bool = True) -> System:
     raise ValueError(f"unknown config {k}")
 
 
-def batched_cells(n_cells: int = 32, seed0: int = 300) -> List[System]:
+def batched_cells(n_cells: int = 32, seed0: int = 300, cells=None,
+                  with_density: bool = True) -> List[System]:
     """Uneven batch: cells of 1x1x1, 2x1x1, 2x2x1 and 2x2x2 diamond, each with
     a random symmetric strain (+-3 %) and +-0.05 Angstrom displacements,
     two levels with 24 and 48 points per conventional-cell repeat, ratio
-    drawn from U[5, 8]."""
+    drawn from U[5, 8].  `cells` picks a subset by index (cell c depends on
+    c alone)."""
     shapes = [(1, 1, 1), (2, 1, 1), (2, 2, 1), (2, 2, 2)]
     out = []
-    for c in range(n_cells):
+    for c in (range(n_cells) if cells is None else cells):
         reps = shapes[c % 4]
         rng = np.random.default_rng(seed0 + 2 * c)
         ratio = float(rng.uniform(5.0, 8.0))
@@ -315,6 +317,7 @@ def batched_cells(n_cells: int = 32, seed0: int = 300) -> List[System]:
             diamond_system(
                 reps, grids, ratio, 16 * reps[0] * reps[1] * reps[2], 0.05, 0.03,
                 seed0 + 2 * c, seed0 + 2 * c + 1, alpha_bound=[2.0], name=f"cfg3_{c}",
+                with_density=with_density,
             )
         )
     return out
