@@ -74,6 +74,28 @@ def set_profile(plan, mask):
     binding.load().isdf_profile(plan.handle, int(mask))
 
 
+def measured_traffic(fam):
+    """HBM bytes per launch of the family from the committed counter summary,
+    or None when there is none or the kernel source changed since."""
+    import hashlib
+
+    if FAMILIES[fam][0] != "gemm_select":
+        return None
+    path = os.path.join(ROOT, "profiles", "traffic_gemm_select_cfg2.md")
+    src = os.path.join(ROOT, "paper_2404_09373_amd", "csrc", "kernels_gemm.hip")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and line.split(":")[0] in ("traffic_bytes_per_launch", "kernel_source_sha256"):
+            k, v = line.split(":", 1)
+            vals[k] = v.strip()
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if vals.get("kernel_source_sha256") != sha or "traffic_bytes_per_launch" not in vals:
+        return None
+    return float(vals["traffic_bytes_per_launch"])
+
+
 def roofline(fam, st, mixed):
     """Roofline figure of family `fam` from its launches in the timed steps."""
     name, bound, kname = FAMILIES[fam]
@@ -96,7 +118,7 @@ def roofline(fam, st, mixed):
         "peak": peak,
         "unit": unit,
         "frac": round(achieved / peak, 4),
-        "traffic": None,
+        "traffic": measured_traffic(fam),
         "avg_launch_us": round(avg_s * 1e6, 3),
         "launches": st["launches"],
         "alg_bytes_per_launch": st["bytes"] / n,
@@ -246,7 +268,19 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--exchanges", type=int, default=7)
     ap.add_argument("--paths", choices=["both", "reference", "optimized"], default="both")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy 2 GiB three times (reference for the HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+
+        a = torch.zeros(2 << 30, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": a.numel(), "copies": 3}))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
