@@ -104,8 +104,9 @@ struct GemmProblem {
 // that shape.
 struct GemmShape {
   int bm, bn, wm, wn;
+  int mf4;  // 1: v_mfma_f64_4x4x4 (4 blocks), 0: v_mfma_f64_16x16x4
 };
-constexpr int GEMM_NSHAPE = 5;
+constexpr int GEMM_NSHAPE = 8;
 extern const GemmShape kShapes[GEMM_NSHAPE];
 isdf_status gemm_f64(hipStream_t s, int epi, const GemmProblem& p, int tag = 0, int shape = -1);
 isdf_status gemm_f64_grouped(hipStream_t s, int epi, const GemmProblem* d_probs, int nprob,
