@@ -3,7 +3,8 @@
 // potentials needed on the function's own and on every coarser grid).
 //
 // Transform: three passes of 1D transforms (x, y, z), each line held in LDS
-// and transformed by a Stockham autosort sequence of radix-4/2/3/5 stages.
+// and transformed by a Stockham autosort sequence of radix-4/2/3/5 stages
+// (compiled per line length for the grids in use, generic otherwise).
 // Lines of one workgroup are neighbours along x, so every global access is a
 // run of consecutive complex values.  Two real fitting functions travel in
 // one complex array (re, im): the Coulomb kernel is real and even in m, so
@@ -57,7 +58,7 @@ __device__ inline void butterfly(const double2* src, double2* dst, int n, int j,
   const int step = n / (Ns * R);
 #pragma unroll
   for (int r = 1; r < R; ++r) {
-    double2 w = tw[(r * k * step) % n];
+    double2 w = tw[r * k * step];  // r k step < R Ns n / (Ns R) = n
     if (sign > 0.0) w.y = -w.y;  // the table holds e^{-2 pi i t/n}
     v[r] = cmul(v[r], w);
   }
@@ -178,6 +179,131 @@ fft_pass_kernel(double2* __restrict__ z, int batch, int n1, int n2, int n3, int 
   }
 }
 
+// ------------------------------------------------ compile-time line sizes
+// The same Stockham sequence with the line length, the radices, the stage
+// strides and the lines per workgroup known at compile time: every index
+// division becomes a shift or a multiply, which the generic kernel pays for
+// at every butterfly.
+constexpr int fft_radix(int n, int s) {
+  int i = 0;
+  while (n % 4 == 0) { if (i == s) return 4; n /= 4; ++i; }
+  while (n % 2 == 0) { if (i == s) return 2; n /= 2; ++i; }
+  while (n % 3 == 0) { if (i == s) return 3; n /= 3; ++i; }
+  while (n % 5 == 0) { if (i == s) return 5; n /= 5; ++i; }
+  return 0;
+}
+constexpr int fft_nstages(int n) {
+  int c = 0;
+  while (fft_radix(n, c) != 0) ++c;
+  return c;
+}
+constexpr int fft_span(int n, int s) {  // product of the first s radices
+  int p = 1;
+  for (int i = 0; i < s; ++i) p *= fft_radix(n, i);
+  return p;
+}
+
+template <int N, int S>
+__device__ inline void fft_stages(double2* src, double2* dst, int nl, const double2* tw, double sign) {
+  if constexpr (S < fft_nstages(N)) {
+    constexpr int R = fft_radix(N, S), NS = fft_span(N, S), NB = N / R;
+    for (int u = threadIdx.x; u < nl * NB; u += 256) {
+      const int line = u / NB, j = u % NB;
+      butterfly<R>(src + line * N, dst + line * N, N, j, NS, tw, sign);
+    }
+    __syncthreads();
+    fft_stages<N, S + 1>(dst, src, nl, tw, sign);
+  }
+}
+
+template <int N, int LPW>
+__global__ void __launch_bounds__(256)
+fft_pass_fixed_kernel(double2* __restrict__ z, int batch, int n1, int n2, int n3, int axis,
+                      double sign, const double2* __restrict__ tw) {
+  extern __shared__ double2 lds[];
+  double2* bufA = lds;
+  double2* bufB = lds + LPW * N;
+  const int64_t ng = (int64_t)n1 * n2 * n3;
+  const int tid = threadIdx.x;
+  const int g = blockIdx.x;
+  int64_t base, estride, lstride;
+  int nl = LPW;
+  if (axis == 0) {
+    const int64_t nlines = (int64_t)n2 * n3 * batch;
+    const int64_t L0 = (int64_t)g * LPW;
+    if (L0 + LPW > nlines) nl = (int)(nlines - L0);
+    base = L0 * N;
+    estride = 1;
+    lstride = N;
+  } else {
+    const int groups_x = n1 / LPW;
+    const int i10 = (g % groups_x) * LPW;
+    const int rest = g / groups_x;
+    if (axis == 1) {
+      const int i3 = rest % n3, b = rest / n3;
+      base = (int64_t)b * ng + i10 + (int64_t)n1 * n2 * i3;
+      estride = n1;
+    } else {
+      const int i2 = rest % n2, b = rest / n2;
+      base = (int64_t)b * ng + i10 + (int64_t)n1 * i2;
+      estride = (int64_t)n1 * n2;
+    }
+    lstride = 1;
+  }
+  const int tot = nl * N;
+  if (axis == 0) {
+    for (int e = tid; e < tot; e += 256) bufA[e] = z[base + e];
+  } else {
+    for (int e = tid; e < tot; e += 256) {
+      const int j = e % LPW, i = e / LPW;
+      bufA[j * N + i] = z[base + j * lstride + i * estride];
+    }
+  }
+  __syncthreads();
+  fft_stages<N, 0>(bufA, bufB, nl, tw, sign);
+  const double2* res = (fft_nstages(N) & 1) ? bufB : bufA;
+  if (axis == 0) {
+    for (int e = tid; e < tot; e += 256) z[base + e] = res[e];
+  } else {
+    for (int e = tid; e < tot; e += 256) {
+      const int j = e % LPW, i = e / LPW;
+      z[base + j * lstride + i * estride] = res[j * N + i];
+    }
+  }
+}
+
+template <int N>
+bool launch_fixed_n(hipStream_t s, double2* z, int batch, int n1, int n2, int n3, int axis,
+                    double sign, const double2* tw, int lpw, int64_t groups) {
+  const size_t shmem = sizeof(double2) * 2 * (size_t)lpw * N;
+  if (lpw == 16)
+    hipLaunchKernelGGL((fft_pass_fixed_kernel<N, 16>), dim3((unsigned)groups), dim3(256), shmem, s,
+                       z, batch, n1, n2, n3, axis, sign, tw);
+  else if (lpw == 8)
+    hipLaunchKernelGGL((fft_pass_fixed_kernel<N, 8>), dim3((unsigned)groups), dim3(256), shmem, s,
+                       z, batch, n1, n2, n3, axis, sign, tw);
+  else
+    return false;
+  return true;
+}
+
+// Line lengths with a compiled kernel (the grids of the workloads).
+bool launch_fixed(hipStream_t s, double2* z, int batch, int n1, int n2, int n3, int axis,
+                  double sign, const double2* tw, int n, int lpw, int64_t groups) {
+  switch (n) {
+    case 24: return launch_fixed_n<24>(s, z, batch, n1, n2, n3, axis, sign, tw, lpw, groups);
+    case 32: return launch_fixed_n<32>(s, z, batch, n1, n2, n3, axis, sign, tw, lpw, groups);
+    case 40: return launch_fixed_n<40>(s, z, batch, n1, n2, n3, axis, sign, tw, lpw, groups);
+    case 48: return launch_fixed_n<48>(s, z, batch, n1, n2, n3, axis, sign, tw, lpw, groups);
+    case 64: return launch_fixed_n<64>(s, z, batch, n1, n2, n3, axis, sign, tw, lpw, groups);
+    case 80: return launch_fixed_n<80>(s, z, batch, n1, n2, n3, axis, sign, tw, lpw, groups);
+    case 96: return launch_fixed_n<96>(s, z, batch, n1, n2, n3, axis, sign, tw, lpw, groups);
+    case 128: return launch_fixed_n<128>(s, z, batch, n1, n2, n3, axis, sign, tw, lpw, groups);
+    case 160: return launch_fixed_n<160>(s, z, batch, n1, n2, n3, axis, sign, tw, lpw, groups);
+    default: return false;
+  }
+}
+
 // host twiddle tables e^{-2 pi i t / n}, cached per (device, n) for the
 // life of the process; a mutex keeps concurrent plans (isdf_fit_batch) safe
 struct TwCache {
@@ -234,17 +360,22 @@ isdf_status fft3d(hipStream_t s, double* zr, int batch, const int grid[3], int s
     FftRadices rad = make_radices(n);
     int lpw;
     int64_t groups;
+    // lines per workgroup: 16 for short lines, 8 from 48 points on (measured
+    // on 32^3, 64^3 and 128^3 batches)
     if (axis == 0) {
-      lpw = n <= 64 ? 16 : 8;
+      lpw = n <= 32 ? 16 : 8;
       const int64_t nl = (int64_t)n2 * n3 * batch;
       groups = (nl + lpw - 1) / lpw;
     } else {
-      lpw = (n1 % 8 == 0) ? 8 : (n1 % 4 == 0) ? 4 : (n1 % 2 == 0) ? 2 : 1;
+      lpw = (n <= 32 && n1 % 16 == 0) ? 16
+            : (n1 % 8 == 0) ? 8 : (n1 % 4 == 0) ? 4 : (n1 % 2 == 0) ? 2 : 1;
       groups = (int64_t)(n1 / lpw) * (axis == 1 ? n3 : n2) * batch;
     }
-    const size_t shmem = sizeof(double2) * 2 * (size_t)lpw * n;
-    hipLaunchKernelGGL(fft_pass_kernel, dim3((unsigned)groups), dim3(256), shmem, s, z, batch, n1,
-                       n2, n3, axis, (double)sign, tw, rad, lpw);
+    if (!launch_fixed(s, z, batch, n1, n2, n3, axis, (double)sign, tw, n, lpw, groups)) {
+      const size_t shmem = sizeof(double2) * 2 * (size_t)lpw * n;
+      hipLaunchKernelGGL(fft_pass_kernel, dim3((unsigned)groups), dim3(256), shmem, s, z, batch, n1,
+                         n2, n3, axis, (double)sign, tw, rad, lpw);
+    }
     ISDF_HIP_TRY(hipGetLastError());
   }
   return ISDF_OK;
