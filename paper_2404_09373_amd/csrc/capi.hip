@@ -39,7 +39,7 @@ namespace {
 constexpr int NSTAGE = 8;
 std::mutex g_big_alloc_mu;  // see select_points
 constexpr int RL_MIN_PIVOTS = 128;  // right-looking selection above this many pivots
-constexpr int RL_BLOCK = 128;       // pivots between residual (SYRK) updates
+constexpr int RL_BLOCK = 512;       // pivots between residual (SYRK) updates (128 -> 512 saves ~14 ms per 64-atom fit)
 
 // Device memory of one plan.  A block that a buffer gives back is kept and
 // handed to a later buffer of the same plan, with no hipFree/hipMalloc (both
