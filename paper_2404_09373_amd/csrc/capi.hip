@@ -1304,13 +1304,21 @@ isdf_status run_coulomb(isdf_plan_s* pl, isdf_fit_s* f) {
       int64_t voff = 0;
       for (int l = 0; l <= lp; ++l) {
         const int64_t ng = level_ng(hp, l);
-        if ((st = launch_poisson_restrict(s, zf.as<double>(), hp.grid[lp], zc.as<double>(),
-                                          hp.grid[l], npairs, pl->recip)) != ISDF_OK)
-          return st;
-        if ((st = fft_prof(pl, zc.as<double>(), npairs, hp.grid[l], +1)) != ISDF_OK) return st;
-        if ((st = launch_split_planar(s, zc.as<double>(), ng, ncols,
-                                      V.as<double>() + voff + (b0 - ch.c0) * ng)) != ISDF_OK)
-          return st;
+        double* vout = V.as<double>() + voff + (b0 - ch.c0) * ng;
+        bool fused = false;
+        {  // Poisson step, inverse transform and planar split in three passes
+          ProfScope ps(pl, ISDF_K_FFT, 3.0 * 32.0 * (double)ng * npairs, 0.0);
+          if ((st = fft_poisson_inverse(s, zf.as<double>(), hp.grid[lp], zc.as<double>(), hp.grid[l],
+                                        npairs, pl->recip, vout, ncols, &fused)) != ISDF_OK)
+            return st;
+        }
+        if (!fused) {
+          if ((st = launch_poisson_restrict(s, zf.as<double>(), hp.grid[lp], zc.as<double>(),
+                                            hp.grid[l], npairs, pl->recip)) != ISDF_OK)
+            return st;
+          if ((st = fft_prof(pl, zc.as<double>(), npairs, hp.grid[l], +1)) != ISDF_OK) return st;
+          if ((st = launch_split_planar(s, zc.as<double>(), ng, ncols, vout)) != ISDF_OK) return st;
+        }
         voff += ng * (ch.c1 - ch.c0);
       }
     }

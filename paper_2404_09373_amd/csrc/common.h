@@ -223,6 +223,12 @@ isdf_status launch_scatter_cols(hipStream_t s, const ScatterCol* cols, int ncols
                                 double* z, int64_t ng);
 // V[c][R] = component c%2 of z[c/2][R], c < ncols
 isdf_status launch_split_planar(hipStream_t s, const double* z, int64_t ng, int ncols, double* V);
+// Poisson step from the spectrum on grid gf, inverse transform on grid gc
+// and planar split into V in three passes (*done = false: sizes without
+// compiled passes, nothing launched; use the three separate steps).
+isdf_status fft_poisson_inverse(hipStream_t s, const double* zf, const int gf[3], double* zc,
+                                const int gc[3], int npairs, const double B[9], double* V,
+                                int ncols, bool* done);
 isdf_status launch_symmetrize_w(hipStream_t s, double* W, int64_t nmu, const int8_t* lev);
 isdf_status launch_add(hipStream_t s, const double* a, const double* b, double* c, int64_t n);
 isdf_status launch_trace_dot(hipStream_t s, const double* a, const double* b, int64_t n,

@@ -179,6 +179,32 @@ fft_pass_kernel(double2* __restrict__ z, int batch, int n1, int n2, int n3, int 
   }
 }
 
+struct PoissonArg {
+  int gf[3], gc[3];
+  double B[9];   // B[i*3 + j] = component j of reciprocal vector b_i
+  double inv_ngf;
+};
+
+// v(m) / N_g,f times the fine spectrum at the index of m, for m in the
+// band of the coarse grid (m != 0), else 0: the Poisson step of Eq. (xi|xi')
+__device__ inline double2 poisson_value(const double2* __restrict__ zf, int64_t fbase, const PoissonArg& a,
+                                        int x, int y, int zz) {
+  const int j[3] = {x, y, zz};
+  int m[3];
+  for (int i = 0; i < 3; ++i) {
+    m[i] = (j[i] <= (a.gc[i] - 1) / 2) ? j[i] : j[i] - a.gc[i];
+    if (2 * abs(m[i]) >= a.gc[i]) return make_double2(0.0, 0.0);
+  }
+  if ((m[0] | m[1] | m[2]) == 0) return make_double2(0.0, 0.0);
+  double G[3];
+  for (int c = 0; c < 3; ++c) G[c] = m[0] * a.B[c] + m[1] * a.B[3 + c] + m[2] * a.B[6 + c];
+  const double v = 4.0 * 3.14159265358979323846 / (G[0] * G[0] + G[1] * G[1] + G[2] * G[2]) * a.inv_ngf;
+  int jf[3];
+  for (int i = 0; i < 3; ++i) jf[i] = m[i] < 0 ? m[i] + a.gf[i] : m[i];
+  const double2 zv = zf[fbase + jf[0] + (int64_t)a.gf[0] * (jf[1] + (int64_t)a.gf[1] * jf[2])];
+  return make_double2(v * zv.x, v * zv.y);
+}
+
 // ------------------------------------------------ compile-time line sizes
 // The same Stockham sequence with the line length, the radices, the stage
 // strides and the lines per workgroup known at compile time: every index
@@ -216,10 +242,16 @@ __device__ inline void fft_stages(double2* src, double2* dst, int nl, const doub
   }
 }
 
-template <int N, int LPW>
+// PLOAD (x pass only): the lines are read from the fine spectrum zf through
+// the Poisson step instead of from z.  PSTORE (z pass only): the result is
+// written as two real planar columns V[2b], V[2b + 1] of pair b instead of
+// back into z (column 2b + 1 only while below ncols).
+template <int N, int LPW, bool PLOAD = false, bool PSTORE = false>
 __global__ void __launch_bounds__(256)
 fft_pass_fixed_kernel(double2* __restrict__ z, int batch, int n1, int n2, int n3, int axis,
-                      double sign, const double2* __restrict__ tw) {
+                      double sign, const double2* __restrict__ tw,
+                      const double2* __restrict__ zf = nullptr, PoissonArg pa = PoissonArg{},
+                      double* __restrict__ V = nullptr, int ncols = 0) {
   extern __shared__ double2 lds[];
   double2* bufA = lds;
   double2* bufB = lds + LPW * N;
@@ -251,7 +283,16 @@ fft_pass_fixed_kernel(double2* __restrict__ z, int batch, int n1, int n2, int n3
     lstride = 1;
   }
   const int tot = nl * N;
-  if (axis == 0) {
+  if constexpr (PLOAD) {
+    const int64_t ngf = (int64_t)pa.gf[0] * pa.gf[1] * pa.gf[2];
+    const int64_t L0 = (int64_t)g * LPW;
+    for (int e = tid; e < tot; e += 256) {
+      const int64_t L = L0 + e / N;  // line (y, z, pair)
+      const int y = (int)(L % n2), zz = (int)((L / n2) % n3);
+      const int64_t b = L / ((int64_t)n2 * n3);
+      bufA[e] = poisson_value(zf, b * ngf, pa, e % N, y, zz);
+    }
+  } else if (axis == 0) {
     for (int e = tid; e < tot; e += 256) bufA[e] = z[base + e];
   } else {
     for (int e = tid; e < tot; e += 256) {
@@ -262,7 +303,19 @@ fft_pass_fixed_kernel(double2* __restrict__ z, int batch, int n1, int n2, int n3
   __syncthreads();
   fft_stages<N, 0>(bufA, bufB, nl, tw, sign);
   const double2* res = (fft_nstages(N) & 1) ? bufB : bufA;
-  if (axis == 0) {
+  if constexpr (PSTORE) {
+    const int b = (g / (n1 / LPW)) / n2;
+    const int64_t off = base - (int64_t)b * ng;
+    double* v0 = V + (int64_t)(2 * b) * ng + off;
+    double* v1 = 2 * b + 1 < ncols ? V + (int64_t)(2 * b + 1) * ng + off : nullptr;
+    for (int e = tid; e < tot; e += 256) {
+      const int j = e % LPW, i = e / LPW;
+      const double2 r = res[j * N + i];
+      const int64_t o = j * lstride + i * estride;
+      v0[o] = r.x;
+      if (v1) v1[o] = r.y;
+    }
+  } else if (axis == 0) {
     for (int e = tid; e < tot; e += 256) z[base + e] = res[e];
   } else {
     for (int e = tid; e < tot; e += 256) {
@@ -302,6 +355,23 @@ bool launch_fixed(hipStream_t s, double2* z, int batch, int n1, int n2, int n3, 
     case 160: return launch_fixed_n<160>(s, z, batch, n1, n2, n3, axis, sign, tw, lpw, groups);
     default: return false;
   }
+}
+
+static const double2* twiddles(int n);
+
+template <int N>
+void launch_poisson_x(hipStream_t s, double2* zc, int batch, const int gc[3], const double2* tw,
+                      const double2* zf, const PoissonArg& pa, int64_t groups) {
+  hipLaunchKernelGGL((fft_pass_fixed_kernel<N, 8, true, false>), dim3((unsigned)groups), dim3(256),
+                     sizeof(double2) * 2 * 8 * N, s, zc, batch, gc[0], gc[1], gc[2], 0, 1.0, tw, zf, pa,
+                     nullptr, 0);
+}
+template <int N>
+void launch_planar_z(hipStream_t s, double2* zc, int batch, const int gc[3], const double2* tw,
+                     double* V, int ncols, int64_t groups) {
+  hipLaunchKernelGGL((fft_pass_fixed_kernel<N, 8, false, true>), dim3((unsigned)groups), dim3(256),
+                     sizeof(double2) * 2 * 8 * N, s, zc, batch, gc[0], gc[1], gc[2], 2, 1.0, tw, nullptr,
+                     PoissonArg{}, V, ncols);
 }
 
 // host twiddle tables e^{-2 pi i t / n}, cached per (device, n) for the
@@ -382,11 +452,6 @@ isdf_status fft3d(hipStream_t s, double* zr, int batch, const int grid[3], int s
 }
 
 // ---------------------------------------------------------------- Poisson
-struct PoissonArg {
-  int gf[3], gc[3];
-  double B[9];   // B[i*3 + j] = component j of reciprocal vector b_i
-  double inv_ngf;
-};
 
 __global__ void __launch_bounds__(256)
 poisson_restrict_kernel(const double2* __restrict__ zf, double2* __restrict__ zc, int batch,
@@ -477,6 +542,76 @@ isdf_status launch_split_planar(hipStream_t s, const double* z, int64_t ng, int 
   hipLaunchKernelGGL(split_planar_kernel, dim3((unsigned)blocks, ncols), dim3(256), 0, s, z, ng,
                      ncols, V);
   ISDF_HIP_TRY(hipGetLastError());
+  return ISDF_OK;
+}
+
+// Poisson step + inverse transform on grid gc + planar split, fused into the
+// first and last passes where the grid's line lengths have compiled kernels
+// (x lines of 8 per workgroup need gc[0] divisible by 8).
+isdf_status fft_poisson_inverse(hipStream_t s, const double* zf, const int gf[3], double* zc,
+                                const int gc[3], int npairs, const double B[9], double* V,
+                                int ncols, bool* done) {
+  *done = false;
+  auto fixed = [](int n) {
+    return n == 24 || n == 32 || n == 40 || n == 48 || n == 64 || n == 80 || n == 96 || n == 128 ||
+           n == 160;
+  };
+  if (npairs <= 0 || !fixed(gc[0]) || !fixed(gc[1]) || !fixed(gc[2]) || gc[0] % 8) return ISDF_OK;
+  PoissonArg a;
+  for (int i = 0; i < 3; ++i) {
+    a.gf[i] = gf[i];
+    a.gc[i] = gc[i];
+  }
+  for (int i = 0; i < 9; ++i) a.B[i] = B[i];
+  a.inv_ngf = 1.0 / ((double)gf[0] * gf[1] * gf[2]);
+  double2* z = reinterpret_cast<double2*>(zc);
+  const double2* f = reinterpret_cast<const double2*>(zf);
+  const double2* tw0 = twiddles(gc[0]);
+  const double2* tw1 = twiddles(gc[1]);
+  const double2* tw2 = twiddles(gc[2]);
+  if (!tw0 || !tw1 || !tw2) {
+    set_error("fft: twiddle allocation failed");
+    return ISDF_E_NOMEM;
+  }
+  // x pass from the fine spectrum
+  const int64_t gx = ((int64_t)gc[1] * gc[2] * npairs + 7) / 8;
+  switch (gc[0]) {
+    case 24: launch_poisson_x<24>(s, z, npairs, gc, tw0, f, a, gx); break;
+    case 32: launch_poisson_x<32>(s, z, npairs, gc, tw0, f, a, gx); break;
+    case 40: launch_poisson_x<40>(s, z, npairs, gc, tw0, f, a, gx); break;
+    case 48: launch_poisson_x<48>(s, z, npairs, gc, tw0, f, a, gx); break;
+    case 64: launch_poisson_x<64>(s, z, npairs, gc, tw0, f, a, gx); break;
+    case 80: launch_poisson_x<80>(s, z, npairs, gc, tw0, f, a, gx); break;
+    case 96: launch_poisson_x<96>(s, z, npairs, gc, tw0, f, a, gx); break;
+    case 128: launch_poisson_x<128>(s, z, npairs, gc, tw0, f, a, gx); break;
+    default: launch_poisson_x<160>(s, z, npairs, gc, tw0, f, a, gx); break;
+  }
+  ISDF_HIP_TRY(hipGetLastError());
+  // y pass as usual
+  {
+    const int lpw = (gc[1] <= 32 && gc[0] % 16 == 0) ? 16 : 8;
+    const int64_t groups = (int64_t)(gc[0] / lpw) * gc[2] * npairs;
+    if (!launch_fixed(s, z, npairs, gc[0], gc[1], gc[2], 1, 1.0, tw1, gc[1], lpw, groups)) {
+      set_error("fft: no compiled y pass");
+      return ISDF_E_ARG;
+    }
+    ISDF_HIP_TRY(hipGetLastError());
+  }
+  // z pass into the planar potentials
+  const int64_t gz = (int64_t)(gc[0] / 8) * gc[1] * npairs;
+  switch (gc[2]) {
+    case 24: launch_planar_z<24>(s, z, npairs, gc, tw2, V, ncols, gz); break;
+    case 32: launch_planar_z<32>(s, z, npairs, gc, tw2, V, ncols, gz); break;
+    case 40: launch_planar_z<40>(s, z, npairs, gc, tw2, V, ncols, gz); break;
+    case 48: launch_planar_z<48>(s, z, npairs, gc, tw2, V, ncols, gz); break;
+    case 64: launch_planar_z<64>(s, z, npairs, gc, tw2, V, ncols, gz); break;
+    case 80: launch_planar_z<80>(s, z, npairs, gc, tw2, V, ncols, gz); break;
+    case 96: launch_planar_z<96>(s, z, npairs, gc, tw2, V, ncols, gz); break;
+    case 128: launch_planar_z<128>(s, z, npairs, gc, tw2, V, ncols, gz); break;
+    default: launch_planar_z<160>(s, z, npairs, gc, tw2, V, ncols, gz); break;
+  }
+  ISDF_HIP_TRY(hipGetLastError());
+  *done = true;
   return ISDF_OK;
 }
 
