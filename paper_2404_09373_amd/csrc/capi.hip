@@ -13,6 +13,7 @@
 // isdf_exchange runs the four-term K of Eq. ints as MFMA GEMMs with the
 // Hadamard product against W fused into their epilogue, and E_x = tr(D K).
 #include <algorithm>
+#include <array>
 #include <atomic>
 #include <cmath>
 #include <cstdio>
@@ -266,6 +267,10 @@ struct isdf_plan_s {
   int ntiles_basis = 0;
   std::vector<int64_t> pts_off, phi_off, func_off;
   int64_t phi_total = 0, pts_total = 0;
+  // per domain: cyclic box of its points on its grid (x0, y0, z0, ex, ey,
+  // ez) and the offset of its box -> point map in d_boxmap (-1: all points)
+  std::vector<std::array<int32_t, 7>> box;
+  DevBuf d_boxmap;
   LatticeArg lat{};
   double recip[9];
   hipEvent_t ev[NSTAGE + 1] = {};
@@ -573,6 +578,48 @@ isdf_status upload_plan(isdf_plan_s* pl) {
   if (!pl->mlp_w.empty())
     if ((st = upload(pl->d_mlp_w, pl->mlp_w)) != ISDF_OK) return st;
   for (int i = 0; i <= NSTAGE; ++i) ISDF_HIP_TRY(hipEventCreate(&pl->ev[i]));
+  // cyclic boxes and point maps (pruned forward transforms)
+  {
+    std::vector<int32_t> maps;
+    pl->box.assign(hp.domains.size(), {0, 0, 0, 0, 0, 0, -1});
+    for (size_t d = 0; d < hp.domains.size(); ++d) {
+      const HostDomain& D = hp.domains[d];
+      const int* g = hp.grid[D.level];
+      std::array<int32_t, 7>& b = pl->box[d];
+      if ((int64_t)D.points.size() == (int64_t)g[0] * g[1] * g[2]) {
+        b = {0, 0, 0, g[0], g[1], g[2], -1};
+        continue;
+      }
+      for (int ax = 0; ax < 3; ++ax) {  // smallest cyclic interval holding every coordinate
+        std::vector<char> occ(g[ax], 0);
+        for (int32_t f : D.points) {
+          const int c = ax == 0 ? f % g[0] : ax == 1 ? (f / g[0]) % g[1] : f / (g[0] * g[1]);
+          occ[c] = 1;
+        }
+        int best_len = 0, best_end = 0;
+        for (int st0 = 0; st0 < g[ax]; ++st0) {  // longest cyclic run of empty coordinates
+          if (occ[st0] || occ[(st0 + g[ax] - 1) % g[ax]] == 0) continue;
+          int len = 0;
+          while (len < g[ax] && !occ[(st0 + len) % g[ax]]) ++len;
+          if (len > best_len) {
+            best_len = len;
+            best_end = (st0 + len) % g[ax];
+          }
+        }
+        b[ax] = best_len ? best_end : 0;
+        b[3 + ax] = g[ax] - best_len;
+      }
+      b[6] = (int32_t)maps.size();
+      maps.resize(maps.size() + (size_t)b[3] * b[4] * b[5], -1);
+      for (size_t i = 0; i < D.points.size(); ++i) {
+        const int32_t f = D.points[i];
+        int c[3] = {f % g[0], (f / g[0]) % g[1], f / (g[0] * g[1])};
+        for (int ax = 0; ax < 3; ++ax) c[ax] = (c[ax] - b[ax] + g[ax]) % g[ax];
+        maps[b[6] + c[0] + (size_t)b[3] * (c[1] + (size_t)b[4] * c[2])] = (int32_t)i;
+      }
+    }
+    if ((st = upload(pl->d_boxmap, maps)) != ISDF_OK) return st;
+  }
   pl->uploaded = true;
   return ISDF_OK;
 }
@@ -1285,6 +1332,56 @@ isdf_status run_coulomb(isdf_plan_s* pl, isdf_fit_s* f) {
       for (int64_t c = b0; c < std::min(b0 + bw, ch.c1); ++c) scat[c].slot = (int)(c - b0);
   }
   if ((st = upload(d_scat, scat)) != ISDF_OK) return st;
+  // pruned forward transforms: one descriptor per column, pairs per batch
+  std::vector<FwdCol> fcols(nmu);
+  for (int64_t c = 0; c < nmu; ++c) {
+    const int d = col_dom[c];
+    const std::array<int32_t, 7>& b = pl->box[d];
+    fcols[c].src = scat[c].src;
+    fcols[c].map = b[6] < 0 ? nullptr : pl->d_boxmap.as<int32_t>() + b[6];
+    for (int i = 0; i < 6; ++i) fcols[c].box[i] = b[i];
+  }
+  auto union_box = [&](const int32_t* a, const int32_t* b, const int* g, int32_t* out) {
+    for (int ax = 0; ax < 3; ++ax) {  // cyclic interval holding both (whole axis if unclear)
+      const int n = g[ax];
+      const int a0 = a[ax], ae = a[3 + ax], b0 = b[ax], be = b[3 + ax];
+      int best0 = 0, bestE = n;
+      for (int cand : {a0, b0}) {
+        const int ea = (a0 - cand + n) % n + ae, eb = (b0 - cand + n) % n + be;
+        const int e = std::max(ea, eb);
+        if (e < bestE) {
+          best0 = cand;
+          bestE = e;
+        }
+      }
+      out[ax] = best0;
+      out[3 + ax] = std::min(bestE, n);
+    }
+  };
+  std::vector<FwdPair> fpairs;
+  std::vector<int64_t> fpair_off;  // per (chunk, batch) in loop order
+  for (auto& ch : chunks) {
+    const int64_t pairs_max = std::max<int64_t>(1, (ngz_max * fft_pairs) / level_ng(hp, ch.lp));
+    const int64_t bw = std::max<int64_t>(2, 2 * pairs_max);
+    for (int64_t b0 = ch.c0; b0 < ch.c1; b0 += bw) {
+      fpair_off.push_back((int64_t)fpairs.size());
+      const int64_t ce = std::min(b0 + bw, ch.c1);
+      for (int64_t c = b0; c < ce; c += 2) {
+        FwdPair P{};
+        P.c0 = (int32_t)c;
+        P.c1 = c + 1 < ce ? (int32_t)(c + 1) : -1;
+        if (P.c1 < 0 || col_dom[c] == col_dom[c + 1])
+          std::copy(fcols[c].box, fcols[c].box + 6, P.box);
+        else
+          union_box(fcols[c].box, fcols[c + 1].box, hp.grid[ch.lp], P.box);
+        fpairs.push_back(P);
+      }
+    }
+  }
+  DevBuf d_fcols, d_fpairs;
+  if ((st = upload(d_fcols, fcols)) != ISDF_OK) return st;
+  if ((st = upload(d_fpairs, fpairs)) != ISDF_OK) return st;
+  size_t batch_no = 0;
   for (size_t ci = 0; ci < chunks.size(); ++ci) {
     const Chunk& ch = chunks[ci];
     const int lp = ch.lp;
@@ -1294,13 +1391,30 @@ isdf_status run_coulomb(isdf_plan_s* pl, isdf_fit_s* f) {
     for (int64_t b0 = ch.c0; b0 < ch.c1; b0 += bw) {
       const int ncols = (int)std::min<int64_t>(bw, ch.c1 - b0);
       const int npairs = (ncols + 1) / 2;
-      int max_n = 0;
-      for (int64_t c = b0; c < b0 + ncols; ++c) max_n = std::max(max_n, scat[c].n);
-      if ((st = launch_fill(s, zf.as<double>(), 2 * ngp * npairs, 0.0)) != ISDF_OK) return st;
-      if ((st = launch_scatter_cols(s, d_scat.as<ScatterCol>() + b0, ncols, max_n, zf.as<double>(),
-                                    ngp)) != ISDF_OK)
-        return st;
-      if ((st = fft_prof(pl, zf.as<double>(), npairs, hp.grid[lp], -1)) != ISDF_OK) return st;
+      const int64_t poff = fpair_off[batch_no++];
+      if (fft_forward_pruned_supported(hp.grid[lp])) {
+        int max_yz = 0, max_z = 0;
+        double touched = 0.0;
+        for (int b = 0; b < npairs; ++b) {
+          const FwdPair& P = fpairs[poff + b];
+          max_yz = std::max(max_yz, P.box[4] * P.box[5]);
+          max_z = std::max(max_z, P.box[5]);
+          touched += (double)hp.grid[lp][0] * (2.0 * P.box[4] * P.box[5] + 2.0 * hp.grid[lp][1] * P.box[5]) +
+                     (double)hp.grid[lp][0] * hp.grid[lp][1] * (P.box[5] + hp.grid[lp][2]);
+        }
+        ProfScope ps(pl, ISDF_K_FFT, 16.0 * touched, 0.0);
+        if ((st = fft_forward_pruned(s, zf.as<double>(), d_fpairs.as<FwdPair>() + poff,
+                                     d_fcols.as<FwdCol>(), npairs, hp.grid[lp], max_yz, max_z)) != ISDF_OK)
+          return st;
+      } else {
+        int max_n = 0;
+        for (int64_t c = b0; c < b0 + ncols; ++c) max_n = std::max(max_n, scat[c].n);
+        if ((st = launch_fill(s, zf.as<double>(), 2 * ngp * npairs, 0.0)) != ISDF_OK) return st;
+        if ((st = launch_scatter_cols(s, d_scat.as<ScatterCol>() + b0, ncols, max_n, zf.as<double>(),
+                                      ngp)) != ISDF_OK)
+          return st;
+        if ((st = fft_prof(pl, zf.as<double>(), npairs, hp.grid[lp], -1)) != ISDF_OK) return st;
+      }
       int64_t voff = 0;
       for (int l = 0; l <= lp; ++l) {
         const int64_t ng = level_ng(hp, l);

@@ -213,6 +213,23 @@ isdf_status fft_prepare(int n);
 isdf_status launch_poisson_restrict(hipStream_t s, const double* zf, const int gf[3], double* zc,
                                     const int gc[3], int batch, const double B[9]);
 // scatter domain columns into complex pair arrays: z[slot/2][2 pts[i] + slot%2] = src[i]
+// Pruned forward transform: one fitting-function column (compact values of
+// its domain) and one pair of columns with the cyclic box that holds them.
+struct FwdCol {
+  const double* src;             // values at the domain's points (nullptr: zero column)
+  const int32_t* map;            // box -> local point index (-1 outside); nullptr: src is the whole grid
+  int32_t box[6];                // x0, y0, z0, ex, ey, ez (cyclic start and extent per axis)
+};
+struct FwdPair {
+  int32_t c0, c1;                // columns (c1 = -1: none)
+  int32_t box[6];                // box holding both columns
+};
+bool fft_forward_pruned_supported(const int g[3]);
+// Forward transforms of npairs column pairs on grid g into z (pair b at
+// b * N_g); max_yz / max_z bound the pairs' box lines and planes.
+isdf_status fft_forward_pruned(hipStream_t s, double* z, const FwdPair* pairs, const FwdCol* cols,
+                               int npairs, const int g[3], int max_yz, int max_z);
+
 struct ScatterCol {
   const double* src;
   const int32_t* pts;

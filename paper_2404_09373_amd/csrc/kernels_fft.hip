@@ -615,4 +615,162 @@ isdf_status fft_poisson_inverse(hipStream_t s, const double* zf, const int gf[3]
   return ISDF_OK;
 }
 
+// ------------------------------------------------ pruned forward transform
+// A window's fitting function is zero outside the (cyclic) box around its
+// points.  Pass x gathers only the lines (y, z) of a pair's box straight
+// from the compact column values (no zero fill, no scatter); pass y
+// transforms only the box's z planes and reads only its y range (zeros
+// elsewhere); pass z reads only the box's z range.  Every value written is
+// the exact transform of the zero-padded columns.
+__device__ inline bool in_range(int i, int lo, int ext, int n, int* d) {
+  int t = i - lo;
+  if (t < 0) t += n;
+  *d = t;
+  return t < ext;
+}
+
+__device__ inline double gather_value(const FwdCol& c, int x, int y, int zz, int n1, int n2, int n3) {
+  if (!c.src) return 0.0;
+  if (!c.map) return c.src[x + (int64_t)n1 * (y + (int64_t)n2 * zz)];
+  int dx, dy, dz;
+  if (!in_range(x, c.box[0], c.box[3], n1, &dx) || !in_range(y, c.box[1], c.box[4], n2, &dy) ||
+      !in_range(zz, c.box[2], c.box[5], n3, &dz))
+    return 0.0;
+  const int idx = c.map[dx + c.box[3] * (dy + c.box[4] * dz)];
+  return idx >= 0 ? c.src[idx] : 0.0;
+}
+
+template <int N, int LPW, int AXIS>
+__global__ void __launch_bounds__(256)
+fft_fwd_pruned_kernel(double2* __restrict__ z, const FwdPair* __restrict__ pairs,
+                      const FwdCol* __restrict__ cols, int n1, int n2, int n3,
+                      const double2* __restrict__ tw) {
+  extern __shared__ double2 lds[];
+  double2* bufA = lds;
+  double2* bufB = lds + LPW * N;
+  const FwdPair P = pairs[blockIdx.y];
+  const int64_t ng = (int64_t)n1 * n2 * n3;
+  double2* zb = z + (int64_t)blockIdx.y * ng;
+  const int tid = threadIdx.x;
+  const int g = blockIdx.x;
+  int nl = LPW;
+  int64_t base = 0, estride = 1, lstride = 1;
+  if (AXIS == 0) {  // lines (y, z) of the pair's box, LPW per workgroup
+    const int nlines = P.box[4] * P.box[5];
+    const int t0 = g * LPW;
+    if (t0 >= nlines) return;
+    nl = min(LPW, nlines - t0);
+    const FwdCol c0 = cols[P.c0];
+    const FwdCol c1 = P.c1 >= 0 ? cols[P.c1] : FwdCol{};
+    for (int e = tid; e < nl * N; e += 256) {
+      const int t = t0 + e / N, x = e % N;
+      int y = P.box[1] + t % P.box[4], zz = P.box[2] + t / P.box[4];
+      if (y >= n2) y -= n2;
+      if (zz >= n3) zz -= n3;
+      bufA[e] = make_double2(gather_value(c0, x, y, zz, n1, n2, n3), gather_value(c1, x, y, zz, n1, n2, n3));
+    }
+  } else {
+    const int groups_x = n1 / LPW;
+    const int i10 = (g % groups_x) * LPW;
+    const int q = g / groups_x;
+    if (AXIS == 1) {  // lines (x, z) for z in the box
+      if (q >= P.box[5]) return;
+      int zz = P.box[2] + q;
+      if (zz >= n3) zz -= n3;
+      base = i10 + (int64_t)n1 * n2 * zz;
+      estride = n1;
+      for (int e = tid; e < LPW * N; e += 256) {
+        const int j = e % LPW, i = e / LPW;
+        int d;
+        bufA[j * N + i] = in_range(i, P.box[1], P.box[4], n2, &d) ? zb[base + j + i * estride]
+                                                                   : make_double2(0.0, 0.0);
+      }
+    } else {  // lines (x, y), all of them; z outside the box reads as zero
+      base = i10 + (int64_t)n1 * q;
+      estride = (int64_t)n1 * n2;
+      for (int e = tid; e < LPW * N; e += 256) {
+        const int j = e % LPW, i = e / LPW;
+        int d;
+        bufA[j * N + i] = in_range(i, P.box[2], P.box[5], n3, &d) ? zb[base + j + i * estride]
+                                                                   : make_double2(0.0, 0.0);
+      }
+    }
+  }
+  __syncthreads();
+  fft_stages<N, 0>(bufA, bufB, nl, tw, -1.0);
+  const double2* res = (fft_nstages(N) & 1) ? bufB : bufA;
+  if (AXIS == 0) {
+    const int t0 = g * LPW;
+    for (int e = tid; e < nl * N; e += 256) {
+      const int t = t0 + e / N, x = e % N;
+      int y = P.box[1] + t % P.box[4], zz = P.box[2] + t / P.box[4];
+      if (y >= n2) y -= n2;
+      if (zz >= n3) zz -= n3;
+      zb[x + (int64_t)n1 * (y + (int64_t)n2 * zz)] = res[e];
+    }
+  } else {
+    for (int e = tid; e < LPW * N; e += 256) {
+      const int j = e % LPW, i = e / LPW;
+      zb[base + j + i * estride] = res[j * N + i];
+    }
+  }
+}
+
+template <int N, int AXIS>
+void launch_fwd_pruned(hipStream_t s, double2* z, const FwdPair* pairs, const FwdCol* cols, int npairs,
+                       const int g[3], const double2* tw, int gx) {
+  constexpr int LPW = 8;
+  hipLaunchKernelGGL((fft_fwd_pruned_kernel<N, LPW, AXIS>), dim3((unsigned)gx, (unsigned)npairs),
+                     dim3(256), sizeof(double2) * 2 * LPW * N, s, z, pairs, cols, g[0], g[1], g[2], tw);
+}
+
+template <int AXIS>
+bool fwd_pass(hipStream_t s, double2* z, const FwdPair* pairs, const FwdCol* cols, int npairs,
+              const int g[3], const double2* tw, int n, int gx) {
+  switch (n) {
+    case 24: launch_fwd_pruned<24, AXIS>(s, z, pairs, cols, npairs, g, tw, gx); return true;
+    case 32: launch_fwd_pruned<32, AXIS>(s, z, pairs, cols, npairs, g, tw, gx); return true;
+    case 40: launch_fwd_pruned<40, AXIS>(s, z, pairs, cols, npairs, g, tw, gx); return true;
+    case 48: launch_fwd_pruned<48, AXIS>(s, z, pairs, cols, npairs, g, tw, gx); return true;
+    case 64: launch_fwd_pruned<64, AXIS>(s, z, pairs, cols, npairs, g, tw, gx); return true;
+    case 80: launch_fwd_pruned<80, AXIS>(s, z, pairs, cols, npairs, g, tw, gx); return true;
+    case 96: launch_fwd_pruned<96, AXIS>(s, z, pairs, cols, npairs, g, tw, gx); return true;
+    case 128: launch_fwd_pruned<128, AXIS>(s, z, pairs, cols, npairs, g, tw, gx); return true;
+    case 160: launch_fwd_pruned<160, AXIS>(s, z, pairs, cols, npairs, g, tw, gx); return true;
+    default: return false;
+  }
+}
+
+bool fft_forward_pruned_supported(const int g[3]) {
+  auto fixed = [](int n) {
+    return n == 24 || n == 32 || n == 40 || n == 48 || n == 64 || n == 80 || n == 96 || n == 128 ||
+           n == 160;
+  };
+  return fixed(g[0]) && fixed(g[1]) && fixed(g[2]) && g[0] % 8 == 0;
+}
+
+isdf_status fft_forward_pruned(hipStream_t s, double* zr, const FwdPair* pairs, const FwdCol* cols,
+                               int npairs, const int g[3], int max_yz, int max_z) {
+  if (npairs <= 0) return ISDF_OK;
+  if (!fft_forward_pruned_supported(g)) {
+    set_error("fft: pruned forward transform needs compiled line lengths");
+    return ISDF_E_ARG;
+  }
+  double2* z = reinterpret_cast<double2*>(zr);
+  const double2* tw0 = twiddles(g[0]);
+  const double2* tw1 = twiddles(g[1]);
+  const double2* tw2 = twiddles(g[2]);
+  if (!tw0 || !tw1 || !tw2) {
+    set_error("fft: twiddle allocation failed");
+    return ISDF_E_NOMEM;
+  }
+  fwd_pass<0>(s, z, pairs, cols, npairs, g, tw0, g[0], (max_yz + 7) / 8);
+  ISDF_HIP_TRY(hipGetLastError());
+  fwd_pass<1>(s, z, pairs, cols, npairs, g, tw1, g[1], (g[0] / 8) * max_z);
+  ISDF_HIP_TRY(hipGetLastError());
+  fwd_pass<2>(s, z, pairs, cols, npairs, g, tw2, g[2], (g[0] / 8) * g[1]);
+  ISDF_HIP_TRY(hipGetLastError());
+  return ISDF_OK;
+}
+
 }  // namespace isdf
