@@ -14,6 +14,7 @@ LIB = os.path.join(PKG, "libisdf.so")
 SOURCES = [
     "capi.hip",
     "kernels_select.hip",
+    "kernels_crb.hip",
     "kernels_gemm.hip",
     "kernels_linalg.hip",
     "kernels_fft.hip",

@@ -38,9 +38,9 @@ using namespace isdf;
 namespace {
 
 constexpr int NSTAGE = 8;
-std::mutex g_big_alloc_mu;  // see select_points
-constexpr int RL_MIN_PIVOTS = 128;  // right-looking selection above this many pivots
-constexpr int RL_BLOCK = 512;       // pivots between residual (SYRK) updates (128 -> 512 saves ~14 ms per 64-atom fit)
+constexpr int RL_MIN_PIVOTS = 128;  // blocked selection of a lone domain above this many pivots
+constexpr int CRB_BLOCK = 512;      // most pivots per block
+constexpr int CRB_CANDIDATES = 4096;  // candidates per block to start with
 
 // Device memory of one plan.  A block that a buffer gives back is kept and
 // handed to a later buffer of the same plan, with no hipFree/hipMalloc (both
@@ -640,6 +640,215 @@ struct SelSpec {
 // Greedy pivoted Cholesky of every spec domain, one batch per level.  Writes
 // pivots (local to the spec domain) to piv_out + piv_off[d], the number found
 // to counts[d] and the residual of the last pivot to dlast[d].
+// Candidate-restricted blocked selection of one domain (see kernels_crb.hip).
+// phi, diag (exact initial diagonal on entry, -1 at chosen points on exit) and
+// the factor L (pts x n_mu, all points) are the domain's own; the pivots go to
+// piv_out + X.piv_off and the final state to *st (count, last residual).
+isdf_status crb_select(isdf_plan_s* pl, const SelDomain& X, const double* phi_base, double* diag_base,
+                       double* L, int32_t* piv_out, SelState* st) {
+  const HostPlan& hp = pl->hp;
+  hipStream_t s = pl->stream;
+  const int n = X.pts, nG = X.nG, nL = X.nL, nmu = X.n_mu;
+  const double* phi = phi_base + X.phi_off;
+  double* d = diag_base + X.diag_off;
+  int32_t* piv = piv_out + X.piv_off;
+  const double tau = hp.tie_tol, eps = hp.eps_isdf;
+  isdf_status e;
+  DevBuf cidx, dC, info, phiC, LC, RCC, LCb, prowb, tmaxb, tidxb, stb, pivC, tdom, sdb, phiP, LP, Ub;
+  const int Tmax = n;
+  int T = std::min(n, CRB_CANDIDATES);
+  if ((e = cidx.alloc(sizeof(int32_t) * n)) != ISDF_OK) return e;
+  if ((e = dC.alloc(sizeof(double) * n)) != ISDF_OK) return e;
+  if ((e = info.alloc(sizeof(CrbInfo))) != ISDF_OK) return e;
+  if ((e = pivC.alloc(sizeof(int32_t) * CRB_BLOCK)) != ISDF_OK) return e;
+  if ((e = prowb.alloc(sizeof(double) * CRB_BLOCK)) != ISDF_OK) return e;
+  if ((e = stb.alloc(sizeof(SelState))) != ISDF_OK) return e;
+  if ((e = sdb.alloc(sizeof(SelDomain))) != ISDF_OK) return e;
+  int kb = 0;
+  double d0max = -1.0, dlast = 0.0;
+  while (kb < nmu) {
+    // candidates of this block and the exactness bound
+    if ((e = launch_crb_candidates(s, d, n, T, cidx.as<int32_t>(), dC.as<double>(),
+                                   info.as<CrbInfo>())) != ISDF_OK)
+      return e;
+    CrbInfo ci{};
+    ISDF_HIP_TRY(hipMemcpyAsync(&ci, info.p, sizeof(CrbInfo), hipMemcpyDeviceToHost, s));
+    ISDF_HIP_TRY(hipStreamSynchronize(s));
+    if (kb == 0) d0max = ci.dmax;
+    if (ci.nactive == 0 || !(ci.dmax > eps * d0max)) break;
+    const int nc = ci.nc;
+    const int nb = std::min(CRB_BLOCK, nmu - kb);
+    // R_CC = M(C, C) - L(C, :kb) L(C, :kb)^T (lower triangle)
+    if ((e = phiC.alloc(sizeof(double) * (size_t)nc * nG)) != ISDF_OK) return e;
+    if ((e = launch_crb_gather(s, phi, n, cidx.as<int32_t>(), nc, nG, phiC.as<double>(), nc)) != ISDF_OK)
+      return e;
+    if ((e = RCC.alloc(sizeof(double) * (size_t)nc * nc)) != ISDF_OK) return e;
+    {
+      GemmProblem g{};
+      g.A = phiC.as<double>();
+      g.lda = nc;
+      g.B = g.A;
+      g.ldb = nc;
+      g.transB = 1;
+      g.C = RCC.as<double>();
+      g.ldc = nc;
+      g.M = g.N = nc;
+      g.K = nG;
+      g.kL = nL;
+      g.lower = 1;
+      if ((e = gemm_prof(pl, ISDF_K_GEMM_SELECT, EPI_THETA, g)) != ISDF_OK) return e;
+    }
+    if (kb > 0) {
+      if ((e = LC.alloc(sizeof(double) * (size_t)nc * kb)) != ISDF_OK) return e;
+      if ((e = launch_crb_gather(s, L, n, cidx.as<int32_t>(), nc, kb, LC.as<double>(), nc)) != ISDF_OK)
+        return e;
+      GemmProblem g{};
+      g.A = LC.as<double>();
+      g.lda = nc;
+      g.B = g.A;
+      g.ldb = nc;
+      g.transB = 1;
+      g.C = RCC.as<double>();
+      g.ldc = nc;
+      g.M = g.N = nc;
+      g.K = kb;
+      g.alpha = -1.0;
+      g.beta = 1.0;
+      g.lower = 1;
+      if ((e = gemm_prof(pl, ISDF_K_GEMM_SELECT, EPI_AXPBY, g)) != ISDF_OK) return e;
+    }
+    // greedy steps on the candidates: right-looking within the block on R_CC
+    SelDomain B{};
+    B.phi_off = 0;
+    B.lfac_off = 0;
+    B.diag_off = 0;
+    B.prow_off = 0;
+    B.mres_off = 0;
+    B.pts = nc;
+    B.nG = 0;
+    B.nL = 0;
+    B.n_mu = nb;
+    B.tile_off = 0;
+    B.ntiles = (nc + SEL_TILE - 1) / SEL_TILE;
+    B.piv_off = 0;
+    B.dstop = ci.theta >= 0.0 ? ci.theta / (1.0 - tau) : 0.0;
+    B.d0fix = d0max;
+    if ((e = copy_in(sdb.p, &B, sizeof(SelDomain))) != ISDF_OK) return e;
+    std::vector<int32_t> td(B.ntiles, 0);
+    if ((e = upload(tdom, td)) != ISDF_OK) return e;
+    if ((e = LCb.alloc(sizeof(double) * (size_t)nc * nb)) != ISDF_OK) return e;
+    if ((e = tmaxb.alloc(sizeof(double) * B.ntiles)) != ISDF_OK) return e;
+    if ((e = tidxb.alloc(sizeof(int32_t) * B.ntiles)) != ISDF_OK) return e;
+    ISDF_HIP_TRY(hipMemsetAsync(stb.p, 0, sizeof(SelState), s));
+    const SelDomain* Dd = sdb.as<SelDomain>();
+    SelState* Sd = stb.as<SelState>();
+    if ((e = launch_sel_init(s, Dd, tdom.as<int32_t>(), 0, B.ntiles, dC.as<double>(), tmaxb.as<double>(),
+                             tidxb.as<int32_t>(), tau)) != ISDF_OK)
+      return e;
+    for (int k = 0; k <= nb; ++k) {
+      {
+        ProfScope ps(pl, ISDF_K_SELECT_PICK, 12.0 * B.ntiles + 16.0 * k, 0.0);
+        if ((e = launch_sel_select(s, Dd, 0, 1, k, Sd, phi, LCb.as<double>(), dC.as<double>(),
+                                   tmaxb.as<double>(), tidxb.as<int32_t>(), prowb.as<double>(),
+                                   pivC.as<int32_t>(), tau, eps)) != ISDF_OK)
+          return e;
+      }
+      if (k == nb) break;
+      ProfScope ps(pl, ISDF_K_SELECT_COLUMN, 8.0 * nc * (k + 4.0), 2.0 * nc * k);
+      if ((e = launch_sel_column(s, Dd, tdom.as<int32_t>(), 0, B.ntiles, k, 0, Sd, phi, RCC.as<double>(),
+                                 LCb.as<double>(), dC.as<double>(), prowb.as<double>(),
+                                 tmaxb.as<double>(), tidxb.as<int32_t>(), tau)) != ISDF_OK)
+        return e;
+    }
+    SelState bs{};
+    ISDF_HIP_TRY(hipMemcpyAsync(&bs, stb.p, sizeof(SelState), hipMemcpyDeviceToHost, s));
+    ISDF_HIP_TRY(hipStreamSynchronize(s));
+    const int sb = bs.count;
+    if (sb == 0) {
+      if (bs.reason == SEL_END_BLOCK && nc < ci.nactive && T < Tmax) {
+        T = std::min(Tmax, 2 * T);  // the cut fell inside a near-tie: widen the candidates
+        continue;
+      }
+      break;
+    }
+    // the block's pivots and their factor columns over every point
+    if ((e = launch_map_pivots(s, cidx.as<int32_t>(), 0, pivC.as<int32_t>(), piv + kb, sb)) != ISDF_OK)
+      return e;
+    double* Lb = L + (int64_t)kb * n;
+    if ((e = phiP.alloc(sizeof(double) * (size_t)sb * nG)) != ISDF_OK) return e;
+    if ((e = launch_crb_gather(s, phi, n, piv + kb, sb, nG, phiP.as<double>(), sb)) != ISDF_OK) return e;
+    {
+      GemmProblem g{};  // M(:, P)
+      g.A = phi;
+      g.lda = n;
+      g.B = phiP.as<double>();
+      g.ldb = sb;
+      g.transB = 1;
+      g.C = Lb;
+      g.ldc = n;
+      g.M = n;
+      g.N = sb;
+      g.K = nG;
+      g.kL = nL;
+      if ((e = gemm_prof(pl, ISDF_K_GEMM_SELECT, EPI_THETA, g)) != ISDF_OK) return e;
+    }
+    if (kb > 0) {  // - L(:, :kb) L(P, :kb)^T
+      if ((e = LP.alloc(sizeof(double) * (size_t)sb * kb)) != ISDF_OK) return e;
+      if ((e = launch_crb_gather(s, L, n, piv + kb, sb, kb, LP.as<double>(), sb)) != ISDF_OK) return e;
+      GemmProblem g{};
+      g.A = L;
+      g.lda = n;
+      g.B = LP.as<double>();
+      g.ldb = sb;
+      g.transB = 1;
+      g.C = Lb;
+      g.ldc = n;
+      g.M = n;
+      g.N = sb;
+      g.K = kb;
+      g.alpha = -1.0;
+      g.beta = 1.0;
+      if ((e = gemm_prof(pl, ISDF_K_GEMM_SELECT, EPI_AXPBY, g)) != ISDF_OK) return e;
+    }
+    // U = L(P, blk) from the block's candidate factor, then L(:, blk) U^{-T}
+    if ((e = Ub.alloc(sizeof(double) * (size_t)sb * sb)) != ISDF_OK) return e;
+    if ((e = launch_crb_gather(s, LCb.as<double>(), nc, pivC.as<int32_t>(), sb, sb, Ub.as<double>(), sb)) !=
+        ISDF_OK)
+      return e;
+    for (int jb = 0; jb < sb; jb += 64) {
+      const int w = std::min(64, sb - jb);
+      if (jb > 0) {
+        GemmProblem g{};
+        g.A = Lb;
+        g.lda = n;
+        g.B = Ub.as<double>() + jb;
+        g.ldb = sb;
+        g.transB = 1;
+        g.C = Lb + (int64_t)jb * n;
+        g.ldc = n;
+        g.M = n;
+        g.N = w;
+        g.K = jb;
+        g.alpha = -1.0;
+        g.beta = 1.0;
+        if ((e = gemm_prof(pl, ISDF_K_GEMM_SELECT, EPI_AXPBY, g)) != ISDF_OK) return e;
+      }
+      if ((e = launch_crb_trsm_block(s, Lb, n, n, Ub.as<double>(), sb, jb, w)) != ISDF_OK) return e;
+    }
+    if ((e = launch_crb_diag(s, d, n, Lb, n, sb, piv + kb)) != ISDF_OK) return e;
+    kb += sb;
+    dlast = bs.dpiv;
+    if (bs.reason == SEL_END_EPS) break;
+  }
+  SelState fin{};
+  fin.d0max = d0max;
+  fin.dpiv = dlast;
+  fin.done = 1;
+  fin.count = kb;
+  fin.reason = kb >= nmu ? SEL_END_COUNT : SEL_END_EPS;
+  return copy_in(st, &fin, sizeof(SelState));
+}
+
 isdf_status select_points(isdf_plan_s* pl, const std::vector<SelSpec>& spec,
                           const double* phi_base, double* diag_base, int32_t* piv_out,
                           const std::vector<int64_t>& piv_off, std::vector<int>& counts,
@@ -673,32 +882,16 @@ isdf_status select_points(isdf_plan_s* pl, const std::vector<SelSpec>& spec,
     pr += x.nG + x.n_mu;
   }
   isdf_status st;
-  // Large single-domain batches (the universal grid) use the right-looking
-  // form: residual Gram kept in HBM, SYRK update every RL_BLOCK pivots.
-  // The memory test and the allocation of the residual Gram are one step
-  // under a process-wide lock, so plans fitted concurrently (isdf_fit_batch)
-  // see each other's residual Grams.
-  std::vector<char> right(nd, 0);
-  int64_t mres_max = 0;
-  DevBuf mres, lfac, prow, tmax, tidx, state, d_sd, d_tile_dom;
-  {
-    std::lock_guard<std::mutex> lock(g_big_alloc_mu);
-    size_t free_b = 0, total_b = 0;
-    ISDF_HIP_TRY(hipMemGetInfo(&free_b, &total_b));
-    const double avail = (double)free_b + (double)(pl->mem ? pl->mem->cached : 0);
-    for (int d = 0; d < nd; ++d) {
-      int nlev = 0;
-      for (int e = 0; e < nd; ++e) nlev += spec[e].level == spec[d].level;
-      const double P = (double)sd[d].pts;
-      if (nlev == 1 && sd[d].n_mu > RL_MIN_PIVOTS && P * P * 8.0 <= 0.4 * avail) {
-        right[d] = 1;
-        sd[d].mres_off = 0;
-        mres_max = std::max<int64_t>(mres_max, (int64_t)sd[d].pts * sd[d].pts);
-      }
-    }
-    if (mres_max > 0)
-      if ((st = mres.alloc(sizeof(double) * mres_max)) != ISDF_OK) return st;
+  // A domain alone on its level with many pivots (the universal grid) runs
+  // the candidate-restricted blocked selection (crb_select); the others are
+  // batched per level, left-looking, one pick and one column launch a step.
+  std::vector<char> blocked(nd, 0);
+  for (int d = 0; d < nd; ++d) {
+    int nlev = 0;
+    for (int e = 0; e < nd; ++e) nlev += spec[e].level == spec[d].level;
+    blocked[d] = nlev == 1 && sd[d].n_mu > RL_MIN_PIVOTS;
   }
+  DevBuf lfac, prow, tmax, tidx, state, d_sd, d_tile_dom;
   if ((st = upload(d_sd, sd)) != ISDF_OK) return st;
   if ((st = upload(d_tile_dom, tile_dom)) != ISDF_OK) return st;
   const int ntiles = (int)tile_dom.size();
@@ -720,31 +913,18 @@ isdf_status select_points(isdf_plan_s* pl, const std::vector<SelSpec>& spec,
       kmax = std::max(kmax, spec[d1].n_mu);
       ++d1;
     }
+    if (blocked[d0]) {
+      if ((st = crb_select(pl, sd[d0], phi_base, diag_base, lfac.as<double>() + sd[d0].lfac_off,
+                           piv_out, S + d0)) != ISDF_OK)
+        return st;
+      d0 = d1;
+      continue;
+    }
     const int t0 = sd[d0].tile_off;
     const int t1 = (d1 < nd) ? sd[d1].tile_off : ntiles;
     if ((st = launch_sel_init(s, D, d_tile_dom.as<int32_t>(), t0, t1 - t0, diag_base,
                               tmax.as<double>(), tidx.as<int32_t>(), tau)) != ISDF_OK)
       return st;
-    const bool rl = right[d0] != 0;
-    const int64_t P = sd[d0].pts;
-    if (rl) {
-      // residual Gram = full pair Gram A_L o (A_L + 2 A_N), lower triangle
-      GemmProblem g{};
-      g.A = phi_base + sd[d0].phi_off;
-      g.lda = P;
-      g.B = g.A;
-      g.ldb = P;
-      g.transB = 1;
-      g.C = mres.as<double>();
-      g.ldc = P;
-      g.M = (int)P;
-      g.N = (int)P;
-      g.K = sd[d0].nG;
-      g.kL = sd[d0].nL;
-      g.lower = 1;
-      if ((st = gemm_prof(pl, ISDF_K_GEMM_SELECT, EPI_THETA, g)) != ISDF_OK) return st;
-    }
-    int kb = 0;
     for (int k = 0; k <= kmax; ++k) {
       double col_bytes = 0.0, col_flops = 0.0, pick_bytes = 0.0;
       for (int d = d0; d < d1; ++d) {
@@ -760,36 +940,13 @@ isdf_status select_points(isdf_plan_s* pl, const std::vector<SelSpec>& spec,
         return st;
       ps_pick.finish();
       if (k == kmax) break;
-      if (rl) {  // residual column + block columns instead of basis + all columns
-        col_bytes = 8.0 * P * ((double)(k - kb) + 4.0);
-        col_flops = 2.0 * P * (double)(k - kb);
-      }
       {
         ProfScope ps_col(pl, ISDF_K_SELECT_COLUMN, col_bytes, col_flops);
-        if ((st = launch_sel_column(s, D, d_tile_dom.as<int32_t>(), t0, t1 - t0, k, rl ? kb : 0, S,
-                                    phi_base, mres.as<double>(), lfac.as<double>(), diag_base,
+        if ((st = launch_sel_column(s, D, d_tile_dom.as<int32_t>(), t0, t1 - t0, k, 0, S,
+                                    phi_base, nullptr, lfac.as<double>(), diag_base,
                                     prow.as<double>(), tmax.as<double>(), tidx.as<int32_t>(),
                                     tau)) != ISDF_OK)
           return st;
-      }
-      if (rl && (k + 1 - kb == RL_BLOCK) && k + 1 < kmax) {
-        // Mres -= L[:, kb..k] L[:, kb..k]^T on the lower triangle
-        GemmProblem g{};
-        g.A = lfac.as<double>() + sd[d0].lfac_off + (int64_t)kb * P;
-        g.lda = P;
-        g.B = g.A;
-        g.ldb = P;
-        g.transB = 1;
-        g.C = mres.as<double>();
-        g.ldc = P;
-        g.M = (int)P;
-        g.N = (int)P;
-        g.K = k + 1 - kb;
-        g.alpha = -1.0;
-        g.beta = 1.0;
-        g.lower = 1;
-        if ((st = gemm_prof(pl, ISDF_K_GEMM_SELECT, EPI_AXPBY, g)) != ISDF_OK) return st;
-        kb = k + 1;
       }
     }
     d0 = d1;

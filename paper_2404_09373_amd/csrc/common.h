@@ -147,14 +147,17 @@ struct SelDomain {
   int32_t pts, nG, nL, n_mu;
   int32_t tile_off, ntiles;
   int32_t piv_off, pad;
+  double dstop;                  // > 0: stop (reason SEL_END_BLOCK) before a pivot with d <= dstop
+  double d0fix;                  // > 0: the eps stop is relative to this, else to the first max
 };
+enum { SEL_END_COUNT = 1, SEL_END_EPS = 2, SEL_END_BLOCK = 3 };
 struct SelState {
   double d0max;
   double dpiv;
   int32_t cur;
   int32_t done;
   int32_t count;
-  int32_t pad;
+  int32_t reason;                // SEL_END_* once done
 };
 constexpr int SEL_TILE = 64;
 isdf_status launch_sel_init(hipStream_t s, const SelDomain* doms, const int32_t* tile_dom,
@@ -183,6 +186,22 @@ struct GatherDom {
   int32_t func_off;              // into the per-domain function list pool
   int32_t pad;
 };
+// ------------------------------------------- candidate-restricted blocks
+struct CrbInfo {
+  int32_t nc;       // candidates listed
+  int32_t nactive;  // points not yet chosen
+  double theta;     // largest d outside the candidates (-1: none)
+  double dmax;      // largest d
+};
+isdf_status launch_crb_candidates(hipStream_t s, const double* d, int n, int T, int32_t* cidx,
+                                  double* dC, CrbInfo* info);
+isdf_status launch_crb_gather(hipStream_t s, const double* src, int64_t lds, const int32_t* idx, int nr,
+                              int nc, double* dst, int64_t ldd);
+isdf_status launch_crb_trsm_block(hipStream_t s, double* X, int64_t ldx, int n, const double* U,
+                                  int64_t ldu, int jb, int nb);
+isdf_status launch_crb_diag(hipStream_t s, double* d, int n, const double* L, int64_t ldl, int nb,
+                            const int32_t* piv);
+
 isdf_status launch_gather_x(hipStream_t s, const GatherDom* doms, int ndom, int max_rows,
                             const double* phi, const int32_t* piv, const int32_t* funcs,
                             double* xrows, double* XL, double* XN, int64_t nmu);

@@ -1,0 +1,218 @@
+// Candidate-restricted blocked pivoted Cholesky for a domain that is alone on
+// its level (the universal grid): the greedy selection of the Interpolative
+// decomposition section (Eq. M(R,R)) over many points with many pivots.
+//
+// A block starts from the exact residual diagonal d.  Its candidates C are
+// the T points of largest d (ties at the cut included); theta is the largest
+// d outside C.  Residual diagonals never grow, so as long as every pivot of
+// the block has d > theta / (1 - tie_tol), no point outside C can be the
+// maximum or enter a tie window: the greedy steps restricted to C are the
+// greedy steps over all points.  The block runs on the small residual
+// R_CC = M(C, C) - L(C, :) L(C, :)^T until that test (or the eps/count stop)
+// ends it; then the block's factor columns of every point follow in bulk,
+//   L(:, blk) = (M(:, P) - L(:, :kb) L(P, :kb)^T) U^{-T},  U = L(P, blk),
+// and d loses their squares.  The next block starts over from the new d.
+#include <climits>
+
+#include "common.h"
+
+namespace isdf {
+
+namespace {
+__device__ inline uint64_t dkey(double v) {  // order-preserving key of v >= 0
+  return (uint64_t)__double_as_longlong(v);
+}
+
+template <typename T, typename Op>
+__device__ inline T block_reduce(T v, T* red, Op op) {
+  for (int o = 32; o > 0; o >>= 1) v = op(v, __shfl_xor(v, o, 64));
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  T r = red[0];
+  for (int i = 1; i < nw; ++i) r = op(r, red[i]);
+  return r;
+}
+}  // namespace
+
+// One workgroup of 1024 threads.  Active points: d >= 0 (chosen points hold
+// -1).  Candidates: the T largest active d, ties at the cut included, listed
+// in ascending point order (the tie rule's order) with their d.
+__global__ void __launch_bounds__(1024)
+crb_candidates_kernel(const double* __restrict__ d, int n, int T, int32_t* __restrict__ cidx,
+                      double* __restrict__ dC, CrbInfo* __restrict__ info) {
+  __shared__ uint64_t red_u[16];
+  __shared__ double red_d[16];
+  __shared__ int32_t scan[1024];
+  const int tid = threadIdx.x;
+  auto add = [](uint64_t a, uint64_t b) { return a + b; };
+  auto dmaxf = [](double a, double b) { return fmax(a, b); };
+  // active count and largest d
+  uint64_t na = 0;
+  double dm = -1.0;
+  for (int i = tid; i < n; i += 1024) {
+    const double v = d[i];
+    if (v >= 0.0) {
+      ++na;
+      dm = fmax(dm, v);
+    }
+  }
+  na = block_reduce<uint64_t>(na, red_u, add);
+  dm = block_reduce<double>(dm, red_d, dmaxf);
+  // the T-th largest key, most significant bit first
+  uint64_t cut = 0;
+  if (na > (uint64_t)T) {
+    for (int b = 63; b >= 0; --b) {
+      const uint64_t trial = cut | (1ull << b);
+      uint64_t c = 0;
+      for (int i = tid; i < n; i += 1024) {
+        const double v = d[i];
+        c += (v >= 0.0 && dkey(v) >= trial) ? 1 : 0;
+      }
+      c = block_reduce<uint64_t>(c, red_u, add);
+      if (c >= (uint64_t)T) cut = trial;
+    }
+  }
+  // largest d below the cut (outside the candidates)
+  double th = -1.0;
+  if (na > (uint64_t)T)
+    for (int i = tid; i < n; i += 1024) {
+      const double v = d[i];
+      if (v >= 0.0 && dkey(v) < cut) th = fmax(th, v);
+    }
+  th = block_reduce<double>(th, red_d, dmaxf);
+  // compaction in point order: thread t owns a contiguous chunk
+  const int chunk = (n + 1023) / 1024;
+  const int lo = min(n, tid * chunk), hi = min(n, lo + chunk);
+  int cnt = 0;
+  for (int i = lo; i < hi; ++i) {
+    const double v = d[i];
+    cnt += (v >= 0.0 && dkey(v) >= cut) ? 1 : 0;
+  }
+  scan[tid] = cnt;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {  // inclusive scan
+    const int add_v = tid >= o ? scan[tid - o] : 0;
+    __syncthreads();
+    scan[tid] += add_v;
+    __syncthreads();
+  }
+  int pos = scan[tid] - cnt;
+  for (int i = lo; i < hi; ++i) {
+    const double v = d[i];
+    if (v >= 0.0 && dkey(v) >= cut) {
+      cidx[pos] = i;
+      dC[pos] = v;
+      ++pos;
+    }
+  }
+  if (tid == 1023) {
+    info->nc = scan[1023];
+    info->nactive = (int32_t)na;
+    info->theta = th;
+    info->dmax = dm;
+  }
+}
+
+isdf_status launch_crb_candidates(hipStream_t s, const double* d, int n, int T, int32_t* cidx,
+                                  double* dC, CrbInfo* info) {
+  if (n <= 0 || T <= 0) {
+    set_error("crb: empty domain or candidate budget");
+    return ISDF_E_ARG;
+  }
+  hipLaunchKernelGGL(crb_candidates_kernel, dim3(1), dim3(1024), 0, s, d, n, T, cidx, dC, info);
+  ISDF_HIP_TRY(hipGetLastError());
+  return ISDF_OK;
+}
+
+// dst[r + c ldd] = src[idx[r] + c lds], r < nr, c < nc
+__global__ void __launch_bounds__(256)
+crb_gather_kernel(const double* __restrict__ src, int64_t lds, const int32_t* __restrict__ idx, int nr,
+                  int nc, double* __restrict__ dst, int64_t ldd) {
+  const int c = blockIdx.y;
+  for (int r = blockIdx.x * 256 + threadIdx.x; r < nr; r += gridDim.x * 256)
+    dst[r + c * ldd] = src[(int64_t)idx[r] + c * lds];
+}
+
+isdf_status launch_crb_gather(hipStream_t s, const double* src, int64_t lds, const int32_t* idx, int nr,
+                              int nc, double* dst, int64_t ldd) {
+  if (nr <= 0 || nc <= 0) return ISDF_OK;
+  const int bx = std::min(64, (nr + 255) / 256);
+  hipLaunchKernelGGL(crb_gather_kernel, dim3(bx, nc), dim3(256), 0, s, src, lds, idx, nr, nc, dst, ldd);
+  ISDF_HIP_TRY(hipGetLastError());
+  return ISDF_OK;
+}
+
+// X[:, jb : jb + nb] <- X[:, jb : jb + nb] U_bb^{-T} for the lower-triangular
+// diagonal block U_bb = U[jb : jb + nb, jb : jb + nb] (nb <= 64), one row of X
+// per thread (forward substitution).
+__global__ void __launch_bounds__(256)
+crb_trsm_block_kernel(double* __restrict__ X, int64_t ldx, int n, const double* __restrict__ U,
+                      int64_t ldu, int jb, int nb) {
+  __shared__ double Ub[64][65];
+  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+    const int q = e % 64, c = e / 64;
+    Ub[q][c] = (q < nb && c < nb) ? U[(jb + q) + (int64_t)(jb + c) * ldu] : 0.0;
+  }
+  __syncthreads();
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  double x[64];
+  double* xr = X + i + (int64_t)jb * ldx;
+#pragma unroll
+  for (int q = 0; q < 64; ++q) {
+    if (q < nb) {
+      double g = xr[(int64_t)q * ldx];
+#pragma unroll
+      for (int c = 0; c < q; ++c) g -= x[c] * Ub[q][c];
+      x[q] = g / Ub[q][q];
+      xr[(int64_t)q * ldx] = x[q];
+    }
+  }
+}
+
+isdf_status launch_crb_trsm_block(hipStream_t s, double* X, int64_t ldx, int n, const double* U,
+                                  int64_t ldu, int jb, int nb) {
+  if (n <= 0 || nb <= 0) return ISDF_OK;
+  if (nb > 64) {
+    set_error("crb: diagonal block wider than 64");
+    return ISDF_E_ARG;
+  }
+  hipLaunchKernelGGL(crb_trsm_block_kernel, dim3((n + 255) / 256), dim3(256), 0, s, X, ldx, n, U, ldu,
+                     jb, nb);
+  ISDF_HIP_TRY(hipGetLastError());
+  return ISDF_OK;
+}
+
+// d(i) <- max(d(i) - sum_q L(i, q)^2, 0) over the block's columns for active
+// points; then the block's pivots leave (d = -1).
+__global__ void __launch_bounds__(256)
+crb_diag_kernel(double* __restrict__ d, int n, const double* __restrict__ L, int64_t ldl, int nb) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const double v = d[i];
+  if (!(v >= 0.0)) return;
+  double a = 0.0;
+  for (int q = 0; q < nb; ++q) {
+    const double l = L[i + (int64_t)q * ldl];
+    a += l * l;
+  }
+  d[i] = fmax(v - a, 0.0);
+}
+__global__ void crb_mark_kernel(double* __restrict__ d, const int32_t* __restrict__ piv, int nb) {
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j < nb) d[piv[j]] = -1.0;
+}
+
+isdf_status launch_crb_diag(hipStream_t s, double* d, int n, const double* L, int64_t ldl, int nb,
+                            const int32_t* piv) {
+  if (n <= 0 || nb <= 0) return ISDF_OK;
+  hipLaunchKernelGGL(crb_diag_kernel, dim3((n + 255) / 256), dim3(256), 0, s, d, n, L, ldl, nb);
+  ISDF_HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(crb_mark_kernel, dim3((nb + 255) / 256), dim3(256), 0, s, d, piv, nb);
+  ISDF_HIP_TRY(hipGetLastError());
+  return ISDF_OK;
+}
+
+}  // namespace isdf

@@ -179,6 +179,7 @@ sel_select_kernel(const SelDomain* __restrict__ doms, int dom_base, int k, SelSt
     if (tid == 0) {
       st[dom].done = 1;
       st[dom].count = k;
+      st[dom].reason = SEL_END_COUNT;
     }
     return;
   }
@@ -192,13 +193,14 @@ sel_select_kernel(const SelDomain* __restrict__ doms, int dom_base, int k, SelSt
     __syncthreads();
   }
   const double Mstar = s_red[0];
-  if (k == 0 && tid == 0) st[dom].d0max = Mstar;
+  if (k == 0 && tid == 0) st[dom].d0max = D.d0fix > 0.0 ? D.d0fix : Mstar;
   __syncthreads();
   const double d0max = st[dom].d0max;
   if (Mstar < 0.0) {  // no candidates left
     if (tid == 0) {
       st[dom].done = 1;
       st[dom].count = k;
+      st[dom].reason = SEL_END_EPS;
     }
     return;
   }
@@ -219,6 +221,7 @@ sel_select_kernel(const SelDomain* __restrict__ doms, int dom_base, int k, SelSt
     if (tid == 0) {
       st[dom].done = 1;
       st[dom].count = k;
+      st[dom].reason = SEL_END_EPS;
     }
     return;
   }
@@ -236,10 +239,12 @@ sel_select_kernel(const SelDomain* __restrict__ doms, int dom_base, int k, SelSt
     if (tid == 0) {
       s_p = cand;
       const double dp = cand == INT_MAX ? 0.0 : diag[D.diag_off + cand];
-      s_stop = cand == INT_MAX || !(dp > eps * d0max);
+      const bool end = cand == INT_MAX || !(dp > eps * d0max);
+      s_stop = end || !(dp > D.dstop);
       if (s_stop) {
         st[dom].done = 1;
         st[dom].count = k;
+        st[dom].reason = end ? SEL_END_EPS : SEL_END_BLOCK;
       } else {
         st[dom].dpiv = dp;
         st[dom].cur = cand;
