@@ -654,14 +654,13 @@ isdf_status crb_select(isdf_plan_s* pl, const SelDomain& X, const double* phi_ba
   int32_t* piv = piv_out + X.piv_off;
   const double tau = hp.tie_tol, eps = hp.eps_isdf;
   isdf_status e;
-  DevBuf cidx, dC, info, phiC, LC, RCC, LCb, prowb, tmaxb, tidxb, stb, pivC, tdom, sdb, phiP, LP, Ub;
+  DevBuf cidx, dC, dC2, info, phiC, LC, RCC, LCb, tmaxb, tidxb, stb, pivC, tdom, sdb, phiP, LP, Ub;
   const int Tmax = n;
   int T = std::min(n, CRB_CANDIDATES);
   if ((e = cidx.alloc(sizeof(int32_t) * n)) != ISDF_OK) return e;
   if ((e = dC.alloc(sizeof(double) * n)) != ISDF_OK) return e;
   if ((e = info.alloc(sizeof(CrbInfo))) != ISDF_OK) return e;
   if ((e = pivC.alloc(sizeof(int32_t) * CRB_BLOCK)) != ISDF_OK) return e;
-  if ((e = prowb.alloc(sizeof(double) * CRB_BLOCK)) != ISDF_OK) return e;
   if ((e = stb.alloc(sizeof(SelState))) != ISDF_OK) return e;
   if ((e = sdb.alloc(sizeof(SelDomain))) != ISDF_OK) return e;
   int kb = 0;
@@ -723,7 +722,6 @@ isdf_status crb_select(isdf_plan_s* pl, const SelDomain& X, const double* phi_ba
     B.lfac_off = 0;
     B.diag_off = 0;
     B.prow_off = 0;
-    B.mres_off = 0;
     B.pts = nc;
     B.nG = 0;
     B.nL = 0;
@@ -731,33 +729,30 @@ isdf_status crb_select(isdf_plan_s* pl, const SelDomain& X, const double* phi_ba
     B.tile_off = 0;
     B.ntiles = (nc + SEL_TILE - 1) / SEL_TILE;
     B.piv_off = 0;
-    B.dstop = ci.theta >= 0.0 ? ci.theta / (1.0 - tau) : 0.0;
-    B.d0fix = d0max;
     if ((e = copy_in(sdb.p, &B, sizeof(SelDomain))) != ISDF_OK) return e;
     std::vector<int32_t> td(B.ntiles, 0);
     if ((e = upload(tdom, td)) != ISDF_OK) return e;
     if ((e = LCb.alloc(sizeof(double) * (size_t)nc * nb)) != ISDF_OK) return e;
-    if ((e = tmaxb.alloc(sizeof(double) * B.ntiles)) != ISDF_OK) return e;
-    if ((e = tidxb.alloc(sizeof(int32_t) * B.ntiles)) != ISDF_OK) return e;
+    if ((e = tmaxb.alloc(sizeof(double) * 2 * B.ntiles)) != ISDF_OK) return e;
+    if ((e = tidxb.alloc(sizeof(int32_t) * 2 * B.ntiles)) != ISDF_OK) return e;
+    if ((e = dC2.alloc(sizeof(double) * (size_t)nc)) != ISDF_OK) return e;
     ISDF_HIP_TRY(hipMemsetAsync(stb.p, 0, sizeof(SelState), s));
     const SelDomain* Dd = sdb.as<SelDomain>();
+    const double dstop = ci.theta >= 0.0 ? ci.theta / (1.0 - tau) : 0.0;
     SelState* Sd = stb.as<SelState>();
     if ((e = launch_sel_init(s, Dd, tdom.as<int32_t>(), 0, B.ntiles, dC.as<double>(), tmaxb.as<double>(),
                              tidxb.as<int32_t>(), tau)) != ISDF_OK)
       return e;
+    // step k reads copy k & 1 of the diagonal and tile maxima, writes the other
+    double* dd[2] = {dC.as<double>(), dC2.as<double>()};
+    double* tm[2] = {tmaxb.as<double>(), tmaxb.as<double>() + B.ntiles};
+    int32_t* ti[2] = {tidxb.as<int32_t>(), tidxb.as<int32_t>() + B.ntiles};
     for (int k = 0; k <= nb; ++k) {
-      {
-        ProfScope ps(pl, ISDF_K_SELECT_PICK, 12.0 * B.ntiles + 16.0 * k, 0.0);
-        if ((e = launch_sel_select(s, Dd, 0, 1, k, Sd, phi, LCb.as<double>(), dC.as<double>(),
-                                   tmaxb.as<double>(), tidxb.as<int32_t>(), prowb.as<double>(),
-                                   pivC.as<int32_t>(), tau, eps)) != ISDF_OK)
-          return e;
-      }
-      if (k == nb) break;
-      ProfScope ps(pl, ISDF_K_SELECT_COLUMN, 8.0 * nc * (k + 4.0), 2.0 * nc * k);
-      if ((e = launch_sel_column(s, Dd, tdom.as<int32_t>(), 0, B.ntiles, k, 0, Sd, phi, RCC.as<double>(),
-                                 LCb.as<double>(), dC.as<double>(), prowb.as<double>(),
-                                 tmaxb.as<double>(), tidxb.as<int32_t>(), tau)) != ISDF_OK)
+      const int c = k & 1;
+      ProfScope ps(pl, ISDF_K_SELECT_COLUMN, 8.0 * nc * (k + 4.0) + 12.0 * B.ntiles, 2.0 * nc * k);
+      if ((e = launch_crb_step(s, k, nb, nc, RCC.as<double>(), LCb.as<double>(), dd[c], dd[c ^ 1], tm[c],
+                               ti[c], tm[c ^ 1], ti[c ^ 1], Sd, pivC.as<int32_t>(), tau, eps, dstop,
+                               d0max)) != ISDF_OK)
         return e;
     }
     SelState bs{};
@@ -876,7 +871,6 @@ isdf_status select_points(isdf_plan_s* pl, const std::vector<SelSpec>& spec,
     x.tile_off = (int)tile_dom.size();
     x.ntiles = (x.pts + SEL_TILE - 1) / SEL_TILE;
     x.piv_off = (int)piv_off[d];
-    x.mres_off = -1;
     for (int t = 0; t < x.ntiles; ++t) tile_dom.push_back(d);
     lf += (int64_t)x.pts * x.n_mu;
     pr += x.nG + x.n_mu;
@@ -942,10 +936,9 @@ isdf_status select_points(isdf_plan_s* pl, const std::vector<SelSpec>& spec,
       if (k == kmax) break;
       {
         ProfScope ps_col(pl, ISDF_K_SELECT_COLUMN, col_bytes, col_flops);
-        if ((st = launch_sel_column(s, D, d_tile_dom.as<int32_t>(), t0, t1 - t0, k, 0, S,
-                                    phi_base, nullptr, lfac.as<double>(), diag_base,
-                                    prow.as<double>(), tmax.as<double>(), tidx.as<int32_t>(),
-                                    tau)) != ISDF_OK)
+        if ((st = launch_sel_column(s, D, d_tile_dom.as<int32_t>(), t0, t1 - t0, k, S, phi_base,
+                                    lfac.as<double>(), diag_base, prow.as<double>(),
+                                    tmax.as<double>(), tidx.as<int32_t>(), tau)) != ISDF_OK)
           return st;
       }
     }

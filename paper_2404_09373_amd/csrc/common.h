@@ -143,12 +143,9 @@ isdf_status launch_basis_eval(hipStream_t s, const LatticeArg& lat, const ShellD
 // Selection (pivoted Cholesky) over a batch of domains.
 struct SelDomain {
   int64_t phi_off, lfac_off, diag_off, prow_off;
-  int64_t mres_off;              // >= 0: right-looking, residual Gram (lower) at this offset
   int32_t pts, nG, nL, n_mu;
   int32_t tile_off, ntiles;
   int32_t piv_off, pad;
-  double dstop;                  // > 0: stop (reason SEL_END_BLOCK) before a pivot with d <= dstop
-  double d0fix;                  // > 0: the eps stop is relative to this, else to the first max
 };
 enum { SEL_END_COUNT = 1, SEL_END_EPS = 2, SEL_END_BLOCK = 3 };
 struct SelState {
@@ -167,12 +164,10 @@ isdf_status launch_sel_select(hipStream_t s, const SelDomain* doms, int dom_base
                               int k, SelState* st, const double* phi, const double* lfac,
                               double* diag, const double* tmax, const int32_t* tidx, double* prow,
                               int32_t* piv, double tau, double eps);
-// Left-looking (mres == nullptr): column from the basis values and all k
-// previous factor columns.  Right-looking: column from the residual Gram
-// (lower triangle, updated up to column kb) and the factor columns kb..k-1.
+// Left-looking column: from the basis values and all k previous factor columns.
 isdf_status launch_sel_column(hipStream_t s, const SelDomain* doms, const int32_t* tile_dom,
-                              int tile_base, int ntiles, int k, int kb, const SelState* st,
-                              const double* phi, const double* mres, double* lfac, double* diag,
+                              int tile_base, int ntiles, int k, const SelState* st,
+                              const double* phi, double* lfac, double* diag,
                               const double* prow, double* tmax, int32_t* tidx, double tau);
 
 // Gather of the pivot rows of Phi into per-domain X rows and the global
@@ -195,6 +190,10 @@ struct CrbInfo {
 };
 isdf_status launch_crb_candidates(hipStream_t s, const double* d, int n, int T, int32_t* cidx,
                                   double* dC, CrbInfo* info);
+isdf_status launch_crb_step(hipStream_t s, int k, int nb, int nc, const double* R, double* Lb,
+                            const double* dcur, double* dnext, const double* tcur, const int32_t* icur,
+                            double* tnext, int32_t* inext, SelState* st, int32_t* pivC, double tau,
+                            double eps, double dstop, double d0max);
 isdf_status launch_crb_gather(hipStream_t s, const double* src, int64_t lds, const int32_t* idx, int nr,
                               int nc, double* dst, int64_t ldd);
 isdf_status launch_crb_trsm_block(hipStream_t s, double* X, int64_t ldx, int n, const double* U,

@@ -19,6 +19,14 @@
 namespace isdf {
 
 namespace {
+__device__ inline double wave_max(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ inline int wave_min_int(int v) {
+  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+  return v;
+}
 __device__ inline uint64_t dkey(double v) {  // order-preserving key of v >= 0
   return (uint64_t)__double_as_longlong(v);
 }
@@ -122,6 +130,136 @@ isdf_status launch_crb_candidates(hipStream_t s, const double* d, int n, int T, 
     return ISDF_E_ARG;
   }
   hipLaunchKernelGGL(crb_candidates_kernel, dim3(1), dim3(1024), 0, s, d, n, T, cidx, dC, info);
+  ISDF_HIP_TRY(hipGetLastError());
+  return ISDF_OK;
+}
+
+// One greedy step of a block on the candidates, pick and column in one
+// launch.  Every workgroup redoes the pick of step k from the tile maxima of
+// step k - 1 (all get the same pivot), then forms the column on its own
+// 64-candidate tile; the diagonal and the tile maxima alternate between two
+// copies, so no workgroup reads what another one writes in this launch.
+// Stops as the separate pick does (count, eps, block threshold); workgroup 0
+// records the state.
+__global__ void __launch_bounds__(256)
+crb_step_kernel(int k, int nb, int nc, const double* __restrict__ R, double* __restrict__ Lb,
+                const double* __restrict__ dcur, double* __restrict__ dnext,
+                const double* __restrict__ tcur, const int32_t* __restrict__ icur,
+                double* __restrict__ tnext, int32_t* __restrict__ inext, SelState* __restrict__ st,
+                int32_t* __restrict__ pivC, double tau, double eps, double dstop, double d0max) {
+  __shared__ double s_red[4];
+  __shared__ int s_redi[4];
+  __shared__ int s_cand;
+  __shared__ double red[4][64];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  if (st->done) return;
+  const int ntiles = (nc + SEL_TILE - 1) / SEL_TILE;
+  // ---- pick
+  int reason = 0, p = INT_MAX;
+  double dp = 0.0;
+  if (k >= nb) {
+    reason = SEL_END_COUNT;
+  } else {
+    double m = -1.0;
+    for (int t = tid; t < ntiles; t += 256) m = fmax(m, tcur[t]);
+    m = wave_max(m);
+    if (lane == 0) s_red[w] = m;
+    __syncthreads();
+    const double Mstar = fmax(fmax(s_red[0], s_red[1]), fmax(s_red[2], s_red[3]));
+    if (Mstar < 0.0) {
+      reason = SEL_END_EPS;
+    } else {
+      const double thr = (1.0 - tau) * Mstar;
+      int ft = INT_MAX;
+      for (int t = tid; t < ntiles; t += 256)
+        if (tcur[t] >= thr) ft = min(ft, t);
+      ft = wave_min_int(ft);
+      if (lane == 0) s_redi[w] = ft;
+      __syncthreads();
+      const int t0 = min(min(s_redi[0], s_redi[1]), min(s_redi[2], s_redi[3]));
+      if (t0 == INT_MAX) {
+        reason = SEL_END_EPS;
+      } else {
+        int cand = INT_MAX;
+        if (w == 0) {
+          const int i = t0 * SEL_TILE + lane;
+          const int quick = icur[t0];
+          if (quick != INT_MAX && dcur[quick] >= thr) {
+            cand = quick;
+          } else if (i < nc) {
+            const double dv = dcur[i];
+            if (dv >= 0.0 && dv >= thr) cand = i;
+          }
+          cand = wave_min_int(cand);
+          if (lane == 0) s_cand = cand;
+        }
+        __syncthreads();
+        p = s_cand;
+        dp = p == INT_MAX ? 0.0 : dcur[p];
+        if (p == INT_MAX || !(dp > eps * d0max)) reason = SEL_END_EPS;
+        else if (!(dp > dstop)) reason = SEL_END_BLOCK;
+      }
+    }
+  }
+  if (reason) {
+    if (blockIdx.x == 0 && tid == 0) {
+      st->done = 1;
+      st->count = k;
+      st->reason = reason;
+    }
+    return;
+  }
+  if (blockIdx.x == 0 && tid == 0) {
+    st->d0max = d0max;
+    st->dpiv = dp;
+    st->cur = p;
+    pivC[k] = p;
+  }
+  // ---- column on this workgroup's tile: 4 waves split the block's columns
+  const int i = blockIdx.x * SEL_TILE + lane;
+  const bool valid = i < nc;
+  const int ii = valid ? i : 0;
+  const int64_t P = nc;
+  double sc = 0.0;
+  const double* lf = Lb + ii;
+  const double* lp = Lb + p;
+  int j = w;
+  for (; j + 12 < k; j += 16) {
+    sc += lf[j * P] * lp[j * P] + lf[(j + 4) * P] * lp[(j + 4) * P] + lf[(j + 8) * P] * lp[(j + 8) * P] +
+          lf[(j + 12) * P] * lp[(j + 12) * P];
+  }
+  for (; j < k; j += 4) sc += lf[j * P] * lp[j * P];
+  red[w][lane] = sc;
+  __syncthreads();
+  if (w != 0) return;
+  sc = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
+  const double rv = (ii >= p) ? R[ii + (int64_t)p * P] : R[p + (int64_t)ii * P];
+  const double ell = (rv - sc) / sqrt(dp);
+  double dv = -1.0;
+  if (valid) {
+    Lb[(int64_t)k * P + i] = ell;
+    const double old = dcur[i];
+    dv = (i == p) ? -1.0 : (old >= 0.0 ? fmax(old - ell * ell, 0.0) : old);
+    dnext[i] = dv;
+  }
+  // tile maximum and the smallest index in its tie window
+  const bool act = valid && dv >= 0.0;
+  const double tm = wave_max(act ? dv : -1.0);
+  const int cnd = (act && tm >= 0.0 && dv >= (1.0 - tau) * tm) ? i : INT_MAX;
+  const int mi = wave_min_int(cnd);
+  if (lane == 0) {
+    tnext[blockIdx.x] = tm;
+    inext[blockIdx.x] = mi;
+  }
+}
+
+isdf_status launch_crb_step(hipStream_t s, int k, int nb, int nc, const double* R, double* Lb,
+                            const double* dcur, double* dnext, const double* tcur, const int32_t* icur,
+                            double* tnext, int32_t* inext, SelState* st, int32_t* pivC, double tau,
+                            double eps, double dstop, double d0max) {
+  const int ntiles = (nc + SEL_TILE - 1) / SEL_TILE;
+  hipLaunchKernelGGL(crb_step_kernel, dim3(ntiles), dim3(256), 0, s, k, nb, nc, R, Lb, dcur, dnext, tcur,
+                     icur, tnext, inext, st, pivC, tau, eps, dstop, d0max);
   ISDF_HIP_TRY(hipGetLastError());
   return ISDF_OK;
 }

@@ -193,7 +193,7 @@ sel_select_kernel(const SelDomain* __restrict__ doms, int dom_base, int k, SelSt
     __syncthreads();
   }
   const double Mstar = s_red[0];
-  if (k == 0 && tid == 0) st[dom].d0max = D.d0fix > 0.0 ? D.d0fix : Mstar;
+  if (k == 0 && tid == 0) st[dom].d0max = Mstar;
   __syncthreads();
   const double d0max = st[dom].d0max;
   if (Mstar < 0.0) {  // no candidates left
@@ -239,12 +239,11 @@ sel_select_kernel(const SelDomain* __restrict__ doms, int dom_base, int k, SelSt
     if (tid == 0) {
       s_p = cand;
       const double dp = cand == INT_MAX ? 0.0 : diag[D.diag_off + cand];
-      const bool end = cand == INT_MAX || !(dp > eps * d0max);
-      s_stop = end || !(dp > D.dstop);
+      s_stop = cand == INT_MAX || !(dp > eps * d0max);
       if (s_stop) {
         st[dom].done = 1;
         st[dom].count = k;
-        st[dom].reason = end ? SEL_END_EPS : SEL_END_BLOCK;
+        st[dom].reason = SEL_END_EPS;
       } else {
         st[dom].dpiv = dp;
         st[dom].cur = cand;
@@ -278,9 +277,8 @@ isdf_status launch_sel_select(hipStream_t s, const SelDomain* doms, int dom_base
 // factor columns, then wave 0 finishes the points.
 __global__ void __launch_bounds__(256)
 sel_column_kernel(const SelDomain* __restrict__ doms, const int32_t* __restrict__ tile_dom,
-                  int tile_base, int k, int kb, const SelState* __restrict__ st,
-                  const double* __restrict__ phi, const double* __restrict__ mres,
-                  double* __restrict__ lfac, double* __restrict__ diag,
+                  int tile_base, int k, const SelState* __restrict__ st,
+                  const double* __restrict__ phi, double* __restrict__ lfac, double* __restrict__ diag,
                   const double* __restrict__ prow, double* __restrict__ tmax,
                   int32_t* __restrict__ tidx, double tau) {
   const int tile = tile_base + (int)blockIdx.x;
@@ -296,17 +294,7 @@ sel_column_kernel(const SelDomain* __restrict__ doms, const int32_t* __restrict_
   const double* pr = prow + D.prow_off;
   const double* ph = phi + D.phi_off + ii;
   double sL = 0.0, sN = 0.0, sc = 0.0;
-  const bool right = D.mres_off >= 0;
-  int j0 = 0;
-  if (right) {
-    // residual Gram entry (ii, p) from the stored lower triangle
-    if (w == 0) {
-      const int p = st[dom].cur;
-      const double* m = mres + D.mres_off;
-      sL = (ii >= p) ? m[ii + (int64_t)p * P] : m[p + (int64_t)ii * P];
-    }
-    j0 = kb;
-  } else {
+  {
     int c = w;
     for (; c + 12 < D.nL; c += 16) {
       const double a0 = ph[c * P], a1 = ph[(c + 4) * P], a2 = ph[(c + 8) * P], a3 = ph[(c + 12) * P];
@@ -320,7 +308,7 @@ sel_column_kernel(const SelDomain* __restrict__ doms, const int32_t* __restrict_
     for (; c < D.nG; c += 4) sN += ph[c * P] * pr[c];
   }
   const double* lf = lfac + D.lfac_off + ii;
-  int j = j0 + w;
+  int j = w;
   for (; j + 12 < k; j += 16) {
     const double b0 = lf[j * P], b1 = lf[(j + 4) * P], b2 = lf[(j + 8) * P], b3 = lf[(j + 12) * P];
     sc += b0 * pr[D.nG + j] + b1 * pr[D.nG + j + 4] + b2 * pr[D.nG + j + 8] + b3 * pr[D.nG + j + 12];
@@ -335,7 +323,7 @@ sel_column_kernel(const SelDomain* __restrict__ doms, const int32_t* __restrict_
   sL = (red[0][0][lane] + red[0][1][lane]) + (red[0][2][lane] + red[0][3][lane]);
   sN = (red[1][0][lane] + red[1][1][lane]) + (red[1][2][lane] + red[1][3][lane]);
   sc = (red[2][0][lane] + red[2][1][lane]) + (red[2][2][lane] + red[2][3][lane]);
-  const double col = (right ? sL : sL * (sL + 2.0 * sN)) - sc;
+  const double col = sL * (sL + 2.0 * sN) - sc;
   const double ell = col / sqrt(st[dom].dpiv);
   double dv = -1.0;
   if (valid) {
@@ -350,12 +338,12 @@ sel_column_kernel(const SelDomain* __restrict__ doms, const int32_t* __restrict_
 }
 
 isdf_status launch_sel_column(hipStream_t s, const SelDomain* doms, const int32_t* tile_dom,
-                              int tile_base, int ntiles, int k, int kb, const SelState* st,
-                              const double* phi, const double* mres, double* lfac, double* diag,
+                              int tile_base, int ntiles, int k, const SelState* st,
+                              const double* phi, double* lfac, double* diag,
                               const double* prow, double* tmax, int32_t* tidx, double tau) {
   if (ntiles <= 0) return ISDF_OK;
   hipLaunchKernelGGL(sel_column_kernel, dim3(ntiles), dim3(256), 0, s, doms, tile_dom, tile_base,
-                     k, kb, st, phi, mres, lfac, diag, prow, tmax, tidx, tau);
+                     k, st, phi, lfac, diag, prow, tmax, tidx, tau);
   ISDF_HIP_TRY(hipGetLastError());
   return ISDF_OK;
 }
