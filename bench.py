@@ -40,13 +40,13 @@ PEAK_FP64_TFS = 78.6
 PEAK_BF16_TFS = 2500.0
 # family id -> (name, bound, kernel name in profiles)
 FAMILIES = {
-    0: ("select_column", "hbm", "sel_column_kernel"),
+    0: ("select_column", "hbm", "sel_column_kernel | crb_step_kernel"),
     1: ("select_pick", "hbm", "sel_select_kernel"),
     2: ("gemm_select", "mfma", "gemm_f64_kernel<*, 1>"),
     3: ("gemm_metric", "mfma", "gemm_f64_kernel<*, 2>"),
     4: ("gemm_fit", "mfma", "gemm_f64_kernel<*, 3>"),
     5: ("gemm_exchange", "mfma", "gemm_f64_kernel<*, 4>"),
-    6: ("fft", "hbm", "fft_pass_kernel"),
+    6: ("fft", "hbm", "fft_pass_fixed_kernel | fft_fwd_pruned_kernel | fft_pass_kernel"),
     7: ("basis", "hbm", "basis_eval_kernel"),
 }
 
