@@ -394,6 +394,12 @@ def main():
             },
             "kernel_families_ms_one_step": {FAMILIES[f][0]: round(v["ms"], 3)
                                             for f, v in r["stats"].items()},
+            # achieved rate of each family in that step (GB/s of algorithmic
+            # bytes for HBM-bound families, TFLOP/s for MFMA ones)
+            "kernel_families_rate_one_step": {
+                FAMILIES[f][0]: (round(v["bytes"] / v["ms"] / 1e6, 1) if FAMILIES[f][1] == "hbm"
+                                 else round(v["flops"] / v["ms"] / 1e9, 2)) if v["ms"] > 0 else None
+                for f, v in r["stats"].items()},
             "candidates": int(np.sum(sel["n_candidates"])),
             "fallback_domains": int(np.sum(sel["fallback"])),
         }

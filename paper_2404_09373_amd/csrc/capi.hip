@@ -19,6 +19,7 @@
 #include <cstdio>
 #include <cstring>
 #include <fstream>
+#include <functional>
 #include <map>
 #include <sstream>
 #include <memory>
@@ -41,6 +42,7 @@ constexpr int NSTAGE = 8;
 constexpr int RL_MIN_PIVOTS = 128;  // blocked selection of a lone domain above this many pivots
 constexpr int CRB_BLOCK = 512;      // most pivots per block
 constexpr int CRB_CANDIDATES = 4096;  // candidates per block to start with
+constexpr int CRB_CHUNK = 32;          // greedy-step launches between state checks
 
 // Device memory of one plan.  A block that a buffer gives back is kept and
 // handed to a later buffer of the same plan, with no hipFree/hipMalloc (both
@@ -294,6 +296,10 @@ struct isdf_plan_s {
   std::map<std::string, std::vector<float>> tune_us;
   bool tuning = false;
   int tune_reps = 3;
+  // universal-grid selection: pinned copies of the block state after the
+  // last two chunks of step launches, and the events that mark them
+  SelState* crb_host = nullptr;
+  hipEvent_t crb_ev[2] = {};
 };
 
 struct isdf_fit_s {
@@ -747,13 +753,32 @@ isdf_status crb_select(isdf_plan_s* pl, const SelDomain& X, const double* phi_ba
     double* dd[2] = {dC.as<double>(), dC2.as<double>()};
     double* tm[2] = {tmaxb.as<double>(), tmaxb.as<double>() + B.ntiles};
     int32_t* ti[2] = {tidxb.as<int32_t>(), tidxb.as<int32_t>() + B.ntiles};
-    for (int k = 0; k <= nb; ++k) {
-      const int c = k & 1;
-      ProfScope ps(pl, ISDF_K_SELECT_COLUMN, 8.0 * nc * (k + 4.0) + 12.0 * B.ntiles, 2.0 * nc * k);
-      if ((e = launch_crb_step(s, k, nb, nc, RCC.as<double>(), LCb.as<double>(), dd[c], dd[c ^ 1], tm[c],
-                               ti[c], tm[c ^ 1], ti[c ^ 1], Sd, pivC.as<int32_t>(), tau, eps, dstop,
-                               d0max)) != ISDF_OK)
-        return e;
+    // Steps go out in chunks; after each chunk the state is copied to pinned
+    // memory, and the copy of the chunk before is checked while this one
+    // runs: a block that stopped early (most do, at the theta bound) costs at
+    // most two chunks of launches that return at once.
+    if (!pl->crb_host) {
+      ISDF_HIP_TRY(hipHostMalloc((void**)&pl->crb_host, 2 * sizeof(SelState)));
+      for (auto& ev : pl->crb_ev) ISDF_HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    }
+    for (int k0 = 0, chunk = 0; k0 <= nb; k0 += CRB_CHUNK, ++chunk) {
+      const int k1 = std::min(nb + 1, k0 + CRB_CHUNK);
+      for (int k = k0; k < k1; ++k) {
+        const int c = k & 1;
+        ProfScope ps(pl, ISDF_K_SELECT_COLUMN, 8.0 * nc * (k + 4.0) + 12.0 * B.ntiles, 2.0 * nc * k);
+        if ((e = launch_crb_step(s, k, nb, nc, RCC.as<double>(), LCb.as<double>(), dd[c], dd[c ^ 1], tm[c],
+                                 ti[c], tm[c ^ 1], ti[c ^ 1], Sd, pivC.as<int32_t>(), tau, eps, dstop,
+                                 d0max)) != ISDF_OK)
+          return e;
+      }
+      if (k1 > nb) break;
+      const int slot = chunk & 1;
+      ISDF_HIP_TRY(hipMemcpyAsync(pl->crb_host + slot, Sd, sizeof(SelState), hipMemcpyDeviceToHost, s));
+      ISDF_HIP_TRY(hipEventRecord(pl->crb_ev[slot], s));
+      if (chunk > 0) {
+        ISDF_HIP_TRY(hipEventSynchronize(pl->crb_ev[slot ^ 1]));
+        if (pl->crb_host[slot ^ 1].done) break;
+      }
     }
     SelState bs{};
     ISDF_HIP_TRY(hipMemcpyAsync(&bs, stb.p, sizeof(SelState), hipMemcpyDeviceToHost, s));
@@ -1293,47 +1318,59 @@ isdf_status blocked_fit(isdf_plan_s* pl, const double* theta, int64_t pts, int n
       if ((st = gemm_prof(pl, ISDF_K_GEMM_FIT, EPI_AXPBY, p)) != ISDF_OK) return st;
     }
   }
-  // G C^T = Theta
+  // G C^T = Theta, then F C = G, by recursive halving of the column range:
+  // each half's update from the other is one wide GEMM, and 64-column
+  // diagonal blocks are applied through their inverses.
   ISDF_HIP_TRY(hipMemcpyAsync(t, theta, sizeof(double) * pts * n, hipMemcpyDeviceToDevice, s));
-  for (int j = 0; j < nblk; ++j) {
-    const int jb = j * nb, w = std::min(nb, n - jb);
-    if (jb > 0) {
+  auto split = [&](int a, int b) { return a + std::max(1, (b - a) / nb / 2) * nb; };  // b - a > nb
+  // G[:, a:b] from T[:, a:b]; T[:, b:] is updated by the caller
+  std::function<isdf_status(int, int)> fwd = [&](int a, int b) -> isdf_status {
+    isdf_status r;
+    if (b - a <= nb) {
       GemmProblem p{};
-      p.A = g; p.lda = pts;
-      p.B = cf + jb; p.ldb = n; p.transB = 1;
-      p.C = t + (int64_t)jb * pts; p.ldc = pts;
-      p.M = (int)pts; p.N = w; p.K = jb;
-      p.alpha = -1.0; p.beta = 1.0;
-      if ((st = gemm_prof(pl, ISDF_K_GEMM_FIT, EPI_AXPBY, p)) != ISDF_OK) return st;
+      p.A = t + (int64_t)a * pts; p.lda = pts;
+      p.B = iv + (int64_t)(a / nb) * nb * nb; p.ldb = nb; p.transB = 1;
+      p.C = g + (int64_t)a * pts; p.ldc = pts;
+      p.M = (int)pts; p.N = b - a; p.K = b - a;
+      p.alpha = 1.0; p.beta = 0.0;
+      return gemm_prof(pl, ISDF_K_GEMM_FIT, EPI_AXPBY, p);
     }
-    GemmProblem p{};
-    p.A = t + (int64_t)jb * pts; p.lda = pts;
-    p.B = iv + (int64_t)j * nb * nb; p.ldb = nb; p.transB = 1;
-    p.C = g + (int64_t)jb * pts; p.ldc = pts;
-    p.M = (int)pts; p.N = w; p.K = w;
-    p.alpha = 1.0; p.beta = 0.0;
-    if ((st = gemm_prof(pl, ISDF_K_GEMM_FIT, EPI_AXPBY, p)) != ISDF_OK) return st;
-  }
-  // F C = G
-  for (int j = nblk - 1; j >= 0; --j) {
-    const int jb = j * nb, w = std::min(nb, n - jb);
-    if (jb + w < n) {
+    const int m = split(a, b);
+    if ((r = fwd(a, m)) != ISDF_OK) return r;
+    GemmProblem p{};  // T[:, m:b] -= G[:, a:m] C[m:b, a:m]^T
+    p.A = g + (int64_t)a * pts; p.lda = pts;
+    p.B = cf + m + (int64_t)a * n; p.ldb = n; p.transB = 1;
+    p.C = t + (int64_t)m * pts; p.ldc = pts;
+    p.M = (int)pts; p.N = b - m; p.K = m - a;
+    p.alpha = -1.0; p.beta = 1.0;
+    if ((r = gemm_prof(pl, ISDF_K_GEMM_FIT, EPI_AXPBY, p)) != ISDF_OK) return r;
+    return fwd(m, b);
+  };
+  // F[:, a:b] from G[:, a:b]; G[:, :a] is updated by the caller
+  std::function<isdf_status(int, int)> bwd = [&](int a, int b) -> isdf_status {
+    isdf_status r;
+    if (b - a <= nb) {
       GemmProblem p{};
-      p.A = F + (int64_t)(jb + w) * pts; p.lda = pts;
-      p.B = cf + (jb + w) + (int64_t)jb * n; p.ldb = n;
-      p.C = g + (int64_t)jb * pts; p.ldc = pts;
-      p.M = (int)pts; p.N = w; p.K = n - jb - w;
-      p.alpha = -1.0; p.beta = 1.0;
-      if ((st = gemm_prof(pl, ISDF_K_GEMM_FIT, EPI_AXPBY, p)) != ISDF_OK) return st;
+      p.A = g + (int64_t)a * pts; p.lda = pts;
+      p.B = iv + (int64_t)(a / nb) * nb * nb; p.ldb = nb;
+      p.C = F + (int64_t)a * pts; p.ldc = pts;
+      p.M = (int)pts; p.N = b - a; p.K = b - a;
+      p.alpha = 1.0; p.beta = 0.0;
+      return gemm_prof(pl, ISDF_K_GEMM_FIT, EPI_AXPBY, p);
     }
-    GemmProblem p{};
-    p.A = g + (int64_t)jb * pts; p.lda = pts;
-    p.B = iv + (int64_t)j * nb * nb; p.ldb = nb;
-    p.C = F + (int64_t)jb * pts; p.ldc = pts;
-    p.M = (int)pts; p.N = w; p.K = w;
-    p.alpha = 1.0; p.beta = 0.0;
-    if ((st = gemm_prof(pl, ISDF_K_GEMM_FIT, EPI_AXPBY, p)) != ISDF_OK) return st;
-  }
+    const int m = split(a, b);
+    if ((r = bwd(m, b)) != ISDF_OK) return r;
+    GemmProblem p{};  // G[:, a:m] -= F[:, m:b] C[m:b, a:m]
+    p.A = F + (int64_t)m * pts; p.lda = pts;
+    p.B = cf + m + (int64_t)a * n; p.ldb = n;
+    p.C = g + (int64_t)a * pts; p.ldc = pts;
+    p.M = (int)pts; p.N = m - a; p.K = b - m;
+    p.alpha = -1.0; p.beta = 1.0;
+    if ((r = gemm_prof(pl, ISDF_K_GEMM_FIT, EPI_AXPBY, p)) != ISDF_OK) return r;
+    return bwd(a, m);
+  };
+  if ((st = fwd(0, n)) != ISDF_OK) return st;
+  if ((st = bwd(0, n)) != ISDF_OK) return st;
   // the buffers are released when this returns: wait for their users
   ISDF_HIP_TRY(hipStreamSynchronize(s));
   return ISDF_OK;
@@ -2725,6 +2762,9 @@ void isdf_plan_destroy(isdf_plan_t plan) {
   for (int i = 0; i <= NSTAGE; ++i)
     if (plan->ev[i]) (void)hipEventDestroy(plan->ev[i]);
   for (auto e : plan->evpool) (void)hipEventDestroy(e);
+  for (auto e : plan->crb_ev)
+    if (e) (void)hipEventDestroy(e);
+  if (plan->crb_host) (void)hipHostFree(plan->crb_host);
   if (plan->cap_stream) (void)hipStreamDestroy(plan->cap_stream);
   delete plan;
 }

@@ -46,7 +46,13 @@ __device__ inline T block_reduce(T v, T* red, Op op) {
 
 // One workgroup of 1024 threads.  Active points: d >= 0 (chosen points hold
 // -1).  Candidates: the T largest active d, ties at the cut included, listed
-// in ascending point order (the tie rule's order) with their d.
+// in ascending point order (the tie rule's order) with their d.  The cut is
+// the largest key with at least T active keys at or above it, found most
+// significant bit first; each thread keeps the keys of its first CAND_KPT
+// points in registers across the passes.  Once exactly T keys lie at or
+// above the cut, lower bits can change neither the set nor theta, and the
+// search stops.
+constexpr int CAND_KPT = 32;
 __global__ void __launch_bounds__(1024)
 crb_candidates_kernel(const double* __restrict__ d, int n, int T, int32_t* __restrict__ cidx,
                       double* __restrict__ dC, CrbInfo* __restrict__ info) {
@@ -56,10 +62,28 @@ crb_candidates_kernel(const double* __restrict__ d, int n, int T, int32_t* __res
   const int tid = threadIdx.x;
   auto add = [](uint64_t a, uint64_t b) { return a + b; };
   auto dmaxf = [](double a, double b) { return fmax(a, b); };
+  // keys (0 for chosen points: never counted, since every trial key is >= 1),
   // active count and largest d
+  uint64_t kr[CAND_KPT];
+  uint32_t act = 0;  // bit j: register key j belongs to an active point
   uint64_t na = 0;
   double dm = -1.0;
-  for (int i = tid; i < n; i += 1024) {
+#pragma unroll
+  for (int j = 0; j < CAND_KPT; ++j) {
+    const int i = tid + j * 1024;
+    uint64_t key = 0;
+    if (i < n) {
+      const double v = d[i];
+      if (v >= 0.0) {
+        key = dkey(v);
+        act |= 1u << j;
+        ++na;
+        dm = fmax(dm, v);
+      }
+    }
+    kr[j] = key;
+  }
+  for (int i = tid + CAND_KPT * 1024; i < n; i += 1024) {
     const double v = d[i];
     if (v >= 0.0) {
       ++na;
@@ -68,27 +92,35 @@ crb_candidates_kernel(const double* __restrict__ d, int n, int T, int32_t* __res
   }
   na = block_reduce<uint64_t>(na, red_u, add);
   dm = block_reduce<double>(dm, red_d, dmaxf);
-  // the T-th largest key, most significant bit first
   uint64_t cut = 0;
   if (na > (uint64_t)T) {
     for (int b = 63; b >= 0; --b) {
       const uint64_t trial = cut | (1ull << b);
       uint64_t c = 0;
-      for (int i = tid; i < n; i += 1024) {
+#pragma unroll
+      for (int j = 0; j < CAND_KPT; ++j) c += kr[j] >= trial ? 1 : 0;
+      for (int i = tid + CAND_KPT * 1024; i < n; i += 1024) {
         const double v = d[i];
         c += (v >= 0.0 && dkey(v) >= trial) ? 1 : 0;
       }
       c = block_reduce<uint64_t>(c, red_u, add);
-      if (c >= (uint64_t)T) cut = trial;
+      if (c >= (uint64_t)T) {
+        cut = trial;
+        if (c == (uint64_t)T) break;
+      }
     }
   }
   // largest d below the cut (outside the candidates)
   double th = -1.0;
-  if (na > (uint64_t)T)
-    for (int i = tid; i < n; i += 1024) {
+  if (na > (uint64_t)T) {
+#pragma unroll
+    for (int j = 0; j < CAND_KPT; ++j)
+      if (((act >> j) & 1u) && kr[j] < cut) th = fmax(th, __longlong_as_double((long long)kr[j]));
+    for (int i = tid + CAND_KPT * 1024; i < n; i += 1024) {
       const double v = d[i];
       if (v >= 0.0 && dkey(v) < cut) th = fmax(th, v);
     }
+  }
   th = block_reduce<double>(th, red_d, dmaxf);
   // compaction in point order: thread t owns a contiguous chunk
   const int chunk = (n + 1023) / 1024;

@@ -29,10 +29,13 @@ __device__ void lds_cholesky(double (*a)[65], int w, int32_t* status) {
     const double djj = a[j][j];
     for (int i = j + 1 + tid; i < w; i += blockDim.x) a[i][j] /= djj;
     __syncthreads();
-    const int m = w - j - 1;
-    for (int idx = tid; idx < m * m; idx += blockDim.x) {
-      const int r = j + 1 + idx / m, c = j + 1 + idx % m;
-      if (c <= r) a[r][c] -= a[r][j] * a[c][j];
+    // trailing lower triangle: column j + 1 + (tid mod 64), rows strided by
+    // the number of 64-thread groups
+    const int c = j + 1 + (tid & 63);
+    if (c < w) {
+      const double acj = a[c][j];
+      for (int r = j + 1 + (tid >> 6); r < w; r += (int)blockDim.x >> 6)
+        if (r >= c) a[r][c] -= a[r][j] * acj;
     }
     __syncthreads();
   }
@@ -54,18 +57,23 @@ potrf_diag_kernel(double* __restrict__ M, int64_t ldm, double* __restrict__ Cf, 
     const int i = idx % w, j = idx / w;
     Cf[i + j * ldc] = (i >= j) ? a[i][j] : 0.0;
   }
-  // inverse of the lower factor, one column per thread
-  if (tid < w) {
-    const int c = tid;
-    for (int i = 0; i < c; ++i) x[i][c] = 0.0;
-    x[c][c] = 1.0 / a[c][c];
-    for (int i = c + 1; i < w; ++i) {
-      double s = 0.0;
-      for (int k = c; k < i; ++k) s += a[i][k] * x[k][c];
-      x[i][c] = -s / a[i][i];
-    }
+  // inverse of the lower factor: L X = I by forward elimination, the rows
+  // below each finished row updated by the whole workgroup
+  for (int idx = tid; idx < 64 * 64; idx += 256) {
+    const int i = idx & 63, j = idx >> 6;
+    x[i][j] = i == j ? 1.0 : 0.0;
   }
   __syncthreads();
+  for (int j = 0; j < w; ++j) {
+    if (tid <= j) x[j][tid] /= a[j][j];  // row j is final (columns <= j)
+    __syncthreads();
+    const int c = tid & 63;
+    if (c <= j) {
+      const double xjc = x[j][c];
+      for (int r = j + 1 + (tid >> 6); r < w; r += 4) x[r][c] -= a[r][j] * xjc;
+    }
+    __syncthreads();
+  }
   for (int idx = tid; idx < 64 * 64; idx += 256) {
     const int i = idx & 63, j = idx >> 6;
     inv[i + j * 64] = (i < w && j < w) ? x[i][j] : 0.0;
