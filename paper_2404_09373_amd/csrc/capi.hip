@@ -41,8 +41,8 @@ namespace {
 constexpr int NSTAGE = 8;
 constexpr int RL_MIN_PIVOTS = 128;  // blocked selection of a lone domain above this many pivots
 constexpr int CRB_BLOCK = 512;      // most pivots per block
-constexpr int CRB_CANDIDATES = 4096;  // candidates per block to start with
-constexpr int CRB_CHUNK = 32;          // greedy-step launches between state checks
+constexpr int CRB_CANDIDATES = 2048;  // candidates per block to start with
+constexpr int CRB_CHUNK = 16;          // greedy-step launches between state checks
 
 // Device memory of one plan.  A block that a buffer gives back is kept and
 // handed to a later buffer of the same plan, with no hipFree/hipMalloc (both
@@ -749,10 +749,23 @@ isdf_status crb_select(isdf_plan_s* pl, const SelDomain& X, const double* phi_ba
     if ((e = launch_sel_init(s, Dd, tdom.as<int32_t>(), 0, B.ntiles, dC.as<double>(), tmaxb.as<double>(),
                              tidxb.as<int32_t>(), tau)) != ISDF_OK)
       return e;
-    // step k reads copy k & 1 of the diagonal and tile maxima, writes the other
-    double* dd[2] = {dC.as<double>(), dC2.as<double>()};
-    double* tm[2] = {tmaxb.as<double>(), tmaxb.as<double>() + B.ntiles};
-    int32_t* ti[2] = {tidxb.as<int32_t>(), tidxb.as<int32_t>() + B.ntiles};
+    CrbBlock cb{};
+    cb.R = RCC.as<double>();
+    cb.Lb = LCb.as<double>();
+    cb.d[0] = dC.as<double>();
+    cb.d[1] = dC2.as<double>();
+    cb.t[0] = tmaxb.as<double>();
+    cb.t[1] = tmaxb.as<double>() + B.ntiles;
+    cb.i[0] = tidxb.as<int32_t>();
+    cb.i[1] = tidxb.as<int32_t>() + B.ntiles;
+    cb.st = Sd;
+    cb.pivC = pivC.as<int32_t>();
+    cb.nc = nc;
+    cb.nb = nb;
+    cb.tau = tau;
+    cb.eps = eps;
+    cb.dstop = dstop;
+    cb.d0max = d0max;
     // Steps go out in chunks; after each chunk the state is copied to pinned
     // memory, and the copy of the chunk before is checked while this one
     // runs: a block that stopped early (most do, at the theta bound) costs at
@@ -764,12 +777,8 @@ isdf_status crb_select(isdf_plan_s* pl, const SelDomain& X, const double* phi_ba
     for (int k0 = 0, chunk = 0; k0 <= nb; k0 += CRB_CHUNK, ++chunk) {
       const int k1 = std::min(nb + 1, k0 + CRB_CHUNK);
       for (int k = k0; k < k1; ++k) {
-        const int c = k & 1;
         ProfScope ps(pl, ISDF_K_SELECT_COLUMN, 8.0 * nc * (k + 4.0) + 12.0 * B.ntiles, 2.0 * nc * k);
-        if ((e = launch_crb_step(s, k, nb, nc, RCC.as<double>(), LCb.as<double>(), dd[c], dd[c ^ 1], tm[c],
-                                 ti[c], tm[c ^ 1], ti[c ^ 1], Sd, pivC.as<int32_t>(), tau, eps, dstop,
-                                 d0max)) != ISDF_OK)
-          return e;
+        if ((e = launch_crb_step(s, k, cb)) != ISDF_OK) return e;
       }
       if (k1 > nb) break;
       const int slot = chunk & 1;

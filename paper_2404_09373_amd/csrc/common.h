@@ -190,10 +190,22 @@ struct CrbInfo {
 };
 isdf_status launch_crb_candidates(hipStream_t s, const double* d, int n, int T, int32_t* cidx,
                                   double* dC, CrbInfo* info);
-isdf_status launch_crb_step(hipStream_t s, int k, int nb, int nc, const double* R, double* Lb,
-                            const double* dcur, double* dnext, const double* tcur, const int32_t* icur,
-                            double* tnext, int32_t* inext, SelState* st, int32_t* pivC, double tau,
-                            double eps, double dstop, double d0max);
+// A block of greedy steps on the candidates, passed by value to every step:
+// step k reads copy k & 1 of the diagonal and tile maxima and writes the
+// other.  (One struct argument keeps the launch cost down: the steps are
+// bound by it.)
+struct CrbBlock {
+  const double* R;  // residual R_CC, lower, nc x nc
+  double* Lb;       // the block's candidate factor columns, nc x nb
+  double* d[2];
+  double* t[2];
+  int32_t* i[2];
+  SelState* st;
+  int32_t* pivC;  // block pivots, candidate positions
+  int32_t nc, nb;
+  double tau, eps, dstop, d0max;
+};
+isdf_status launch_crb_step(hipStream_t s, int k, const CrbBlock& b);
 isdf_status launch_crb_gather(hipStream_t s, const double* src, int64_t lds, const int32_t* idx, int nr,
                               int nc, double* dst, int64_t ldd);
 isdf_status launch_crb_trsm_block(hipStream_t s, double* X, int64_t ldx, int n, const double* U,

@@ -174,17 +174,25 @@ isdf_status launch_crb_candidates(hipStream_t s, const double* d, int n, int T, 
 // Stops as the separate pick does (count, eps, block threshold); workgroup 0
 // records the state.
 __global__ void __launch_bounds__(256)
-crb_step_kernel(int k, int nb, int nc, const double* __restrict__ R, double* __restrict__ Lb,
-                const double* __restrict__ dcur, double* __restrict__ dnext,
-                const double* __restrict__ tcur, const int32_t* __restrict__ icur,
-                double* __restrict__ tnext, int32_t* __restrict__ inext, SelState* __restrict__ st,
-                int32_t* __restrict__ pivC, double tau, double eps, double dstop, double d0max) {
+crb_step_kernel(int k, CrbBlock blk) {
   __shared__ double s_red[4];
   __shared__ int s_redi[4];
   __shared__ int s_cand;
   __shared__ double red[4][64];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  SelState* __restrict__ st = blk.st;
   if (st->done) return;
+  const int nb = blk.nb, nc = blk.nc, c = k & 1;
+  const double* __restrict__ R = blk.R;
+  double* __restrict__ Lb = blk.Lb;
+  const double* __restrict__ dcur = blk.d[c];
+  double* __restrict__ dnext = blk.d[c ^ 1];
+  const double* __restrict__ tcur = blk.t[c];
+  const int32_t* __restrict__ icur = blk.i[c];
+  double* __restrict__ tnext = blk.t[c ^ 1];
+  int32_t* __restrict__ inext = blk.i[c ^ 1];
+  int32_t* __restrict__ pivC = blk.pivC;
+  const double tau = blk.tau, eps = blk.eps, dstop = blk.dstop, d0max = blk.d0max;
   const int ntiles = (nc + SEL_TILE - 1) / SEL_TILE;
   // ---- pick
   int reason = 0, p = INT_MAX;
@@ -285,13 +293,9 @@ crb_step_kernel(int k, int nb, int nc, const double* __restrict__ R, double* __r
   }
 }
 
-isdf_status launch_crb_step(hipStream_t s, int k, int nb, int nc, const double* R, double* Lb,
-                            const double* dcur, double* dnext, const double* tcur, const int32_t* icur,
-                            double* tnext, int32_t* inext, SelState* st, int32_t* pivC, double tau,
-                            double eps, double dstop, double d0max) {
-  const int ntiles = (nc + SEL_TILE - 1) / SEL_TILE;
-  hipLaunchKernelGGL(crb_step_kernel, dim3(ntiles), dim3(256), 0, s, k, nb, nc, R, Lb, dcur, dnext, tcur,
-                     icur, tnext, inext, st, pivC, tau, eps, dstop, d0max);
+isdf_status launch_crb_step(hipStream_t s, int k, const CrbBlock& b) {
+  const int ntiles = (b.nc + SEL_TILE - 1) / SEL_TILE;
+  hipLaunchKernelGGL(crb_step_kernel, dim3(ntiles), dim3(256), 0, s, k, b);
   ISDF_HIP_TRY(hipGetLastError());
   return ISDF_OK;
 }
