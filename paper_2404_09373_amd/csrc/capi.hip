@@ -374,6 +374,25 @@ struct ProfScope {
   ~ProfScope() { finish(); }
 };
 
+// Events around the three passes of one transform call, one record per pass
+// (a pass is one kernel launch) when the FFT family is being timed.
+struct FftEvents {
+  isdf_plan_s* pl;
+  hipEvent_t e[6] = {};
+  bool on = false;
+  explicit FftEvents(isdf_plan_s* p) : pl(p) {
+    if (!((pl->prof >> ISDF_K_FFT) & 1)) return;
+    on = true;
+    for (auto& x : e)
+      if (!(x = prof_event(pl))) on = false;
+  }
+  hipEvent_t* ev() { return on ? e : nullptr; }
+  void commit(std::array<double, 3> bytes) {
+    if (!on) return;
+    for (int p = 0; p < 3; ++p) pl->pending.push_back({ISDF_K_FFT, e[2 * p], e[2 * p + 1], bytes[p], 0.0});
+  }
+};
+
 // Accumulate the finished records (call after the stream has synchronised).
 void prof_collect(isdf_plan_s* pl) {
   for (auto& r : pl->pending) {
@@ -1590,18 +1609,22 @@ isdf_status run_coulomb(isdf_plan_s* pl, isdf_fit_s* f) {
       const int64_t poff = fpair_off[batch_no++];
       if (fft_forward_pruned_supported(hp.grid[lp])) {
         int max_yz = 0, max_z = 0;
-        double touched = 0.0;
+        double touched[3] = {0.0, 0.0, 0.0};  // complex points read + written per pass
+        const int* g = hp.grid[lp];
         for (int b = 0; b < npairs; ++b) {
           const FwdPair& P = fpairs[poff + b];
           max_yz = std::max(max_yz, P.box[4] * P.box[5]);
           max_z = std::max(max_z, P.box[5]);
-          touched += (double)hp.grid[lp][0] * (2.0 * P.box[4] * P.box[5] + 2.0 * hp.grid[lp][1] * P.box[5]) +
-                     (double)hp.grid[lp][0] * hp.grid[lp][1] * (P.box[5] + hp.grid[lp][2]);
+          touched[0] += 2.0 * g[0] * P.box[4] * P.box[5];
+          touched[1] += 2.0 * g[0] * g[1] * P.box[5];
+          touched[2] += (double)g[0] * g[1] * (P.box[5] + g[2]);
         }
-        ProfScope ps(pl, ISDF_K_FFT, 16.0 * touched, 0.0);
+        FftEvents fe(pl);
         if ((st = fft_forward_pruned(s, zf.as<double>(), d_fpairs.as<FwdPair>() + poff,
-                                     d_fcols.as<FwdCol>(), npairs, hp.grid[lp], max_yz, max_z)) != ISDF_OK)
+                                     d_fcols.as<FwdCol>(), npairs, hp.grid[lp], max_yz, max_z, fe.ev())) !=
+            ISDF_OK)
           return st;
+        fe.commit({16.0 * touched[0], 16.0 * touched[1], 16.0 * touched[2]});
       } else {
         int max_n = 0;
         for (int64_t c = b0; c < b0 + ncols; ++c) max_n = std::max(max_n, scat[c].n);
@@ -1617,10 +1640,12 @@ isdf_status run_coulomb(isdf_plan_s* pl, isdf_fit_s* f) {
         double* vout = V.as<double>() + voff + (b0 - ch.c0) * ng;
         bool fused = false;
         {  // Poisson step, inverse transform and planar split in three passes
-          ProfScope ps(pl, ISDF_K_FFT, 3.0 * 32.0 * (double)ng * npairs, 0.0);
+          FftEvents fe(pl);
           if ((st = fft_poisson_inverse(s, zf.as<double>(), hp.grid[lp], zc.as<double>(), hp.grid[l],
-                                        npairs, pl->recip, vout, ncols, &fused)) != ISDF_OK)
+                                        npairs, pl->recip, vout, ncols, &fused, fe.ev())) != ISDF_OK)
             return st;
+          const double pass_bytes = 32.0 * (double)ng * npairs;
+          if (fused) fe.commit({pass_bytes, pass_bytes, pass_bytes});
         }
         if (!fused) {
           if ((st = launch_poisson_restrict(s, zf.as<double>(), hp.grid[lp], zc.as<double>(),

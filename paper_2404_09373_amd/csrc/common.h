@@ -256,9 +256,11 @@ struct FwdPair {
 };
 bool fft_forward_pruned_supported(const int g[3]);
 // Forward transforms of npairs column pairs on grid g into z (pair b at
-// b * N_g); max_yz / max_z bound the pairs' box lines and planes.
+// b * N_g); max_yz / max_z bound the pairs' box lines and planes.  ev (6
+// events or null): ev[2 p] and ev[2 p + 1] are recorded around pass p.
 isdf_status fft_forward_pruned(hipStream_t s, double* z, const FwdPair* pairs, const FwdCol* cols,
-                               int npairs, const int g[3], int max_yz, int max_z);
+                               int npairs, const int g[3], int max_yz, int max_z,
+                               hipEvent_t* ev = nullptr);
 
 struct ScatterCol {
   const double* src;
@@ -272,10 +274,11 @@ isdf_status launch_scatter_cols(hipStream_t s, const ScatterCol* cols, int ncols
 isdf_status launch_split_planar(hipStream_t s, const double* z, int64_t ng, int ncols, double* V);
 // Poisson step from the spectrum on grid gf, inverse transform on grid gc
 // and planar split into V in three passes (*done = false: sizes without
-// compiled passes, nothing launched; use the three separate steps).
+// compiled passes, nothing launched; use the three separate steps).  ev as
+// for fft_forward_pruned.
 isdf_status fft_poisson_inverse(hipStream_t s, const double* zf, const int gf[3], double* zc,
                                 const int gc[3], int npairs, const double B[9], double* V,
-                                int ncols, bool* done);
+                                int ncols, bool* done, hipEvent_t* ev = nullptr);
 isdf_status launch_symmetrize_w(hipStream_t s, double* W, int64_t nmu, const int8_t* lev);
 isdf_status launch_add(hipStream_t s, const double* a, const double* b, double* c, int64_t n);
 isdf_status launch_trace_dot(hipStream_t s, const double* a, const double* b, int64_t n,
@@ -301,6 +304,12 @@ isdf_status gemm_mixed(hipStream_t s, int epi, int splits, const MixedProblem& p
 isdf_status gemm_mixed_grouped(hipStream_t s, int epi, int splits, const MixedProblem* d_probs,
                                int nprob, int total_tiles, int tag = 4);
 int mixed_tiles(int M, int N);
+// Single mixed products (not Theta, not lower) with at least this many
+// 64 x 128 tiles run on the wide-tile kernel.
+#ifndef MIXED_WIDE_MIN_TILES
+#define MIXED_WIDE_MIN_TILES 256
+#endif
+int mixed_tiles_wide(int M, int N);
 // planes[p][o][k] (ld ldd, plane stride `plane`) of scale * src[o so + ks sk],
 // ks = kidx ? kidx[k] : k (kidx[k] < 0 gives 0)
 isdf_status launch_split_bf16(hipStream_t s, const double* src, int64_t so, int64_t sk,

@@ -550,7 +550,7 @@ isdf_status launch_split_planar(hipStream_t s, const double* z, int64_t ng, int 
 // (x lines of 8 per workgroup need gc[0] divisible by 8).
 isdf_status fft_poisson_inverse(hipStream_t s, const double* zf, const int gf[3], double* zc,
                                 const int gc[3], int npairs, const double B[9], double* V,
-                                int ncols, bool* done) {
+                                int ncols, bool* done, hipEvent_t* ev) {
   *done = false;
   auto fixed = [](int n) {
     return n == 24 || n == 32 || n == 40 || n == 48 || n == 64 || n == 80 || n == 96 || n == 128 ||
@@ -573,8 +573,14 @@ isdf_status fft_poisson_inverse(hipStream_t s, const double* zf, const int gf[3]
     set_error("fft: twiddle allocation failed");
     return ISDF_E_NOMEM;
   }
+  auto mark = [&](int i) -> isdf_status {
+    if (ev) ISDF_HIP_TRY(hipEventRecord(ev[i], s));
+    return ISDF_OK;
+  };
+  isdf_status st;
   // x pass from the fine spectrum
   const int64_t gx = ((int64_t)gc[1] * gc[2] * npairs + 7) / 8;
+  if ((st = mark(0)) != ISDF_OK) return st;
   switch (gc[0]) {
     case 24: launch_poisson_x<24>(s, z, npairs, gc, tw0, f, a, gx); break;
     case 32: launch_poisson_x<32>(s, z, npairs, gc, tw0, f, a, gx); break;
@@ -587,7 +593,9 @@ isdf_status fft_poisson_inverse(hipStream_t s, const double* zf, const int gf[3]
     default: launch_poisson_x<160>(s, z, npairs, gc, tw0, f, a, gx); break;
   }
   ISDF_HIP_TRY(hipGetLastError());
+  if ((st = mark(1)) != ISDF_OK) return st;
   // y pass as usual
+  if ((st = mark(2)) != ISDF_OK) return st;
   {
     const int lpw = (gc[1] <= 32 && gc[0] % 16 == 0) ? 16 : 8;
     const int64_t groups = (int64_t)(gc[0] / lpw) * gc[2] * npairs;
@@ -597,8 +605,10 @@ isdf_status fft_poisson_inverse(hipStream_t s, const double* zf, const int gf[3]
     }
     ISDF_HIP_TRY(hipGetLastError());
   }
+  if ((st = mark(3)) != ISDF_OK) return st;
   // z pass into the planar potentials
   const int64_t gz = (int64_t)(gc[0] / 8) * gc[1] * npairs;
+  if ((st = mark(4)) != ISDF_OK) return st;
   switch (gc[2]) {
     case 24: launch_planar_z<24>(s, z, npairs, gc, tw2, V, ncols, gz); break;
     case 32: launch_planar_z<32>(s, z, npairs, gc, tw2, V, ncols, gz); break;
@@ -611,6 +621,7 @@ isdf_status fft_poisson_inverse(hipStream_t s, const double* zf, const int gf[3]
     default: launch_planar_z<160>(s, z, npairs, gc, tw2, V, ncols, gz); break;
   }
   ISDF_HIP_TRY(hipGetLastError());
+  if ((st = mark(5)) != ISDF_OK) return st;
   *done = true;
   return ISDF_OK;
 }
@@ -750,7 +761,7 @@ bool fft_forward_pruned_supported(const int g[3]) {
 }
 
 isdf_status fft_forward_pruned(hipStream_t s, double* zr, const FwdPair* pairs, const FwdCol* cols,
-                               int npairs, const int g[3], int max_yz, int max_z) {
+                               int npairs, const int g[3], int max_yz, int max_z, hipEvent_t* ev) {
   if (npairs <= 0) return ISDF_OK;
   if (!fft_forward_pruned_supported(g)) {
     set_error("fft: pruned forward transform needs compiled line lengths");
@@ -764,12 +775,18 @@ isdf_status fft_forward_pruned(hipStream_t s, double* zr, const FwdPair* pairs, 
     set_error("fft: twiddle allocation failed");
     return ISDF_E_NOMEM;
   }
+  if (ev) ISDF_HIP_TRY(hipEventRecord(ev[0], s));
   fwd_pass<0>(s, z, pairs, cols, npairs, g, tw0, g[0], (max_yz + 7) / 8);
   ISDF_HIP_TRY(hipGetLastError());
+  if (ev) ISDF_HIP_TRY(hipEventRecord(ev[1], s));
+  if (ev) ISDF_HIP_TRY(hipEventRecord(ev[2], s));
   fwd_pass<1>(s, z, pairs, cols, npairs, g, tw1, g[1], (g[0] / 8) * max_z);
   ISDF_HIP_TRY(hipGetLastError());
+  if (ev) ISDF_HIP_TRY(hipEventRecord(ev[3], s));
+  if (ev) ISDF_HIP_TRY(hipEventRecord(ev[4], s));
   fwd_pass<2>(s, z, pairs, cols, npairs, g, tw2, g[2], (g[0] / 8) * g[1]);
   ISDF_HIP_TRY(hipGetLastError());
+  if (ev) ISDF_HIP_TRY(hipEventRecord(ev[5], s));
   return ISDF_OK;
 }
 

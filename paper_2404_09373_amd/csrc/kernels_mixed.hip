@@ -33,6 +33,25 @@ typedef double d4m __attribute__((ext_vector_type(4)));
 namespace {
 constexpr int BM = 64, BN = 64, BK = 32, KFLUSH = 256;
 
+// Workgroups go round-robin over the 8 XCDs (each with its own L2): dispatch
+// slot b (XCD b % 8) is mapped to a contiguous range of tiles, and within a
+// problem the dimension with fewer tiles runs fastest, so the tiles an XCD
+// has in flight share blocks of the larger operand in its L2.
+constexpr int NXCD = 8;
+__device__ inline int xcd_tile(int b, int nb) {
+  const int x = b % NXCD, q = b / NXCD, per = nb / NXCD, rem = nb % NXCD;
+  return (x < rem ? x * (per + 1) : rem * (per + 1) + (x - rem) * per) + q;
+}
+__device__ inline void tile_coords(int local, int tilesM, int tilesN, int* tm, int* tn) {
+  if (tilesN <= tilesM) {
+    *tn = local % tilesN;
+    *tm = local / tilesN;
+  } else {
+    *tm = local % tilesM;
+    *tn = local / tilesM;
+  }
+}
+
 __device__ inline const MixedProblem* find_mixed(const MixedProblem* probs, int nprob, int tile) {
   int lo = 0, hi = nprob - 1;
   while (lo < hi) {
@@ -46,11 +65,11 @@ __device__ inline const MixedProblem* find_mixed(const MixedProblem* probs, int 
 template <int EPI, int S, int TAG>
 __global__ void __launch_bounds__(256)
 gemm_mixed_kernel(MixedProblem single, const MixedProblem* __restrict__ probs, int nprob) {
-  const MixedProblem* pp = probs ? find_mixed(probs, nprob, blockIdx.x) : &single;
+  const int tile = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+  const MixedProblem* pp = probs ? find_mixed(probs, nprob, tile) : &single;
   const MixedProblem p = *pp;
-  const int tilesM = (p.M + BM - 1) / BM;
-  const int local = (int)blockIdx.x - p.tile_start;
-  const int tm = local % tilesM, tn = local / tilesM;
+  int tm, tn;
+  tile_coords(tile - p.tile_start, (p.M + BM - 1) / BM, (p.N + BN - 1) / BN, &tm, &tn);
   const int m0 = tm * BM, n0 = tn * BN;
   if (n0 >= p.N) return;
   if (p.lower && m0 + BM <= n0) return;
@@ -77,9 +96,16 @@ gemm_mixed_kernel(MixedProblem single, const MixedProblem* __restrict__ probs, i
   // each thread stages one 16-byte chunk (8 bf16 along k) per plane and operand
   const int lr = tid >> 2;          // row within the tile (0..63)
   const int lk = (tid & 3) * 8;     // k offset within the chunk
+  const bool tile_in = m0 + BM <= p.M && n0 + BN <= p.N;
   for (int k0 = 0; k0 < p.K; k0 += BK) {
     bf8v ra[S], rb[S];
-    {
+    if (tile_in && k0 + BK <= p.K) {  // interior: no bounds tests (see the wide kernel)
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        ra[s] = *reinterpret_cast<const bf8v*>(p.A + s * p.plane_a + (int64_t)(m0 + lr) * p.lda + k0 + lk);
+        rb[s] = *reinterpret_cast<const bf8v*>(p.B + s * p.plane_b + (int64_t)(n0 + lr) * p.ldb + k0 + lk);
+      }
+    } else {
       const int gm = m0 + lr, gk = k0 + lk;
 #pragma unroll
       for (int s = 0; s < S; ++s) {
@@ -196,6 +222,199 @@ gemm_mixed_kernel(MixedProblem single, const MixedProblem* __restrict__ probs, i
 
 int mixed_tiles(int M, int N) { return ((M + BM - 1) / BM) * ((N + BN - 1) / BN); }
 
+// ---------------------------------------------------------- wide products
+// The same split products for single AXPBY / HADAMARD problems with many
+// tiles, on 64 x 128 tiles: four waves of 32 x 64 (2 x 4 MFMA tiles), so a
+// k chunk costs 6 S operand reads from LDS for 8 S (S + 1) / 2 MFMAs.  Two
+// LDS stages: chunk c + 1 is loaded into registers during chunk c's MFMAs
+// and stored into the other stage, one barrier per chunk.  LDS rows are 64
+// bytes (four 16-byte units of 8 values of k) without padding; unit u of row
+// r sits at position u ^ ((r >> 1) & 3), so that every group of 8 lanes
+// touches 8 distinct 16-byte bank groups both when staging (2 rows x 4
+// units) and when reading fragments (8 rows, one unit).
+namespace {
+constexpr int WBM = 64, WBN = 128;
+__device__ inline int swz(int r, int u) { return r * BK + ((u ^ ((r >> 1) & 3)) << 3); }
+}  // namespace
+
+int mixed_tiles_wide(int M, int N) { return ((M + WBM - 1) / WBM) * ((N + WBN - 1) / WBN); }
+
+template <int EPI, int S, int TAG>
+__global__ void __launch_bounds__(256, 2)
+gemm_mixed_wide_kernel(MixedProblem p) {
+  int tm, tn;
+  tile_coords(xcd_tile((int)blockIdx.x, (int)gridDim.x), (p.M + WBM - 1) / WBM, (p.N + WBN - 1) / WBN, &tm,
+              &tn);
+  const int m0 = tm * WBM, n0 = tn * WBN;
+
+  __shared__ __attribute__((aligned(16))) __bf16 As[2][S][WBM * BK];
+  __shared__ __attribute__((aligned(16))) __bf16 Bs[2][S][WBN * BK];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave & 1, wn = wave >> 1;  // wave tile rows wm*32.., columns wn*64..
+
+  f4v hi[2][4], lo[2][4];
+  d4m acc[2][4];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      hi[a][b] = lo[a][b] = f4v{0.f, 0.f, 0.f, 0.f};
+      acc[a][b] = d4m{0.0, 0.0, 0.0, 0.0};
+    }
+
+  // staging: A rows lr (64 rows), B rows lr and lr + 64; unit lu of 8 k values
+  const int lr = tid >> 2, lu = tid & 3;
+  bf8v ra[S], rb[S][2];
+  auto fetch = [&](const __bf16* base, int64_t plane, int64_t ld, int rows, int r, int gk) -> bf8v {
+    bf8v v;
+    if (r < rows && gk + 8 <= p.K) {
+      v = *reinterpret_cast<const bf8v*>(base + plane + (int64_t)r * ld + gk);
+    } else {
+#pragma unroll
+      for (int t = 0; t < 8; ++t)
+        v[t] = (r < rows && gk + t < p.K) ? base[plane + (int64_t)r * ld + gk + t] : (__bf16)0.0f;
+    }
+    return v;
+  };
+  // Interior chunks of interior tiles (a wave-uniform test) load without any
+  // bounds test: a guarded load per value would make every load wait for
+  // completion at its branch, and the next chunk would no longer be in
+  // flight during the MFMAs.
+  const bool tile_in = m0 + WBM <= p.M && n0 + WBN <= p.N;
+  const __bf16* pa = p.A + (int64_t)(m0 + lr) * p.lda + lu * 8;
+  const __bf16* pb0 = p.B + (int64_t)(n0 + lr) * p.ldb + lu * 8;
+  const __bf16* pb1 = pb0 + (int64_t)64 * p.ldb;
+  auto load = [&](int k0) {
+    if (tile_in && k0 + BK <= p.K) {
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        ra[s] = *reinterpret_cast<const bf8v*>(pa + s * p.plane_a + k0);
+        rb[s][0] = *reinterpret_cast<const bf8v*>(pb0 + s * p.plane_b + k0);
+        rb[s][1] = *reinterpret_cast<const bf8v*>(pb1 + s * p.plane_b + k0);
+      }
+    } else {
+      const int gk = k0 + lu * 8;
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        ra[s] = fetch(p.A, s * p.plane_a, p.lda, p.M, m0 + lr, gk);
+        rb[s][0] = fetch(p.B, s * p.plane_b, p.ldb, p.N, n0 + lr, gk);
+        rb[s][1] = fetch(p.B, s * p.plane_b, p.ldb, p.N, n0 + lr + 64, gk);
+      }
+    }
+  };
+  auto store = [&](int st) {
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      *reinterpret_cast<bf8v*>(&As[st][s][swz(lr, lu)]) = ra[s];
+      *reinterpret_cast<bf8v*>(&Bs[st][s][swz(lr, lu)]) = rb[s][0];
+      *reinterpret_cast<bf8v*>(&Bs[st][s][swz(lr + 64, lu)]) = rb[s][1];
+    }
+  };
+  load(0);
+  store(0);
+  __syncthreads();
+  const int fu = lane >> 4;  // fragment unit: k = 8 fu .. 8 fu + 7
+  for (int k0 = 0, st = 0; k0 < p.K; k0 += BK, st ^= 1) {
+    const bool more = k0 + BK < p.K;
+    if (more) load(k0 + BK);  // in flight during this chunk's MFMAs
+    // planes 0 and 1 first; plane 2 (x6) then reuses plane 1's registers
+    bf8v x0[4], y0[2], x1[4], y1[2];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      x0[t] = *reinterpret_cast<const bf8v*>(&Bs[st][0][swz(wn * 64 + t * 16 + (lane & 15), fu)]);
+      x1[t] = *reinterpret_cast<const bf8v*>(&Bs[st][1][swz(wn * 64 + t * 16 + (lane & 15), fu)]);
+    }
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      y0[t] = *reinterpret_cast<const bf8v*>(&As[st][0][swz(wm * 32 + t * 16 + (lane & 15), fu)]);
+      y1[t] = *reinterpret_cast<const bf8v*>(&As[st][1][swz(wm * 32 + t * 16 + (lane & 15), fu)]);
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        hi[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x0[b], y0[a], hi[a][b], 0, 0, 0);
+        f4v l = lo[a][b];
+        l = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x0[b], y1[a], l, 0, 0, 0);
+        l = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x1[b], y0[a], l, 0, 0, 0);
+        if (S == 3) l = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x1[b], y1[a], l, 0, 0, 0);
+        lo[a][b] = l;
+      }
+    if constexpr (S == 3) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        x1[t] = *reinterpret_cast<const bf8v*>(&Bs[st][2][swz(wn * 64 + t * 16 + (lane & 15), fu)]);
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+        y1[t] = *reinterpret_cast<const bf8v*>(&As[st][2][swz(wm * 32 + t * 16 + (lane & 15), fu)]);
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          f4v l = lo[a][b];
+          l = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x0[b], y1[a], l, 0, 0, 0);
+          l = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x1[b], y0[a], l, 0, 0, 0);
+          lo[a][b] = l;
+        }
+    }
+    if (((k0 + BK) % KFLUSH) == 0 || !more) {
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            acc[a][b][v] += (double)hi[a][b][v] + (double)lo[a][b][v];
+            hi[a][b][v] = lo[a][b][v] = 0.f;
+          }
+    }
+    if (more) store(st ^ 1);  // the other stage: its last readers passed the previous barrier
+    __syncthreads();
+  }
+  // lane holds C(m0 + wm*32 + a*16 + lane%16, n0 + wn*64 + b*16 + 4(lane/16) + v)
+#pragma unroll
+  for (int a = 0; a < 2; ++a) {
+    const int gm = m0 + wm * 32 + a * 16 + (lane & 15);
+    if (gm >= p.M) continue;
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int gn = n0 + wn * 64 + b * 16 + 4 * (lane >> 4) + v;
+        if (gn >= p.N) continue;
+        double* cp = p.C + (int64_t)gm + (int64_t)gn * p.ldc;
+        const double x = acc[a][b][v];
+        double y;
+        if (EPI == EPI_HADAMARD)
+          y = p.alpha * x * p.E[(int64_t)gm + (int64_t)gn * p.lde];
+        else
+          y = p.alpha * x;
+        if (p.beta != 0.0) y += p.beta * *cp;
+        *cp = y;
+      }
+  }
+}
+
+template <int S, int TAG>
+static void launch_wide_st(hipStream_t s, int epi, const MixedProblem& p, int tiles) {
+  if (epi == EPI_HADAMARD)
+    hipLaunchKernelGGL((gemm_mixed_wide_kernel<EPI_HADAMARD, S, TAG>), dim3(tiles), dim3(256), 0, s, p);
+  else
+    hipLaunchKernelGGL((gemm_mixed_wide_kernel<EPI_AXPBY, S, TAG>), dim3(tiles), dim3(256), 0, s, p);
+}
+
+template <int S>
+static void launch_wide_s(hipStream_t s, int epi, int tag, const MixedProblem& p, int tiles) {
+  switch (tag) {
+    case 2: launch_wide_st<S, 2>(s, epi, p, tiles); break;
+    case 3: launch_wide_st<S, 3>(s, epi, p, tiles); break;
+    default: launch_wide_st<S, 4>(s, epi, p, tiles); break;
+  }
+}
+
 template <int S, int TAG>
 static void launch_st(hipStream_t s, int epi, const MixedProblem& single, const MixedProblem* probs,
                       int nprob, int tiles) {
@@ -224,6 +443,14 @@ isdf_status gemm_mixed(hipStream_t s, int epi, int splits, const MixedProblem& p
   if (p.M <= 0 || p.N <= 0) return ISDF_OK;
   MixedProblem q = p;
   q.tile_start = 0;
+  // products with enough 64 x 128 tiles to fill the chip take the wide kernel
+  if (epi != EPI_THETA && !p.lower && mixed_tiles_wide(p.M, p.N) >= MIXED_WIDE_MIN_TILES) {
+    const int tiles = mixed_tiles_wide(p.M, p.N);
+    if (splits == 2) launch_wide_s<2>(s, epi, tag, q, tiles);
+    else launch_wide_s<3>(s, epi, tag, q, tiles);
+    ISDF_HIP_TRY(hipGetLastError());
+    return ISDF_OK;
+  }
   const int tiles = mixed_tiles(p.M, p.N);
   if (splits == 2) launch_s<2>(s, epi, tag, q, nullptr, 1, tiles);
   else launch_s<3>(s, epi, tag, q, nullptr, 1, tiles);
