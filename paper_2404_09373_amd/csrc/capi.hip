@@ -43,6 +43,7 @@ constexpr int RL_MIN_PIVOTS = 128;  // blocked selection of a lone domain above 
 constexpr int CRB_BLOCK = 512;      // most pivots per block
 constexpr int CRB_CANDIDATES = 2048;  // candidates per block to start with
 constexpr int CRB_CHUNK = 16;          // greedy-step launches between state checks
+constexpr int KSPLIT = 8;              // k ranges of the mixed exchange's final product
 
 // Device memory of one plan.  A block that a buffer gives back is kept and
 // handed to a later buffer of the same plan, with no hipFree/hipMalloc (both
@@ -317,9 +318,14 @@ struct isdf_fit_s {
   DevBuf xrows, XL, XN, XG, theta, F, W, lev;
   // exchange workspace
   DevBuf EG, EL, QGG, QGL, QLL, Y1, Y2, partial, ex_out;
-  // mixed precision: fit-time operand planes and per-exchange planes
-  Planes xg_row, xl_row, xl_col, xn_col;
-  Planes Dp, EGp, ELp, QGGp, QGLp, QGLTp, QLLp, Y1p, Y2p;
+  // mixed precision: fit-time operand planes and per-exchange planes.
+  // xln: row a = [X^L(:, a); X^N(:, a)] (k over 2 N_mu); Q1 = [Q_GG Q_GL] and
+  // Q2 = [Q_GL^T Q_LL] as A operands (rows mu, k over 2 N_mu); Y12: row a =
+  // [Y1(:, a); Y2(:, a)].  K = -(xln) (Y12)^T runs as KSPLIT partial products.
+  Planes xg_row, xl_row, xln;
+  Planes Dp, EGp, ELp, Q1, Q2, Y12;
+  DevBuf Kpart, d_yprobs, d_kprobs;
+  int ytiles = 0, ktiles = 0, kparts = 0;
   // factored density: D = C C^T for the energy
   DevBuf Docc;
   // captured exchange: replayed while (mode, operands, K) stay the same
@@ -2013,14 +2019,17 @@ isdf_status exchange_prepare(isdf_plan_s* plan, isdf_fit_s* fit, int n_occ) {
   const int64_t nmu = fit->nmu, N = plan->hp.n_basis;
   const int64_t ec = n_occ > 0 ? n_occ : N;  // columns of E_G, E_L
   isdf_status st;
+  const bool mixed = mixed_on(plan, ISDF_MIX_EXCHANGE);
   if (!fit->Y1.p) {
     if ((st = fit->Y1.alloc(sizeof(double) * nmu * N)) != ISDF_OK) return st;
     if ((st = fit->Y2.alloc(sizeof(double) * nmu * N)) != ISDF_OK) return st;
+    if ((st = fit->partial.alloc(sizeof(double) * 1024)) != ISDF_OK) return st;
+    if ((st = fit->ex_out.alloc(sizeof(double))) != ISDF_OK) return st;
+  }
+  if (!mixed && !fit->QGG.p) {  // the mixed path writes Q straight into split planes
     if ((st = fit->QGG.alloc(sizeof(double) * nmu * nmu)) != ISDF_OK) return st;
     if ((st = fit->QGL.alloc(sizeof(double) * nmu * nmu)) != ISDF_OK) return st;
     if ((st = fit->QLL.alloc(sizeof(double) * nmu * nmu)) != ISDF_OK) return st;
-    if ((st = fit->partial.alloc(sizeof(double) * 1024)) != ISDF_OK) return st;
-    if ((st = fit->ex_out.alloc(sizeof(double))) != ISDF_OK) return st;
   }
   if (fit->EG.bytes < sizeof(double) * nmu * ec) {
     if ((st = fit->EG.alloc(sizeof(double) * nmu * ec)) != ISDF_OK) return st;
@@ -2028,27 +2037,72 @@ isdf_status exchange_prepare(isdf_plan_s* plan, isdf_fit_s* fit, int n_occ) {
   }
   if (n_occ > 0 && !fit->Docc.p)
     if ((st = fit->Docc.alloc(sizeof(double) * N * N)) != ISDF_OK) return st;
-  if (mixed_on(plan, ISDF_MIX_EXCHANGE)) {
+  if (mixed) {
     const int S = mixed_splits(plan);
     const int m = (int)nmu, n = (int)N;
     hipStream_t s = plan->stream;
-    if (!fit->xg_row.buf.p) {  // fit-time operands, split once
+    if (!fit->xg_row.buf.p) {  // fit-time operands and problem tables, built once
       if ((st = make_planes(s, S, fit->XG.as<double>(), 1, nmu, nullptr, m, n, fit->xg_row)) != ISDF_OK)
         return st;
       if ((st = make_planes(s, S, fit->XL.as<double>(), 1, nmu, nullptr, m, n, fit->xl_row)) != ISDF_OK)
         return st;
-      if ((st = make_planes(s, S, fit->XL.as<double>(), nmu, 1, nullptr, n, m, fit->xl_col)) != ISDF_OK)
+      if ((st = size_planes(S, n, 2 * m, fit->xln)) != ISDF_OK) return st;
+      fit->xln.rows = n;
+      fit->xln.cols = 2 * m;
+      fit->xln.ld = (2 * m + 7) / 8 * 8;
+      fit->xln.plane = (int64_t)n * fit->xln.ld;
+      __bf16* xb = static_cast<__bf16*>(fit->xln.buf.p);
+      if ((st = launch_split_bf16(s, fit->XL.as<double>(), nmu, 1, nullptr, n, m, S, xb, fit->xln.ld,
+                                  fit->xln.plane, 1.0)) != ISDF_OK)
         return st;
-      if ((st = make_planes(s, S, fit->XN.as<double>(), nmu, 1, nullptr, n, m, fit->xn_col)) != ISDF_OK)
+      if ((st = launch_split_bf16(s, fit->XN.as<double>(), nmu, 1, nullptr, n, m, S, xb + m, fit->xln.ld,
+                                  fit->xln.plane, 1.0)) != ISDF_OK)
         return st;
+      for (Planes* q : {&fit->Q1, &fit->Q2}) {
+        if ((st = size_planes(S, m, 2 * m, *q)) != ISDF_OK) return st;
+        q->rows = m;
+        q->cols = 2 * m;
+        q->ld = (2 * m + 7) / 8 * 8;
+        q->plane = (int64_t)m * q->ld;
+      }
+      if ((st = size_planes(S, n, 2 * m, fit->Y12)) != ISDF_OK) return st;
+      fit->Y12.rows = n;
+      fit->Y12.cols = 2 * m;
+      fit->Y12.ld = (2 * m + 7) / 8 * 8;
+      fit->Y12.plane = (int64_t)n * fit->Y12.ld;
+      // Y1 = Q1 xln^T and Y2 = Q2 xln^T, one grouped launch
+      std::vector<MixedProblem> yp(2);
+      int tiles = 0;
+      for (int i = 0; i < 2; ++i) {
+        yp[i] = mixed_problem(i == 0 ? fit->Q1 : fit->Q2, fit->xln, (i == 0 ? fit->Y1 : fit->Y2).as<double>(),
+                              nmu, m, n, 2 * m, 1.0, 0.0, nullptr, 0);
+        yp[i].tile_start = tiles;
+        tiles += mixed_tiles_wide(m, n);
+      }
+      fit->ytiles = tiles;
+      if ((st = upload(fit->d_yprobs, yp)) != ISDF_OK) return st;
+      // K = -(xln)(Y12)^T over k ranges of KSPLIT_CHUNK, partials summed in order
+      const int kc = std::max(32, (2 * m + KSPLIT - 1) / KSPLIT / 32 * 32);
+      std::vector<MixedProblem> kp;
+      tiles = 0;
+      for (int k0 = 0; k0 < 2 * m; k0 += kc) {
+        MixedProblem q = mixed_problem(fit->xln, fit->Y12, nullptr, N, n, n, std::min(kc, 2 * m - k0), -1.0,
+                                       0.0, nullptr, 0);
+        q.A += k0;
+        q.B += k0;
+        q.tile_start = tiles;
+        tiles += mixed_tiles(n, n);
+        kp.push_back(q);
+      }
+      fit->kparts = (int)kp.size();
+      fit->ktiles = tiles;
+      if ((st = fit->Kpart.alloc(sizeof(double) * (size_t)fit->kparts * n * n)) != ISDF_OK) return st;
+      for (int i = 0; i < fit->kparts; ++i) kp[i].C = fit->Kpart.as<double>() + (int64_t)i * n * n;
+      if ((st = upload(fit->d_kprobs, kp)) != ISDF_OK) return st;
     }
     if ((st = size_planes(S, n_occ > 0 ? n_occ : n, n, fit->Dp)) != ISDF_OK) return st;
     if ((st = size_planes(S, m, (int)ec, fit->EGp)) != ISDF_OK) return st;
     if ((st = size_planes(S, m, (int)ec, fit->ELp)) != ISDF_OK) return st;
-    for (Planes* q : {&fit->QGGp, &fit->QGLp, &fit->QGLTp, &fit->QLLp})
-      if ((st = size_planes(S, m, m, *q)) != ISDF_OK) return st;
-    if ((st = size_planes(S, n, m, fit->Y1p)) != ISDF_OK) return st;
-    if ((st = size_planes(S, n, m, fit->Y2p)) != ISDF_OK) return st;
   }
   return ISDF_OK;
 }
@@ -2101,24 +2155,48 @@ isdf_status exchange_enqueue(isdf_plan_s* plan, isdf_fit_s* fit, const double* i
     if ((st = mg(EPI_AXPBY, fit->xl_row, fit->Dp, EL, nmu, m, ec, n, 1.0, 0.0)) != ISDF_OK) return st;
     if ((st = make_planes(s, S, EG, 1, nmu, nullptr, m, ec, fit->EGp)) != ISDF_OK) return st;
     if ((st = make_planes(s, S, EL, 1, nmu, nullptr, m, ec, fit->ELp)) != ISDF_OK) return st;
-    // Q = P o W with P = E X^T (dense) or E_S E_T^T (factored)
+    // Q_ST = P_ST o W with P_ST = E_S B_T^T, B = E (factored) or X (dense).  The
+    // product C(i, j) = (B_T E_S^T)(i, j) W(i, j) = Q_ST(j, i) (W is symmetric)
+    // lands transposed, at row j and column i of the A operand, so each
+    // block of Q1 = [Q_GG Q_GL] and Q2 = [Q_GL^T Q_LL] is one product whose
+    // planes are written straight from the epilogue.
     const Planes& BG = n_occ > 0 ? fit->EGp : fit->xg_row;
     const Planes& BL = n_occ > 0 ? fit->ELp : fit->xl_row;
-    if ((st = mg(EPI_HADAMARD, fit->EGp, BG, QGG, nmu, m, m, ec, 1.0, 0.0)) != ISDF_OK) return st;
-    if ((st = mg(EPI_HADAMARD, fit->EGp, BL, QGL, nmu, m, m, ec, 1.0, 0.0)) != ISDF_OK) return st;
-    if ((st = mg(EPI_HADAMARD, fit->ELp, BL, QLL, nmu, m, m, ec, 1.0, 0.0)) != ISDF_OK) return st;
-    if ((st = make_planes(s, S, QGG, 1, nmu, nullptr, m, m, fit->QGGp)) != ISDF_OK) return st;
-    if ((st = make_planes(s, S, QGL, 1, nmu, nullptr, m, m, fit->QGLp)) != ISDF_OK) return st;
-    if ((st = make_planes(s, S, QGL, nmu, 1, nullptr, m, m, fit->QGLTp)) != ISDF_OK) return st;
-    if ((st = make_planes(s, S, QLL, 1, nmu, nullptr, m, m, fit->QLLp)) != ISDF_OK) return st;
-    if ((st = mg(EPI_AXPBY, fit->QGGp, fit->xl_col, Y1, nmu, m, n, m, 1.0, 0.0)) != ISDF_OK) return st;
-    if ((st = mg(EPI_AXPBY, fit->QGLp, fit->xn_col, Y1, nmu, m, n, m, 1.0, 1.0)) != ISDF_OK) return st;
-    if ((st = mg(EPI_AXPBY, fit->QGLTp, fit->xl_col, Y2, nmu, m, n, m, 1.0, 0.0)) != ISDF_OK) return st;
-    if ((st = mg(EPI_AXPBY, fit->QLLp, fit->xn_col, Y2, nmu, m, n, m, 1.0, 1.0)) != ISDF_OK) return st;
-    if ((st = make_planes(s, S, Y1, nmu, 1, nullptr, n, m, fit->Y1p)) != ISDF_OK) return st;
-    if ((st = make_planes(s, S, Y2, nmu, 1, nullptr, n, m, fit->Y2p)) != ISDF_OK) return st;
-    if ((st = mg(EPI_AXPBY, fit->xl_col, fit->Y1p, K, N, n, n, m, -1.0, 0.0)) != ISDF_OK) return st;
-    if ((st = mg(EPI_AXPBY, fit->xn_col, fit->Y2p, K, N, n, n, m, -1.0, 1.0)) != ISDF_OK) return st;
+    auto hq = [&](const Planes& A, const Planes& B, Planes& dst, int off) {
+      MixedProblem q = mixed_problem(A, B, nullptr, 0, m, m, ec, 1.0, 0.0, W, nmu);
+      q.P = static_cast<__bf16*>(dst.buf.p);
+      q.plane_p = dst.plane;
+      q.ldp = dst.ld;
+      q.p_off = off;
+      return mixed_prof(plan, ISDF_K_GEMM_EXCHANGE, EPI_HADAMARD_PLANES, q);
+    };
+    if ((st = hq(BG, fit->EGp, fit->Q1, 0)) != ISDF_OK) return st;   // Q_GG
+    if ((st = hq(BL, fit->EGp, fit->Q1, m)) != ISDF_OK) return st;   // Q_GL
+    if ((st = hq(fit->EGp, BL, fit->Q2, 0)) != ISDF_OK) return st;   // Q_GL^T
+    if ((st = hq(BL, fit->ELp, fit->Q2, m)) != ISDF_OK) return st;   // Q_LL
+    {  // Y1 = Q1 xln^T, Y2 = Q2 xln^T
+      ProfScope ps(plan, ISDF_K_GEMM_EXCHANGE, 2.0 * (2.0 * S * (2.0 * m * m + 2.0 * m * n) + 8.0 * m * n),
+                   2.0 * (2.0 * m * (double)n * 2.0 * m));
+      if ((st = gemm_mixed_wide_grouped(s, EPI_AXPBY, S, fit->d_yprobs.as<MixedProblem>(), 2, fit->ytiles,
+                                        family_tag(ISDF_K_GEMM_EXCHANGE))) != ISDF_OK)
+        return st;
+    }
+    __bf16* yb = static_cast<__bf16*>(fit->Y12.buf.p);
+    if ((st = launch_split_bf16(s, Y1, nmu, 1, nullptr, n, m, S, yb, fit->Y12.ld, fit->Y12.plane, 1.0)) !=
+        ISDF_OK)
+      return st;
+    if ((st = launch_split_bf16(s, Y2, nmu, 1, nullptr, n, m, S, yb + m, fit->Y12.ld, fit->Y12.plane, 1.0)) !=
+        ISDF_OK)
+      return st;
+    {  // K = -(xln)(Y12)^T: partial products over k ranges, then their ordered sum
+      ProfScope ps(plan, ISDF_K_GEMM_EXCHANGE, 2.0 * S * (4.0 * m * n) + 8.0 * fit->kparts * n * (double)n,
+                   2.0 * n * (double)n * 2.0 * m);
+      if ((st = gemm_mixed_grouped(s, EPI_AXPBY, S, fit->d_kprobs.as<MixedProblem>(), fit->kparts,
+                                   fit->ktiles, family_tag(ISDF_K_GEMM_EXCHANGE))) != ISDF_OK)
+        return st;
+    }
+    if ((st = launch_sum_parts(s, fit->Kpart.as<double>(), fit->kparts, (int64_t)n * n, K)) != ISDF_OK)
+      return st;
   } else {
     if (n_occ > 0) {
       // E_G = X^G C, E_L = X^L C; Q_ST = (E_S E_T^T) o W

@@ -79,7 +79,10 @@ isdf_status build_host_plan(const isdf_system* sys, HostPlan& hp);
 // Epilogues: EPI_AXPBY  C = alpha*acc + beta*C
 //            EPI_THETA  acc split at k = kL: C = aL*(aL + 2*aN)
 //            EPI_HADAMARD C = alpha*acc*E(m,n) (+ beta*C)
-enum { EPI_AXPBY = 0, EPI_THETA = 1, EPI_HADAMARD = 2 };
+// EPI_HADAMARD_PLANES (split-BF16 products only): C o E written as the split
+// planes of the transposed product, element (m, n) at P + plane_p s + n ldp +
+// p_off + m for plane s.
+enum { EPI_AXPBY = 0, EPI_THETA = 1, EPI_HADAMARD = 2, EPI_HADAMARD_PLANES = 3 };
 struct GemmProblem {
   const double* A;
   const double* B;
@@ -299,8 +302,17 @@ struct MixedProblem {
   double alpha, beta;
   int32_t tile_start;
   int32_t lower;
+  __bf16* P;  // EPI_HADAMARD_PLANES output
+  int64_t plane_p, ldp;
+  int32_t p_off;
 };
 isdf_status gemm_mixed(hipStream_t s, int epi, int splits, const MixedProblem& p, int tag = 4);
+// Grouped problems on the wide-tile kernel (tile_start in units of
+// mixed_tiles_wide); epilogues AXPBY, HADAMARD, HADAMARD_PLANES.
+isdf_status gemm_mixed_wide_grouped(hipStream_t s, int epi, int splits, const MixedProblem* d_probs,
+                                    int nprob, int total_tiles, int tag = 4);
+// out[i] = sum over s of parts[s count + i], s in order (deterministic).
+isdf_status launch_sum_parts(hipStream_t s, const double* parts, int nparts, int64_t count, double* out);
 isdf_status gemm_mixed_grouped(hipStream_t s, int epi, int splits, const MixedProblem* d_probs,
                                int nprob, int total_tiles, int tag = 4);
 int mixed_tiles(int M, int N);

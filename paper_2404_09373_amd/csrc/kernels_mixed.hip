@@ -241,10 +241,11 @@ int mixed_tiles_wide(int M, int N) { return ((M + WBM - 1) / WBM) * ((N + WBN - 
 
 template <int EPI, int S, int TAG>
 __global__ void __launch_bounds__(256, 2)
-gemm_mixed_wide_kernel(MixedProblem p) {
+gemm_mixed_wide_kernel(MixedProblem single, const MixedProblem* __restrict__ probs, int nprob) {
+  const int tile = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+  const MixedProblem p = probs ? *find_mixed(probs, nprob, tile) : single;
   int tm, tn;
-  tile_coords(xcd_tile((int)blockIdx.x, (int)gridDim.x), (p.M + WBM - 1) / WBM, (p.N + WBN - 1) / WBN, &tm,
-              &tn);
+  tile_coords(tile - p.tile_start, (p.M + WBM - 1) / WBM, (p.N + WBN - 1) / WBN, &tm, &tn);
   const int m0 = tm * WBM, n0 = tn * WBN;
 
   __shared__ __attribute__((aligned(16))) __bf16 As[2][S][WBM * BK];
@@ -375,6 +376,45 @@ gemm_mixed_wide_kernel(MixedProblem p) {
     __syncthreads();
   }
   // lane holds C(m0 + wm*32 + a*16 + lane%16, n0 + wn*64 + b*16 + 4(lane/16) + v)
+  if constexpr (EPI == EPI_HADAMARD_PLANES) {
+    // The transposed tile's planes go through LDS (the B stages, free now:
+    // S x 128 x 64 values) and out as 16-byte rows of 8 values of m.
+    __bf16* Ps = &Bs[0][0][0];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      const int cm = wm * 32 + a * 16 + (lane & 15), gm = m0 + cm;
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int rn = wn * 64 + b * 16 + 4 * (lane >> 4) + v, gn = n0 + rn;
+          double y = (gm < p.M && gn < p.N) ? p.alpha * acc[a][b][v] * p.E[(int64_t)gm + (int64_t)gn * p.lde]
+                                            : 0.0;
+#pragma unroll
+          for (int q = 0; q < S; ++q) {
+            const __bf16 h = (__bf16)(float)y;
+            Ps[(q * WBN + rn) * WBM + cm] = h;
+            y -= (double)(float)h;
+          }
+        }
+    }
+    __syncthreads();
+    const bool vec = (p.p_off % 8) == 0 && m0 + WBM <= p.M && n0 + WBN <= p.N;
+    if (vec) {
+      for (int e = tid; e < S * WBN * (WBM / 8); e += 256) {
+        const int q = e / (WBN * (WBM / 8)), r = (e / (WBM / 8)) % WBN, c8 = (e % (WBM / 8)) * 8;
+        *reinterpret_cast<bf8v*>(p.P + q * p.plane_p + (int64_t)(n0 + r) * p.ldp + p.p_off + m0 + c8) =
+            *reinterpret_cast<const bf8v*>(&Ps[(q * WBN + r) * WBM + c8]);
+      }
+    } else {
+      for (int e = tid; e < S * WBN * WBM; e += 256) {
+        const int q = e / (WBN * WBM), r = (e / WBM) % WBN, c = e % WBM;
+        if (n0 + r < p.N && m0 + c < p.M)
+          p.P[q * p.plane_p + (int64_t)(n0 + r) * p.ldp + p.p_off + m0 + c] = Ps[(q * WBN + r) * WBM + c];
+      }
+    }
+    return;
+  }
 #pragma unroll
   for (int a = 0; a < 2; ++a) {
     const int gm = m0 + wm * 32 + a * 16 + (lane & 15);
@@ -385,8 +425,8 @@ gemm_mixed_wide_kernel(MixedProblem p) {
       for (int v = 0; v < 4; ++v) {
         const int gn = n0 + wn * 64 + b * 16 + 4 * (lane >> 4) + v;
         if (gn >= p.N) continue;
-        double* cp = p.C + (int64_t)gm + (int64_t)gn * p.ldc;
         const double x = acc[a][b][v];
+        double* cp = p.C + (int64_t)gm + (int64_t)gn * p.ldc;
         double y;
         if (EPI == EPI_HADAMARD)
           y = p.alpha * x * p.E[(int64_t)gm + (int64_t)gn * p.lde];
@@ -399,19 +439,26 @@ gemm_mixed_wide_kernel(MixedProblem p) {
 }
 
 template <int S, int TAG>
-static void launch_wide_st(hipStream_t s, int epi, const MixedProblem& p, int tiles) {
+static void launch_wide_st(hipStream_t s, int epi, const MixedProblem& p, const MixedProblem* probs,
+                           int nprob, int tiles) {
   if (epi == EPI_HADAMARD)
-    hipLaunchKernelGGL((gemm_mixed_wide_kernel<EPI_HADAMARD, S, TAG>), dim3(tiles), dim3(256), 0, s, p);
+    hipLaunchKernelGGL((gemm_mixed_wide_kernel<EPI_HADAMARD, S, TAG>), dim3(tiles), dim3(256), 0, s, p,
+                       probs, nprob);
+  else if (epi == EPI_HADAMARD_PLANES)
+    hipLaunchKernelGGL((gemm_mixed_wide_kernel<EPI_HADAMARD_PLANES, S, TAG>), dim3(tiles), dim3(256), 0, s,
+                       p, probs, nprob);
   else
-    hipLaunchKernelGGL((gemm_mixed_wide_kernel<EPI_AXPBY, S, TAG>), dim3(tiles), dim3(256), 0, s, p);
+    hipLaunchKernelGGL((gemm_mixed_wide_kernel<EPI_AXPBY, S, TAG>), dim3(tiles), dim3(256), 0, s, p, probs,
+                       nprob);
 }
 
 template <int S>
-static void launch_wide_s(hipStream_t s, int epi, int tag, const MixedProblem& p, int tiles) {
+static void launch_wide_s(hipStream_t s, int epi, int tag, const MixedProblem& p, const MixedProblem* probs,
+                          int nprob, int tiles) {
   switch (tag) {
-    case 2: launch_wide_st<S, 2>(s, epi, p, tiles); break;
-    case 3: launch_wide_st<S, 3>(s, epi, p, tiles); break;
-    default: launch_wide_st<S, 4>(s, epi, p, tiles); break;
+    case 2: launch_wide_st<S, 2>(s, epi, p, probs, nprob, tiles); break;
+    case 3: launch_wide_st<S, 3>(s, epi, p, probs, nprob, tiles); break;
+    default: launch_wide_st<S, 4>(s, epi, p, probs, nprob, tiles); break;
   }
 }
 
@@ -443,11 +490,13 @@ isdf_status gemm_mixed(hipStream_t s, int epi, int splits, const MixedProblem& p
   if (p.M <= 0 || p.N <= 0) return ISDF_OK;
   MixedProblem q = p;
   q.tile_start = 0;
-  // products with enough 64 x 128 tiles to fill the chip take the wide kernel
-  if (epi != EPI_THETA && !p.lower && mixed_tiles_wide(p.M, p.N) >= MIXED_WIDE_MIN_TILES) {
+  // products with enough 64 x 128 tiles to fill the chip take the wide
+  // kernel, and so does the planes epilogue (it exists only there)
+  if (epi == EPI_HADAMARD_PLANES ||
+      (epi != EPI_THETA && !p.lower && mixed_tiles_wide(p.M, p.N) >= MIXED_WIDE_MIN_TILES)) {
     const int tiles = mixed_tiles_wide(p.M, p.N);
-    if (splits == 2) launch_wide_s<2>(s, epi, tag, q, tiles);
-    else launch_wide_s<3>(s, epi, tag, q, tiles);
+    if (splits == 2) launch_wide_s<2>(s, epi, tag, q, nullptr, 1, tiles);
+    else launch_wide_s<3>(s, epi, tag, q, nullptr, 1, tiles);
     ISDF_HIP_TRY(hipGetLastError());
     return ISDF_OK;
   }
@@ -458,9 +507,45 @@ isdf_status gemm_mixed(hipStream_t s, int epi, int splits, const MixedProblem& p
   return ISDF_OK;
 }
 
+isdf_status gemm_mixed_wide_grouped(hipStream_t s, int epi, int splits, const MixedProblem* d_probs,
+                                    int nprob, int total_tiles, int tag) {
+  if (nprob <= 0 || total_tiles <= 0) return ISDF_OK;
+  if (epi == EPI_THETA) {
+    set_error("mixed GEMM: the wide kernel has no Theta epilogue");
+    return ISDF_E_ARG;
+  }
+  MixedProblem dummy{};
+  if (splits == 2) launch_wide_s<2>(s, epi, tag, dummy, d_probs, nprob, total_tiles);
+  else launch_wide_s<3>(s, epi, tag, dummy, d_probs, nprob, total_tiles);
+  ISDF_HIP_TRY(hipGetLastError());
+  return ISDF_OK;
+}
+
+__global__ void __launch_bounds__(256)
+sum_parts_kernel(const double* __restrict__ parts, int nparts, int64_t count, double* __restrict__ out) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    double a = 0.0;
+    for (int q = 0; q < nparts; ++q) a += parts[(int64_t)q * count + i];
+    out[i] = a;
+  }
+}
+
+isdf_status launch_sum_parts(hipStream_t s, const double* parts, int nparts, int64_t count, double* out) {
+  if (count <= 0) return ISDF_OK;
+  const int64_t blocks = std::min<int64_t>((count + 255) / 256, 4096);
+  hipLaunchKernelGGL(sum_parts_kernel, dim3((unsigned)blocks), dim3(256), 0, s, parts, nparts, count, out);
+  ISDF_HIP_TRY(hipGetLastError());
+  return ISDF_OK;
+}
+
 isdf_status gemm_mixed_grouped(hipStream_t s, int epi, int splits, const MixedProblem* d_probs,
                                int nprob, int total_tiles, int tag) {
   if (nprob <= 0 || total_tiles <= 0) return ISDF_OK;
+  if (epi == EPI_HADAMARD_PLANES) {
+    set_error("mixed GEMM: the planes epilogue runs on the wide kernel");
+    return ISDF_E_ARG;
+  }
   MixedProblem dummy{};
   if (splits == 2) launch_s<2>(s, epi, tag, dummy, d_probs, nprob, total_tiles);
   else launch_s<3>(s, epi, tag, dummy, d_probs, nprob, total_tiles);
