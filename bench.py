@@ -74,15 +74,23 @@ def set_profile(plan, mask):
     binding.load().isdf_profile(plan.handle, int(mask))
 
 
+# family -> (counter summary under profiles/, kernel source the summary was taken on)
+TRAFFIC = {
+    "fft": ("traffic_fft_cfg2.md", "kernels_fft.hip"),
+}
+
+
 def measured_traffic(fam):
-    """HBM bytes per launch of the family from the committed counter summary,
+    """HBM bytes per launch of the family from its committed counter summary,
     or None when there is none or the kernel source changed since."""
     import hashlib
 
-    if FAMILIES[fam][0] != "gemm_select":
+    name = FAMILIES[fam][0]
+    if name not in TRAFFIC:
         return None
-    path = os.path.join(ROOT, "profiles", "traffic_gemm_select_cfg2.md")
-    src = os.path.join(ROOT, "paper_2404_09373_amd", "csrc", "kernels_gemm.hip")
+    summary, source = TRAFFIC[name]
+    path = os.path.join(ROOT, "profiles", summary)
+    src = os.path.join(ROOT, "paper_2404_09373_amd", "csrc", source)
     if not os.path.exists(path):
         return None
     vals = {}
