@@ -46,6 +46,9 @@ __device__ inline double2 csub(double2 a, double2 b) { return make_double2(a.x -
 // multiply by sign * i
 __device__ inline double2 mul_si(double2 a, double sign) { return make_double2(-sign * a.y, sign * a.x); }
 
+template <int R>
+__device__ inline void radix_core(const double2* v, double2* y, double sign);
+
 // one radix-R butterfly of a Stockham stage
 template <int R>
 __device__ inline void butterfly(const double2* src, double2* dst, int n, int j, int Ns,
@@ -63,6 +66,15 @@ __device__ inline void butterfly(const double2* src, double2* dst, int n, int j,
     v[r] = cmul(v[r], w);
   }
   double2 y[R];
+  radix_core<R>(v, y, sign);
+  const int idxD = (j / Ns) * Ns * R + k;
+#pragma unroll
+  for (int r = 0; r < R; ++r) dst[idxD + r * Ns] = y[r];
+}
+
+// the radix-R DFT of v (twiddles applied) into y
+template <int R>
+__device__ inline void radix_core(const double2* v, double2* y, double sign) {
   if (R == 2) {
     y[0] = cadd(v[0], v[1]);
     y[1] = csub(v[0], v[1]);
@@ -96,9 +108,6 @@ __device__ inline void butterfly(const double2* src, double2* dst, int n, int j,
     y[2] = cadd(a2, b2);
     y[3] = csub(a2, b2);
   }
-  const int idxD = (j / Ns) * Ns * R + k;
-#pragma unroll
-  for (int r = 0; r < R; ++r) dst[idxD + r * Ns] = y[r];
 }
 
 __global__ void __launch_bounds__(256)
@@ -229,16 +238,48 @@ constexpr int fft_span(int n, int s) {  // product of the first s radices
   return p;
 }
 
-template <int N, int S>
-__device__ inline void fft_stages(double2* src, double2* dst, int nl, const double2* tw, double sign) {
+// The Stockham stages of a compiled line length in one LDS buffer: each
+// thread reads its butterflies' inputs, the workgroup synchronises, and the
+// outputs go back into the same buffer.  Half the LDS of ping-pong buffers,
+// so more workgroups (and more lines in flight from HBM) per CU, at two
+// barriers a stage instead of one.
+template <int N, int S, int NL>
+__device__ inline void fft_stages_ip(double2* buf, int nl, const double2* tw, double sign) {
   if constexpr (S < fft_nstages(N)) {
     constexpr int R = fft_radix(N, S), NS = fft_span(N, S), NB = N / R;
-    for (int u = threadIdx.x; u < nl * NB; u += 256) {
-      const int line = u / NB, j = u % NB;
-      butterfly<R>(src + line * N, dst + line * N, N, j, NS, tw, sign);
+    constexpr int UMAX = (NL * NB + 255) / 256;
+    constexpr int STEP = N / (NS * R);
+    double2 y[UMAX][R];
+    int dsto[UMAX];
+#pragma unroll
+    for (int q = 0; q < UMAX; ++q) {
+      const int u = (int)threadIdx.x + 256 * q;
+      dsto[q] = -1;
+      if (u < nl * NB) {
+        const int line = u / NB, j = u % NB, k = j % NS;
+        const double2* src = buf + line * N;
+        double2 v[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[r] = src[j + r * NB];
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          double2 w = tw[r * k * STEP];
+          if (sign > 0.0) w.y = -w.y;
+          v[r] = cmul(v[r], w);
+        }
+        radix_core<R>(v, y[q], sign);
+        dsto[q] = line * N + (j / NS) * NS * R + k;
+      }
     }
     __syncthreads();
-    fft_stages<N, S + 1>(dst, src, nl, tw, sign);
+#pragma unroll
+    for (int q = 0; q < UMAX; ++q)
+      if (dsto[q] >= 0) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) buf[dsto[q] + r * NS] = y[q][r];
+      }
+    __syncthreads();
+    fft_stages_ip<N, S + 1, NL>(buf, nl, tw, sign);
   }
 }
 
@@ -254,7 +295,6 @@ fft_pass_fixed_kernel(double2* __restrict__ z, int batch, int n1, int n2, int n3
                       double* __restrict__ V = nullptr, int ncols = 0) {
   extern __shared__ double2 lds[];
   double2* bufA = lds;
-  double2* bufB = lds + LPW * N;
   const int64_t ng = (int64_t)n1 * n2 * n3;
   const int tid = threadIdx.x;
   const int g = blockIdx.x;
@@ -301,8 +341,8 @@ fft_pass_fixed_kernel(double2* __restrict__ z, int batch, int n1, int n2, int n3
     }
   }
   __syncthreads();
-  fft_stages<N, 0>(bufA, bufB, nl, tw, sign);
-  const double2* res = (fft_nstages(N) & 1) ? bufB : bufA;
+  fft_stages_ip<N, 0, LPW>(bufA, nl, tw, sign);
+  const double2* res = bufA;
   if constexpr (PSTORE) {
     const int b = (g / (n1 / LPW)) / n2;
     const int64_t off = base - (int64_t)b * ng;
@@ -328,7 +368,7 @@ fft_pass_fixed_kernel(double2* __restrict__ z, int batch, int n1, int n2, int n3
 template <int N>
 bool launch_fixed_n(hipStream_t s, double2* z, int batch, int n1, int n2, int n3, int axis,
                     double sign, const double2* tw, int lpw, int64_t groups) {
-  const size_t shmem = sizeof(double2) * 2 * (size_t)lpw * N;
+  const size_t shmem = sizeof(double2) * (size_t)lpw * N;
   if (lpw == 16)
     hipLaunchKernelGGL((fft_pass_fixed_kernel<N, 16>), dim3((unsigned)groups), dim3(256), shmem, s,
                        z, batch, n1, n2, n3, axis, sign, tw);
@@ -363,14 +403,14 @@ template <int N>
 void launch_poisson_x(hipStream_t s, double2* zc, int batch, const int gc[3], const double2* tw,
                       const double2* zf, const PoissonArg& pa, int64_t groups) {
   hipLaunchKernelGGL((fft_pass_fixed_kernel<N, 8, true, false>), dim3((unsigned)groups), dim3(256),
-                     sizeof(double2) * 2 * 8 * N, s, zc, batch, gc[0], gc[1], gc[2], 0, 1.0, tw, zf, pa,
+                     sizeof(double2) * 8 * N, s, zc, batch, gc[0], gc[1], gc[2], 0, 1.0, tw, zf, pa,
                      nullptr, 0);
 }
 template <int N>
 void launch_planar_z(hipStream_t s, double2* zc, int batch, const int gc[3], const double2* tw,
                      double* V, int ncols, int64_t groups) {
   hipLaunchKernelGGL((fft_pass_fixed_kernel<N, 8, false, true>), dim3((unsigned)groups), dim3(256),
-                     sizeof(double2) * 2 * 8 * N, s, zc, batch, gc[0], gc[1], gc[2], 2, 1.0, tw, nullptr,
+                     sizeof(double2) * 8 * N, s, zc, batch, gc[0], gc[1], gc[2], 2, 1.0, tw, nullptr,
                      PoissonArg{}, V, ncols);
 }
 
@@ -658,7 +698,6 @@ fft_fwd_pruned_kernel(double2* __restrict__ z, const FwdPair* __restrict__ pairs
                       const double2* __restrict__ tw) {
   extern __shared__ double2 lds[];
   double2* bufA = lds;
-  double2* bufB = lds + LPW * N;
   const FwdPair P = pairs[blockIdx.y];
   const int64_t ng = (int64_t)n1 * n2 * n3;
   double2* zb = z + (int64_t)blockIdx.y * ng;
@@ -708,8 +747,8 @@ fft_fwd_pruned_kernel(double2* __restrict__ z, const FwdPair* __restrict__ pairs
     }
   }
   __syncthreads();
-  fft_stages<N, 0>(bufA, bufB, nl, tw, -1.0);
-  const double2* res = (fft_nstages(N) & 1) ? bufB : bufA;
+  fft_stages_ip<N, 0, LPW>(bufA, nl, tw, -1.0);
+  const double2* res = bufA;
   if (AXIS == 0) {
     const int t0 = g * LPW;
     for (int e = tid; e < nl * N; e += 256) {
@@ -732,7 +771,7 @@ void launch_fwd_pruned(hipStream_t s, double2* z, const FwdPair* pairs, const Fw
                        const int g[3], const double2* tw, int gx) {
   constexpr int LPW = 8;
   hipLaunchKernelGGL((fft_fwd_pruned_kernel<N, LPW, AXIS>), dim3((unsigned)gx, (unsigned)npairs),
-                     dim3(256), sizeof(double2) * 2 * LPW * N, s, z, pairs, cols, g[0], g[1], g[2], tw);
+                     dim3(256), sizeof(double2) * LPW * N, s, z, pairs, cols, g[0], g[1], g[2], tw);
 }
 
 template <int AXIS>
