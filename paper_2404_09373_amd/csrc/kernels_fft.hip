@@ -408,10 +408,16 @@ void launch_poisson_x(hipStream_t s, double2* zc, int batch, const int gc[3], co
 }
 template <int N>
 void launch_planar_z(hipStream_t s, double2* zc, int batch, const int gc[3], const double2* tw,
-                     double* V, int ncols, int64_t groups) {
-  hipLaunchKernelGGL((fft_pass_fixed_kernel<N, 8, false, true>), dim3((unsigned)groups), dim3(256),
-                     sizeof(double2) * 8 * N, s, zc, batch, gc[0], gc[1], gc[2], 2, 1.0, tw, nullptr,
-                     PoissonArg{}, V, ncols);
+                     double* V, int ncols, int lpw) {
+  const int64_t groups = (int64_t)(gc[0] / lpw) * gc[1] * batch;
+  if (lpw == 16)
+    hipLaunchKernelGGL((fft_pass_fixed_kernel<N, 16, false, true>), dim3((unsigned)groups), dim3(256),
+                       sizeof(double2) * 16 * N, s, zc, batch, gc[0], gc[1], gc[2], 2, 1.0, tw, nullptr,
+                       PoissonArg{}, V, ncols);
+  else
+    hipLaunchKernelGGL((fft_pass_fixed_kernel<N, 8, false, true>), dim3((unsigned)groups), dim3(256),
+                       sizeof(double2) * 8 * N, s, zc, batch, gc[0], gc[1], gc[2], 2, 1.0, tw, nullptr,
+                       PoissonArg{}, V, ncols);
 }
 
 // host twiddle tables e^{-2 pi i t / n}, cached per (device, n) for the
@@ -647,18 +653,20 @@ isdf_status fft_poisson_inverse(hipStream_t s, const double* zf, const int gf[3]
   }
   if ((st = mark(3)) != ISDF_OK) return st;
   // z pass into the planar potentials
-  const int64_t gz = (int64_t)(gc[0] / 8) * gc[1] * npairs;
+  // 16 lines a group where they divide the grid: each strided element of a
+  // real plane is then a run of 128 bytes
+  const int zlpw = gc[0] % 16 == 0 ? 16 : 8;
   if ((st = mark(4)) != ISDF_OK) return st;
   switch (gc[2]) {
-    case 24: launch_planar_z<24>(s, z, npairs, gc, tw2, V, ncols, gz); break;
-    case 32: launch_planar_z<32>(s, z, npairs, gc, tw2, V, ncols, gz); break;
-    case 40: launch_planar_z<40>(s, z, npairs, gc, tw2, V, ncols, gz); break;
-    case 48: launch_planar_z<48>(s, z, npairs, gc, tw2, V, ncols, gz); break;
-    case 64: launch_planar_z<64>(s, z, npairs, gc, tw2, V, ncols, gz); break;
-    case 80: launch_planar_z<80>(s, z, npairs, gc, tw2, V, ncols, gz); break;
-    case 96: launch_planar_z<96>(s, z, npairs, gc, tw2, V, ncols, gz); break;
-    case 128: launch_planar_z<128>(s, z, npairs, gc, tw2, V, ncols, gz); break;
-    default: launch_planar_z<160>(s, z, npairs, gc, tw2, V, ncols, gz); break;
+    case 24: launch_planar_z<24>(s, z, npairs, gc, tw2, V, ncols, zlpw); break;
+    case 32: launch_planar_z<32>(s, z, npairs, gc, tw2, V, ncols, zlpw); break;
+    case 40: launch_planar_z<40>(s, z, npairs, gc, tw2, V, ncols, zlpw); break;
+    case 48: launch_planar_z<48>(s, z, npairs, gc, tw2, V, ncols, zlpw); break;
+    case 64: launch_planar_z<64>(s, z, npairs, gc, tw2, V, ncols, zlpw); break;
+    case 80: launch_planar_z<80>(s, z, npairs, gc, tw2, V, ncols, zlpw); break;
+    case 96: launch_planar_z<96>(s, z, npairs, gc, tw2, V, ncols, zlpw); break;
+    case 128: launch_planar_z<128>(s, z, npairs, gc, tw2, V, ncols, zlpw); break;
+    default: launch_planar_z<160>(s, z, npairs, gc, tw2, V, ncols, zlpw); break;
   }
   ISDF_HIP_TRY(hipGetLastError());
   if ((st = mark(5)) != ISDF_OK) return st;
