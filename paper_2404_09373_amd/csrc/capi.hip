@@ -324,8 +324,8 @@ struct isdf_fit_s {
   // [Y1(:, a); Y2(:, a)].  K = -(xln) (Y12)^T runs as KSPLIT partial products.
   Planes xg_row, xl_row, xln;
   Planes Dp, EGp, ELp, Q1, Q2, Y12;
-  DevBuf Kpart, d_yprobs, d_kprobs;
-  int ytiles = 0, ktiles = 0, kparts = 0;
+  DevBuf Kpart, d_yprobs, d_kprobs, d_qprobs;
+  int ytiles = 0, ktiles = 0, kparts = 0, qprobs_nocc = -1;
   // factored density: D = C C^T for the energy
   DevBuf Docc;
   // captured exchange: replayed while (mode, operands, K) stay the same
@@ -2103,6 +2103,33 @@ isdf_status exchange_prepare(isdf_plan_s* plan, isdf_fit_s* fit, int n_occ) {
     if ((st = size_planes(S, n_occ > 0 ? n_occ : n, n, fit->Dp)) != ISDF_OK) return st;
     if ((st = size_planes(S, m, (int)ec, fit->EGp)) != ISDF_OK) return st;
     if ((st = size_planes(S, m, (int)ec, fit->ELp)) != ISDF_OK) return st;
+    if (fit->qprobs_nocc != n_occ) {
+      // Q_ST = P_ST o W with P_ST = E_S B_T^T, B = E (factored) or X (dense).
+      // The product C(i, j) = (B_T E_S^T)(i, j) W(i, j) = Q_ST(j, i) (W is
+      // symmetric) lands transposed, at row j and column i of the A operand,
+      // so each block of Q1 = [Q_GG Q_GL] and Q2 = [Q_GL^T Q_LL] is one
+      // product whose planes the epilogue writes; the four share W's tiles.
+      fit->EGp.rows = fit->ELp.rows = m;
+      fit->EGp.cols = fit->ELp.cols = (int)ec;
+      fit->EGp.ld = fit->ELp.ld = (ec + 7) / 8 * 8;
+      fit->EGp.plane = fit->ELp.plane = (int64_t)m * fit->EGp.ld;
+      const Planes& BG = n_occ > 0 ? fit->EGp : fit->xg_row;
+      const Planes& BL = n_occ > 0 ? fit->ELp : fit->xl_row;
+      const Planes* ops[4][2] = {{&BG, &fit->EGp}, {&BL, &fit->EGp}, {&fit->EGp, &BL}, {&BL, &fit->ELp}};
+      Planes* dst[4] = {&fit->Q1, &fit->Q1, &fit->Q2, &fit->Q2};
+      const int off[4] = {0, m, 0, m};
+      std::vector<MixedProblem> qp(4);
+      for (int i = 0; i < 4; ++i) {
+        qp[i] = mixed_problem(*ops[i][0], *ops[i][1], nullptr, 0, m, m, (int)ec, 1.0, 0.0,
+                              fit->W.as<double>(), nmu);
+        qp[i].P = static_cast<__bf16*>(dst[i]->buf.p);
+        qp[i].plane_p = dst[i]->plane;
+        qp[i].ldp = dst[i]->ld;
+        qp[i].p_off = off[i];
+      }
+      if ((st = upload(fit->d_qprobs, qp)) != ISDF_OK) return st;
+      fit->qprobs_nocc = n_occ;
+    }
   }
   return ISDF_OK;
 }
@@ -2155,25 +2182,14 @@ isdf_status exchange_enqueue(isdf_plan_s* plan, isdf_fit_s* fit, const double* i
     if ((st = mg(EPI_AXPBY, fit->xl_row, fit->Dp, EL, nmu, m, ec, n, 1.0, 0.0)) != ISDF_OK) return st;
     if ((st = make_planes(s, S, EG, 1, nmu, nullptr, m, ec, fit->EGp)) != ISDF_OK) return st;
     if ((st = make_planes(s, S, EL, 1, nmu, nullptr, m, ec, fit->ELp)) != ISDF_OK) return st;
-    // Q_ST = P_ST o W with P_ST = E_S B_T^T, B = E (factored) or X (dense).  The
-    // product C(i, j) = (B_T E_S^T)(i, j) W(i, j) = Q_ST(j, i) (W is symmetric)
-    // lands transposed, at row j and column i of the A operand, so each
-    // block of Q1 = [Q_GG Q_GL] and Q2 = [Q_GL^T Q_LL] is one product whose
-    // planes are written straight from the epilogue.
-    const Planes& BG = n_occ > 0 ? fit->EGp : fit->xg_row;
-    const Planes& BL = n_occ > 0 ? fit->ELp : fit->xl_row;
-    auto hq = [&](const Planes& A, const Planes& B, Planes& dst, int off) {
-      MixedProblem q = mixed_problem(A, B, nullptr, 0, m, m, ec, 1.0, 0.0, W, nmu);
-      q.P = static_cast<__bf16*>(dst.buf.p);
-      q.plane_p = dst.plane;
-      q.ldp = dst.ld;
-      q.p_off = off;
-      return mixed_prof(plan, ISDF_K_GEMM_EXCHANGE, EPI_HADAMARD_PLANES, q);
-    };
-    if ((st = hq(BG, fit->EGp, fit->Q1, 0)) != ISDF_OK) return st;   // Q_GG
-    if ((st = hq(BL, fit->EGp, fit->Q1, m)) != ISDF_OK) return st;   // Q_GL
-    if ((st = hq(fit->EGp, BL, fit->Q2, 0)) != ISDF_OK) return st;   // Q_GL^T
-    if ((st = hq(BL, fit->ELp, fit->Q2, m)) != ISDF_OK) return st;   // Q_LL
+    {  // the four Q blocks (exchange_prepare), interleaved tile by tile
+      ProfScope ps(plan, ISDF_K_GEMM_EXCHANGE,
+                   4.0 * (2.0 * S * 2.0 * m * (double)ec + 2.0 * S * (double)m * m) + 8.0 * (double)m * m,
+                   4.0 * 2.0 * m * (double)m * ec);
+      if ((st = gemm_mixed_wide_grouped(s, EPI_HADAMARD_PLANES, S, fit->d_qprobs.as<MixedProblem>(), -4,
+                                        4 * mixed_tiles_wide(m, m), family_tag(ISDF_K_GEMM_EXCHANGE))) != ISDF_OK)
+        return st;
+    }
     {  // Y1 = Q1 xln^T, Y2 = Q2 xln^T
       ProfScope ps(plan, ISDF_K_GEMM_EXCHANGE, 2.0 * (2.0 * S * (2.0 * m * m + 2.0 * m * n) + 8.0 * m * n),
                    2.0 * (2.0 * m * (double)n * 2.0 * m));

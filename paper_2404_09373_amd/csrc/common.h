@@ -308,7 +308,9 @@ struct MixedProblem {
 };
 isdf_status gemm_mixed(hipStream_t s, int epi, int splits, const MixedProblem& p, int tag = 4);
 // Grouped problems on the wide-tile kernel (tile_start in units of
-// mixed_tiles_wide); epilogues AXPBY, HADAMARD, HADAMARD_PLANES.
+// mixed_tiles_wide); epilogues AXPBY, HADAMARD, HADAMARD_PLANES.  nprob < 0:
+// -nprob problems with one M x N tile grid, interleaved tile by tile
+// (total_tiles = -nprob x tiles of one).
 isdf_status gemm_mixed_wide_grouped(hipStream_t s, int epi, int splits, const MixedProblem* d_probs,
                                     int nprob, int total_tiles, int tag = 4);
 // out[i] = sum over s of parts[s count + i], s in order (deterministic).

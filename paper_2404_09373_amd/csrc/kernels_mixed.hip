@@ -242,10 +242,14 @@ int mixed_tiles_wide(int M, int N) { return ((M + WBM - 1) / WBM) * ((N + WBN - 
 template <int EPI, int S, int TAG>
 __global__ void __launch_bounds__(256, 2)
 gemm_mixed_wide_kernel(MixedProblem single, const MixedProblem* __restrict__ probs, int nprob) {
+  // nprob < 0: -nprob problems of one tile grid, interleaved tile by tile
+  // (tile t is tile t / -nprob of problem t % -nprob), so the problems'
+  // tiles at one position run together on one XCD and share its L2
   const int tile = xcd_tile((int)blockIdx.x, (int)gridDim.x);
-  const MixedProblem p = probs ? *find_mixed(probs, nprob, tile) : single;
+  const MixedProblem p = !probs ? single : nprob < 0 ? probs[tile % -nprob] : *find_mixed(probs, nprob, tile);
+  const int local = !probs ? tile : nprob < 0 ? tile / -nprob : tile - p.tile_start;
   int tm, tn;
-  tile_coords(tile - p.tile_start, (p.M + WBM - 1) / WBM, (p.N + WBN - 1) / WBN, &tm, &tn);
+  tile_coords(local, (p.M + WBM - 1) / WBM, (p.N + WBN - 1) / WBN, &tm, &tn);
   const int m0 = tm * WBM, n0 = tn * WBN;
 
   __shared__ __attribute__((aligned(16))) __bf16 As[2][S][WBM * BK];
@@ -509,7 +513,7 @@ isdf_status gemm_mixed(hipStream_t s, int epi, int splits, const MixedProblem& p
 
 isdf_status gemm_mixed_wide_grouped(hipStream_t s, int epi, int splits, const MixedProblem* d_probs,
                                     int nprob, int total_tiles, int tag) {
-  if (nprob <= 0 || total_tiles <= 0) return ISDF_OK;
+  if (nprob == 0 || total_tiles <= 0) return ISDF_OK;
   if (epi == EPI_THETA) {
     set_error("mixed GEMM: the wide kernel has no Theta epilogue");
     return ISDF_E_ARG;
