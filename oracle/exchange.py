@@ -54,3 +54,27 @@ def exchange_matrix(XL: np.ndarray, XN: np.ndarray, W: np.ndarray, D: np.ndarray
 
 def exchange_energy(D: np.ndarray, K: np.ndarray) -> float:
     return float(np.sum(D * K))
+
+
+def exchange_occ_ri(XL: np.ndarray, XN: np.ndarray, W: np.ndarray, C: np.ndarray) -> np.ndarray:
+    """K C for a factored density D = C C^T (occ-RI output, the occupied
+    orbitals of the exchange section): the pair products X^S D X^T' become
+    (X^S C)(X^T C)', and K is applied to C without forming it, so every
+    product has an n_occ-wide side:
+
+      K C = -[ X^L' (P_GG o W) E_L + X^L' (P_GL o W) E_N
+             + X^N' (P_LG o W) E_L + X^N' (P_LL o W) E_N ],
+
+    E_S = X^S C, P_ST = E_S E_T'.  E_x = tr(D K) = sum(C o (K C))."""
+    XG = XL + XN
+    EG, EL, EN = XG @ C, XL @ C, XN @ C
+    P_GG = EG @ EG.T
+    P_GL = EG @ EL.T
+    P_LG = EL @ EG.T
+    P_LL = EL @ EL.T
+    return -(
+        XL.T @ ((P_GG * W) @ EL)
+        + XL.T @ ((P_GL * W) @ EN)
+        + XN.T @ ((P_LG * W) @ EL)
+        + XN.T @ ((P_LL * W) @ EN)
+    )

@@ -337,6 +337,23 @@ def test_exchange_invariants_cfg1(cfg1_oracle):
     assert ev[0] >= -1e-10 * ev[-1]
 
 
+def test_occ_ri_output_matches_full_exchange(cfg1_oracle):
+    """occ-RI output (K C for D = C C^T): the oracle's contraction over
+    n_occ-wide products equals the full four-term K built from D = C C^T and
+    then applied to C, and sum(C o KC) is the same E_x (catches a swapped
+    L/N block or a transposed pair product in the occupied-orbital form)."""
+    s, r = cfg1_oracle
+    C = s.C_occ
+    KC = exchange.exchange_occ_ri(r.XL, r.XN, r.W, C)
+    D = C @ C.T
+    K_full = exchange.exchange_matrix(r.XL, r.XN, r.W, D)
+    ref = K_full @ C
+    assert np.max(np.abs(KC - ref)) <= 1e-12 * np.max(np.abs(ref))
+    assert abs(np.sum(C * KC) - exchange.exchange_energy(D, K_full)) <= 1e-12 * abs(r.E_x)
+    # and the pipeline's own K (from the density of the workload) agrees
+    assert np.max(np.abs(KC - r.K @ C)) <= 1e-10 * np.max(np.abs(ref))
+
+
 def test_single_level_textbook_thc():
     """One level, one universal domain: the four-term formula reduces to the
     textbook K = -X^T [(X D X^T) o W] X."""
