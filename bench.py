@@ -349,8 +349,25 @@ def main():
         timed = kernel_stats(plan)[dom]
         set_profile(plan, 0)
         ms = (t1 - t0) / args.steps * 1e3
+        # occ-RI output (K C, K never formed) on one more fit, outside the
+        # timed steps: per-build time and its energy against the full K's
+        fit = plan.fit()
+        _, e_full = fit.exchange_occ(Cocc, K)
+        KC = torch.empty_like(Cocc)
+        for _ in range(2):
+            fit.exchange_occ_ri(Cocc, KC)
+        torch.cuda.synchronize()
+        r0 = time.perf_counter()
+        for _ in range(args.exchanges):
+            _, e_ri = fit.exchange_occ_ri(Cocc, KC)
+        torch.cuda.synchronize()
+        ri_ms = (time.perf_counter() - r0) / args.exchanges * 1e3
+        fit.close()
+        occ_ri = {"ms_per_build": round(ri_ms, 3), "E_x": e_ri,
+                  "abs_dE_per_atom_vs_full_K": abs(e_ri - e_full) / s.n_atoms}
         return dict(ms_per_step=ms, value=ms / args.exchanges / 1e3, E_x=ex, n_mu=n_mu,
-                    stats=breakdown, stages=stages, selection=sel, dominant=dom, timed=timed)
+                    stats=breakdown, stages=stages, selection=sel, dominant=dom, timed=timed,
+                    occ_ri=occ_ri)
 
     results = {}
     if args.paths in ("both", "reference"):
@@ -410,6 +427,8 @@ def main():
                 for f, v in r["stats"].items()},
             "candidates": int(np.sum(sel["n_candidates"])),
             "fallback_domains": int(np.sum(sel["fallback"])),
+            # K C only (occ-RI), per build; the headline uses the full K
+            "occ_ri_exchange": r["occ_ri"],
         }
 
     line = {

@@ -244,6 +244,20 @@ isdf_status isdf_exchange(isdf_plan_t plan, isdf_fit_t fit, const double* D_dev,
 isdf_status isdf_exchange_occ(isdf_plan_t plan, isdf_fit_t fit, const double* C_dev,
                               int32_t n_occ, double* K_dev, double* e_x);
 
+/* occ-RI output: K C for D = C C' without forming K (the exchange section's
+ * occupied-orbital form, K applied to the occupied orbitals):
+ *   K C = -[X^L'(P_GG o W)E_L + X^L'(P_GL o W)E_N + X^N'(P_LG o W)E_L
+ *           + X^N'(P_LL o W)E_N],  E_S = X^S C, P_ST = E_S E_T',
+ * so every product has an n_occ-wide side (about 14 N_mu^2 n_occ flops
+ * against 6 N_mu^2 n_occ + 8 N_mu^2 N for the full K); e_x = tr(C' K C) =
+ * tr(D K), the same energy.
+ * C_dev: device pointer to N x n_occ FP64, row-major (C[mu * n_occ + i]).
+ * KC_dev: device pointer to N x n_occ FP64, row-major, written.
+ * e_x, graph capture and errors as isdf_exchange (ISDF_E_ARG also for n_occ
+ * outside 1..N). */
+isdf_status isdf_exchange_occ_ri(isdf_plan_t plan, isdf_fit_t fit, const double* C_dev,
+                                 int32_t n_occ, double* KC_dev, double* e_x);
+
 /* Tile-shape tuning of the FP64 GEMMs (for callers that set up a plan once
  * and run it many times).  Runs one fit and one dense and one factored
  * exchange (D = I, C = the first n_occ unit vectors) on the plan; every

@@ -44,6 +44,7 @@ constexpr int CRB_BLOCK = 512;      // most pivots per block
 constexpr int CRB_CANDIDATES = 2048;  // candidates per block to start with
 constexpr int CRB_CHUNK = 16;          // greedy-step launches between state checks
 constexpr int KSPLIT = 8;              // k ranges of the mixed exchange's final product
+constexpr int KSPLIT_RI = 16;          // k ranges of the mixed occ-RI final product
 
 // Device memory of one plan.  A block that a buffer gives back is kept and
 // handed to a later buffer of the same plan, with no hipFree/hipMalloc (both
@@ -326,6 +327,13 @@ struct isdf_fit_s {
   Planes Dp, EGp, ELp, Q1, Q2, Y12;
   DevBuf Kpart, d_yprobs, d_kprobs, d_qprobs;
   int ytiles = 0, ktiles = 0, kparts = 0, qprobs_nocc = -1;
+  // occ-RI output (K C): E_N = X^N C, Z1 = [Q_GG Q_GL][E_L; E_N],
+  // Z2 = [Q_GL^T Q_LL][E_L; E_N] (N_mu x n_occ); mixed: ELN (row i = [E_L(:, i);
+  // E_N(:, i)]) and Z12 (row i = [Z1(:, i); Z2(:, i)]) planes, and (K C)^T =
+  // -(Z12)(xln)^T as k-range partial products
+  DevBuf EN, Z1, Z2, KCpart, d_zprobs, d_kcprobs;
+  Planes ELN, Z12;
+  int ri_nocc = -1, kcparts = 0, kctiles = 0;
   // factored density: D = C C^T for the energy
   DevBuf Docc;
   // captured exchange: replayed while (mode, operands, K) stay the same
@@ -334,6 +342,7 @@ struct isdf_fit_s {
   const void* xkey_in = nullptr;
   const void* xkey_out = nullptr;
   int xkey_nocc = -1;
+  bool xkey_ri = false;
   void drop_graph() {
     if (xexec) (void)hipGraphExecDestroy(xexec);
     if (xgraph) (void)hipGraphDestroy(xgraph);
@@ -2015,7 +2024,7 @@ isdf_status write_tune_file(const isdf_plan_s* pl, const char* path) {
 // Workspace of the exchange (n_occ = 0: dense D, else the factored form).
 // Everything the kernel sequence touches is sized here, so that the
 // sequence itself allocates nothing and can be captured as a graph.
-isdf_status exchange_prepare(isdf_plan_s* plan, isdf_fit_s* fit, int n_occ) {
+isdf_status exchange_prepare(isdf_plan_s* plan, isdf_fit_s* fit, int n_occ, bool ri) {
   const int64_t nmu = fit->nmu, N = plan->hp.n_basis;
   const int64_t ec = n_occ > 0 ? n_occ : N;  // columns of E_G, E_L
   isdf_status st;
@@ -2130,6 +2139,50 @@ isdf_status exchange_prepare(isdf_plan_s* plan, isdf_fit_s* fit, int n_occ) {
       if ((st = upload(fit->d_qprobs, qp)) != ISDF_OK) return st;
       fit->qprobs_nocc = n_occ;
     }
+  }
+  if (ri && fit->ri_nocc != n_occ) {
+    const int m = (int)nmu, n = (int)N, o = n_occ;
+    for (DevBuf* b : {&fit->EN, &fit->Z1, &fit->Z2})
+      if ((st = b->alloc(sizeof(double) * nmu * o)) != ISDF_OK) return st;
+    if (mixed) {
+      const int S = mixed_splits(plan);
+      for (Planes* q : {&fit->ELN, &fit->Z12}) {
+        if ((st = size_planes(S, o, 2 * m, *q)) != ISDF_OK) return st;
+        q->rows = o;
+        q->cols = 2 * m;
+        q->ld = (2 * m + 7) / 8 * 8;
+        q->plane = (int64_t)o * q->ld;
+      }
+      // Z1 = Q1 ELN^T, Z2 = Q2 ELN^T: one grouped launch
+      std::vector<MixedProblem> zp(2);
+      int tiles = 0;
+      for (int i = 0; i < 2; ++i) {
+        zp[i] = mixed_problem(i == 0 ? fit->Q1 : fit->Q2, fit->ELN, (i == 0 ? fit->Z1 : fit->Z2).as<double>(),
+                              nmu, m, o, 2 * m, 1.0, 0.0, nullptr, 0);
+        zp[i].tile_start = tiles;
+        tiles += mixed_tiles_wide(m, o);
+      }
+      if ((st = upload(fit->d_zprobs, zp)) != ISDF_OK) return st;
+      // (K C)^T = -(Z12)(xln)^T over k ranges, partials summed in order
+      const int kc = std::max(32, (2 * m + KSPLIT_RI - 1) / KSPLIT_RI / 32 * 32);
+      std::vector<MixedProblem> kp;
+      tiles = 0;
+      for (int k0 = 0; k0 < 2 * m; k0 += kc) {
+        MixedProblem q = mixed_problem(fit->Z12, fit->xln, nullptr, o, o, n, std::min(kc, 2 * m - k0), -1.0,
+                                       0.0, nullptr, 0);
+        q.A += k0;
+        q.B += k0;
+        q.tile_start = tiles;
+        tiles += mixed_tiles(o, n);
+        kp.push_back(q);
+      }
+      fit->kcparts = (int)kp.size();
+      fit->kctiles = tiles;
+      if ((st = fit->KCpart.alloc(sizeof(double) * (size_t)fit->kcparts * o * n)) != ISDF_OK) return st;
+      for (int i = 0; i < fit->kcparts; ++i) kp[i].C = fit->KCpart.as<double>() + (int64_t)i * o * n;
+      if ((st = upload(fit->d_kcprobs, kp)) != ISDF_OK) return st;
+    }
+    fit->ri_nocc = n_occ;
   }
   return ISDF_OK;
 }
@@ -2249,8 +2302,108 @@ isdf_status exchange_enqueue(isdf_plan_s* plan, isdf_fit_s* fit, const double* i
   return launch_trace_dot(s, Dm, K, N * N, fit->partial.as<double>(), 1024, fit->ex_out.as<double>());
 }
 
+// occ-RI output on plan->stream (no allocation, no synchronisation):
+// KC = K C (N x n_occ, row-major like C) for D = C C^T, without forming K:
+// E_L = X^L C, E_N = X^N C, Z1 = Q_GG E_L + Q_GL E_N, Z2 = Q_GL^T E_L +
+// Q_LL E_N, K C = -(X^L' Z1 + X^N' Z2); e_x = sum(C o KC) = tr(D K).
+isdf_status exchange_enqueue_ri(isdf_plan_s* plan, isdf_fit_s* fit, const double* Cin, int n_occ, double* KC,
+                                bool stage_event) {
+  hipStream_t s = plan->stream;
+  const int64_t nmu = fit->nmu, N = plan->hp.n_basis;
+  const int m = (int)nmu, n = (int)N, o = n_occ;
+  const double* XL = fit->XL.as<double>();
+  const double* XN = fit->XN.as<double>();
+  const double* XG = fit->XG.as<double>();
+  const double* W = fit->W.as<double>();
+  double* EG = fit->EG.as<double>();
+  double* EL = fit->EL.as<double>();
+  double* EN = fit->EN.as<double>();
+  double* Z1 = fit->Z1.as<double>();
+  double* Z2 = fit->Z2.as<double>();
+  isdf_status st;
+  auto gemm = [&](int epi, const double* A, int64_t lda, int tA, const double* B, int64_t ldb, int tB,
+                  double* C, int64_t ldc, int M, int Nn, int Kk, double alpha, double beta, const double* E) {
+    GemmProblem p{};
+    p.A = A; p.lda = lda; p.transA = tA;
+    p.B = B; p.ldb = ldb; p.transB = tB;
+    p.C = C; p.ldc = ldc;
+    p.E = E; p.lde = nmu;
+    p.M = M; p.N = Nn; p.K = Kk;
+    p.alpha = alpha; p.beta = beta;
+    return gemm_prof(plan, ISDF_K_GEMM_EXCHANGE, epi, p);
+  };
+  if (mixed_on(plan, ISDF_MIX_EXCHANGE)) {
+    const int S = mixed_splits(plan);
+    if ((st = make_planes(s, S, Cin, 1, o, nullptr, o, n, fit->Dp)) != ISDF_OK) return st;
+    for (int t = 0; t < 2; ++t) {
+      MixedProblem q = mixed_problem(t == 0 ? fit->xg_row : fit->xl_row, fit->Dp, t == 0 ? EG : EL, nmu, m, o, n,
+                                     1.0, 0.0, nullptr, 0);
+      if ((st = mixed_prof(plan, ISDF_K_GEMM_EXCHANGE, EPI_AXPBY, q)) != ISDF_OK) return st;
+    }
+    if ((st = launch_sub(s, EG, EL, EN, nmu * o)) != ISDF_OK) return st;
+    if ((st = make_planes(s, S, EG, 1, nmu, nullptr, m, o, fit->EGp)) != ISDF_OK) return st;
+    if ((st = make_planes(s, S, EL, 1, nmu, nullptr, m, o, fit->ELp)) != ISDF_OK) return st;
+    {  // Q1 = [Q_GG Q_GL], Q2 = [Q_GL^T Q_LL] as split planes (exchange_prepare)
+      ProfScope ps(plan, ISDF_K_GEMM_EXCHANGE,
+                   4.0 * (2.0 * S * 2.0 * m * (double)o + 2.0 * S * (double)m * m) + 8.0 * (double)m * m,
+                   4.0 * 2.0 * m * (double)m * o);
+      if ((st = gemm_mixed_wide_grouped(s, EPI_HADAMARD_PLANES, S, fit->d_qprobs.as<MixedProblem>(), -4,
+                                        4 * mixed_tiles_wide(m, m), family_tag(ISDF_K_GEMM_EXCHANGE))) != ISDF_OK)
+        return st;
+    }
+    __bf16* eb = static_cast<__bf16*>(fit->ELN.buf.p);
+    if ((st = launch_split_bf16(s, EL, nmu, 1, nullptr, o, m, S, eb, fit->ELN.ld, fit->ELN.plane, 1.0)) != ISDF_OK)
+      return st;
+    if ((st = launch_split_bf16(s, EN, nmu, 1, nullptr, o, m, S, eb + m, fit->ELN.ld, fit->ELN.plane, 1.0)) !=
+        ISDF_OK)
+      return st;
+    {  // Z1 = Q1 ELN^T, Z2 = Q2 ELN^T
+      ProfScope ps(plan, ISDF_K_GEMM_EXCHANGE, 2.0 * (2.0 * S * (2.0 * m * m + 2.0 * m * o) + 8.0 * m * o),
+                   2.0 * (2.0 * m * (double)o * 2.0 * m));
+      if ((st = gemm_mixed_wide_grouped(s, EPI_AXPBY, S, fit->d_zprobs.as<MixedProblem>(), 2,
+                                        2 * mixed_tiles_wide(m, o), family_tag(ISDF_K_GEMM_EXCHANGE))) != ISDF_OK)
+        return st;
+    }
+    __bf16* zb = static_cast<__bf16*>(fit->Z12.buf.p);
+    if ((st = launch_split_bf16(s, Z1, nmu, 1, nullptr, o, m, S, zb, fit->Z12.ld, fit->Z12.plane, 1.0)) != ISDF_OK)
+      return st;
+    if ((st = launch_split_bf16(s, Z2, nmu, 1, nullptr, o, m, S, zb + m, fit->Z12.ld, fit->Z12.plane, 1.0)) !=
+        ISDF_OK)
+      return st;
+    {  // (K C)^T = -(Z12)(xln)^T: partial products over k ranges, then their ordered sum
+      ProfScope ps(plan, ISDF_K_GEMM_EXCHANGE, 2.0 * S * (2.0 * m * (o + n)) + 8.0 * fit->kcparts * o * (double)n,
+                   2.0 * o * (double)n * 2.0 * m);
+      if ((st = gemm_mixed_grouped(s, EPI_AXPBY, S, fit->d_kcprobs.as<MixedProblem>(), fit->kcparts, fit->kctiles,
+                                   family_tag(ISDF_K_GEMM_EXCHANGE))) != ISDF_OK)
+        return st;
+    }
+    if ((st = launch_sum_parts(s, fit->KCpart.as<double>(), fit->kcparts, (int64_t)o * n, KC)) != ISDF_OK)
+      return st;
+  } else {
+    if ((st = gemm(EPI_AXPBY, XG, nmu, 0, Cin, o, 1, EG, nmu, m, o, n, 1.0, 0.0, nullptr)) != ISDF_OK) return st;
+    if ((st = gemm(EPI_AXPBY, XL, nmu, 0, Cin, o, 1, EL, nmu, m, o, n, 1.0, 0.0, nullptr)) != ISDF_OK) return st;
+    if ((st = launch_sub(s, EG, EL, EN, nmu * o)) != ISDF_OK) return st;
+    double* QGG = fit->QGG.as<double>();
+    double* QGL = fit->QGL.as<double>();
+    double* QLL = fit->QLL.as<double>();
+    if ((st = gemm(EPI_HADAMARD, EG, nmu, 0, EG, nmu, 1, QGG, nmu, m, m, o, 1.0, 0.0, W)) != ISDF_OK) return st;
+    if ((st = gemm(EPI_HADAMARD, EG, nmu, 0, EL, nmu, 1, QGL, nmu, m, m, o, 1.0, 0.0, W)) != ISDF_OK) return st;
+    if ((st = gemm(EPI_HADAMARD, EL, nmu, 0, EL, nmu, 1, QLL, nmu, m, m, o, 1.0, 0.0, W)) != ISDF_OK) return st;
+    if ((st = gemm(EPI_AXPBY, QGG, nmu, 0, EL, nmu, 0, Z1, nmu, m, o, m, 1.0, 0.0, nullptr)) != ISDF_OK) return st;
+    if ((st = gemm(EPI_AXPBY, QGL, nmu, 0, EN, nmu, 0, Z1, nmu, m, o, m, 1.0, 1.0, nullptr)) != ISDF_OK) return st;
+    if ((st = gemm(EPI_AXPBY, QGL, nmu, 1, EL, nmu, 0, Z2, nmu, m, o, m, 1.0, 0.0, nullptr)) != ISDF_OK) return st;
+    if ((st = gemm(EPI_AXPBY, QLL, nmu, 0, EN, nmu, 0, Z2, nmu, m, o, m, 1.0, 1.0, nullptr)) != ISDF_OK) return st;
+    // (K C)^T (n_occ x N column-major = K C row-major) = -(Z1' X^L + Z2' X^N)
+    if ((st = gemm(EPI_AXPBY, Z1, nmu, 1, XL, nmu, 0, KC, o, o, n, m, -1.0, 0.0, nullptr)) != ISDF_OK) return st;
+    if ((st = gemm(EPI_AXPBY, Z2, nmu, 1, XN, nmu, 0, KC, o, o, n, m, -1.0, 1.0, nullptr)) != ISDF_OK) return st;
+  }
+  if (stage_event) ISDF_HIP_TRY(hipEventRecord(plan->ev[1], s));
+  return launch_trace_dot(s, Cin, KC, N * o, fit->partial.as<double>(), 1024, fit->ex_out.as<double>());
+}
+
+// ri: occ-RI output (exchange_enqueue_ri), else the full K.
 isdf_status exchange_run(isdf_plan_s* plan, isdf_fit_s* fit, const double* in, int n_occ, double* K,
-                         double* e_x) {
+                         double* e_x, bool ri = false) {
   if (fit->plan != plan) {
     set_error("isdf_exchange: fit belongs to another plan");
     return ISDF_E_STATE;
@@ -2258,10 +2411,15 @@ isdf_status exchange_run(isdf_plan_s* plan, isdf_fit_s* fit, const double* in, i
   MemScope mscope(plan->mem);
   hipStream_t s = plan->stream;
   isdf_status st;
-  if ((st = exchange_prepare(plan, fit, n_occ)) != ISDF_OK) return st;
+  if ((st = exchange_prepare(plan, fit, n_occ, ri)) != ISDF_OK) return st;
+  auto enqueue = [&](bool stage_event) {
+    return ri ? exchange_enqueue_ri(plan, fit, in, n_occ, K, stage_event)
+              : exchange_enqueue(plan, fit, in, n_occ, K, stage_event);
+  };
   const bool graph = plan->opts.eager_exchange == 0 && !((plan->prof >> ISDF_K_GEMM_EXCHANGE) & 1) &&
                      !plan->tuning;
-  if (graph && (!fit->xexec || fit->xkey_in != in || fit->xkey_out != K || fit->xkey_nocc != n_occ)) {
+  if (graph && (!fit->xexec || fit->xkey_in != in || fit->xkey_out != K || fit->xkey_nocc != n_occ ||
+                fit->xkey_ri != ri)) {
     fit->drop_graph();
     if (!plan->cap_stream)
       ISDF_HIP_TRY(hipStreamCreateWithFlags(&plan->cap_stream, hipStreamNonBlocking));
@@ -2274,7 +2432,7 @@ isdf_status exchange_run(isdf_plan_s* plan, isdf_fit_s* fit, const double* in, i
       set_error(std::string("isdf_exchange: graph capture: ") + hipGetErrorString(e));
       return ISDF_E_HIP;
     }
-    st = exchange_enqueue(plan, fit, in, n_occ, K, false);
+    st = enqueue(false);
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(plan->cap_stream, &g);
     plan->stream = s;
@@ -2298,12 +2456,13 @@ isdf_status exchange_run(isdf_plan_s* plan, isdf_fit_s* fit, const double* in, i
     fit->xkey_in = in;
     fit->xkey_out = K;
     fit->xkey_nocc = n_occ;
+    fit->xkey_ri = ri;
   }
   ISDF_HIP_TRY(hipEventRecord(plan->ev[0], s));
   if (graph) {
     ISDF_HIP_TRY(hipGraphLaunch(fit->xexec, s));
   } else {
-    if ((st = exchange_enqueue(plan, fit, in, n_occ, K, true)) != ISDF_OK) return st;
+    if ((st = enqueue(true)) != ISDF_OK) return st;
   }
   ISDF_HIP_TRY(hipEventRecord(plan->ev[2], s));
   double ex = 0.0;
@@ -2791,6 +2950,19 @@ isdf_status isdf_exchange_occ(isdf_plan_t plan, isdf_fit_t fit, const double* C_
     return ISDF_E_ARG;
   }
   return exchange_run(plan, fit, C_occ, n_occ, K, e_x);
+}
+
+isdf_status isdf_exchange_occ_ri(isdf_plan_t plan, isdf_fit_t fit, const double* C_occ, int32_t n_occ,
+                                 double* KC, double* e_x) {
+  if (!plan || !fit || !C_occ || !KC || n_occ < 1) {
+    set_error("isdf_exchange_occ_ri: null argument or n_occ < 1");
+    return ISDF_E_ARG;
+  }
+  if (n_occ > plan->hp.n_basis) {
+    set_error("isdf_exchange_occ_ri: n_occ above the basis size");
+    return ISDF_E_ARG;
+  }
+  return exchange_run(plan, fit, C_occ, n_occ, KC, e_x, true);
 }
 
 isdf_status isdf_autotune(isdf_plan_t plan, int32_t n_occ, int32_t reps, const char* json_out) {

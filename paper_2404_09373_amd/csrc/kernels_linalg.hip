@@ -168,18 +168,25 @@ isdf_status launch_fill(hipStream_t s, double* p, int64_t n, double v) {
   return ISDF_OK;
 }
 
-__global__ void add_kernel(const double* a, const double* b, double* c, int64_t n) {
+__global__ void add_kernel(const double* a, const double* b, double* c, int64_t n, double sb) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
-    c[i] = a[i] + b[i];
+    c[i] = a[i] + sb * b[i];
 }
-isdf_status launch_add(hipStream_t s, const double* a, const double* b, double* c, int64_t n) {
+static isdf_status launch_add_scaled(hipStream_t s, const double* a, const double* b, double* c, int64_t n,
+                                     double sb) {
   if (n <= 0) return ISDF_OK;
   int64_t blocks = (n + 255) / 256;
   if (blocks > 65536) blocks = 65536;
-  hipLaunchKernelGGL(add_kernel, dim3((unsigned)blocks), dim3(256), 0, s, a, b, c, n);
+  hipLaunchKernelGGL(add_kernel, dim3((unsigned)blocks), dim3(256), 0, s, a, b, c, n, sb);
   ISDF_HIP_TRY(hipGetLastError());
   return ISDF_OK;
+}
+isdf_status launch_add(hipStream_t s, const double* a, const double* b, double* c, int64_t n) {
+  return launch_add_scaled(s, a, b, c, n, 1.0);
+}
+isdf_status launch_sub(hipStream_t s, const double* a, const double* b, double* c, int64_t n) {
+  return launch_add_scaled(s, a, b, c, n, -1.0);
 }
 
 // M(i, j) = Theta(piv_i, j), n x n column-major

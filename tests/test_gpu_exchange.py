@@ -111,3 +111,80 @@ def test_graph_replays_match_eager(torch, cfg1, precision, occ):
         f.close()
     for p in (pg, pe):
         p.close()
+
+
+# ---------------------------------------------------------------- occ-RI
+@pytest.mark.parametrize("precision", [binding.FP64, binding.MIXED_X6])
+def test_occ_ri_matches_oracle_and_full(torch, cfg1, precision):
+    """K C without forming K equals the oracle's K applied to C (the oracle's
+    occ-RI form is pinned against its full K) and the library's own full K
+    times C, with the same energy."""
+    from oracle import exchange, pipeline
+
+    s = cfg1
+    ref = pipeline.run(s)
+    KC_ref = exchange.exchange_occ_ri(ref.XL, ref.XN, ref.W, s.C_occ)
+    plan = binding.Plan(s, precision=precision)
+    fit = plan.fit()
+    C = torch.tensor(s.C_occ, dtype=torch.float64, device="cuda")
+    KC, e = fit.exchange_occ_ri(C)
+    K, e_full = fit.exchange_occ(C)
+    KC = KC.cpu().numpy()
+    KC_full = K.cpu().numpy() @ s.C_occ
+    scale = float(np.max(np.abs(KC_ref)))
+    d_ref = float(np.max(np.abs(KC - KC_ref))) / scale
+    d_full = float(np.max(np.abs(KC - KC_full))) / scale
+    dE = abs(e - ref.E_x) / s.n_atoms
+    print(f"[occ-ri] precision {precision}: rel max|dKC| vs oracle {d_ref:.2e}, vs full K {d_full:.2e}, "
+          f"|dE|/atom {dE:.2e}, E_x {e:.10f} / full {e_full:.10f}")
+    if precision == binding.FP64:
+        assert d_ref <= 1e-9 and d_full <= 1e-12 and dE <= 1e-6
+    else:
+        assert d_ref <= 1e-5 and d_full <= 1e-5 and dE <= 1e-6
+    fit.close()
+    plan.close()
+
+
+@pytest.mark.parametrize("precision", [binding.FP64, binding.MIXED_X6])
+def test_occ_ri_graph_replays_match_eager(torch, cfg1, precision):
+    s = cfg1
+    pg = binding.Plan(s, precision=precision)
+    pe = binding.Plan(s, precision=precision, eager_exchange=True)
+    fg, fe = pg.fit(), pe.fit()
+    base = torch.tensor(s.C_occ, dtype=torch.float64, device="cuda")
+    buf = base.clone()
+    KCg = torch.empty_like(buf)
+    gen = torch.Generator(device="cuda").manual_seed(7)
+    for r in range(4):
+        buf.copy_(base * (1.0 + 0.05 * r))
+        x = torch.randn((512, 512), generator=gen, device="cuda", dtype=torch.float64)
+        y = (x @ x.T).sum().item()
+        torch.cuda.synchronize()
+        _, eg = fg.exchange_occ_ri(buf, KCg)
+        KCe, ee = fe.exchange_occ_ri(buf.clone())
+        torch.cuda.synchronize()
+        assert np.isfinite(y)
+        same = torch.equal(KCg, KCe)
+        print(f"[occ-ri graph] precision {precision} replay {r}: bitwise {same}, e {eg:.12f} / {ee:.12f}")
+        assert same and eg == ee
+    for f in (fg, fe):
+        f.close()
+    for p in (pg, pe):
+        p.close()
+
+
+def test_occ_ri_rejects_bad_arguments(torch, cfg1):
+    plan = binding.Plan(cfg1)
+    fit = plan.fit()
+    n = plan.n_basis
+    with pytest.raises(ValueError):
+        fit.exchange_occ_ri(torch.zeros((n + 1, 4), dtype=torch.float64, device="cuda"))
+    KC = torch.empty((n, 4), dtype=torch.float64, device="cuda")
+    C0 = torch.zeros((n, 4), dtype=torch.float64, device="cuda")
+    lib = binding.load()
+    assert lib.isdf_exchange_occ_ri(plan.handle, fit.handle, binding.C.c_void_p(C0.data_ptr()), 0,
+                                    binding.C.c_void_p(KC.data_ptr()), None) == -1  # ISDF_E_ARG
+    assert lib.isdf_exchange_occ_ri(plan.handle, fit.handle, binding.C.c_void_p(C0.data_ptr()), n + 1,
+                                    binding.C.c_void_p(KC.data_ptr()), None) == -1
+    fit.close()
+    plan.close()
