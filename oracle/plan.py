@@ -29,7 +29,11 @@ Readings (the paper is silent or ambiguous):
   atoms only to the window of the lower atom index removes the double count
   that the literal L/G/N sets would give.
 * Points per domain: N_mu,d = floor(r |L_d| + 1/2), capped at the domain's
-  point count (r <= 0: all points, stop by eps_isdf only).
+  point count.  r <= 0 (threshold only, stop by eps_isdf): N_mu,d is the
+  smaller of the point count and |L|(|L| + 1)/2 + |L||N|, the number of
+  distinct pair products the domain fits, which bounds the rank of its pair
+  Gram (Eq. M(R,R)), so the cap never ends a selection that the threshold
+  would continue.
 """
 from __future__ import annotations
 
@@ -209,9 +213,9 @@ def build_plan(sysm) -> Plan:
     widths = perpendicular_widths(lattice)
     ratio = float(sysm.n_mu_ratio)
 
-    def n_mu_for(nL: int, npts: int) -> int:
+    def n_mu_for(nL: int, nN: int, npts: int) -> int:
         if ratio <= 0:
-            return npts
+            return int(min(npts, nL * (nL + 1) // 2 + nL * nN))
         return int(min(np.floor(ratio * nL + 0.5), npts))
 
     domains: List[Domain] = []
@@ -221,7 +225,7 @@ def build_plan(sysm) -> Plan:
         npts = int(np.prod(grids[0]))
         domains.append(
             Domain(0, -1, np.arange(npts, dtype=np.int64), L0, np.zeros(0, dtype=np.int64),
-                   n_mu_for(L0.size, npts), np.inf)
+                   n_mu_for(L0.size, 0, npts), np.inf)
         )
     # atom windows on finer levels
     for lev in range(1, nlev):
@@ -244,7 +248,7 @@ def build_plan(sysm) -> Plan:
                 if dist_cache[B] <= np.sqrt(ln_inv_tau / f_alpha[f]) + r_max:
                     keep.append(f)
             N = np.array(keep, dtype=np.int64)
-            domains.append(Domain(lev, A, pts, L, N, n_mu_for(L.size, pts.size), r_max))
+            domains.append(Domain(lev, A, pts, L, N, n_mu_for(L.size, N.size, pts.size), r_max))
 
     return Plan(
         lattice=lattice,
@@ -262,3 +266,61 @@ def build_plan(sysm) -> Plan:
         ln_inv_tau=float(ln_inv_tau),
         volume=float(abs(np.linalg.det(lattice))),
     )
+
+
+def _smooth235(n: int) -> bool:
+    for p in (2, 3, 5):
+        while n % p == 0:
+            n //= p
+    return n == 1
+
+
+def grids_for_threshold(lattice, shell_alpha, alpha_bound, eps_K: float) -> np.ndarray:
+    """Grid ladder [n_levels, 3] from the Fourier threshold eps_K (Eq. Ggrid
+    and the threshold table of the "Computational details" section).
+
+    Readings: the exponent of Eq. Ggrid for a level is the largest exponent
+    living on it (the shell level rule above), G_max = sqrt(-4 a ln eps_K);
+    every reciprocal vector G = 2 pi m . B (B rows: b_j with a_i . b_j =
+    delta_ij) with |G| <= G_max must lie in the kept band, which for an even
+    axis of n points is |m_i| <= n/2 - 1 (the Nyquist plane is not kept);
+    axes are even and 2,3,5-smooth; a level is never coarser than the one
+    below it.
+    """
+    lattice = np.asarray(lattice, dtype=np.float64).reshape(3, 3)
+    alphas = np.asarray(shell_alpha, dtype=np.float64)
+    bounds = np.asarray(alpha_bound, dtype=np.float64).reshape(-1)
+    if not (0.0 < eps_K < 1.0) or np.any(~(alphas > 0)):
+        raise ValueError("eps_K must lie in (0, 1) and exponents must be positive")
+    nlev = bounds.size + 1
+    level = np.full(alphas.size, nlev - 1)
+    for s, a in enumerate(alphas):
+        for lev in range(nlev - 1):
+            if a < bounds[lev]:
+                level[s] = lev
+                break
+    recip = np.linalg.inv(lattice).T  # rows b_j
+    out = np.zeros((nlev, 3), dtype=np.int64)
+    for lev in range(nlev):
+        on = alphas[level == lev]
+        if on.size == 0:
+            raise ValueError(f"level {lev} holds no shell")
+        gmax = np.sqrt(-4.0 * on.max() * np.log(eps_K))
+        lim = np.floor(gmax * np.linalg.norm(lattice, axis=1) / (2.0 * np.pi)).astype(np.int64)
+        need = np.zeros(3, dtype=np.int64)
+        m2, m3 = np.meshgrid(np.arange(-lim[1], lim[1] + 1), np.arange(-lim[2], lim[2] + 1), indexing="ij")
+        m2, m3 = m2.ravel(), m3.ravel()
+        for m1 in range(-lim[0], lim[0] + 1):
+            M = np.stack([np.full(m2.size, m1), m2, m3], axis=1)
+            G = 2.0 * np.pi * (M @ recip)
+            inside = np.sum(G * G, axis=1) <= gmax * gmax
+            if inside.any():
+                need = np.maximum(need, np.abs(M[inside]).max(axis=0))
+        for i in range(3):
+            n = 2 * (int(need[i]) + 1)
+            while not _smooth235(n):
+                n += 2
+            if lev > 0:
+                n = max(n, int(out[lev - 1, i]))
+            out[lev, i] = n
+    return out

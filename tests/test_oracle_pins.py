@@ -444,3 +444,114 @@ def test_restricted_selection_equals_full_on_needed_set():
         assert isdf.restriction_is_exact(d0, cand, Lr[piv_r[-1], len(piv_r) - 1] ** 2, s.tie_tol)
         worst = need[np.argmin(d0[need])]
         assert not isdf.restriction_is_exact(d0, np.setdiff1d(cand, [worst]), dlast, s.tie_tol)
+
+
+# ------------------------------------------- thresholds (Eq. Ggrid, rank cap)
+def _gaussian_spectrum(lattice, alpha, nref=48):
+    """|DFT| / DFT[0] of the periodic Gaussian sum_T exp(-alpha |r - T|^2)
+    sampled on an nref^3 grid; nref is chosen so that the Gaussian's
+    spectrum is below 1e-16 at the reference grid's Nyquist plane, so the
+    values are its Fourier coefficients (no aliasing at the levels tested)."""
+    f = np.arange(nref) / nref
+    F = np.stack(np.meshgrid(f, f, f, indexing="ij"), axis=-1).reshape(-1, 3)
+    R = F @ lattice
+    vol = abs(np.linalg.det(lattice))
+    width = min(vol / np.linalg.norm(np.cross(lattice[(i + 1) % 3], lattice[(i + 2) % 3])) for i in range(3))
+    k = int(np.ceil(np.sqrt(np.log(1e18) / alpha) / width)) + 1
+    vals = np.zeros(R.shape[0])
+    for n1 in range(-k, k + 1):
+        for n2 in range(-k, k + 1):
+            for n3 in range(-k, k + 1):
+                d = R - np.array([n1, n2, n3], dtype=np.float64) @ lattice
+                vals += np.exp(-alpha * np.sum(d * d, axis=1))
+    c = np.abs(np.fft.fftn(vals.reshape(nref, nref, nref)))
+    m = np.rint(np.fft.fftfreq(nref) * nref).astype(int)
+    M = np.stack(np.meshgrid(m, m, m, indexing="ij"), axis=-1)
+    return c / c[0, 0, 0], M
+
+
+def _smaller_even_smooth(n):
+    for c in range(n - 2, 1, -2):
+        if all(p in (2, 3, 5) for p in _prime_factors(c)):
+            return c
+    return None
+
+
+def _prime_factors(n):
+    out, p = [], 2
+    while n > 1:
+        while n % p == 0:
+            out.append(p)
+            n //= p
+        p += 1
+    return out
+
+
+_SKEWED = np.array([[6.0, 0.0, 0.0], [1.5, 5.5, 0.0], [0.8, 1.1, 5.2]])
+_OBLIQUE = np.array([[7.0, 0.0, 0.0], [3.5, 3.0, 0.0], [1.0, 1.0, 4.0]])
+
+
+@pytest.mark.parametrize("lattice,alpha,eps", [
+    (np.eye(3) * 6.74, 0.45, 1e-2), (np.eye(3) * 6.74, 1.35, 1e-2), (np.eye(3) * 6.74, 1.35, 1e-3),
+    (np.eye(3) * 6.74, 1.35, 1e-5), (np.eye(3) * 6.74, 0.45, 1e-8), (np.eye(3) * 6.74, 0.3, 0.3),
+    (_SKEWED, 0.8, 1e-2), (_SKEWED, 0.8, 1e-4), (_SKEWED, 1.2, 1e-6),
+    (_OBLIQUE, 0.8, 1e-2), (_OBLIQUE, 0.8, 1e-4), (_OBLIQUE, 0.3, 1e-3),
+])
+def test_threshold_grid_resolves_the_gaussian(lattice, alpha, eps):
+    """The eps_K grid (Eq. Ggrid) keeps every Fourier coefficient of the
+    level's sharpest Gaussian that is at least eps_K of the mean, measured by
+    FFT of its samples: every coefficient outside the kept band |m_i| <=
+    n_i/2 - 1 is below eps_K, and on the next smaller even smooth length of
+    any axis some dropped coefficient is not (minimality).  Catches a wrong
+    factor in G_max (2 alpha, ln without the 4), a kept Nyquist plane and a
+    transposed reciprocal basis (skewed cell)."""
+    n = oplan.grids_for_threshold(lattice, [0.1, alpha], [], eps)[0]
+    rel, M = _gaussian_spectrum(lattice, alpha)
+    outside = np.any(np.abs(M) >= n // 2, axis=-1)
+    assert rel[outside].max() < eps
+    for i in range(3):
+        n_small = _smaller_even_smooth(int(n[i]))
+        if n_small is None:
+            continue
+        dropped = np.abs(M[..., i]) >= n_small // 2
+        assert rel[dropped].max() >= eps, f"axis {i}: {n_small} would do"
+
+
+def test_threshold_ladder_levels():
+    """Two levels: the coarse grid follows the largest exponent below the
+    bound, the fine grid the largest overall, and the fine grid is never
+    coarser than the coarse one (catches the level rule applied with <=,
+    or the wrong exponent per level)."""
+    lat = np.eye(3) * 6.74
+    g = oplan.grids_for_threshold(lat, [0.15, 1.35, 2.0, 12.15], [2.0], 1e-2)
+    coarse = oplan.grids_for_threshold(lat, [0.15, 1.35], [], 1e-2)[0]
+    fine = oplan.grids_for_threshold(lat, [2.0, 12.15], [], 1e-2)[0]
+    assert np.array_equal(g[0], coarse) and np.array_equal(g[1], fine)
+    # a sharp exponent sits exactly at the bound: it belongs to the fine level
+    g2 = oplan.grids_for_threshold(lat, [0.15, 2.0], [2.0], 1e-2)
+    assert np.array_equal(g2[0], oplan.grids_for_threshold(lat, [0.15], [], 1e-2)[0])
+    # a fine level below the coarse one is raised to it
+    g3 = oplan.grids_for_threshold(lat, [0.16, 1.9, 2.0], [1.95], 1e-2)
+    assert np.all(g3[1] >= g3[0])
+    with pytest.raises(ValueError):
+        oplan.grids_for_threshold(lat, [0.15, 0.3], [2.0], 1e-2)  # fine level empty
+
+
+def test_threshold_only_cap_bounds_the_pair_rank():
+    """With r <= 0 the plan caps N_mu,d at |L|(|L|+1)/2 + |L||N|.  The
+    numerical rank of every domain's pair Gram (Eq. M(R,R)) is at most that
+    bound, and the eps-only selection stops by the threshold at or below
+    it, so the cap never cuts a selection short (catches a cap that counts
+    only L L pairs or forgets the L N pairs)."""
+    s = tiny_system("two_atom", grids=((10, 10, 10), (16, 16, 16)), n_mu_ratio=0.0)
+    p = oplan.build_plan(s)
+    for dom in p.domains:
+        Phi = basis.domain_values(p, dom)
+        nL, nN = dom.L.size, dom.N.size
+        M = isdf.gram_columns(Phi, nL, np.arange(Phi.shape[0]))
+        rank = np.linalg.matrix_rank(M, tol=1e-12 * np.max(np.abs(M)))
+        assert rank <= nL * (nL + 1) // 2 + nL * nN
+        assert dom.n_mu == min(dom.points.size, nL * (nL + 1) // 2 + nL * nN)
+        piv, _, d, d0 = isdf.pivoted_cholesky(Phi, nL, dom.n_mu, 1e-10, s.tie_tol)
+        assert piv.size < dom.n_mu or np.max(d) <= 1e-10 * np.max(d0)
+        assert abs(piv.size - rank) <= max(2, rank // 10)
