@@ -266,6 +266,113 @@ def cpu_baseline(sysm):
 
 TUNE_FILE = os.path.join(ROOT, "paper_2404_09373_amd", "tune", "gfx950.json")
 
+# Threshold-driven diamond cells of the studies: two levels split at
+# alpha = 2 (the sharp 4.05 and 12.15 shells on atom windows), grids from
+# eps_K (Eq. Ggrid), point counts from eps_ISDF with a ratio cap that only
+# bounds memory (the studies report when it binds).
+STUDY_EPS_K = 1e-2
+
+
+def _study_system(binding, reps, eps_isdf, ratio_cap, with_density, seed):
+    from workloads import diamond_system
+
+    n_cells = reps[0] * reps[1] * reps[2]
+    s = diamond_system(reps, ((24, 24, 24), (48, 48, 48)), ratio_cap, 16 * n_cells, 0.05, 0.0,
+                       seed, seed + 1, alpha_bound=[2.0], name=f"diamond{reps}",
+                       with_density=with_density)
+    s.grids = binding.grids_for_threshold(s.lattice, s.shell_alpha, s.alpha_bound, STUDY_EPS_K)
+    s.eps_isdf = eps_isdf
+    return s
+
+
+def _fit_counts(plan, fit):
+    pts = [fit.get("points", d).size for d in range(plan.n_domains)]
+    caps = [plan.domain(d)["n_mu"] for d in range(plan.n_domains)]
+    return pts[0], int(sum(pts[1:])), int(sum(p == c for p, c in zip(pts, caps)))
+
+
+def study_thresholds(torch, binding, log):
+    """Error per atom against eps_ISDF at fixed eps_K = 1e-2 on cells of 8 to
+    64 atoms (the local-fitting and size-independence studies of the
+    Results section), FP64.  The error is taken against the same cell fitted
+    at eps_ISDF = 1e-7 on the same grids."""
+    out = []
+    for reps in [(1, 1, 1), (2, 1, 1), (2, 2, 1), (2, 2, 2)]:
+        s = _study_system(binding, reps, 1e-7, 16.0, True, 600 + 2 * sum(reps))
+        D = torch.tensor(s.D, dtype=torch.float64, device="cuda")
+        energies = {}
+        for eps in (1e-7, 1e-2, 1e-3, 1e-4, 1e-5):
+            s.eps_isdf = eps
+            plan = binding.Plan(s)
+            fit = plan.fit()
+            _, e = fit.exchange(D)
+            n_u, n_loc, capped = _fit_counts(plan, fit)
+            energies[eps] = e
+            rec = {"study": "thresholds", "cell": list(reps), "atoms": s.n_atoms, "N": s.n_basis,
+                   "grids": s.grids.tolist(), "eps_K": STUDY_EPS_K, "eps_isdf": eps,
+                   "n_xi_local": n_loc, "n_xi_universal": n_u, "domains_at_cap": capped,
+                   "E_x": e, "abs_dE_per_atom_vs_1e-7": abs(e - energies[1e-7]) / s.n_atoms}
+            out.append(rec)
+            print(json.dumps(rec), flush=True)
+            fit.close()
+            plan.close()
+        log(f"thresholds {reps} done")
+    return out
+
+
+def study_scaling(torch, binding, log, reps_list=None, repeat=3):
+    """Fit and exchange build times against system size (the scaling study of
+    the Results section): eps_K = 1e-2, eps_ISDF = 1e-4 (the paper's diamond
+    settings), BF16-split x6 contractions, full selection.  The occupied
+    coefficients are seeded Gaussian columns (the build's cost does not
+    depend on their values)."""
+    reps_list = reps_list or [(1, 1, 1), (2, 1, 1), (2, 2, 1), (2, 2, 2), (3, 2, 2), (3, 3, 2), (3, 3, 3)]
+    out = []
+    for reps in reps_list:
+        s = _study_system(binding, reps, 1e-4, 8.0, False, 700 + 2 * sum(reps))
+        n = s.n_basis
+        rng = np.random.default_rng(11)
+        C = torch.tensor(rng.standard_normal((n, s.n_occ)) / np.sqrt(n), dtype=torch.float64, device="cuda")
+        plan = binding.Plan(s, precision=binding.MIXED_X6)
+        plan.fit().close()  # warm: tables, blocks, compiled tile shapes
+        torch.cuda.synchronize()
+        t_fit = []
+        for _ in range(repeat):
+            t0 = time.perf_counter()
+            fit = plan.fit()
+            torch.cuda.synchronize()
+            t_fit.append(time.perf_counter() - t0)
+            if _ < repeat - 1:
+                fit.close()
+        n_u, n_loc, capped = _fit_counts(plan, fit)
+        K = torch.empty((n, n), dtype=torch.float64, device="cuda")
+        KC = torch.empty_like(C)
+        times = {}
+        for name, call in (("exchange_ms", lambda: fit.exchange_occ(C, K)),
+                           ("occ_ri_ms", lambda: fit.exchange_occ_ri(C, KC))):
+            call()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(repeat):
+                call()
+            torch.cuda.synchronize()
+            times[name] = 1e3 * (time.perf_counter() - t0) / repeat
+        rec = {"study": "scaling", "cell": list(reps), "atoms": s.n_atoms, "N": n, "n_occ": s.n_occ,
+               "grids": s.grids.tolist(), "n_xi_universal": n_u, "n_xi_local": n_loc,
+               "domains_at_cap": capped, "fit_ms": 1e3 * min(t_fit), **times}
+        out.append(rec)
+        print(json.dumps(rec), flush=True)
+        fit.close()
+        plan.close()
+        log(f"scaling {reps} done")
+    big = [r for r in out if r["atoms"] >= 32]
+    if len(big) >= 2:
+        lx = np.log([r["N"] for r in big])
+        slope = {k: float(np.polyfit(lx, np.log([r[k] for r in big]), 1)[0])
+                 for k in ("fit_ms", "exchange_ms", "occ_ri_ms")}
+        print(json.dumps({"study": "scaling_exponents", "cells_from_atoms": 32, **slope}), flush=True)
+    return out
+
 
 def main():
     ap = argparse.ArgumentParser()
@@ -278,6 +385,8 @@ def main():
     ap.add_argument("--paths", choices=["both", "reference", "optimized"], default="both")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 2 GiB three times (reference for the HBM byte counters)")
+    ap.add_argument("--study", choices=["thresholds", "scaling"],
+                    help="run a threshold or scaling study (JSON line per measurement) instead of the benchmark")
     args = ap.parse_args()
     if args.copy_calibration:
         import torch
@@ -302,6 +411,10 @@ def main():
         print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
     assert torch.cuda.is_available(), "bench needs a GPU"
+    if args.study:
+        torch.cuda.set_device(0)
+        (study_thresholds if args.study == "thresholds" else study_scaling)(torch, binding, log)
+        return
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     s = config(args.config)

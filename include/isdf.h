@@ -90,7 +90,9 @@ typedef struct {
                                  alpha < alpha_bound[l], else on the finest               */
   double image_tol;           /* periodic-image cutoff tau (e.g. 1e-10)                  */
   double eps_r;               /* window accuracy of Eq. rcut (e.g. 1e-5)                 */
-  double n_mu_ratio;          /* points per owned function; <= 0: threshold only         */
+  double n_mu_ratio;          /* points per owned function; <= 0: threshold only, n_mu,d
+                                 = min(points, |L|(|L|+1)/2 + |L||N|), the rank bound of
+                                 the domain's pair Gram                                   */
   double eps_isdf;            /* relative stop of the pivoted Cholesky (e.g. 1e-14)      */
   double tie_tol;             /* relative tie window of the pivot argmax (e.g. 1e-8)     */
 } isdf_system;
@@ -121,6 +123,26 @@ typedef struct {
  * ISDF_E_UNSUPPORTED for grids that are not 2,3,5-smooth, axes above 256,
  * levels that are not strictly finer, or l > 1. */
 isdf_status isdf_plan(const isdf_system* sys, const isdf_options* opts, isdf_plan_t* out);
+
+/* Grid ladder from the Fourier threshold eps_K (Eq. Ggrid; the threshold
+ * table of the "Computational details" section).  Host only.
+ * For level l, a_l is the largest exponent among the shells living on it
+ * (the level rule of isdf_system) and G_max,l = sqrt(-4 a_l ln eps_K).
+ * Axis i of level l gets the smallest even 2,3,5-smooth length n whose kept
+ * band |m_i| <= n/2 - 1 (the Nyquist plane is not kept) holds the index m_i
+ * of every reciprocal vector G = 2 pi sum_j m_j b_j with |G| <= G_max,l;
+ * a level is never coarser than the one below it.
+ *   lattice      [3][3] host, rows a_i (Bohr)
+ *   shell_alpha  [n_shells] host, exponents (Bohr^-2)
+ *   alpha_bound  [n_levels-1] host (may be NULL when n_levels == 1)
+ *   grid_out     [n_levels][3] host, caller-owned; written on success only
+ * Errors: ISDF_E_ARG (null pointers, counts out of range, eps_K outside
+ * (0, 1), a non-positive exponent, a level holding no shell, a singular
+ * lattice); ISDF_E_UNSUPPORTED when an axis would need more than 256
+ * points. */
+isdf_status isdf_grids_for_threshold(const double* lattice, int32_t n_shells,
+                                     const double* shell_alpha, int32_t n_levels,
+                                     const double* alpha_bound, double eps_K, int32_t* grid_out);
 
 /* Sizes: number of basis functions N, total requested points N_mu, domains. */
 isdf_status isdf_plan_info(isdf_plan_t plan, int64_t* n_basis, int64_t* n_mu, int32_t* n_domains);

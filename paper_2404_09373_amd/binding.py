@@ -32,7 +32,7 @@ EXPORTED = [
     "isdf_plan_destroy", "isdf_last_error", "isdf_version", "isdf_fit_with_candidates",
     "isdf_fit_selection", "isdf_fit_features", "isdf_mlp_forward", "isdf_mlp_loss_grad",
     "isdf_mlp_train", "isdf_profile", "isdf_kernel_stats", "isdf_exchange_occ", "isdf_autotune",
-    "isdf_fit_batch", "isdf_exchange_occ_ri",
+    "isdf_fit_batch", "isdf_exchange_occ_ri", "isdf_grids_for_threshold",
 ]
 MLP_NPARAM = 5313
 
@@ -140,6 +140,9 @@ def load(required: bool = True):
     lib.isdf_exchange_occ.argtypes = [vp, vp, vp, C.c_int32, vp, C.POINTER(C.c_double)]
     lib.isdf_exchange_occ_ri.argtypes = [vp, vp, vp, C.c_int32, vp, C.POINTER(C.c_double)]
     lib.isdf_autotune.argtypes = [vp, C.c_int32, C.c_int32, C.c_char_p]
+    lib.isdf_grids_for_threshold.argtypes = [C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_double),
+                                             C.c_int32, C.POINTER(C.c_double), C.c_double,
+                                             C.POINTER(C.c_int32)]
     lib.isdf_fit_batch.argtypes = [C.POINTER(vp), C.c_int32, C.c_int32, C.POINTER(vp),
                                    C.POINTER(C.c_int)]
     lib.isdf_kernel_stats.argtypes = [vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64),
@@ -150,7 +153,7 @@ def load(required: bool = True):
                  "isdf_fit_with_candidates", "isdf_fit_selection", "isdf_fit_features",
                  "isdf_mlp_forward", "isdf_mlp_loss_grad", "isdf_mlp_train", "isdf_profile",
                  "isdf_kernel_stats", "isdf_exchange_occ", "isdf_autotune", "isdf_fit_batch",
-                 "isdf_exchange_occ_ri"):
+                 "isdf_exchange_occ_ri", "isdf_grids_for_threshold"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -282,6 +285,22 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def grids_for_threshold(lattice, shell_alpha, alpha_bound, eps_K: float) -> np.ndarray:
+    """Grid ladder [n_levels, 3] for the Fourier threshold eps_K
+    (isdf_grids_for_threshold; host only)."""
+    lib = load()
+    lat = np.ascontiguousarray(lattice, dtype=np.float64).reshape(9)
+    alpha = np.ascontiguousarray(shell_alpha, dtype=np.float64)
+    bounds = np.ascontiguousarray(alpha_bound, dtype=np.float64).reshape(-1)
+    nlev = bounds.size + 1
+    out = np.zeros((nlev, 3), dtype=np.int32)
+    _check(lib.isdf_grids_for_threshold(_ptr(lat, C.c_double), alpha.size, _ptr(alpha, C.c_double), nlev,
+                                        _ptr(bounds, C.c_double) if bounds.size else None,
+                                        float(eps_K), _ptr(out, C.c_int32)),
+           "isdf_grids_for_threshold")
+    return out.astype(np.int64)
 
 
 def fit_batch(plans, max_concurrent: int = 4, allow_rank: bool = True):

@@ -2490,6 +2490,12 @@ extern "C" {
 const char* isdf_last_error(void) { return g_err.c_str(); }
 const char* isdf_version(void) { return "isdf-mi355x 0.1 (gfx950)"; }
 
+isdf_status isdf_grids_for_threshold(const double* lattice, int32_t n_shells,
+                                     const double* shell_alpha, int32_t n_levels,
+                                     const double* alpha_bound, double eps_K, int32_t* grid_out) {
+  return threshold_grids(lattice, n_shells, shell_alpha, n_levels, alpha_bound, eps_K, grid_out);
+}
+
 isdf_status isdf_plan(const isdf_system* sys, const isdf_options* opts, isdf_plan_t* out) {
   if (!out) {
     set_error("isdf_plan: null output handle");

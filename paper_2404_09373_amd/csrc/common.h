@@ -72,6 +72,10 @@ struct HostPlan {
 // error status with set_error() called.
 isdf_status build_host_plan(const isdf_system* sys, HostPlan& hp);
 
+// Grid ladder for a Fourier threshold eps_K (isdf_grids_for_threshold).
+isdf_status threshold_grids(const double* lattice, int n_shells, const double* shell_alpha,
+                            int n_levels, const double* alpha_bound, double eps_K, int32_t* out);
+
 // -------------------------------------------------------------- GEMM engine
 // Column-major FP64 GEMM problem:  C(m,n) = epi( sum_k opA(m,k) opB(k,n) ).
 //   opA(m,k) = transA ? A[k + m*lda] : A[m + k*lda]

@@ -16,7 +16,10 @@
 //     same-level functions of atoms with a larger index, screened by
 //     min-image distance <= r_img(alpha) + r_max; a same-level pair of two
 //     atoms is thus fitted once, on the lower atom's window;
-//   * n_mu,d = floor(ratio |L_d| + 1/2) capped at the point count.
+//   * n_mu,d = floor(ratio |L_d| + 1/2) capped at the point count; with
+//     ratio <= 0 (stop by eps_isdf only) the cap is the smaller of the point
+//     count and the domain's distinct pair products |L|(|L|+1)/2 + |L||N|,
+//     which bound the rank of its pair Gram.
 #include <algorithm>
 #include <cmath>
 #include <set>
@@ -282,8 +285,11 @@ isdf_status build_host_plan(const isdf_system* sys, HostPlan& hp) {
     V3 cr = {aj.y * ak.z - aj.z * ak.y, aj.z * ak.x - aj.x * ak.z, aj.x * ak.y - aj.y * ak.x};
     wmin = std::min(wmin, hp.volume / norm(cr));
   }
-  auto n_mu_for = [&](int nL, int npts) -> int {
-    if (hp.n_mu_ratio <= 0) return npts;
+  // threshold only: at most the number of distinct pair products of the
+  // domain (L L pairs once, L N pairs), which bounds the rank of its Gram
+  auto n_mu_for = [&](int nL, int nN, int npts) -> int {
+    if (hp.n_mu_ratio <= 0)
+      return (int)std::min<int64_t>(npts, (int64_t)nL * (nL + 1) / 2 + (int64_t)nL * nN);
     double v = std::floor(hp.n_mu_ratio * nL + 0.5);
     return (int)std::min<double>(v, npts);
   };
@@ -301,7 +307,7 @@ isdf_status build_host_plan(const isdf_system* sys, HostPlan& hp) {
       int64_t np = (int64_t)hp.grid[0][0] * hp.grid[0][1] * hp.grid[0][2];
       d.points.resize(np);
       for (int64_t i = 0; i < np; ++i) d.points[i] = (int32_t)i;
-      d.n_mu = n_mu_for(d.nL, (int)np);
+      d.n_mu = n_mu_for(d.nL, 0, (int)np);
       d.r_max = INFINITY;
       hp.domains.push_back(std::move(d));
     }
@@ -338,7 +344,7 @@ isdf_status build_host_plan(const isdf_system* sys, HostPlan& hp) {
         if (dist[B] <= std::sqrt(hp.ln_inv_tau / alpha) + r_max) d.funcs.push_back(f);
       }
       d.nN = (int)d.funcs.size() - d.nL;
-      d.n_mu = n_mu_for(d.nL, (int)d.points.size());
+      d.n_mu = n_mu_for(d.nL, d.nN, (int)d.points.size());
       hp.domains.push_back(std::move(d));
     }
   }
@@ -348,6 +354,91 @@ isdf_status build_host_plan(const isdf_system* sys, HostPlan& hp) {
     set_error("isdf_plan: no domain has local functions");
     return ISDF_E_ARG;
   }
+  return ISDF_OK;
+}
+
+// Grid ladder for a Fourier threshold (Eq. Ggrid).  A level's grid must
+// keep every reciprocal vector G = 2 pi (m1 b1 + m2 b2 + m3 b3) with
+// |G| <= G_max = sqrt(-4 a ln eps_K), a the largest exponent living on the
+// level.  Axis i keeps |m_i| <= n_i/2 - 1 (the Nyquist plane is dropped), so
+// n_i is the smallest even 2,3,5-smooth length with n_i/2 - 1 >= the largest
+// |m_i| over that ball; levels never get coarser than the one below.
+isdf_status threshold_grids(const double* lattice, int n_shells, const double* shell_alpha,
+                            int n_levels, const double* alpha_bound, double eps_K, int32_t* out) {
+  if (!lattice || !shell_alpha || !out || n_shells <= 0 || n_levels <= 0 || n_levels > 8 ||
+      (n_levels > 1 && !alpha_bound) || !(eps_K > 0 && eps_K < 1)) {
+    set_error("isdf_grids_for_threshold: null pointers, bad counts or eps_K outside (0, 1)");
+    return ISDF_E_ARG;
+  }
+  double inv[9], det;
+  invert3(lattice, inv, &det);
+  if (!(std::fabs(det) > 0) || !std::isfinite(det)) {
+    set_error("isdf_grids_for_threshold: singular lattice");
+    return ISDF_E_ARG;
+  }
+  std::vector<double> amax(n_levels, 0.0);
+  for (int s = 0; s < n_shells; ++s) {
+    const double a = shell_alpha[s];
+    if (!(a > 0) || !std::isfinite(a)) {
+      set_error("isdf_grids_for_threshold: non-positive exponent");
+      return ISDF_E_ARG;
+    }
+    int lev = n_levels - 1;
+    for (int l = 0; l < n_levels - 1; ++l)
+      if (a < alpha_bound[l]) {
+        lev = l;
+        break;
+      }
+    amax[lev] = std::max(amax[lev], a);
+  }
+  // reciprocal basis b_j (rows): b_j . a_i = delta_ij, i.e. column j of inv
+  double b[3][3];
+  for (int j = 0; j < 3; ++j)
+    for (int c = 0; c < 3; ++c) b[j][c] = inv[3 * c + j];
+  double alen[3];
+  for (int i = 0; i < 3; ++i)
+    alen[i] = std::sqrt(lattice[3 * i] * lattice[3 * i] + lattice[3 * i + 1] * lattice[3 * i + 1] +
+                        lattice[3 * i + 2] * lattice[3 * i + 2]);
+  const double two_pi = 2.0 * M_PI;
+  std::vector<int32_t> grid(3 * n_levels);
+  for (int l = 0; l < n_levels; ++l) {
+    if (!(amax[l] > 0)) {
+      set_error("isdf_grids_for_threshold: a level holds no shell");
+      return ISDF_E_ARG;
+    }
+    const double gmax = std::sqrt(-4.0 * amax[l] * std::log(eps_K));
+    int box[3], need[3] = {0, 0, 0};
+    for (int i = 0; i < 3; ++i) {
+      const double bi = std::floor(gmax * alen[i] / two_pi);
+      if (bi > 200) {
+        set_error("isdf_grids_for_threshold: an axis would exceed 256 points");
+        return ISDF_E_UNSUPPORTED;
+      }
+      box[i] = (int)bi;  // |m_i| <= G_max |a_i| / (2 pi) for every G in the ball
+    }
+    const double g2max = gmax * gmax;
+    for (int m1 = -box[0]; m1 <= box[0]; ++m1)
+      for (int m2 = -box[1]; m2 <= box[1]; ++m2)
+        for (int m3 = -box[2]; m3 <= box[2]; ++m3) {
+          double g[3];
+          for (int c = 0; c < 3; ++c) g[c] = two_pi * (m1 * b[0][c] + m2 * b[1][c] + m3 * b[2][c]);
+          if (g[0] * g[0] + g[1] * g[1] + g[2] * g[2] > g2max) continue;
+          need[0] = std::max(need[0], std::abs(m1));
+          need[1] = std::max(need[1], std::abs(m2));
+          need[2] = std::max(need[2], std::abs(m3));
+        }
+    for (int i = 0; i < 3; ++i) {
+      int n = 2 * (need[i] + 1);
+      while (!smooth235(n)) n += 2;
+      if (l > 0) n = std::max(n, (int)grid[3 * (l - 1) + i]);
+      if (n > 256) {
+        set_error("isdf_grids_for_threshold: an axis would exceed 256 points");
+        return ISDF_E_UNSUPPORTED;
+      }
+      grid[3 * l + i] = n;
+    }
+  }
+  std::copy(grid.begin(), grid.end(), out);
   return ISDF_OK;
 }
 

@@ -55,6 +55,64 @@ def test_plan_matches_oracle(which):
     _compare_plan(s)
 
 
+def test_plan_threshold_only_matches_oracle():
+    """n_mu_ratio <= 0: every domain's point cap is the rank bound of its
+    pair Gram, the same in both plans."""
+    s = config(1, with_density=False)
+    s.n_mu_ratio = 0.0
+    s.grids = oplan.grids_for_threshold(s.lattice, s.shell_alpha, s.alpha_bound, 1e-2)
+    _compare_plan(s)
+
+
+_LADDER_SYSTEMS = [config(1, with_density=False), config(2, with_density=False),
+                   config(4, with_density=False)] + batched_cells(4, with_density=False)
+
+
+@pytest.mark.parametrize("eps_K", [0.3, 1e-2, 1e-3, 1e-5, 1e-8])
+def test_grids_for_threshold_match_oracle(eps_K):
+    """isdf_grids_for_threshold gives the oracle's ladder exactly (cubic,
+    supercell and strained cells; the 216-atom cell at 1e-8 exceeds 256
+    points on both sides)."""
+    for s in _LADDER_SYSTEMS:
+        ref = oplan.grids_for_threshold(s.lattice, s.shell_alpha, s.alpha_bound, eps_K)
+        if ref.max() > 256:
+            with pytest.raises(binding.IsdfError) as e:
+                binding.grids_for_threshold(s.lattice, s.shell_alpha, s.alpha_bound, eps_K)
+            assert e.value.status == -7
+            continue
+        got = binding.grids_for_threshold(s.lattice, s.shell_alpha, s.alpha_bound, eps_K)
+        assert np.array_equal(got, ref), f"{s.name} eps_K {eps_K}: {got.tolist()} vs {ref.tolist()}"
+
+
+def test_grids_for_threshold_oblique_cell_matches_oracle():
+    lat = np.array([[7.0, 0.0, 0.0], [3.5, 3.0, 0.0], [1.0, 1.0, 4.0]])
+    for a, e in [(0.8, 1e-2), (0.8, 1e-4), (0.3, 1e-3), (1.2, 1e-6)]:
+        alphas = [0.1, a, 2.5 * a]
+        ref = oplan.grids_for_threshold(lat, alphas, [a * 1.01], e)
+        assert np.array_equal(binding.grids_for_threshold(lat, alphas, [a * 1.01], e), ref)
+
+
+def test_grids_for_threshold_errors():
+    lat = np.eye(3) * 6.74
+    for alphas, bounds, eps in [([0.3], [], 0.0), ([0.3], [], 1.0), ([0.3, -1.0], [], 1e-2),
+                                ([0.15, 0.3], [2.0], 1e-2)]:
+        with pytest.raises(binding.IsdfError) as e:
+            binding.grids_for_threshold(lat, alphas, bounds, eps)
+        assert e.value.status == -1
+    with pytest.raises(binding.IsdfError) as e:
+        binding.grids_for_threshold(np.zeros((3, 3)), [0.3], [], 1e-2)
+    assert e.value.status == -1
+    with pytest.raises(binding.IsdfError) as e:
+        binding.grids_for_threshold(lat, [400.0], [], 1e-12)
+    assert e.value.status == -7
+    lib = binding.load()
+    out = np.full(3, -5, dtype=np.int32)
+    alpha = np.array([0.3])
+    assert lib.isdf_grids_for_threshold(None, 1, binding._ptr(alpha, C.c_double), 1, None, 1e-2,
+                                        binding._ptr(out, C.c_int32)) == -1
+    assert np.all(out == -5)  # untouched on error
+
+
 @pytest.mark.slow
 def test_plan_matches_oracle_cfg2():
     _compare_plan(config(2, with_density=False))

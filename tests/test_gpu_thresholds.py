@@ -1,0 +1,80 @@
+"""Threshold-driven fits on the GPU (threshold table of the "Computational
+details" section): grids from eps_K (Eq. Ggrid) and point counts from
+eps_ISDF alone (n_mu_ratio = 0), on the 8-atom diamond cell with
+eps_K = 1e-2 and eps_ISDF = 1e-2 .. 1e-5, the settings of the paper's
+local-fitting error study.
+
+Each threshold: the library's grid ladder equals the oracle's, the pivots of
+every domain equal the oracle's, and K and E_x match the oracle within the
+FP64 tolerance.  Across thresholds the error against the tightest fit falls
+as eps_ISDF falls (the trend of the paper's local-fitting figure)."""
+import numpy as np
+import pytest
+
+from paper_2404_09373_amd import binding
+from workloads import config
+
+pytestmark = pytest.mark.gpu
+
+EPS_K = 1e-2
+EPS_ISDF = [1e-2, 1e-3, 1e-4, 1e-5]
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+
+    assert t.cuda.is_available()
+    return t
+
+
+def _system(eps_isdf):
+    s = config(1)
+    s.grids = binding.grids_for_threshold(s.lattice, s.shell_alpha, s.alpha_bound, EPS_K)
+    s.n_mu_ratio = 0.0
+    s.eps_isdf = eps_isdf
+    return s
+
+
+@pytest.fixture(scope="module")
+def results(torch):
+    return {}
+
+
+@pytest.mark.parametrize("eps_isdf", EPS_ISDF)
+def test_threshold_fit_matches_oracle(torch, results, eps_isdf):
+    from oracle import pipeline
+    from oracle import plan as oplan
+
+    s = _system(eps_isdf)
+    assert np.array_equal(s.grids, oplan.grids_for_threshold(s.lattice, s.shell_alpha, s.alpha_bound, EPS_K))
+    ref = pipeline.run(s)
+    plan = binding.Plan(s)
+    fit = plan.fit()
+    n_local = 0
+    for d in range(plan.n_domains):
+        got = fit.get("points", d)
+        assert np.array_equal(got, ref.pivots[d]), f"domain {d}: {got.size} vs {ref.pivots[d].size} points"
+        if d > 0:
+            n_local += got.size
+    D = torch.tensor(s.D, dtype=torch.float64, device="cuda")
+    K, e = fit.exchange(D)
+    dK = float(np.max(np.abs(K.cpu().numpy() - ref.K)))
+    dE = abs(e - ref.E_x) / s.n_atoms
+    print(f"[threshold] grids {s.grids.tolist()} eps_ISDF {eps_isdf:.0e}: N_xi local {n_local}, "
+          f"universal {ref.pivots[0].size}, E_x {e:.10f}, max|dK| {dK:.2e}, |dE|/atom {dE:.2e}")
+    assert dK <= 1e-7 and dE <= 1e-6
+    results[eps_isdf] = (e, n_local)
+    fit.close()
+    plan.close()
+
+
+def test_threshold_error_falls_with_eps_isdf(results):
+    if len(results) < len(EPS_ISDF):
+        pytest.skip("needs every threshold fit of this module")
+    e_ref = results[EPS_ISDF[-1]][0]
+    errs = [abs(results[t][0] - e_ref) / 8 for t in EPS_ISDF[:-1]]
+    counts = [results[t][1] for t in EPS_ISDF]
+    print(f"[threshold] |E_x - E_x(1e-5)|/atom {['%.2e' % x for x in errs]}, local points {counts}")
+    assert counts == sorted(counts)
+    assert errs[0] > errs[1] > errs[2]
