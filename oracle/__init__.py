@@ -22,6 +22,9 @@ performing interpolative separable density fitting" (arXiv 2404.09373):
   exchange.py  four-term multigrid THC exchange matrix (Eq. ints)
   brute.py     exact exchange from every pair density, no ISDF, computed
                two ways (pair tensor and occupied-orbital Poisson solves)
+  universal.py the universal grid with every point as a fitting function:
+               diffuse-diffuse exchange from occupied pair densities by FFT
+               (occ-RI), (R_U|R_U') never stored
   mlp.py       FP64 forward/backward of the point-scoring network
   pipeline.py  the whole fit + exchange with per-stage timers
 

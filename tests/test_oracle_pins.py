@@ -555,3 +555,50 @@ def test_threshold_only_cap_bounds_the_pair_rank():
         piv, _, d, d0 = isdf.pivoted_cholesky(Phi, nL, dom.n_mu, 1e-10, s.tie_tol)
         assert piv.size < dom.n_mu or np.max(d) <= 1e-10 * np.max(d0)
         assert abs(piv.size - rank) <= max(2, rank // 10)
+
+
+# ------------------------------------- universal grid, all points (occ-RI)
+def test_universal_all_points_equals_exact_single_level():
+    """One level: the universal domain owns every pair, so with every grid
+    point as a fitting function its occ-RI exchange is the exact exchange
+    (pair-tensor and occupied-orbital routes).  Catches a missing dV, a
+    wrong pair product (E_i E_i) or a transposed Phi."""
+    from oracle import universal
+
+    s = tiny_system("one_atom", grids=((15, 15, 15),), alpha_bound=(), n_occ=2)
+    p = oplan.build_plan(s)
+    Kt, _ = brute.exchange_tensor_route(p, s.D)
+    Ko = brute.exchange_orbital_route(p, s.C_occ)
+    KC = universal.universal_exchange_occ_ri(p, s.C_occ)
+    scale = np.max(np.abs(Kt @ s.C_occ))
+    assert np.max(np.abs(KC - Kt @ s.C_occ)) <= 1e-12 * scale
+    assert np.max(np.abs(KC - Ko @ s.C_occ)) <= 1e-12 * scale
+    sub = universal.universal_exchange_occ_ri(p, s.C_occ, cols=[1])
+    assert np.array_equal(sub[:, 0], KC[:, 1])
+
+
+def test_universal_all_points_two_levels_is_the_diffuse_block():
+    """Two levels: only diffuse-diffuse pairs belong to the universal grid.
+    The result equals the exact exchange of a system that keeps only the
+    diffuse shells on the universal grid, and rows of sharp functions are
+    zero (catches pairs of sharp functions leaking into the universal
+    block)."""
+    import dataclasses
+
+    from oracle import universal
+
+    s = tiny_system("two_atom", grids=((12, 12, 12), (24, 24, 24)), alpha_bound=(2.0,), n_occ=3)
+    p = oplan.build_plan(s)
+    KC = universal.universal_exchange_occ_ri(p, s.C_occ)
+    keep = s.shell_alpha < 2.0
+    red = dataclasses.replace(s, shell_atom=s.shell_atom[keep], shell_l=s.shell_l[keep],
+                              shell_alpha=s.shell_alpha[keep], grids=s.grids[:1],
+                              alpha_bound=np.zeros(0))
+    pr = oplan.build_plan(red)
+    L0 = p.domains[0].G
+    assert pr.n_basis == L0.size
+    Kr, _ = brute.exchange_tensor_route(pr, s.D[np.ix_(L0, L0)])
+    ref = Kr @ s.C_occ[L0]
+    assert np.max(np.abs(KC[L0] - ref)) <= 1e-12 * np.max(np.abs(ref))
+    others = np.setdiff1d(np.arange(p.n_basis), L0)
+    assert others.size > 0 and np.all(KC[others] == 0.0)
