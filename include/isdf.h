@@ -280,6 +280,29 @@ isdf_status isdf_exchange_occ(isdf_plan_t plan, isdf_fit_t fit, const double* C_
 isdf_status isdf_exchange_occ_ri(isdf_plan_t plan, isdf_fit_t fit, const double* C_dev,
                                  int32_t n_occ, double* KC_dev, double* e_x);
 
+/* Universal grid with every point as a fitting function (the sinc functions
+ * of the sparse grid; sections "Building the exchange matrix" and Results):
+ * the exchange of the pairs the universal domain holds (both functions on
+ * level 0), applied to the occupied orbitals without interpolation points
+ * and without storing the Coulomb operator between grid points:
+ *   (K_UU C)(mu, i) = -dV sum_R phi_mu(R) sum_j E(R, j) V[E_j E_i](R),
+ *   E = Phi_U C,  V[rho] the potential of a grid density by FFT Poisson
+ * solves (band without the Nyquist planes and G = 0, as for W), one per
+ * occupied pair i <= j, each SCF iteration (occ-RI).  Rows of functions off
+ * the universal grid are zero; e_x = tr(C' K_UU C).  Exact for these pairs
+ * (no fitting error); the pairs held by atom windows are not included.
+ * C_dev: device pointer to N x n_occ FP64, row-major (C[mu * n_occ + i]).
+ * KC_dev: device pointer to N x n_occ FP64, row-major, written.
+ * e_x: host pointer or NULL.  Eager launches; synchronises the stream.
+ * Device memory: n_occ (n_occ + 1) / 2 potentials of N_g doubles (2.2 GB at
+ * a 32^3 grid and 128 orbitals) plus about 2 GB of transform buffers,
+ * released on return.
+ * Errors: ISDF_E_ARG (null pointers, n_occ outside 1..N, non-finite
+ * energy), ISDF_E_STATE (fit not from this plan), ISDF_E_UNSUPPORTED (no
+ * universal domain), ISDF_E_NOMEM, ISDF_E_HIP. */
+isdf_status isdf_exchange_universal(isdf_plan_t plan, isdf_fit_t fit, const double* C_dev,
+                                    int32_t n_occ, double* KC_dev, double* e_x);
+
 /* Tile-shape tuning of the FP64 GEMMs (for callers that set up a plan once
  * and run it many times).  Runs one fit and one dense and one factored
  * exchange (D = I, C = the first n_occ unit vectors) on the plan; every

@@ -20,6 +20,7 @@ SOURCES = [
     "kernels_fft.hip",
     "kernels_mlp.hip",
     "kernels_mixed.hip",
+    "kernels_universal.hip",
     "plan.cpp",
 ]
 

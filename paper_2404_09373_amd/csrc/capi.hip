@@ -2401,6 +2401,107 @@ isdf_status exchange_enqueue_ri(isdf_plan_s* plan, isdf_fit_s* fit, const double
   return launch_trace_dot(s, Cin, KC, N * o, fit->partial.as<double>(), 1024, fit->ex_out.as<double>());
 }
 
+// Exchange of the universal domain's pairs with every grid point as a
+// fitting function (F = I): K_UU C = -dV Phi_U^T Z, Z(R, i) = sum_j E(R, j)
+// V[E_j E_i](R), E = Phi_U C, the potentials by batched FFT Poisson solves
+// of the n_occ (n_occ + 1) / 2 pair densities (the Coulomb operator between
+// grid points is never formed).  Eager launches on the plan's stream.
+isdf_status universal_exchange(isdf_plan_s* pl, isdf_fit_s* f, const double* C, int o, double* KC,
+                               double* e_x) {
+  HostPlan& hp = pl->hp;
+  if (hp.domains.empty() || hp.domains[0].atom >= 0 || hp.domains[0].level != 0 ||
+      hp.domains[0].nN != 0) {
+    set_error("isdf_exchange_universal: the plan has no universal domain");
+    return ISDF_E_UNSUPPORTED;
+  }
+  if (f->plan != pl) {
+    set_error("isdf_exchange_universal: fit belongs to another plan");
+    return ISDF_E_STATE;
+  }
+  MemScope mscope(pl->mem);
+  hipStream_t s = pl->stream;
+  const HostDomain& U = hp.domains[0];
+  const int64_t ng = level_ng(hp, 0);
+  const int n0 = U.nL;
+  const int64_t N = hp.n_basis;
+  if ((int64_t)U.points.size() != ng || (int64_t)U.funcs.size() != n0) {
+    set_error("isdf_exchange_universal: universal domain does not cover its grid");
+    return ISDF_E_STATE;
+  }
+  const double* Phi = f->phi.as<double>() + pl->phi_off[0];  // ng x n0, column-major
+  const int32_t* funcs = pl->d_funcs.as<int32_t>() + pl->func_off[0];
+  const int64_t P = (int64_t)o * (o + 1) / 2;
+  // pair densities per FFT batch: complex work arrays of at most ~1 GB each
+  const int64_t per_pair = 16 * ng;
+  int64_t ncb = 2 * std::max<int64_t>(1, std::min<int64_t>(65535, (int64_t)1e9 / per_pair));
+  ncb = std::min<int64_t>(ncb, P + (P & 1));
+  isdf_status st;
+  DevBuf C0, E, V, Z, KC0, zf, zc, dpairs, partial, out;
+  if ((st = C0.alloc(sizeof(double) * n0 * o)) != ISDF_OK || (st = E.alloc(sizeof(double) * ng * o)) != ISDF_OK ||
+      (st = Z.alloc(sizeof(double) * ng * o)) != ISDF_OK || (st = KC0.alloc(sizeof(double) * n0 * o)) != ISDF_OK ||
+      (st = V.alloc(sizeof(double) * P * ng)) != ISDF_OK ||
+      (st = zf.alloc(sizeof(double) * ng * ncb)) != ISDF_OK || (st = zc.alloc(sizeof(double) * ng * ncb)) != ISDF_OK ||
+      (st = partial.alloc(sizeof(double) * 1024)) != ISDF_OK || (st = out.alloc(sizeof(double))) != ISDF_OK)
+    return st;
+  std::vector<int32_t> pairs((size_t)(2 * P));
+  for (int64_t a = 0, p = 0; a < o; ++a)
+    for (int64_t b = a; b < o; ++b, ++p) {
+      pairs[2 * p] = (int32_t)a;
+      pairs[2 * p + 1] = (int32_t)b;
+    }
+  if ((st = upload(dpairs, pairs)) != ISDF_OK) return st;
+  auto gemm = [&](const double* A, int64_t lda, int tA, const double* B, int64_t ldb, double* Cm, int64_t ldc,
+                  int M, int Nn, int Kk, double alpha) {
+    GemmProblem p{};
+    p.A = A; p.lda = lda; p.transA = tA;
+    p.B = B; p.ldb = ldb; p.transB = 0;
+    p.C = Cm; p.ldc = ldc;
+    p.M = M; p.N = Nn; p.K = Kk;
+    p.alpha = alpha; p.beta = 0.0;
+    return gemm_prof(pl, ISDF_K_GEMM_EXCHANGE, EPI_AXPBY, p);
+  };
+  // E = Phi_U C(funcs, :)
+  if ((st = launch_gather_rows_t(s, C, o, funcs, n0, C0.as<double>())) != ISDF_OK) return st;
+  if ((st = gemm(Phi, ng, 0, C0.as<double>(), n0, E.as<double>(), ng, (int)ng, o, n0, 1.0)) != ISDF_OK) return st;
+  // potentials of the pair densities, batch by batch, into V (column p = pair p)
+  const int* g0 = hp.grid[0];
+  for (int64_t p0 = 0; p0 < P; p0 += ncb) {
+    const int nc = (int)std::min<int64_t>(ncb, P - p0);
+    const int npc = (nc + 1) / 2;
+    double* vout = V.as<double>() + p0 * ng;
+    if ((st = launch_pair_density(s, E.as<double>(), ng, dpairs.as<int32_t>() + 2 * p0, nc, zf.as<double>())) !=
+        ISDF_OK)
+      return st;
+    if ((st = fft_prof(pl, zf.as<double>(), npc, g0, -1)) != ISDF_OK) return st;
+    bool fused = false;
+    if ((st = fft_poisson_inverse(s, zf.as<double>(), g0, zc.as<double>(), g0, npc, pl->recip, vout, nc, &fused)) !=
+        ISDF_OK)
+      return st;
+    if (!fused) {
+      if ((st = launch_poisson_restrict(s, zf.as<double>(), g0, zc.as<double>(), g0, npc, pl->recip)) != ISDF_OK)
+        return st;
+      if ((st = fft_prof(pl, zc.as<double>(), npc, g0, +1)) != ISDF_OK) return st;
+      if ((st = launch_split_planar(s, zc.as<double>(), ng, nc, vout)) != ISDF_OK) return st;
+    }
+  }
+  if ((st = launch_z_accumulate(s, E.as<double>(), V.as<double>(), ng, o, Z.as<double>())) != ISDF_OK) return st;
+  // K_UU C rows of the universal functions = -dV Phi_U^T Z; other rows zero
+  const double dV = hp.volume / (double)ng;
+  if ((st = gemm(Phi, ng, 1, Z.as<double>(), ng, KC0.as<double>(), n0, n0, o, (int)ng, -dV)) != ISDF_OK) return st;
+  if ((st = launch_fill(s, KC, N * o, 0.0)) != ISDF_OK) return st;
+  if ((st = launch_scatter_rows(s, KC0.as<double>(), n0, o, funcs, KC)) != ISDF_OK) return st;
+  if ((st = launch_trace_dot(s, C, KC, N * o, partial.as<double>(), 1024, out.as<double>())) != ISDF_OK) return st;
+  double ex = 0.0;
+  ISDF_HIP_TRY(hipMemcpyAsync(&ex, out.p, sizeof(double), hipMemcpyDeviceToHost, s));
+  ISDF_HIP_TRY(hipStreamSynchronize(s));
+  if (e_x) *e_x = ex;
+  if (!std::isfinite(ex)) {
+    set_error("isdf_exchange_universal: non-finite energy (NaN or Inf in C?)");
+    return ISDF_E_ARG;
+  }
+  return ISDF_OK;
+}
+
 // ri: occ-RI output (exchange_enqueue_ri), else the full K.
 isdf_status exchange_run(isdf_plan_s* plan, isdf_fit_s* fit, const double* in, int n_occ, double* K,
                          double* e_x, bool ri = false) {
@@ -2969,6 +3070,19 @@ isdf_status isdf_exchange_occ_ri(isdf_plan_t plan, isdf_fit_t fit, const double*
     return ISDF_E_ARG;
   }
   return exchange_run(plan, fit, C_occ, n_occ, KC, e_x, true);
+}
+
+isdf_status isdf_exchange_universal(isdf_plan_t plan, isdf_fit_t fit, const double* C_occ, int32_t n_occ,
+                                    double* KC, double* e_x) {
+  if (!plan || !fit || !C_occ || !KC || n_occ < 1) {
+    set_error("isdf_exchange_universal: null argument or n_occ < 1");
+    return ISDF_E_ARG;
+  }
+  if (n_occ > plan->hp.n_basis) {
+    set_error("isdf_exchange_universal: n_occ above the basis size");
+    return ISDF_E_ARG;
+  }
+  return universal_exchange(plan, fit, C_occ, n_occ, KC, e_x);
 }
 
 isdf_status isdf_autotune(isdf_plan_t plan, int32_t n_occ, int32_t reps, const char* json_out) {

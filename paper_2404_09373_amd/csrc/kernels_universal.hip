@@ -1,0 +1,136 @@
+// Universal grid with every point as a fitting function: the elementwise
+// steps of the occ-RI exchange of its diffuse-diffuse pairs (section
+// "Building the exchange matrix"; the sinc functions of the sparse grid in
+// the Results section).  The Coulomb operator between grid points is
+// applied by the batched FFT Poisson passes of kernels_fft.hip; the two
+// products with the basis values run on the FP64 GEMM engine.
+//
+//   E(R, i)  = sum_nu Phi_U(R, nu) C(nu, i)           (GEMM)
+//   rho_p(R) = E(R, a_p) E(R, b_p),  p = (a_p <= b_p) pair_density_kernel
+//   V_p      = potential of rho_p                     (FFT Poisson)
+//   Z(R, i)  = sum_j E(R, j) V_{pair(i, j)}(R)        z_accumulate_kernel
+//   K_UU C   = -dV Phi_U^T Z                          (GEMM, row scatter)
+#include <algorithm>
+
+#include "common.h"
+
+namespace isdf {
+
+// C0[k + i n0] = C[funcs[k] o + i]: rows of the universal domain's functions
+// from the row-major N x o coefficients, as an n0 x o column-major block.
+__global__ void gather_rows_t_kernel(const double* C, int o, const int32_t* funcs, int n0, double* C0) {
+  const int64_t n = (int64_t)n0 * o;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+    const int k = (int)(t % n0), i = (int)(t / n0);
+    C0[t] = C[(int64_t)funcs[k] * o + i];
+  }
+}
+
+isdf_status launch_gather_rows_t(hipStream_t s, const double* C, int o, const int32_t* funcs, int n0,
+                                 double* C0) {
+  const int64_t n = (int64_t)n0 * o;
+  if (n <= 0) return ISDF_OK;
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 65536);
+  hipLaunchKernelGGL(gather_rows_t_kernel, dim3((unsigned)blocks), dim3(256), 0, s, C, o, funcs, n0, C0);
+  ISDF_HIP_TRY(hipGetLastError());
+  return ISDF_OK;
+}
+
+// KC[funcs[k] o + i] = KC0[k + i n0] (the other rows are left as they are).
+__global__ void scatter_rows_kernel(const double* KC0, int n0, int o, const int32_t* funcs, double* KC) {
+  const int64_t n = (int64_t)n0 * o;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+    const int k = (int)(t % n0), i = (int)(t / n0);
+    KC[(int64_t)funcs[k] * o + i] = KC0[t];
+  }
+}
+
+isdf_status launch_scatter_rows(hipStream_t s, const double* KC0, int n0, int o, const int32_t* funcs,
+                                double* KC) {
+  const int64_t n = (int64_t)n0 * o;
+  if (n <= 0) return ISDF_OK;
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 65536);
+  hipLaunchKernelGGL(scatter_rows_kernel, dim3((unsigned)blocks), dim3(256), 0, s, KC0, n0, o, funcs, KC);
+  ISDF_HIP_TRY(hipGetLastError());
+  return ISDF_OK;
+}
+
+// Pair densities of `ncols` consecutive pairs, two per complex array in the
+// layout of the batched transforms: z[q][R] = (rho_{2q}(R), rho_{2q+1}(R)),
+// the imaginary part zero for an odd last column.  pairs[2 p], pairs[2 p + 1]
+// = (a_p, b_p).  Grid: x over points, y over complex arrays.
+__global__ void pair_density_kernel(const double* __restrict__ E, int64_t ng, const int32_t* __restrict__ pairs,
+                                    int ncols, double2* __restrict__ z) {
+  const int q = blockIdx.y;
+  const int c0 = 2 * q, c1 = 2 * q + 1;
+  const int a0 = pairs[2 * c0], b0 = pairs[2 * c0 + 1];
+  const bool has1 = c1 < ncols;
+  const int a1 = has1 ? pairs[2 * c1] : 0, b1 = has1 ? pairs[2 * c1 + 1] : 0;
+  double2* zq = z + (int64_t)q * ng;
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < ng; r += (int64_t)gridDim.x * blockDim.x) {
+    double2 v;
+    v.x = E[r + a0 * ng] * E[r + b0 * ng];
+    v.y = has1 ? E[r + a1 * ng] * E[r + b1 * ng] : 0.0;
+    zq[r] = v;
+  }
+}
+
+isdf_status launch_pair_density(hipStream_t s, const double* E, int64_t ng, const int32_t* pairs, int ncols,
+                                double* z) {
+  if (ncols <= 0) return ISDF_OK;
+  const int nq = (ncols + 1) / 2;
+  if (nq > 65535) {
+    set_error("universal exchange: too many pair densities in one batch");
+    return ISDF_E_ARG;
+  }
+  const int64_t bx = std::min<int64_t>((ng + 255) / 256, 1024);
+  hipLaunchKernelGGL(pair_density_kernel, dim3((unsigned)bx, (unsigned)nq), dim3(256), 0, s, E, ng, pairs, ncols,
+                     reinterpret_cast<double2*>(z));
+  ISDF_HIP_TRY(hipGetLastError());
+  return ISDF_OK;
+}
+
+// Z(R, i) = sum_j E(R, j) V_{pair(min(i,j), max(i,j))}(R), pairs numbered
+// row by row over a <= b: pair(a, b) = a o - a (a - 1) / 2 + b - a.  One
+// thread per point and a block of ZB occupied columns (blockIdx.y); the sum
+// over j runs in order, so the result does not depend on the launch.
+constexpr int ZB = 8;
+__global__ void z_accumulate_kernel(const double* __restrict__ E, const double* __restrict__ V, int64_t ng,
+                                    int o, double* __restrict__ Z) {
+  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (r >= ng) return;
+  const int i0 = blockIdx.y * ZB;
+  double acc[ZB];
+#pragma unroll
+  for (int t = 0; t < ZB; ++t) acc[t] = 0.0;
+  for (int j = 0; j < o; ++j) {
+    const double e = E[r + (int64_t)j * ng];
+#pragma unroll
+    for (int t = 0; t < ZB; ++t) {
+      const int i = i0 + t;
+      if (i < o) {
+        const int64_t a = i < j ? i : j, b = i < j ? j : i;
+        const int64_t p = a * o - a * (a - 1) / 2 + (b - a);
+        acc[t] += e * V[p * ng + r];
+      }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < ZB; ++t)
+    if (i0 + t < o) Z[r + (int64_t)(i0 + t) * ng] = acc[t];
+}
+
+isdf_status launch_z_accumulate(hipStream_t s, const double* E, const double* V, int64_t ng, int o, double* Z) {
+  if (ng <= 0 || o <= 0) return ISDF_OK;
+  const int64_t bx = (ng + 255) / 256;
+  const int by = (o + ZB - 1) / ZB;
+  if (bx > 0x7fffffff || by > 65535) {
+    set_error("universal exchange: grid or occupied count too large");
+    return ISDF_E_UNSUPPORTED;
+  }
+  hipLaunchKernelGGL(z_accumulate_kernel, dim3((unsigned)bx, (unsigned)by), dim3(256), 0, s, E, V, ng, o, Z);
+  ISDF_HIP_TRY(hipGetLastError());
+  return ISDF_OK;
+}
+
+}  // namespace isdf

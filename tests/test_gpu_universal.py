@@ -1,0 +1,109 @@
+"""Universal grid with every point as a fitting function on the GPU
+(isdf_exchange_universal): the diffuse-diffuse exchange from occupied pair
+densities by FFT Poisson solves, (R_U|R_U') never stored.
+
+* one-level system: the universal domain owns every pair, so the result is
+  the exact exchange (oracle brute force, both routes pinned);
+* 8-atom cell: every entry against the oracle's occ-RI route;
+* 64-atom cell at its full size: sampled occupied columns against the
+  oracle, and C^T K_UU C symmetric and negative semidefinite;
+* argument errors and a plan without a universal domain.
+"""
+import numpy as np
+import pytest
+
+from paper_2404_09373_amd import binding
+from workloads import config, tiny_system
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+
+    assert t.cuda.is_available()
+    return t
+
+
+def _run(torch, s):
+    plan = binding.Plan(s)
+    fit = plan.fit()
+    C = torch.tensor(s.C_occ, dtype=torch.float64, device="cuda")
+    KC, e = fit.exchange_universal(C)
+    out = KC.cpu().numpy()
+    fit.close()
+    plan.close()
+    return out, e
+
+
+def test_universal_single_level_is_exact(torch):
+    from oracle import brute
+    from oracle import plan as oplan
+
+    s = tiny_system("one_atom", grids=((15, 15, 15),), alpha_bound=(), n_occ=2)
+    KC, e = _run(torch, s)
+    Kt, _ = brute.exchange_tensor_route(oplan.build_plan(s), s.D)
+    ref = Kt @ s.C_occ
+    d = float(np.max(np.abs(KC - ref))) / float(np.max(np.abs(ref)))
+    print(f"[universal] one level 15^3: rel max|dKC| vs exact {d:.2e}, E {e:.12f} / {np.sum(s.D * Kt):.12f}")
+    assert d <= 1e-11 and abs(e - np.sum(s.D * Kt)) <= 1e-11 * abs(e)
+
+
+def test_universal_cfg1_matches_oracle(torch):
+    from oracle import universal
+    from oracle import plan as oplan
+
+    s = config(1)
+    KC, e = _run(torch, s)
+    ref = universal.universal_exchange_occ_ri(oplan.build_plan(s), s.C_occ)
+    d = float(np.max(np.abs(KC - ref))) / float(np.max(np.abs(ref)))
+    e_ref = float(np.sum(s.C_occ * ref))
+    print(f"[universal] cfg1: rel max|dKC| {d:.2e}, E_UU {e:.12f} / {e_ref:.12f}")
+    assert d <= 1e-11 and abs(e - e_ref) <= 1e-11 * abs(e_ref)
+
+
+def test_universal_cfg2_sampled_columns(torch):
+    from oracle import universal
+    from oracle import plan as oplan
+
+    s = config(2)
+    KC, e = _run(torch, s)
+    cols = [0, 77, s.n_occ - 1]
+    ref = universal.universal_exchange_occ_ri(oplan.build_plan(s), s.C_occ, cols=cols)
+    d = float(np.max(np.abs(KC[:, cols] - ref))) / float(np.max(np.abs(ref)))
+    G = s.C_occ.T @ KC  # C^T K_UU C
+    asym = float(np.max(np.abs(G - G.T))) / float(np.max(np.abs(G)))
+    ev = np.linalg.eigvalsh(0.5 * (G + G.T))
+    print(f"[universal] cfg2 sampled columns {cols}: rel max|dKC| {d:.2e}; C'KC asym {asym:.1e}, "
+          f"eig max {ev[-1]:.2e} min {ev[0]:.2e}, E_UU {e:.10f} tr {np.trace(G):.10f}")
+    assert d <= 1e-11
+    assert asym <= 1e-12 and ev[-1] <= 1e-12 * abs(ev[0])
+    assert abs(e - np.trace(G)) <= 1e-12 * abs(e)
+
+
+def test_universal_rejects_bad_arguments(torch):
+    s = config(1)
+    plan = binding.Plan(s)
+    fit = plan.fit()
+    n = plan.n_basis
+    with pytest.raises(ValueError):
+        fit.exchange_universal(torch.zeros((n + 1, 4), dtype=torch.float64, device="cuda"))
+    C0 = torch.zeros((n, 4), dtype=torch.float64, device="cuda")
+    KC = torch.empty_like(C0)
+    lib = binding.load()
+    for bad in (0, n + 1):
+        assert lib.isdf_exchange_universal(plan.handle, fit.handle, binding.C.c_void_p(C0.data_ptr()), bad,
+                                           binding.C.c_void_p(KC.data_ptr()), None) == -1
+    fit.close()
+    plan.close()
+    # every shell above the bound: the plan holds atom windows only
+    t = tiny_system("one_atom", grids=((12, 12, 12), (24, 24, 24)), alpha_bound=(0.1,), n_occ=2)
+    p2 = binding.Plan(t)
+    f2 = p2.fit()
+    C2 = torch.tensor(t.C_occ, dtype=torch.float64, device="cuda")
+    with pytest.raises(binding.IsdfError) as err:
+        f2.exchange_universal(C2)
+    assert err.value.status == -7
+    f2.close()
+    p2.close()
