@@ -52,3 +52,39 @@ def universal_exchange_occ_ri(plan, C_occ: np.ndarray, cols=None, workers: int =
         KC[dom.G, c] = -dV * (Phi.T @ Z)
     assert ng == Phi.shape[0]
     return KC
+
+
+def paper_exchange_occ_ri(sysm, C_occ: np.ndarray, plan=None, workers: int = -1):
+    """K C of the method with the universal grid taken at every point: the
+    universal domain's fitting functions are its grid points (F = I, X rows
+    = Phi_U), the atom windows are fitted as usual (greedy pivoted Cholesky,
+    Eq. lsqr), W = (xi|xi') over all of them (Eq. (xi|xi'), here formed
+    densely, which is only affordable on small grids), and K C follows the
+    occ-RI form of the four-term exchange (``exchange.exchange_occ_ri``).
+
+    Returns (KC, window pivots per domain, with an empty entry for the
+    universal domain)."""
+    from . import isdf
+    from .coulomb import coulomb_metric
+    from .exchange import build_X, exchange_occ_ri
+    from .plan import build_plan
+
+    plan = plan if plan is not None else build_plan(sysm)
+    universal_domain(plan)
+    piv_list, F_list, rows_list, pivots = [], [], [], []
+    for d, dom in enumerate(plan.domains):
+        Phi = basis.domain_values(plan, dom)
+        if d == 0:
+            piv = np.arange(Phi.shape[0], dtype=np.int64)
+            F = np.eye(Phi.shape[0])
+            pivots.append(np.zeros(0, dtype=np.int64))
+        else:
+            piv, _, _, _ = isdf.pivoted_cholesky(Phi, dom.L.size, dom.n_mu, sysm.eps_isdf, sysm.tie_tol)
+            F, _, _ = isdf.fit_functions(Phi, dom.L.size, piv)
+            pivots.append(piv)
+        piv_list.append(piv)
+        F_list.append(F)
+        rows_list.append(Phi[piv, :])
+    XL, XN = build_X(plan, piv_list, rows_list)
+    W = coulomb_metric(plan, F_list, workers)
+    return exchange_occ_ri(XL, XN, W, C_occ), pivots

@@ -602,3 +602,24 @@ def test_universal_all_points_two_levels_is_the_diffuse_block():
     assert np.max(np.abs(KC[L0] - ref)) <= 1e-12 * np.max(np.abs(ref))
     others = np.setdiff1d(np.arange(p.n_basis), L0)
     assert others.size > 0 and np.all(KC[others] == 0.0)
+
+
+def test_paper_exchange_reaches_exact_two_levels():
+    """Every universal point a fitting function and windows at the exact
+    limit (enough points for their pair rank): K C equals the exact
+    exchange of the two-level plan (catches a cross block between the
+    universal points and the windows taken with the wrong scale or
+    orientation)."""
+    from oracle import universal
+
+    s = tiny_system("two_atom", grids=((12, 12, 12), (24, 24, 24)), alpha_bound=(2.0,), n_occ=3,
+                    n_mu_ratio=40.0)
+    p = oplan.build_plan(s)
+    Kt, _ = brute.exchange_tensor_route(p, s.D)
+    KC, piv = universal.paper_exchange_occ_ri(s, s.C_occ, plan=p)
+    ref = Kt @ s.C_occ
+    assert piv[0].size == 0 and all(x.size > 0 for x in piv[1:])
+    assert np.max(np.abs(KC - ref)) <= 1e-8 * np.max(np.abs(ref))
+    s.n_mu_ratio = 2.0  # fewer window points: a fitting error appears
+    KC2, _ = universal.paper_exchange_occ_ri(s, s.C_occ)
+    assert np.max(np.abs(KC2 - ref)) > 1e-6 * np.max(np.abs(ref))
