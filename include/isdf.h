@@ -114,7 +114,12 @@ typedef struct {
   int32_t pad0;
   const char* tune_file;      /* JSON tile-shape table written by isdf_autotune, read at
                                  plan time (copied); NULL: the built-in size rule          */
-  int32_t reserved[2];
+  int32_t universal_all_points; /* 1: every universal grid point is a fitting function
+                                 (the sinc functions of the sparse grid; no selection or
+                                 fit there, (R_U|R_U') applied by FFT, never stored);
+                                 the exchange is then available as K C only
+                                 (isdf_exchange_occ_ri); needs atom windows             */
+  int32_t reserved;
 } isdf_options;
 
 /* Build the multigrid plan (host only, no device work).
@@ -276,7 +281,14 @@ isdf_status isdf_exchange_occ(isdf_plan_t plan, isdf_fit_t fit, const double* C_
  * C_dev: device pointer to N x n_occ FP64, row-major (C[mu * n_occ + i]).
  * KC_dev: device pointer to N x n_occ FP64, row-major, written.
  * e_x, graph capture and errors as isdf_exchange (ISDF_E_ARG also for n_occ
- * outside 1..N). */
+ * outside 1..N).
+ * With universal_all_points the result is the method with every universal
+ * point a fitting function: the window terms as above (W over window
+ * fitting functions), the universal-window cross terms through the stored
+ * block W_Uw = (R_U|xi_w) (N_g x N_mu,windows), and the universal-universal
+ * term by occ-RI FFT Poisson solves (as isdf_exchange_universal); launched
+ * eagerly (no graph), with the memory noted there.  isdf_exchange and
+ * isdf_exchange_occ return ISDF_E_UNSUPPORTED for such fits. */
 isdf_status isdf_exchange_occ_ri(isdf_plan_t plan, isdf_fit_t fit, const double* C_dev,
                                  int32_t n_occ, double* KC_dev, double* e_x);
 

@@ -336,6 +336,10 @@ struct isdf_fit_s {
   int ri_nocc = -1, kcparts = 0, kctiles = 0;
   // factored density: D = C C^T for the energy
   DevBuf Docc;
+  // every universal point a fitting function: W_Uw = (R_U | xi_w), N_g x N_mu
+  // (the fit's xi are then the window functions only)
+  bool all_points = false;
+  DevBuf WUw;
   // captured exchange: replayed while (mode, operands, K) stay the same
   hipGraph_t xgraph = nullptr;
   hipGraphExec_t xexec = nullptr;
@@ -1127,7 +1131,7 @@ isdf_status run_selection(isdf_plan_s* pl, isdf_fit_s* f, const int64_t* pinned,
   std::vector<int> full_id;
   std::vector<int64_t> full_poff;
   for (int d = 0; d < nd; ++d) {
-    if (mode[d] != 0) continue;
+    if (mode[d] != 0 || hp.domains[d].n_mu == 0) continue;  // no points requested: count stays 0
     const HostDomain& D = hp.domains[d];
     full.push_back(SelSpec{D.level, (int)D.points.size(), (int)D.funcs.size(), D.nL, D.n_mu,
                            pl->phi_off[d], pl->pts_off[d]});
@@ -1543,6 +1547,12 @@ isdf_status run_coulomb(isdf_plan_s* pl, isdf_fit_s* f) {
     }
   }
   if ((st = upload(d_probs, probs)) != ISDF_OK) return st;
+  // every universal point a fitting function: W_Uw(R, xi) = dV_0 V_xi(R)
+  // straight from the level-0 potentials (F_U = I)
+  const int64_t ng0 = level_ng(hp, 0);
+  if (f->all_points) {
+    if ((st = f->WUw.alloc(sizeof(double) * ng0 * std::max<int64_t>(nmu, 1))) != ISDF_OK) return st;
+  }
   // mixed precision for the universal rows (the level-0 row block has one
   // domain whose points are the whole grid, so no row gather is involved)
   const bool w_mixed = mixed_on(pl, ISDF_MIX_W) && nd > 0 && hp.domains[0].atom < 0 &&
@@ -1672,9 +1682,13 @@ isdf_status run_coulomb(isdf_plan_s* pl, isdf_fit_s* f) {
         voff += ng * (ch.c1 - ch.c0);
       }
     }
+    if (f->all_points) {  // level-0 potentials of this chunk sit first in V
+      if ((st = launch_scale_copy(s, V.as<double>(), f->WUw.as<double>() + ch.c0 * ng0, ng0 * (ch.c1 - ch.c0),
+                                  hp.volume / (double)ng0)) != ISDF_OK)
+        return st;
+    }
     for (const GemmLaunch& gl : glaunch[ci]) {
       if (gl.level == 0 && w_mixed) {
-        const int64_t ng0 = level_ng(hp, 0);
         const int w = (int)(ch.c1 - ch.c0);
         if ((st = make_planes(s, mixed_splits(pl), V.as<double>(), ng0, 1, nullptr, w, (int)ng0, Vp0)) !=
             ISDF_OK)
@@ -1740,8 +1754,10 @@ isdf_status do_fit(isdf_plan_s* pl, const int64_t* pinned, const int64_t* cand_i
   ISDF_HIP_TRY(hipEventRecord(pl->ev[1], s));
   // 2. selection
   f->mode.assign(nd, 0);
+  f->all_points = pl->opts.universal_all_points != 0;
   for (int d = 0; d < nd; ++d) {
     const int pts = (int)hp.domains[d].points.size();
+    if (hp.domains[d].n_mu == 0) continue;  // nothing to select
     if (cand_in) {
       f->mode[d] = 2;
     } else if (pl->opts.selector == ISDF_SEL_MLP && !(force_full && (*force_full)[d])) {
@@ -2401,47 +2417,59 @@ isdf_status exchange_enqueue_ri(isdf_plan_s* plan, isdf_fit_s* fit, const double
   return launch_trace_dot(s, Cin, KC, N * o, fit->partial.as<double>(), 1024, fit->ex_out.as<double>());
 }
 
-// Exchange of the universal domain's pairs with every grid point as a
-// fitting function (F = I): K_UU C = -dV Phi_U^T Z, Z(R, i) = sum_j E(R, j)
-// V[E_j E_i](R), E = Phi_U C, the potentials by batched FFT Poisson solves
-// of the n_occ (n_occ + 1) / 2 pair densities (the Coulomb operator between
-// grid points is never formed).  Eager launches on the plan's stream.
-isdf_status universal_exchange(isdf_plan_s* pl, isdf_fit_s* f, const double* C, int o, double* KC,
-                               double* e_x) {
+// Universal-grid terms of K C (row-major N x o), added into KC on the plan's
+// stream.  The universal domain takes every grid point as a fitting
+// function (F = I), E_U = Phi_U C.
+//   universal-universal: -dV Phi_U^T Z, Z(R, i) = sum_j E_U(R, j) V[E_j E_i](R),
+//     the potentials by batched FFT Poisson solves of the n_occ (n_occ + 1) / 2
+//     pair densities (the operator between grid points is never formed);
+//   cross (fits made with universal_all_points; W_Uw = (R_U | xi_w) stored):
+//     A1 = W_Uw o (E_U E_G^T), A2 = W_Uw o (E_U E_L^T) over the window xi,
+//     universal rows -Phi_U^T (A1 E_L + A2 E_N), window rows
+//     -(X^L' A1' E_U + X^N' A2' E_U) (the four-term exchange with the
+//     universal block of X^N empty).
+// Synchronises the stream before returning (its buffers are released).
+isdf_status universal_terms(isdf_plan_s* pl, isdf_fit_s* f, const double* C, int o, double* KC, bool cross) {
   HostPlan& hp = pl->hp;
   if (hp.domains.empty() || hp.domains[0].atom >= 0 || hp.domains[0].level != 0 ||
       hp.domains[0].nN != 0) {
-    set_error("isdf_exchange_universal: the plan has no universal domain");
+    set_error("universal exchange: the plan has no universal domain");
     return ISDF_E_UNSUPPORTED;
   }
   if (f->plan != pl) {
-    set_error("isdf_exchange_universal: fit belongs to another plan");
+    set_error("universal exchange: fit belongs to another plan");
     return ISDF_E_STATE;
   }
-  MemScope mscope(pl->mem);
   hipStream_t s = pl->stream;
   const HostDomain& U = hp.domains[0];
   const int64_t ng = level_ng(hp, 0);
   const int n0 = U.nL;
   const int64_t N = hp.n_basis;
   if ((int64_t)U.points.size() != ng || (int64_t)U.funcs.size() != n0) {
-    set_error("isdf_exchange_universal: universal domain does not cover its grid");
+    set_error("universal exchange: universal domain does not cover its grid");
     return ISDF_E_STATE;
   }
   const double* Phi = f->phi.as<double>() + pl->phi_off[0];  // ng x n0, column-major
   const int32_t* funcs = pl->d_funcs.as<int32_t>() + pl->func_off[0];
   const int64_t P = (int64_t)o * (o + 1) / 2;
+  const int64_t m = f->nmu;
+  cross = cross && m > 0;
   // pair densities per FFT batch: complex work arrays of at most ~1 GB each
   const int64_t per_pair = 16 * ng;
   int64_t ncb = 2 * std::max<int64_t>(1, std::min<int64_t>(65535, (int64_t)1e9 / per_pair));
   ncb = std::min<int64_t>(ncb, P + (P & 1));
   isdf_status st;
-  DevBuf C0, E, V, Z, KC0, zf, zc, dpairs, partial, out;
+  DevBuf C0, E, V, Z, KC0, zf, zc, dpairs, A1, A2, Z1U, Z1w, Z2w;
   if ((st = C0.alloc(sizeof(double) * n0 * o)) != ISDF_OK || (st = E.alloc(sizeof(double) * ng * o)) != ISDF_OK ||
       (st = Z.alloc(sizeof(double) * ng * o)) != ISDF_OK || (st = KC0.alloc(sizeof(double) * n0 * o)) != ISDF_OK ||
       (st = V.alloc(sizeof(double) * P * ng)) != ISDF_OK ||
-      (st = zf.alloc(sizeof(double) * ng * ncb)) != ISDF_OK || (st = zc.alloc(sizeof(double) * ng * ncb)) != ISDF_OK ||
-      (st = partial.alloc(sizeof(double) * 1024)) != ISDF_OK || (st = out.alloc(sizeof(double))) != ISDF_OK)
+      (st = zf.alloc(sizeof(double) * ng * ncb)) != ISDF_OK || (st = zc.alloc(sizeof(double) * ng * ncb)) != ISDF_OK)
+    return st;
+  if (cross && ((st = A1.alloc(sizeof(double) * ng * m)) != ISDF_OK ||
+                (st = A2.alloc(sizeof(double) * ng * m)) != ISDF_OK ||
+                (st = Z1U.alloc(sizeof(double) * ng * o)) != ISDF_OK ||
+                (st = Z1w.alloc(sizeof(double) * m * o)) != ISDF_OK ||
+                (st = Z2w.alloc(sizeof(double) * m * o)) != ISDF_OK))
     return st;
   std::vector<int32_t> pairs((size_t)(2 * P));
   for (int64_t a = 0, p = 0; a < o; ++a)
@@ -2450,19 +2478,50 @@ isdf_status universal_exchange(isdf_plan_s* pl, isdf_fit_s* f, const double* C, 
       pairs[2 * p + 1] = (int32_t)b;
     }
   if ((st = upload(dpairs, pairs)) != ISDF_OK) return st;
-  auto gemm = [&](const double* A, int64_t lda, int tA, const double* B, int64_t ldb, double* Cm, int64_t ldc,
-                  int M, int Nn, int Kk, double alpha) {
+  auto gemm = [&](int epi, const double* A, int64_t lda, int tA, const double* B, int64_t ldb, int tB, double* Cm,
+                  int64_t ldc, int64_t M, int64_t Nn, int64_t Kk, double alpha, double beta, const double* Ep,
+                  int64_t lde) {
     GemmProblem p{};
     p.A = A; p.lda = lda; p.transA = tA;
-    p.B = B; p.ldb = ldb; p.transB = 0;
+    p.B = B; p.ldb = ldb; p.transB = tB;
     p.C = Cm; p.ldc = ldc;
-    p.M = M; p.N = Nn; p.K = Kk;
-    p.alpha = alpha; p.beta = 0.0;
-    return gemm_prof(pl, ISDF_K_GEMM_EXCHANGE, EPI_AXPBY, p);
+    p.E = Ep; p.lde = lde;
+    p.M = (int)M; p.N = (int)Nn; p.K = (int)Kk;
+    p.alpha = alpha; p.beta = beta;
+    return gemm_prof(pl, ISDF_K_GEMM_EXCHANGE, epi, p);
   };
-  // E = Phi_U C(funcs, :)
+  // E_U = Phi_U C(funcs, :)
   if ((st = launch_gather_rows_t(s, C, o, funcs, n0, C0.as<double>())) != ISDF_OK) return st;
-  if ((st = gemm(Phi, ng, 0, C0.as<double>(), n0, E.as<double>(), ng, (int)ng, o, n0, 1.0)) != ISDF_OK) return st;
+  if ((st = gemm(EPI_AXPBY, Phi, ng, 0, C0.as<double>(), n0, 0, E.as<double>(), ng, ng, o, n0, 1.0, 0.0, nullptr,
+                 0)) != ISDF_OK)
+    return st;
+  if (cross) {
+    const double* EG = f->EG.as<double>();
+    const double* EL = f->EL.as<double>();
+    const double* EN = f->EN.as<double>();
+    const double* W = f->WUw.as<double>();
+    if ((st = gemm(EPI_HADAMARD, E.as<double>(), ng, 0, EG, m, 1, A1.as<double>(), ng, ng, m, o, 1.0, 0.0, W,
+                   ng)) != ISDF_OK ||
+        (st = gemm(EPI_HADAMARD, E.as<double>(), ng, 0, EL, m, 1, A2.as<double>(), ng, ng, m, o, 1.0, 0.0, W,
+                   ng)) != ISDF_OK)
+      return st;
+    if ((st = gemm(EPI_AXPBY, A1.as<double>(), ng, 0, EL, m, 0, Z1U.as<double>(), ng, ng, o, m, 1.0, 0.0, nullptr,
+                   0)) != ISDF_OK ||
+        (st = gemm(EPI_AXPBY, A2.as<double>(), ng, 0, EN, m, 0, Z1U.as<double>(), ng, ng, o, m, 1.0, 1.0, nullptr,
+                   0)) != ISDF_OK)
+      return st;
+    if ((st = gemm(EPI_AXPBY, A1.as<double>(), ng, 1, E.as<double>(), ng, 0, Z1w.as<double>(), m, m, o, ng, 1.0,
+                   0.0, nullptr, 0)) != ISDF_OK ||
+        (st = gemm(EPI_AXPBY, A2.as<double>(), ng, 1, E.as<double>(), ng, 0, Z2w.as<double>(), m, m, o, ng, 1.0,
+                   0.0, nullptr, 0)) != ISDF_OK)
+      return st;
+    // (K C)^T += -(Z1w' X^L + Z2w' X^N): window rows of the cross terms
+    if ((st = gemm(EPI_AXPBY, Z1w.as<double>(), m, 1, f->XL.as<double>(), m, 0, KC, o, o, N, m, -1.0, 1.0,
+                   nullptr, 0)) != ISDF_OK ||
+        (st = gemm(EPI_AXPBY, Z2w.as<double>(), m, 1, f->XN.as<double>(), m, 0, KC, o, o, N, m, -1.0, 1.0,
+                   nullptr, 0)) != ISDF_OK)
+      return st;
+  }
   // potentials of the pair densities, batch by batch, into V (column p = pair p)
   const int* g0 = hp.grid[0];
   for (int64_t p0 = 0; p0 < P; p0 += ncb) {
@@ -2484,12 +2543,31 @@ isdf_status universal_exchange(isdf_plan_s* pl, isdf_fit_s* f, const double* C, 
       if ((st = launch_split_planar(s, zc.as<double>(), ng, nc, vout)) != ISDF_OK) return st;
     }
   }
-  if ((st = launch_z_accumulate(s, E.as<double>(), V.as<double>(), ng, o, Z.as<double>())) != ISDF_OK) return st;
-  // K_UU C rows of the universal functions = -dV Phi_U^T Z; other rows zero
+  // universal rows: -Phi_U^T (dV Z_UU + A1 E_L + A2 E_N)
   const double dV = hp.volume / (double)ng;
-  if ((st = gemm(Phi, ng, 1, Z.as<double>(), ng, KC0.as<double>(), n0, n0, o, (int)ng, -dV)) != ISDF_OK) return st;
+  if ((st = launch_z_accumulate(s, E.as<double>(), V.as<double>(), ng, o, dV, cross ? Z1U.as<double>() : nullptr,
+                                Z.as<double>())) != ISDF_OK)
+    return st;
+  if ((st = gemm(EPI_AXPBY, Phi, ng, 1, Z.as<double>(), ng, 0, KC0.as<double>(), n0, n0, o, ng, -1.0, 0.0, nullptr,
+                 0)) != ISDF_OK)
+    return st;
+  if ((st = launch_scatter_add_rows(s, KC0.as<double>(), n0, o, funcs, KC)) != ISDF_OK) return st;
+  ISDF_HIP_TRY(hipStreamSynchronize(s));
+  return ISDF_OK;
+}
+
+// isdf_exchange_universal: the universal-universal block alone.
+isdf_status universal_exchange(isdf_plan_s* pl, isdf_fit_s* f, const double* C, int o, double* KC,
+                               double* e_x) {
+  MemScope mscope(pl->mem);
+  hipStream_t s = pl->stream;
+  const int64_t N = pl->hp.n_basis;
+  isdf_status st;
+  DevBuf partial, out;
+  if ((st = partial.alloc(sizeof(double) * 1024)) != ISDF_OK || (st = out.alloc(sizeof(double))) != ISDF_OK)
+    return st;
   if ((st = launch_fill(s, KC, N * o, 0.0)) != ISDF_OK) return st;
-  if ((st = launch_scatter_rows(s, KC0.as<double>(), n0, o, funcs, KC)) != ISDF_OK) return st;
+  if ((st = universal_terms(pl, f, C, o, KC, false)) != ISDF_OK) return st;
   if ((st = launch_trace_dot(s, C, KC, N * o, partial.as<double>(), 1024, out.as<double>())) != ISDF_OK) return st;
   double ex = 0.0;
   ISDF_HIP_TRY(hipMemcpyAsync(&ex, out.p, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -2509,6 +2587,11 @@ isdf_status exchange_run(isdf_plan_s* plan, isdf_fit_s* fit, const double* in, i
     set_error("isdf_exchange: fit belongs to another plan");
     return ISDF_E_STATE;
   }
+  if (fit->all_points && !ri) {
+    set_error("isdf_exchange: a fit with every universal point a fitting function gives K C only "
+              "(isdf_exchange_occ_ri)");
+    return ISDF_E_UNSUPPORTED;
+  }
   MemScope mscope(plan->mem);
   hipStream_t s = plan->stream;
   isdf_status st;
@@ -2518,7 +2601,7 @@ isdf_status exchange_run(isdf_plan_s* plan, isdf_fit_s* fit, const double* in, i
               : exchange_enqueue(plan, fit, in, n_occ, K, stage_event);
   };
   const bool graph = plan->opts.eager_exchange == 0 && !((plan->prof >> ISDF_K_GEMM_EXCHANGE) & 1) &&
-                     !plan->tuning;
+                     !plan->tuning && !fit->all_points;
   if (graph && (!fit->xexec || fit->xkey_in != in || fit->xkey_out != K || fit->xkey_nocc != n_occ ||
                 fit->xkey_ri != ri)) {
     fit->drop_graph();
@@ -2564,6 +2647,12 @@ isdf_status exchange_run(isdf_plan_s* plan, isdf_fit_s* fit, const double* in, i
     ISDF_HIP_TRY(hipGraphLaunch(fit->xexec, s));
   } else {
     if ((st = enqueue(true)) != ISDF_OK) return st;
+    if (fit->all_points) {  // the window terms are in K C: add the universal ones
+      if ((st = universal_terms(plan, fit, in, n_occ, K, true)) != ISDF_OK) return st;
+      if ((st = launch_trace_dot(s, in, K, plan->hp.n_basis * n_occ, fit->partial.as<double>(), 1024,
+                                 fit->ex_out.as<double>())) != ISDF_OK)
+        return st;
+    }
   }
   ISDF_HIP_TRY(hipEventRecord(plan->ev[2], s));
   double ex = 0.0;
@@ -2635,6 +2724,16 @@ isdf_status isdf_plan(const isdf_system* sys, const isdf_options* opts, isdf_pla
   if (pl->opts.tune_file) {
     if ((st = read_tune_file(pl->opts.tune_file, pl->tune)) != ISDF_OK) return st;
     pl->opts.tune_file = nullptr;  // not kept: the caller owns the string
+  }
+  if (pl->opts.universal_all_points) {
+    HostPlan& hp = pl->hp;
+    if (hp.domains.size() < 2 || hp.domains[0].atom >= 0 || hp.domains[0].level != 0) {
+      set_error("isdf_plan: universal_all_points needs a universal domain and atom windows "
+                "(a one-level plan: isdf_exchange_universal)");
+      return ISDF_E_UNSUPPORTED;
+    }
+    hp.n_mu_total -= hp.domains[0].n_mu;
+    hp.domains[0].n_mu = 0;  // no interpolation points: every grid point is a fitting function
   }
   pl->stream = static_cast<hipStream_t>(pl->opts.stream);
   pl->mem = std::make_shared<MemCtx>();

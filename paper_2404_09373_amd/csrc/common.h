@@ -295,11 +295,13 @@ isdf_status launch_trace_dot(hipStream_t s, const double* a, const double* b, in
 // universal grid with every point as a fitting function (kernels_universal.hip)
 isdf_status launch_gather_rows_t(hipStream_t s, const double* C, int o, const int32_t* funcs, int n0,
                                  double* C0);
-isdf_status launch_scatter_rows(hipStream_t s, const double* KC0, int n0, int o, const int32_t* funcs,
-                                double* KC);
+isdf_status launch_scatter_add_rows(hipStream_t s, const double* KC0, int n0, int o, const int32_t* funcs,
+                                    double* KC);
+isdf_status launch_scale_copy(hipStream_t s, const double* src, double* dst, int64_t n, double alpha);
 isdf_status launch_pair_density(hipStream_t s, const double* E, int64_t ng, const int32_t* pairs, int ncols,
                                 double* z);
-isdf_status launch_z_accumulate(hipStream_t s, const double* E, const double* V, int64_t ng, int o, double* Z);
+isdf_status launch_z_accumulate(hipStream_t s, const double* E, const double* V, int64_t ng, int o, double scale,
+                                const double* add, double* Z);
 
 // ------------------------------------------------------- mixed precision
 // BF16-split GEMM problem: A planes hold (m, k) at A + p plane_a + m lda + k,

@@ -10,6 +10,8 @@
 //   V_p      = potential of rho_p                     (FFT Poisson)
 //   Z(R, i)  = sum_j E(R, j) V_{pair(i, j)}(R)        z_accumulate_kernel
 //   K_UU C   = -dV Phi_U^T Z                          (GEMM, row scatter)
+// With atom windows fitted as usual, the universal-window cross terms of the
+// same K C run on the GEMM engine and their universal rows join Z here.
 #include <algorithm>
 
 #include "common.h"
@@ -36,21 +38,35 @@ isdf_status launch_gather_rows_t(hipStream_t s, const double* C, int o, const in
   return ISDF_OK;
 }
 
-// KC[funcs[k] o + i] = KC0[k + i n0] (the other rows are left as they are).
-__global__ void scatter_rows_kernel(const double* KC0, int n0, int o, const int32_t* funcs, double* KC) {
+// KC[funcs[k] o + i] += KC0[k + i n0] (funcs distinct; other rows untouched).
+__global__ void scatter_add_rows_kernel(const double* KC0, int n0, int o, const int32_t* funcs, double* KC) {
   const int64_t n = (int64_t)n0 * o;
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
     const int k = (int)(t % n0), i = (int)(t / n0);
-    KC[(int64_t)funcs[k] * o + i] = KC0[t];
+    KC[(int64_t)funcs[k] * o + i] += KC0[t];
   }
 }
 
-isdf_status launch_scatter_rows(hipStream_t s, const double* KC0, int n0, int o, const int32_t* funcs,
-                                double* KC) {
+isdf_status launch_scatter_add_rows(hipStream_t s, const double* KC0, int n0, int o, const int32_t* funcs,
+                                    double* KC) {
   const int64_t n = (int64_t)n0 * o;
   if (n <= 0) return ISDF_OK;
   const int64_t blocks = std::min<int64_t>((n + 255) / 256, 65536);
-  hipLaunchKernelGGL(scatter_rows_kernel, dim3((unsigned)blocks), dim3(256), 0, s, KC0, n0, o, funcs, KC);
+  hipLaunchKernelGGL(scatter_add_rows_kernel, dim3((unsigned)blocks), dim3(256), 0, s, KC0, n0, o, funcs, KC);
+  ISDF_HIP_TRY(hipGetLastError());
+  return ISDF_OK;
+}
+
+// dst[t] = alpha src[t]
+__global__ void scale_copy_kernel(const double* src, double* dst, int64_t n, double alpha) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
+    dst[t] = alpha * src[t];
+}
+
+isdf_status launch_scale_copy(hipStream_t s, const double* src, double* dst, int64_t n, double alpha) {
+  if (n <= 0) return ISDF_OK;
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 65536);
+  hipLaunchKernelGGL(scale_copy_kernel, dim3((unsigned)blocks), dim3(256), 0, s, src, dst, n, alpha);
   ISDF_HIP_TRY(hipGetLastError());
   return ISDF_OK;
 }
@@ -90,13 +106,15 @@ isdf_status launch_pair_density(hipStream_t s, const double* E, int64_t ng, cons
   return ISDF_OK;
 }
 
-// Z(R, i) = sum_j E(R, j) V_{pair(min(i,j), max(i,j))}(R), pairs numbered
-// row by row over a <= b: pair(a, b) = a o - a (a - 1) / 2 + b - a.  One
-// thread per point and a block of ZB occupied columns (blockIdx.y); the sum
-// over j runs in order, so the result does not depend on the launch.
+// Z(R, i) = scale sum_j E(R, j) V_{pair(min(i,j), max(i,j))}(R) (+ add(R, i)),
+// pairs numbered row by row over a <= b: pair(a, b) = a o - a (a - 1) / 2 +
+// b - a.  One thread per point and a block of ZB occupied columns
+// (blockIdx.y); the sum over j runs in order, so the result does not depend
+// on the launch.
 constexpr int ZB = 8;
 __global__ void z_accumulate_kernel(const double* __restrict__ E, const double* __restrict__ V, int64_t ng,
-                                    int o, double* __restrict__ Z) {
+                                    int o, double scale, const double* __restrict__ add,
+                                    double* __restrict__ Z) {
   const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (r >= ng) return;
   const int i0 = blockIdx.y * ZB;
@@ -117,10 +135,14 @@ __global__ void z_accumulate_kernel(const double* __restrict__ E, const double* 
   }
 #pragma unroll
   for (int t = 0; t < ZB; ++t)
-    if (i0 + t < o) Z[r + (int64_t)(i0 + t) * ng] = acc[t];
+    if (i0 + t < o) {
+      const int64_t at = r + (int64_t)(i0 + t) * ng;
+      Z[at] = scale * acc[t] + (add ? add[at] : 0.0);
+    }
 }
 
-isdf_status launch_z_accumulate(hipStream_t s, const double* E, const double* V, int64_t ng, int o, double* Z) {
+isdf_status launch_z_accumulate(hipStream_t s, const double* E, const double* V, int64_t ng, int o, double scale,
+                                const double* add, double* Z) {
   if (ng <= 0 || o <= 0) return ISDF_OK;
   const int64_t bx = (ng + 255) / 256;
   const int by = (o + ZB - 1) / ZB;
@@ -128,7 +150,8 @@ isdf_status launch_z_accumulate(hipStream_t s, const double* E, const double* V,
     set_error("universal exchange: grid or occupied count too large");
     return ISDF_E_UNSUPPORTED;
   }
-  hipLaunchKernelGGL(z_accumulate_kernel, dim3((unsigned)bx, (unsigned)by), dim3(256), 0, s, E, V, ng, o, Z);
+  hipLaunchKernelGGL(z_accumulate_kernel, dim3((unsigned)bx, (unsigned)by), dim3(256), 0, s, E, V, ng, o, scale,
+                     add, Z);
   ISDF_HIP_TRY(hipGetLastError());
   return ISDF_OK;
 }

@@ -107,3 +107,56 @@ def test_universal_rejects_bad_arguments(torch):
     assert err.value.status == -7
     f2.close()
     p2.close()
+
+
+# ------------------------------- the method with every universal point a fitting function
+def _all_points_cell():
+    s = config(1)
+    s.grids = np.array([[12, 12, 12], [36, 36, 36]])
+    return s
+
+
+@pytest.mark.parametrize("precision", [binding.FP64, binding.MIXED_X6])
+def test_all_points_method_matches_oracle(torch, precision):
+    """universal_all_points: no selection on the universal grid, windows as
+    usual, cross terms through W_Uw and the universal block by FFT; K C
+    against the oracle's dense form of the same method."""
+    from oracle import universal
+
+    s = _all_points_cell()
+    ref, piv = universal.paper_exchange_occ_ri(s, s.C_occ)
+    plan = binding.Plan(s, precision=precision, universal_all_points=True)
+    fit = plan.fit()
+    assert fit.get("points", 0).size == 0
+    for d in range(1, plan.n_domains):
+        assert np.array_equal(fit.get("points", d), piv[d]), f"domain {d}"
+    C = torch.tensor(s.C_occ, dtype=torch.float64, device="cuda")
+    KC, e = fit.exchange_occ_ri(C)
+    KC2, e2 = fit.exchange_occ_ri(C)  # a second call on the same fit
+    KC, KC2 = KC.cpu().numpy(), KC2.cpu().numpy()
+    d = float(np.max(np.abs(KC - ref))) / float(np.max(np.abs(ref)))
+    e_ref = float(np.sum(s.C_occ * ref))
+    dE = abs(e - e_ref) / s.n_atoms
+    # the same cell with a fitted universal grid, for scale
+    pf = binding.Plan(s, precision=precision)
+    ff = pf.fit()
+    _, e_fit = ff.exchange_occ_ri(C)
+    print(f"[all points] precision {precision}: rel max|dKC| {d:.2e}, |dE|/atom {dE:.2e}, "
+          f"E_x {e:.10f} (fitted universal grid {e_fit:.10f})")
+    tol = 1e-11 if precision == binding.FP64 else 1e-5
+    assert d <= tol and dE <= (1e-11 if precision == binding.FP64 else 1e-7)
+    assert np.array_equal(KC, KC2) and e == e2
+    with pytest.raises(binding.IsdfError) as err:
+        fit.exchange_occ(C)
+    assert err.value.status == -7
+    for f in (fit, ff):
+        f.close()
+    for p in (plan, pf):
+        p.close()
+
+
+def test_all_points_needs_windows():
+    s = tiny_system("one_atom", grids=((15, 15, 15),), alpha_bound=(), n_occ=2)
+    with pytest.raises(binding.IsdfError) as err:
+        binding.Plan(s, universal_all_points=True)
+    assert err.value.status == -7
