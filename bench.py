@@ -385,6 +385,8 @@ def main():
     ap.add_argument("--paths", choices=["both", "reference", "optimized"], default="both")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 2 GiB three times (reference for the HBM byte counters)")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the measurements beside the headline (occ-RI output, universal grid at every point)")
     ap.add_argument("--study", choices=["thresholds", "scaling"],
                     help="run a threshold or scaling study (JSON line per measurement) instead of the benchmark")
     args = ap.parse_args()
@@ -462,6 +464,10 @@ def main():
         timed = kernel_stats(plan)[dom]
         set_profile(plan, 0)
         ms = (t1 - t0) / args.steps * 1e3
+        if args.no_extra:
+            return dict(ms_per_step=ms, value=ms / args.exchanges / 1e3, E_x=ex, n_mu=n_mu,
+                        stats=breakdown, stages=stages, selection=sel, dominant=dom, timed=timed,
+                        occ_ri=None, universal=None)
         # occ-RI output (K C, K never formed) on one more fit, outside the
         # timed steps: per-build time and its energy against the full K's
         fit = plan.fit()
@@ -513,7 +519,7 @@ def main():
     # grid, the universal block of K C by occ-RI FFT Poisson solves; K C
     # only, so it is reported beside the headline, not as it
     all_points = None
-    if args.paths == "both":
+    if args.paths == "both" and not args.no_extra:
         plan = binding.Plan(s, stream=stream, precision=binding.MIXED_X6, tune_file=tune,
                             universal_all_points=True)
         plan.fit().close()
