@@ -160,3 +160,39 @@ def test_all_points_needs_windows():
     with pytest.raises(binding.IsdfError) as err:
         binding.Plan(s, universal_all_points=True)
     assert err.value.status == -7
+
+
+@pytest.mark.parametrize("n_occ", [1, 3])
+def test_universal_few_orbitals(torch, n_occ):
+    """An odd number of pair densities (one complex array half empty) and a
+    single orbital, against the oracle."""
+    from oracle import universal
+    from oracle import plan as oplan
+
+    s = config(1)
+    C_sub = np.ascontiguousarray(s.C_occ[:, :n_occ])
+    plan = binding.Plan(s)
+    fit = plan.fit()
+    KC, e = fit.exchange_universal(torch.tensor(C_sub, dtype=torch.float64, device="cuda"))
+    ref = universal.universal_exchange_occ_ri(oplan.build_plan(s), C_sub)
+    d = float(np.max(np.abs(KC.cpu().numpy() - ref))) / float(np.max(np.abs(ref)))
+    print(f"[universal] cfg1 n_occ {n_occ}: rel max|dKC| {d:.2e}")
+    assert d <= 1e-11 and abs(e - float(np.sum(C_sub * ref))) <= 1e-11 * abs(e)
+    fit.close()
+    plan.close()
+
+
+def test_all_points_single_orbital(torch):
+    from oracle import universal
+
+    s = _all_points_cell()
+    C_sub = np.ascontiguousarray(s.C_occ[:, :1])
+    ref, _ = universal.paper_exchange_occ_ri(s, C_sub)
+    plan = binding.Plan(s, universal_all_points=True)
+    fit = plan.fit()
+    KC, e = fit.exchange_occ_ri(torch.tensor(C_sub, dtype=torch.float64, device="cuda"))
+    d = float(np.max(np.abs(KC.cpu().numpy() - ref))) / float(np.max(np.abs(ref)))
+    print(f"[all points] n_occ 1: rel max|dKC| {d:.2e}")
+    assert d <= 1e-11
+    fit.close()
+    plan.close()
