@@ -357,19 +357,41 @@ def study_scaling(torch, binding, log, reps_list=None, repeat=3):
                 call()
             torch.cuda.synchronize()
             times[name] = 1e3 * (time.perf_counter() - t0) / repeat
+        fit.close()
+        plan.close()
+        # the same cell with every universal point a fitting function
+        plan = binding.Plan(s, precision=binding.MIXED_X6, universal_all_points=True)
+        plan.fit().close()
+        torch.cuda.synchronize()
+        t_ap = []
+        for _ in range(repeat):
+            t0 = time.perf_counter()
+            fit = plan.fit()
+            torch.cuda.synchronize()
+            t_ap.append(time.perf_counter() - t0)
+            if _ < repeat - 1:
+                fit.close()
+        fit.exchange_occ_ri(C, KC)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(repeat):
+            fit.exchange_occ_ri(C, KC)
+        torch.cuda.synchronize()
+        times["all_points_fit_ms"] = 1e3 * min(t_ap)
+        times["all_points_kc_ms"] = 1e3 * (time.perf_counter() - t0) / repeat
+        fit.close()
+        plan.close()
         rec = {"study": "scaling", "cell": list(reps), "atoms": s.n_atoms, "N": n, "n_occ": s.n_occ,
                "grids": s.grids.tolist(), "n_xi_universal": n_u, "n_xi_local": n_loc,
                "domains_at_cap": capped, "fit_ms": 1e3 * min(t_fit), **times}
         out.append(rec)
         print(json.dumps(rec), flush=True)
-        fit.close()
-        plan.close()
         log(f"scaling {reps} done")
     big = [r for r in out if r["atoms"] >= 32]
     if len(big) >= 2:
         lx = np.log([r["N"] for r in big])
         slope = {k: float(np.polyfit(lx, np.log([r[k] for r in big]), 1)[0])
-                 for k in ("fit_ms", "exchange_ms", "occ_ri_ms")}
+                 for k in ("fit_ms", "exchange_ms", "occ_ri_ms", "all_points_fit_ms", "all_points_kc_ms")}
         print(json.dumps({"study": "scaling_exponents", "cells_from_atoms": 32, **slope}), flush=True)
     return out
 
