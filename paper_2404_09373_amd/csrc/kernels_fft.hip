@@ -375,15 +375,23 @@ bool launch_fixed_n(hipStream_t s, double2* z, int batch, int n1, int n2, int n3
   else if (lpw == 8)
     hipLaunchKernelGGL((fft_pass_fixed_kernel<N, 8>), dim3((unsigned)groups), dim3(256), shmem, s,
                        z, batch, n1, n2, n3, axis, sign, tw);
+  else if (lpw == 4)  // y and z lines of grids whose x extent is 4 mod 8
+    hipLaunchKernelGGL((fft_pass_fixed_kernel<N, 4>), dim3((unsigned)groups), dim3(256), shmem, s,
+                       z, batch, n1, n2, n3, axis, sign, tw);
   else
     return false;
   return true;
 }
 
-// Line lengths with a compiled kernel (the grids of the workloads).
+// Line lengths with a compiled kernel (the grids of the workloads, and the
+// lengths the Fourier-threshold ladders of the diamond cells give).
 bool launch_fixed(hipStream_t s, double2* z, int batch, int n1, int n2, int n3, int axis,
                   double sign, const double2* tw, int n, int lpw, int64_t groups) {
   switch (n) {
+    case 12: return launch_fixed_n<12>(s, z, batch, n1, n2, n3, axis, sign, tw, lpw, groups);
+    case 36: return launch_fixed_n<36>(s, z, batch, n1, n2, n3, axis, sign, tw, lpw, groups);
+    case 72: return launch_fixed_n<72>(s, z, batch, n1, n2, n3, axis, sign, tw, lpw, groups);
+    case 100: return launch_fixed_n<100>(s, z, batch, n1, n2, n3, axis, sign, tw, lpw, groups);
     case 24: return launch_fixed_n<24>(s, z, batch, n1, n2, n3, axis, sign, tw, lpw, groups);
     case 32: return launch_fixed_n<32>(s, z, batch, n1, n2, n3, axis, sign, tw, lpw, groups);
     case 40: return launch_fixed_n<40>(s, z, batch, n1, n2, n3, axis, sign, tw, lpw, groups);
