@@ -2417,6 +2417,57 @@ isdf_status exchange_enqueue_ri(isdf_plan_s* plan, isdf_fit_s* fit, const double
   return launch_trace_dot(s, Cin, KC, N * o, fit->partial.as<double>(), 1024, fit->ex_out.as<double>());
 }
 
+// C (M x N, column-major, ldc = M) = alpha op(A) op(B), plus the old C when
+// `accumulate`, with K cut into slices whose products run as one grouped
+// launch and are summed in order (skinny products with a long K: a 64 x 64
+// tile grid of tens of tiles would leave most of the chip idle).
+isdf_status gemm_split_k(isdf_plan_s* pl, const double* A, int64_t lda, int tA, const double* B, int64_t ldb,
+                         int tB, double* C, int64_t M, int64_t N, int64_t K, double alpha, bool accumulate) {
+  hipStream_t s = pl->stream;
+  if (M <= 0 || N <= 0) return ISDF_OK;
+  const int tiles1 = gemm_tiles((int)M, (int)N, 0);
+  const int parts = (int)std::max<int64_t>(1, std::min<int64_t>((512 + tiles1 - 1) / tiles1, K / 256));
+  const int slot0 = accumulate ? 1 : 0;
+  isdf_status st;
+  DevBuf part, dprobs;
+  if ((st = part.alloc(sizeof(double) * (parts + slot0) * M * N)) != ISDF_OK) return st;
+  if (accumulate)
+    ISDF_HIP_TRY(hipMemcpyAsync(part.p, C, sizeof(double) * M * N, hipMemcpyDeviceToDevice, s));
+  std::vector<GemmProblem> probs;
+  const int64_t kc = (K + parts - 1) / parts;
+  int tiles = 0;
+  for (int q = 0; q < parts; ++q) {
+    const int64_t k0 = q * kc, k1 = std::min(K, k0 + kc);
+    if (k1 <= k0) break;
+    GemmProblem p{};
+    p.A = tA ? A + k0 : A + k0 * lda;
+    p.lda = lda;
+    p.transA = tA;
+    p.B = tB ? B + k0 * ldb : B + k0;
+    p.ldb = ldb;
+    p.transB = tB;
+    p.C = part.as<double>() + (slot0 + probs.size()) * M * N;
+    p.ldc = M;
+    p.M = (int)M;
+    p.N = (int)N;
+    p.K = (int)(k1 - k0);
+    p.alpha = alpha;
+    p.beta = 0.0;
+    p.tile_start = tiles;
+    tiles += tiles1;
+    probs.push_back(p);
+  }
+  if ((st = upload(dprobs, probs)) != ISDF_OK) return st;
+  {
+    ProfScope ps(pl, ISDF_K_GEMM_EXCHANGE, 8.0 * (double)K * (M + N) + 8.0 * probs.size() * M * N,
+                 2.0 * (double)M * N * K);
+    if ((st = gemm_f64_grouped(s, EPI_AXPBY, dprobs.as<GemmProblem>(), (int)probs.size(), tiles,
+                               family_tag(ISDF_K_GEMM_EXCHANGE), 0)) != ISDF_OK)
+      return st;
+  }
+  return launch_sum_parts(s, part.as<double>(), (int)probs.size() + slot0, M * N, C);
+}
+
 // Universal-grid terms of K C (row-major N x o), added into KC on the plan's
 // stream.  The universal domain takes every grid point as a fitting
 // function (F = I), E_U = Phi_U C.
@@ -2510,16 +2561,16 @@ isdf_status universal_terms(isdf_plan_s* pl, isdf_fit_s* f, const double* C, int
         (st = gemm(EPI_AXPBY, A2.as<double>(), ng, 0, EN, m, 0, Z1U.as<double>(), ng, ng, o, m, 1.0, 1.0, nullptr,
                    0)) != ISDF_OK)
       return st;
-    if ((st = gemm(EPI_AXPBY, A1.as<double>(), ng, 1, E.as<double>(), ng, 0, Z1w.as<double>(), m, m, o, ng, 1.0,
-                   0.0, nullptr, 0)) != ISDF_OK ||
-        (st = gemm(EPI_AXPBY, A2.as<double>(), ng, 1, E.as<double>(), ng, 0, Z2w.as<double>(), m, m, o, ng, 1.0,
-                   0.0, nullptr, 0)) != ISDF_OK)
+    if ((st = gemm_split_k(pl, A1.as<double>(), ng, 1, E.as<double>(), ng, 0, Z1w.as<double>(), m, o, ng, 1.0,
+                           false)) != ISDF_OK ||
+        (st = gemm_split_k(pl, A2.as<double>(), ng, 1, E.as<double>(), ng, 0, Z2w.as<double>(), m, o, ng, 1.0,
+                           false)) != ISDF_OK)
       return st;
     // (K C)^T += -(Z1w' X^L + Z2w' X^N): window rows of the cross terms
-    if ((st = gemm(EPI_AXPBY, Z1w.as<double>(), m, 1, f->XL.as<double>(), m, 0, KC, o, o, N, m, -1.0, 1.0,
-                   nullptr, 0)) != ISDF_OK ||
-        (st = gemm(EPI_AXPBY, Z2w.as<double>(), m, 1, f->XN.as<double>(), m, 0, KC, o, o, N, m, -1.0, 1.0,
-                   nullptr, 0)) != ISDF_OK)
+    if ((st = gemm_split_k(pl, Z1w.as<double>(), m, 1, f->XL.as<double>(), m, 0, KC, o, N, m, -1.0, true)) !=
+            ISDF_OK ||
+        (st = gemm_split_k(pl, Z2w.as<double>(), m, 1, f->XN.as<double>(), m, 0, KC, o, N, m, -1.0, true)) !=
+            ISDF_OK)
       return st;
   }
   // potentials of the pair densities, batch by batch, into V (column p = pair p)
@@ -2548,8 +2599,8 @@ isdf_status universal_terms(isdf_plan_s* pl, isdf_fit_s* f, const double* C, int
   if ((st = launch_z_accumulate(s, E.as<double>(), V.as<double>(), ng, o, dV, cross ? Z1U.as<double>() : nullptr,
                                 Z.as<double>())) != ISDF_OK)
     return st;
-  if ((st = gemm(EPI_AXPBY, Phi, ng, 1, Z.as<double>(), ng, 0, KC0.as<double>(), n0, n0, o, ng, -1.0, 0.0, nullptr,
-                 0)) != ISDF_OK)
+  if ((st = gemm_split_k(pl, Phi, ng, 1, Z.as<double>(), ng, 0, KC0.as<double>(), n0, o, ng, -1.0, false)) !=
+      ISDF_OK)
     return st;
   if ((st = launch_scatter_add_rows(s, KC0.as<double>(), n0, o, funcs, KC)) != ISDF_OK) return st;
   ISDF_HIP_TRY(hipStreamSynchronize(s));
