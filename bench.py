@@ -542,8 +542,10 @@ def main():
     # only, so it is reported beside the headline, not as it
     all_points = None
     if args.paths == "both" and not args.no_extra:
+        sel = dict(selector=binding.SEL_MLP, mlp_weights=weights, mlp_keep=2.0, mlp_cutoff=0.05) \
+            if weights is not None else {}
         plan = binding.Plan(s, stream=stream, precision=binding.MIXED_X6, tune_file=tune,
-                            universal_all_points=True)
+                            universal_all_points=True, **sel)
         plan.fit().close()
         torch.cuda.synchronize()
         t0 = time.perf_counter()

@@ -196,3 +196,31 @@ def test_all_points_single_orbital(torch):
     assert d <= 1e-11
     fit.close()
     plan.close()
+
+
+def test_all_points_with_learned_selector(torch):
+    """The learned candidate selector on the windows of an all-points plan
+    (the universal domain requests no points and is left out): the same
+    pivots and the same K C as full selection, whatever the weights (here
+    an untrained network; failed candidate lists fall back to full
+    selection)."""
+    from oracle import mlp as omlp
+
+    s = _all_points_cell()
+    C = torch.tensor(s.C_occ, dtype=torch.float64, device="cuda")
+    pf = binding.Plan(s, universal_all_points=True)
+    pm = binding.Plan(s, universal_all_points=True, selector=binding.SEL_MLP,
+                      mlp_weights=omlp.init_params(0).astype(np.float32), mlp_keep=2.0, mlp_cutoff=0.05)
+    ff, fm = pf.fit(), pm.fit()
+    for d in range(pf.n_domains):
+        assert np.array_equal(ff.get("points", d), fm.get("points", d)), f"domain {d}"
+    KCf, ef = ff.exchange_occ_ri(C)
+    KCm, em = fm.exchange_occ_ri(C)
+    info = fm.selection()
+    print(f"[all points] learned selector: candidates {int(np.sum(info['n_candidates']))}, "
+          f"fallbacks {int(np.sum(info['fallback']))}, E_x {em:.12f} / {ef:.12f}")
+    assert torch.equal(KCf, KCm) and ef == em
+    for f in (ff, fm):
+        f.close()
+    for p in (pf, pm):
+        p.close()
