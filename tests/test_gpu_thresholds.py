@@ -78,3 +78,44 @@ def test_threshold_error_falls_with_eps_isdf(results):
     print(f"[threshold] |E_x - E_x(1e-5)|/atom {['%.2e' % x for x in errs]}, local points {counts}")
     assert counts == sorted(counts)
     assert errs[0] > errs[1] > errs[2]
+
+
+def test_threshold_cfg2_full_size_sampled_domains(torch):
+    """The 64-atom cell on its eps_K = 1e-2 ladder (16^3 / 24^3 / 72^3),
+    threshold only at eps_ISDF = 1e-4: the pivots of the universal domain
+    and of sampled windows on both finer levels equal the oracle's, and the
+    exchange of seeded occupied coefficients keeps the properties that hold
+    at any size (K symmetric and negative semidefinite, E_x = tr(C'KC))."""
+    from oracle import basis, isdf
+    from oracle import plan as oplan
+
+    s = config(2, with_density=False)
+    s.grids = binding.grids_for_threshold(s.lattice, s.shell_alpha, s.alpha_bound, EPS_K)
+    assert np.array_equal(s.grids, oplan.grids_for_threshold(s.lattice, s.shell_alpha, s.alpha_bound, EPS_K))
+    s.n_mu_ratio = 0.0
+    s.eps_isdf = 1e-4
+    op = oplan.build_plan(s)
+    plan = binding.Plan(s)
+    fit = plan.fit()
+    assert plan.n_domains == len(op.domains)
+    for d in (0, 1, 40, 64, 65, 100, 128):
+        dom = op.domains[d]
+        Phi = basis.domain_values(op, dom)
+        piv, _, _, _ = isdf.pivoted_cholesky(Phi, dom.L.size, dom.n_mu, s.eps_isdf, s.tie_tol)
+        got = fit.get("points", d)
+        print(f"[threshold cfg2] domain {d} (level {dom.level}): {got.size} points")
+        assert np.array_equal(got, piv), f"domain {d}"
+    n = plan.n_basis
+    rng = np.random.default_rng(17)
+    Ch = rng.standard_normal((n, 32)) / np.sqrt(n)
+    K, e = fit.exchange_occ(torch.tensor(Ch, dtype=torch.float64, device="cuda"))
+    K = K.cpu().numpy()
+    scale = float(np.max(np.abs(K)))
+    ev = np.linalg.eigvalsh(0.5 * (K + K.T))
+    print(f"[threshold cfg2] N_mu {fit.n_mu}: asym {np.max(np.abs(K - K.T)) / scale:.1e}, "
+          f"eig max {ev[-1]:.2e} min {ev[0]:.2e}, E_x {e:.10f}")
+    assert np.max(np.abs(K - K.T)) <= 1e-12 * scale
+    assert ev[-1] <= 1e-10 * abs(ev[0])
+    assert abs(e - float(np.sum(Ch * (K @ Ch)))) <= 1e-10 * abs(e)
+    fit.close()
+    plan.close()
