@@ -469,7 +469,7 @@ isdf_status launch_map_pivots(hipStream_t s, const int32_t* cand, int64_t cand_o
   return ISDF_OK;
 }
 
-// Fallback judge: final residual of every point, d(R) - sum_j F(R,j) Theta(R,j);
+// Fallback check: final residual of every point, d(R) - sum_j F(R,j) Theta(R,j);
 // writes the domain maximum.
 __global__ void __launch_bounds__(256)
 final_residual_kernel(const JudgeDomain* __restrict__ doms, const double* __restrict__ diag,
