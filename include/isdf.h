@@ -119,7 +119,9 @@ typedef struct {
                                  fit there, (R_U|R_U') applied by FFT, never stored);
                                  the exchange is then available as K C only
                                  (isdf_exchange_occ_ri); needs atom windows             */
-  int32_t reserved;
+  int32_t universal_tile_mb;  /* most MB of universal pair potentials held at once (their
+                                 pairs go in row tiles); 0: the smaller of 16 GB and 40 %
+                                 of the free memory                                       */
 } isdf_options;
 
 /* Build the multigrid plan (host only, no device work).
@@ -306,9 +308,10 @@ isdf_status isdf_exchange_occ_ri(isdf_plan_t plan, isdf_fit_t fit, const double*
  * C_dev: device pointer to N x n_occ FP64, row-major (C[mu * n_occ + i]).
  * KC_dev: device pointer to N x n_occ FP64, row-major, written.
  * e_x: host pointer or NULL.  Eager launches; synchronises the stream.
- * Device memory: n_occ (n_occ + 1) / 2 potentials of N_g doubles (2.2 GB at
- * a 32^3 grid and 128 orbitals) plus about 2 GB of transform buffers,
- * released on return.
+ * Device memory: the potentials of the n_occ (n_occ + 1) / 2 pair densities
+ * (N_g doubles each; 2.2 GB at a 32^3 grid and 128 orbitals) are held for
+ * row tiles of pairs within the plan's universal_tile_mb budget, plus about
+ * 2 GB of transform buffers, released on return.
  * Errors: ISDF_E_ARG (null pointers, n_occ outside 1..N, non-finite
  * energy), ISDF_E_STATE (fit not from this plan), ISDF_E_UNSUPPORTED (no
  * universal domain), ISDF_E_NOMEM, ISDF_E_HIP. */

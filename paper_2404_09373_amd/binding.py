@@ -91,7 +91,7 @@ class _Options(C.Structure):
         ("pad0", C.c_int32),
         ("tune_file", C.c_char_p),
         ("universal_all_points", C.c_int32),
-        ("reserved", C.c_int32),
+        ("universal_tile_mb", C.c_int32),
     ]
 
 
@@ -177,7 +177,7 @@ class Plan:
     def __init__(self, sysm, precision: int = FP64, selector: int = SEL_FULL, stream=None,
                  w_batch: int = 0, mlp_weights=None, mlp_keep: float = 2.0,
                  mlp_cutoff: float = 0.05, mixed_mask: int = 0, eager_exchange: bool = False,
-                 tune_file=None, universal_all_points: bool = False):
+                 tune_file=None, universal_all_points: bool = False, universal_tile_mb: int = 0):
         lib = load()
         self._keep = []
         s = _System()
@@ -221,6 +221,7 @@ class Plan:
         o.mixed_mask = int(mixed_mask)
         o.eager_exchange = 1 if eager_exchange else 0
         o.universal_all_points = 1 if universal_all_points else 0
+        o.universal_tile_mb = int(universal_tile_mb)
         if tune_file is not None:
             tf = str(tune_file).encode()
             self._keep.append(tf)

@@ -2505,15 +2505,33 @@ isdf_status universal_terms(isdf_plan_s* pl, isdf_fit_s* f, const double* C, int
   const int64_t P = (int64_t)o * (o + 1) / 2;
   const int64_t m = f->nmu;
   cross = cross && m > 0;
+  // pair potentials are held for tiles of pair rows [a0, a1) within a
+  // budget (universal_tile_mb, else the smaller of 16 GB and 40 % of the
+  // free memory); a tile holds at least one row
+  size_t free_b = 0, total_b = 0;
+  ISDF_HIP_TRY(hipMemGetInfo(&free_b, &total_b));
+  const double v_budget = pl->opts.universal_tile_mb > 0
+                              ? (double)pl->opts.universal_tile_mb * (1 << 20)
+                              : std::min(16e9, 0.4 * ((double)free_b + (pl->mem ? (double)pl->mem->cached : 0.0)));
+  std::vector<std::pair<int, int>> tiles;
+  int64_t tile_max = 0;
+  for (int a0 = 0; a0 < o;) {
+    int a1 = a0;
+    int64_t np = 0;
+    while (a1 < o && (a1 == a0 || (double)(np + (o - a1)) * ng * 8.0 <= v_budget)) np += o - a1++;
+    tiles.emplace_back(a0, a1);
+    tile_max = std::max(tile_max, np);
+    a0 = a1;
+  }
   // pair densities per FFT batch: complex work arrays of at most ~1 GB each
   const int64_t per_pair = 16 * ng;
   int64_t ncb = 2 * std::max<int64_t>(1, std::min<int64_t>(65535, (int64_t)1e9 / per_pair));
-  ncb = std::min<int64_t>(ncb, P + (P & 1));
+  ncb = std::min<int64_t>(ncb, tile_max + (tile_max & 1));
   isdf_status st;
   DevBuf C0, E, V, Z, KC0, zf, zc, dpairs, A1, A2, Z1U, Z1w, Z2w;
   if ((st = C0.alloc(sizeof(double) * n0 * o)) != ISDF_OK || (st = E.alloc(sizeof(double) * ng * o)) != ISDF_OK ||
       (st = Z.alloc(sizeof(double) * ng * o)) != ISDF_OK || (st = KC0.alloc(sizeof(double) * n0 * o)) != ISDF_OK ||
-      (st = V.alloc(sizeof(double) * P * ng)) != ISDF_OK ||
+      (st = V.alloc(sizeof(double) * tile_max * ng)) != ISDF_OK ||
       (st = zf.alloc(sizeof(double) * ng * ncb)) != ISDF_OK || (st = zc.alloc(sizeof(double) * ng * ncb)) != ISDF_OK)
     return st;
   if (cross && ((st = A1.alloc(sizeof(double) * ng * m)) != ISDF_OK ||
@@ -2528,7 +2546,7 @@ isdf_status universal_terms(isdf_plan_s* pl, isdf_fit_s* f, const double* C, int
       pairs[2 * p] = (int32_t)a;
       pairs[2 * p + 1] = (int32_t)b;
     }
-  if ((st = upload(dpairs, pairs)) != ISDF_OK) return st;
+  if ((st = upload(dpairs, pairs)) != ISDF_OK) return st;  // all pairs, row by row
   auto gemm = [&](int epi, const double* A, int64_t lda, int tA, const double* B, int64_t ldb, int tB, double* Cm,
                   int64_t ldc, int64_t M, int64_t Nn, int64_t Kk, double alpha, double beta, const double* Ep,
                   int64_t lde) {
@@ -2573,32 +2591,41 @@ isdf_status universal_terms(isdf_plan_s* pl, isdf_fit_s* f, const double* C, int
             ISDF_OK)
       return st;
   }
-  // potentials of the pair densities, batch by batch, into V (column p = pair p)
+  // per tile of pair rows: potentials of its pair densities, batch by
+  // batch, into V (column q = the tile's pair q), then their part of Z
   const int* g0 = hp.grid[0];
-  for (int64_t p0 = 0; p0 < P; p0 += ncb) {
-    const int nc = (int)std::min<int64_t>(ncb, P - p0);
-    const int npc = (nc + 1) / 2;
-    double* vout = V.as<double>() + p0 * ng;
-    if ((st = launch_pair_density(s, E.as<double>(), ng, dpairs.as<int32_t>() + 2 * p0, nc, zf.as<double>())) !=
-        ISDF_OK)
-      return st;
-    if ((st = fft_prof(pl, zf.as<double>(), npc, g0, -1)) != ISDF_OK) return st;
-    bool fused = false;
-    if ((st = fft_poisson_inverse(s, zf.as<double>(), g0, zc.as<double>(), g0, npc, pl->recip, vout, nc, &fused)) !=
-        ISDF_OK)
-      return st;
-    if (!fused) {
-      if ((st = launch_poisson_restrict(s, zf.as<double>(), g0, zc.as<double>(), g0, npc, pl->recip)) != ISDF_OK)
+  if ((st = launch_fill(s, Z.as<double>(), ng * o, 0.0)) != ISDF_OK) return st;
+  for (const auto& t : tiles) {
+    const int a0 = t.first, a1 = t.second;
+    const int64_t first = (int64_t)a0 * o - (int64_t)a0 * (a0 - 1) / 2;  // pair index of (a0, a0)
+    const int64_t np = (int64_t)(a1 - a0) * o - ((int64_t)a1 * (a1 - 1) - (int64_t)a0 * (a0 - 1)) / 2;
+    for (int64_t q0 = 0; q0 < np; q0 += ncb) {
+      const int nc = (int)std::min<int64_t>(ncb, np - q0);
+      const int npc = (nc + 1) / 2;
+      double* vout = V.as<double>() + q0 * ng;
+      if ((st = launch_pair_density(s, E.as<double>(), ng, dpairs.as<int32_t>() + 2 * (first + q0), nc,
+                                    zf.as<double>())) != ISDF_OK)
         return st;
-      if ((st = fft_prof(pl, zc.as<double>(), npc, g0, +1)) != ISDF_OK) return st;
-      if ((st = launch_split_planar(s, zc.as<double>(), ng, nc, vout)) != ISDF_OK) return st;
+      if ((st = fft_prof(pl, zf.as<double>(), npc, g0, -1)) != ISDF_OK) return st;
+      bool fused = false;
+      if ((st = fft_poisson_inverse(s, zf.as<double>(), g0, zc.as<double>(), g0, npc, pl->recip, vout, nc,
+                                    &fused)) != ISDF_OK)
+        return st;
+      if (!fused) {
+        if ((st = launch_poisson_restrict(s, zf.as<double>(), g0, zc.as<double>(), g0, npc, pl->recip)) != ISDF_OK)
+          return st;
+        if ((st = fft_prof(pl, zc.as<double>(), npc, g0, +1)) != ISDF_OK) return st;
+        if ((st = launch_split_planar(s, zc.as<double>(), ng, nc, vout)) != ISDF_OK) return st;
+      }
     }
+    if ((st = launch_z_accumulate_rows(s, E.as<double>(), V.as<double>(), ng, o, a0, a1, Z.as<double>())) !=
+        ISDF_OK)
+      return st;
   }
   // universal rows: -Phi_U^T (dV Z_UU + A1 E_L + A2 E_N)
   const double dV = hp.volume / (double)ng;
-  if ((st = launch_z_accumulate(s, E.as<double>(), V.as<double>(), ng, o, dV, cross ? Z1U.as<double>() : nullptr,
-                                Z.as<double>())) != ISDF_OK)
-    return st;
+  if ((st = launch_scale_copy(s, Z.as<double>(), Z.as<double>(), ng * o, dV)) != ISDF_OK) return st;
+  if (cross && (st = launch_add(s, Z.as<double>(), Z1U.as<double>(), Z.as<double>(), ng * o)) != ISDF_OK) return st;
   if ((st = gemm_split_k(pl, Phi, ng, 1, Z.as<double>(), ng, 0, KC0.as<double>(), n0, o, ng, -1.0, false)) !=
       ISDF_OK)
     return st;
@@ -2750,6 +2777,10 @@ isdf_status isdf_plan(const isdf_system* sys, const isdf_options* opts, isdf_pla
   if (pl->opts.precision != ISDF_FP64 && pl->opts.precision != ISDF_MIXED_X3 &&
       pl->opts.precision != ISDF_MIXED_X6) {
     set_error("isdf_plan: unknown precision");
+    return ISDF_E_ARG;
+  }
+  if (pl->opts.universal_tile_mb < 0) {
+    set_error("isdf_plan: universal_tile_mb must not be negative");
     return ISDF_E_ARG;
   }
   if (pl->opts.mixed_mask < 0 || pl->opts.mixed_mask > 7) {

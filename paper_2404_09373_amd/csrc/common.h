@@ -300,8 +300,8 @@ isdf_status launch_scatter_add_rows(hipStream_t s, const double* KC0, int n0, in
 isdf_status launch_scale_copy(hipStream_t s, const double* src, double* dst, int64_t n, double alpha);
 isdf_status launch_pair_density(hipStream_t s, const double* E, int64_t ng, const int32_t* pairs, int ncols,
                                 double* z);
-isdf_status launch_z_accumulate(hipStream_t s, const double* E, const double* V, int64_t ng, int o, double scale,
-                                const double* add, double* Z);
+isdf_status launch_z_accumulate_rows(hipStream_t s, const double* E, const double* V, int64_t ng, int o, int a0,
+                                     int a1, double* Z);
 
 // ------------------------------------------------------- mixed precision
 // BF16-split GEMM problem: A planes hold (m, k) at A + p plane_a + m lda + k,

@@ -8,7 +8,8 @@
 //   E(R, i)  = sum_nu Phi_U(R, nu) C(nu, i)           (GEMM)
 //   rho_p(R) = E(R, a_p) E(R, b_p),  p = (a_p <= b_p) pair_density_kernel
 //   V_p      = potential of rho_p                     (FFT Poisson)
-//   Z(R, i)  = sum_j E(R, j) V_{pair(i, j)}(R)        z_accumulate_kernel
+//   Z(R, i)  = sum_j E(R, j) V_{pair(i, j)}(R)        z_accumulate_rows_kernel,
+//              over tiles of pair rows that bound the potentials held
 //   K_UU C   = -dV Phi_U^T Z                          (GEMM, row scatter)
 // With atom windows fitted as usual, the universal-window cross terms of the
 // same K C run on the GEMM engine and their universal rows join Z here.
@@ -106,52 +107,49 @@ isdf_status launch_pair_density(hipStream_t s, const double* E, int64_t ng, cons
   return ISDF_OK;
 }
 
-// Z(R, i) = scale sum_j E(R, j) V_{pair(min(i,j), max(i,j))}(R) (+ add(R, i)),
-// pairs numbered row by row over a <= b: pair(a, b) = a o - a (a - 1) / 2 +
-// b - a.  One thread per point and a block of ZB occupied columns
-// (blockIdx.y); the sum over j runs in order, so the result does not depend
-// on the launch.
+// Z(R, i) += sum over the pairs (a <= b) of rows a0 <= a < a1 that hold i:
+// E(R, b) V_ab(R) where a = i, E(R, a) V_ai(R) where a < i.  The pairs of
+// the tile are numbered row by row from (a0, a0): row a starts at
+// (a - a0) o - (a (a - 1) - a0 (a0 - 1)) / 2.  One thread per point and a
+// block of ZB occupied columns (blockIdx.y); within a tile the sum over the
+// partner runs in ascending order, and tiles are added in order, so the
+// result does not depend on the launch.  Z starts at zero.
 constexpr int ZB = 8;
-__global__ void z_accumulate_kernel(const double* __restrict__ E, const double* __restrict__ V, int64_t ng,
-                                    int o, double scale, const double* __restrict__ add,
-                                    double* __restrict__ Z) {
+__global__ void z_accumulate_rows_kernel(const double* __restrict__ E, const double* __restrict__ V, int64_t ng,
+                                         int o, int a0, int a1, double* __restrict__ Z) {
   const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (r >= ng) return;
   const int i0 = blockIdx.y * ZB;
-  double acc[ZB];
+  auto row0 = [&](int64_t a) -> int64_t {
+    return (a - a0) * o - (a * (a - 1) - (int64_t)a0 * (a0 - 1)) / 2;
+  };
 #pragma unroll
-  for (int t = 0; t < ZB; ++t) acc[t] = 0.0;
-  for (int j = 0; j < o; ++j) {
-    const double e = E[r + (int64_t)j * ng];
-#pragma unroll
-    for (int t = 0; t < ZB; ++t) {
-      const int i = i0 + t;
-      if (i < o) {
-        const int64_t a = i < j ? i : j, b = i < j ? j : i;
-        const int64_t p = a * o - a * (a - 1) / 2 + (b - a);
-        acc[t] += e * V[p * ng + r];
-      }
+  for (int t = 0; t < ZB; ++t) {
+    const int i = i0 + t;
+    if (i >= o || i < a0) continue;
+    double acc = 0.0;
+    const int amax = i < a1 ? i : a1;
+    for (int a = a0; a < amax; ++a)  // pairs (a, i), a < i
+      acc += E[r + (int64_t)a * ng] * V[(row0(a) + (i - a)) * ng + r];
+    if (i < a1) {  // pairs (i, b), b >= i
+      const int64_t base = row0(i);
+      for (int b = i; b < o; ++b) acc += E[r + (int64_t)b * ng] * V[(base + (b - i)) * ng + r];
     }
+    Z[r + (int64_t)i * ng] += acc;
   }
-#pragma unroll
-  for (int t = 0; t < ZB; ++t)
-    if (i0 + t < o) {
-      const int64_t at = r + (int64_t)(i0 + t) * ng;
-      Z[at] = scale * acc[t] + (add ? add[at] : 0.0);
-    }
 }
 
-isdf_status launch_z_accumulate(hipStream_t s, const double* E, const double* V, int64_t ng, int o, double scale,
-                                const double* add, double* Z) {
-  if (ng <= 0 || o <= 0) return ISDF_OK;
+isdf_status launch_z_accumulate_rows(hipStream_t s, const double* E, const double* V, int64_t ng, int o, int a0,
+                                     int a1, double* Z) {
+  if (ng <= 0 || o <= 0 || a1 <= a0) return ISDF_OK;
   const int64_t bx = (ng + 255) / 256;
   const int by = (o + ZB - 1) / ZB;
   if (bx > 0x7fffffff || by > 65535) {
     set_error("universal exchange: grid or occupied count too large");
     return ISDF_E_UNSUPPORTED;
   }
-  hipLaunchKernelGGL(z_accumulate_kernel, dim3((unsigned)bx, (unsigned)by), dim3(256), 0, s, E, V, ng, o, scale,
-                     add, Z);
+  hipLaunchKernelGGL(z_accumulate_rows_kernel, dim3((unsigned)bx, (unsigned)by), dim3(256), 0, s, E, V, ng, o, a0,
+                     a1, Z);
   ISDF_HIP_TRY(hipGetLastError());
   return ISDF_OK;
 }

@@ -224,3 +224,38 @@ def test_all_points_with_learned_selector(torch):
         f.close()
     for p in (pf, pm):
         p.close()
+
+
+def test_universal_tiles_of_pair_rows(torch):
+    """A budget of 1 MB holds a few pair rows at a time (the 8-atom cell's
+    24^3 grid: 110 kB a potential): many tiles give the same K_UU C as one
+    tile (sums in another order), also inside the all-points exchange."""
+    s = config(1)
+    C = torch.tensor(s.C_occ, dtype=torch.float64, device="cuda")
+    out = {}
+    for mb in (0, 1):
+        plan = binding.Plan(s, universal_tile_mb=mb)
+        fit = plan.fit()
+        KC, e = fit.exchange_universal(C)
+        out[mb] = (KC.cpu().numpy(), e)
+        fit.close()
+        plan.close()
+    d = float(np.max(np.abs(out[0][0] - out[1][0]))) / float(np.max(np.abs(out[0][0])))
+    print(f"[universal] 1 MB tiles vs one tile: rel max|dKC| {d:.2e}")
+    assert d <= 1e-13 and abs(out[0][1] - out[1][1]) <= 1e-13 * abs(out[0][1])
+    s2 = _all_points_cell()
+    C2 = torch.tensor(s2.C_occ, dtype=torch.float64, device="cuda")
+    res = []
+    for mb in (0, 1):
+        plan = binding.Plan(s2, universal_all_points=True, universal_tile_mb=mb)
+        fit = plan.fit()
+        KC, e = fit.exchange_occ_ri(C2)
+        res.append(KC.cpu().numpy())
+        fit.close()
+        plan.close()
+    d2 = float(np.max(np.abs(res[0] - res[1]))) / float(np.max(np.abs(res[0])))
+    print(f"[all points] 1 MB tiles vs one tile: rel max|dKC| {d2:.2e}")
+    assert d2 <= 1e-13
+    with pytest.raises(binding.IsdfError) as err:
+        binding.Plan(s, universal_tile_mb=-1)
+    assert err.value.status == -1
