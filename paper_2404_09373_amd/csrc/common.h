@@ -225,6 +225,8 @@ isdf_status launch_gather_x(hipStream_t s, const GatherDom* doms, int ndom, int 
                             double* xrows, double* XL, double* XN, int64_t nmu);
 
 isdf_status launch_fill(hipStream_t s, double* p, int64_t n, double v);
+// C(m, n) = c (c + 2 t), c = C(m, n) (ldc), t = T(m, n) (ldt = M; 0 if T is null)
+isdf_status launch_theta_combine(hipStream_t s, double* C, int64_t ldc, const double* T, int M, int N);
 isdf_status launch_gather_square(hipStream_t s, const double* theta, int64_t pts, int n,
                                  const int32_t* piv, double* M);
 // small domains (n <= 64): Cholesky of M = Theta[piv,:] and F = Theta M^-1 per row

@@ -189,6 +189,28 @@ isdf_status launch_sub(hipStream_t s, const double* a, const double* b, double* 
   return launch_add_scaled(s, a, b, c, n, -1.0);
 }
 
+// C(m, n) = c (c + 2 t) with c = C(m, n) (ldc) and t = T(m, n) (ldt = M;
+// t = 0 when T is null): the Hadamard Gram of Eq. M(R,R) from its two parts
+// a_L (in C) and a_N (in T).
+__global__ void theta_combine_kernel(double* C, int64_t ldc, const double* T, int M, int N) {
+  const int64_t n_all = (int64_t)M * N;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n_all;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int m = (int)(t % M), n = (int)(t / M);
+    double* c = C + m + (int64_t)n * ldc;
+    const double x = *c;
+    *c = x * (x + 2.0 * (T ? T[t] : 0.0));
+  }
+}
+isdf_status launch_theta_combine(hipStream_t s, double* C, int64_t ldc, const double* T, int M, int N) {
+  const int64_t n_all = (int64_t)M * N;
+  if (n_all <= 0) return ISDF_OK;
+  const int64_t blocks = std::min<int64_t>((n_all + 255) / 256, 65536);
+  hipLaunchKernelGGL(theta_combine_kernel, dim3((unsigned)blocks), dim3(256), 0, s, C, ldc, T, M, N);
+  ISDF_HIP_TRY(hipGetLastError());
+  return ISDF_OK;
+}
+
 // M(i, j) = Theta(piv_i, j), n x n column-major
 __global__ void gather_square_kernel(const double* theta, int64_t pts, int n, const int32_t* piv,
                                      double* M) {
