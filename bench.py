@@ -320,6 +320,40 @@ def study_thresholds(torch, binding, log):
     return out
 
 
+def study_universal(torch, binding, log, builds=5):
+    """The 64-atom cell with every universal point a fitting function (full
+    selection on the windows, x6 window terms): fit time, then K C per build
+    (isdf_exchange_occ_ri) and the universal block alone
+    (isdf_exchange_universal), each over `builds` builds after two warm ones."""
+    from workloads import config
+
+    s = config(2)
+    C = torch.tensor(s.C_occ, dtype=torch.float64, device="cuda")
+    plan = binding.Plan(s, precision=binding.MIXED_X6, universal_all_points=True)
+    plan.fit().close()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fit = plan.fit()
+    torch.cuda.synchronize()
+    rec = {"study": "universal", "fit_ms": 1e3 * (time.perf_counter() - t0)}
+    KC = torch.empty_like(C)
+    for name, call in (("kc_ms_per_build", lambda: fit.exchange_occ_ri(C, KC)),
+                       ("universal_block_ms", lambda: fit.exchange_universal(C, KC))):
+        for _ in range(2):
+            call()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(builds):
+            _, e = call()
+        torch.cuda.synchronize()
+        rec[name] = 1e3 * (time.perf_counter() - t0) / builds
+        rec[name.replace("_ms_per_build", "").replace("_ms", "") + "_energy"] = e
+        log(f"universal: {name} done")
+    print(json.dumps(rec), flush=True)
+    fit.close()
+    plan.close()
+
+
 def study_scaling(torch, binding, log, reps_list=None, repeat=3):
     """Fit and exchange build times against system size (the scaling study of
     the Results section): eps_K = 1e-2, eps_ISDF = 1e-4 (the paper's diamond
@@ -411,7 +445,7 @@ def main():
                     help="only copy 2 GiB three times (reference for the HBM byte counters)")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the measurements beside the headline (occ-RI output, universal grid at every point)")
-    ap.add_argument("--study", choices=["thresholds", "scaling"],
+    ap.add_argument("--study", choices=["thresholds", "scaling", "universal"],
                     help="run a threshold or scaling study (JSON line per measurement) instead of the benchmark")
     ap.add_argument("--cells", default="",
                     help="scaling study cells as repeats of the 8-atom cell, e.g. 4x3x3,4x4x4 (default 1x1x1 .. 3x3x3)")
@@ -443,6 +477,8 @@ def main():
         torch.cuda.set_device(0)
         if args.study == "thresholds":
             study_thresholds(torch, binding, log)
+        elif args.study == "universal":
+            study_universal(torch, binding, log)
         else:
             cells = [tuple(int(x) for x in c.split("x")) for c in args.cells.split(",") if c]
             study_scaling(torch, binding, log, reps_list=cells or None)
