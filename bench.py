@@ -139,9 +139,9 @@ def roofline(fam, st, mixed):
 def train_selector(torch, log):
     """Full FP64 selections of the 8-atom cell and of a 64-atom cell with other
     displacements -> features/labels -> Adam on the GPU (library kernels)."""
-    from oracle import mlp as omlp  # parameter initialisation only (He normal, seeded)
     from paper_2404_09373_amd import binding
     from workloads import config, diamond_system
+    from workloads.selector_init import initial_weights
 
     systems = [config(1, with_density=False),
                diamond_system((2, 2, 2), ((32, 32, 32), (64, 64, 64), (128, 128, 128)), 8.0, 128,
@@ -158,7 +158,7 @@ def train_selector(torch, log):
     X = torch.cat(Xs)
     Y = torch.cat(Ys)
     t = time.perf_counter()
-    w, hist = binding.mlp_train(X, Y, omlp.init_params(0).astype(np.float32), epochs=10,
+    w, hist = binding.mlp_train(X, Y, initial_weights(0).astype(np.float32), epochs=10,
                                 batch=16384, lr=2e-3, seed=1)
     log(f"trained selector on {X.shape[0]} points in {time.perf_counter() - t:.2f}s, "
         f"loss {hist[0]:.4f} -> {hist[-1]:.4f}")

@@ -52,12 +52,12 @@ def unpack(theta):
 
 
 def init_params(seed: int = 0) -> np.ndarray:
-    """He-normal weights, zero biases."""
-    rng = np.random.default_rng(seed)
-    th = np.zeros(NPARAM)
-    th[OFF_W1:OFF_B1] = rng.standard_normal(NH * NF) * np.sqrt(2.0 / NF)
-    th[OFF_W2:OFF_B2] = rng.standard_normal(NH * NH) * np.sqrt(2.0 / NH)
-    th[OFF_W3:OFF_B3] = rng.standard_normal(NH) * np.sqrt(2.0 / NH)
+    """He-normal weights, zero biases: the seeded initial weights of the
+    shared input generators (``workloads.selector_init``)."""
+    from workloads.selector_init import initial_weights
+
+    th = initial_weights(seed)
+    assert th.size == NPARAM
     return th
 
 

@@ -17,3 +17,4 @@ from .diamond import (  # noqa: F401
     level_bounds,
     batched_cells,
 )
+from .selector_init import initial_weights  # noqa: F401
