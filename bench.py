@@ -40,7 +40,7 @@ PEAK_FP64_TFS = 78.6
 PEAK_BF16_TFS = 2500.0
 # family id -> (name, bound, kernel name in profiles)
 FAMILIES = {
-    0: ("select_column", "hbm", "sel_column_kernel | crb_step_kernel"),
+    0: ("select_column", "hbm", "sel_column_kernel"),
     1: ("select_pick", "hbm", "sel_select_kernel"),
     2: ("gemm_select", "mfma", "gemm_f64_kernel<*, 1>"),
     3: ("gemm_metric", "mfma", "gemm_f64_kernel<*, 2>"),
@@ -48,6 +48,7 @@ FAMILIES = {
     5: ("gemm_exchange", "mfma", "gemm_f64_kernel<*, 4>"),
     6: ("fft", "hbm", "fft_pass_fixed_kernel | fft_fwd_pruned_kernel | fft_pass_kernel"),
     7: ("basis", "hbm", "basis_eval_kernel"),
+    8: ("select_block", "hbm", "crb_step_kernel"),
 }
 
 

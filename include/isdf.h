@@ -378,11 +378,14 @@ isdf_status isdf_stage_times(isdf_plan_t plan, double* t_ms, int32_t n);
  *   ISDF_K_GEMM_FIT       Theta, blocked Cholesky and triangular-solve products
  *   ISDF_K_GEMM_EXCHANGE  exchange products (Eq. ints)
  *   ISDF_K_FFT            FFT passes of the Poisson solves
- *   ISDF_K_BASIS          basis values + Gram diagonal */
+ *   ISDF_K_BASIS          basis values + Gram diagonal
+ *   ISDF_K_SELECT_BLOCK   candidate-restricted steps of the universal grid's
+ *                         selection (pick + column on the candidates, one
+ *                         launch per pivot) */
 enum {
   ISDF_K_SELECT_COLUMN = 0, ISDF_K_SELECT_PICK = 1, ISDF_K_GEMM_SELECT = 2,
   ISDF_K_GEMM_METRIC = 3, ISDF_K_GEMM_FIT = 4, ISDF_K_GEMM_EXCHANGE = 5, ISDF_K_FFT = 6,
-  ISDF_K_BASIS = 7, ISDF_K_NFAMILY = 8, ISDF_K_ALL = (1 << 8) - 1
+  ISDF_K_BASIS = 7, ISDF_K_SELECT_BLOCK = 8, ISDF_K_NFAMILY = 9, ISDF_K_ALL = (1 << 9) - 1
 };
 isdf_status isdf_profile(isdf_plan_t plan, int32_t family_mask);
 isdf_status isdf_kernel_stats(isdf_plan_t plan, int32_t family, double* ms, int64_t* launches,

@@ -862,7 +862,7 @@ isdf_status crb_select(isdf_plan_s* pl, const SelDomain& X, const double* phi_ba
     for (int k0 = 0, chunk = 0; k0 <= nb; k0 += CRB_CHUNK, ++chunk) {
       const int k1 = std::min(nb + 1, k0 + CRB_CHUNK);
       for (int k = k0; k < k1; ++k) {
-        ProfScope ps(pl, ISDF_K_SELECT_COLUMN, 8.0 * nc * (k + 4.0) + 12.0 * B.ntiles, 2.0 * nc * k);
+        ProfScope ps(pl, ISDF_K_SELECT_BLOCK, 8.0 * nc * (k + 4.0) + 12.0 * B.ntiles, 2.0 * nc * k);
         if ((e = launch_crb_step(s, k, cb)) != ISDF_OK) return e;
       }
       if (k1 > nb) break;
