@@ -745,7 +745,7 @@ isdf_status crb_select(isdf_plan_s* pl, const SelDomain& X, const double* phi_ba
   int32_t* piv = piv_out + X.piv_off;
   const double tau = hp.tie_tol, eps = hp.eps_isdf;
   isdf_status e;
-  DevBuf cidx, dC, dC2, info, phiC, LC, RCC, LCb, tmaxb, tidxb, stb, pivC, tdom, sdb, phiP, LP, Ub;
+  DevBuf cidx, dC, dC2, info, phiC, LC, RCC, LCb, tmaxb, tidxb, tvalb, stb, pivC, tdom, sdb, phiP, LP, Ub;
   const int Tmax = n;
   int T = std::min(n, CRB_CANDIDATES);
   if ((e = cidx.alloc(sizeof(int32_t) * n)) != ISDF_OK) return e;
@@ -826,13 +826,14 @@ isdf_status crb_select(isdf_plan_s* pl, const SelDomain& X, const double* phi_ba
     if ((e = LCb.alloc(sizeof(double) * (size_t)nc * nb)) != ISDF_OK) return e;
     if ((e = tmaxb.alloc(sizeof(double) * 2 * B.ntiles)) != ISDF_OK) return e;
     if ((e = tidxb.alloc(sizeof(int32_t) * 2 * B.ntiles)) != ISDF_OK) return e;
+    if ((e = tvalb.alloc(sizeof(double) * 2 * B.ntiles)) != ISDF_OK) return e;
     if ((e = dC2.alloc(sizeof(double) * (size_t)nc)) != ISDF_OK) return e;
     ISDF_HIP_TRY(hipMemsetAsync(stb.p, 0, sizeof(SelState), s));
     const SelDomain* Dd = sdb.as<SelDomain>();
     const double dstop = ci.theta >= 0.0 ? ci.theta / (1.0 - tau) : 0.0;
     SelState* Sd = stb.as<SelState>();
     if ((e = launch_sel_init(s, Dd, tdom.as<int32_t>(), 0, B.ntiles, dC.as<double>(), tmaxb.as<double>(),
-                             tidxb.as<int32_t>(), tau)) != ISDF_OK)
+                             tidxb.as<int32_t>(), tau, tvalb.as<double>())) != ISDF_OK)
       return e;
     CrbBlock cb{};
     cb.R = RCC.as<double>();
@@ -843,6 +844,8 @@ isdf_status crb_select(isdf_plan_s* pl, const SelDomain& X, const double* phi_ba
     cb.t[1] = tmaxb.as<double>() + B.ntiles;
     cb.i[0] = tidxb.as<int32_t>();
     cb.i[1] = tidxb.as<int32_t>() + B.ntiles;
+    cb.v[0] = tvalb.as<double>();
+    cb.v[1] = tvalb.as<double>() + B.ntiles;
     cb.st = Sd;
     cb.pivC = pivC.as<int32_t>();
     cb.nc = nc;

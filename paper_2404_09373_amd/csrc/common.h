@@ -166,7 +166,7 @@ struct SelState {
 constexpr int SEL_TILE = 64;
 isdf_status launch_sel_init(hipStream_t s, const SelDomain* doms, const int32_t* tile_dom,
                             int tile_base, int ntiles, const double* diag, double* tmax,
-                            int32_t* tidx, double tau);
+                            int32_t* tidx, double tau, double* tval = nullptr);
 isdf_status launch_sel_select(hipStream_t s, const SelDomain* doms, int dom_base, int ndom,
                               int k, SelState* st, const double* phi, const double* lfac,
                               double* diag, const double* tmax, const int32_t* tidx, double* prow,
@@ -207,6 +207,7 @@ struct CrbBlock {
   double* d[2];
   double* t[2];
   int32_t* i[2];
+  double* v[2];  // residual at each tile's tie candidate i[c][tile]
   SelState* st;
   int32_t* pivC;  // block pivots, candidate positions
   int32_t nc, nb;

@@ -169,19 +169,24 @@ isdf_status launch_crb_candidates(hipStream_t s, const double* d, int n, int T, 
 // One greedy step of a block on the candidates, pick and column in one
 // launch.  Every workgroup redoes the pick of step k from the tile maxima of
 // step k - 1 (all get the same pivot), then forms the column on its own
-// 64-candidate tile; the diagonal and the tile maxima alternate between two
-// copies, so no workgroup reads what another one writes in this launch.
-// Stops as the separate pick does (count, eps, block threshold); workgroup 0
-// records the state.
+// 64-candidate tile; the diagonal, the tile maxima, the tiles' tie
+// candidates and their residuals alternate between two copies, so no
+// workgroup reads what another one writes in this launch.  Stops as the
+// separate pick does (count, eps, block threshold); workgroup 0 records the
+// state.  The pick is a chain of dependent reads; it is kept short: the
+// done flag and the tile maxima are read together, the maxima stay in
+// registers for the first-tile search, and the pivot's residual comes with
+// its tile's candidate instead of from a read of the diagonal (the tile is
+// scanned only when its own candidate lies below the global tie window).
 __global__ void __launch_bounds__(256)
 crb_step_kernel(int k, CrbBlock blk) {
   __shared__ double s_red[4];
   __shared__ int s_redi[4];
   __shared__ int s_cand;
+  __shared__ double s_dp;
   __shared__ double red[4][64];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   SelState* __restrict__ st = blk.st;
-  if (st->done) return;
   const int nb = blk.nb, nc = blk.nc, c = k & 1;
   const double* __restrict__ R = blk.R;
   double* __restrict__ Lb = blk.Lb;
@@ -189,19 +194,24 @@ crb_step_kernel(int k, CrbBlock blk) {
   double* __restrict__ dnext = blk.d[c ^ 1];
   const double* __restrict__ tcur = blk.t[c];
   const int32_t* __restrict__ icur = blk.i[c];
+  const double* __restrict__ vcur = blk.v[c];
   double* __restrict__ tnext = blk.t[c ^ 1];
   int32_t* __restrict__ inext = blk.i[c ^ 1];
+  double* __restrict__ vnext = blk.v[c ^ 1];
   int32_t* __restrict__ pivC = blk.pivC;
   const double tau = blk.tau, eps = blk.eps, dstop = blk.dstop, d0max = blk.d0max;
   const int ntiles = (nc + SEL_TILE - 1) / SEL_TILE;
+  const int done = st->done;
+  const double t_own = tid < ntiles ? tcur[tid] : -1.0;
+  if (done) return;
   // ---- pick
   int reason = 0, p = INT_MAX;
   double dp = 0.0;
   if (k >= nb) {
     reason = SEL_END_COUNT;
   } else {
-    double m = -1.0;
-    for (int t = tid; t < ntiles; t += 256) m = fmax(m, tcur[t]);
+    double m = t_own;
+    for (int t = tid + 256; t < ntiles; t += 256) m = fmax(m, tcur[t]);
     m = wave_max(m);
     if (lane == 0) s_red[w] = m;
     __syncthreads();
@@ -210,8 +220,8 @@ crb_step_kernel(int k, CrbBlock blk) {
       reason = SEL_END_EPS;
     } else {
       const double thr = (1.0 - tau) * Mstar;
-      int ft = INT_MAX;
-      for (int t = tid; t < ntiles; t += 256)
+      int ft = (tid < ntiles && t_own >= thr) ? tid : INT_MAX;
+      for (int t = tid + 256; t < ntiles; t += 256)
         if (tcur[t] >= thr) ft = min(ft, t);
       ft = wave_min_int(ft);
       if (lane == 0) s_redi[w] = ft;
@@ -220,22 +230,28 @@ crb_step_kernel(int k, CrbBlock blk) {
       if (t0 == INT_MAX) {
         reason = SEL_END_EPS;
       } else {
-        int cand = INT_MAX;
         if (w == 0) {
-          const int i = t0 * SEL_TILE + lane;
           const int quick = icur[t0];
-          if (quick != INT_MAX && dcur[quick] >= thr) {
+          const double qv = vcur[t0];
+          int cand;
+          double cv;
+          if (quick != INT_MAX && qv >= thr) {
             cand = quick;
-          } else if (i < nc) {
-            const double dv = dcur[i];
-            if (dv >= 0.0 && dv >= thr) cand = i;
+            cv = qv;
+          } else {
+            const int i = t0 * SEL_TILE + lane;
+            const double dv = i < nc ? dcur[i] : -1.0;
+            cand = wave_min_int((i < nc && dv >= 0.0 && dv >= thr) ? i : INT_MAX);
+            cv = __shfl(dv, cand == INT_MAX ? 0 : (cand & 63), 64);
           }
-          cand = wave_min_int(cand);
-          if (lane == 0) s_cand = cand;
+          if (lane == 0) {
+            s_cand = cand;
+            s_dp = cand == INT_MAX ? 0.0 : cv;
+          }
         }
         __syncthreads();
         p = s_cand;
-        dp = p == INT_MAX ? 0.0 : dcur[p];
+        dp = s_dp;
         if (p == INT_MAX || !(dp > eps * d0max)) reason = SEL_END_EPS;
         else if (!(dp > dstop)) reason = SEL_END_BLOCK;
       }
@@ -260,6 +276,13 @@ crb_step_kernel(int k, CrbBlock blk) {
   const bool valid = i < nc;
   const int ii = valid ? i : 0;
   const int64_t P = nc;
+  // the pivot row of the residual and the old diagonal do not depend on the
+  // column sum: their reads go out first
+  double rv = 0.0, old = -1.0;
+  if (w == 0) {
+    rv = (ii >= p) ? R[ii + (int64_t)p * P] : R[p + (int64_t)ii * P];
+    old = dcur[ii];
+  }
   double sc = 0.0;
   const double* lf = Lb + ii;
   const double* lp = Lb + p;
@@ -273,23 +296,23 @@ crb_step_kernel(int k, CrbBlock blk) {
   __syncthreads();
   if (w != 0) return;
   sc = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
-  const double rv = (ii >= p) ? R[ii + (int64_t)p * P] : R[p + (int64_t)ii * P];
   const double ell = (rv - sc) / sqrt(dp);
   double dv = -1.0;
   if (valid) {
     Lb[(int64_t)k * P + i] = ell;
-    const double old = dcur[i];
     dv = (i == p) ? -1.0 : (old >= 0.0 ? fmax(old - ell * ell, 0.0) : old);
     dnext[i] = dv;
   }
-  // tile maximum and the smallest index in its tie window
+  // tile maximum, the smallest index in its tie window and its residual
   const bool act = valid && dv >= 0.0;
   const double tm = wave_max(act ? dv : -1.0);
   const int cnd = (act && tm >= 0.0 && dv >= (1.0 - tau) * tm) ? i : INT_MAX;
   const int mi = wave_min_int(cnd);
+  const double vm = __shfl(dv, mi == INT_MAX ? 0 : (mi & 63), 64);
   if (lane == 0) {
     tnext[blockIdx.x] = tm;
     inext[blockIdx.x] = mi;
+    vnext[blockIdx.x] = mi == INT_MAX ? -1.0 : vm;
   }
 }
 

@@ -124,38 +124,43 @@ __device__ inline int wave_min_int(int v) {
 }
 
 // Tile partials: tmax = max residual over active points of the tile (-1 if
-// none), tidx = smallest active index with d >= (1 - tau) tmax.
+// none), tidx = smallest active index with d >= (1 - tau) tmax, and, when
+// tval is given, the residual at that index (-1 if none).  The tile's
+// points are consecutive indices starting at a multiple of 64, so the lane
+// holding index mi is mi mod 64.
 __device__ inline void tile_partial(double dv, bool active, int i, double tau, double* tmax,
-                                    int32_t* tidx, int tile) {
+                                    int32_t* tidx, int tile, double* tval = nullptr) {
   const double v = active ? dv : -1.0;
   const double m = wave_max(v);
   const double thr = (1.0 - tau) * m;
   const int cand = (active && m >= 0.0 && dv >= thr) ? i : INT_MAX;
   const int mi = wave_min_int(cand);
+  const double vm = __shfl(dv, mi == INT_MAX ? 0 : (mi & 63), 64);
   if ((threadIdx.x & 63) == 0) {
     tmax[tile] = m;
     tidx[tile] = mi;
+    if (tval) tval[tile] = mi == INT_MAX ? -1.0 : vm;
   }
 }
 
 __global__ void __launch_bounds__(64)
 sel_init_kernel(const SelDomain* __restrict__ doms, const int32_t* __restrict__ tile_dom,
                 int tile_base, const double* __restrict__ diag, double* __restrict__ tmax,
-                int32_t* __restrict__ tidx, double tau) {
+                int32_t* __restrict__ tidx, double tau, double* __restrict__ tval) {
   const int tile = tile_base + (int)blockIdx.x;
   const SelDomain D = doms[tile_dom[tile]];
   const int i = (tile - D.tile_off) * SEL_TILE + (int)threadIdx.x;
   const bool valid = i < D.pts;
   const double dv = valid ? diag[D.diag_off + i] : -1.0;
-  tile_partial(dv, valid && dv >= 0.0, i, tau, tmax, tidx, tile);
+  tile_partial(dv, valid && dv >= 0.0, i, tau, tmax, tidx, tile, tval);
 }
 
 isdf_status launch_sel_init(hipStream_t s, const SelDomain* doms, const int32_t* tile_dom,
                             int tile_base, int ntiles, const double* diag, double* tmax,
-                            int32_t* tidx, double tau) {
+                            int32_t* tidx, double tau, double* tval) {
   if (ntiles <= 0) return ISDF_OK;
   hipLaunchKernelGGL(sel_init_kernel, dim3(ntiles), dim3(64), 0, s, doms, tile_dom, tile_base,
-                     diag, tmax, tidx, tau);
+                     diag, tmax, tidx, tau, tval);
   ISDF_HIP_TRY(hipGetLastError());
   return ISDF_OK;
 }
