@@ -371,8 +371,9 @@ isdf_status isdf_stage_times(isdf_plan_t plan, double* t_ms, int32_t n);
  * (what the method must move or compute: basis columns, factor columns and
  * residuals for the selection column kernel; 2 M N K per GEMM, N (N + 1) K
  * for a lower-triangle update).
- *   ISDF_K_SELECT_COLUMN  pivoted-Cholesky column + residual update
- *   ISDF_K_SELECT_PICK    tie-rule pivot pick
+ *   ISDF_K_SELECT_COLUMN  pivoted-Cholesky column + residual update of the
+ *                         windows (batched per level, left-looking)
+ *   ISDF_K_SELECT_PICK    tie-rule pivot pick of the windows
  *   ISDF_K_GEMM_SELECT    residual pair Gram and its rank updates (right-looking)
  *   ISDF_K_GEMM_METRIC    W = dV F^T V products
  *   ISDF_K_GEMM_FIT       Theta, blocked Cholesky and triangular-solve products
