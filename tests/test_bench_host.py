@@ -1,0 +1,72 @@
+"""Host logic of the benchmark (no GPU): the one-GPU rule, the roofline
+arithmetic, the hash-gated traffic figure, and the kernel-family table
+against the C header's family enum."""
+import json
+import os
+import re
+import shutil
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120, cwd=ROOT)
+    assert r.returncode == 2
+    line = json.loads(r.stdout.strip().splitlines()[-1])
+    assert "one GPU" in line["error"]
+
+
+def test_family_table_matches_header():
+    text = open(os.path.join(ROOT, "include", "isdf.h")).read()
+    enum = dict((k, int(v)) for k, v in re.findall(r"ISDF_K_([A-Z_]+) = (\d+)", text))
+    nfam = enum.pop("NFAMILY")
+    assert sorted(enum.values()) == list(range(nfam)) == sorted(bench.FAMILIES)
+    assert bench.ALL_FAMILIES == (1 << nfam) - 1
+    for name, fam in enum.items():
+        assert bench.FAMILIES[fam][0] == name.lower(), (name, bench.FAMILIES[fam])
+        assert bench.FAMILIES[fam][1] in ("hbm", "mfma")
+
+
+def test_roofline_arithmetic(monkeypatch):
+    monkeypatch.setattr(bench, "measured_traffic", lambda fam: None)
+    # HBM family: 4 launches, 2 ms in all, 4 GB algorithmic -> 1 GB in 0.5 ms = 2000 GB/s
+    st = {"ms": 2.0, "launches": 4, "bytes": 4e9, "flops": 0.0}
+    r = bench.roofline(6, st, mixed=False)
+    assert r["bound"] == "hbm" and r["unit"] == "GB/s" and r["family"] == "fft"
+    assert r["achieved"] == pytest.approx(2000.0) and r["peak"] == bench.PEAK_HBM_GBS
+    assert r["frac"] == pytest.approx(2000.0 / bench.PEAK_HBM_GBS, abs=1e-4)
+    assert r["avg_launch_us"] == pytest.approx(500.0) and r["alg_bytes_per_launch"] == pytest.approx(1e9)
+    assert r["mfma_issue_frac"] is None
+    # GEMM family in FP64: 2 launches, 1 ms, 4e10 flop -> 40 TFLOP/s against the FP64 peak
+    st = {"ms": 1.0, "launches": 2, "bytes": 0.0, "flops": 4e10}
+    r = bench.roofline(4, st, mixed=False)
+    assert r["unit"] == "TFLOP/s" and r["peak"] == bench.PEAK_FP64_TFS
+    assert r["achieved"] == pytest.approx(40.0)
+    # the exchange family in BF16 splits is priced against the BF16 peak, six products per flop
+    r = bench.roofline(5, st, mixed=True)
+    assert r["peak"] == bench.PEAK_BF16_TFS and "gemm_mixed_kernel" in r["kernel"]
+    assert r["mfma_issue_frac"] == pytest.approx(6 * 40.0 / bench.PEAK_BF16_TFS, abs=1e-4)
+
+
+def test_traffic_figure_needs_the_measured_source(tmp_path, monkeypatch):
+    # the committed summary matches the committed FFT source
+    assert bench.measured_traffic(6) == pytest.approx(float(
+        re.search(r"traffic_bytes_per_launch: (\S+)", open(os.path.join(ROOT, "profiles", "traffic_fft_cfg2.md")).read()
+                  ).group(1)))
+    # a changed source voids it; families without a summary have none
+    (tmp_path / "profiles").mkdir()
+    (tmp_path / "paper_2404_09373_amd" / "csrc").mkdir(parents=True)
+    shutil.copy(os.path.join(ROOT, "profiles", "traffic_fft_cfg2.md"), tmp_path / "profiles")
+    src = open(os.path.join(ROOT, "paper_2404_09373_amd", "csrc", "kernels_fft.hip")).read()
+    (tmp_path / "paper_2404_09373_amd" / "csrc" / "kernels_fft.hip").write_text(src + "\n// changed\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.measured_traffic(6) is None
+    assert bench.measured_traffic(0) is None
