@@ -309,8 +309,10 @@ fft_pass_fixed_kernel(double2* __restrict__ z, int batch, int n1, int n2, int n3
     lstride = N;
   } else {
     const int groups_x = n1 / LPW;
-    const int i10 = (g % groups_x) * LPW;
-    const int rest = g / groups_x;
+    // planar z pass: neighbouring workgroups step along y (2 KB apart at
+    // n1 = 128) instead of along x; the other passes step along x
+    const int i10 = PSTORE ? ((g / n2) % groups_x) * LPW : (g % groups_x) * LPW;
+    const int rest = PSTORE ? (g % n2) + n2 * (g / n2 / groups_x) : g / groups_x;
     if (axis == 1) {
       const int i3 = rest % n3, b = rest / n3;
       base = (int64_t)b * ng + i10 + (int64_t)n1 * n2 * i3;
@@ -344,7 +346,7 @@ fft_pass_fixed_kernel(double2* __restrict__ z, int batch, int n1, int n2, int n3
   fft_stages_ip<N, 0, LPW>(bufA, nl, tw, sign);
   const double2* res = bufA;
   if constexpr (PSTORE) {
-    const int b = (g / (n1 / LPW)) / n2;
+    const int b = (g / n2) / (n1 / LPW);
     const int64_t off = base - (int64_t)b * ng;
     double* v0 = V + (int64_t)(2 * b) * ng + off;
     double* v1 = 2 * b + 1 < ncols ? V + (int64_t)(2 * b + 1) * ng + off : nullptr;
