@@ -309,10 +309,12 @@ fft_pass_fixed_kernel(double2* __restrict__ z, int batch, int n1, int n2, int n3
     lstride = N;
   } else {
     const int groups_x = n1 / LPW;
-    // planar z pass: neighbouring workgroups step along y (2 KB apart at
-    // n1 = 128) instead of along x; the other passes step along x
-    const int i10 = PSTORE ? ((g / n2) % groups_x) * LPW : (g % groups_x) * LPW;
-    const int rest = PSTORE ? (g % n2) + n2 * (g / n2 / groups_x) : g / groups_x;
+    // neighbouring workgroups step along the other strided axis (y for z
+    // lines, z for y lines) rather than along x; rest = (that index) +
+    // (its extent) * (pair)
+    const int nother = axis == 1 ? n3 : n2;
+    const int i10 = ((g / nother) % groups_x) * LPW;
+    const int rest = (g % nother) + nother * (g / nother / groups_x);
     if (axis == 1) {
       const int i3 = rest % n3, b = rest / n3;
       base = (int64_t)b * ng + i10 + (int64_t)n1 * n2 * i3;
@@ -739,8 +741,10 @@ fft_fwd_pruned_kernel(double2* __restrict__ z, const FwdPair* __restrict__ pairs
     }
   } else {
     const int groups_x = n1 / LPW;
-    const int i10 = (g % groups_x) * LPW;
-    const int q = g / groups_x;
+    // z lines (groups_x n2 workgroups): neighbouring workgroups step along y,
+    // as in the planar z pass; y lines step along x
+    const int i10 = (AXIS == 2 ? (g / n2) % groups_x : g % groups_x) * LPW;
+    const int q = AXIS == 2 ? g % n2 : g / groups_x;
     if (AXIS == 1) {  // lines (x, z) for z in the box
       if (q >= P.box[5]) return;
       int zz = P.box[2] + q;
