@@ -1,9 +1,14 @@
 """Periodic Gaussian basis values on level grids.
 
 mu(r) = sum_T N_l(a) Y_l(r - A - T) exp(-a |r - A - T|^2) with
-N_s = (2a/pi)^(3/4), N_p = N_s 2 sqrt(a) and Y_p = (x, y, z); the paper
-evaluates atomic orbitals directly on the real-space grids (Results,
-first paragraph).  Image terms with a |r - A - T|^2 > ln(1/tau) are dropped.
+N_s = (2a/pi)^(3/4), N_p = N_s 2 sqrt(a), N_d = N_s 4a/sqrt(3), Y_p =
+(x, y, z) and Y_d the five real solid harmonics in the order m = -2..2:
+sqrt3 xy, sqrt3 yz, z^2 - (x^2 + y^2)/2, sqrt3 xz, sqrt3/2 (x^2 - y^2)
+(each with integral of Y^2 over the unit sphere 4 pi/5, so one N_d
+normalises all five).  The paper evaluates atomic orbitals directly on the
+real-space grids (Results, first paragraph); its basis sets are
+uncontracted Gaussians with d functions (same paragraph).  Image terms with
+a |r - A - T|^2 > ln(1/tau) are dropped.
 """
 from __future__ import annotations
 
@@ -14,7 +19,24 @@ from .plan import Plan, grid_positions
 
 def shell_norm(l: int, a: float) -> float:
     n = (2.0 * a / np.pi) ** 0.75
-    return n * 2.0 * np.sqrt(a) if l == 1 else n
+    if l == 1:
+        return n * 2.0 * np.sqrt(a)
+    if l == 2:
+        return n * 4.0 * a / np.sqrt(3.0)
+    return n
+
+
+def solid_harmonic(l: int, comp: int, d: np.ndarray) -> np.ndarray:
+    """Angular factor Y_l,comp(d) of displacements d[..., 3]; comp is the
+    Cartesian axis for p and the index of m = -2..2 for d."""
+    x, y, z = d[..., 0], d[..., 1], d[..., 2]
+    if l == 0:
+        return np.ones_like(x)
+    if l == 1:
+        return d[..., comp]
+    r3 = np.sqrt(3.0)
+    return (r3 * x * y, r3 * y * z, z * z - 0.5 * (x * x + y * y), r3 * x * z,
+            0.5 * r3 * (x * x - y * y))[comp]
 
 
 def min_image_dist_many(lattice: np.ndarray, X: np.ndarray, y: np.ndarray) -> np.ndarray:
@@ -63,10 +85,10 @@ def evaluate(plan: Plan, level: int, points: np.ndarray, funcs: np.ndarray,
             m = a * r2 <= lnt
             g = np.where(m, nrm * np.exp(-a * np.where(m, r2, 0.0)), 0.0)
             for (c, comp) in cols:
-                if comp < 0:
+                if l == 0:
                     out[p0:p0 + chunk, c] = g.sum(axis=1)
                 else:
-                    out[p0:p0 + chunk, c] = np.einsum("pi,pi->p", g, diff[:, :, comp])
+                    out[p0:p0 + chunk, c] = np.einsum("pi,pi->p", g, solid_harmonic(l, comp, diff))
     return out
 
 

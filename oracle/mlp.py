@@ -24,6 +24,9 @@ W1[64][16], b1[64], W2[64][64], b2[64], w3[64], b3 (5313 values).
 Loss: mean weighted binary cross-entropy,
   l = -(pw y log p + (1 - y) log(1 - p)), p = sigmoid(z),
 so dl/dz = pw y (p - 1) + (1 - y) p.
+Optimiser: Adam (Kingma and Ba) with bias-corrected moments,
+  m <- b1 m + (1 - b1) g,  v <- b2 v + (1 - b2) g^2,
+  theta <- theta - lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps).
 """
 from __future__ import annotations
 
@@ -168,3 +171,13 @@ def top_candidates(scores: np.ndarray, k: int) -> np.ndarray:
     k = min(k, scores.size)
     order = np.lexsort((np.arange(scores.size), -scores))
     return np.sort(order[:k])
+
+
+def adam_step(theta, g, m, v, t: int, lr: float, b1: float, b2: float, eps: float):
+    """One Adam update at step t (1-based); returns (theta, m, v), all new
+    arrays (FP64)."""
+    m = b1 * np.asarray(m, dtype=np.float64) + (1.0 - b1) * g
+    v = b2 * np.asarray(v, dtype=np.float64) + (1.0 - b2) * g * g
+    mh = m / (1.0 - b1 ** t)
+    vh = v / (1.0 - b2 ** t)
+    return np.asarray(theta, dtype=np.float64) - lr * mh / (np.sqrt(vh) + eps), m, v

@@ -28,6 +28,10 @@ Readings (the paper is silent or ambiguous):
   window centre (minimum image).  Giving a same-level pair of two different
   atoms only to the window of the lower atom index removes the double count
   that the literal L/G/N sets would give.
+* domain_mode = 1 (the alternative kept in the C ABI): one domain per level
+  over the whole level grid, L = the level's functions, N = every function
+  of a coarser level; an ordered pair is then fitted on the level of its
+  sharper function.
 * Points per domain: N_mu,d = floor(r |L_d| + 1/2), capped at the domain's
   point count.  r <= 0 (threshold only, stop by eps_isdf): N_mu,d is the
   smaller of the point count and |L|(|L| + 1)/2 + |L||N|, the number of
@@ -67,7 +71,7 @@ class Plan:
     f_shell: np.ndarray
     f_atom: np.ndarray
     f_l: np.ndarray
-    f_comp: np.ndarray  # -1 for s, 0/1/2 for p_x/p_y/p_z
+    f_comp: np.ndarray  # -1 for s, 0/1/2 for p_x/p_y/p_z, 0..4 for d (m = -2..2)
     f_alpha: np.ndarray
     f_level: np.ndarray
     # per shell
@@ -185,11 +189,13 @@ def build_plan(sysm) -> Plan:
                 shell_level[s] = lev
                 break
 
-    # functions: shell order, p components x, y, z
+    # functions: shell order, p components x, y, z, d components m = -2..2
     f_shell, f_atom, f_l, f_comp, f_alpha, f_level = [], [], [], [], [], []
     for s in range(len(sysm.shell_alpha)):
         l = int(sysm.shell_l[s])
-        comps = [-1] if l == 0 else [0, 1, 2]
+        if l not in (0, 1, 2):
+            raise ValueError("shells with l = 0, 1 or 2 only")
+        comps = [-1] if l == 0 else list(range(2 * l + 1))
         for cpt in comps:
             f_shell.append(s)
             f_atom.append(int(sysm.shell_atom[s]))
@@ -219,6 +225,19 @@ def build_plan(sysm) -> Plan:
         return int(min(np.floor(ratio * nL + 0.5), npts))
 
     domains: List[Domain] = []
+    if int(getattr(sysm, "domain_mode", 0)) == 1:
+        for lev in range(nlev):
+            L = np.nonzero(f_level == lev)[0]
+            if L.size == 0:
+                continue
+            N = np.nonzero(f_level < lev)[0]
+            npts = int(np.prod(grids[lev]))
+            domains.append(Domain(lev, -1, np.arange(npts, dtype=np.int64), L, N,
+                                  n_mu_for(L.size, N.size, npts), np.inf))
+        return Plan(lattice=lattice, xyz=xyz, grids=grids, f_shell=f_shell, f_atom=f_atom,
+                    f_l=np.array(f_l), f_comp=np.array(f_comp), f_alpha=f_alpha, f_level=f_level,
+                    shell_level=shell_level, shell_images=shell_images, domains=domains,
+                    ln_inv_tau=float(ln_inv_tau), volume=float(abs(np.linalg.det(lattice))))
     # universal domain (level 0)
     L0 = np.nonzero(f_level == 0)[0]
     if L0.size:

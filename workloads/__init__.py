@@ -16,5 +16,7 @@ from .diamond import (  # noqa: F401
     random_density,
     level_bounds,
     batched_cells,
+    primitive_norm,
+    LARGE_SHELLS,
 )
 from .selector_init import initial_weights  # noqa: F401

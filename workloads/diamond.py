@@ -9,6 +9,10 @@ are 13 per atom:
     s shells at 0.15 * 3**k (k = 0..4) and sp shells (one s and one p that
     share an exponent) at 0.3 and 1.2 Bohr^-2.
 
+The large 384-atom configuration carries 44 functions per atom with d
+shells (LARGE_SHELLS): s, p and d primitives at 0.1 * 2.5**k, the d shells
+as the five real solid harmonics.
+
 Grid ladders follow the two-grid scheme of the paper (a coarse universal
 grid plus atom-centred dense windows) extended to L levels.  The exponent
 bound of level l scales with the inverse square grid spacing (the
@@ -58,6 +62,19 @@ CARBON_SHELLS: Tuple[Tuple[int, float], ...] = (
 )
 
 
+# the large configuration's per-atom set: exponents 0.1 * 2.5**k with s at
+# k = 0..7, p at k = 0..6 and d (real solid harmonics) at k = 0..2, i.e.
+# 8 s + 7 p + 3 d shells = 44 functions, ascending exponent, s, p, d
+LARGE_SHELLS: Tuple[Tuple[int, float], ...] = tuple(
+    sorted(
+        [(0, 0.1 * 2.5 ** k) for k in range(8)]
+        + [(1, 0.1 * 2.5 ** k) for k in range(7)]
+        + [(2, 0.1 * 2.5 ** k) for k in range(3)],
+        key=lambda t: (t[1], t[0]),
+    )
+)
+
+
 @dataclasses.dataclass
 class System:
     """A periodic cell with uncontracted shells, grid ladder and thresholds.
@@ -65,7 +82,8 @@ class System:
     lattice     (3,3) rows a1, a2, a3 in Bohr
     xyz         (n_atoms, 3) Cartesian atom positions in Bohr
     shell_atom  (n_shells,) int atom index of each shell (atom-major order)
-    shell_l     (n_shells,) int angular momentum (0 or 1)
+    shell_l     (n_shells,) int angular momentum (0, 1 or 2; d as real solid
+                harmonics, 5 functions)
     shell_alpha (n_shells,) float exponent in Bohr^-2
     grids       (n_levels, 3) int grid points per axis, coarse -> fine
     alpha_bound (n_levels-1,) shells with alpha < alpha_bound[l] live on
@@ -75,6 +93,8 @@ class System:
     n_mu_ratio  interpolation points per owned function (<= 0: threshold only)
     eps_isdf    relative stop of the pivoted Cholesky
     tie_tol     relative tie window of the pivot argmax
+    domain_mode 0: universal grid + atom windows, 1: one full-cell domain per
+                level
     n_occ       occupied orbitals
     C_occ       (N, n_occ) S-orthonormal occupied orbitals
     D           (N, N) density matrix C_occ C_occ^T
@@ -93,6 +113,7 @@ class System:
     n_mu_ratio: float = 6.0
     eps_isdf: float = 1e-14
     tie_tol: float = 1e-8
+    domain_mode: int = 0
     n_occ: int = 0
     C_occ: Optional[np.ndarray] = None
     D: Optional[np.ndarray] = None
@@ -171,55 +192,162 @@ def diamond_geometry(
     return lattice, xyz
 
 
+# Cartesian monomials (x^i y^j z^k) of each angular momentum, and the real
+# solid harmonics (Racah normalisation, sum_m S_lm^2 = r^(2l)) as rows of
+# coefficients over those monomials, in the order m = -l .. l:
+#   d: sqrt3 xy, sqrt3 yz, z^2 - (x^2 + y^2)/2, sqrt3 xz, sqrt3/2 (x^2 - y^2)
+_CART = {
+    0: ((0, 0, 0),),
+    1: ((1, 0, 0), (0, 1, 0), (0, 0, 1)),
+    2: ((2, 0, 0), (0, 2, 0), (0, 0, 2), (1, 1, 0), (1, 0, 1), (0, 1, 1)),
+}
+_R3 = np.sqrt(3.0)
+_SPH = {
+    0: np.eye(1),
+    1: np.eye(3),
+    2: np.array(
+        [
+            [0.0, 0.0, 0.0, _R3, 0.0, 0.0],
+            [0.0, 0.0, 0.0, 0.0, 0.0, _R3],
+            [-0.5, -0.5, 1.0, 0.0, 0.0, 0.0],
+            [0.0, 0.0, 0.0, 0.0, _R3, 0.0],
+            [0.5 * _R3, -0.5 * _R3, 0.0, 0.0, 0.0, 0.0],
+        ]
+    ),
+}
+
+
+def primitive_norm(l: int, a: float) -> float:
+    """N with int (N S_lm(r) exp(-a r^2))^2 d^3r = 1 for every m:
+    N_s = (2a/pi)^(3/4), N_p = N_s 2 sqrt(a), N_d = N_s 4a/sqrt(3)."""
+    n = (2.0 * a / np.pi) ** 0.75
+    return n * (1.0, 2.0 * np.sqrt(a), 4.0 * a / _R3)[int(l)]
+
+
+def _os_1d(la: int, lb: int, PA: np.ndarray, PB: np.ndarray, p: float):
+    """One-dimensional Obara-Saika overlap ratios s[i][j] = S_ij / S_00 for
+    i <= la, j <= lb (vectorised over the last axis):
+    s[i+1][j] = PA s[i][j] + (i s[i-1][j] + j s[i][j-1]) / 2p, and the same
+    with PB for j + 1."""
+    h = 0.5 / p
+    s = [[None] * (lb + 1) for _ in range(la + 1)]
+    s[0][0] = np.ones_like(PA)
+    for i in range(la + 1):
+        for j in range(lb + 1):
+            if i == 0 and j == 0:
+                continue
+            if i > 0:
+                v = PA * s[i - 1][j]
+                if i > 1:
+                    v = v + (i - 1) * h * s[i - 2][j]
+                if j > 0:
+                    v = v + j * h * s[i - 1][j - 1]
+            else:
+                v = PB * s[i][j - 1]
+                if j > 1:
+                    v = v + (j - 1) * h * s[i][j - 2]
+            s[i][j] = v
+    return s
+
+
 def periodic_overlap(lattice, xyz, shell_atom, shell_l, shell_alpha) -> np.ndarray:
     """Closed-form overlap S_uv = sum_T <u_0 | v_0(. - T)> of normalised
-    periodic s/p Gaussians (Gaussian product theorem).
+    periodic Gaussians with l <= 2 (Gaussian product theorem and the
+    Obara-Saika recursion for the Cartesian factors, then the Cartesian ->
+    real-solid-harmonic map of each shell).
 
-    Normalisation: N_s = (2a/pi)^(3/4), N_p = N_s * 2 sqrt(a), p = (x, y, z).
-    Used to build an S-orthonormal density and as an analytic reference for
-    grid quadratures.
+    Functions: N_l(a) S_lm(r - A) exp(-a |r - A|^2) with primitive_norm N_l;
+    p = (x, y, z), d in the order m = -2..2 of _SPH.  Used to build an
+    S-orthonormal density and as an analytic reference for grid quadratures.
+    Shells are grouped by (l, exponent) and every group pair is evaluated
+    for all atom pairs and translations at once.
     """
     lattice = np.asarray(lattice, dtype=np.float64)
-    nsh = len(shell_alpha)
-    offs = np.concatenate([[0], np.cumsum(2 * np.asarray(shell_l) + 1)])
+    xyz = np.asarray(xyz, dtype=np.float64)
+    shell_atom = np.asarray(shell_atom, dtype=np.int64)
+    shell_l = np.asarray(shell_l, dtype=np.int64)
+    shell_alpha = np.asarray(shell_alpha, dtype=np.float64)
+    if shell_l.max() > 2:
+        raise ValueError("shells up to l = 2")
+    nsh = shell_alpha.size
+    nat = xyz.shape[0]
+    offs = np.concatenate([[0], np.cumsum(2 * shell_l + 1)]).astype(np.int64)
     N = int(offs[-1])
     S = np.zeros((N, N))
+    cut = 80.0  # mu |A - B - T|^2 beyond this contributes < e^-80
     amin = float(np.min(shell_alpha))
-    # translations within the decay range of the most diffuse product
-    rmax = np.sqrt(60.0 / (amin / 2.0)) + 2.0 * np.max(np.linalg.norm(lattice, axis=1))
+    rmax = np.sqrt(cut / (amin / 2.0))
+    # ordered atom pairs and translations with |A - B - T| <= rmax: reduce
+    # A - B to the cell around the origin, then scan the translations that
+    # can bring it within rmax
     inv = np.linalg.inv(lattice)
-    nmax = [int(np.ceil(rmax * np.linalg.norm(inv[:, i]))) + 1 for i in range(3)]
+    ia, ib = np.meshgrid(np.arange(nat), np.arange(nat), indexing="ij")
+    ia, ib = ia.ravel(), ib.ravel()
+    f = (xyz[ia] - xyz[ib]) @ inv
+    dred = (f - np.round(f)) @ lattice
+    reach = rmax + float(np.max(np.linalg.norm(dred, axis=1)))
+    nmax = [int(np.ceil(reach * np.linalg.norm(inv[:, i]))) + 1 for i in range(3)]
     rng = [np.arange(-n, n + 1) for n in nmax]
-    T = np.array(np.meshgrid(*rng, indexing="ij")).reshape(3, -1).T @ lattice
-    for i in range(nsh):
-        a = shell_alpha[i]
-        A = xyz[shell_atom[i]]
-        Na = (2 * a / np.pi) ** 0.75 * (2 * np.sqrt(a) if shell_l[i] == 1 else 1.0)
-        for j in range(nsh):
-            b = shell_alpha[j]
-            B = xyz[shell_atom[j]] + T  # (nT, 3)
-            Nb = (2 * b / np.pi) ** 0.75 * (2 * np.sqrt(b) if shell_l[j] == 1 else 1.0)
+    Tall = np.array(np.meshgrid(*rng, indexing="ij")).reshape(3, -1).T @ lattice
+    Tall = Tall[np.linalg.norm(Tall, axis=1) <= reach]
+    pa_l, pb_l, d_l = [], [], []
+    for T in Tall:
+        dAB = dred - T  # A - (B + T') for some lattice vector T'
+        r2 = np.einsum("ij,ij->i", dAB, dAB)
+        k = r2 <= rmax * rmax
+        if k.any():
+            pa_l.append(ia[k])
+            pb_l.append(ib[k])
+            d_l.append(dAB[k])
+    pa = np.concatenate(pa_l)
+    pb = np.concatenate(pb_l)
+    dAB = np.concatenate(d_l)
+    r2 = np.einsum("ij,ij->i", dAB, dAB)
+    order = np.argsort(r2, kind="stable")  # nearest first: a cutoff is a prefix
+    pa, pb, dAB, r2 = pa[order], pb[order], dAB[order], r2[order]
+    ap = pa * nat + pb
+    # shell groups: (l, alpha) -> shell index per atom (-1 if absent)
+    keys = sorted({(int(l), float(a)) for l, a in zip(shell_l, shell_alpha)})
+    of_atom = {}
+    for key in keys:
+        m = np.full(nat, -1, dtype=np.int64)
+        for s in range(nsh):
+            if (int(shell_l[s]), float(shell_alpha[s])) == key:
+                if m[shell_atom[s]] >= 0:
+                    raise ValueError("two shells of one atom share (l, alpha)")
+                m[shell_atom[s]] = s
+        of_atom[key] = m
+    for (la, a) in keys:
+        ra = of_atom[(la, a)]
+        for (lb, b) in keys:
+            rb = of_atom[(lb, b)]
             p = a + b
             mu = a * b / p
-            AB = A - B
-            r2 = np.sum(AB * AB, axis=1)
-            keep = mu * r2 < 80.0
-            Bk = B[keep]
-            E0 = np.exp(-mu * r2[keep]) * (np.pi / p) ** 1.5
-            P = (a * A + b * Bk) / p
-            PA = P - A
-            PB = P - Bk
-            li, lj = shell_l[i], shell_l[j]
-            oi, oj = offs[i], offs[j]
-            if li == 0 and lj == 0:
-                S[oi, oj] = Na * Nb * np.sum(E0)
-            elif li == 1 and lj == 0:
-                S[oi : oi + 3, oj] = Na * Nb * (PA * E0[:, None]).sum(0)
-            elif li == 0 and lj == 1:
-                S[oi, oj : oj + 3] = Na * Nb * (PB * E0[:, None]).sum(0)
-            else:
-                blk = np.einsum("ti,tj,t->ij", PA, PB, E0) + np.eye(3) * np.sum(E0) / (2 * p)
-                S[oi : oi + 3, oj : oj + 3] = Na * Nb * blk
+            n = int(np.searchsorted(r2, cut / mu, side="right"))
+            if n == 0:
+                continue
+            d = dAB[:n]
+            E0 = np.exp(-mu * r2[:n]) * (np.pi / p) ** 1.5
+            PA = -(b / p) * d  # P - A with P = (a A + b (B + T)) / p
+            PB = (a / p) * d   # P - (B + T)
+            s1 = [_os_1d(la, lb, PA[:, x], PB[:, x], p) for x in range(3)]
+            ca, cb = _CART[la], _CART[lb]
+            cart = np.empty((len(ca), len(cb), n))
+            for u, (i1, i2, i3) in enumerate(ca):
+                for v, (j1, j2, j3) in enumerate(cb):
+                    cart[u, v] = E0 * s1[0][i1][j1] * s1[1][i2][j2] * s1[2][i3][j3]
+            sph = cart * (primitive_norm(la, a) * primitive_norm(lb, b))
+            if la == 2:
+                sph = np.tensordot(_SPH[2], sph, axes=(1, 0))
+            if lb == 2:
+                sph = np.tensordot(_SPH[2], sph, axes=(1, 1)).transpose(1, 0, 2)
+            # sum over translations per atom pair, then place the shell pairs
+            A_, B_ = np.nonzero((ra[:, None] >= 0) & (rb[None, :] >= 0))
+            oi, oj = offs[ra[A_]], offs[rb[B_]]
+            for m_ in range(sph.shape[0]):
+                for n_ in range(sph.shape[1]):
+                    acc = np.bincount(ap[:n], weights=sph[m_, n_], minlength=nat * nat)
+                    S[oi + m_, oj + n_] = acc.reshape(nat, nat)[A_, B_]
     return 0.5 * (S + S.T)
 
 
@@ -246,9 +374,10 @@ def diamond_system(
     name="",
     with_density=True,
     tie_tol=1e-8,
+    shells=CARBON_SHELLS,
 ) -> System:
     lattice, xyz = diamond_geometry(reps, displacement_angstrom, strain, geom_seed)
-    sa, sl, sal = _shells_for_atoms(xyz.shape[0])
+    sa, sl, sal = _shells_for_atoms(xyz.shape[0], shells)
     grids = np.array(grids, dtype=np.int64)
     if alpha_bound is None:
         alpha_bound = level_bounds(lattice, grids)
@@ -280,6 +409,11 @@ def config(k: int, with_density: bool = True) -> System:
        grids 32^3 / 64^3 / 128^3, 8 points per owned function, 128 occupied.
     4: 3x3x3 supercell (216 atoms), grids 40^3 / 80^3 / 160^3, ratio 8,
        432 occupied (the learned-selector inference workload).
+    5: 4x4x3 supercell (384 atoms) with +-0.05 Angstrom displacements, the
+       44-function set LARGE_SHELLS (N = 16896), four isotropic levels
+       24x24x18 / 48x48x36 / 96x96x72 / 192x192x144 (exponent bounds
+       0.125 / 0.5 / 2 from level_bounds), 5 points per owned function,
+       768 occupied.
     """
     if k == 1:
         return diamond_system(
@@ -295,6 +429,11 @@ def config(k: int, with_density: bool = True) -> System:
         return diamond_system(
             (3, 3, 3), ((40, 40, 40), (80, 80, 80), (160, 160, 160)), 8.0, 432,
             0.05, 0.0, 400, 401, name="cfg4", with_density=with_density,
+        )
+    if k == 5:
+        return diamond_system(
+            (4, 4, 3), ((24, 24, 18), (48, 48, 36), (96, 96, 72), (192, 192, 144)), 5.0, 768,
+            0.05, 0.0, 500, 501, name="cfg5", with_density=with_density, shells=LARGE_SHELLS,
         )
     raise ValueError(f"unknown config {k}")
 
@@ -337,12 +476,17 @@ def tiny_system(
 
     one_atom: a single carbon-like atom with shells s0.3, p0.3 (sp), s1.2, s4.05
     two_atom: two such atoms in a cubic cell, one of them off-centre.
+    d_atom:   one atom with d shells on both levels: s0.3, p0.3, d0.5,
+              s1.2, d2.5
+    d_two:    two d_atom atoms (cross-atom d-d pairs on the fine windows)
     """
     shells = ((0, 0.3), (1, 0.3), (0, 1.2), (0, 4.05))
     lattice = np.eye(3) * cell_bohr
-    if kind == "one_atom":
+    if kind in ("d_atom", "d_two"):
+        shells = ((0, 0.3), (1, 0.3), (2, 0.5), (0, 1.2), (2, 2.5))
+    if kind in ("one_atom", "d_atom"):
         xyz = np.array([[0.37, 0.21, 0.11]]) * cell_bohr
-    elif kind == "two_atom":
+    elif kind in ("two_atom", "d_two"):
         xyz = np.array([[0.12, 0.2, 0.31], [0.61, 0.55, 0.47]]) * cell_bohr
     else:
         raise ValueError(kind)
