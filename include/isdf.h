@@ -81,7 +81,10 @@ typedef struct {
   const double* xyz;          /* [n_atoms][3] Cartesian positions (Bohr)                 */
   int32_t n_shells;
   const int32_t* shell_atom;  /* [n_shells] atom of each shell, atom-major order         */
-  const int32_t* shell_l;     /* [n_shells] 0 (s) or 1 (p); uncontracted, normalised     */
+  const int32_t* shell_l;     /* [n_shells] 0 (s), 1 (p: x, y, z) or 2 (d: the five real
+                                 solid harmonics sqrt3 xy, sqrt3 yz, z^2 - (x^2+y^2)/2,
+                                 sqrt3 xz, sqrt3/2 (x^2 - y^2), order m = -2..2);
+                                 uncontracted primitives with unit single-centre norm  */
   const double* shell_alpha;  /* [n_shells] exponent (Bohr^-2)                           */
   int32_t n_levels;           /* 1..8                                                     */
   const int32_t* grid;        /* [n_levels][3] points per axis, coarse -> fine, each axis
@@ -95,6 +98,11 @@ typedef struct {
                                  the domain's pair Gram                                   */
   double eps_isdf;            /* relative stop of the pivoted Cholesky (e.g. 1e-14)      */
   double tie_tol;             /* relative tie window of the pivot argmax (e.g. 1e-8)     */
+  int32_t domain_mode;        /* 0: universal level-0 domain + one spherical window per
+                                 atom on each finer level (section "Computational
+                                 details"); 1: one domain per level over the whole level
+                                 grid, L = the level's functions, N = all coarser ones  */
+  int32_t pad_sys;
 } isdf_system;
 
 typedef struct {
@@ -126,9 +134,10 @@ typedef struct {
 
 /* Build the multigrid plan (host only, no device work).
  * Reads sys and opts; on success *out owns copies of everything it needs.
- * Errors: ISDF_E_ARG for null pointers, non-positive grids, NaN exponents;
- * ISDF_E_UNSUPPORTED for grids that are not 2,3,5-smooth, axes above 256,
- * levels that are not strictly finer, or l > 1. */
+ * Errors: ISDF_E_ARG for null pointers, non-positive grids, NaN exponents,
+ * domain_mode outside {0, 1}; ISDF_E_UNSUPPORTED for grids that are not
+ * 2,3,5-smooth, axes above 256, levels that are not strictly finer, or
+ * l > 2. */
 isdf_status isdf_plan(const isdf_system* sys, const isdf_options* opts, isdf_plan_t* out);
 
 /* Grid ladder from the Fourier threshold eps_K (Eq. Ggrid; the threshold

@@ -74,6 +74,8 @@ class _System(C.Structure):
         ("n_mu_ratio", C.c_double),
         ("eps_isdf", C.c_double),
         ("tie_tol", C.c_double),
+        ("domain_mode", C.c_int32),
+        ("pad_sys", C.c_int32),
     ]
 
 
@@ -206,6 +208,7 @@ class Plan:
         s.n_mu_ratio = float(sysm.n_mu_ratio)
         s.eps_isdf = float(sysm.eps_isdf)
         s.tie_tol = float(sysm.tie_tol)
+        s.domain_mode = int(getattr(sysm, "domain_mode", 0))
         o = _Options()
         o.precision = precision
         o.selector = selector

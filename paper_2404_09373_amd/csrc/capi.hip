@@ -606,8 +606,11 @@ isdf_status upload_plan(isdf_plan_s* pl) {
   std::vector<ShellDev> sh(hp.n_shells);
   for (int s = 0; s < hp.n_shells; ++s) {
     double a = hp.shell_alpha[s];
+    // unit single-centre norm: N_s = (2a/pi)^(3/4), N_p = N_s 2 sqrt(a),
+    // N_d = N_s 4a/sqrt(3) (one factor for all five real solid harmonics)
     double nrm = std::pow(2.0 * a / M_PI, 0.75);
     if (hp.shell_l[s] == 1) nrm *= 2.0 * std::sqrt(a);
+    if (hp.shell_l[s] == 2) nrm *= 4.0 * a / std::sqrt(3.0);
     sh[s] = ShellDev{a, nrm, hp.shell_l[s], hp.img_off[s], hp.img_cnt[s], 0};
   }
   std::vector<ColShell> cols;
@@ -633,7 +636,7 @@ isdf_status upload_plan(isdf_plan_s* pl) {
     for (int c = 0; c < dd.nG;) {
       int s = hp.f_shell[D.funcs[c]];
       cols.push_back(ColShell{s, c});
-      c += hp.shell_l[s] == 1 ? 3 : 1;
+      c += 2 * hp.shell_l[s] + 1;
     }
     dd.colshell_cnt = (int)cols.size() - dd.colshell_off;
     doms.push_back(dd);
@@ -2859,7 +2862,8 @@ isdf_status isdf_plan(const isdf_system* sys, const isdf_options* opts, isdf_pla
   }
   if (pl->opts.universal_all_points) {
     HostPlan& hp = pl->hp;
-    if (hp.domains.size() < 2 || hp.domains[0].atom >= 0 || hp.domains[0].level != 0) {
+    if (hp.domain_mode != 0 || hp.domains.size() < 2 || hp.domains[0].atom >= 0 ||
+        hp.domains[0].level != 0) {
       set_error("isdf_plan: universal_all_points needs a universal domain and atom windows "
                 "(a one-level plan: isdf_exchange_universal)");
       return ISDF_E_UNSUPPORTED;

@@ -65,6 +65,7 @@ struct HostPlan {
   std::vector<double> alpha_bound;
   double eps_r, n_mu_ratio, eps_isdf, tie_tol;
   std::vector<HostDomain> domains;
+  int domain_mode = 0;
   int64_t n_mu_total = 0;
 };
 

@@ -3,7 +3,8 @@
 //
 // Basis (Results section: atomic orbitals evaluated directly on the grids):
 //   mu(r) = sum_T N Y_l(r - A - T) exp(-alpha |r - A - T|^2), terms with
-//   alpha |r - A - T|^2 > ln(1/tau) dropped.  One thread per grid point,
+//   alpha |r - A - T|^2 > ln(1/tau) dropped; Y_l is 1 (s), x, y, z (p) or
+//   the five real solid harmonics (d, m = -2..2).  One thread per grid point,
 //   columns written point-fastest (coalesced), Gram diagonal
 //   d(R) = a_L (a_L + 2 a_N), a_X = sum_{mu in X} mu(R)^2, fused in.
 //
@@ -52,7 +53,9 @@ basis_eval_kernel(LatticeArg lat, const ShellDev* __restrict__ shells,
   for (int e = 0; e < d.colshell_cnt; ++e) {
     const ColShell cs = colshells[d.colshell_off + e];
     const ShellDev sh = shells[cs.shell];
-    double v0 = 0.0, vx = 0.0, vy = 0.0, vz = 0.0;
+    // s: v[0]; p: v[0..2] = x, y, z; d: v[0..4] = the real solid harmonics
+    // sqrt3 xy, sqrt3 yz, z^2 - (x^2 + y^2)/2, sqrt3 xz, sqrt3/2 (x^2 - y^2)
+    double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     const double* c = img + 3 * (int64_t)sh.img_off;
     for (int m = 0; m < sh.img_cnt; ++m) {
       const double dx = x - c[3 * m], dy = y - c[3 * m + 1], dz = z - c[3 * m + 2];
@@ -60,35 +63,38 @@ basis_eval_kernel(LatticeArg lat, const ShellDev* __restrict__ shells,
       if (sh.alpha * r2 <= lat.ln_inv_tau) {
         const double g = sh.norm * exp(-sh.alpha * r2);
         if (sh.l == 0) {
-          v0 += g;
+          v[0] += g;
+        } else if (sh.l == 1) {
+          v[0] += g * dx;
+          v[1] += g * dy;
+          v[2] += g * dz;
         } else {
-          vx += g * dx;
-          vy += g * dy;
-          vz += g * dz;
+          constexpr double R3 = 1.7320508075688772;
+          v[0] += g * (R3 * dx * dy);
+          v[1] += g * (R3 * dy * dz);
+          v[2] += g * (dz * dz - 0.5 * (dx * dx + dy * dy));
+          v[3] += g * (R3 * dx * dz);
+          v[4] += g * (0.5 * R3 * (dx * dx - dy * dy));
         }
       }
     }
-    if (sh.l == 0) {
-      out[cs.col * P] = v0;
-      if (cs.col < d.nL) {
-        aL += v0 * v0;
-        mL = fmax(mL, v0 * v0);
-        sL += v0;
-      } else {
-        aN += v0 * v0;
+    const int nc = 2 * sh.l + 1;
+    double s2 = 0.0, mx = 0.0, sm = 0.0;
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+      if (q < nc) {
+        out[(cs.col + q) * P] = v[q];
+        s2 += v[q] * v[q];
+        mx = fmax(mx, v[q] * v[q]);
+        sm += v[q];
       }
+    }
+    if (cs.col < d.nL) {
+      aL += s2;
+      mL = fmax(mL, mx);
+      sL += sm;
     } else {
-      out[cs.col * P] = vx;
-      out[(cs.col + 1) * P] = vy;
-      out[(cs.col + 2) * P] = vz;
-      const double s = vx * vx + vy * vy + vz * vz;
-      if (cs.col < d.nL) {
-        aL += s;
-        mL = fmax(mL, fmax(vx * vx, fmax(vy * vy, vz * vz)));
-        sL += vx + vy + vz;
-      } else {
-        aN += s;
-      }
+      aN += s2;
     }
   }
   diag[d.diag_off + i] = aL * (aL + 2.0 * aN);

@@ -16,6 +16,8 @@
 //     same-level functions of atoms with a larger index, screened by
 //     min-image distance <= r_img(alpha) + r_max; a same-level pair of two
 //     atoms is thus fitted once, on the lower atom's window;
+//   * domain_mode 1 (the alternative of the C ABI): one full-grid domain per
+//     level, L = the level's functions, N = all coarser functions;
 //   * n_mu,d = floor(ratio |L_d| + 1/2) capped at the point count; with
 //     ratio <= 0 (stop by eps_isdf only) the cap is the smaller of the point
 //     count and the domain's distinct pair products |L|(|L|+1)/2 + |L||N|,
@@ -228,8 +230,8 @@ isdf_status build_host_plan(const isdf_system* sys, HostPlan& hp) {
       set_error("isdf_plan: exponents must be positive and finite");
       return ISDF_E_ARG;
     }
-    if (hp.shell_l[s] < 0 || hp.shell_l[s] > 1) {
-      set_error("isdf_plan: only s and p shells are supported");
+    if (hp.shell_l[s] < 0 || hp.shell_l[s] > 2) {
+      set_error("isdf_plan: only s, p and d shells are supported");
       return ISDF_E_UNSUPPORTED;
     }
     for (int l = 0; l < hp.n_levels - 1; ++l)
@@ -242,13 +244,15 @@ isdf_status build_host_plan(const isdf_system* sys, HostPlan& hp) {
       return ISDF_E_ARG;
     }
   }
+  // functions: 1 (s), 3 (p: x, y, z) or 5 (d: real solid harmonics,
+  // m = -2..2) per shell
   hp.f_shell.clear();
   for (int s = 0; s < hp.n_shells; ++s) {
-    int nc = hp.shell_l[s] == 1 ? 3 : 1;
+    const int nc = 2 * hp.shell_l[s] + 1;
     for (int c = 0; c < nc; ++c) {
       hp.f_shell.push_back(s);
       hp.f_atom.push_back(hp.shell_atom[s]);
-      hp.f_comp.push_back(hp.shell_l[s] == 1 ? c : -1);
+      hp.f_comp.push_back(hp.shell_l[s] > 0 ? c : -1);
       hp.f_level.push_back(hp.shell_level[s]);
     }
   }
@@ -295,6 +299,34 @@ isdf_status build_host_plan(const isdf_system* sys, HostPlan& hp) {
   };
 
   hp.domains.clear();
+  hp.domain_mode = sys->domain_mode;
+  if (hp.domain_mode != 0 && hp.domain_mode != 1) {
+    set_error("isdf_plan: domain_mode must be 0 or 1");
+    return ISDF_E_ARG;
+  }
+  if (hp.domain_mode == 1) {
+    // one domain per level over the whole level grid: L = the level's
+    // functions, N = every coarser function (a pair is fitted on the level
+    // of its sharper function)
+    for (int lev = 0; lev < hp.n_levels; ++lev) {
+      HostDomain d;
+      d.level = lev;
+      d.atom = -1;
+      d.r_max = INFINITY;
+      for (int f = 0; f < hp.n_basis; ++f)
+        if (hp.f_level[f] == lev) d.funcs.push_back(f);
+      d.nL = (int)d.funcs.size();
+      if (d.nL == 0) continue;
+      for (int f = 0; f < hp.n_basis; ++f)
+        if (hp.f_level[f] < lev) d.funcs.push_back(f);
+      d.nN = (int)d.funcs.size() - d.nL;
+      const int64_t np = (int64_t)hp.grid[lev][0] * hp.grid[lev][1] * hp.grid[lev][2];
+      d.points.resize(np);
+      for (int64_t i = 0; i < np; ++i) d.points[i] = (int32_t)i;
+      d.n_mu = n_mu_for(d.nL, d.nN, (int)np);
+      hp.domains.push_back(std::move(d));
+    }
+  } else {
   {
     HostDomain d;
     d.level = 0;
@@ -347,6 +379,7 @@ isdf_status build_host_plan(const isdf_system* sys, HostPlan& hp) {
       d.n_mu = n_mu_for(d.nL, d.nN, (int)d.points.size());
       hp.domains.push_back(std::move(d));
     }
+  }
   }
   hp.n_mu_total = 0;
   for (auto& d : hp.domains) hp.n_mu_total += d.n_mu;

@@ -41,7 +41,7 @@ def _compare_plan(sysm):
     p.close()
 
 
-@pytest.mark.parametrize("which", ["cfg1", "tiny1", "tiny2", "strained"])
+@pytest.mark.parametrize("which", ["cfg1", "tiny1", "tiny2", "strained", "d_two", "full_cell"])
 def test_plan_matches_oracle(which):
     if which == "cfg1":
         s = config(1, with_density=False)
@@ -49,6 +49,11 @@ def test_plan_matches_oracle(which):
         s = tiny_system("one_atom")
     elif which == "tiny2":
         s = tiny_system("two_atom")
+    elif which == "d_two":
+        s = tiny_system("d_two")
+    elif which == "full_cell":
+        s = tiny_system("d_two", grids=((10, 10, 10), (20, 20, 20)))
+        s.domain_mode = 1
     else:
         s = batched_cells(4)[3]  # 2x2x2 strained cell, uneven grids
         s.grids = np.array([[24, 48, 40], [48, 96, 80]])
@@ -135,8 +140,11 @@ def test_plan_errors():
     assert _status(s) == -1
     s = tiny_system("one_atom")
     s.shell_l = s.shell_l.copy()
-    s.shell_l[0] = 2
+    s.shell_l[0] = 3
     assert _status(s) == -7
+    s = tiny_system("one_atom")
+    s.domain_mode = 2
+    assert _status(s) == -1
     assert _status(tiny_system("one_atom"), lattice=np.zeros((3, 3))) == -1
     assert _status(tiny_system("one_atom"), image_tol=0.0) == -1
 

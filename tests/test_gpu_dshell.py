@@ -1,0 +1,74 @@
+"""d shells and the full-cell domain mode on the GPU against the FP64
+oracle, stage by stage (same tolerances as test_gpu_parity: basis values and
+X rows 1e-12 relative, pivots identical, Theta 1e-11, F 1e-7, W 1e-9,
+max|dK| <= 1e-7 Ha and |dE_x| <= 1e-6 Ha/atom)."""
+import numpy as np
+import pytest
+
+from oracle import pipeline
+from paper_2404_09373_amd import binding
+from test_gpu_parity import _check_all
+from workloads import tiny_system
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+
+    assert t.cuda.is_available(), "GPU tests need a GPU"
+    return t
+
+
+@pytest.mark.parametrize("kind", ["d_atom", "d_two"])
+def test_d_shell_cells_stage_parity(torch, kind):
+    """Cells whose shells include d functions on the universal grid (d 0.5)
+    and on the atom windows (d 2.5)."""
+    s = tiny_system(kind, n_occ=3)
+    ref = pipeline.run(s)
+    plan = binding.Plan(s)
+    print(f"[{kind}] N {plan.n_basis} N_mu {plan.n_mu} domains {plan.n_domains}", flush=True)
+    fit = plan.fit()
+    K, ex = _check_all(s, ref, plan, fit, torch, kind)
+    assert np.max(np.abs(K - K.T)) <= 1e-12 * np.max(np.abs(K)) and ex < 0
+
+
+def test_d_shell_strained_cell_stage_parity(torch):
+    s = tiny_system("d_two", n_occ=3)
+    s.lattice = s.lattice @ (np.eye(3) + np.array([[0.03, -0.01, 0.0], [-0.01, 0.0, 0.02],
+                                                   [0.0, 0.02, -0.02]]))
+    from workloads import periodic_overlap, random_density
+    S = periodic_overlap(s.lattice, s.xyz, s.shell_atom, s.shell_l, s.shell_alpha)
+    s.C_occ, s.D = random_density(S, 3, 11)
+    ref = pipeline.run(s)
+    plan = binding.Plan(s)
+    fit = plan.fit()
+    _check_all(s, ref, plan, fit, torch, "d_two_strained")
+
+
+def test_full_cell_domain_mode_stage_parity(torch):
+    """domain_mode = 1: one full-grid domain per level (the finer level's
+    domain carries every coarser function as N)."""
+    s = tiny_system("d_two", grids=((10, 10, 10), (20, 20, 20)), n_occ=3)
+    s.domain_mode = 1
+    ref = pipeline.run(s)
+    plan = binding.Plan(s)
+    assert plan.n_domains == 2
+    fit = plan.fit()
+    _check_all(s, ref, plan, fit, torch, "full_cell")
+
+
+def test_d_shell_mixed_precision_within_gate(torch):
+    """BF16 x6 exchange and W rows on a d-shell cell against the oracle:
+    |dE_x| <= 1e-6 Ha/atom (the accuracy gate of the mixed path)."""
+    s = tiny_system("d_two", n_occ=3)
+    ref = pipeline.run(s)
+    plan = binding.Plan(s, precision=binding.MIXED_X6)
+    fit = plan.fit()
+    D = torch.tensor(s.D, dtype=torch.float64, device="cuda")
+    K, ex = fit.exchange(D)
+    dK = float(np.max(np.abs(K.cpu().numpy() - ref.K)))
+    dE = abs(ex - ref.E_x) / s.n_atoms
+    print(f"[d_two x6] max|dK| {dK:.2e} |dE|/atom {dE:.2e}")
+    assert dE <= 1e-6 and dK <= 1e-6
