@@ -303,6 +303,26 @@ isdf_status isdf_exchange_occ(isdf_plan_t plan, isdf_fit_t fit, const double* C_
 isdf_status isdf_exchange_occ_ri(isdf_plan_t plan, isdf_fit_t fit, const double* C_dev,
                                  int32_t n_occ, double* KC_dev, double* e_x);
 
+/* The occ-RI exchange of isdf_exchange_occ_ri in FP64 without any device
+ * allocation, for callers that cannot allocate: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, result (K C, e_x = tr(C' K C)) and kernels as the FP64 form of
+ * isdf_exchange_occ_ri, whatever the plan's precision; launched kernel by
+ * kernel (no graph).  Its workspace (E_G, E_L, E_N, Z1, Z2: N_mu x n_occ;
+ * Q_GG, Q_GL, Q_LL: N_mu x N_mu; FP64) lives in a fixed device array of
+ * ISDF_NOALLOC_SCRATCH_MB MB built into the library, one per GPU, held until
+ * the process ends; every call on a GPU shares it, so calls that overlap on
+ * one GPU race (serialise them, e.g. one stream per GPU).  The fit itself
+ * is made by isdf_fit as usual.  Synchronises the stream.
+ * Errors: ISDF_E_ARG (null pointers, n_occ outside 1..N, a workspace
+ * 8 (3 N_mu^2 + 5 N_mu n_occ) bytes, each part rounded up to 256 bytes,
+ * above the array, non-finite energy), ISDF_E_STATE (fit not from this
+ * plan), ISDF_E_UNSUPPORTED (fits made with universal_all_points),
+ * ISDF_E_HIP. */
+#define ISDF_NOALLOC_SCRATCH_MB 32
+isdf_status isdf_exchange_occ_ri_noalloc(isdf_plan_t plan, isdf_fit_t fit, const double* C_dev,
+                                         int32_t n_occ, double* KC_dev, double* e_x);
+
 /* Universal grid with every point as a fitting function (the sinc functions
  * of the sparse grid; sections "Building the exchange matrix" and Results):
  * the exchange of the pairs the universal domain holds (both functions on

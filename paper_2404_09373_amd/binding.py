@@ -33,7 +33,9 @@ EXPORTED = [
     "isdf_fit_selection", "isdf_fit_features", "isdf_mlp_forward", "isdf_mlp_loss_grad",
     "isdf_mlp_train", "isdf_profile", "isdf_kernel_stats", "isdf_exchange_occ", "isdf_autotune",
     "isdf_fit_batch", "isdf_exchange_occ_ri", "isdf_grids_for_threshold", "isdf_exchange_universal",
+    "isdf_exchange_occ_ri_noalloc",
 ]
+NOALLOC_SCRATCH_MB = 32
 MLP_NPARAM = 5313
 
 
@@ -143,6 +145,7 @@ def load(required: bool = True):
     lib.isdf_exchange_occ.argtypes = [vp, vp, vp, C.c_int32, vp, C.POINTER(C.c_double)]
     lib.isdf_exchange_occ_ri.argtypes = [vp, vp, vp, C.c_int32, vp, C.POINTER(C.c_double)]
     lib.isdf_exchange_universal.argtypes = [vp, vp, vp, C.c_int32, vp, C.POINTER(C.c_double)]
+    lib.isdf_exchange_occ_ri_noalloc.argtypes = [vp, vp, vp, C.c_int32, vp, C.POINTER(C.c_double)]
     lib.isdf_autotune.argtypes = [vp, C.c_int32, C.c_int32, C.c_char_p]
     lib.isdf_grids_for_threshold.argtypes = [C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_double),
                                              C.c_int32, C.POINTER(C.c_double), C.c_double,
@@ -157,7 +160,8 @@ def load(required: bool = True):
                  "isdf_fit_with_candidates", "isdf_fit_selection", "isdf_fit_features",
                  "isdf_mlp_forward", "isdf_mlp_loss_grad", "isdf_mlp_train", "isdf_profile",
                  "isdf_kernel_stats", "isdf_exchange_occ", "isdf_autotune", "isdf_fit_batch",
-                 "isdf_exchange_occ_ri", "isdf_grids_for_threshold", "isdf_exchange_universal"):
+                 "isdf_exchange_occ_ri", "isdf_grids_for_threshold", "isdf_exchange_universal",
+                 "isdf_exchange_occ_ri_noalloc"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -453,6 +457,26 @@ class Fit:
         _check(load().isdf_exchange_occ_ri(self.plan.handle, self.handle, C.c_void_p(C_occ.data_ptr()),
                                            int(C_occ.shape[1]), C.c_void_p(KC.data_ptr()), C.byref(ex)),
                "isdf_exchange_occ_ri")
+        return KC, ex.value
+
+    def exchange_occ_ri_noalloc(self, C_occ, KC):
+        """K C through isdf_exchange_occ_ri_noalloc (FP64, workspace in the
+        library's fixed scratch array; KC caller-allocated like C_occ);
+        returns (KC, e_x)."""
+        import torch
+
+        if not isinstance(C_occ, torch.Tensor) or not C_occ.is_cuda or C_occ.dtype != torch.float64:
+            raise TypeError("C_occ must be a float64 CUDA tensor")
+        C_occ = C_occ.contiguous()
+        if C_occ.dim() != 2 or C_occ.shape[0] != self.plan.n_basis:
+            raise ValueError("C_occ must have shape (N, n_occ)")
+        if KC.shape != C_occ.shape or KC.dtype != torch.float64 or not KC.is_contiguous():
+            raise ValueError("KC must be a contiguous float64 tensor shaped like C_occ")
+        ex = C.c_double()
+        _check(load().isdf_exchange_occ_ri_noalloc(self.plan.handle, self.handle,
+                                                   C.c_void_p(C_occ.data_ptr()), int(C_occ.shape[1]),
+                                                   C.c_void_p(KC.data_ptr()), C.byref(ex)),
+               "isdf_exchange_occ_ri_noalloc")
         return KC, ex.value
 
     def exchange_universal(self, C_occ, KC=None):

@@ -2375,21 +2375,25 @@ isdf_status exchange_enqueue(isdf_plan_s* plan, isdf_fit_s* fit, const double* i
 // KC = K C (N x n_occ, row-major like C) for D = C C^T, without forming K:
 // E_L = X^L C, E_N = X^N C, Z1 = Q_GG E_L + Q_GL E_N, Z2 = Q_GL^T E_L +
 // Q_LL E_N, K C = -(X^L' Z1 + X^N' Z2); e_x = sum(C o KC) = tr(D K).
-isdf_status exchange_enqueue_ri(isdf_plan_s* plan, isdf_fit_s* fit, const double* Cin, int n_occ, double* KC,
-                                bool stage_event) {
+// Workspace of the FP64 occ-RI products: E_G, E_L, E_N, Z1, Z2 (N_mu x n_occ)
+// and the three Hadamard blocks Q_GG, Q_GL, Q_LL (N_mu x N_mu), column-major.
+struct RiBuffers {
+  double *EG, *EL, *EN, *QGG, *QGL, *QLL, *Z1, *Z2;
+};
+
+// FP64 occ-RI products into the given workspace (no allocation):
+//   E_G = X^G C, E_L = X^L C, E_N = E_G - E_L,
+//   Q_ST = W o (E_S E_T^T), Z1 = Q_GG E_L + Q_GL E_N, Z2 = Q_GL^T E_L + Q_LL E_N,
+//   (K C)^T = -(Z1^T X^L + Z2^T X^N)   (n_occ x N column-major = K C row-major).
+isdf_status ri_fp64_products(isdf_plan_s* plan, isdf_fit_s* fit, const double* Cin, int o, double* KC,
+                             const RiBuffers& b) {
   hipStream_t s = plan->stream;
-  const int64_t nmu = fit->nmu, N = plan->hp.n_basis;
-  const int m = (int)nmu, n = (int)N, o = n_occ;
+  const int64_t nmu = fit->nmu;
+  const int m = (int)nmu, n = (int)plan->hp.n_basis;
   const double* XL = fit->XL.as<double>();
   const double* XN = fit->XN.as<double>();
   const double* XG = fit->XG.as<double>();
   const double* W = fit->W.as<double>();
-  double* EG = fit->EG.as<double>();
-  double* EL = fit->EL.as<double>();
-  double* EN = fit->EN.as<double>();
-  double* Z1 = fit->Z1.as<double>();
-  double* Z2 = fit->Z2.as<double>();
-  isdf_status st;
   auto gemm = [&](int epi, const double* A, int64_t lda, int tA, const double* B, int64_t ldb, int tB,
                   double* C, int64_t ldc, int M, int Nn, int Kk, double alpha, double beta, const double* E) {
     GemmProblem p{};
@@ -2401,6 +2405,32 @@ isdf_status exchange_enqueue_ri(isdf_plan_s* plan, isdf_fit_s* fit, const double
     p.alpha = alpha; p.beta = beta;
     return gemm_prof(plan, ISDF_K_GEMM_EXCHANGE, epi, p);
   };
+  isdf_status st;
+  if ((st = gemm(EPI_AXPBY, XG, nmu, 0, Cin, o, 1, b.EG, nmu, m, o, n, 1.0, 0.0, nullptr)) != ISDF_OK) return st;
+  if ((st = gemm(EPI_AXPBY, XL, nmu, 0, Cin, o, 1, b.EL, nmu, m, o, n, 1.0, 0.0, nullptr)) != ISDF_OK) return st;
+  if ((st = launch_sub(s, b.EG, b.EL, b.EN, nmu * o)) != ISDF_OK) return st;
+  if ((st = gemm(EPI_HADAMARD, b.EG, nmu, 0, b.EG, nmu, 1, b.QGG, nmu, m, m, o, 1.0, 0.0, W)) != ISDF_OK) return st;
+  if ((st = gemm(EPI_HADAMARD, b.EG, nmu, 0, b.EL, nmu, 1, b.QGL, nmu, m, m, o, 1.0, 0.0, W)) != ISDF_OK) return st;
+  if ((st = gemm(EPI_HADAMARD, b.EL, nmu, 0, b.EL, nmu, 1, b.QLL, nmu, m, m, o, 1.0, 0.0, W)) != ISDF_OK) return st;
+  if ((st = gemm(EPI_AXPBY, b.QGG, nmu, 0, b.EL, nmu, 0, b.Z1, nmu, m, o, m, 1.0, 0.0, nullptr)) != ISDF_OK) return st;
+  if ((st = gemm(EPI_AXPBY, b.QGL, nmu, 0, b.EN, nmu, 0, b.Z1, nmu, m, o, m, 1.0, 1.0, nullptr)) != ISDF_OK) return st;
+  if ((st = gemm(EPI_AXPBY, b.QGL, nmu, 1, b.EL, nmu, 0, b.Z2, nmu, m, o, m, 1.0, 0.0, nullptr)) != ISDF_OK) return st;
+  if ((st = gemm(EPI_AXPBY, b.QLL, nmu, 0, b.EN, nmu, 0, b.Z2, nmu, m, o, m, 1.0, 1.0, nullptr)) != ISDF_OK) return st;
+  if ((st = gemm(EPI_AXPBY, b.Z1, nmu, 1, XL, nmu, 0, KC, o, o, n, m, -1.0, 0.0, nullptr)) != ISDF_OK) return st;
+  return gemm(EPI_AXPBY, b.Z2, nmu, 1, XN, nmu, 0, KC, o, o, n, m, -1.0, 1.0, nullptr);
+}
+
+isdf_status exchange_enqueue_ri(isdf_plan_s* plan, isdf_fit_s* fit, const double* Cin, int n_occ, double* KC,
+                                bool stage_event) {
+  hipStream_t s = plan->stream;
+  const int64_t nmu = fit->nmu, N = plan->hp.n_basis;
+  const int m = (int)nmu, n = (int)N, o = n_occ;
+  double* EG = fit->EG.as<double>();
+  double* EL = fit->EL.as<double>();
+  double* EN = fit->EN.as<double>();
+  double* Z1 = fit->Z1.as<double>();
+  double* Z2 = fit->Z2.as<double>();
+  isdf_status st;
   if (mixed_on(plan, ISDF_MIX_EXCHANGE)) {
     const int S = mixed_splits(plan);
     if ((st = make_planes(s, S, Cin, 1, o, nullptr, o, n, fit->Dp)) != ISDF_OK) return st;
@@ -2449,22 +2479,8 @@ isdf_status exchange_enqueue_ri(isdf_plan_s* plan, isdf_fit_s* fit, const double
     if ((st = launch_sum_parts(s, fit->KCpart.as<double>(), fit->kcparts, (int64_t)o * n, KC)) != ISDF_OK)
       return st;
   } else {
-    if ((st = gemm(EPI_AXPBY, XG, nmu, 0, Cin, o, 1, EG, nmu, m, o, n, 1.0, 0.0, nullptr)) != ISDF_OK) return st;
-    if ((st = gemm(EPI_AXPBY, XL, nmu, 0, Cin, o, 1, EL, nmu, m, o, n, 1.0, 0.0, nullptr)) != ISDF_OK) return st;
-    if ((st = launch_sub(s, EG, EL, EN, nmu * o)) != ISDF_OK) return st;
-    double* QGG = fit->QGG.as<double>();
-    double* QGL = fit->QGL.as<double>();
-    double* QLL = fit->QLL.as<double>();
-    if ((st = gemm(EPI_HADAMARD, EG, nmu, 0, EG, nmu, 1, QGG, nmu, m, m, o, 1.0, 0.0, W)) != ISDF_OK) return st;
-    if ((st = gemm(EPI_HADAMARD, EG, nmu, 0, EL, nmu, 1, QGL, nmu, m, m, o, 1.0, 0.0, W)) != ISDF_OK) return st;
-    if ((st = gemm(EPI_HADAMARD, EL, nmu, 0, EL, nmu, 1, QLL, nmu, m, m, o, 1.0, 0.0, W)) != ISDF_OK) return st;
-    if ((st = gemm(EPI_AXPBY, QGG, nmu, 0, EL, nmu, 0, Z1, nmu, m, o, m, 1.0, 0.0, nullptr)) != ISDF_OK) return st;
-    if ((st = gemm(EPI_AXPBY, QGL, nmu, 0, EN, nmu, 0, Z1, nmu, m, o, m, 1.0, 1.0, nullptr)) != ISDF_OK) return st;
-    if ((st = gemm(EPI_AXPBY, QGL, nmu, 1, EL, nmu, 0, Z2, nmu, m, o, m, 1.0, 0.0, nullptr)) != ISDF_OK) return st;
-    if ((st = gemm(EPI_AXPBY, QLL, nmu, 0, EN, nmu, 0, Z2, nmu, m, o, m, 1.0, 1.0, nullptr)) != ISDF_OK) return st;
-    // (K C)^T (n_occ x N column-major = K C row-major) = -(Z1' X^L + Z2' X^N)
-    if ((st = gemm(EPI_AXPBY, Z1, nmu, 1, XL, nmu, 0, KC, o, o, n, m, -1.0, 0.0, nullptr)) != ISDF_OK) return st;
-    if ((st = gemm(EPI_AXPBY, Z2, nmu, 1, XN, nmu, 0, KC, o, o, n, m, -1.0, 1.0, nullptr)) != ISDF_OK) return st;
+    const RiBuffers b{EG, EL, EN, fit->QGG.as<double>(), fit->QGL.as<double>(), fit->QLL.as<double>(), Z1, Z2};
+    if ((st = ri_fp64_products(plan, fit, Cin, o, KC, b)) != ISDF_OK) return st;
   }
   if (stage_event) ISDF_HIP_TRY(hipEventRecord(plan->ev[1], s));
   return launch_trace_dot(s, Cin, KC, N * o, fit->partial.as<double>(), 1024, fit->ex_out.as<double>());
@@ -2806,6 +2822,46 @@ isdf_status exchange_run(isdf_plan_s* plan, isdf_fit_s* fit, const double* in, i
 }  // namespace
 
 // ====================================================================== C ABI
+// ---------------------------------------------------------------------------
+// Exchange with no device allocation (isdf_exchange_occ_ri_noalloc): the
+// FP64 occ-RI workspace lives in this file-scope array, one copy per GPU,
+// held until the process ends.  Host code never passes the array's name to a
+// kernel (on the host it is a stand-in, not a device address): each device's
+// address comes from hipGetSymbolAddress, taken once with that device
+// current, and only that address is used.  Every call on a GPU shares its
+// array, so calls that overlap on one GPU race.
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(ISDF_NOALLOC_SCRATCH_MB) << 20;
+static __device__ __align__(256) char scratch[NOALLOC_SCRATCH_BYTES];
+
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_addr;  // device -> address of its copy of `scratch`
+
+isdf_status scratch_address(void** out) {
+  int dev = -1;
+  ISDF_HIP_TRY(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_addr.find(dev);
+  if (it == g_scratch_addr.end()) {
+    void* p = nullptr;
+    ISDF_HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) {
+      set_error("isdf_exchange_occ_ri_noalloc: no device address for the scratch array");
+      return ISDF_E_HIP;
+    }
+    it = g_scratch_addr.emplace(dev, p).first;
+  }
+  *out = it->second;
+  return ISDF_OK;
+}
+
+// Bytes of the FP64 occ-RI workspace for N_mu points and n_occ orbitals
+// (every part rounded up to 256 bytes).
+size_t noalloc_bytes(int64_t nmu, int64_t o) {
+  auto r = [](size_t b) { return (b + 255) / 256 * 256; };
+  return 5 * r(sizeof(double) * nmu * o) + 3 * r(sizeof(double) * nmu * nmu) + r(sizeof(double) * 1024) +
+         r(sizeof(double));
+}
+
 extern "C" {
 
 const char* isdf_last_error(void) { return g_err.c_str(); }
@@ -3305,6 +3361,75 @@ isdf_status isdf_exchange_occ_ri(isdf_plan_t plan, isdf_fit_t fit, const double*
     return ISDF_E_ARG;
   }
   return exchange_run(plan, fit, C_occ, n_occ, KC, e_x, true);
+}
+
+isdf_status isdf_exchange_occ_ri_noalloc(isdf_plan_t plan, isdf_fit_t fit, const double* C_occ,
+                                         int32_t n_occ, double* KC, double* e_x) {
+  if (!plan || !fit || !C_occ || !KC || n_occ < 1) {
+    set_error("isdf_exchange_occ_ri_noalloc: null argument or n_occ < 1");
+    return ISDF_E_ARG;
+  }
+  if (n_occ > plan->hp.n_basis) {
+    set_error("isdf_exchange_occ_ri_noalloc: n_occ above the basis size");
+    return ISDF_E_ARG;
+  }
+  if (fit->plan != plan) {
+    set_error("isdf_exchange_occ_ri_noalloc: fit belongs to another plan");
+    return ISDF_E_STATE;
+  }
+  if (fit->all_points) {
+    set_error("isdf_exchange_occ_ri_noalloc: fits with every universal point a fitting function "
+              "need the allocating isdf_exchange_occ_ri");
+    return ISDF_E_UNSUPPORTED;
+  }
+  const int64_t nmu = fit->nmu, o = n_occ;
+  const size_t need = noalloc_bytes(nmu, o);
+  if (need > NOALLOC_SCRATCH_BYTES) {
+    set_error("isdf_exchange_occ_ri_noalloc: workspace of " + std::to_string(need) +
+              " bytes (3 N_mu^2 + 5 N_mu n_occ doubles) exceeds the fixed " +
+              std::to_string(NOALLOC_SCRATCH_BYTES) + "-byte scratch array");
+    return ISDF_E_ARG;
+  }
+  void* base = nullptr;
+  isdf_status st;
+  if ((st = scratch_address(&base)) != ISDF_OK) return st;
+  char* p = static_cast<char*>(base);
+  auto take = [&](size_t bytes) {
+    double* q = reinterpret_cast<double*>(p);
+    p += (bytes + 255) / 256 * 256;
+    return q;
+  };
+  RiBuffers b{};
+  b.EG = take(sizeof(double) * nmu * o);
+  b.EL = take(sizeof(double) * nmu * o);
+  b.EN = take(sizeof(double) * nmu * o);
+  b.Z1 = take(sizeof(double) * nmu * o);
+  b.Z2 = take(sizeof(double) * nmu * o);
+  b.QGG = take(sizeof(double) * nmu * nmu);
+  b.QGL = take(sizeof(double) * nmu * nmu);
+  b.QLL = take(sizeof(double) * nmu * nmu);
+  double* partial = take(sizeof(double) * 1024);
+  double* ex_out = take(sizeof(double));
+  hipStream_t s = plan->stream;
+  ISDF_HIP_TRY(hipEventRecord(plan->ev[0], s));
+  // every buffer is written before it is read (beta = 0 first, the partial
+  // sums by the reduction itself), so nothing needs clearing
+  if ((st = ri_fp64_products(plan, fit, C_occ, n_occ, KC, b)) != ISDF_OK) return st;
+  if ((st = launch_trace_dot(s, C_occ, KC, plan->hp.n_basis * o, partial, 1024, ex_out)) != ISDF_OK) return st;
+  ISDF_HIP_TRY(hipEventRecord(plan->ev[2], s));
+  double ex = 0.0;
+  ISDF_HIP_TRY(hipMemcpyAsync(&ex, ex_out, sizeof(double), hipMemcpyDeviceToHost, s));
+  ISDF_HIP_TRY(hipStreamSynchronize(s));
+  prof_collect(plan);
+  float ms = 0.f;
+  ISDF_HIP_TRY(hipEventElapsedTime(&ms, plan->ev[0], plan->ev[2]));
+  plan->stage_ms[6] = plan->stage_ms[7] = ms;
+  if (e_x) *e_x = ex;
+  if (!std::isfinite(ex)) {
+    set_error("isdf_exchange_occ_ri_noalloc: non-finite exchange energy (NaN or Inf in C?)");
+    return ISDF_E_ARG;
+  }
+  return ISDF_OK;
 }
 
 isdf_status isdf_exchange_universal(isdf_plan_t plan, isdf_fit_t fit, const double* C_occ, int32_t n_occ,
