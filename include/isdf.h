@@ -355,9 +355,8 @@ isdf_status isdf_exchange_universal(isdf_plan_t plan, isdf_fit_t fit, const doub
  * `reps` launches, and the fastest is kept in the plan and written to
  * json_out (NULL: kept only).  Results do not depend on the shape; only the
  * speed does.  Load the file into later plans with isdf_options.tune_file.
- * The products that run on the vendor FP64 GEMM (large plain products of
- * the fit) are timed on the tile engine here; the table only serves the
- * engine.
+ * The shapes include the large 128 x 64 / 128 x 128 tiles on
+ * v_mfma_f64_4x4x4 (not for gathered-row or non-square triangle problems).
  * Errors: ISDF_E_ARG (n_occ outside 1..N, reps < 1, file not writable),
  * those of isdf_fit and isdf_exchange (ISDF_E_UNSUPPORTED for plans with
  * universal_all_points, whose fits give K C only). */

@@ -35,9 +35,7 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]
 
-
-# the vendor FP64 GEMM for the fit's large plain products
-LIBS = ["-L/opt/rocm/lib", "-Wl,-rpath,/opt/rocm/lib", "-lrocblas"]
+LIBS: list = []
 
 
 def _compile(src: str) -> str:

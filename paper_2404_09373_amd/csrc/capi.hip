@@ -27,7 +27,6 @@
 #include <numeric>
 #include <thread>
 
-#include <rocblas/rocblas.h>
 
 #include "common.h"
 
@@ -304,8 +303,6 @@ struct isdf_plan_s {
   // last two chunks of step launches, and the events that mark them
   SelState* crb_host = nullptr;
   hipEvent_t crb_ev[2] = {};
-  // vendor FP64 GEMM for the fit's large plain products (created on first use)
-  rocblas_handle blas = nullptr;
 };
 
 struct isdf_fit_s {
@@ -507,6 +504,7 @@ isdf_status tune_problem(isdf_plan_s* pl, int epi, int tag, const GemmProblem& p
   float tbest = 0.f;
   for (int sh = 0; sh < GEMM_NSHAPE; ++sh) {
     if (p.lower && kShapes[sh].bm != kShapes[sh].bn) continue;
+    if (p.bidx && kShapes[sh].mf4 == 2) continue;  // the large tiles take no gathered rows
     float tmin = 0.f;
     for (int r = 0; r < pl->tune_reps; ++r) {
       if (rd) ISDF_HIP_TRY(hipMemcpyAsync(p.C, save.p, cbytes, hipMemcpyDeviceToDevice, s));
@@ -545,49 +543,6 @@ isdf_status gemm_prof(isdf_plan_s* pl, int fam, int epi, const GemmProblem& p) {
       it = pl->tune.find(key);
     }
     if (it != pl->tune.end()) shape = it->second;
-  }
-  // Large plain products of the fit (AXPBY epilogue, no gathered rows, no
-  // triangle-only tiles) run on the vendor FP64 GEMM, which reaches about
-  // twice the rate of the engine here on these shapes (53-66 against 20-27
-  // TFLOP/s measured); so do the large Hadamard Grams (EPI_THETA: a_L and
-  // a_N as products, then C = a_L (a_L + 2 a_N) elementwise).  The
-  // exchange's products stay on the engine (they are captured into
-  // graphs), and tuning times the engine only.
-  if ((epi == EPI_AXPBY || epi == EPI_THETA) && !p.bidx && !p.lower && !pl->tuning &&
-      fam != ISDF_K_GEMM_EXCHANGE && p.K > 0 && (double)p.M * p.N * p.K >= (double)(1 << 30)) {
-    if (!pl->blas && rocblas_create_handle(&pl->blas) != rocblas_status_success) {
-      pl->blas = nullptr;
-      set_error("rocblas_create_handle failed");
-      return ISDF_E_HIP;
-    }
-    if (rocblas_set_stream(pl->blas, pl->stream) != rocblas_status_success) {
-      set_error("rocblas_set_stream failed");
-      return ISDF_E_HIP;
-    }
-    ProfScope ps(pl, fam, gemm_bytes(p), gemm_flops(p));
-    auto dgemm = [&](int64_t k0, int64_t k1, double alpha, double beta, double* C, int64_t ldc) -> isdf_status {
-      const double* A = p.transA ? p.A + k0 : p.A + k0 * p.lda;
-      const double* B = p.transB ? p.B + k0 * p.ldb : p.B + k0;
-      const rocblas_status r = rocblas_dgemm(
-          pl->blas, p.transA ? rocblas_operation_transpose : rocblas_operation_none,
-          p.transB ? rocblas_operation_transpose : rocblas_operation_none, p.M, p.N, (rocblas_int)(k1 - k0), &alpha,
-          A, p.lda, B, p.ldb, &beta, C, ldc);
-      if (r != rocblas_status_success) {
-        set_error(std::string("rocblas_dgemm: ") + rocblas_status_to_string(r));
-        return ISDF_E_HIP;
-      }
-      return ISDF_OK;
-    };
-    if (epi == EPI_AXPBY) return dgemm(0, p.K, p.alpha, p.beta, p.C, p.ldc);
-    const int64_t kL = std::max<int64_t>(0, std::min<int64_t>(p.kL, p.K));
-    isdf_status st;
-    if ((st = dgemm(0, kL, 1.0, 0.0, p.C, p.ldc)) != ISDF_OK) return st;  // kL = 0: C = 0
-    DevBuf aN;
-    if (kL < p.K) {
-      if ((st = aN.alloc(sizeof(double) * p.M * p.N)) != ISDF_OK) return st;
-      if ((st = dgemm(kL, p.K, 1.0, 0.0, aN.as<double>(), p.M)) != ISDF_OK) return st;
-    }
-    return launch_theta_combine(pl->stream, p.C, p.ldc, kL < p.K ? aN.as<double>() : nullptr, p.M, p.N);
   }
   ProfScope ps(pl, fam, gemm_bytes(p), gemm_flops(p));
   return gemm_f64(pl->stream, epi, p, tag, shape);
@@ -3545,7 +3500,6 @@ void isdf_plan_destroy(isdf_plan_t plan) {
   for (auto e : plan->crb_ev)
     if (e) (void)hipEventDestroy(e);
   if (plan->crb_host) (void)hipHostFree(plan->crb_host);
-  if (plan->blas) (void)rocblas_destroy_handle(plan->blas);
   if (plan->cap_stream) (void)hipStreamDestroy(plan->cap_stream);
   delete plan;
 }

@@ -112,13 +112,16 @@ struct GemmProblem {
 // that shape.
 struct GemmShape {
   int bm, bn, wm, wn;
-  int mf4;  // 1: v_mfma_f64_4x4x4 (4 blocks), 0: v_mfma_f64_16x16x4
+  int mf4;  // 1: v_mfma_f64_4x4x4 (4 blocks), 0: v_mfma_f64_16x16x4, 2: the large-tile
+            // 4x4x4 kernel (gemm_big_kernel)
 };
-constexpr int GEMM_NSHAPE = 8;
+constexpr int GEMM_NSHAPE = 12;
 extern const GemmShape kShapes[GEMM_NSHAPE];
 isdf_status gemm_f64(hipStream_t s, int epi, const GemmProblem& p, int tag = 0, int shape = -1);
+// ta, tb: the operand layouts every problem of the group shares (required by
+// the large-tile shapes, whose layouts are compile-time; -1 otherwise).
 isdf_status gemm_f64_grouped(hipStream_t s, int epi, const GemmProblem* d_probs, int nprob,
-                             int total_tiles, int tag = 0, int shape = 0);
+                             int total_tiles, int tag = 0, int shape = 0, int ta = -1, int tb = -1);
 int gemm_tiles(int M, int N, int shape = 0, bool lower = false);
 int gemm_default_shape(int epi, int M, int N, int K, bool lower = false);
 
