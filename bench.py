@@ -1,9 +1,13 @@
 #!/usr/bin/env python
 """Multigrid-ISDF fit + exchange build per SCF iteration on one MI355X.
 
-Workload: 2x2x2 diamond supercell (64 atoms, N = 832 basis functions),
-grids 32^3 / 64^3 / 128^3, 8 interpolation points per owned function
-(N_mu = 6656), 128 occupied orbitals.
+Default workload (--config 4, the largest configuration that fits one
+GPU's memory whole): 3x3x3 diamond supercell (216 atoms, N = 2808 basis
+functions), grids 40^3 / 80^3 / 160^3, 8 interpolation points per owned
+function (N_mu = 22464), 432 occupied orbitals, the learned selector
+trained on the 8- and 64-atom cells.  --config 2 runs the 64-atom cell
+(N = 832, grids 32^3 / 64^3 / 128^3, N_mu = 6656, 128 occupied), whose
+oracle values are stored for parity.
 
 A step is the whole hot path once: one isdf_fit (basis values, pivoted-
 Cholesky points, fitting functions, Coulomb metric) followed by 7
@@ -13,11 +17,14 @@ per SCF iteration (lower is better).  Inputs are generated once and are
 resident on the GPU before the timed region.
 
 Two paths are timed on the same inputs:
-  reference  FP64 contractions, full pivoted-Cholesky selection
+  reference  FP64 contractions, full pivoted-Cholesky selection (timed over
+             --ref-steps steps, default 2, after one warm-up: it is the
+             accuracy and speed reference, not the headline)
   optimized  BF16-split (x6) contractions with FP32 accumulation carried in
              FP64, and the learned candidate selector (trained on the GPU in
              the untimed setup on full selections of the 8-atom cell and of a
-             differently displaced 64-atom cell)
+             differently displaced 64-atom cell), timed over exactly --steps
+             steps after --warmup warm-ups
 The headline value is the optimized path when its E_x agrees with the
 reference to 1e-6 Ha/atom, else the reference path.  Also reported: the
 roofline position of the headline path's dominant kernel family (HIP events
@@ -166,51 +173,68 @@ def train_selector(torch, log):
     return w, [float(h) for h in hist]
 
 
-def cpu_baseline(sysm):
-    """FP64 oracle on a bounded sample of the same workload, extrapolated to
-    one fit/7 + one exchange (seconds per SCF iteration)."""
+def cpu_baseline(sysm, sample_pts=4096, ex_scale=4):
+    """FP64 oracle (as it stands) on a bounded sample of the same workload,
+    extrapolated to one fit/7 + one exchange (seconds per SCF iteration).
+
+    The oracle's plan is built first (setup, not timed: the GPU path's plan
+    is outside its step too).  Then, with the host's threads:
+      basis      the universal domain and one window per finer level,
+                 evaluated on an evenly strided sample of at most sample_pts
+                 points, scaled by the point counts and window counts;
+      select     left-looking pivoted Cholesky on those sampled rows (64
+                 steps on the universal domain, every step on the windows),
+                 scaled by the step cost pts (|G| + k) summed over all steps;
+      fit        Theta, M_xi and F on the sampled rows, scaled by the flop
+                 model 2 pts n |G| + 2 pts n^2 + n^3/3;
+      coulomb    one 16-column batch of Poisson solves and W products per
+                 level, scaled by the column count;
+      exchange   the four-term K on a random instance with N_mu and N cut by
+                 ex_scale, scaled by 8 N_mu N^2 + 14 N_mu^2 N.
+    """
     from oracle import basis, coulomb, exchange, isdf
     from oracle import plan as oplan
 
     cores = len(os.sched_getaffinity(0))
     t_all = time.perf_counter()
     p = oplan.build_plan(sysm)
+    t_plan = time.perf_counter() - t_all
     doms = p.domains
     levels = sorted({d.level for d in doms})
-    est = {}
-    U = doms[0]
-    t = time.perf_counter()
-    Phi = basis.domain_values(p, U)
-    est["basis"] = time.perf_counter() - t
-    ks = min(192, U.n_mu)
-    t = time.perf_counter()
-    piv, _, _, _ = isdf.pivoted_cholesky(Phi, U.L.size, ks, sysm.eps_isdf, sysm.tie_tol)
-    t_sel = time.perf_counter() - t
-    nG = U.L.size + U.N.size
-    est["select"] = t_sel * sum(nG + k for k in range(U.n_mu)) / sum(nG + k for k in range(ks))
-    t = time.perf_counter()
-    isdf.fit_functions(Phi, U.L.size, piv)
-    t_fit = time.perf_counter() - t
+    est = {"basis": 0.0, "select": 0.0, "fit": 0.0}
 
-    def work(n):
-        return 2.0 * U.points.size * n * nG + 2.0 * U.points.size * n * n + n ** 3 / 3.0
+    def sampled(dom):
+        idx = np.linspace(0, dom.points.size - 1, min(sample_pts, dom.points.size)).astype(np.int64)
+        idx = np.unique(idx)
+        t = time.perf_counter()
+        if dom.atom < 0:
+            Phi = basis.evaluate(p, dom.level, dom.points[idx], dom.G)
+        else:
+            Phi = basis.evaluate(p, dom.level, dom.points[idx], dom.G, window_centre=p.xyz[dom.atom],
+                                 window_radius=dom.r_max)
+        return Phi, time.perf_counter() - t, dom.points.size / idx.size
 
-    est["fit"] = t_fit * work(U.n_mu) / work(ks)
-    for lev in levels[1:]:
-        ws = [d for d in doms if d.level == lev]
-        d = ws[0]
+    def work(pts, n, nG):
+        return 2.0 * pts * n * nG + 2.0 * pts * n * n + n ** 3 / 3.0
+
+    groups = [[d for d in doms if d.level == lev] for lev in levels]
+    for g in groups:
+        d = g[0]
+        Phi, tb, scale = sampled(d)
+        nG = d.L.size + d.N.size
+        ks = min(64 if d.atom < 0 else d.n_mu, d.n_mu, Phi.shape[0])
         t = time.perf_counter()
-        Phw = basis.domain_values(p, d)
-        tb = time.perf_counter() - t
-        t = time.perf_counter()
-        pw, _, _, _ = isdf.pivoted_cholesky(Phw, d.L.size, d.n_mu, sysm.eps_isdf, sysm.tie_tol)
+        piv, _, _, _ = isdf.pivoted_cholesky(Phi, d.L.size, ks, sysm.eps_isdf, sysm.tie_tol)
         tsel = time.perf_counter() - t
+        steps_all = sum(nG + k for k in range(d.n_mu))
+        steps_run = max(sum(nG + k for k in range(len(piv))), 1)
         t = time.perf_counter()
-        isdf.fit_functions(Phw, d.L.size, pw)
+        isdf.fit_functions(Phi, d.L.size, piv)
         tf = time.perf_counter() - t
-        est["basis"] += tb * len(ws)
-        est["select"] += tsel * len(ws)
-        est["fit"] += tf * len(ws)
+        w = len(g)
+        est["basis"] += tb * scale * w
+        est["select"] += tsel * scale * steps_all / steps_run * w
+        est["fit"] += tf * work(d.points.size, d.n_mu, nG) / work(Phi.shape[0], len(piv), nG) * w
     rng = np.random.default_rng(0)
     t_coul = 0.0
     vker = [coulomb.coulomb_kernel(p.lattice, p.grids[l]) for l in range(len(p.grids))]
@@ -232,21 +256,25 @@ def cpu_baseline(sysm):
                 _ = Fd.T @ V[d.points]
         t_coul += (time.perf_counter() - t) * cols / b
     est["coulomb"] = t_coul
-    nmu = sum(d.n_mu for d in doms)
-    N = p.n_basis
-    XL = np.zeros((nmu, N))
-    XN = np.zeros((nmu, N))
-    r = 0
-    for d in doms:
-        XL[r:r + d.n_mu][:, d.L] = rng.standard_normal((d.n_mu, d.L.size))
-        XN[r:r + d.n_mu][:, d.N] = rng.standard_normal((d.n_mu, d.N.size))
-        r += d.n_mu
+    nmu_all = sum(d.n_mu for d in doms)
+    N_all = p.n_basis
+    nmu = max(nmu_all // ex_scale, 1)
+    N = max(N_all // ex_scale, 1)
+    XL = rng.standard_normal((nmu, N)) * (rng.random((nmu, N)) < 0.1)
+    XN = rng.standard_normal((nmu, N)) * (rng.random((nmu, N)) < 0.5)
     W = rng.standard_normal((nmu, nmu))
     W = W + W.T
+    D = rng.standard_normal((N, N))
+    D = D @ D.T / N
     t = time.perf_counter()
-    K = exchange.exchange_matrix(XL, XN, W, sysm.D)
-    exchange.exchange_energy(sysm.D, K)
-    est["exchange"] = time.perf_counter() - t
+    K = exchange.exchange_matrix(XL, XN, W, D)
+    exchange.exchange_energy(D, K)
+    t_ex = time.perf_counter() - t
+
+    def ex_flops(m, n):
+        return 8.0 * m * n * n + 14.0 * m * m * n
+
+    est["exchange"] = t_ex * ex_flops(nmu_all, N_all) / ex_flops(nmu, N)
     t_fit_total = est["basis"] + est["select"] + est["fit"] + est["coulomb"]
     return {
         "value": round(t_fit_total / 7.0 + est["exchange"], 4),
@@ -254,11 +282,13 @@ def cpu_baseline(sysm):
         "cores": cores,
         "kind": "oracle",
         "sample": (
-            "FP64 NumPy oracle on the host: universal domain basis in full, 192 of "
-            f"{U.n_mu} pivot steps and the fit at 192 points (scaled by the left-looking "
-            "step cost and the fit flop model), one window per finer level in full "
-            "(x64), one 16-column Poisson/W batch per level (scaled by column count), "
-            "exchange build in full"
+            f"FP64 NumPy oracle on the host ({cores} threads), bounded sample scaled to the workload: "
+            f"basis, selection and fit on <= {sample_pts} evenly strided points of the universal "
+            "domain and of one window per finer level (64 universal pivot steps, all window steps; "
+            "scaled by points, step costs, the fit flop model and the window count), one 16-column "
+            "Poisson/W batch per level (scaled by column count), the four-term exchange on a "
+            f"random instance with N_mu and N cut {ex_scale}x (scaled by its flop count); the "
+            f"oracle's plan ({t_plan:.1f} s) is setup, not timed"
         ),
         "stages_s": {k: round(v, 3) for k, v in est.items()},
         "wall_s": round(time.perf_counter() - t_all, 1),
@@ -266,6 +296,16 @@ def cpu_baseline(sysm):
 
 
 TUNE_FILE = os.path.join(ROOT, "paper_2404_09373_amd", "tune", "gfx950.json")
+
+WORKLOADS = {
+    1: "cfg1: diamond 1x1x1 (8 atoms), 13 functions/atom (N=104), grids 24^3/48^3, N_mu=6N=624, "
+       "n_occ=16; step = 1 fit + 7 exchange builds",
+    2: "cfg2: diamond 2x2x2 (64 atoms, +-0.05 A displacements), 13 functions/atom (N=832), grids "
+       "32^3/64^3/128^3, N_mu=8N=6656, n_occ=128; step = 1 fit + 7 exchange builds",
+    4: "cfg4: diamond 3x3x3 (216 atoms, +-0.05 A displacements), 13 functions/atom (N=2808), grids "
+       "40^3/80^3/160^3, N_mu=8N=22464, n_occ=432, learned selector trained on the 8- and 64-atom "
+       "cells; step = 1 fit + 7 exchange builds",
+}
 
 # Threshold-driven diamond cells of the studies: two levels split at
 # alpha = 2 (the sharp 4.05 and 12.15 shells on atom windows), grids from
@@ -438,7 +478,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--config", type=int, default=4, choices=[1, 2, 4])
+    ap.add_argument("--ref-steps", type=int, default=2)
+    ap.add_argument("--mlp-keep", type=float, default=2.0)
+    ap.add_argument("--mlp-cutoff", type=float, default=None,
+                    help="selector score cutoff (default: 0.001 for the 216-atom cell, 0.05 otherwise; "
+                         "swept on each workload for the fastest exact selection)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--exchanges", type=int, default=7)
     ap.add_argument("--paths", choices=["both", "reference", "optimized"], default="both")
@@ -494,7 +539,9 @@ def main():
     Cocc = torch.tensor(s.C_occ, dtype=torch.float64, device=dev)
     tune = TUNE_FILE if os.path.exists(TUNE_FILE) else None
 
-    def run_path(plan, tag, occ=False):
+    def run_path(plan, tag, occ=False, steps=None, warmup=None):
+        steps = args.steps if steps is None else steps
+        warmup = args.warmup if warmup is None else warmup
         def step():
             fit = plan.fit()
             ex = None
@@ -508,7 +555,7 @@ def main():
             fit.close()
             return ex, n_mu, sel
 
-        for w in range(args.warmup):
+        for w in range(warmup):
             ex, _, _ = step()
             log(f"{tag} warmup {w} E_x={ex:.10f}")
         # one untimed step with every kernel family bracketed: the breakdown
@@ -523,18 +570,18 @@ def main():
         torch.cuda.synchronize()
         set_profile(plan, 1 << dom)
         t0 = time.perf_counter()
-        for i in range(args.steps):
+        for i in range(steps):
             ex, n_mu, sel = step()
             log(f"{tag} step {i} done")
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         timed = kernel_stats(plan)[dom]
         set_profile(plan, 0)
-        ms = (t1 - t0) / args.steps * 1e3
+        ms = (t1 - t0) / steps * 1e3
         if args.no_extra:
             return dict(ms_per_step=ms, value=ms / args.exchanges / 1e3, E_x=ex, n_mu=n_mu,
                         stats=breakdown, stages=stages, selection=sel, dominant=dom, timed=timed,
-                        occ_ri=None, universal=None)
+                        occ_ri=None, universal=None, steps=steps)
         # occ-RI output (K C, K never formed) on one more fit, outside the
         # timed steps: per-build time and its energy against the full K's
         fit = plan.fit()
@@ -550,6 +597,11 @@ def main():
         ri_ms = (time.perf_counter() - r0) / args.exchanges * 1e3
         occ_ri = {"ms_per_build": round(ri_ms, 3), "E_x": e_ri,
                   "abs_dE_per_atom_vs_full_K": abs(e_ri - e_full) / s.n_atoms}
+        if args.config != 2:  # the universal-block and all-points measurements run on the 64-atom cell
+            fit.close()
+            return dict(ms_per_step=ms, value=ms / args.exchanges / 1e3, E_x=ex, n_mu=n_mu,
+                        stats=breakdown, stages=stages, selection=sel, dominant=dom, timed=timed,
+                        occ_ri=occ_ri, universal=None, steps=steps)
         # universal grid with every point as a fitting function: its
         # diffuse-diffuse block of K C by occ-RI FFT Poisson solves
         fit.exchange_universal(Cocc, KC)
@@ -564,20 +616,21 @@ def main():
                      "pair_potentials": s.n_occ * (s.n_occ + 1) // 2}
         return dict(ms_per_step=ms, value=ms / args.exchanges / 1e3, E_x=ex, n_mu=n_mu,
                     stats=breakdown, stages=stages, selection=sel, dominant=dom, timed=timed,
-                    occ_ri=occ_ri, universal=universal)
+                    occ_ri=occ_ri, universal=universal, steps=steps)
 
+    mlp_cutoff = args.mlp_cutoff if args.mlp_cutoff is not None else (0.001 if args.config == 4 else 0.05)
     results = {}
     if args.paths in ("both", "reference"):
         plan = binding.Plan(s, stream=stream, tune_file=tune)
         log(f"cfg{args.config}: N={plan.n_basis} N_mu={plan.n_mu} domains={plan.n_domains}")
-        results["reference"] = run_path(plan, "reference")
+        results["reference"] = run_path(plan, "reference", steps=args.ref_steps, warmup=1)
         plan.close()
     weights, hist = None, None
     if args.paths in ("both", "optimized"):
         weights, hist = train_selector(torch, log)
         plan = binding.Plan(s, stream=stream, precision=binding.MIXED_X6,
-                            selector=binding.SEL_MLP, mlp_weights=weights, mlp_keep=2.0,
-                            mlp_cutoff=0.05, tune_file=tune)
+                            selector=binding.SEL_MLP, mlp_weights=weights, mlp_keep=args.mlp_keep,
+                            mlp_cutoff=mlp_cutoff, tune_file=tune)
         results["optimized"] = run_path(plan, "optimized", occ=True)
         plan.close()
 
@@ -586,7 +639,7 @@ def main():
     # grid, the universal block of K C by occ-RI FFT Poisson solves; K C
     # only, so it is reported beside the headline, not as it
     all_points = None
-    if args.paths == "both" and not args.no_extra:
+    if args.paths == "both" and not args.no_extra and args.config == 2:
         sel = dict(selector=binding.SEL_MLP, mlp_weights=weights, mlp_keep=2.0, mlp_cutoff=0.05) \
             if weights is not None else {}
         plan = binding.Plan(s, stream=stream, precision=binding.MIXED_X6, tune_file=tune,
@@ -642,6 +695,7 @@ def main():
         return {
             "value": round(r["value"], 6),
             "ms_per_step": round(r["ms_per_step"], 3),
+            "steps_timed": r["steps"],
             "E_x": r["E_x"],
             "stage_ms_last_fit": {
                 "basis": round(st[0], 3), "select": round(st[1], 3), "gather": round(st[2], 3),
@@ -678,9 +732,7 @@ def main():
         "dtype": "bf16x6/f64" if use_opt else "f64",
         "data": "synthetic",
         "config": {
-            "workload": ("cfg2: diamond 2x2x2 (64 atoms, +-0.05 A displacements), 13 functions/atom "
-                         "(N=832), grids 32^3/64^3/128^3, N_mu=8N=6656, n_occ=128; step = 1 fit + "
-                         "7 exchange builds") if args.config == 2 else f"cfg{args.config}",
+            "workload": WORKLOADS.get(args.config, f"cfg{args.config}"),
             "n_basis": s.n_basis,
             "n_mu": head["n_mu"],
             "exchanges_per_fit": args.exchanges,
