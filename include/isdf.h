@@ -130,7 +130,23 @@ typedef struct {
   int32_t universal_tile_mb;  /* most MB of universal pair potentials held at once (their
                                  pairs go in row tiles); 0: the smaller of 16 GB and 40 %
                                  of the free memory                                       */
+  int32_t w_storage;          /* ISDF_W_F64 (default) or ISDF_W_F32: the Coulomb metric
+                                 W = (xi|xi') (Eq. (xi|xi')) is formed in FP64 and, with
+                                 F32, kept in FP32 after the fit (half the memory and the
+                                 exchange's reads of it; entries rounded to 24 bits)      */
+  int32_t pad1;
+  void* workspace;            /* caller-owned device buffer (e.g. torch.empty), 256-byte
+                                 aligned, or NULL: the plan then takes every device buffer
+                                 of its fits and exchanges from it (never hipMalloc) and
+                                 returns ISDF_E_NOMEM when it runs out; it must outlive the
+                                 plan and its fits.  Size it with isdf_plan_workspace_bytes
+                                 after a fit and exchange of a plan without one.  (Process-
+                                 wide FFT twiddle tables and the 64 MB pinned host staging
+                                 ring are not part of it.)                                */
+  size_t workspace_bytes;
 } isdf_options;
+/* Storage of the Coulomb metric W held by a fit. */
+enum { ISDF_W_F64 = 0, ISDF_W_F32 = 1 };
 
 /* Build the multigrid plan (host only, no device work).
  * Reads sys and opts; on success *out owns copies of everything it needs.
@@ -159,6 +175,14 @@ isdf_status isdf_plan(const isdf_system* sys, const isdf_options* opts, isdf_pla
 isdf_status isdf_grids_for_threshold(const double* lattice, int32_t n_shells,
                                      const double* shell_alpha, int32_t n_levels,
                                      const double* alpha_bound, double eps_K, int32_t* grid_out);
+
+/* Device bytes the plan's buffers have needed at once so far (blocks in use
+ * plus the plan's block cache, the high-water mark over its fits and
+ * exchange builds; 0 before any device work).  After one isdf_fit and the
+ * exchange calls of a plan made without a workspace, this is the size of a
+ * workspace with which a plan of the same system and options repeats them
+ * without allocating. */
+isdf_status isdf_plan_workspace_bytes(isdf_plan_t plan, size_t* bytes);
 
 /* Sizes: number of basis functions N, total requested points N_mu, domains. */
 isdf_status isdf_plan_info(isdf_plan_t plan, int64_t* n_basis, int64_t* n_mu, int32_t* n_domains);
@@ -370,7 +394,8 @@ isdf_status isdf_autotune(isdf_plan_t plan, int32_t n_occ, int32_t reps, const c
  *   ISDF_FIELD_THETA  domain d: Theta = M(P_d, xi), n_points x n, column-major
  *   ISDF_FIELD_F      domain d: fitting functions, n_points x n, column-major
  *   ISDF_FIELD_XL / ISDF_FIELD_XN  all: N_mu x N column-major
- *   ISDF_FIELD_W      all: N_mu x N_mu column-major (symmetric)
+ *   ISDF_FIELD_W      all: N_mu x N_mu column-major (symmetric); FP64 values
+ *                     (widened from the stored FP32 when w_storage = ISDF_W_F32)
  * `bytes` must equal the size of the field or ISDF_E_ARG is returned. */
 enum {
   ISDF_FIELD_PHI = 0, ISDF_FIELD_DIAG = 1, ISDF_FIELD_POINTS = 2, ISDF_FIELD_COUNT = 3,

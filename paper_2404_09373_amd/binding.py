@@ -22,6 +22,7 @@ STATUS = {
 }
 FIELD = {"phi": 0, "diag": 1, "points": 2, "count": 3, "theta": 4, "F": 5, "XL": 6, "XN": 7, "W": 8}
 FP64, MIXED_X3, MIXED_X6 = 0, 1, 2
+W_F64, W_F32 = 0, 1
 MIX_THETA, MIX_W, MIX_EXCHANGE = 1, 2, 4
 SEL_FULL, SEL_MLP = 0, 1
 
@@ -33,7 +34,7 @@ EXPORTED = [
     "isdf_fit_selection", "isdf_fit_features", "isdf_mlp_forward", "isdf_mlp_loss_grad",
     "isdf_mlp_train", "isdf_profile", "isdf_kernel_stats", "isdf_exchange_occ", "isdf_autotune",
     "isdf_fit_batch", "isdf_exchange_occ_ri", "isdf_grids_for_threshold", "isdf_exchange_universal",
-    "isdf_exchange_occ_ri_noalloc",
+    "isdf_exchange_occ_ri_noalloc", "isdf_plan_workspace_bytes",
 ]
 NOALLOC_SCRATCH_MB = 32
 MLP_NPARAM = 5313
@@ -96,6 +97,10 @@ class _Options(C.Structure):
         ("tune_file", C.c_char_p),
         ("universal_all_points", C.c_int32),
         ("universal_tile_mb", C.c_int32),
+        ("w_storage", C.c_int32),
+        ("pad1", C.c_int32),
+        ("workspace", C.c_void_p),
+        ("workspace_bytes", C.c_size_t),
     ]
 
 
@@ -146,6 +151,7 @@ def load(required: bool = True):
     lib.isdf_exchange_occ_ri.argtypes = [vp, vp, vp, C.c_int32, vp, C.POINTER(C.c_double)]
     lib.isdf_exchange_universal.argtypes = [vp, vp, vp, C.c_int32, vp, C.POINTER(C.c_double)]
     lib.isdf_exchange_occ_ri_noalloc.argtypes = [vp, vp, vp, C.c_int32, vp, C.POINTER(C.c_double)]
+    lib.isdf_plan_workspace_bytes.argtypes = [vp, C.POINTER(C.c_size_t)]
     lib.isdf_autotune.argtypes = [vp, C.c_int32, C.c_int32, C.c_char_p]
     lib.isdf_grids_for_threshold.argtypes = [C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_double),
                                              C.c_int32, C.POINTER(C.c_double), C.c_double,
@@ -161,7 +167,7 @@ def load(required: bool = True):
                  "isdf_mlp_forward", "isdf_mlp_loss_grad", "isdf_mlp_train", "isdf_profile",
                  "isdf_kernel_stats", "isdf_exchange_occ", "isdf_autotune", "isdf_fit_batch",
                  "isdf_exchange_occ_ri", "isdf_grids_for_threshold", "isdf_exchange_universal",
-                 "isdf_exchange_occ_ri_noalloc"):
+                 "isdf_exchange_occ_ri_noalloc", "isdf_plan_workspace_bytes"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -183,7 +189,8 @@ class Plan:
     def __init__(self, sysm, precision: int = FP64, selector: int = SEL_FULL, stream=None,
                  w_batch: int = 0, mlp_weights=None, mlp_keep: float = 2.0,
                  mlp_cutoff: float = 0.05, mixed_mask: int = 0, eager_exchange: bool = False,
-                 tune_file=None, universal_all_points: bool = False, universal_tile_mb: int = 0):
+                 tune_file=None, universal_all_points: bool = False, universal_tile_mb: int = 0,
+                 w_storage: int = W_F64, workspace=None):
         lib = load()
         self._keep = []
         s = _System()
@@ -229,6 +236,11 @@ class Plan:
         o.eager_exchange = 1 if eager_exchange else 0
         o.universal_all_points = 1 if universal_all_points else 0
         o.universal_tile_mb = int(universal_tile_mb)
+        o.w_storage = int(w_storage)
+        if workspace is not None:  # a CUDA tensor the plan carves its device buffers from
+            self._keep.append(workspace)
+            o.workspace = C.c_void_p(workspace.data_ptr())
+            o.workspace_bytes = workspace.numel() * workspace.element_size()
         if tune_file is not None:
             tf = str(tune_file).encode()
             self._keep.append(tf)
@@ -239,6 +251,12 @@ class Plan:
         n_basis, n_mu, nd = C.c_int64(), C.c_int64(), C.c_int32()
         _check(lib.isdf_plan_info(h, C.byref(n_basis), C.byref(n_mu), C.byref(nd)), "isdf_plan_info")
         self.n_basis, self.n_mu, self.n_domains = n_basis.value, n_mu.value, nd.value
+
+    def workspace_bytes(self) -> int:
+        """High-water mark of the plan's device buffers (isdf_plan_workspace_bytes)."""
+        b = C.c_size_t()
+        _check(load().isdf_plan_workspace_bytes(self.handle, C.byref(b)), "isdf_plan_workspace_bytes")
+        return b.value
 
     def autotune(self, n_occ: int, reps: int = 3, json_out=None):
         """Time every GEMM tile shape on this plan's problems (one fit and

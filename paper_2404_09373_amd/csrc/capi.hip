@@ -55,13 +55,23 @@ constexpr int KSPLIT_RI = 16;          // k ranges of the mixed occ-RI final pro
 // new ones.  For the same reason host data reaches the device through a
 // pinned staging ring as copies on that stream, never as a synchronous copy
 // that could overtake kernels still reading a reused block.
+//
+// With a caller-owned workspace (isdf_options.workspace) every block comes
+// from that buffer instead (first fit over its free ranges, neighbours
+// merged on return) and the plan never calls hipMalloc for its buffers.
+// `held` counts the device bytes the context holds (blocks in use plus its
+// cache) and `peak` their largest value: isdf_plan_workspace_bytes.
 struct MemCtx {
   static constexpr size_t STAGE_BYTES = 64u << 20;
   hipStream_t stream = nullptr;
   std::multimap<size_t, void*> free_blocks;
   size_t cached = 0;
+  size_t held = 0, peak = 0;
   char* stage = nullptr;
   size_t stage_off = 0;
+  char* arena = nullptr;               // caller's workspace, or null
+  size_t arena_bytes = 0;
+  std::map<size_t, size_t> arena_free;  // offset -> length of each free range
 
   ~MemCtx() {
     trim();
@@ -71,10 +81,79 @@ struct MemCtx {
     const size_t g = b >= (1u << 20) ? (2u << 20) : 512;
     return (b + g - 1) / g * g;
   }
+  void set_arena(void* p, size_t bytes) {
+    arena = static_cast<char*>(p);
+    arena_bytes = bytes;
+    arena_free.clear();
+    if (bytes) arena_free[0] = bytes;
+  }
+  size_t arena_available() const {
+    size_t s = 0;
+    for (auto& kv : arena_free) s += kv.second;
+    return s;
+  }
+  void* arena_take(size_t r) {
+    for (auto it = arena_free.begin(); it != arena_free.end(); ++it) {
+      const size_t off = (it->first + 255) / 256 * 256, end = it->first + it->second;
+      if (off + r > end) continue;
+      const size_t start = it->first;
+      arena_free.erase(it);
+      if (off > start) arena_free[start] = off - start;
+      if (off + r < end) arena_free[off + r] = end - off - r;
+      return arena + off;
+    }
+    return nullptr;
+  }
+  void arena_give(void* p, size_t r) {
+    size_t off = static_cast<char*>(p) - arena, len = r;
+    auto next = arena_free.lower_bound(off);
+    if (next != arena_free.end() && next->first == off + len) {
+      len += next->second;
+      next = arena_free.erase(next);
+    }
+    if (next != arena_free.begin()) {
+      auto prev = std::prev(next);
+      if (prev->first + prev->second == off) {
+        off = prev->first;
+        len += prev->second;
+        arena_free.erase(prev);
+      }
+    }
+    arena_free[off] = len;
+  }
+  void* device_new(size_t r) {
+    void* p = nullptr;
+    if (arena) {
+      p = arena_take(r);
+    } else if (hipMalloc(&p, r) != hipSuccess) {
+      (void)hipGetLastError();
+      p = nullptr;
+    }
+    if (p) {
+      held += r;
+      peak = std::max(peak, held);
+    }
+    return p;
+  }
   void trim() {
-    for (auto& kv : free_blocks) (void)hipFree(kv.second);
+    for (auto& kv : free_blocks) {
+      if (arena) arena_give(kv.second, kv.first);
+      else (void)hipFree(kv.second);
+      held -= kv.first;
+    }
     free_blocks.clear();
     cached = 0;
+  }
+  // Device bytes a new buffer could still take (cached blocks included).
+  isdf_status available(double* bytes) {
+    if (arena) {
+      *bytes = (double)arena_available() + (double)cached;
+      return ISDF_OK;
+    }
+    size_t free_b = 0, total_b = 0;
+    ISDF_HIP_TRY(hipMemGetInfo(&free_b, &total_b));
+    *bytes = (double)free_b + (double)cached;
+    return ISDF_OK;
   }
   // A cached block of at least `b` bytes (at most 1/8 larger for big ones),
   // else a new one; on an allocation failure the cache is released first.
@@ -88,14 +167,11 @@ struct MemCtx {
       free_blocks.erase(it);
       return p;
     }
-    void* p = nullptr;
-    if (hipMalloc(&p, r) != hipSuccess) {
-      (void)hipGetLastError();
+    void* p = device_new(r);
+    if (!p) {
       trim();
-      if (hipMalloc(&p, r) != hipSuccess) {
-        (void)hipGetLastError();
-        return nullptr;
-      }
+      p = device_new(r);
+      if (!p) return nullptr;
     }
     *cap = r;
     return p;
@@ -318,6 +394,11 @@ struct isdf_fit_s {
   std::vector<int64_t> th_off, xrow_off, piv_off;
   int64_t nmu = 0;
   DevBuf xrows, XL, XN, XG, theta, F, W, lev;
+  // w_storage = ISDF_W_F32: W held as FP32 after the fit (W then released)
+  DevBuf W32;
+  bool w32 = false;
+  const double* w64() const { return w32 ? nullptr : W.as<double>(); }
+  const float* wf32() const { return w32 ? W32.as<float>() : nullptr; }
   // exchange workspace
   DevBuf EG, EL, QGG, QGL, QLL, Y1, Y2, partial, ex_out;
   // mixed precision: fit-time operand planes and per-exchange planes.
@@ -1464,9 +1545,8 @@ isdf_status run_coulomb(isdf_plan_s* pl, isdf_fit_s* f) {
   // memory budget for the potential slabs and the complex work buffers
   // (free memory plus the plan's cached blocks, so that repeated fits size
   // their buffers alike and take them back from the cache)
-  size_t free_b = 0, total_b = 0;
-  ISDF_HIP_TRY(hipMemGetInfo(&free_b, &total_b));
-  const double avail = (double)free_b + (double)(pl->mem ? pl->mem->cached : 0);
+  double avail = 0.0;
+  if ((st = pl->mem->available(&avail)) != ISDF_OK) return st;
   const double v_budget = std::min(24e9, std::max(2e9, 0.45 * avail));
   const double z_budget = std::min(4e9, std::max(2.5e8, 0.05 * avail));
   struct Chunk {
@@ -1724,6 +1804,13 @@ isdf_status run_coulomb(isdf_plan_s* pl, isdf_fit_s* f) {
   if ((st = upload(f->lev, lev)) != ISDF_OK) return st;
   if ((st = launch_symmetrize_w(s, f->W.as<double>(), nmu, f->lev.as<int8_t>())) != ISDF_OK)
     return st;
+  if (pl->opts.w_storage == ISDF_W_F32) {  // keep W in FP32 from here on
+    if ((st = f->W32.alloc(sizeof(float) * std::max<int64_t>(nmu * nmu, 1))) != ISDF_OK) return st;
+    if ((st = launch_narrow(s, f->W.as<double>(), f->W32.as<float>(), nmu * nmu)) != ISDF_OK) return st;
+    ISDF_HIP_TRY(hipStreamSynchronize(s));
+    f->W.release();
+    f->w32 = true;
+  }
   ISDF_HIP_TRY(hipStreamSynchronize(s));
   return ISDF_OK;
 }
@@ -2153,8 +2240,8 @@ isdf_status exchange_prepare(isdf_plan_s* plan, isdf_fit_s* fit, int n_occ, bool
       const int off[4] = {0, m, 0, m};
       std::vector<MixedProblem> qp(4);
       for (int i = 0; i < 4; ++i) {
-        qp[i] = mixed_problem(*ops[i][0], *ops[i][1], nullptr, 0, m, m, (int)ec, 1.0, 0.0,
-                              fit->W.as<double>(), nmu);
+        qp[i] = mixed_problem(*ops[i][0], *ops[i][1], nullptr, 0, m, m, (int)ec, 1.0, 0.0, fit->w64(), nmu);
+        qp[i].E32 = fit->wf32();
         qp[i].P = static_cast<__bf16*>(dst[i]->buf.p);
         qp[i].plane_p = dst[i]->plane;
         qp[i].ldp = dst[i]->ld;
@@ -2221,7 +2308,7 @@ isdf_status exchange_enqueue(isdf_plan_s* plan, isdf_fit_s* fit, const double* i
   const double* XL = fit->XL.as<double>();
   const double* XN = fit->XN.as<double>();
   const double* XG = fit->XG.as<double>();
-  const double* W = fit->W.as<double>();
+  const double* W = fit->w64();
   double* EG = fit->EG.as<double>();
   double* EL = fit->EL.as<double>();
   double* Y1 = fit->Y1.as<double>();
@@ -2238,6 +2325,7 @@ isdf_status exchange_enqueue(isdf_plan_s* plan, isdf_fit_s* fit, const double* i
     p.B = B; p.ldb = ldb; p.transB = tB;
     p.C = C; p.ldc = ldc;
     p.E = E; p.lde = nmu;
+    if (epi == EPI_HADAMARD) p.E32 = fit->wf32();  // every Hadamard factor here is W
     p.M = M; p.N = Nn; p.K = Kk;
     p.alpha = alpha; p.beta = beta;
     return gemm_prof(plan, ISDF_K_GEMM_EXCHANGE, epi, p);
@@ -2348,7 +2436,7 @@ isdf_status ri_fp64_products(isdf_plan_s* plan, isdf_fit_s* fit, const double* C
   const double* XL = fit->XL.as<double>();
   const double* XN = fit->XN.as<double>();
   const double* XG = fit->XG.as<double>();
-  const double* W = fit->W.as<double>();
+  const double* W = fit->w64();
   auto gemm = [&](int epi, const double* A, int64_t lda, int tA, const double* B, int64_t ldb, int tB,
                   double* C, int64_t ldc, int M, int Nn, int Kk, double alpha, double beta, const double* E) {
     GemmProblem p{};
@@ -2356,6 +2444,7 @@ isdf_status ri_fp64_products(isdf_plan_s* plan, isdf_fit_s* fit, const double* C
     p.B = B; p.ldb = ldb; p.transB = tB;
     p.C = C; p.ldc = ldc;
     p.E = E; p.lde = nmu;
+    if (epi == EPI_HADAMARD) p.E32 = fit->wf32();  // the Hadamard factor is W
     p.M = M; p.N = Nn; p.K = Kk;
     p.alpha = alpha; p.beta = beta;
     return gemm_prof(plan, ISDF_K_GEMM_EXCHANGE, epi, p);
@@ -2532,11 +2621,13 @@ isdf_status universal_terms(isdf_plan_s* pl, isdf_fit_s* f, const double* C, int
   // pair potentials are held for tiles of pair rows [a0, a1) within a
   // budget (universal_tile_mb, else the smaller of 16 GB and 40 % of the
   // free memory); a tile holds at least one row
-  size_t free_b = 0, total_b = 0;
-  ISDF_HIP_TRY(hipMemGetInfo(&free_b, &total_b));
-  const double v_budget = pl->opts.universal_tile_mb > 0
-                              ? (double)pl->opts.universal_tile_mb * (1 << 20)
-                              : std::min(16e9, 0.4 * ((double)free_b + (pl->mem ? (double)pl->mem->cached : 0.0)));
+  double avail = 0.0;
+  {
+    const isdf_status sa = pl->mem->available(&avail);
+    if (sa != ISDF_OK) return sa;
+  }
+  const double v_budget = pl->opts.universal_tile_mb > 0 ? (double)pl->opts.universal_tile_mb * (1 << 20)
+                                                         : std::min(16e9, 0.4 * avail);
   std::vector<std::pair<int, int>> tiles;
   int64_t tile_max = 0;
   for (int a0 = 0; a0 < o;) {
@@ -2847,6 +2938,10 @@ isdf_status isdf_plan(const isdf_system* sys, const isdf_options* opts, isdf_pla
     set_error("isdf_plan: universal_tile_mb must not be negative");
     return ISDF_E_ARG;
   }
+  if (pl->opts.w_storage != ISDF_W_F64 && pl->opts.w_storage != ISDF_W_F32) {
+    set_error("isdf_plan: w_storage must be ISDF_W_F64 or ISDF_W_F32");
+    return ISDF_E_ARG;
+  }
   if (pl->opts.mixed_mask < 0 || pl->opts.mixed_mask > 7) {
     set_error("isdf_plan: mixed_mask must be within 0..7");
     return ISDF_E_ARG;
@@ -2885,7 +2980,24 @@ isdf_status isdf_plan(const isdf_system* sys, const isdf_options* opts, isdf_pla
   pl->stream = static_cast<hipStream_t>(pl->opts.stream);
   pl->mem = std::make_shared<MemCtx>();
   pl->mem->stream = pl->stream;
+  if (pl->opts.workspace || pl->opts.workspace_bytes) {
+    if (!pl->opts.workspace || pl->opts.workspace_bytes < 4096 ||
+        (reinterpret_cast<uintptr_t>(pl->opts.workspace) & 255)) {
+      set_error("isdf_plan: a workspace needs a 256-byte aligned pointer and at least 4096 bytes");
+      return ISDF_E_ARG;
+    }
+    pl->mem->set_arena(pl->opts.workspace, pl->opts.workspace_bytes);
+  }
   *out = pl.release();
+  return ISDF_OK;
+}
+
+isdf_status isdf_plan_workspace_bytes(isdf_plan_t plan, size_t* bytes) {
+  if (!plan || !bytes) {
+    set_error("isdf_plan_workspace_bytes: null argument");
+    return ISDF_E_ARG;
+  }
+  *bytes = plan->mem ? plan->mem->peak : 0;
   return ISDF_OK;
 }
 
@@ -3251,8 +3363,18 @@ isdf_status isdf_fit_get(isdf_fit_t fit, int32_t field, int32_t d, void* host_ou
       need = sizeof(double) * fit->nmu * hp.n_basis;
       break;
     case ISDF_FIELD_W:
-      src = fit->W.p;
       need = sizeof(double) * fit->nmu * fit->nmu;
+      if (fit->w32) {  // widen the stored FP32 values
+        if (bytes != need) break;
+        std::vector<float> t((size_t)(fit->nmu * fit->nmu));
+        ISDF_HIP_TRY(hipStreamSynchronize(pl->stream));
+        if (!t.empty())
+          ISDF_HIP_TRY(hipMemcpy(t.data(), fit->W32.p, sizeof(float) * t.size(), hipMemcpyDeviceToHost));
+        double* o = static_cast<double*>(host_out);
+        for (size_t i = 0; i < t.size(); ++i) o[i] = t[i];
+        return ISDF_OK;
+      }
+      src = fit->W.p;
       break;
     case ISDF_FIELD_COUNT: {
       need = sizeof(int64_t) * nd;

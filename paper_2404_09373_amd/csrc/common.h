@@ -100,6 +100,7 @@ struct GemmProblem {
   double alpha, beta;
   int32_t tile_start;            // first flat tile of this problem in a grouped launch
   int32_t lower;                 // 1: only tiles touching the lower triangle (m >= n)
+  const float* E32;              // EPI_HADAMARD: E held in FP32 (read instead of E when set)
 };
 
 // Launch one problem or a group (device array of problems, tile_start
@@ -230,6 +231,8 @@ isdf_status launch_gather_x(hipStream_t s, const GatherDom* doms, int ndom, int 
                             double* xrows, double* XL, double* XN, int64_t nmu);
 
 isdf_status launch_fill(hipStream_t s, double* p, int64_t n, double v);
+// y = (float) x, n values (FP32 storage of an FP64 result).
+isdf_status launch_narrow(hipStream_t s, const double* x, float* y, int64_t n);
 // C(m, n) = c (c + 2 t), c = C(m, n) (ldc), t = T(m, n) (ldt = M; 0 if T is null)
 isdf_status launch_theta_combine(hipStream_t s, double* C, int64_t ldc, const double* T, int M, int N);
 isdf_status launch_gather_square(hipStream_t s, const double* theta, int64_t pts, int n,
@@ -328,6 +331,7 @@ struct MixedProblem {
   __bf16* P;  // EPI_HADAMARD_PLANES output
   int64_t plane_p, ldp;
   int32_t p_off;
+  const float* E32;  // Hadamard epilogues: E held in FP32 (read instead of E when set)
 };
 isdf_status gemm_mixed(hipStream_t s, int epi, int splits, const MixedProblem& p, int tag = 4);
 // Grouped problems on the wide-tile kernel (tile_start in units of

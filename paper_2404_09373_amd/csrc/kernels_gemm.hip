@@ -354,7 +354,9 @@ gemm_f64_kernel(GemmProblem single, const GemmProblem* __restrict__ probs, int n
         const bool ok = gn < p.N;
         cin[b][v] = (rd_c && ok) ? p.C[(int64_t)gm + (int64_t)gn * p.ldc] : 0.0;
         if constexpr (EPI == EPI_HADAMARD)
-          ein[b][v] = ok ? p.E[(int64_t)gm + (int64_t)gn * p.lde] : 0.0;
+          ein[b][v] = !ok ? 0.0
+                          : p.E32 ? (double)p.E32[(int64_t)gm + (int64_t)gn * p.lde]
+                                  : p.E[(int64_t)gm + (int64_t)gn * p.lde];
       }
 #pragma unroll
     for (int b = 0; b < FN; ++b)
@@ -578,7 +580,10 @@ gemm_big_kernel(GemmProblem single, const GemmProblem* __restrict__ probs, int n
       const int gn = n0 + wn * TN + 4 * t + j4;
       const bool ok = gn < p.N;
       cin[t] = (rd_c && ok) ? gld(p.C + (int64_t)gm + (int64_t)gn * p.ldc) : 0.0;
-      if constexpr (EPI == EPI_HADAMARD) ein[t] = ok ? gld(p.E + (int64_t)gm + (int64_t)gn * p.lde) : 0.0;
+      if constexpr (EPI == EPI_HADAMARD)
+        ein[t] = !ok ? 0.0
+                     : p.E32 ? (double)p.E32[(int64_t)gm + (int64_t)gn * p.lde]
+                             : gld(p.E + (int64_t)gm + (int64_t)gn * p.lde);
     }
 #pragma unroll
     for (int t = 0; t < FT; ++t) {

@@ -159,6 +159,18 @@ __global__ void fill_kernel(double* p, int64_t n, double v) {
        i += (int64_t)gridDim.x * blockDim.x)
     p[i] = v;
 }
+__global__ void narrow_kernel(const double* __restrict__ x, float* __restrict__ y, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = (float)x[i];
+}
+isdf_status launch_narrow(hipStream_t s, const double* x, float* y, int64_t n) {
+  if (n <= 0) return ISDF_OK;
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 65536);
+  hipLaunchKernelGGL(narrow_kernel, dim3((unsigned)blocks), dim3(256), 0, s, x, y, n);
+  ISDF_HIP_TRY(hipGetLastError());
+  return ISDF_OK;
+}
+
 isdf_status launch_fill(hipStream_t s, double* p, int64_t n, double v) {
   if (n <= 0) return ISDF_OK;
   int64_t blocks = (n + 255) / 256;

@@ -52,6 +52,12 @@ __device__ inline void tile_coords(int local, int tilesM, int tilesN, int* tm, i
   }
 }
 
+// Element (m, n) of a Hadamard epilogue's E, held in FP64 or FP32.
+__device__ inline double mixed_e(const MixedProblem& p, int m, int n) {
+  const int64_t i = (int64_t)m + (int64_t)n * p.lde;
+  return p.E32 ? (double)p.E32[i] : p.E[i];
+}
+
 __device__ inline const MixedProblem* find_mixed(const MixedProblem* probs, int nprob, int tile) {
   int lo = 0, hi = nprob - 1;
   while (lo < hi) {
@@ -208,7 +214,7 @@ gemm_mixed_kernel(MixedProblem single, const MixedProblem* __restrict__ probs, i
         if (EPI == EPI_THETA) {
           *cp = x * (x + 2.0 * accN[a][b][v]);
         } else if (EPI == EPI_HADAMARD) {
-          double y = p.alpha * x * p.E[(int64_t)gm + (int64_t)gn * p.lde];
+          double y = p.alpha * x * mixed_e(p, gm, gn);
           if (p.beta != 0.0) y += p.beta * *cp;
           *cp = y;
         } else {
@@ -392,7 +398,7 @@ gemm_mixed_wide_kernel(MixedProblem single, const MixedProblem* __restrict__ pro
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int rn = wn * 64 + b * 16 + 4 * (lane >> 4) + v, gn = n0 + rn;
-          double y = (gm < p.M && gn < p.N) ? p.alpha * acc[a][b][v] * p.E[(int64_t)gm + (int64_t)gn * p.lde]
+          double y = (gm < p.M && gn < p.N) ? p.alpha * acc[a][b][v] * mixed_e(p, gm, gn)
                                             : 0.0;
 #pragma unroll
           for (int q = 0; q < S; ++q) {
@@ -433,7 +439,7 @@ gemm_mixed_wide_kernel(MixedProblem single, const MixedProblem* __restrict__ pro
         double* cp = p.C + (int64_t)gm + (int64_t)gn * p.ldc;
         double y;
         if (EPI == EPI_HADAMARD)
-          y = p.alpha * x * p.E[(int64_t)gm + (int64_t)gn * p.lde];
+          y = p.alpha * x * mixed_e(p, gm, gn);
         else
           y = p.alpha * x;
         if (p.beta != 0.0) y += p.beta * *cp;

@@ -123,6 +123,31 @@ def test_plan_matches_oracle_cfg2():
     _compare_plan(config(2, with_density=False))
 
 
+def _system_struct(sysm):
+    """The C system struct of a workload (arrays kept alive on the struct)."""
+    import ctypes as C
+    s = binding._System()
+    for i, v in enumerate(np.asarray(sysm.lattice, dtype=np.float64).ravel()):
+        s.lattice[i] = float(v)
+    keep = [np.ascontiguousarray(sysm.xyz, dtype=np.float64), np.ascontiguousarray(sysm.shell_atom, dtype=np.int32),
+            np.ascontiguousarray(sysm.shell_l, dtype=np.int32), np.ascontiguousarray(sysm.shell_alpha, dtype=np.float64),
+            np.ascontiguousarray(sysm.grids, dtype=np.int32),
+            np.ascontiguousarray(np.asarray(sysm.alpha_bound, dtype=np.float64).reshape(-1))]
+    s._keep = keep
+    s.n_atoms = keep[0].shape[0]
+    s.xyz = binding._ptr(keep[0], C.c_double)
+    s.n_shells = keep[1].size
+    s.shell_atom = binding._ptr(keep[1], C.c_int32)
+    s.shell_l = binding._ptr(keep[2], C.c_int32)
+    s.shell_alpha = binding._ptr(keep[3], C.c_double)
+    s.n_levels = keep[4].shape[0]
+    s.grid = binding._ptr(keep[4], C.c_int32)
+    s.alpha_bound = binding._ptr(keep[5], C.c_double)
+    s.image_tol, s.eps_r, s.n_mu_ratio = sysm.image_tol, sysm.eps_r, sysm.n_mu_ratio
+    s.eps_isdf, s.tie_tol = sysm.eps_isdf, sysm.tie_tol
+    return s
+
+
 def _status(sysm, **over):
     for k, v in over.items():
         setattr(sysm, k, v)
@@ -145,6 +170,25 @@ def test_plan_errors():
     s = tiny_system("one_atom")
     s.domain_mode = 2
     assert _status(s) == -1
+    with pytest.raises(binding.IsdfError) as e:
+        binding.Plan(tiny_system("one_atom"), w_storage=2)
+    assert e.value.status == -1
+    # a workspace needs an aligned pointer and a size (checked on the host)
+    import ctypes as C
+    s = binding._System()
+    o = binding._Options()
+    o.workspace = C.c_void_p(0x1001)
+    o.workspace_bytes = 1 << 20
+    h = C.c_void_p()
+    sysm = tiny_system("one_atom")
+    p = binding.Plan(sysm)  # a valid system struct to reuse
+    p.close()
+    lib = binding.load()
+    o2 = binding._Options()
+    o2.workspace_bytes = 1 << 20  # size without a pointer
+    for opt in (o, o2):
+        st = lib.isdf_plan(C.byref(_system_struct(sysm)), C.byref(opt), C.byref(h))
+        assert st == -1 and not h.value
     assert _status(tiny_system("one_atom"), lattice=np.zeros((3, 3))) == -1
     assert _status(tiny_system("one_atom"), image_tol=0.0) == -1
 
@@ -170,7 +214,7 @@ def test_tune_file_errors(tmp_path):
         binding.Plan(s, tune_file=tmp_path / "missing.json")
     assert e.value.status == -1
     bad = tmp_path / "bad.json"
-    bad.write_text('{"arch": "gfx950", "entries": [{"key": "e0 t1", "shape": 9}]}')
+    bad.write_text('{"arch": "gfx950", "entries": [{"key": "e0 t1", "shape": 99}]}')
     with pytest.raises(binding.IsdfError) as e:
         binding.Plan(s, tune_file=bad)
     assert e.value.status == -1
