@@ -56,13 +56,21 @@ def run(sysm, pinned: Optional[List[np.ndarray]] = None, domains=None,
         times["diag"] += time.perf_counter() - t
         diag_list.append(dg)
         t = time.perf_counter()
+        all_pts = pinned is None and dom.n_mu >= dom.points.size
         if pinned is not None:
             piv = np.asarray(pinned[d], dtype=np.int64)
+        elif all_pts:
+            # every point of the domain requested: the points themselves are
+            # the interpolation points and F = I (no selection, no solve)
+            piv = np.arange(dom.points.size, dtype=np.int64)
         else:
             piv, _, _, _ = isdf.pivoted_cholesky(Phi, nL, dom.n_mu, sysm.eps_isdf, sysm.tie_tol)
         times["select"] += time.perf_counter() - t
         t = time.perf_counter()
-        F, _, _ = isdf.fit_functions(Phi, nL, piv)
+        if all_pts:
+            F = np.eye(dom.points.size)
+        else:
+            F, _, _ = isdf.fit_functions(Phi, nL, piv)
         times["fit"] += time.perf_counter() - t
         piv_list.append(piv)
         F_list.append(F)

@@ -346,3 +346,20 @@ def test_domain_mode_full_cell_plan_and_exact_limit():
     s.n_mu_ratio = 80.0
     r = pipeline.run(s)
     assert np.max(np.abs(r.K - Kt)) <= 1e-8 * np.max(np.abs(Kt))
+
+
+# ------------------------------------------- every domain point requested
+def test_all_points_domain_is_identity_fit():
+    """A domain asked for at least as many points as it has takes all of
+    them in ascending order with F = I (the paper's all-points universal
+    grid).  The fitted pair densities are then exact on the grid, so with
+    enough window points the ISDF exchange equals the brute-force one."""
+    s = tiny_system("d_atom", grids=((6, 6, 6), (24, 24, 24)), n_occ=3)
+    s.n_mu_ratio = 400.0
+    p = oplan.build_plan(s)
+    assert p.domains[0].n_mu == p.domains[0].points.size == 216
+    r = pipeline.run(s)
+    assert np.array_equal(r.pivots[0], np.arange(216))
+    assert np.array_equal(r.F[0], np.eye(216))
+    Kt, _ = brute.exchange_tensor_route(p, s.D)
+    assert np.max(np.abs(r.K - Kt)) <= 1e-8 * np.max(np.abs(Kt))
