@@ -56,7 +56,9 @@ def run(sysm, pinned: Optional[List[np.ndarray]] = None, domains=None,
         times["diag"] += time.perf_counter() - t
         diag_list.append(dg)
         t = time.perf_counter()
-        all_pts = pinned is None and dom.n_mu >= dom.points.size
+        # a count-driven domain (ratio > 0) capped at its point count; in the
+        # threshold-only mode the cap is an upper limit and eps_isdf stops it
+        all_pts = pinned is None and sysm.n_mu_ratio > 0 and dom.n_mu >= dom.points.size
         if pinned is not None:
             piv = np.asarray(pinned[d], dtype=np.int64)
         elif all_pts:

@@ -363,3 +363,22 @@ def test_all_points_domain_is_identity_fit():
     assert np.array_equal(r.F[0], np.eye(216))
     Kt, _ = brute.exchange_tensor_route(p, s.D)
     assert np.max(np.abs(r.K - Kt)) <= 1e-8 * np.max(np.abs(Kt))
+
+
+def test_threshold_mode_cap_still_selects():
+    """In the threshold-only mode (ratio <= 0) the cap n_mu_d = points is an
+    upper limit, not a request for every point: the capped universal domain
+    of this cell is still selected greedily, its first pivot the tie-rule
+    argmax of the Gram diagonal, not the first grid point."""
+    s = tiny_system("d_two", grids=((4, 4, 4), (24, 24, 24)), n_occ=3)
+    s.n_mu_ratio = 0.0
+    s.eps_isdf = 1e-6
+    p = oplan.build_plan(s)
+    dom = p.domains[0]
+    assert dom.n_mu == dom.points.size == 64 and dom.N.size == 0
+    r = pipeline.run(s)
+    Phi = basis.domain_values(p, dom)
+    dg = np.sum(Phi ** 2, axis=1) ** 2  # a_L (a_L + 2 a_N) with N empty
+    first = int(np.min(np.nonzero(dg >= (1.0 - s.tie_tol) * dg.max())[0]))
+    assert r.pivots[0][0] == first != 0
+    assert not np.array_equal(r.pivots[0], np.arange(r.pivots[0].size))
