@@ -144,6 +144,19 @@ typedef struct {
                                  wide FFT twiddle tables and the 64 MB pinned host staging
                                  ring are not part of it.)                                */
   size_t workspace_bytes;
+  int32_t phi_budget_mb;      /* most MB of basis values (Phi of Eq. (Theta)) held at once.
+                                 When the domains' Phi exceeds it, the fit runs over
+                                 consecutive domain groups that fit it, evaluating the
+                                 basis twice (selection pass, then the pass that gathers
+                                 X and forms Theta and F) and keeps no Phi afterwards
+                                 (ISDF_FIELD_PHI then returns ISDF_E_STATE); the results
+                                 are those of the one-pass fit.  0: 40 % of the free
+                                 memory                                                   */
+  int32_t ri_rows;            /* rows of Q = W o (E E^T) that isdf_exchange_occ_ri holds
+                                 at once (row blocks of Z1, Z2; the result does not
+                                 depend on it).  0: all N_mu rows when they fit half of
+                                 the free memory, else blocks of a multiple of 256 rows
+                                 that fit 40 % of it                                      */
 } isdf_options;
 /* Storage of the Coulomb metric W held by a fit. */
 enum { ISDF_W_F64 = 0, ISDF_W_F32 = 1 };
@@ -201,9 +214,14 @@ isdf_status isdf_plan_domain_functions(isdf_plan_t plan, int32_t d, int32_t* fun
 /* Fit (interpolative decomposition + Coulomb metric), once per geometry
  * (section "Using multiple grids for exchange", item 1).  Allocates the
  * fit's device buffers, runs every stage on the plan's stream and
- * synchronises.  Errors: ISDF_E_NOMEM, ISDF_E_HIP, ISDF_E_NOT_SPD (a local
- * interpolation metric failed its Cholesky), ISDF_E_RANK (a domain stopped
- * early by eps_isdf while n_mu_ratio > 0; the fit is still usable). */
+ * synchronises.  With n_mu_ratio > 0, a domain whose requested count
+ * n_mu_d equals its point count (the cap of the n_mu rule) takes every
+ * point, in ascending order, with F_d = I: its pair densities are then
+ * exact on the grid, no selection or solve runs and its Theta is not
+ * formed (ISDF_FIELD_THETA gives zeros).
+ * Errors: ISDF_E_NOMEM, ISDF_E_HIP, ISDF_E_NOT_SPD (a local interpolation
+ * metric failed its Cholesky), ISDF_E_RANK (a domain stopped early by
+ * eps_isdf while n_mu_ratio > 0; the fit is still usable). */
 isdf_status isdf_fit(isdf_plan_t plan, isdf_fit_t* out);
 
 /* Fits of several plans (independent cells of a batch) at once: up to

@@ -101,6 +101,8 @@ class _Options(C.Structure):
         ("pad1", C.c_int32),
         ("workspace", C.c_void_p),
         ("workspace_bytes", C.c_size_t),
+        ("phi_budget_mb", C.c_int32),
+        ("ri_rows", C.c_int32),
     ]
 
 
@@ -190,7 +192,8 @@ class Plan:
                  w_batch: int = 0, mlp_weights=None, mlp_keep: float = 2.0,
                  mlp_cutoff: float = 0.05, mixed_mask: int = 0, eager_exchange: bool = False,
                  tune_file=None, universal_all_points: bool = False, universal_tile_mb: int = 0,
-                 w_storage: int = W_F64, workspace=None):
+                 w_storage: int = W_F64, workspace=None, phi_budget_mb: int = 0,
+                 ri_rows: int = 0):
         lib = load()
         self._keep = []
         s = _System()
@@ -237,6 +240,8 @@ class Plan:
         o.universal_all_points = 1 if universal_all_points else 0
         o.universal_tile_mb = int(universal_tile_mb)
         o.w_storage = int(w_storage)
+        o.phi_budget_mb = int(phi_budget_mb)
+        o.ri_rows = int(ri_rows)
         if workspace is not None:  # a CUDA tensor the plan carves its device buffers from
             self._keep.append(workspace)
             o.workspace = C.c_void_p(workspace.data_ptr())

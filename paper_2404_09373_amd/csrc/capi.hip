@@ -347,6 +347,7 @@ struct isdf_plan_s {
   std::vector<float> mlp_w;
   int ntiles_basis = 0;
   std::vector<int64_t> pts_off, phi_off, func_off;
+  std::vector<int> tile_off;  // first basis tile of each domain (n_domains + 1 entries)
   int64_t phi_total = 0, pts_total = 0;
   // per domain: cyclic box of its points on its grid (x0, y0, z0, ex, ey,
   // ez) and the offset of its box -> point map in d_boxmap (-1: all points)
@@ -394,6 +395,8 @@ struct isdf_fit_s {
   std::vector<int64_t> th_off, xrow_off, piv_off;
   int64_t nmu = 0;
   DevBuf xrows, XL, XN, XG, theta, F, W, lev;
+  bool phi_streamed = false;  // basis values evaluated per domain group and not kept
+  int groups = 1;
   // w_storage = ISDF_W_F32: W held as FP32 after the fit (W then released)
   DevBuf W32;
   bool w32 = false;
@@ -409,6 +412,11 @@ struct isdf_fit_s {
   Planes Dp, EGp, ELp, Q1, Q2, Y12;
   DevBuf Kpart, d_yprobs, d_kprobs, d_qprobs;
   int ytiles = 0, ktiles = 0, kparts = 0, qprobs_nocc = -1;
+  bool ydense = false;  // Y12, Kpart and their problem tables built
+  // rows of Q held at once (Q1/Q2 planes or the FP64 Q buffers): N_mu, or a
+  // row block of the occ-RI exchange (then QLG holds Q_GL^T's rows)
+  int64_t q_rows = 0;
+  DevBuf QLG;
   // occ-RI output (K C): E_N = X^N C, Z1 = [Q_GG Q_GL][E_L; E_N],
   // Z2 = [Q_GL^T Q_LL][E_L; E_N] (N_mu x n_occ); mixed: ELN (row i = [E_L(:, i);
   // E_N(:, i)]) and Z12 (row i = [Z1(:, i); Z2(:, i)]) planes, and (K C)^T =
@@ -656,6 +664,7 @@ isdf_status upload_plan(isdf_plan_s* pl) {
   pl->pts_off.clear();
   pl->phi_off.clear();
   pl->func_off.clear();
+  pl->tile_off.clear();
   int64_t phi_off = 0;
   for (size_t d = 0; d < hp.domains.size(); ++d) {
     const HostDomain& D = hp.domains[d];
@@ -681,9 +690,11 @@ isdf_status upload_plan(isdf_plan_s* pl) {
     pl->func_off.push_back((int64_t)funcs.size());
     points.insert(points.end(), D.points.begin(), D.points.end());
     funcs.insert(funcs.end(), D.funcs.begin(), D.funcs.end());
+    pl->tile_off.push_back((int)tiles.size());
     for (int st = 0; st < dd.pts; st += 256) tiles.push_back(BasisTile{(int)d, st});
     phi_off += (int64_t)dd.pts * dd.nG;
   }
+  pl->tile_off.push_back((int)tiles.size());
   pl->phi_total = phi_off;
   pl->pts_total = (int64_t)points.size();
   pl->ntiles_basis = (int)tiles.size();
@@ -765,6 +776,7 @@ struct SelSpec {
   int level;
   int pts, nG, nL, n_mu;
   int64_t phi_off, diag_off;
+  int lone;  // the plan's only domain on its level (blocked selection above RL_MIN_PIVOTS)
 };
 
 // Greedy pivoted Cholesky of every spec domain, one batch per level.  Writes
@@ -1041,11 +1053,7 @@ isdf_status select_points(isdf_plan_s* pl, const std::vector<SelSpec>& spec,
   // the candidate-restricted blocked selection (crb_select); the others are
   // batched per level, left-looking, one pick and one column launch a step.
   std::vector<char> blocked(nd, 0);
-  for (int d = 0; d < nd; ++d) {
-    int nlev = 0;
-    for (int e = 0; e < nd; ++e) nlev += spec[e].level == spec[d].level;
-    blocked[d] = nlev == 1 && sd[d].n_mu > RL_MIN_PIVOTS;
-  }
+  for (int d = 0; d < nd; ++d) blocked[d] = spec[d].lone && sd[d].n_mu > RL_MIN_PIVOTS;
   DevBuf lfac, prow, tmax, tidx, state, d_sd, d_tile_dom;
   if ((st = upload(d_sd, sd)) != ISDF_OK) return st;
   if ((st = upload(d_tile_dom, tile_dom)) != ISDF_OK) return st;
@@ -1115,11 +1123,14 @@ isdf_status select_points(isdf_plan_s* pl, const std::vector<SelSpec>& spec,
   return ISDF_OK;
 }
 
-// Features of every point of every domain (learned selector input).
-isdf_status compute_features(isdf_plan_s* pl, isdf_fit_s* f, float* feats) {
+// Features of every point of domains [g0, g1) (learned selector input),
+// at their global point offsets in feats (16 per point).
+isdf_status compute_features(isdf_plan_s* pl, isdf_fit_s* f, float* feats, int g0 = 0, int g1 = -1) {
   HostPlan& hp = pl->hp;
   hipStream_t s = pl->stream;
   const int nd = (int)hp.domains.size();
+  if (g1 < 0) g1 = nd;
+  if (g1 <= g0) return ISDF_OK;
   MlpGeom g{};
   for (int i = 0; i < 9; ++i) {
     g.lat[i] = hp.lattice[i];
@@ -1161,20 +1172,44 @@ isdf_status compute_features(isdf_plan_s* pl, isdf_fit_s* f, float* feats) {
   DevBuf d_md, d_atoms;
   if ((st = upload(d_md, md)) != ISDF_OK) return st;
   if ((st = upload(d_atoms, hp.xyz)) != ISDF_OK) return st;
-  if ((st = launch_diag_stats(s, d_md.as<MlpDomain>(), nd, f->diag0.as<double>())) != ISDF_OK) return st;
+  if ((st = launch_diag_stats(s, d_md.as<MlpDomain>() + g0, g1 - g0, f->diag0.as<double>())) != ISDF_OK)
+    return st;
   if ((st = launch_features(s, g, d_md.as<MlpDomain>(), pl->d_points.as<int32_t>(),
-                            pl->d_tiles.as<BasisTile>(), pl->ntiles_basis, f->aux.as<double>(),
-                            f->diag0.as<double>(), d_atoms.as<double>(), feats)) != ISDF_OK)
+                            pl->d_tiles.as<BasisTile>() + pl->tile_off[g0], pl->tile_off[g1] - pl->tile_off[g0],
+                            f->aux.as<double>(), f->diag0.as<double>(), d_atoms.as<double>(), feats)) != ISDF_OK)
     return st;
   ISDF_HIP_TRY(hipStreamSynchronize(s));
   return ISDF_OK;
 }
 
 // Selection for a fit.  mode[d]: 0 full, 1 candidates from the learned
-// scores, 2 candidates given by the caller (cand_in).
-isdf_status run_selection(isdf_plan_s* pl, isdf_fit_s* f, const int64_t* pinned,
-                          const std::vector<int>& mode, const int64_t* cand_in,
-                          const int64_t* ncand_in) {
+// scores, 2 candidates given by the caller (cand_in), 3 every point of the
+// domain (n_mu_d equals its point count: pivots 0..pts-1, F = I).
+// sel_setup sizes the per-domain state and handles what needs no basis
+// values (pinned points, all-point domains, the caller's candidate lists);
+// sel_group then selects domains [g0, g1) from their basis values at
+// phi_base + phi_off[d] (the whole pool, or one domain group of it).
+struct SelCtx {
+  DevBuf cand;         // candidate lists, at pts_off[d] for domain d
+  DevBuf feats, z;     // learned selector: features and scores of every point
+  std::vector<int32_t> nc_host;
+  bool pinned = false, any_cand = false, any_learned = false;
+};
+
+int lone_on_level(const HostPlan& hp, int d) {
+  int n = 0;
+  for (const HostDomain& D : hp.domains) n += D.level == hp.domains[d].level;
+  return n == 1;
+}
+
+SelSpec full_spec(isdf_plan_s* pl, int d) {
+  const HostDomain& D = pl->hp.domains[d];
+  return SelSpec{D.level, (int)D.points.size(), (int)D.funcs.size(), D.nL, D.n_mu,
+                 pl->phi_off[d], pl->pts_off[d], lone_on_level(pl->hp, d)};
+}
+
+isdf_status sel_setup(isdf_plan_s* pl, isdf_fit_s* f, SelCtx& cx, const int64_t* pinned,
+                      const std::vector<int>& mode, const int64_t* cand_in, const int64_t* ncand_in) {
   HostPlan& hp = pl->hp;
   hipStream_t s = pl->stream;
   const int nd = (int)hp.domains.size();
@@ -1192,6 +1227,7 @@ isdf_status run_selection(isdf_plan_s* pl, isdf_fit_s* f, const int64_t* pinned,
   f->dfinal.assign(nd, 0.0);
   f->fallback.assign(nd, 0);
   if (pinned) {
+    cx.pinned = true;
     std::vector<int32_t> hp_piv(pv);
     int64_t o = 0;
     for (int d = 0; d < nd; ++d) {
@@ -1212,45 +1248,33 @@ isdf_status run_selection(isdf_plan_s* pl, isdf_fit_s* f, const int64_t* pinned,
       }
       f->count[d] = hp.domains[d].n_mu;
     }
-    if ((st = copy_in(f->piv.p, hp_piv.data(), sizeof(int32_t) * pv)) != ISDF_OK) return st;
-    return ISDF_OK;
+    return copy_in(f->piv.p, hp_piv.data(), sizeof(int32_t) * pv);
   }
-  // full-mode domains
-  std::vector<SelSpec> full;
-  std::vector<int> full_id;
-  std::vector<int64_t> full_poff;
-  for (int d = 0; d < nd; ++d) {
-    if (mode[d] != 0 || hp.domains[d].n_mu == 0) continue;  // no points requested: count stays 0
-    const HostDomain& D = hp.domains[d];
-    full.push_back(SelSpec{D.level, (int)D.points.size(), (int)D.funcs.size(), D.nL, D.n_mu,
-                           pl->phi_off[d], pl->pts_off[d]});
-    full_id.push_back(d);
-    full_poff.push_back(f->piv_off[d]);
-  }
-  std::vector<int> cnt;
-  std::vector<double> dl;
-  if (!full.empty()) {
-    if ((st = select_points(pl, full, f->phi.as<double>(), f->dwork.as<double>(), f->piv.as<int32_t>(),
-                            full_poff, cnt, dl)) != ISDF_OK)
-      return st;
-    for (size_t i = 0; i < full.size(); ++i) {
-      f->count[full_id[i]] = cnt[i];
-      f->dlast[full_id[i]] = dl[i];
-      f->ncand[full_id[i]] = full[i].pts;
+  // all-point domains: the pivots are the points themselves
+  {
+    std::vector<int32_t> iota;
+    for (int d = 0; d < nd; ++d) {
+      if (mode[d] != 3) continue;
+      const int np = (int)hp.domains[d].points.size();
+      iota.resize(np);
+      for (int i = 0; i < np; ++i) iota[i] = i;
+      if ((st = copy_in(f->piv.as<int32_t>() + f->piv_off[d], iota.data(), sizeof(int32_t) * np)) != ISDF_OK)
+        return st;
+      f->count[d] = np;
+      f->ncand[d] = np;
     }
   }
-  // candidate-mode domains
-  std::vector<int> cid;
-  for (int d = 0; d < nd; ++d)
-    if (mode[d] != 0) cid.push_back(d);
-  if (cid.empty()) return ISDF_OK;
-  DevBuf cand;  // candidate lists, at pts_off[d] for domain d
-  if ((st = cand.alloc(sizeof(int32_t) * std::max<int64_t>(pl->pts_total, 1))) != ISDF_OK) return st;
+  cx.nc_host.assign(nd, 0);
+  for (int d = 0; d < nd; ++d) {
+    if (mode[d] == 1 || mode[d] == 2) cx.any_cand = true;
+    if (mode[d] == 1) cx.any_learned = true;
+  }
+  if (!cx.any_cand) return ISDF_OK;
+  if ((st = cx.cand.alloc(sizeof(int32_t) * std::max<int64_t>(pl->pts_total, 1))) != ISDF_OK) return st;
   if ((st = f->cflag.alloc(std::max<int64_t>(pl->pts_total, 1))) != ISDF_OK) return st;
   ISDF_HIP_TRY(hipMemsetAsync(f->cflag.p, 1, pl->pts_total, s));
-  std::vector<int32_t> nc_host(nd, 0);
-  bool any_learned = false, any_given = false;
-  for (int d : cid) (mode[d] == 1 ? any_learned : any_given) = true;
+  bool any_given = false;
+  for (int d = 0; d < nd; ++d) any_given |= mode[d] == 2;
   if (any_given) {
     std::vector<int32_t> hc(std::max<int64_t>(pl->pts_total, 1), 0);
     std::vector<uint8_t> hf(std::max<int64_t>(pl->pts_total, 1), 1);
@@ -1273,20 +1297,66 @@ isdf_status run_selection(isdf_plan_s* pl, isdf_fit_s* f, const int64_t* pinned,
           hc[pl->pts_off[d] + i] = (int32_t)v;
           hf[pl->pts_off[d] + v] = 1;
         }
-        nc_host[d] = (int32_t)n;
+        cx.nc_host[d] = (int32_t)n;
       }
       o += std::max<int64_t>(n, 0);
     }
-    if ((st = copy_in(cand.p, hc.data(), sizeof(int32_t) * hc.size())) != ISDF_OK) return st;
+    if ((st = copy_in(cx.cand.p, hc.data(), sizeof(int32_t) * hc.size())) != ISDF_OK) return st;
     if ((st = copy_in(f->cflag.p, hf.data(), hf.size())) != ISDF_OK) return st;
   }
-  if (any_learned) {
-    DevBuf feats, z, d_cd, d_nc, d_w;
-    if ((st = feats.alloc(sizeof(float) * 16 * pl->pts_total)) != ISDF_OK) return st;
-    if ((st = z.alloc(sizeof(float) * pl->pts_total)) != ISDF_OK) return st;
-    if ((st = compute_features(pl, f, feats.as<float>())) != ISDF_OK) return st;
-    if ((st = launch_mlp_forward(s, pl->d_mlp_w.as<float>(), feats.as<float>(), pl->pts_total,
-                                 z.as<float>())) != ISDF_OK)
+  if (cx.any_learned) {
+    if ((st = cx.feats.alloc(sizeof(float) * 16 * std::max<int64_t>(pl->pts_total, 1))) != ISDF_OK) return st;
+    if ((st = cx.z.alloc(sizeof(float) * std::max<int64_t>(pl->pts_total, 1))) != ISDF_OK) return st;
+  }
+  return ISDF_OK;
+}
+
+isdf_status sel_group(isdf_plan_s* pl, isdf_fit_s* f, SelCtx& cx, const std::vector<int>& mode, int g0, int g1,
+                      const double* phi_base) {
+  HostPlan& hp = pl->hp;
+  hipStream_t s = pl->stream;
+  isdf_status st;
+  if (cx.pinned) return ISDF_OK;
+  // full-mode domains
+  std::vector<SelSpec> full;
+  std::vector<int> full_id;
+  std::vector<int64_t> full_poff;
+  for (int d = g0; d < g1; ++d) {
+    if (mode[d] != 0 || hp.domains[d].n_mu == 0) continue;  // no points requested: count stays 0
+    full.push_back(full_spec(pl, d));
+    full_id.push_back(d);
+    full_poff.push_back(f->piv_off[d]);
+  }
+  std::vector<int> cnt;
+  std::vector<double> dl;
+  if (!full.empty()) {
+    if ((st = select_points(pl, full, phi_base, f->dwork.as<double>(), f->piv.as<int32_t>(), full_poff, cnt,
+                            dl)) != ISDF_OK)
+      return st;
+    for (size_t i = 0; i < full.size(); ++i) {
+      f->count[full_id[i]] = cnt[i];
+      f->dlast[full_id[i]] = dl[i];
+      f->ncand[full_id[i]] = full[i].pts;
+    }
+  }
+  // candidate-mode domains
+  std::vector<int> cid;
+  bool learned = false;
+  for (int d = g0; d < g1; ++d)
+    if (mode[d] == 1 || mode[d] == 2) {
+      cid.push_back(d);
+      learned |= mode[d] == 1;
+    }
+  if (cid.empty()) {
+    ISDF_HIP_TRY(hipStreamSynchronize(s));
+    return ISDF_OK;
+  }
+  int32_t* cand = cx.cand.as<int32_t>();
+  if (learned) {
+    const int64_t p0 = pl->pts_off[g0], p1 = g1 < (int)hp.domains.size() ? pl->pts_off[g1] : pl->pts_total;
+    if ((st = compute_features(pl, f, cx.feats.as<float>(), g0, g1)) != ISDF_OK) return st;
+    if ((st = launch_mlp_forward(s, pl->d_mlp_w.as<float>(), cx.feats.as<float>() + 16 * p0, p1 - p0,
+                                 cx.z.as<float>() + p0)) != ISDF_OK)
       return st;
     std::vector<CandDomain> cd;
     std::vector<int> cd_id;
@@ -1302,18 +1372,18 @@ isdf_status run_selection(isdf_plan_s* pl, isdf_fit_s* f, const int64_t* pinned,
       cd.push_back(c);
       cd_id.push_back(d);
     }
+    DevBuf d_cd, d_nc;
     if ((st = upload(d_cd, cd)) != ISDF_OK) return st;
     if ((st = d_nc.alloc(sizeof(int32_t) * cd.size())) != ISDF_OK) return st;
     const double pc = std::min(std::max(pl->opts.mlp_cutoff, 1e-30), 1.0 - 1e-7);
     const float zcut = (float)std::log(pc / (1.0 - pc));  // logit of the score cutoff
-    if ((st = launch_topk_compact(s, d_cd.as<CandDomain>(), (int)cd.size(), z.as<float>(), zcut,
-                                  cand.as<int32_t>(), d_nc.as<int32_t>(),
-                                  f->cflag.as<uint8_t>())) != ISDF_OK)
+    if ((st = launch_topk_compact(s, d_cd.as<CandDomain>(), (int)cd.size(), cx.z.as<float>(), zcut, cand,
+                                  d_nc.as<int32_t>(), f->cflag.as<uint8_t>())) != ISDF_OK)
       return st;
     std::vector<int32_t> nc(cd.size());
     ISDF_HIP_TRY(hipMemcpyAsync(nc.data(), d_nc.p, sizeof(int32_t) * nc.size(), hipMemcpyDeviceToHost, s));
     ISDF_HIP_TRY(hipStreamSynchronize(s));
-    for (size_t i = 0; i < cd.size(); ++i) nc_host[cd_id[i]] = nc[i];
+    for (size_t i = 0; i < cd.size(); ++i) cx.nc_host[cd_id[i]] = nc[i];
   }
   // compact candidate rows, select on them, map pivots back
   std::vector<GatherRows> gr;
@@ -1331,9 +1401,9 @@ isdf_status run_selection(isdf_plan_s* pl, isdf_fit_s* f, const int64_t* pinned,
     g.cand_off = pl->pts_off[d];
     g.pts = (int)D.points.size();
     g.nG = (int)D.funcs.size();
-    g.nc = nc_host[d];
+    g.nc = cx.nc_host[d];
     gr.push_back(g);
-    cs.push_back(SelSpec{D.level, g.nc, g.nG, D.nL, std::min(D.n_mu, g.nc), phic, dgc});
+    cs.push_back(SelSpec{D.level, g.nc, g.nG, D.nL, std::min(D.n_mu, g.nc), phic, dgc, lone_on_level(hp, d)});
     cpoff.push_back(pvc);
     phic += (int64_t)g.nc * g.nG;
     dgc += g.nc;
@@ -1346,18 +1416,17 @@ isdf_status run_selection(isdf_plan_s* pl, isdf_fit_s* f, const int64_t* pinned,
   if ((st = phic_b.alloc(sizeof(double) * std::max<int64_t>(phic, 1))) != ISDF_OK) return st;
   if ((st = diagc_b.alloc(sizeof(double) * std::max<int64_t>(dgc, 1))) != ISDF_OK) return st;
   if ((st = pivc.alloc(sizeof(int32_t) * std::max<int64_t>(pvc, 1))) != ISDF_OK) return st;
-  if ((st = launch_gather_rows(s, d_gr.as<GatherRows>(), (int)gr.size(), max_nc, f->phi.as<double>(),
-                               f->diag0.as<double>(), cand.as<int32_t>(), phic_b.as<double>(),
-                               diagc_b.as<double>())) != ISDF_OK)
+  if ((st = launch_gather_rows(s, d_gr.as<GatherRows>(), (int)gr.size(), max_nc, phi_base, f->diag0.as<double>(),
+                               cand, phic_b.as<double>(), diagc_b.as<double>())) != ISDF_OK)
     return st;
-  if ((st = select_points(pl, cs, phic_b.as<double>(), diagc_b.as<double>(), pivc.as<int32_t>(), cpoff,
-                          cnt, dl)) != ISDF_OK)
+  if ((st = select_points(pl, cs, phic_b.as<double>(), diagc_b.as<double>(), pivc.as<int32_t>(), cpoff, cnt,
+                          dl)) != ISDF_OK)
     return st;
   for (size_t i = 0; i < cid.size(); ++i) {
     const int d = cid[i];
     f->count[d] = cnt[i];
     f->dlast[d] = dl[i];
-    if ((st = launch_map_pivots(s, cand.as<int32_t>(), pl->pts_off[d], pivc.as<int32_t>() + cpoff[i],
+    if ((st = launch_map_pivots(s, cand, pl->pts_off[d], pivc.as<int32_t>() + cpoff[i],
                                 f->piv.as<int32_t>() + f->piv_off[d], cnt[i])) != ISDF_OK)
       return st;
   }
@@ -1388,16 +1457,14 @@ isdf_status run_selection(isdf_plan_s* pl, isdf_fit_s* f, const int64_t* pinned,
     if (exact && !short_of_points) continue;
     f->fallback[d] = 1;
     if (mode[d] != 1) continue;  // caller-given candidates: report only
-    const HostDomain& D = hp.domains[d];
-    redo.push_back(SelSpec{D.level, (int)D.points.size(), (int)D.funcs.size(), D.nL, D.n_mu,
-                           pl->phi_off[d], pl->pts_off[d]});
+    redo.push_back(full_spec(pl, d));
     redo_id.push_back(d);
     redo_poff.push_back(f->piv_off[d]);
   }
   if (!redo.empty()) {
     // dwork still holds the untouched initial diagonals of these domains
-    if ((st = select_points(pl, redo, f->phi.as<double>(), f->dwork.as<double>(), f->piv.as<int32_t>(),
-                            redo_poff, cnt, dl)) != ISDF_OK)
+    if ((st = select_points(pl, redo, phi_base, f->dwork.as<double>(), f->piv.as<int32_t>(), redo_poff, cnt,
+                            dl)) != ISDF_OK)
       return st;
     for (size_t i = 0; i < redo.size(); ++i) {
       f->count[redo_id[i]] = cnt[i];
@@ -1598,7 +1665,8 @@ isdf_status run_coulomb(isdf_plan_s* pl, isdf_fit_s* f) {
       std::vector<GemmProblem> lp_probs;
       const double dV = hp.volume / (double)level_ng(hp, l);
       for (int d = 0; d < nd; ++d) {
-        if (hp.domains[d].level != l || f->count[d] == 0) continue;
+        // all-point domains (F = I) take their rows of the potentials as they are
+        if (hp.domains[d].level != l || f->count[d] == 0 || f->mode[d] == 3) continue;
         const HostDomain& D = hp.domains[d];
         GemmProblem p{};
         p.A = f->F.as<double>() + f->th_off[d];
@@ -1644,7 +1712,7 @@ isdf_status run_coulomb(isdf_plan_s* pl, isdf_fit_s* f) {
   // mixed precision for the universal rows (the level-0 row block has one
   // domain whose points are the whole grid, so no row gather is involved)
   const bool w_mixed = mixed_on(pl, ISDF_MIX_W) && nd > 0 && hp.domains[0].atom < 0 &&
-                       hp.domains[0].level == 0 && f->count[0] > 0;
+                       hp.domains[0].level == 0 && f->count[0] > 0 && f->mode[0] != 3;
   Planes Fp0, Vp0;
   if (w_mixed) {
     const int64_t pts0 = (int64_t)hp.domains[0].points.size();
@@ -1775,6 +1843,23 @@ isdf_status run_coulomb(isdf_plan_s* pl, isdf_fit_s* f) {
                                   hp.volume / (double)ng0)) != ISDF_OK)
         return st;
     }
+    {  // rows of all-point domains: W(xi_i, xi') = dV V_xi'(R_i)
+      int64_t voff = 0;
+      for (int l = 0; l <= lp; ++l) {
+        const int64_t ng = level_ng(hp, l);
+        for (int d = 0; d < nd; ++d) {
+          if (hp.domains[d].level != l || f->count[d] == 0 || f->mode[d] != 3) continue;
+          const HostDomain& D = hp.domains[d];
+          const bool whole = (int64_t)D.points.size() == ng && D.atom < 0;
+          if ((st = launch_scale_rows(s, V.as<double>() + voff, ng,
+                                      whole ? nullptr : pl->d_points.as<int32_t>() + pl->pts_off[d],
+                                      (int)D.points.size(), (int)(ch.c1 - ch.c0), hp.volume / (double)ng,
+                                      f->W.as<double>() + f->xoff[d] + ch.c0 * nmu, nmu)) != ISDF_OK)
+            return st;
+        }
+        voff += ng * (ch.c1 - ch.c0);
+      }
+    }
     for (const GemmLaunch& gl : glaunch[ci]) {
       if (gl.level == 0 && w_mixed) {
         const int w = (int)(ch.c1 - ch.c0);
@@ -1815,6 +1900,66 @@ isdf_status run_coulomb(isdf_plan_s* pl, isdf_fit_s* f) {
   return ISDF_OK;
 }
 
+// Stage clock of a fit: event pairs per stage segment, summed after the
+// final synchronisation (a streamed fit visits the stages once per group).
+struct StageClock {
+  std::vector<std::pair<int, std::array<hipEvent_t, 2>>> segs;
+  hipStream_t s = nullptr;
+  int open_stage = -1;
+  ~StageClock() {
+    for (auto& x : segs)
+      for (hipEvent_t e : x.second) (void)hipEventDestroy(e);
+  }
+  isdf_status begin(int stage) {
+    std::array<hipEvent_t, 2> e{};
+    ISDF_HIP_TRY(hipEventCreate(&e[0]));
+    ISDF_HIP_TRY(hipEventCreate(&e[1]));
+    segs.push_back({stage, e});
+    ISDF_HIP_TRY(hipEventRecord(e[0], s));
+    open_stage = stage;
+    return ISDF_OK;
+  }
+  isdf_status end() {
+    ISDF_HIP_TRY(hipEventRecord(segs.back().second[1], s));
+    open_stage = -1;
+    return ISDF_OK;
+  }
+  isdf_status next(int stage) {
+    isdf_status st;
+    if (open_stage >= 0 && (st = end()) != ISDF_OK) return st;
+    return begin(stage);
+  }
+  isdf_status collect(double* ms_out, int n) {
+    for (int i = 0; i < n; ++i) ms_out[i] = 0.0;
+    for (auto& x : segs) {
+      float ms = 0.f;
+      ISDF_HIP_TRY(hipEventElapsedTime(&ms, x.second[0], x.second[1]));
+      if (x.first < n) ms_out[x.first] += ms;
+    }
+    return ISDF_OK;
+  }
+};
+
+// Consecutive domain groups whose basis values fit the budget (a domain
+// larger than the budget is a group of its own).
+std::vector<std::pair<int, int>> phi_groups(isdf_plan_s* pl, double budget_bytes) {
+  const int nd = (int)pl->hp.domains.size();
+  std::vector<std::pair<int, int>> g;
+  int g0 = 0;
+  double acc = 0.0;
+  for (int d = 0; d < nd; ++d) {
+    const double b = 8.0 * (double)pl->hp.domains[d].points.size() * pl->hp.domains[d].funcs.size();
+    if (d > g0 && acc + b > budget_bytes) {
+      g.push_back({g0, d});
+      g0 = d;
+      acc = 0.0;
+    }
+    acc += b;
+  }
+  g.push_back({g0, nd});
+  return g;
+}
+
 isdf_status do_fit(isdf_plan_s* pl, const int64_t* pinned, const int64_t* cand_in,
                    const int64_t* ncand_in, const std::vector<int>* force_full, isdf_fit_t* out) {
   if (!pl || !out) {
@@ -1829,39 +1974,81 @@ isdf_status do_fit(isdf_plan_s* pl, const int64_t* pinned, const int64_t* cand_i
   std::unique_ptr<isdf_fit_s> f(new isdf_fit_s());
   f->plan = pl;
   const int nd = (int)hp.domains.size();
-  // 1. basis + diagonal
-  ISDF_HIP_TRY(hipEventRecord(pl->ev[0], s));
-  if ((st = f->phi.alloc(sizeof(double) * std::max<int64_t>(pl->phi_total, 1))) != ISDF_OK) return st;
+  StageClock clk;
+  clk.s = s;
+  // domain groups by the basis-value budget
+  double budget = 0.0;
+  if (pl->opts.phi_budget_mb > 0) {
+    budget = 1048576.0 * pl->opts.phi_budget_mb;
+  } else {
+    double avail = 0.0;
+    if ((st = pl->mem->available(&avail)) != ISDF_OK) return st;
+    budget = 0.4 * avail;
+  }
+  const std::vector<std::pair<int, int>> groups =
+      8.0 * (double)pl->phi_total > budget ? phi_groups(pl, budget) : std::vector<std::pair<int, int>>{{0, nd}};
+  const bool streamed = groups.size() > 1;
+  int64_t phi_cap = pl->phi_total;
+  if (streamed) {
+    phi_cap = 0;
+    for (auto& g : groups) {
+      const int64_t e = (g.second < nd ? pl->phi_off[g.second] : pl->phi_total) - pl->phi_off[g.first];
+      phi_cap = std::max(phi_cap, e);
+    }
+  }
+  f->phi_streamed = streamed;
+  auto grp_pts = [&](const std::pair<int, int>& g, int64_t* p0) {
+    *p0 = pl->pts_off[g.first];
+    return (g.second < nd ? pl->pts_off[g.second] : pl->pts_total) - *p0;
+  };
+  // basis values (and diagonal, aux) of one group; phi_base + phi_off[d]
+  // addresses domain d of the group
+  auto basis = [&](const std::pair<int, int>& g, double** phi_base) -> isdf_status {
+    *phi_base = f->phi.as<double>() - (streamed ? pl->phi_off[g.first] : 0);
+    const int t0 = pl->tile_off[g.first], t1 = pl->tile_off[g.second];
+    int64_t p0;
+    const int64_t np = grp_pts(g, &p0);
+    const int64_t e = (g.second < nd ? pl->phi_off[g.second] : pl->phi_total) - pl->phi_off[g.first];
+    ProfScope ps_basis(pl, ISDF_K_BASIS, 8.0 * ((double)e + np), 0.0);
+    return launch_basis_eval(s, pl->lat, pl->d_shells.as<ShellDev>(), pl->d_img.as<double>(),
+                             pl->d_colshells.as<ColShell>(), pl->d_doms.as<DomainDev>(), pl->d_points.as<int32_t>(),
+                             pl->d_tiles.as<BasisTile>() + t0, t1 - t0, *phi_base, f->diag0.as<double>(),
+                             f->aux.as<double>());
+  };
+  // 1-2. basis values, then selection, per group
+  if ((st = f->phi.alloc(sizeof(double) * std::max<int64_t>(phi_cap, 1))) != ISDF_OK) return st;
   if ((st = f->diag0.alloc(sizeof(double) * pl->pts_total)) != ISDF_OK) return st;
   if ((st = f->dwork.alloc(sizeof(double) * pl->pts_total)) != ISDF_OK) return st;
   if ((st = f->aux.alloc(sizeof(double) * 4 * pl->pts_total)) != ISDF_OK) return st;
-  double basis_bytes = 8.0 * ((double)pl->phi_total + pl->pts_total);
-  ProfScope ps_basis(pl, ISDF_K_BASIS, basis_bytes, 0.0);
-  if ((st = launch_basis_eval(s, pl->lat, pl->d_shells.as<ShellDev>(), pl->d_img.as<double>(),
-                              pl->d_colshells.as<ColShell>(), pl->d_doms.as<DomainDev>(),
-                              pl->d_points.as<int32_t>(), pl->d_tiles.as<BasisTile>(),
-                              pl->ntiles_basis, f->phi.as<double>(), f->diag0.as<double>(),
-                              f->aux.as<double>())) != ISDF_OK)
-    return st;
-  ps_basis.finish();
-  ISDF_HIP_TRY(hipMemcpyAsync(f->dwork.p, f->diag0.p, sizeof(double) * pl->pts_total,
-                              hipMemcpyDeviceToDevice, s));
-  ISDF_HIP_TRY(hipEventRecord(pl->ev[1], s));
-  // 2. selection
   f->mode.assign(nd, 0);
   f->all_points = pl->opts.universal_all_points != 0;
   for (int d = 0; d < nd; ++d) {
     const int pts = (int)hp.domains[d].points.size();
     if (hp.domains[d].n_mu == 0) continue;  // nothing to select
-    if (cand_in) {
+    if (!pinned && hp.n_mu_ratio > 0 && hp.domains[d].n_mu >= pts) {
+      f->mode[d] = 3;  // count-driven and capped at the point count: every point, F = I
+    } else if (cand_in) {
       f->mode[d] = 2;
     } else if (pl->opts.selector == ISDF_SEL_MLP && !(force_full && (*force_full)[d])) {
       const int keep = (int)std::ceil(pl->opts.mlp_keep * (double)hp.domains[d].n_mu);
       f->mode[d] = keep < pts ? 1 : 0;
     }
   }
-  if ((st = run_selection(pl, f.get(), pinned, f->mode, cand_in, ncand_in)) != ISDF_OK) return st;
-  ISDF_HIP_TRY(hipEventRecord(pl->ev[2], s));
+  SelCtx cx;
+  if ((st = sel_setup(pl, f.get(), cx, pinned, f->mode, cand_in, ncand_in)) != ISDF_OK) return st;
+  for (const auto& g : groups) {
+    double* phi_base = nullptr;
+    if ((st = clk.next(0)) != ISDF_OK) return st;
+    if ((st = basis(g, &phi_base)) != ISDF_OK) return st;
+    int64_t p0;
+    const int64_t np = grp_pts(g, &p0);
+    ISDF_HIP_TRY(hipMemcpyAsync(f->dwork.as<double>() + p0, f->diag0.as<double>() + p0, sizeof(double) * np,
+                                hipMemcpyDeviceToDevice, s));
+    if ((st = clk.next(1)) != ISDF_OK) return st;
+    if ((st = sel_group(pl, f.get(), cx, f->mode, g.first, g.second, phi_base)) != ISDF_OK) return st;
+  }
+  if ((st = clk.end()) != ISDF_OK) return st;
+  for (DevBuf* b : {&cx.cand, &cx.feats, &cx.z}) b->release();  // no longer needed
   bool rank_short = false;
   f->xoff.assign(nd, 0);
   int64_t nmu = 0;
@@ -1871,7 +2058,7 @@ isdf_status do_fit(isdf_plan_s* pl, const int64_t* pinned, const int64_t* cand_i
     if (f->count[d] < hp.domains[d].n_mu) rank_short = true;
   }
   f->nmu = nmu;
-  // 3. gather X
+  // 3-5 per group: gather X, Theta, fitting functions
   const int64_t N = hp.n_basis;
   if ((st = f->XL.alloc(sizeof(double) * nmu * N)) != ISDF_OK) return st;
   if ((st = f->XN.alloc(sizeof(double) * nmu * N)) != ISDF_OK) return st;
@@ -1882,7 +2069,6 @@ isdf_status do_fit(isdf_plan_s* pl, const int64_t* pinned, const int64_t* cand_i
   f->xrow_off.assign(nd, 0);
   f->th_off.assign(nd, 0);
   int64_t xr = 0, th = 0;
-  int max_rows = 0;
   for (int d = 0; d < nd; ++d) {
     const HostDomain& D = hp.domains[d];
     GatherDom& g = gd[d];
@@ -1899,28 +2085,45 @@ isdf_status do_fit(isdf_plan_s* pl, const int64_t* pinned, const int64_t* cand_i
     f->th_off[d] = th;
     xr += (int64_t)g.count * g.nG;
     th += (int64_t)g.count * g.pts;
-    max_rows = std::max(max_rows, g.count);
   }
   DevBuf d_gd;
   if ((st = upload(d_gd, gd)) != ISDF_OK) return st;
   if ((st = f->xrows.alloc(sizeof(double) * std::max<int64_t>(xr, 1))) != ISDF_OK) return st;
-  if ((st = launch_gather_x(s, d_gd.as<GatherDom>(), nd, max_rows, f->phi.as<double>(),
-                            f->piv.as<int32_t>(), pl->d_funcs.as<int32_t>(), f->xrows.as<double>(),
-                            f->XL.as<double>(), f->XN.as<double>(), nmu)) != ISDF_OK)
-    return st;
-  if ((st = launch_add(s, f->XL.as<double>(), f->XN.as<double>(), f->XG.as<double>(), nmu * N)) !=
-      ISDF_OK)
-    return st;
-  ISDF_HIP_TRY(hipEventRecord(pl->ev[3], s));
-  // 4. Theta
   if ((st = f->theta.alloc(sizeof(double) * std::max<int64_t>(th, 1))) != ISDF_OK) return st;
   if ((st = f->F.alloc(sizeof(double) * std::max<int64_t>(th, 1))) != ISDF_OK) return st;
-  {
+  DevBuf spd;
+  if ((st = spd.alloc(sizeof(int32_t))) != ISDF_OK) return st;
+  ISDF_HIP_TRY(hipMemsetAsync(spd.p, 0, sizeof(int32_t), s));
+  // all-point domains: F = I, Theta not formed (zeros)
+  for (int d = 0; d < nd; ++d) {
+    if (f->mode[d] != 3) continue;
+    const int64_t np = gd[d].pts;
+    if ((st = launch_fill(s, f->F.as<double>() + f->th_off[d], np * np, 0.0)) != ISDF_OK) return st;
+    if ((st = launch_set_diag(s, f->F.as<double>() + f->th_off[d], np, (int)np, 1.0)) != ISDF_OK) return st;
+    if ((st = launch_fill(s, f->theta.as<double>() + f->th_off[d], np * np, 0.0)) != ISDF_OK) return st;
+  }
+  auto fitted = [&](int d) { return f->count[d] > 0 && f->mode[d] != 3; };
+  for (const auto& g : groups) {
+    const int g0 = g.first, g1 = g.second;
+    double* phi_base = f->phi.as<double>();
+    if (streamed) {
+      if ((st = clk.next(0)) != ISDF_OK) return st;
+      if ((st = basis(g, &phi_base)) != ISDF_OK) return st;
+    }
+    if ((st = clk.next(2)) != ISDF_OK) return st;
+    int max_rows = 0;
+    for (int d = g0; d < g1; ++d) max_rows = std::max(max_rows, gd[d].count);
+    if ((st = launch_gather_x(s, d_gd.as<GatherDom>() + g0, g1 - g0, max_rows, phi_base, f->piv.as<int32_t>(),
+                              pl->d_funcs.as<int32_t>(), f->xrows.as<double>(), f->XL.as<double>(),
+                              f->XN.as<double>(), nmu)) != ISDF_OK)
+      return st;
+    // Theta
+    if ((st = clk.next(3)) != ISDF_OK) return st;
     std::vector<GemmProblem> probs;
-    for (int d = 0; d < nd; ++d) {
-      if (f->count[d] == 0) continue;
+    for (int d = g0; d < g1; ++d) {
+      if (!fitted(d)) continue;
       GemmProblem p{};
-      p.A = f->phi.as<double>() + pl->phi_off[d];
+      p.A = phi_base + pl->phi_off[d];
       p.lda = gd[d].pts;
       p.B = f->xrows.as<double>() + f->xrow_off[d];
       p.ldb = gd[d].nG;
@@ -1938,22 +2141,22 @@ isdf_status do_fit(isdf_plan_s* pl, const int64_t* pinned, const int64_t* cand_i
       const int S = mixed_splits(pl);
       Planes Ap, Bp;
       DevBuf kx;
-      for (int d = 0; d < nd; ++d) {
-        if (f->count[d] == 0) continue;
+      for (int d = g0; d < g1; ++d) {
+        if (!fitted(d)) continue;
         const int nL = gd[d].nL, nG = gd[d].nG, padL = (nL + 31) / 32 * 32;
         std::vector<int32_t> kidx(padL + (nG - nL));
         for (int c = 0; c < padL; ++c) kidx[c] = c < nL ? c : -1;
         for (int c = nL; c < nG; ++c) kidx[padL + c - nL] = c;
         if ((st = upload(kx, kidx)) != ISDF_OK) return st;
         const int Kp = (int)kidx.size();
-        if ((st = make_planes(s, S, f->phi.as<double>() + pl->phi_off[d], 1, gd[d].pts,
-                              kx.as<int32_t>(), gd[d].pts, Kp, Ap)) != ISDF_OK)
+        if ((st = make_planes(s, S, phi_base + pl->phi_off[d], 1, gd[d].pts, kx.as<int32_t>(), gd[d].pts, Kp,
+                              Ap)) != ISDF_OK)
           return st;
-        if ((st = make_planes(s, S, f->xrows.as<double>() + f->xrow_off[d], nG, 1, kx.as<int32_t>(),
-                              f->count[d], Kp, Bp)) != ISDF_OK)
+        if ((st = make_planes(s, S, f->xrows.as<double>() + f->xrow_off[d], nG, 1, kx.as<int32_t>(), f->count[d],
+                              Kp, Bp)) != ISDF_OK)
           return st;
-        MixedProblem mp = mixed_problem(Ap, Bp, f->theta.as<double>() + f->th_off[d], gd[d].pts,
-                                        gd[d].pts, f->count[d], Kp, 1.0, 0.0, nullptr, 0);
+        MixedProblem mp = mixed_problem(Ap, Bp, f->theta.as<double>() + f->th_off[d], gd[d].pts, gd[d].pts,
+                                        f->count[d], Kp, 1.0, 0.0, nullptr, 0);
         mp.kL = padL;
         if ((st = mixed_prof(pl, ISDF_K_GEMM_FIT, EPI_THETA, mp)) != ISDF_OK) return st;
         ISDF_HIP_TRY(hipStreamSynchronize(s));  // planes and index are reused
@@ -1988,21 +2191,16 @@ isdf_status do_fit(isdf_plan_s* pl, const int64_t* pinned, const int64_t* cand_i
             return st;
         }
       }
+      ISDF_HIP_TRY(hipStreamSynchronize(s));  // the problem table is released
     }
-    ISDF_HIP_TRY(hipStreamSynchronize(s));
-  }
-  ISDF_HIP_TRY(hipEventRecord(pl->ev[4], s));
-  // 5. fitting functions
-  DevBuf spd;
-  if ((st = spd.alloc(sizeof(int32_t))) != ISDF_OK) return st;
-  ISDF_HIP_TRY(hipMemsetAsync(spd.p, 0, sizeof(int32_t), s));
-  {
+    // fitting functions
+    if ((st = clk.next(4)) != ISDF_OK) return st;
     std::vector<SmallFitDom> sf;
     std::vector<int32_t> tile_dom;
     int nmax = 0;
-    for (int d = 0; d < nd; ++d) {
+    for (int d = g0; d < g1; ++d) {
       const int n = f->count[d];
-      if (n == 0 || n > 64) continue;
+      if (!fitted(d) || n > 64) continue;
       SmallFitDom x{};
       x.theta_off = f->th_off[d];
       x.pts = gd[d].pts;
@@ -2018,35 +2216,37 @@ isdf_status do_fit(isdf_plan_s* pl, const int64_t* pinned, const int64_t* cand_i
       if ((st = upload(d_sf, sf)) != ISDF_OK) return st;
       if ((st = upload(d_td, tile_dom)) != ISDF_OK) return st;
       if ((st = launch_small_fit(s, d_sf.as<SmallFitDom>(), d_td.as<int32_t>(), (int)tile_dom.size(),
-                                 f->theta.as<double>(), f->piv.as<int32_t>(), f->F.as<double>(),
-                                 spd.as<int32_t>(), nmax)) != ISDF_OK)
+                                 f->theta.as<double>(), f->piv.as<int32_t>(), f->F.as<double>(), spd.as<int32_t>(),
+                                 nmax)) != ISDF_OK)
         return st;
       ISDF_HIP_TRY(hipStreamSynchronize(s));
     }
-    for (int d = 0; d < nd; ++d) {
+    for (int d = g0; d < g1; ++d) {
       const int n = f->count[d];
-      if (n <= 64) continue;
+      if (!fitted(d) || n <= 64) continue;
       if ((st = blocked_fit(pl, f->theta.as<double>() + f->th_off[d], gd[d].pts, n,
                             f->piv.as<int32_t>() + f->piv_off[d], f->F.as<double>() + f->th_off[d],
                             spd.as<int32_t>())) != ISDF_OK)
         return st;
     }
   }
-  ISDF_HIP_TRY(hipEventRecord(pl->ev[5], s));
+  if ((st = clk.next(2)) != ISDF_OK) return st;
+  if ((st = launch_add(s, f->XL.as<double>(), f->XN.as<double>(), f->XG.as<double>(), nmu * N)) != ISDF_OK)
+    return st;
+  if (streamed) {  // the basis values of the last group are not kept
+    ISDF_HIP_TRY(hipStreamSynchronize(s));
+    f->phi.release();
+  }
   // 6. Coulomb metric
+  if ((st = clk.next(5)) != ISDF_OK) return st;
   if ((st = run_coulomb(pl, f.get())) != ISDF_OK) return st;
-  ISDF_HIP_TRY(hipEventRecord(pl->ev[6], s));
+  if ((st = clk.end()) != ISDF_OK) return st;
   ISDF_HIP_TRY(hipStreamSynchronize(s));
   prof_collect(pl);
   int32_t spd_flag = 0;
   ISDF_HIP_TRY(hipMemcpy(&spd_flag, spd.p, sizeof(int32_t), hipMemcpyDeviceToHost));
-  float ms;
-  const int map[6] = {0, 1, 2, 3, 4, 5};
-  (void)map;
-  for (int i = 0; i < 6; ++i) {
-    ISDF_HIP_TRY(hipEventElapsedTime(&ms, pl->ev[i], pl->ev[i + 1]));
-    pl->stage_ms[i] = ms;
-  }
+  if ((st = clk.collect(pl->stage_ms, 6)) != ISDF_OK) return st;
+  f->groups = (int)groups.size();
   pl->fits_alive++;
   *out = f.release();
   if (spd_flag) {
@@ -2135,33 +2335,72 @@ isdf_status write_tune_file(const isdf_plan_s* pl, const char* path) {
 // Workspace of the exchange (n_occ = 0: dense D, else the factored form).
 // Everything the kernel sequence touches is sized here, so that the
 // sequence itself allocates nothing and can be captured as a graph.
+// Rows of Q held at once by the occ-RI exchange: all N_mu when the full Q
+// buffers fit half of the free memory, else row blocks (multiples of 256)
+// that fit 40 % of it.  The dense exchange always holds all rows.
+isdf_status ri_q_rows(isdf_plan_s* plan, isdf_fit_s* fit, bool mixed, int64_t* rows) {
+  const int64_t m = fit->nmu;
+  if (plan->opts.ri_rows > 0) {
+    *rows = std::min<int64_t>(m, plan->opts.ri_rows);
+    return ISDF_OK;
+  }
+  double avail = 0.0;
+  isdf_status st;
+  if ((st = plan->mem->available(&avail)) != ISDF_OK) return st;
+  const double ld2 = (double)((2 * m + 7) / 8 * 8);
+  const double full = mixed ? 2.0 * mixed_splits(plan) * m * ld2 * 2.0 : 3.0 * 8.0 * m * m;
+  const double per_row = mixed ? 2.0 * mixed_splits(plan) * ld2 * 2.0 : 4.0 * 8.0 * m;
+  if (full <= 0.5 * avail) {
+    *rows = m;
+    return ISDF_OK;
+  }
+  int64_t r = (int64_t)(0.4 * avail / per_row) / 256 * 256;
+  *rows = std::min<int64_t>(m, std::max<int64_t>(256, r));
+  return ISDF_OK;
+}
+
 isdf_status exchange_prepare(isdf_plan_s* plan, isdf_fit_s* fit, int n_occ, bool ri) {
   const int64_t nmu = fit->nmu, N = plan->hp.n_basis;
   const int64_t ec = n_occ > 0 ? n_occ : N;  // columns of E_G, E_L
   isdf_status st;
   const bool mixed = mixed_on(plan, ISDF_MIX_EXCHANGE);
-  if (!fit->Y1.p) {
+  if (!ri && !fit->Y1.p) {  // dense K only
     if ((st = fit->Y1.alloc(sizeof(double) * nmu * N)) != ISDF_OK) return st;
     if ((st = fit->Y2.alloc(sizeof(double) * nmu * N)) != ISDF_OK) return st;
+  }
+  if (!fit->partial.p) {
     if ((st = fit->partial.alloc(sizeof(double) * 1024)) != ISDF_OK) return st;
     if ((st = fit->ex_out.alloc(sizeof(double))) != ISDF_OK) return st;
   }
-  if (!mixed && !fit->QGG.p) {  // the mixed path writes Q straight into split planes
-    if ((st = fit->QGG.alloc(sizeof(double) * nmu * nmu)) != ISDF_OK) return st;
-    if ((st = fit->QGL.alloc(sizeof(double) * nmu * nmu)) != ISDF_OK) return st;
-    if ((st = fit->QLL.alloc(sizeof(double) * nmu * nmu)) != ISDF_OK) return st;
+  // rows of Q: the dense exchange needs all, occ-RI may run in row blocks
+  int64_t need_rows = nmu;
+  if (ri && fit->q_rows < nmu && (st = ri_q_rows(plan, fit, mixed, &need_rows)) != ISDF_OK) return st;
+  const bool new_q = fit->q_rows < need_rows;
+  if (new_q) {
+    fit->q_rows = need_rows;
+    fit->drop_graph();  // a captured exchange would read the old buffers
+  }
+  const int64_t qr = fit->q_rows;
+  if (!mixed && (new_q || !fit->QGG.p)) {  // the mixed path writes Q straight into split planes
+    for (DevBuf* q : {&fit->QGG, &fit->QGL, &fit->QLL})
+      if ((st = q->alloc(sizeof(double) * qr * nmu)) != ISDF_OK) return st;
+    if (qr < nmu) {
+      if ((st = fit->QLG.alloc(sizeof(double) * qr * nmu)) != ISDF_OK) return st;
+    } else {
+      fit->QLG.release();
+    }
   }
   if (fit->EG.bytes < sizeof(double) * nmu * ec) {
     if ((st = fit->EG.alloc(sizeof(double) * nmu * ec)) != ISDF_OK) return st;
     if ((st = fit->EL.alloc(sizeof(double) * nmu * ec)) != ISDF_OK) return st;
   }
-  if (n_occ > 0 && !fit->Docc.p)
+  if (!ri && n_occ > 0 && !fit->Docc.p)
     if ((st = fit->Docc.alloc(sizeof(double) * N * N)) != ISDF_OK) return st;
   if (mixed) {
     const int S = mixed_splits(plan);
     const int m = (int)nmu, n = (int)N;
     hipStream_t s = plan->stream;
-    if (!fit->xg_row.buf.p) {  // fit-time operands and problem tables, built once
+    if (!fit->xg_row.buf.p) {  // fit-time operands, built once
       if ((st = make_planes(s, S, fit->XG.as<double>(), 1, nmu, nullptr, m, n, fit->xg_row)) != ISDF_OK)
         return st;
       if ((st = make_planes(s, S, fit->XL.as<double>(), 1, nmu, nullptr, m, n, fit->xl_row)) != ISDF_OK)
@@ -2178,13 +2417,20 @@ isdf_status exchange_prepare(isdf_plan_s* plan, isdf_fit_s* fit, int n_occ, bool
       if ((st = launch_split_bf16(s, fit->XN.as<double>(), nmu, 1, nullptr, n, m, S, xb + m, fit->xln.ld,
                                   fit->xln.plane, 1.0)) != ISDF_OK)
         return st;
+    }
+    if (new_q || !fit->Q1.buf.p) {  // Q1 = [Q_GG Q_GL], Q2 = [Q_GL^T Q_LL]: q_rows rows of 2 N_mu
       for (Planes* q : {&fit->Q1, &fit->Q2}) {
-        if ((st = size_planes(S, m, 2 * m, *q)) != ISDF_OK) return st;
-        q->rows = m;
+        if ((st = size_planes(S, (int)qr, 2 * m, *q)) != ISDF_OK) return st;
+        q->rows = (int)qr;
         q->cols = 2 * m;
         q->ld = (2 * m + 7) / 8 * 8;
-        q->plane = (int64_t)m * q->ld;
+        q->plane = qr * q->ld;
       }
+      fit->qprobs_nocc = -1;  // problem tables point at the planes
+      fit->ri_nocc = -1;
+      fit->ydense = false;
+    }
+    if (!ri && !fit->ydense) {  // dense K: Y12 planes and the Y and K problem tables
       if ((st = size_planes(S, n, 2 * m, fit->Y12)) != ISDF_OK) return st;
       fit->Y12.rows = n;
       fit->Y12.cols = 2 * m;
@@ -2219,6 +2465,7 @@ isdf_status exchange_prepare(isdf_plan_s* plan, isdf_fit_s* fit, int n_occ, bool
       if ((st = fit->Kpart.alloc(sizeof(double) * (size_t)fit->kparts * n * n)) != ISDF_OK) return st;
       for (int i = 0; i < fit->kparts; ++i) kp[i].C = fit->Kpart.as<double>() + (int64_t)i * n * n;
       if ((st = upload(fit->d_kprobs, kp)) != ISDF_OK) return st;
+      fit->ydense = true;
     }
     if ((st = size_planes(S, n_occ > 0 ? n_occ : n, n, fit->Dp)) != ISDF_OK) return st;
     if ((st = size_planes(S, m, (int)ec, fit->EGp)) != ISDF_OK) return st;
@@ -2229,6 +2476,8 @@ isdf_status exchange_prepare(isdf_plan_s* plan, isdf_fit_s* fit, int n_occ, bool
       // symmetric) lands transposed, at row j and column i of the A operand,
       // so each block of Q1 = [Q_GG Q_GL] and Q2 = [Q_GL^T Q_LL] is one
       // product whose planes the epilogue writes; the four share W's tiles.
+      // Row block [r0, r1) of Q1 and Q2: rows r0.. of the second operand
+      // and columns r0.. of W, written from row 0 of the planes.
       fit->EGp.rows = fit->ELp.rows = m;
       fit->EGp.cols = fit->ELp.cols = (int)ec;
       fit->EGp.ld = fit->ELp.ld = (ec + 7) / 8 * 8;
@@ -2238,14 +2487,20 @@ isdf_status exchange_prepare(isdf_plan_s* plan, isdf_fit_s* fit, int n_occ, bool
       const Planes* ops[4][2] = {{&BG, &fit->EGp}, {&BL, &fit->EGp}, {&fit->EGp, &BL}, {&BL, &fit->ELp}};
       Planes* dst[4] = {&fit->Q1, &fit->Q1, &fit->Q2, &fit->Q2};
       const int off[4] = {0, m, 0, m};
-      std::vector<MixedProblem> qp(4);
-      for (int i = 0; i < 4; ++i) {
-        qp[i] = mixed_problem(*ops[i][0], *ops[i][1], nullptr, 0, m, m, (int)ec, 1.0, 0.0, fit->w64(), nmu);
-        qp[i].E32 = fit->wf32();
-        qp[i].P = static_cast<__bf16*>(dst[i]->buf.p);
-        qp[i].plane_p = dst[i]->plane;
-        qp[i].ldp = dst[i]->ld;
-        qp[i].p_off = off[i];
+      std::vector<MixedProblem> qp;
+      for (int64_t r0 = 0; r0 < nmu; r0 += qr) {
+        const int rb = (int)std::min<int64_t>(qr, nmu - r0);
+        for (int i = 0; i < 4; ++i) {
+          MixedProblem q = mixed_problem(*ops[i][0], *ops[i][1], nullptr, 0, m, rb, (int)ec, 1.0, 0.0,
+                                         fit->w64() ? fit->w64() + r0 * nmu : nullptr, nmu);
+          q.B += r0 * ops[i][1]->ld;
+          q.E32 = fit->wf32() ? fit->wf32() + r0 * nmu : nullptr;
+          q.P = static_cast<__bf16*>(dst[i]->buf.p);
+          q.plane_p = dst[i]->plane;
+          q.ldp = dst[i]->ld;
+          q.p_off = off[i];
+          qp.push_back(q);
+        }
       }
       if ((st = upload(fit->d_qprobs, qp)) != ISDF_OK) return st;
       fit->qprobs_nocc = n_occ;
@@ -2264,20 +2519,25 @@ isdf_status exchange_prepare(isdf_plan_s* plan, isdf_fit_s* fit, int n_occ, bool
         q->ld = (2 * m + 7) / 8 * 8;
         q->plane = (int64_t)o * q->ld;
       }
-      // Z1 = Q1 ELN^T, Z2 = Q2 ELN^T: one grouped launch
-      std::vector<MixedProblem> zp(2);
-      int tiles = 0;
-      for (int i = 0; i < 2; ++i) {
-        zp[i] = mixed_problem(i == 0 ? fit->Q1 : fit->Q2, fit->ELN, (i == 0 ? fit->Z1 : fit->Z2).as<double>(),
-                              nmu, m, o, 2 * m, 1.0, 0.0, nullptr, 0);
-        zp[i].tile_start = tiles;
-        tiles += mixed_tiles_wide(m, o);
+      // per row block: Z1 = Q1 ELN^T, Z2 = Q2 ELN^T, one grouped launch
+      std::vector<MixedProblem> zp;
+      for (int64_t r0 = 0; r0 < nmu; r0 += qr) {
+        const int rb = (int)std::min<int64_t>(qr, nmu - r0);
+        int tiles = 0;
+        for (int i = 0; i < 2; ++i) {
+          MixedProblem z = mixed_problem(i == 0 ? fit->Q1 : fit->Q2, fit->ELN,
+                                         (i == 0 ? fit->Z1 : fit->Z2).as<double>() + r0, nmu, rb, o, 2 * m, 1.0,
+                                         0.0, nullptr, 0);
+          z.tile_start = tiles;
+          tiles += mixed_tiles_wide(rb, o);
+          zp.push_back(z);
+        }
       }
       if ((st = upload(fit->d_zprobs, zp)) != ISDF_OK) return st;
       // (K C)^T = -(Z12)(xln)^T over k ranges, partials summed in order
       const int kc = std::max(32, (2 * m + KSPLIT_RI - 1) / KSPLIT_RI / 32 * 32);
       std::vector<MixedProblem> kp;
-      tiles = 0;
+      int tiles = 0;
       for (int k0 = 0; k0 < 2 * m; k0 += kc) {
         MixedProblem q = mixed_problem(fit->Z12, fit->xln, nullptr, o, o, n, std::min(kc, 2 * m - k0), -1.0,
                                        0.0, nullptr, 0);
@@ -2422,12 +2682,19 @@ isdf_status exchange_enqueue(isdf_plan_s* plan, isdf_fit_s* fit, const double* i
 // and the three Hadamard blocks Q_GG, Q_GL, Q_LL (N_mu x N_mu), column-major.
 struct RiBuffers {
   double *EG, *EL, *EN, *QGG, *QGL, *QLL, *Z1, *Z2;
+  // row blocks: qrows rows per block in QGG, QGL, QLG, QLL (qrows x N_mu
+  // each); 0 or N_mu: one block, no QLG
+  double* QLG;
+  int64_t qrows;
 };
 
 // FP64 occ-RI products into the given workspace (no allocation):
 //   E_G = X^G C, E_L = X^L C, E_N = E_G - E_L,
 //   Q_ST = W o (E_S E_T^T), Z1 = Q_GG E_L + Q_GL E_N, Z2 = Q_GL^T E_L + Q_LL E_N,
 //   (K C)^T = -(Z1^T X^L + Z2^T X^N)   (n_occ x N column-major = K C row-major).
+// With row blocks, rows [r0, r1) of Z1 and Z2 come from the same rows of
+// Q_GG, Q_GL, Q_LL and Q_LG = Q_GL^T (W symmetric: Q_LG(r, :) is
+// W(r, :) o (E_L(r, :) E_G^T)), so no N_mu x N_mu buffer is held.
 isdf_status ri_fp64_products(isdf_plan_s* plan, isdf_fit_s* fit, const double* Cin, int o, double* KC,
                              const RiBuffers& b) {
   hipStream_t s = plan->stream;
@@ -2437,31 +2704,59 @@ isdf_status ri_fp64_products(isdf_plan_s* plan, isdf_fit_s* fit, const double* C
   const double* XN = fit->XN.as<double>();
   const double* XG = fit->XG.as<double>();
   const double* W = fit->w64();
+  const float* W32 = fit->wf32();
   auto gemm = [&](int epi, const double* A, int64_t lda, int tA, const double* B, int64_t ldb, int tB,
-                  double* C, int64_t ldc, int M, int Nn, int Kk, double alpha, double beta, const double* E) {
+                  double* C, int64_t ldc, int M, int Nn, int Kk, double alpha, double beta, int64_t e_row) {
     GemmProblem p{};
     p.A = A; p.lda = lda; p.transA = tA;
     p.B = B; p.ldb = ldb; p.transB = tB;
     p.C = C; p.ldc = ldc;
-    p.E = E; p.lde = nmu;
-    if (epi == EPI_HADAMARD) p.E32 = fit->wf32();  // the Hadamard factor is W
+    if (epi == EPI_HADAMARD) {  // the Hadamard factor is W, from row e_row on
+      p.E = W ? W + e_row : nullptr;
+      p.E32 = W32 ? W32 + e_row : nullptr;
+    }
+    p.lde = nmu;
     p.M = M; p.N = Nn; p.K = Kk;
     p.alpha = alpha; p.beta = beta;
     return gemm_prof(plan, ISDF_K_GEMM_EXCHANGE, epi, p);
   };
   isdf_status st;
-  if ((st = gemm(EPI_AXPBY, XG, nmu, 0, Cin, o, 1, b.EG, nmu, m, o, n, 1.0, 0.0, nullptr)) != ISDF_OK) return st;
-  if ((st = gemm(EPI_AXPBY, XL, nmu, 0, Cin, o, 1, b.EL, nmu, m, o, n, 1.0, 0.0, nullptr)) != ISDF_OK) return st;
+  if ((st = gemm(EPI_AXPBY, XG, nmu, 0, Cin, o, 1, b.EG, nmu, m, o, n, 1.0, 0.0, 0)) != ISDF_OK) return st;
+  if ((st = gemm(EPI_AXPBY, XL, nmu, 0, Cin, o, 1, b.EL, nmu, m, o, n, 1.0, 0.0, 0)) != ISDF_OK) return st;
   if ((st = launch_sub(s, b.EG, b.EL, b.EN, nmu * o)) != ISDF_OK) return st;
-  if ((st = gemm(EPI_HADAMARD, b.EG, nmu, 0, b.EG, nmu, 1, b.QGG, nmu, m, m, o, 1.0, 0.0, W)) != ISDF_OK) return st;
-  if ((st = gemm(EPI_HADAMARD, b.EG, nmu, 0, b.EL, nmu, 1, b.QGL, nmu, m, m, o, 1.0, 0.0, W)) != ISDF_OK) return st;
-  if ((st = gemm(EPI_HADAMARD, b.EL, nmu, 0, b.EL, nmu, 1, b.QLL, nmu, m, m, o, 1.0, 0.0, W)) != ISDF_OK) return st;
-  if ((st = gemm(EPI_AXPBY, b.QGG, nmu, 0, b.EL, nmu, 0, b.Z1, nmu, m, o, m, 1.0, 0.0, nullptr)) != ISDF_OK) return st;
-  if ((st = gemm(EPI_AXPBY, b.QGL, nmu, 0, b.EN, nmu, 0, b.Z1, nmu, m, o, m, 1.0, 1.0, nullptr)) != ISDF_OK) return st;
-  if ((st = gemm(EPI_AXPBY, b.QGL, nmu, 1, b.EL, nmu, 0, b.Z2, nmu, m, o, m, 1.0, 0.0, nullptr)) != ISDF_OK) return st;
-  if ((st = gemm(EPI_AXPBY, b.QLL, nmu, 0, b.EN, nmu, 0, b.Z2, nmu, m, o, m, 1.0, 1.0, nullptr)) != ISDF_OK) return st;
-  if ((st = gemm(EPI_AXPBY, b.Z1, nmu, 1, XL, nmu, 0, KC, o, o, n, m, -1.0, 0.0, nullptr)) != ISDF_OK) return st;
-  return gemm(EPI_AXPBY, b.Z2, nmu, 1, XN, nmu, 0, KC, o, o, n, m, -1.0, 1.0, nullptr);
+  if (b.qrows <= 0 || b.qrows >= nmu) {
+    if ((st = gemm(EPI_HADAMARD, b.EG, nmu, 0, b.EG, nmu, 1, b.QGG, nmu, m, m, o, 1.0, 0.0, 0)) != ISDF_OK) return st;
+    if ((st = gemm(EPI_HADAMARD, b.EG, nmu, 0, b.EL, nmu, 1, b.QGL, nmu, m, m, o, 1.0, 0.0, 0)) != ISDF_OK) return st;
+    if ((st = gemm(EPI_HADAMARD, b.EL, nmu, 0, b.EL, nmu, 1, b.QLL, nmu, m, m, o, 1.0, 0.0, 0)) != ISDF_OK) return st;
+    if ((st = gemm(EPI_AXPBY, b.QGG, nmu, 0, b.EL, nmu, 0, b.Z1, nmu, m, o, m, 1.0, 0.0, 0)) != ISDF_OK) return st;
+    if ((st = gemm(EPI_AXPBY, b.QGL, nmu, 0, b.EN, nmu, 0, b.Z1, nmu, m, o, m, 1.0, 1.0, 0)) != ISDF_OK) return st;
+    if ((st = gemm(EPI_AXPBY, b.QGL, nmu, 1, b.EL, nmu, 0, b.Z2, nmu, m, o, m, 1.0, 0.0, 0)) != ISDF_OK) return st;
+    if ((st = gemm(EPI_AXPBY, b.QLL, nmu, 0, b.EN, nmu, 0, b.Z2, nmu, m, o, m, 1.0, 1.0, 0)) != ISDF_OK) return st;
+  } else {
+    for (int64_t r0 = 0; r0 < nmu; r0 += b.qrows) {
+      const int rb = (int)std::min<int64_t>(b.qrows, nmu - r0);
+      const int64_t q = b.qrows;  // leading dimension of the block buffers
+      // Q_XY(r, :) = W(r, :) o (E_X(r, :) E_Y^T): rows r0.. of W are W + r0 (lde N_mu)
+      if ((st = gemm(EPI_HADAMARD, b.EG + r0, nmu, 0, b.EG, nmu, 1, b.QGG, q, rb, m, o, 1.0, 0.0, r0)) != ISDF_OK)
+        return st;
+      if ((st = gemm(EPI_HADAMARD, b.EG + r0, nmu, 0, b.EL, nmu, 1, b.QGL, q, rb, m, o, 1.0, 0.0, r0)) != ISDF_OK)
+        return st;
+      if ((st = gemm(EPI_HADAMARD, b.EL + r0, nmu, 0, b.EG, nmu, 1, b.QLG, q, rb, m, o, 1.0, 0.0, r0)) != ISDF_OK)
+        return st;
+      if ((st = gemm(EPI_HADAMARD, b.EL + r0, nmu, 0, b.EL, nmu, 1, b.QLL, q, rb, m, o, 1.0, 0.0, r0)) != ISDF_OK)
+        return st;
+      if ((st = gemm(EPI_AXPBY, b.QGG, q, 0, b.EL, nmu, 0, b.Z1 + r0, nmu, rb, o, m, 1.0, 0.0, 0)) != ISDF_OK)
+        return st;
+      if ((st = gemm(EPI_AXPBY, b.QGL, q, 0, b.EN, nmu, 0, b.Z1 + r0, nmu, rb, o, m, 1.0, 1.0, 0)) != ISDF_OK)
+        return st;
+      if ((st = gemm(EPI_AXPBY, b.QLG, q, 0, b.EL, nmu, 0, b.Z2 + r0, nmu, rb, o, m, 1.0, 0.0, 0)) != ISDF_OK)
+        return st;
+      if ((st = gemm(EPI_AXPBY, b.QLL, q, 0, b.EN, nmu, 0, b.Z2 + r0, nmu, rb, o, m, 1.0, 1.0, 0)) != ISDF_OK)
+        return st;
+    }
+  }
+  if ((st = gemm(EPI_AXPBY, b.Z1, nmu, 1, XL, nmu, 0, KC, o, o, n, m, -1.0, 0.0, 0)) != ISDF_OK) return st;
+  return gemm(EPI_AXPBY, b.Z2, nmu, 1, XN, nmu, 0, KC, o, o, n, m, -1.0, 1.0, 0);
 }
 
 isdf_status exchange_enqueue_ri(isdf_plan_s* plan, isdf_fit_s* fit, const double* Cin, int n_occ, double* KC,
@@ -2486,26 +2781,32 @@ isdf_status exchange_enqueue_ri(isdf_plan_s* plan, isdf_fit_s* fit, const double
     if ((st = launch_sub(s, EG, EL, EN, nmu * o)) != ISDF_OK) return st;
     if ((st = make_planes(s, S, EG, 1, nmu, nullptr, m, o, fit->EGp)) != ISDF_OK) return st;
     if ((st = make_planes(s, S, EL, 1, nmu, nullptr, m, o, fit->ELp)) != ISDF_OK) return st;
-    {  // Q1 = [Q_GG Q_GL], Q2 = [Q_GL^T Q_LL] as split planes (exchange_prepare)
-      ProfScope ps(plan, ISDF_K_GEMM_EXCHANGE,
-                   4.0 * (2.0 * S * 2.0 * m * (double)o + 2.0 * S * (double)m * m) + 8.0 * (double)m * m,
-                   4.0 * 2.0 * m * (double)m * o);
-      if ((st = gemm_mixed_wide_grouped(s, EPI_HADAMARD_PLANES, S, fit->d_qprobs.as<MixedProblem>(), -4,
-                                        4 * mixed_tiles_wide(m, m), family_tag(ISDF_K_GEMM_EXCHANGE))) != ISDF_OK)
-        return st;
-    }
     __bf16* eb = static_cast<__bf16*>(fit->ELN.buf.p);
     if ((st = launch_split_bf16(s, EL, nmu, 1, nullptr, o, m, S, eb, fit->ELN.ld, fit->ELN.plane, 1.0)) != ISDF_OK)
       return st;
     if ((st = launch_split_bf16(s, EN, nmu, 1, nullptr, o, m, S, eb + m, fit->ELN.ld, fit->ELN.plane, 1.0)) !=
         ISDF_OK)
       return st;
-    {  // Z1 = Q1 ELN^T, Z2 = Q2 ELN^T
-      ProfScope ps(plan, ISDF_K_GEMM_EXCHANGE, 2.0 * (2.0 * S * (2.0 * m * m + 2.0 * m * o) + 8.0 * m * o),
-                   2.0 * (2.0 * m * (double)o * 2.0 * m));
-      if ((st = gemm_mixed_wide_grouped(s, EPI_AXPBY, S, fit->d_zprobs.as<MixedProblem>(), 2,
-                                        2 * mixed_tiles_wide(m, o), family_tag(ISDF_K_GEMM_EXCHANGE))) != ISDF_OK)
-        return st;
+    // per row block of Q (all N_mu rows at once unless memory asks for blocks)
+    int blk = 0;
+    for (int64_t r0 = 0; r0 < nmu; r0 += fit->q_rows, ++blk) {
+      const int rb = (int)std::min<int64_t>(fit->q_rows, nmu - r0);
+      {  // rows r0.. of Q1 = [Q_GG Q_GL], Q2 = [Q_GL^T Q_LL] as split planes (exchange_prepare)
+        ProfScope ps(plan, ISDF_K_GEMM_EXCHANGE,
+                     4.0 * (2.0 * S * (m + (double)rb) * o + 2.0 * S * (double)rb * m) + 8.0 * (double)rb * m,
+                     4.0 * 2.0 * rb * (double)m * o);
+        if ((st = gemm_mixed_wide_grouped(s, EPI_HADAMARD_PLANES, S, fit->d_qprobs.as<MixedProblem>() + 4 * blk, -4,
+                                          4 * mixed_tiles_wide(m, rb), family_tag(ISDF_K_GEMM_EXCHANGE))) !=
+            ISDF_OK)
+          return st;
+      }
+      {  // rows r0.. of Z1 = Q1 ELN^T, Z2 = Q2 ELN^T
+        ProfScope ps(plan, ISDF_K_GEMM_EXCHANGE, 2.0 * (2.0 * S * (2.0 * rb * m + 2.0 * m * o) + 8.0 * rb * o),
+                     2.0 * (2.0 * rb * (double)o * 2.0 * m));
+        if ((st = gemm_mixed_wide_grouped(s, EPI_AXPBY, S, fit->d_zprobs.as<MixedProblem>() + 2 * blk, 2,
+                                          2 * mixed_tiles_wide(rb, o), family_tag(ISDF_K_GEMM_EXCHANGE))) != ISDF_OK)
+          return st;
+      }
     }
     __bf16* zb = static_cast<__bf16*>(fit->Z12.buf.p);
     if ((st = launch_split_bf16(s, Z1, nmu, 1, nullptr, o, m, S, zb, fit->Z12.ld, fit->Z12.plane, 1.0)) != ISDF_OK)
@@ -2523,7 +2824,8 @@ isdf_status exchange_enqueue_ri(isdf_plan_s* plan, isdf_fit_s* fit, const double
     if ((st = launch_sum_parts(s, fit->KCpart.as<double>(), fit->kcparts, (int64_t)o * n, KC)) != ISDF_OK)
       return st;
   } else {
-    const RiBuffers b{EG, EL, EN, fit->QGG.as<double>(), fit->QGL.as<double>(), fit->QLL.as<double>(), Z1, Z2};
+    const RiBuffers b{EG,  EL, EN, fit->QGG.as<double>(), fit->QGL.as<double>(), fit->QLL.as<double>(),
+                      Z1,  Z2, fit->QLG.as<double>(), fit->q_rows};
     if ((st = ri_fp64_products(plan, fit, Cin, o, KC, b)) != ISDF_OK) return st;
   }
   if (stage_event) ISDF_HIP_TRY(hipEventRecord(plan->ev[1], s));
@@ -2938,6 +3240,10 @@ isdf_status isdf_plan(const isdf_system* sys, const isdf_options* opts, isdf_pla
     set_error("isdf_plan: universal_tile_mb must not be negative");
     return ISDF_E_ARG;
   }
+  if (pl->opts.phi_budget_mb < 0 || pl->opts.ri_rows < 0) {
+    set_error("isdf_plan: phi_budget_mb and ri_rows must not be negative");
+    return ISDF_E_ARG;
+  }
   if (pl->opts.w_storage != ISDF_W_F64 && pl->opts.w_storage != ISDF_W_F32) {
     set_error("isdf_plan: w_storage must be ISDF_W_F64 or ISDF_W_F32");
     return ISDF_E_ARG;
@@ -3339,6 +3645,10 @@ isdf_status isdf_fit_get(isdf_fit_t fit, int32_t field, int32_t d, void* host_ou
   std::vector<int32_t> tmp32;
   switch (field) {
     case ISDF_FIELD_PHI:
+      if (fit->phi_streamed) {
+        set_error("isdf_fit_get: the fit streamed its basis values by domain group and kept none");
+        return ISDF_E_STATE;
+      }
       src = fit->phi.as<double>() + pl->phi_off[d];
       need = sizeof(double) * hp.domains[d].points.size() * hp.domains[d].funcs.size();
       break;

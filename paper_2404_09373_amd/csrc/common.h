@@ -231,6 +231,11 @@ isdf_status launch_gather_x(hipStream_t s, const GatherDom* doms, int ndom, int 
                             double* xrows, double* XL, double* XN, int64_t nmu);
 
 isdf_status launch_fill(hipStream_t s, double* p, int64_t n, double v);
+// p(i, i) = v for i < n (column-major, leading dimension ld)
+isdf_status launch_set_diag(hipStream_t s, double* p, int64_t ld, int n, double v);
+// dst(i, c) = alpha src(idx ? idx[i] : i, c) for i < rows, c < cols (column-major)
+isdf_status launch_scale_rows(hipStream_t s, const double* src, int64_t lds, const int32_t* idx, int rows,
+                              int cols, double alpha, double* dst, int64_t ldd);
 // y = (float) x, n values (FP32 storage of an FP64 result).
 isdf_status launch_narrow(hipStream_t s, const double* x, float* y, int64_t n);
 // C(m, n) = c (c + 2 t), c = C(m, n) (ldc), t = T(m, n) (ldt = M; 0 if T is null)

@@ -180,6 +180,36 @@ isdf_status launch_fill(hipStream_t s, double* p, int64_t n, double v) {
   return ISDF_OK;
 }
 
+// p(i, i) = v for i < n (column-major, leading dimension ld)
+__global__ void set_diag_kernel(double* p, int64_t ld, int n, double v) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i + (int64_t)i * ld] = v;
+}
+isdf_status launch_set_diag(hipStream_t s, double* p, int64_t ld, int n, double v) {
+  if (n <= 0) return ISDF_OK;
+  const int blocks = std::min((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(set_diag_kernel, dim3(blocks), dim3(256), 0, s, p, ld, n, v);
+  ISDF_HIP_TRY(hipGetLastError());
+  return ISDF_OK;
+}
+
+// dst(i, c) = alpha src(idx ? idx[i] : i, c), i < rows, c < cols
+// (column-major, leading dimensions lds and ldd)
+__global__ void __launch_bounds__(256)
+scale_rows_kernel(const double* __restrict__ src, int64_t lds, const int32_t* __restrict__ idx, int rows,
+                  double alpha, double* __restrict__ dst, int64_t ldd) {
+  const int64_t c = blockIdx.y;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < rows; i += gridDim.x * blockDim.x)
+    dst[i + c * ldd] = alpha * src[(idx ? idx[i] : i) + c * lds];
+}
+isdf_status launch_scale_rows(hipStream_t s, const double* src, int64_t lds, const int32_t* idx, int rows,
+                              int cols, double alpha, double* dst, int64_t ldd) {
+  if (rows <= 0 || cols <= 0) return ISDF_OK;
+  const int bx = std::min((rows + 255) / 256, 64);
+  hipLaunchKernelGGL(scale_rows_kernel, dim3(bx, cols), dim3(256), 0, s, src, lds, idx, rows, alpha, dst, ldd);
+  ISDF_HIP_TRY(hipGetLastError());
+  return ISDF_OK;
+}
+
 __global__ void add_kernel(const double* a, const double* b, double* c, int64_t n, double sb) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)

@@ -173,6 +173,10 @@ def test_plan_errors():
     with pytest.raises(binding.IsdfError) as e:
         binding.Plan(tiny_system("one_atom"), w_storage=2)
     assert e.value.status == -1
+    for kw in (dict(phi_budget_mb=-1), dict(ri_rows=-5)):
+        with pytest.raises(binding.IsdfError) as e:
+            binding.Plan(tiny_system("one_atom"), **kw)
+        assert e.value.status == -1
     # a workspace needs an aligned pointer and a size (checked on the host)
     import ctypes as C
     s = binding._System()
