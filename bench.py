@@ -1,24 +1,30 @@
 #!/usr/bin/env python
 """Multigrid-ISDF fit + exchange build per SCF iteration on one MI355X.
 
-Default workload (--config 4, the largest configuration that fits one
-GPU's memory whole): 3x3x3 diamond supercell (216 atoms, N = 2808 basis
-functions), grids 40^3 / 80^3 / 160^3, 8 interpolation points per owned
-function (N_mu = 22464), 432 occupied orbitals, the learned selector
-trained on the 8- and 64-atom cells.  --config 2 runs the 64-atom cell
-(N = 832, grids 32^3 / 64^3 / 128^3, N_mu = 6656, 128 occupied), whose
-oracle values are stored for parity.
+Default workload (--config 5, the largest configuration): 4x4x3 diamond
+supercell (384 atoms) with +-0.05 Angstrom displacements, 44 functions per
+atom (8 s, 7 p, 3 d shells of exponents 0.1 2.5^k; N = 16,896), four
+grids 24x24x18 / 48x48x36 / 96x96x72 / 192x192x144, 5 interpolation points
+per owned function (N_mu = 77,568, the universal grid taking all of its
+10,368 points), 768 occupied orbitals.  The exchange is K C (occ-RI: the
+N x N matrix K is never formed; E_x = tr(C^T K C)), the metric W of the
+optimized path is held in FP32 and the basis values (1.1 TB over all
+domains) are streamed by domain group.  --config 4 runs the 216-atom cell
+(N = 2808, grids 40^3 / 80^3 / 160^3, N_mu = 22464, 432 occupied) and
+--config 2 the 64-atom cell (N = 832, grids 32^3 / 64^3 / 128^3, N_mu =
+6656, 128 occupied), whose oracle values are stored for parity; both build
+the full K from the factored density.
 
 A step is the whole hot path once: one isdf_fit (basis values, pivoted-
-Cholesky points, fitting functions, Coulomb metric) followed by 7
-isdf_exchange calls.  The paper amortises the fit over the SCF iterations
-with a weight of 1/7, so value = step time / 7 = t_fit/7 + t_K in seconds
-per SCF iteration (lower is better).  Inputs are generated once and are
-resident on the GPU before the timed region.
+Cholesky points, fitting functions, Coulomb metric) followed by 7 exchange
+builds.  The paper amortises the fit over the SCF iterations with a weight
+of 1/7, so value = step time / 7 = t_fit/7 + t_K in seconds per SCF
+iteration (lower is better).  Inputs are generated once and are resident on
+the GPU before the timed region.
 
 Two paths are timed on the same inputs:
-  reference  FP64 contractions, full pivoted-Cholesky selection (timed over
-             --ref-steps steps, default 2, after one warm-up: it is the
+  reference  FP64 contractions, full pivoted-Cholesky selection, W in FP64
+             (timed over --ref-steps steps after one warm-up: it is the
              accuracy and speed reference, not the headline)
   optimized  BF16-split (x6) contractions with FP32 accumulation carried in
              FP64, and the learned candidate selector (trained on the GPU in
@@ -26,10 +32,12 @@ Two paths are timed on the same inputs:
              differently displaced 64-atom cell), timed over exactly --steps
              steps after --warmup warm-ups
 The headline value is the optimized path when its E_x agrees with the
-reference to 1e-6 Ha/atom, else the reference path.  Also reported: the
-roofline position of the headline path's dominant kernel family (HIP events
-around each of its launches in the timed region), parity against the stored
-FP64-oracle result, and the oracle timed on a bounded sample on the host.
+reference to 1e-6 Ha/atom, else the reference path.  The last warm-up step
+of each path runs with every kernel family bracketed by HIP events (the
+per-family breakdown); the timed steps bracket only the dominant family,
+whose launches give the roofline figure.  Also reported: parity against the
+stored FP64-oracle result where there is one, and the oracle timed on a
+bounded sample on the host.
 """
 import argparse
 import json
@@ -173,7 +181,7 @@ def train_selector(torch, log):
     return w, [float(h) for h in hist]
 
 
-def cpu_baseline(sysm, sample_pts=4096, ex_scale=4):
+def cpu_baseline(sysm, sample_pts=4096, ex_scale=4, occ_ri=False):
     """FP64 oracle (as it stands) on a bounded sample of the same workload,
     extrapolated to one fit/7 + one exchange (seconds per SCF iteration).
 
@@ -190,7 +198,11 @@ def cpu_baseline(sysm, sample_pts=4096, ex_scale=4):
       coulomb    one 16-column batch of Poisson solves and W products per
                  level, scaled by the column count;
       exchange   the four-term K on a random instance with N_mu and N cut by
-                 ex_scale, scaled by 8 N_mu N^2 + 14 N_mu^2 N.
+                 ex_scale, scaled by 8 N_mu N^2 + 14 N_mu^2 N; with occ_ri, K C
+                 (the oracle's occ-RI form) with N_mu, N and n_occ cut by
+                 ex_scale, scaled by its products' 16 N_mu^2 n_occ + 14 N_mu N n_occ.
+    A domain that takes every one of its points (F = I) has no selection
+    or fit to time.
     """
     from oracle import basis, coulomb, exchange, isdf
     from oracle import plan as oplan
@@ -233,6 +245,8 @@ def cpu_baseline(sysm, sample_pts=4096, ex_scale=4):
         tf = time.perf_counter() - t
         w = len(g)
         est["basis"] += tb * scale * w
+        if sysm.n_mu_ratio > 0 and d.n_mu >= d.points.size:
+            continue  # every point taken, F = I
         est["select"] += tsel * scale * steps_all / steps_run * w
         est["fit"] += tf * work(d.points.size, d.n_mu, nG) / work(Phi.shape[0], len(piv), nG) * w
     rng = np.random.default_rng(0)
@@ -264,17 +278,31 @@ def cpu_baseline(sysm, sample_pts=4096, ex_scale=4):
     XN = rng.standard_normal((nmu, N)) * (rng.random((nmu, N)) < 0.5)
     W = rng.standard_normal((nmu, nmu))
     W = W + W.T
-    D = rng.standard_normal((N, N))
-    D = D @ D.T / N
-    t = time.perf_counter()
-    K = exchange.exchange_matrix(XL, XN, W, D)
-    exchange.exchange_energy(D, K)
-    t_ex = time.perf_counter() - t
+    if occ_ri:
+        o_all = int(sysm.n_occ)
+        o = max(o_all // ex_scale, 1)
+        Cr = rng.standard_normal((N, o)) / np.sqrt(N)
+        t = time.perf_counter()
+        KC = exchange.exchange_occ_ri(XL, XN, W, Cr)
+        float(np.sum(Cr * KC))
+        t_ex = time.perf_counter() - t
 
-    def ex_flops(m, n):
-        return 8.0 * m * n * n + 14.0 * m * m * n
+        def ri_flops(m, n, k):
+            return 16.0 * m * m * k + 14.0 * m * n * k
 
-    est["exchange"] = t_ex * ex_flops(nmu_all, N_all) / ex_flops(nmu, N)
+        est["exchange"] = t_ex * ri_flops(nmu_all, N_all, o_all) / ri_flops(nmu, N, o)
+    else:
+        D = rng.standard_normal((N, N))
+        D = D @ D.T / N
+        t = time.perf_counter()
+        K = exchange.exchange_matrix(XL, XN, W, D)
+        exchange.exchange_energy(D, K)
+        t_ex = time.perf_counter() - t
+
+        def ex_flops(m, n):
+            return 8.0 * m * n * n + 14.0 * m * m * n
+
+        est["exchange"] = t_ex * ex_flops(nmu_all, N_all) / ex_flops(nmu, N)
     t_fit_total = est["basis"] + est["select"] + est["fit"] + est["coulomb"]
     return {
         "value": round(t_fit_total / 7.0 + est["exchange"], 4),
@@ -286,8 +314,10 @@ def cpu_baseline(sysm, sample_pts=4096, ex_scale=4):
             f"basis, selection and fit on <= {sample_pts} evenly strided points of the universal "
             "domain and of one window per finer level (64 universal pivot steps, all window steps; "
             "scaled by points, step costs, the fit flop model and the window count), one 16-column "
-            "Poisson/W batch per level (scaled by column count), the four-term exchange on a "
-            f"random instance with N_mu and N cut {ex_scale}x (scaled by its flop count); the "
+            "Poisson/W batch per level (scaled by column count), the "
+            + ("occ-RI exchange K C on a random instance with N_mu, N and n_occ" if occ_ri
+               else "four-term exchange on a random instance with N_mu and N")
+            + f" cut {ex_scale}x (scaled by its flop count); the "
             f"oracle's plan ({t_plan:.1f} s) is setup, not timed"
         ),
         "stages_s": {k: round(v, 3) for k, v in est.items()},
@@ -305,6 +335,11 @@ WORKLOADS = {
     4: "cfg4: diamond 3x3x3 (216 atoms, +-0.05 A displacements), 13 functions/atom (N=2808), grids "
        "40^3/80^3/160^3, N_mu=8N=22464, n_occ=432, learned selector trained on the 8- and 64-atom "
        "cells; step = 1 fit + 7 exchange builds",
+    5: "cfg5: diamond 4x4x3 (384 atoms, +-0.05 A displacements), 44 functions/atom (8 s, 7 p, 3 d; "
+       "N=16896), grids 24x24x18/48x48x36/96x96x72/192x192x144, N_mu=5N capped (universal grid all "
+       "10368 points) = 77568, n_occ=768, W in FP32 on the optimized path, basis values streamed by "
+       "domain group, learned selector trained on the 8- and 64-atom cells; step = 1 fit + 7 occ-RI "
+       "exchange builds (K C)",
 }
 
 # Threshold-driven diamond cells of the studies: two levels split at
@@ -476,10 +511,11 @@ def study_scaling(torch, binding, log, reps_list=None, repeat=3):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", type=int, default=4, choices=[1, 2, 4])
-    ap.add_argument("--ref-steps", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (default 2 on the 384-atom cell, else 5)")
+    ap.add_argument("--warmup", type=int, default=None, help="warm-up steps (default 1 on the 384-atom cell, else 2)")
+    ap.add_argument("--config", type=int, default=5, choices=[1, 2, 4, 5])
+    ap.add_argument("--ref-steps", type=int, default=None,
+                    help="timed steps of the reference path (default 1 on the 384-atom cell, else 2)")
     ap.add_argument("--mlp-keep", type=float, default=2.0)
     ap.add_argument("--mlp-cutoff", type=float, default=None,
                     help="selector score cutoff (default: 0.001 for the 216-atom cell, 0.05 otherwise; "
@@ -496,6 +532,13 @@ def main():
     ap.add_argument("--cells", default="",
                     help="scaling study cells as repeats of the 8-atom cell, e.g. 4x3x3,4x4x4 (default 1x1x1 .. 3x3x3)")
     args = ap.parse_args()
+    big = args.config == 5
+    if args.steps is None:
+        args.steps = 2 if big else 5
+    if args.warmup is None:
+        args.warmup = 1 if big else 2
+    if args.ref_steps is None:
+        args.ref_steps = 1 if big else 2
     if args.copy_calibration:
         import torch
 
@@ -533,10 +576,13 @@ def main():
     torch.cuda.set_device(dev)
     s = config(args.config)
     stream = torch.cuda.current_stream(dev).cuda_stream
-    D = torch.tensor(s.D, dtype=torch.float64, device=dev)
-    K = torch.empty_like(D)
+    # the 384-atom cell's exchange is K C (occ-RI): no N x N matrix on the device
+    ri_head = args.config == 5
+    D = None if ri_head else torch.tensor(s.D, dtype=torch.float64, device=dev)
+    K = None if ri_head else torch.empty_like(D)
 
     Cocc = torch.tensor(s.C_occ, dtype=torch.float64, device=dev)
+    KC_head = torch.empty_like(Cocc)
     tune = TUNE_FILE if os.path.exists(TUNE_FILE) else None
 
     def run_path(plan, tag, occ=False, steps=None, warmup=None):
@@ -546,7 +592,9 @@ def main():
             fit = plan.fit()
             ex = None
             for _ in range(args.exchanges):
-                if occ:
+                if ri_head:
+                    _, ex = fit.exchange_occ_ri(Cocc, KC_head)
+                elif occ:
                     _, ex = fit.exchange_occ(Cocc, K)
                 else:
                     _, ex = fit.exchange(D, K)
@@ -555,12 +603,14 @@ def main():
             fit.close()
             return ex, n_mu, sel
 
-        for w in range(warmup):
+        # untimed steps; the last one (or one more when there are none) with
+        # every kernel family bracketed: the breakdown
+        for w in range(max(warmup, 1)):
+            last = w == max(warmup, 1) - 1
+            if last:
+                set_profile(plan, ALL_FAMILIES)
             ex, _, _ = step()
-            log(f"{tag} warmup {w} E_x={ex:.10f}")
-        # one untimed step with every kernel family bracketed: the breakdown
-        set_profile(plan, ALL_FAMILIES)
-        step()
+            log(f"{tag} {'warmup' if warmup else 'breakdown step'} {w} E_x={ex:.10f}")
         breakdown = kernel_stats(plan)
         stages = plan.stage_times()
         set_profile(plan, 0)
@@ -578,7 +628,7 @@ def main():
         timed = kernel_stats(plan)[dom]
         set_profile(plan, 0)
         ms = (t1 - t0) / steps * 1e3
-        if args.no_extra:
+        if args.no_extra or ri_head:  # with the occ-RI headline there is no full K to set beside it
             return dict(ms_per_step=ms, value=ms / args.exchanges / 1e3, E_x=ex, n_mu=n_mu,
                         stats=breakdown, stages=stages, selection=sel, dominant=dom, timed=timed,
                         occ_ri=None, universal=None, steps=steps)
@@ -618,7 +668,7 @@ def main():
                     stats=breakdown, stages=stages, selection=sel, dominant=dom, timed=timed,
                     occ_ri=occ_ri, universal=universal, steps=steps)
 
-    mlp_cutoff = args.mlp_cutoff if args.mlp_cutoff is not None else (0.001 if args.config == 4 else 0.05)
+    mlp_cutoff = args.mlp_cutoff if args.mlp_cutoff is not None else (0.001 if args.config >= 4 else 0.05)
     results = {}
     if args.paths in ("both", "reference"):
         plan = binding.Plan(s, stream=stream, tune_file=tune)
@@ -630,7 +680,8 @@ def main():
         weights, hist = train_selector(torch, log)
         plan = binding.Plan(s, stream=stream, precision=binding.MIXED_X6,
                             selector=binding.SEL_MLP, mlp_weights=weights, mlp_keep=args.mlp_keep,
-                            mlp_cutoff=mlp_cutoff, tune_file=tune)
+                            mlp_cutoff=mlp_cutoff, tune_file=tune,
+                            w_storage=binding.W_F32 if args.config == 5 else binding.W_F64)
         results["optimized"] = run_path(plan, "optimized", occ=True)
         plan.close()
 
@@ -687,7 +738,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle sample) ...")
-        cpu = cpu_baseline(s)
+        cpu = cpu_baseline(s, ex_scale=8 if ri_head else 4, occ_ri=ri_head)
 
     def summary(r):
         st = r["stages"]
@@ -736,8 +787,10 @@ def main():
             "n_basis": s.n_basis,
             "n_mu": head["n_mu"],
             "exchanges_per_fit": args.exchanges,
-            "headline_path": ("optimized (bf16-split x6 + learned selector, factored-density "
-                              "exchange)") if use_opt else "reference (fp64, full selection, dense D)",
+            "headline_path": ("optimized (bf16-split x6 + learned selector, " +
+                              ("W in FP32, occ-RI exchange K C)" if ri_head else "factored-density exchange)"))
+            if use_opt else ("reference (fp64, full selection, " +
+                             ("occ-RI exchange K C)" if ri_head else "dense D)")),
             "gemm_tile_table": os.path.relpath(tune, ROOT) if tune else None,
         },
         "paths": {k: summary(v) for k, v in results.items()},

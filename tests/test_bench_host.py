@@ -70,3 +70,18 @@ def test_traffic_figure_needs_the_measured_source(tmp_path, monkeypatch):
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     assert bench.measured_traffic(6) is None
     assert bench.measured_traffic(0) is None
+
+
+def test_cpu_baseline_both_exchange_forms():
+    """The bounded oracle sample runs for the full K and for K C, and an
+    all-point domain (F = I) adds no selection or fit time."""
+    import bench
+    from workloads import tiny_system
+
+    s = tiny_system("d_atom", grids=((6, 6, 6), (24, 24, 24)), n_occ=3)
+    s.n_mu_ratio = 30.0  # the universal domain takes its 216 points
+    for ri in (False, True):
+        r = bench.cpu_baseline(s, sample_pts=512, ex_scale=1, occ_ri=ri)
+        assert r["kind"] == "oracle" and r["value"] > 0 and r["cores"] >= 1
+        assert ("occ-RI" in r["sample"]) == ri
+        assert r["stages_s"]["select"] > 0  # the window still selects
