@@ -154,9 +154,9 @@ typedef struct {
                                  memory                                                   */
   int32_t ri_rows;            /* rows of Q = W o (E E^T) that isdf_exchange_occ_ri holds
                                  at once (row blocks of Z1, Z2; the result does not
-                                 depend on it).  0: all N_mu rows when they fit half of
-                                 the free memory, else blocks of a multiple of 256 rows
-                                 that fit 40 % of it                                      */
+                                 depend on it).  0: all N_mu rows when they fit a
+                                 quarter of the free memory, else blocks of a multiple
+                                 of 256 rows that fit 15 % of it                          */
 } isdf_options;
 /* Storage of the Coulomb metric W held by a fit. */
 enum { ISDF_W_F64 = 0, ISDF_W_F32 = 1 };
@@ -196,6 +196,13 @@ isdf_status isdf_grids_for_threshold(const double* lattice, int32_t n_shells,
  * workspace with which a plan of the same system and options repeats them
  * without allocating. */
 isdf_status isdf_plan_workspace_bytes(isdf_plan_t plan, size_t* bytes);
+
+/* Device blocks the plan has taken so far (hipMalloc calls, or carve-outs
+ * of the workspace): count, bytes and host milliseconds spent in them.  A
+ * plan keeps the blocks its fits and exchanges release and serves later
+ * requests of the same size from them, so repeated fits of one plan should
+ * add none (any arguments may be NULL). */
+isdf_status isdf_plan_alloc_stats(isdf_plan_t plan, int64_t* calls, double* bytes, double* ms);
 
 /* Sizes: number of basis functions N, total requested points N_mu, domains. */
 isdf_status isdf_plan_info(isdf_plan_t plan, int64_t* n_basis, int64_t* n_mu, int32_t* n_domains);

@@ -34,7 +34,7 @@ EXPORTED = [
     "isdf_fit_selection", "isdf_fit_features", "isdf_mlp_forward", "isdf_mlp_loss_grad",
     "isdf_mlp_train", "isdf_profile", "isdf_kernel_stats", "isdf_exchange_occ", "isdf_autotune",
     "isdf_fit_batch", "isdf_exchange_occ_ri", "isdf_grids_for_threshold", "isdf_exchange_universal",
-    "isdf_exchange_occ_ri_noalloc", "isdf_plan_workspace_bytes",
+    "isdf_exchange_occ_ri_noalloc", "isdf_plan_workspace_bytes", "isdf_plan_alloc_stats",
 ]
 NOALLOC_SCRATCH_MB = 32
 MLP_NPARAM = 5313
@@ -154,6 +154,7 @@ def load(required: bool = True):
     lib.isdf_exchange_universal.argtypes = [vp, vp, vp, C.c_int32, vp, C.POINTER(C.c_double)]
     lib.isdf_exchange_occ_ri_noalloc.argtypes = [vp, vp, vp, C.c_int32, vp, C.POINTER(C.c_double)]
     lib.isdf_plan_workspace_bytes.argtypes = [vp, C.POINTER(C.c_size_t)]
+    lib.isdf_plan_alloc_stats.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_double), C.POINTER(C.c_double)]
     lib.isdf_autotune.argtypes = [vp, C.c_int32, C.c_int32, C.c_char_p]
     lib.isdf_grids_for_threshold.argtypes = [C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_double),
                                              C.c_int32, C.POINTER(C.c_double), C.c_double,
@@ -169,7 +170,7 @@ def load(required: bool = True):
                  "isdf_mlp_forward", "isdf_mlp_loss_grad", "isdf_mlp_train", "isdf_profile",
                  "isdf_kernel_stats", "isdf_exchange_occ", "isdf_autotune", "isdf_fit_batch",
                  "isdf_exchange_occ_ri", "isdf_grids_for_threshold", "isdf_exchange_universal",
-                 "isdf_exchange_occ_ri_noalloc", "isdf_plan_workspace_bytes"):
+                 "isdf_exchange_occ_ri_noalloc", "isdf_plan_workspace_bytes", "isdf_plan_alloc_stats"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -262,6 +263,13 @@ class Plan:
         b = C.c_size_t()
         _check(load().isdf_plan_workspace_bytes(self.handle, C.byref(b)), "isdf_plan_workspace_bytes")
         return b.value
+
+    def alloc_stats(self) -> dict:
+        """Device blocks taken so far (isdf_plan_alloc_stats)."""
+        n, b, ms = C.c_int64(), C.c_double(), C.c_double()
+        _check(load().isdf_plan_alloc_stats(self.handle, C.byref(n), C.byref(b), C.byref(ms)),
+               "isdf_plan_alloc_stats")
+        return dict(calls=n.value, bytes=b.value, ms=ms.value)
 
     def autotune(self, n_occ: int, reps: int = 3, json_out=None):
         """Time every GEMM tile shape on this plan's problems (one fit and

@@ -20,6 +20,7 @@
 #include <cstring>
 #include <fstream>
 #include <functional>
+#include <chrono>
 #include <map>
 #include <sstream>
 #include <memory>
@@ -121,17 +122,24 @@ struct MemCtx {
     }
     arena_free[off] = len;
   }
+  // new device blocks so far: count, bytes and host time in the allocator
+  int64_t n_new = 0;
+  double new_bytes = 0.0, new_ms = 0.0;
   void* device_new(size_t r) {
     void* p = nullptr;
+    const auto t0 = std::chrono::steady_clock::now();
     if (arena) {
       p = arena_take(r);
     } else if (hipMalloc(&p, r) != hipSuccess) {
       (void)hipGetLastError();
       p = nullptr;
     }
+    new_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     if (p) {
       held += r;
       peak = std::max(peak, held);
+      ++n_new;
+      new_bytes += (double)r;
     }
     return p;
   }
@@ -155,8 +163,25 @@ struct MemCtx {
     *bytes = (double)free_b + (double)cached;
     return ISDF_OK;
   }
+  // Release one cached block.
+  void drop(std::multimap<size_t, void*>::iterator it) {
+    if (arena) arena_give(it->second, it->first);
+    else (void)hipFree(it->second);
+    held -= it->first;
+    cached -= it->first;
+    free_blocks.erase(it);
+  }
+  // Release the largest cached block (false when the cache is empty).
+  bool drop_largest() {
+    if (free_blocks.empty()) return false;
+    drop(std::prev(free_blocks.end()));
+    return true;
+  }
   // A cached block of at least `b` bytes (at most 1/8 larger for big ones),
-  // else a new one; on an allocation failure the cache is released first.
+  // else a new one.  When the device is full, the smallest cached block
+  // larger than the request is released first (the blocks of other sizes
+  // keep serving the buffers they were made for), then the largest ones
+  // until the allocation succeeds.
   void* get(size_t b, size_t* cap) {
     const size_t r = round(b);
     auto it = free_blocks.lower_bound(r);
@@ -168,11 +193,12 @@ struct MemCtx {
       return p;
     }
     void* p = device_new(r);
-    if (!p) {
-      trim();
+    if (!p && it != free_blocks.end()) {
+      drop(it);
       p = device_new(r);
-      if (!p) return nullptr;
     }
+    while (!p && drop_largest()) p = device_new(r);
+    if (!p) return nullptr;
     *cap = r;
     return p;
   }
@@ -255,6 +281,15 @@ struct DevBuf {
       return ISDF_E_NOMEM;
     }
     return ISDF_OK;
+  }
+  // Like alloc, but any block held already that is large enough is kept
+  // (work buffers reused across domain groups of varying size).
+  isdf_status reserve(size_t b) {
+    if (p && mem && mem == t_mem && b <= cap) {
+      bytes = b;
+      return ISDF_OK;
+    }
+    return alloc(b);
   }
   template <class T>
   T* as() const {
@@ -380,6 +415,9 @@ struct isdf_plan_s {
   // last two chunks of step launches, and the events that mark them
   SelState* crb_host = nullptr;
   hipEvent_t crb_ev[2] = {};
+  // device bytes each memory-sized rule assumed available the first time it
+  // ran (see plan_available)
+  std::map<int, double> avail_memo;
 };
 
 struct isdf_fit_s {
@@ -449,6 +487,24 @@ struct isdf_fit_s {
 };
 
 namespace {
+
+// Device bytes a buffer-sizing rule of the plan may assume available: free
+// memory plus the plan's cached blocks, measured the first time the rule
+// asks and kept, so that repeated fits and exchanges of the plan size their
+// buffers alike and take them back from its cache (a large allocation costs
+// far more than the kernels that fill it).
+enum { AVAIL_PHI = 0, AVAIL_COULOMB = 1, AVAIL_RI = 2, AVAIL_UNIVERSAL = 3 };
+isdf_status plan_available(isdf_plan_s* pl, int rule, double* bytes) {
+  auto it = pl->avail_memo.find(rule);
+  if (it != pl->avail_memo.end()) {
+    *bytes = it->second;
+    return ISDF_OK;
+  }
+  isdf_status st;
+  if ((st = pl->mem->available(bytes)) != ISDF_OK) return st;
+  pl->avail_memo[rule] = *bytes;
+  return ISDF_OK;
+}
 
 hipEvent_t prof_event(isdf_plan_s* pl) {
   if (pl->evnext == pl->evpool.size()) {
@@ -1192,6 +1248,7 @@ isdf_status compute_features(isdf_plan_s* pl, isdf_fit_s* f, float* feats, int g
 struct SelCtx {
   DevBuf cand;         // candidate lists, at pts_off[d] for domain d
   DevBuf feats, z;     // learned selector: features and scores of every point
+  DevBuf phic, diagc, pivc;  // compacted candidate rows of a group (kept across groups)
   std::vector<int32_t> nc_host;
   bool pinned = false, any_cand = false, any_learned = false;
 };
@@ -1411,11 +1468,12 @@ isdf_status sel_group(isdf_plan_s* pl, isdf_fit_s* f, SelCtx& cx, const std::vec
     max_nc = std::max(max_nc, g.nc);
     f->ncand[d] = g.nc;
   }
-  DevBuf d_gr, phic_b, diagc_b, pivc;
+  DevBuf d_gr;
+  DevBuf &phic_b = cx.phic, &diagc_b = cx.diagc, &pivc = cx.pivc;
   if ((st = upload(d_gr, gr)) != ISDF_OK) return st;
-  if ((st = phic_b.alloc(sizeof(double) * std::max<int64_t>(phic, 1))) != ISDF_OK) return st;
-  if ((st = diagc_b.alloc(sizeof(double) * std::max<int64_t>(dgc, 1))) != ISDF_OK) return st;
-  if ((st = pivc.alloc(sizeof(int32_t) * std::max<int64_t>(pvc, 1))) != ISDF_OK) return st;
+  if ((st = phic_b.reserve(sizeof(double) * std::max<int64_t>(phic, 1))) != ISDF_OK) return st;
+  if ((st = diagc_b.reserve(sizeof(double) * std::max<int64_t>(dgc, 1))) != ISDF_OK) return st;
+  if ((st = pivc.reserve(sizeof(int32_t) * std::max<int64_t>(pvc, 1))) != ISDF_OK) return st;
   if ((st = launch_gather_rows(s, d_gr.as<GatherRows>(), (int)gr.size(), max_nc, phi_base, f->diag0.as<double>(),
                                cand, phic_b.as<double>(), diagc_b.as<double>())) != ISDF_OK)
     return st;
@@ -1587,15 +1645,17 @@ isdf_status blocked_fit(isdf_plan_s* pl, const double* theta, int64_t pts, int n
 // W[rows of level l, chunk] = dV_l F_d^T V_l[P_d, chunk] is one wide grouped
 // GEMM per grid.  Chunk widths follow a memory budget; FFT batches follow the
 // size of the complex work buffers.
-isdf_status run_coulomb(isdf_plan_s* pl, isdf_fit_s* f) {
+// scratch (may be null): a device block the caller no longer needs (the
+// streamed basis values); when it is large enough it holds the FP64 W of an
+// FP32-stored metric, the potential slabs and the FFT work buffers, so that
+// none of them is allocated.
+isdf_status run_coulomb(isdf_plan_s* pl, isdf_fit_s* f, DevBuf* scratch = nullptr) {
   HostPlan& hp = pl->hp;
   hipStream_t s = pl->stream;
   const int nd = (int)hp.domains.size();
   const int64_t nmu = f->nmu;
   const int L = hp.n_levels;
   isdf_status st;
-  if ((st = f->W.alloc(sizeof(double) * nmu * nmu)) != ISDF_OK) return st;
-  if ((st = launch_fill(s, f->W.as<double>(), nmu * nmu, 0.0)) != ISDF_OK) return st;
   // global xi indices are contiguous per level
   std::vector<int64_t> lev_begin(L, -1), lev_end(L, -1);
   std::vector<int> col_dom(nmu), col_j(nmu);
@@ -1613,7 +1673,7 @@ isdf_status run_coulomb(isdf_plan_s* pl, isdf_fit_s* f) {
   // (free memory plus the plan's cached blocks, so that repeated fits size
   // their buffers alike and take them back from the cache)
   double avail = 0.0;
-  if ((st = pl->mem->available(&avail)) != ISDF_OK) return st;
+  if ((st = plan_available(pl, AVAIL_COULOMB, &avail)) != ISDF_OK) return st;
   const double v_budget = std::min(24e9, std::max(2e9, 0.45 * avail));
   const double z_budget = std::min(4e9, std::max(2.5e8, 0.05 * avail));
   struct Chunk {
@@ -1648,9 +1708,37 @@ isdf_status run_coulomb(isdf_plan_s* pl, isdf_fit_s* f) {
   int64_t ngz_max = 0;
   for (auto& c : chunks) ngz_max = std::max(ngz_max, level_ng(hp, c.lp));
   int64_t fft_pairs = std::max<int64_t>(1, (int64_t)(z_budget / (16.0 * ngz_max)));
-  if ((st = zf.alloc(sizeof(double) * 2 * ngz_max * fft_pairs)) != ISDF_OK) return st;
-  if ((st = zc.alloc(sizeof(double) * 2 * ngz_max * fft_pairs)) != ISDF_OK) return st;
-  if ((st = V.alloc(sizeof(double) * std::max<int64_t>(vmax, 1))) != ISDF_OK) return st;
+  // W (FP64), V, zf, zc: carved from the scratch block when it holds them
+  const bool w_transient = pl->opts.w_storage == ISDF_W_F32;
+  auto a256 = [](size_t b) { return (b + 255) / 256 * 256; };
+  const size_t b_w = sizeof(double) * nmu * nmu, b_z = sizeof(double) * 2 * ngz_max * fft_pairs,
+               b_v = sizeof(double) * std::max<int64_t>(vmax, 1);
+  const size_t need = (w_transient ? a256(b_w) : 0) + a256(b_v) + 2 * a256(b_z);
+  double *Wd = nullptr, *Vd = nullptr, *zfd = nullptr, *zcd = nullptr;
+  if (scratch && scratch->p && scratch->cap >= need) {
+    char* q = static_cast<char*>(scratch->p);
+    if (w_transient) {
+      Wd = reinterpret_cast<double*>(q);
+      q += a256(b_w);
+    }
+    Vd = reinterpret_cast<double*>(q);
+    q += a256(b_v);
+    zfd = reinterpret_cast<double*>(q);
+    q += a256(b_z);
+    zcd = reinterpret_cast<double*>(q);
+  } else {
+    if ((st = zf.alloc(b_z)) != ISDF_OK) return st;
+    if ((st = zc.alloc(b_z)) != ISDF_OK) return st;
+    if ((st = V.alloc(b_v)) != ISDF_OK) return st;
+    zfd = zf.as<double>();
+    zcd = zc.as<double>();
+    Vd = V.as<double>();
+  }
+  if (!Wd) {
+    if ((st = f->W.alloc(b_w)) != ISDF_OK) return st;
+    Wd = f->W.as<double>();
+  }
+  if ((st = launch_fill(s, Wd, nmu * nmu, 0.0)) != ISDF_OK) return st;
   std::vector<GemmProblem> probs;
   struct GemmLaunch {
     int level, off, cnt, tiles, shape;
@@ -1668,28 +1756,39 @@ isdf_status run_coulomb(isdf_plan_s* pl, isdf_fit_s* f) {
         // all-point domains (F = I) take their rows of the potentials as they are
         if (hp.domains[d].level != l || f->count[d] == 0 || f->mode[d] == 3) continue;
         const HostDomain& D = hp.domains[d];
+        // same level: only the columns from the domain's own xi on (each
+        // pair of different domains once, mirrored by the symmetrisation)
+        const int64_t cs = l == ch.lp ? std::max<int64_t>(ch.c0, f->xoff[d]) : ch.c0;
+        if (cs >= ch.c1) continue;
         GemmProblem p{};
         p.A = f->F.as<double>() + f->th_off[d];
         p.lda = (int64_t)D.points.size();
         p.transA = 1;
-        p.B = V.as<double>() + voff;
+        p.B = Vd + voff + (cs - ch.c0) * level_ng(hp, l);
         p.ldb = level_ng(hp, l);
         p.bidx = ((int64_t)D.points.size() == level_ng(hp, l) && D.atom < 0)
                      ? nullptr
                      : pl->d_points.as<int32_t>() + pl->pts_off[d];
-        p.C = f->W.as<double>() + f->xoff[d] + ch.c0 * nmu;
+        p.C = Wd + f->xoff[d] + cs * nmu;
         p.ldc = nmu;
         p.M = f->count[d];
-        p.N = (int)(ch.c1 - ch.c0);
+        p.N = (int)(ch.c1 - cs);
         p.K = (int)D.points.size();
         p.alpha = dV;
         p.beta = 0.0;
         lp_probs.push_back(p);
       }
+      // window rows (gathered potentials): tiles 128 columns wide, and tall
+      // enough for the whole row count up to 128, so that the gathered rows
+      // of V are read once per column tile (they dominate the traffic)
+      auto metric_shape = [](const GemmProblem& p) {
+        if (!p.bidx) return gemm_default_shape(EPI_AXPBY, p.M, p.N, p.K);
+        return p.M <= 64 ? 4 : p.M <= 128 ? 2 : gemm_default_shape(EPI_AXPBY, p.M, p.N, p.K);
+      };
       for (int shape = 0; shape < GEMM_NSHAPE; ++shape) {
         GemmLaunch gl{l, (int)probs.size(), 0, 0, shape, 0.0, 0.0};
         for (GemmProblem p : lp_probs) {
-          if (gemm_default_shape(EPI_AXPBY, p.M, p.N, p.K) != shape) continue;
+          if (metric_shape(p) != shape) continue;
           p.tile_start = gl.tiles;
           gl.tiles += gemm_tiles(p.M, p.N, shape);
           gl.bytes += gemm_bytes(p);
@@ -1801,7 +1900,7 @@ isdf_status run_coulomb(isdf_plan_s* pl, isdf_fit_s* f) {
           touched[2] += (double)g[0] * g[1] * (P.box[5] + g[2]);
         }
         FftEvents fe(pl);
-        if ((st = fft_forward_pruned(s, zf.as<double>(), d_fpairs.as<FwdPair>() + poff,
+        if ((st = fft_forward_pruned(s, zfd, d_fpairs.as<FwdPair>() + poff,
                                      d_fcols.as<FwdCol>(), npairs, hp.grid[lp], max_yz, max_z, fe.ev())) !=
             ISDF_OK)
           return st;
@@ -1809,37 +1908,37 @@ isdf_status run_coulomb(isdf_plan_s* pl, isdf_fit_s* f) {
       } else {
         int max_n = 0;
         for (int64_t c = b0; c < b0 + ncols; ++c) max_n = std::max(max_n, scat[c].n);
-        if ((st = launch_fill(s, zf.as<double>(), 2 * ngp * npairs, 0.0)) != ISDF_OK) return st;
-        if ((st = launch_scatter_cols(s, d_scat.as<ScatterCol>() + b0, ncols, max_n, zf.as<double>(),
+        if ((st = launch_fill(s, zfd, 2 * ngp * npairs, 0.0)) != ISDF_OK) return st;
+        if ((st = launch_scatter_cols(s, d_scat.as<ScatterCol>() + b0, ncols, max_n, zfd,
                                       ngp)) != ISDF_OK)
           return st;
-        if ((st = fft_prof(pl, zf.as<double>(), npairs, hp.grid[lp], -1)) != ISDF_OK) return st;
+        if ((st = fft_prof(pl, zfd, npairs, hp.grid[lp], -1)) != ISDF_OK) return st;
       }
       int64_t voff = 0;
       for (int l = 0; l <= lp; ++l) {
         const int64_t ng = level_ng(hp, l);
-        double* vout = V.as<double>() + voff + (b0 - ch.c0) * ng;
+        double* vout = Vd + voff + (b0 - ch.c0) * ng;
         bool fused = false;
         {  // Poisson step, inverse transform and planar split in three passes
           FftEvents fe(pl);
-          if ((st = fft_poisson_inverse(s, zf.as<double>(), hp.grid[lp], zc.as<double>(), hp.grid[l],
+          if ((st = fft_poisson_inverse(s, zfd, hp.grid[lp], zcd, hp.grid[l],
                                         npairs, pl->recip, vout, ncols, &fused, fe.ev())) != ISDF_OK)
             return st;
           const double pass_bytes = 32.0 * (double)ng * npairs;
           if (fused) fe.commit({pass_bytes, pass_bytes, pass_bytes});
         }
         if (!fused) {
-          if ((st = launch_poisson_restrict(s, zf.as<double>(), hp.grid[lp], zc.as<double>(),
+          if ((st = launch_poisson_restrict(s, zfd, hp.grid[lp], zcd,
                                             hp.grid[l], npairs, pl->recip)) != ISDF_OK)
             return st;
-          if ((st = fft_prof(pl, zc.as<double>(), npairs, hp.grid[l], +1)) != ISDF_OK) return st;
-          if ((st = launch_split_planar(s, zc.as<double>(), ng, ncols, vout)) != ISDF_OK) return st;
+          if ((st = fft_prof(pl, zcd, npairs, hp.grid[l], +1)) != ISDF_OK) return st;
+          if ((st = launch_split_planar(s, zcd, ng, ncols, vout)) != ISDF_OK) return st;
         }
         voff += ng * (ch.c1 - ch.c0);
       }
     }
     if (f->all_points) {  // level-0 potentials of this chunk sit first in V
-      if ((st = launch_scale_copy(s, V.as<double>(), f->WUw.as<double>() + ch.c0 * ng0, ng0 * (ch.c1 - ch.c0),
+      if ((st = launch_scale_copy(s, Vd, f->WUw.as<double>() + ch.c0 * ng0, ng0 * (ch.c1 - ch.c0),
                                   hp.volume / (double)ng0)) != ISDF_OK)
         return st;
     }
@@ -1851,10 +1950,10 @@ isdf_status run_coulomb(isdf_plan_s* pl, isdf_fit_s* f) {
           if (hp.domains[d].level != l || f->count[d] == 0 || f->mode[d] != 3) continue;
           const HostDomain& D = hp.domains[d];
           const bool whole = (int64_t)D.points.size() == ng && D.atom < 0;
-          if ((st = launch_scale_rows(s, V.as<double>() + voff, ng,
+          if ((st = launch_scale_rows(s, Vd + voff, ng,
                                       whole ? nullptr : pl->d_points.as<int32_t>() + pl->pts_off[d],
                                       (int)D.points.size(), (int)(ch.c1 - ch.c0), hp.volume / (double)ng,
-                                      f->W.as<double>() + f->xoff[d] + ch.c0 * nmu, nmu)) != ISDF_OK)
+                                      Wd + f->xoff[d] + ch.c0 * nmu, nmu)) != ISDF_OK)
             return st;
         }
         voff += ng * (ch.c1 - ch.c0);
@@ -1863,10 +1962,10 @@ isdf_status run_coulomb(isdf_plan_s* pl, isdf_fit_s* f) {
     for (const GemmLaunch& gl : glaunch[ci]) {
       if (gl.level == 0 && w_mixed) {
         const int w = (int)(ch.c1 - ch.c0);
-        if ((st = make_planes(s, mixed_splits(pl), V.as<double>(), ng0, 1, nullptr, w, (int)ng0, Vp0)) !=
+        if ((st = make_planes(s, mixed_splits(pl), Vd, ng0, 1, nullptr, w, (int)ng0, Vp0)) !=
             ISDF_OK)
           return st;
-        MixedProblem mp = mixed_problem(Fp0, Vp0, f->W.as<double>() + f->xoff[0] + ch.c0 * nmu, nmu,
+        MixedProblem mp = mixed_problem(Fp0, Vp0, Wd + f->xoff[0] + ch.c0 * nmu, nmu,
                                         f->count[0], w, (int)ng0, hp.volume / (double)ng0, 0.0,
                                         nullptr, 0);
         if ((st = mixed_prof(pl, ISDF_K_GEMM_METRIC, EPI_AXPBY, mp)) != ISDF_OK) return st;
@@ -1882,18 +1981,25 @@ isdf_status run_coulomb(isdf_plan_s* pl, isdf_fit_s* f) {
         return st;
     }
   }
-  // level of each xi, then symmetrise
+  // level and domain of each xi, then symmetrise
   std::vector<int8_t> lev(nmu);
+  std::vector<int32_t> xdom(nmu);
   for (int d = 0; d < nd; ++d)
-    for (int j = 0; j < f->count[d]; ++j) lev[f->xoff[d] + j] = (int8_t)hp.domains[d].level;
+    for (int j = 0; j < f->count[d]; ++j) {
+      lev[f->xoff[d] + j] = (int8_t)hp.domains[d].level;
+      xdom[f->xoff[d] + j] = d;
+    }
+  DevBuf d_xdom;
   if ((st = upload(f->lev, lev)) != ISDF_OK) return st;
-  if ((st = launch_symmetrize_w(s, f->W.as<double>(), nmu, f->lev.as<int8_t>())) != ISDF_OK)
+  if ((st = upload(d_xdom, xdom)) != ISDF_OK) return st;
+  if ((st = launch_symmetrize_w(s, Wd, nmu, f->lev.as<int8_t>(), d_xdom.as<int32_t>())) !=
+      ISDF_OK)
     return st;
   if (pl->opts.w_storage == ISDF_W_F32) {  // keep W in FP32 from here on
     if ((st = f->W32.alloc(sizeof(float) * std::max<int64_t>(nmu * nmu, 1))) != ISDF_OK) return st;
-    if ((st = launch_narrow(s, f->W.as<double>(), f->W32.as<float>(), nmu * nmu)) != ISDF_OK) return st;
+    if ((st = launch_narrow(s, Wd, f->W32.as<float>(), nmu * nmu)) != ISDF_OK) return st;
     ISDF_HIP_TRY(hipStreamSynchronize(s));
-    f->W.release();
+    f->W.release();  // (nothing held when W sat in the scratch block)
     f->w32 = true;
   }
   ISDF_HIP_TRY(hipStreamSynchronize(s));
@@ -1982,7 +2088,7 @@ isdf_status do_fit(isdf_plan_s* pl, const int64_t* pinned, const int64_t* cand_i
     budget = 1048576.0 * pl->opts.phi_budget_mb;
   } else {
     double avail = 0.0;
-    if ((st = pl->mem->available(&avail)) != ISDF_OK) return st;
+    if ((st = plan_available(pl, AVAIL_PHI, &avail)) != ISDF_OK) return st;
     budget = 0.4 * avail;
   }
   const std::vector<std::pair<int, int>> groups =
@@ -2048,7 +2154,7 @@ isdf_status do_fit(isdf_plan_s* pl, const int64_t* pinned, const int64_t* cand_i
     if ((st = sel_group(pl, f.get(), cx, f->mode, g.first, g.second, phi_base)) != ISDF_OK) return st;
   }
   if ((st = clk.end()) != ISDF_OK) return st;
-  for (DevBuf* b : {&cx.cand, &cx.feats, &cx.z}) b->release();  // no longer needed
+  for (DevBuf* b : {&cx.cand, &cx.feats, &cx.z, &cx.phic, &cx.diagc, &cx.pivc}) b->release();  // no longer needed
   bool rank_short = false;
   f->xoff.assign(nd, 0);
   int64_t nmu = 0;
@@ -2233,14 +2339,15 @@ isdf_status do_fit(isdf_plan_s* pl, const int64_t* pinned, const int64_t* cand_i
   if ((st = clk.next(2)) != ISDF_OK) return st;
   if ((st = launch_add(s, f->XL.as<double>(), f->XN.as<double>(), f->XG.as<double>(), nmu * N)) != ISDF_OK)
     return st;
-  if (streamed) {  // the basis values of the last group are not kept
+  // 6. Coulomb metric (a streamed fit keeps no basis values: their block
+  // serves as the metric's work space and is released afterwards)
+  if ((st = clk.next(5)) != ISDF_OK) return st;
+  if ((st = run_coulomb(pl, f.get(), streamed ? &f->phi : nullptr)) != ISDF_OK) return st;
+  if ((st = clk.end()) != ISDF_OK) return st;
+  if (streamed) {
     ISDF_HIP_TRY(hipStreamSynchronize(s));
     f->phi.release();
   }
-  // 6. Coulomb metric
-  if ((st = clk.next(5)) != ISDF_OK) return st;
-  if ((st = run_coulomb(pl, f.get())) != ISDF_OK) return st;
-  if ((st = clk.end()) != ISDF_OK) return st;
   ISDF_HIP_TRY(hipStreamSynchronize(s));
   prof_collect(pl);
   int32_t spd_flag = 0;
@@ -2336,8 +2443,9 @@ isdf_status write_tune_file(const isdf_plan_s* pl, const char* path) {
 // Everything the kernel sequence touches is sized here, so that the
 // sequence itself allocates nothing and can be captured as a graph.
 // Rows of Q held at once by the occ-RI exchange: all N_mu when the full Q
-// buffers fit half of the free memory, else row blocks (multiples of 256)
-// that fit 40 % of it.  The dense exchange always holds all rows.
+// buffers fit a quarter of the free memory, else row blocks (multiples of
+// 256) that fit 15 % of it (the fit's own blocks stay cached beside them).
+// The dense exchange always holds all rows.
 isdf_status ri_q_rows(isdf_plan_s* plan, isdf_fit_s* fit, bool mixed, int64_t* rows) {
   const int64_t m = fit->nmu;
   if (plan->opts.ri_rows > 0) {
@@ -2346,15 +2454,15 @@ isdf_status ri_q_rows(isdf_plan_s* plan, isdf_fit_s* fit, bool mixed, int64_t* r
   }
   double avail = 0.0;
   isdf_status st;
-  if ((st = plan->mem->available(&avail)) != ISDF_OK) return st;
+  if ((st = plan_available(plan, AVAIL_RI, &avail)) != ISDF_OK) return st;
   const double ld2 = (double)((2 * m + 7) / 8 * 8);
   const double full = mixed ? 2.0 * mixed_splits(plan) * m * ld2 * 2.0 : 3.0 * 8.0 * m * m;
   const double per_row = mixed ? 2.0 * mixed_splits(plan) * ld2 * 2.0 : 4.0 * 8.0 * m;
-  if (full <= 0.5 * avail) {
+  if (full <= 0.25 * avail) {
     *rows = m;
     return ISDF_OK;
   }
-  int64_t r = (int64_t)(0.4 * avail / per_row) / 256 * 256;
+  int64_t r = (int64_t)(0.15 * avail / per_row) / 256 * 256;
   *rows = std::min<int64_t>(m, std::max<int64_t>(256, r));
   return ISDF_OK;
 }
@@ -2925,7 +3033,7 @@ isdf_status universal_terms(isdf_plan_s* pl, isdf_fit_s* f, const double* C, int
   // free memory); a tile holds at least one row
   double avail = 0.0;
   {
-    const isdf_status sa = pl->mem->available(&avail);
+    const isdf_status sa = plan_available(pl, AVAIL_UNIVERSAL, &avail);
     if (sa != ISDF_OK) return sa;
   }
   const double v_budget = pl->opts.universal_tile_mb > 0 ? (double)pl->opts.universal_tile_mb * (1 << 20)
@@ -3304,6 +3412,17 @@ isdf_status isdf_plan_workspace_bytes(isdf_plan_t plan, size_t* bytes) {
     return ISDF_E_ARG;
   }
   *bytes = plan->mem ? plan->mem->peak : 0;
+  return ISDF_OK;
+}
+
+isdf_status isdf_plan_alloc_stats(isdf_plan_t plan, int64_t* calls, double* bytes, double* ms) {
+  if (!plan) {
+    set_error("isdf_plan_alloc_stats: null plan");
+    return ISDF_E_ARG;
+  }
+  if (calls) *calls = plan->mem->n_new;
+  if (bytes) *bytes = plan->mem->new_bytes;
+  if (ms) *ms = plan->mem->new_ms;
   return ISDF_OK;
 }
 

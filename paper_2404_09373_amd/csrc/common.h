@@ -301,7 +301,7 @@ isdf_status launch_split_planar(hipStream_t s, const double* z, int64_t ng, int 
 isdf_status fft_poisson_inverse(hipStream_t s, const double* zf, const int gf[3], double* zc,
                                 const int gc[3], int npairs, const double B[9], double* V,
                                 int ncols, bool* done, hipEvent_t* ev = nullptr);
-isdf_status launch_symmetrize_w(hipStream_t s, double* W, int64_t nmu, const int8_t* lev);
+isdf_status launch_symmetrize_w(hipStream_t s, double* W, int64_t nmu, const int8_t* lev, const int32_t* dom);
 isdf_status launch_add(hipStream_t s, const double* a, const double* b, double* c, int64_t n);
 isdf_status launch_sub(hipStream_t s, const double* a, const double* b, double* c, int64_t n);  // c = a - b
 isdf_status launch_trace_dot(hipStream_t s, const double* a, const double* b, int64_t n,

@@ -393,6 +393,7 @@ bool launch_fixed(hipStream_t s, double2* z, int batch, int n1, int n2, int n3, 
                   double sign, const double2* tw, int n, int lpw, int64_t groups) {
   switch (n) {
     case 12: return launch_fixed_n<12>(s, z, batch, n1, n2, n3, axis, sign, tw, lpw, groups);
+    case 18: return launch_fixed_n<18>(s, z, batch, n1, n2, n3, axis, sign, tw, lpw, groups);
     case 36: return launch_fixed_n<36>(s, z, batch, n1, n2, n3, axis, sign, tw, lpw, groups);
     case 72: return launch_fixed_n<72>(s, z, batch, n1, n2, n3, axis, sign, tw, lpw, groups);
     case 100: return launch_fixed_n<100>(s, z, batch, n1, n2, n3, axis, sign, tw, lpw, groups);
@@ -404,8 +405,22 @@ bool launch_fixed(hipStream_t s, double2* z, int batch, int n1, int n2, int n3, 
     case 80: return launch_fixed_n<80>(s, z, batch, n1, n2, n3, axis, sign, tw, lpw, groups);
     case 96: return launch_fixed_n<96>(s, z, batch, n1, n2, n3, axis, sign, tw, lpw, groups);
     case 128: return launch_fixed_n<128>(s, z, batch, n1, n2, n3, axis, sign, tw, lpw, groups);
+    case 144: return launch_fixed_n<144>(s, z, batch, n1, n2, n3, axis, sign, tw, lpw, groups);
     case 160: return launch_fixed_n<160>(s, z, batch, n1, n2, n3, axis, sign, tw, lpw, groups);
+    case 192: return launch_fixed_n<192>(s, z, batch, n1, n2, n3, axis, sign, tw, lpw, groups);
     default: return false;
+  }
+}
+
+// Line lengths of the fused Poisson / planar passes and of the pruned
+// forward transform (every one also has a launch_fixed case).
+static bool fused_len(int n) {
+  switch (n) {
+    case 18: case 24: case 32: case 36: case 40: case 48: case 64: case 72: case 80: case 96: case 128:
+    case 144: case 160: case 192:
+      return true;
+    default:
+      return false;
   }
 }
 
@@ -610,11 +625,7 @@ isdf_status fft_poisson_inverse(hipStream_t s, const double* zf, const int gf[3]
                                 const int gc[3], int npairs, const double B[9], double* V,
                                 int ncols, bool* done, hipEvent_t* ev) {
   *done = false;
-  auto fixed = [](int n) {
-    return n == 24 || n == 32 || n == 40 || n == 48 || n == 64 || n == 80 || n == 96 || n == 128 ||
-           n == 160;
-  };
-  if (npairs <= 0 || !fixed(gc[0]) || !fixed(gc[1]) || !fixed(gc[2]) || gc[0] % 8) return ISDF_OK;
+  if (npairs <= 0 || !fused_len(gc[0]) || !fused_len(gc[1]) || !fused_len(gc[2]) || gc[0] % 8) return ISDF_OK;
   PoissonArg a;
   for (int i = 0; i < 3; ++i) {
     a.gf[i] = gf[i];
@@ -647,8 +658,14 @@ isdf_status fft_poisson_inverse(hipStream_t s, const double* zf, const int gf[3]
     case 64: launch_poisson_x<64>(s, z, npairs, gc, tw0, f, a, gx); break;
     case 80: launch_poisson_x<80>(s, z, npairs, gc, tw0, f, a, gx); break;
     case 96: launch_poisson_x<96>(s, z, npairs, gc, tw0, f, a, gx); break;
+    case 72: launch_poisson_x<72>(s, z, npairs, gc, tw0, f, a, gx); break;
     case 128: launch_poisson_x<128>(s, z, npairs, gc, tw0, f, a, gx); break;
-    default: launch_poisson_x<160>(s, z, npairs, gc, tw0, f, a, gx); break;
+    case 144: launch_poisson_x<144>(s, z, npairs, gc, tw0, f, a, gx); break;
+    case 160: launch_poisson_x<160>(s, z, npairs, gc, tw0, f, a, gx); break;
+    case 192: launch_poisson_x<192>(s, z, npairs, gc, tw0, f, a, gx); break;
+    default:
+      set_error("fft: no compiled x pass for the Poisson step");
+      return ISDF_E_ARG;
   }
   ISDF_HIP_TRY(hipGetLastError());
   if ((st = mark(1)) != ISDF_OK) return st;
@@ -670,7 +687,12 @@ isdf_status fft_poisson_inverse(hipStream_t s, const double* zf, const int gf[3]
   const int zlpw = gc[0] % 16 == 0 ? 16 : 8;
   if ((st = mark(4)) != ISDF_OK) return st;
   switch (gc[2]) {
+    case 18: launch_planar_z<18>(s, z, npairs, gc, tw2, V, ncols, zlpw); break;
     case 24: launch_planar_z<24>(s, z, npairs, gc, tw2, V, ncols, zlpw); break;
+    case 36: launch_planar_z<36>(s, z, npairs, gc, tw2, V, ncols, zlpw); break;
+    case 72: launch_planar_z<72>(s, z, npairs, gc, tw2, V, ncols, zlpw); break;
+    case 144: launch_planar_z<144>(s, z, npairs, gc, tw2, V, ncols, zlpw); break;
+    case 192: launch_planar_z<192>(s, z, npairs, gc, tw2, V, ncols, zlpw); break;
     case 32: launch_planar_z<32>(s, z, npairs, gc, tw2, V, ncols, zlpw); break;
     case 40: launch_planar_z<40>(s, z, npairs, gc, tw2, V, ncols, zlpw); break;
     case 48: launch_planar_z<48>(s, z, npairs, gc, tw2, V, ncols, zlpw); break;
@@ -678,7 +700,10 @@ isdf_status fft_poisson_inverse(hipStream_t s, const double* zf, const int gf[3]
     case 80: launch_planar_z<80>(s, z, npairs, gc, tw2, V, ncols, zlpw); break;
     case 96: launch_planar_z<96>(s, z, npairs, gc, tw2, V, ncols, zlpw); break;
     case 128: launch_planar_z<128>(s, z, npairs, gc, tw2, V, ncols, zlpw); break;
-    default: launch_planar_z<160>(s, z, npairs, gc, tw2, V, ncols, zlpw); break;
+    case 160: launch_planar_z<160>(s, z, npairs, gc, tw2, V, ncols, zlpw); break;
+    default:
+      set_error("fft: no compiled z pass for the planar potentials");
+      return ISDF_E_ARG;
   }
   ISDF_HIP_TRY(hipGetLastError());
   if ((st = mark(5)) != ISDF_OK) return st;
@@ -800,7 +825,12 @@ template <int AXIS>
 bool fwd_pass(hipStream_t s, double2* z, const FwdPair* pairs, const FwdCol* cols, int npairs,
               const int g[3], const double2* tw, int n, int gx) {
   switch (n) {
+    case 18: launch_fwd_pruned<18, AXIS>(s, z, pairs, cols, npairs, g, tw, gx); return true;
     case 24: launch_fwd_pruned<24, AXIS>(s, z, pairs, cols, npairs, g, tw, gx); return true;
+    case 36: launch_fwd_pruned<36, AXIS>(s, z, pairs, cols, npairs, g, tw, gx); return true;
+    case 72: launch_fwd_pruned<72, AXIS>(s, z, pairs, cols, npairs, g, tw, gx); return true;
+    case 144: launch_fwd_pruned<144, AXIS>(s, z, pairs, cols, npairs, g, tw, gx); return true;
+    case 192: launch_fwd_pruned<192, AXIS>(s, z, pairs, cols, npairs, g, tw, gx); return true;
     case 32: launch_fwd_pruned<32, AXIS>(s, z, pairs, cols, npairs, g, tw, gx); return true;
     case 40: launch_fwd_pruned<40, AXIS>(s, z, pairs, cols, npairs, g, tw, gx); return true;
     case 48: launch_fwd_pruned<48, AXIS>(s, z, pairs, cols, npairs, g, tw, gx); return true;
@@ -814,11 +844,7 @@ bool fwd_pass(hipStream_t s, double2* z, const FwdPair* pairs, const FwdCol* col
 }
 
 bool fft_forward_pruned_supported(const int g[3]) {
-  auto fixed = [](int n) {
-    return n == 24 || n == 32 || n == 40 || n == 48 || n == 64 || n == 80 || n == 96 || n == 128 ||
-           n == 160;
-  };
-  return fixed(g[0]) && fixed(g[1]) && fixed(g[2]) && g[0] % 8 == 0;
+  return fused_len(g[0]) && fused_len(g[1]) && fused_len(g[2]) && g[0] % 8 == 0;
 }
 
 isdf_status fft_forward_pruned(hipStream_t s, double* zr, const FwdPair* pairs, const FwdCol* cols,

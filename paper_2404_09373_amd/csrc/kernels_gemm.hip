@@ -85,6 +85,7 @@ struct TileLoader {
   int64_t ca, cb;    // pointer step per chunk
   int am, ak, bn, bk;  // this thread's tile coordinates of slot 0
   bool a_ok[NA], b_ok[NB];  // row/column inside the problem (slot-wise)
+  int32_t nrow;        // gathered B rows: this thread's row of the chunk loaded next
 
   __device__ void init(const GemmProblem& p, int m0, int n0, int tid) {
     if (!p.transA) {  // A(m, k) at m + k lda: m fastest
@@ -112,6 +113,7 @@ struct TileLoader {
       cb = BK;
 #pragma unroll
       for (int r = 0; r < NB; ++r) b_ok[r] = n0 + bn + (NT / BK) * r < p.N;
+      nrow = (p.bidx && bk < p.K) ? gldi(p.bidx + bk) : 0;
     } else {  // B(k, n) at n + k ldb: n fastest
       bn = tid % BN_;
       bk = tid / BN_;
@@ -140,7 +142,13 @@ struct TileLoader {
     if (!p.transB) {
       const bool kok = kfull || k0 + bk < p.K;
       int64_t row = k0 + bk;
-      if (p.bidx && kok) row = gldi(p.bidx + k0 + bk);
+      if (p.bidx) {
+        // the row index was read one chunk ahead, so the value loads below do
+        // not wait for an index load; read the next chunk's now
+        row = nrow;
+        const int kn = k0 + BK + bk;
+        nrow = kn < p.K ? gldi(p.bidx + kn) : 0;
+      }
 #pragma unroll
       for (int r = 0; r < NB; ++r) rb[r] = (b_ok[r] && kok) ? gld(pb + row + r * sb) : 0.0;
     } else {

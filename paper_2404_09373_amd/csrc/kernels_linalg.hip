@@ -269,26 +269,26 @@ isdf_status launch_gather_square(hipStream_t s, const double* theta, int64_t pts
 
 // W symmetrisation: entries of two same-level xi are formed in both orders
 // and averaged; a coarser-row entry is mirrored to its finer-row partner.
-__global__ void symmetrize_w_kernel(double* W, int64_t nmu, const int8_t* lev) {
+__global__ void symmetrize_w_kernel(double* W, int64_t nmu, const int8_t* lev, const int32_t* dom) {
   const int64_t j = blockIdx.x;
   for (int64_t i = threadIdx.x; i < j; i += blockDim.x) {
     const int li = lev[i], lj = lev[j];
     double* wij = W + i + j * nmu;
     double* wji = W + j + i * nmu;
-    if (li == lj) {
+    if (li == lj && dom[i] == dom[j]) {  // one domain's block: both orders formed
       const double m = 0.5 * (*wij + *wji);
       *wij = m;
       *wji = m;
-    } else if (li < lj) {
+    } else if (li <= lj) {  // the row of the lower level (or lower domain) was formed
       *wji = *wij;
     } else {
       *wij = *wji;
     }
   }
 }
-isdf_status launch_symmetrize_w(hipStream_t s, double* W, int64_t nmu, const int8_t* lev) {
+isdf_status launch_symmetrize_w(hipStream_t s, double* W, int64_t nmu, const int8_t* lev, const int32_t* dom) {
   if (nmu <= 1) return ISDF_OK;
-  hipLaunchKernelGGL(symmetrize_w_kernel, dim3((unsigned)nmu), dim3(256), 0, s, W, nmu, lev);
+  hipLaunchKernelGGL(symmetrize_w_kernel, dim3((unsigned)nmu), dim3(256), 0, s, W, nmu, lev, dom);
   ISDF_HIP_TRY(hipGetLastError());
   return ISDF_OK;
 }

@@ -106,3 +106,25 @@ def test_occ_ri_row_blocks(torch, precision, cfg1_oracle):
     assert d_blk <= 1e-12
     assert dE <= 1e-6
     assert dK <= (1e-7 if precision == "fp64" else 1e-5)
+
+
+def test_repeated_fits_take_no_new_blocks(torch):
+    """A plan's second fit and exchange (streamed basis values, learned
+    selector, occ-RI rows in blocks) are served from the blocks the first
+    ones released: no new device allocation."""
+    s = config(2)
+    plan = binding.Plan(s, precision=binding.MIXED_X6, selector=binding.SEL_MLP,
+                        mlp_weights=initial_weights(3).astype(np.float32), mlp_keep=3.0, mlp_cutoff=0.5,
+                        phi_budget_mb=1500, ri_rows=2048)
+    C = torch.tensor(s.C_occ, dtype=torch.float64, device="cuda")
+    KC = torch.empty_like(C)
+    for rep in range(3):
+        fit = plan.fit()
+        fit.exchange_occ_ri(C, KC)
+        fit.close()
+        st = plan.alloc_stats()
+        print(f"[alloc] after fit {rep}: {st}")
+        if rep == 1:
+            first = st
+    assert st["calls"] == first["calls"] and st["bytes"] == first["bytes"]
+    plan.close()
