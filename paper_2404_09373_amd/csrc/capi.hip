@@ -3531,7 +3531,13 @@ isdf_status isdf_fit_batch(const isdf_plan_t* plans, int32_t n, int32_t max_conc
   std::vector<std::string> msg(n);
   std::atomic<int> next(0);
   auto worker = [&]() {
-    if (hipSetDevice(dev) != hipSuccess) return;
+    // a worker that cannot select the caller's device takes no plan (the
+    // others take them all; if none can, every plan reports the error)
+    const hipError_t e = hipSetDevice(dev);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return;
+    }
     for (int k; (k = next.fetch_add(1)) < n;) {
       const int i = order[k];
       sts[i] = do_fit(plans[i], nullptr, nullptr, nullptr, nullptr, &fits[i]);
@@ -3542,6 +3548,11 @@ isdf_status isdf_fit_batch(const isdf_plan_t* plans, int32_t n, int32_t max_conc
   std::vector<std::thread> pool;
   for (int t = 0; t < nt; ++t) pool.emplace_back(worker);
   for (auto& t : pool) t.join();
+  for (int k = next.load(); k < n; ++k) {  // never started: no worker could select the device
+    const int i = order[k];
+    sts[i] = ISDF_E_HIP;
+    msg[i] = "no worker thread could select device " + std::to_string(dev);
+  }
   for (int i = 0; i < n; ++i)
     if (own[i]) {
       (void)hipStreamSynchronize(own[i]);

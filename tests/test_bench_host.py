@@ -57,17 +57,22 @@ def test_roofline_arithmetic(monkeypatch):
 
 
 def test_traffic_figure_needs_the_measured_source(tmp_path, monkeypatch):
-    # the committed summary matches the committed FFT source
-    assert bench.measured_traffic(6) == pytest.approx(float(
-        re.search(r"traffic_bytes_per_launch: (\S+)", open(os.path.join(ROOT, "profiles", "traffic_fft_cfg2.md")).read()
-                  ).group(1)))
-    # a changed source voids it; families without a summary have none
+    """A committed traffic summary is used only while the hash of the
+    kernel source it was measured on matches the source in the tree."""
+    import hashlib
+
     (tmp_path / "profiles").mkdir()
     (tmp_path / "paper_2404_09373_amd" / "csrc").mkdir(parents=True)
-    shutil.copy(os.path.join(ROOT, "profiles", "traffic_fft_cfg2.md"), tmp_path / "profiles")
     src = open(os.path.join(ROOT, "paper_2404_09373_amd", "csrc", "kernels_fft.hip")).read()
-    (tmp_path / "paper_2404_09373_amd" / "csrc" / "kernels_fft.hip").write_text(src + "\n// changed\n")
+    srcp = tmp_path / "paper_2404_09373_amd" / "csrc" / "kernels_fft.hip"
+    srcp.write_text(src)
+    sha = hashlib.sha256(srcp.read_bytes()).hexdigest()
+    (tmp_path / "profiles" / "traffic_fft_cfg2.md").write_text(
+        f"traffic_bytes_per_launch: 2459581000\nkernel_source_sha256: {sha}\n")
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.measured_traffic(6) == pytest.approx(2459581000.0)
+    # a changed source voids it; families without a summary have none
+    srcp.write_text(src + "\n// changed\n")
     assert bench.measured_traffic(6) is None
     assert bench.measured_traffic(0) is None
 
