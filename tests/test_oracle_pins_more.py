@@ -7,7 +7,7 @@ import dataclasses
 import numpy as np
 import pytest
 
-from oracle import basis, brute, coulomb, isdf, mlp, pipeline
+from oracle import basis, brute, coulomb, exchange, isdf, mlp, pipeline
 from oracle import plan as oplan
 from workloads import config, periodic_overlap, primitive_norm, tiny_system
 
@@ -382,3 +382,73 @@ def test_threshold_mode_cap_still_selects():
     first = int(np.min(np.nonzero(dg >= (1.0 - s.tie_tol) * dg.max())[0]))
     assert r.pivots[0][0] == first != 0
     assert not np.array_equal(r.pivots[0], np.arange(r.pivots[0].size))
+
+
+# ------------------------------------------- density screening (occ-RI)
+@pytest.fixture(scope="module")
+def cfg1_bonds():
+    from workloads import bond_orbitals
+
+    s = config(1)
+    C, D, bonds = bond_orbitals(s)
+    s.C_occ, s.D = C, D
+    return s, pipeline.run(s)
+
+
+def test_bond_orbitals_are_orthonormal_and_local():
+    """One bond orbital per bond (two per carbon), S-orthonormal, and most of
+    its weight on the two bonded atoms."""
+    from workloads import bond_orbitals
+
+    s = config(1, with_density=False)
+    C, D, bonds = bond_orbitals(s)
+    assert len(bonds) == 2 * s.n_atoms == C.shape[1]
+    S = periodic_overlap(s.lattice, s.xyz, s.shell_atom, s.shell_l, s.shell_alpha)
+    assert np.max(np.abs(C.T @ S @ C - np.eye(C.shape[1]))) <= 1e-12
+    fatom = np.repeat(s.shell_atom, 2 * s.shell_l + 1)
+    for k, (a, b) in enumerate(bonds):
+        w = C[:, k] * (S @ C[:, k])  # Mulliken weights, sum 1
+        assert abs(w.sum() - 1.0) <= 1e-12
+        assert w[(fatom == a) | (fatom == b)].sum() >= 0.6
+
+
+def test_screened_occ_ri_without_screening_is_occ_ri(cfg1_bonds):
+    s, r = cfg1_bonds
+    KC, bound, kept = exchange.exchange_occ_ri_screened(r.XL, r.XN, r.W, s.C_occ, 64, 0.0)
+    assert kept == 1.0 and np.max(bound) == 0.0
+    ref = exchange.exchange_occ_ri(r.XL, r.XN, r.W, s.C_occ)
+    assert np.max(np.abs(KC - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+def test_screened_occ_ri_within_its_bound(cfg1_bonds):
+    """Tile bounds cover every |Q| entry; leaving out the tiles below tau
+    moves K C by no more than the stated elementwise bound; and the screened
+    K C is K_s C for the dense four-term K_s built from the same masked Q
+    blocks, which is symmetric only when Q_LG leaves out exactly the
+    transposed tiles of Q_GL."""
+    s, r = cfg1_bonds
+    C, XL, XN, W = s.C_occ, r.XL, r.XN, r.W
+    block = 64
+    BGG, BGL, BLL = exchange.occ_ri_tile_bounds(XL, XN, W, C, block)
+    EG, EL = (XL + XN) @ C, XL @ C
+    m = W.shape[0]
+    tiles = np.arange(m) // block
+    for B, Q in ((BGG, (EG @ EG.T) * W), (BGL, (EG @ EL.T) * W), (BLL, (EL @ EL.T) * W)):
+        assert np.all(np.abs(Q) <= B[np.ix_(tiles, tiles)] * (1 + 1e-12))
+    tau = float(np.quantile(np.concatenate([BGG.ravel(), BGL.ravel(), BLL.ravel()]), 0.4))
+    KC, bound, kept = exchange.exchange_occ_ri_screened(XL, XN, W, C, block, tau)
+    assert 0.3 < kept < 0.9
+    full = exchange.exchange_occ_ri(XL, XN, W, C)
+    dKC = np.abs(KC - full)
+    assert np.max(dKC) > 0.0
+    assert np.all(dKC <= bound + 1e-12 * np.max(np.abs(full)))
+    # the dense form of the same screened blocks
+    keep = lambda B: np.repeat(np.repeat(B >= tau, block, 0), block, 1)[:m, :m]
+    EN = XN @ C
+    QGG = (EG @ EG.T) * W * keep(BGG)
+    QGL = (EG @ EL.T) * W * keep(BGL)
+    QLG = (EL @ EG.T) * W * keep(BGL).T
+    QLL = (EL @ EL.T) * W * keep(BLL)
+    Ks = -(XL.T @ QGG @ XL + XL.T @ QGL @ XN + XN.T @ QLG @ XL + XN.T @ QLL @ XN)
+    assert np.max(np.abs(Ks - Ks.T)) <= 1e-12 * np.max(np.abs(Ks))
+    assert np.max(np.abs(Ks @ C - KC)) <= 1e-12 * np.max(np.abs(KC))

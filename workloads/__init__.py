@@ -18,5 +18,6 @@ from .diamond import (  # noqa: F401
     batched_cells,
     primitive_norm,
     LARGE_SHELLS,
+    bond_orbitals,
 )
 from .selector_init import initial_weights  # noqa: F401

@@ -361,6 +361,64 @@ def random_density(S: np.ndarray, n_occ: int, seed: int):
     return C, C @ C.T
 
 
+def bond_orbitals(sysm: "System", hybrid_alpha: float = 0.3):
+    """Localised occupied orbitals of a diamond-like cell: one per bond.
+
+    Bonds are the atom pairs closer than 1.2 times the shortest minimum-image
+    distance (each carbon has four, so there are 2 n_atoms of them, the
+    closed-shell count).  Orbital b of bond (A, B) starts as the sum of two
+    sp3 hybrids, s + sqrt3 (u . p) on A and on B, built from the s and p
+    shells whose exponent is closest to `hybrid_alpha`, u the unit vector
+    from the atom to its partner; the set is then made S-orthonormal by
+    C = C0 (C0^T S C0)^(-1/2), the orthonormal set closest to C0 (Loewdin),
+    which keeps it localised.  Returns (C, D = C C^T, bond atom pairs)."""
+    lat = np.asarray(sysm.lattice, dtype=np.float64)
+    xyz = np.asarray(sysm.xyz, dtype=np.float64)
+    n = xyz.shape[0]
+    inv = np.linalg.inv(lat)
+    shifts = np.array([[i, j, k] for i in (-1, 0, 1) for j in (-1, 0, 1) for k in (-1, 0, 1)], dtype=np.float64)
+
+    def min_image(d):
+        f = d @ inv
+        f -= np.round(f)
+        cand = (f[None, :] + shifts) @ lat
+        return cand[np.argmin(np.sum(cand * cand, axis=1))]
+
+    vec = {}
+    dmin = np.inf
+    for a in range(n):
+        for b in range(a + 1, n):
+            v = min_image(xyz[b] - xyz[a])
+            vec[(a, b)] = v
+            dmin = min(dmin, float(np.linalg.norm(v)))
+    bonds = [(a, b) for (a, b), v in vec.items() if np.linalg.norm(v) < 1.2 * dmin]
+    # function index of each shell's first component (atom-major order)
+    first, off = [], 0
+    for l in sysm.shell_l:
+        first.append(off)
+        off += 2 * int(l) + 1
+    nb = off
+
+    def hybrid(atom, u):
+        h = np.zeros(nb)
+        sh = [i for i in range(len(sysm.shell_atom)) if sysm.shell_atom[i] == atom]
+        s_sh = min((i for i in sh if sysm.shell_l[i] == 0), key=lambda i: abs(sysm.shell_alpha[i] - hybrid_alpha))
+        p_sh = min((i for i in sh if sysm.shell_l[i] == 1), key=lambda i: abs(sysm.shell_alpha[i] - hybrid_alpha))
+        h[first[s_sh]] = 1.0
+        h[first[p_sh]:first[p_sh] + 3] = np.sqrt(3.0) * u
+        return h
+
+    C0 = np.zeros((nb, len(bonds)))
+    for k, (a, b) in enumerate(bonds):
+        u = vec[(a, b)] / np.linalg.norm(vec[(a, b)])
+        C0[:, k] = hybrid(a, u) + hybrid(b, -u)
+    S = periodic_overlap(lat, xyz, sysm.shell_atom, sysm.shell_l, sysm.shell_alpha)
+    G = C0.T @ S @ C0
+    w, U = np.linalg.eigh(G)
+    C = C0 @ (U @ np.diag(w ** -0.5) @ U.T)
+    return C, C @ C.T, bonds
+
+
 def diamond_system(
     reps=(1, 1, 1),
     grids=((24, 24, 24), (48, 48, 48)),
