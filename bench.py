@@ -430,6 +430,98 @@ def study_universal(torch, binding, log, builds=5):
     plan.close()
 
 
+def study_batch(torch, binding, log, n_cells=32, max_concurrent=4, repeat=3):
+    """The uneven batch of 32 strained, displaced cells (8 each of 1x1x1,
+    2x1x1, 2x2x1, 2x2x2; two levels, ratio U[5, 8]): FP64 fits one by one
+    (per cell) and all at once (isdf_fit_batch, `max_concurrent` plans on
+    their own streams), best of `repeat` after one warm fit per plan, then
+    one exchange build per cell.  One JSON line per cell and one summary."""
+    from workloads import batched_cells
+
+    cells = batched_cells(n_cells)
+    # 32 plans keep their blocks for reuse: bound each one's Coulomb buffers
+    plans = [binding.Plan(c, w_batch=64) for c in cells]
+    for p in plans:  # tables uploaded, device blocks cached
+        p.fit().close()
+    torch.cuda.synchronize()
+    log("batch: warm fits done")
+    per_cell = [float("inf")] * len(plans)
+    t_seq, t_batch = float("inf"), float("inf")
+    for _ in range(repeat):
+        t_all = time.perf_counter()
+        for i, p in enumerate(plans):
+            t0 = time.perf_counter()
+            p.fit().close()
+            torch.cuda.synchronize()
+            per_cell[i] = min(per_cell[i], time.perf_counter() - t0)
+        t_seq = min(t_seq, time.perf_counter() - t_all)
+        t0 = time.perf_counter()
+        fits = binding.fit_batch(plans, max_concurrent=max_concurrent)
+        torch.cuda.synchronize()
+        t_batch = min(t_batch, time.perf_counter() - t0)
+        for f in fits:
+            f.close()
+        log("batch: repeat done")
+    fits = binding.fit_batch(plans, max_concurrent=max_concurrent)
+    for i, (c, p, f) in enumerate(zip(cells, plans, fits)):
+        C = torch.tensor(c.C_occ, dtype=torch.float64, device="cuda")
+        K = torch.empty((c.n_basis, c.n_basis), dtype=torch.float64, device="cuda")
+        f.exchange_occ(C, K)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, e = f.exchange_occ(C, K)
+        torch.cuda.synchronize()
+        print(json.dumps({"study": "batch", "cell": i, "atoms": c.n_atoms, "n_basis": c.n_basis,
+                          "n_mu": f.n_mu, "grids": np.asarray(c.grids).tolist(),
+                          "fit_ms": round(1e3 * per_cell[i], 3),
+                          "exchange_ms": round(1e3 * (time.perf_counter() - t0), 3), "E_x": e}), flush=True)
+        f.close()
+    print(json.dumps({"study": "batch", "cells": len(cells), "max_concurrent": max_concurrent,
+                      "fits_one_by_one_s": round(t_seq, 4), "fits_batched_s": round(t_batch, 4),
+                      "speedup": round(t_seq / t_batch, 3)}), flush=True)
+    for p in plans:
+        p.close()
+
+
+def study_screening(torch, binding, log, configs=(2, 4), taus=(1e-10, 1e-8, 1e-6, 1e-4), builds=5):
+    """Density screening of the occ-RI exchange (FP64 products) with
+    localised bond orbitals: per threshold, the kept fraction of the Q tiles,
+    the time per K C build (after two warm ones) and the change of E_x and
+    K C against the unscreened build.  One JSON line per (cell, threshold)."""
+    from workloads import bond_orbitals, config
+
+    for k in configs:
+        s = config(k, with_density=False)
+        C_np, _, _ = bond_orbitals(s)
+        C = torch.tensor(C_np, dtype=torch.float64, device="cuda")
+        base = None
+        for tau in (0.0,) + tuple(taus):
+            plan = binding.Plan(s, ri_screen_tau=tau)
+            fit = plan.fit()
+            KC = torch.empty_like(C)
+            for _ in range(2):
+                fit.exchange_occ_ri(C, KC)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(builds):
+                _, e = fit.exchange_occ_ri(C, KC)
+            torch.cuda.synchronize()
+            ms = 1e3 * (time.perf_counter() - t0) / builds
+            rec = {"study": "screening", "cell": f"cfg{k}", "atoms": s.n_atoms, "n_mu": fit.n_mu, "tau": tau,
+                   "kc_ms_per_build": round(ms, 3), "E_x": e}
+            if tau == 0.0:
+                base = (KC.clone(), e)
+                rec["kept_fraction"] = 1.0
+            else:
+                rec["kept_fraction"] = round(fit.screen_kept(), 4)
+                rec["abs_dE_per_atom"] = abs(e - base[1]) / s.n_atoms
+                rec["max_abs_dKC"] = float(torch.max(torch.abs(KC - base[0])))
+            print(json.dumps(rec), flush=True)
+            fit.close()
+            plan.close()
+        log(f"screening cfg{k} done")
+
+
 def study_scaling(torch, binding, log, reps_list=None, repeat=3):
     """Fit and exchange build times against system size (the scaling study of
     the Results section): eps_K = 1e-2, eps_ISDF = 1e-4 (the paper's diamond
@@ -527,7 +619,7 @@ def main():
                     help="only copy 2 GiB three times (reference for the HBM byte counters)")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the measurements beside the headline (occ-RI output, universal grid at every point)")
-    ap.add_argument("--study", choices=["thresholds", "scaling", "universal"],
+    ap.add_argument("--study", choices=["thresholds", "scaling", "universal", "batch", "screening"],
                     help="run a threshold or scaling study (JSON line per measurement) instead of the benchmark")
     ap.add_argument("--cells", default="",
                     help="scaling study cells as repeats of the 8-atom cell, e.g. 4x3x3,4x4x4 (default 1x1x1 .. 3x3x3)")
@@ -568,6 +660,10 @@ def main():
             study_thresholds(torch, binding, log)
         elif args.study == "universal":
             study_universal(torch, binding, log)
+        elif args.study == "batch":
+            study_batch(torch, binding, log)
+        elif args.study == "screening":
+            study_screening(torch, binding, log)
         else:
             cells = [tuple(int(x) for x in c.split("x")) for c in args.cells.split(",") if c]
             study_scaling(torch, binding, log, reps_list=cells or None)

@@ -112,7 +112,11 @@ typedef struct {
   double mlp_cutoff;          /* MLP: also every point with score >= mlp_cutoff (0..1)    */
   const float* mlp_weights;   /* MLP: host array of ISDF_MLP_NPARAM floats, copied       */
   void* stream;               /* hipStream_t or NULL                                      */
-  int32_t w_batch;            /* fitting functions per Poisson batch (0: automatic)      */
+  int32_t w_batch;            /* most fitting functions whose potentials (on every grid)
+                                 are held at once, and twice the most Poisson solves per
+                                 FFT batch; bounds the Coulomb stage's memory (many plans
+                                 fitting at once).  0: as many as 45 % of the free memory
+                                 (at most 24 GB) holds                                    */
   int32_t mixed_mask;         /* contractions run in the mixed precision when precision
                                  is ISDF_MIXED_*: bit 0 Theta, bit 1 W (universal rows),
                                  bit 2 exchange; 0 means W and exchange                   */
@@ -157,6 +161,15 @@ typedef struct {
                                  depend on it).  0: all N_mu rows when they fit a
                                  quarter of the free memory, else blocks of a multiple
                                  of 256 rows that fit 15 % of it                          */
+  double ri_screen_tau;       /* density screening of isdf_exchange_occ_ri (the near-
+                                 sightedness of the density matrix, Conclusions): fitting
+                                 indices in tiles of 64; a tile (b, c) of Q_ST =
+                                 W o (E_S E_T^T) is left out when
+                                 max_{b x c}|W| sum_i max_b|E_S(., i)| max_c|E_T(., i)|
+                                 is below it (a bound on every |Q| entry of the tile),
+                                 skipping its products.  Pays off with localised
+                                 occupied orbitals.  0 (default): no screening.  Needs
+                                 the FP64 exchange (no mixed bit 2)                       */
 } isdf_options;
 /* Storage of the Coulomb metric W held by a fit. */
 enum { ISDF_W_F64 = 0, ISDF_W_F32 = 1 };
@@ -427,6 +440,11 @@ enum {
   ISDF_FIELD_THETA = 4, ISDF_FIELD_F = 5, ISDF_FIELD_XL = 6, ISDF_FIELD_XN = 7, ISDF_FIELD_W = 8
 };
 isdf_status isdf_fit_get(isdf_fit_t fit, int32_t field, int32_t d, void* host_out, size_t bytes);
+
+/* Density screening of the fit's last isdf_exchange_occ_ri (ri_screen_tau
+ * > 0): the fraction of the 64 x 64 tiles of Q_GG, Q_GL and Q_LL kept
+ * (synchronises).  ISDF_E_STATE when no screened exchange has run. */
+isdf_status isdf_fit_screen_stats(isdf_fit_t fit, double* kept_fraction);
 
 /* Total fitted points (after any early stop). */
 isdf_status isdf_fit_info(isdf_fit_t fit, int64_t* n_mu);

@@ -35,6 +35,7 @@ EXPORTED = [
     "isdf_mlp_train", "isdf_profile", "isdf_kernel_stats", "isdf_exchange_occ", "isdf_autotune",
     "isdf_fit_batch", "isdf_exchange_occ_ri", "isdf_grids_for_threshold", "isdf_exchange_universal",
     "isdf_exchange_occ_ri_noalloc", "isdf_plan_workspace_bytes", "isdf_plan_alloc_stats",
+    "isdf_fit_screen_stats",
 ]
 NOALLOC_SCRATCH_MB = 32
 MLP_NPARAM = 5313
@@ -103,6 +104,7 @@ class _Options(C.Structure):
         ("workspace_bytes", C.c_size_t),
         ("phi_budget_mb", C.c_int32),
         ("ri_rows", C.c_int32),
+        ("ri_screen_tau", C.c_double),
     ]
 
 
@@ -155,6 +157,7 @@ def load(required: bool = True):
     lib.isdf_exchange_occ_ri_noalloc.argtypes = [vp, vp, vp, C.c_int32, vp, C.POINTER(C.c_double)]
     lib.isdf_plan_workspace_bytes.argtypes = [vp, C.POINTER(C.c_size_t)]
     lib.isdf_plan_alloc_stats.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    lib.isdf_fit_screen_stats.argtypes = [vp, C.POINTER(C.c_double)]
     lib.isdf_autotune.argtypes = [vp, C.c_int32, C.c_int32, C.c_char_p]
     lib.isdf_grids_for_threshold.argtypes = [C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_double),
                                              C.c_int32, C.POINTER(C.c_double), C.c_double,
@@ -170,7 +173,8 @@ def load(required: bool = True):
                  "isdf_mlp_forward", "isdf_mlp_loss_grad", "isdf_mlp_train", "isdf_profile",
                  "isdf_kernel_stats", "isdf_exchange_occ", "isdf_autotune", "isdf_fit_batch",
                  "isdf_exchange_occ_ri", "isdf_grids_for_threshold", "isdf_exchange_universal",
-                 "isdf_exchange_occ_ri_noalloc", "isdf_plan_workspace_bytes", "isdf_plan_alloc_stats"):
+                 "isdf_exchange_occ_ri_noalloc", "isdf_plan_workspace_bytes", "isdf_plan_alloc_stats",
+                 "isdf_fit_screen_stats"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -194,7 +198,7 @@ class Plan:
                  mlp_cutoff: float = 0.05, mixed_mask: int = 0, eager_exchange: bool = False,
                  tune_file=None, universal_all_points: bool = False, universal_tile_mb: int = 0,
                  w_storage: int = W_F64, workspace=None, phi_budget_mb: int = 0,
-                 ri_rows: int = 0):
+                 ri_rows: int = 0, ri_screen_tau: float = 0.0):
         lib = load()
         self._keep = []
         s = _System()
@@ -243,6 +247,7 @@ class Plan:
         o.w_storage = int(w_storage)
         o.phi_budget_mb = int(phi_budget_mb)
         o.ri_rows = int(ri_rows)
+        o.ri_screen_tau = float(ri_screen_tau)
         if workspace is not None:  # a CUDA tensor the plan carves its device buffers from
             self._keep.append(workspace)
             o.workspace = C.c_void_p(workspace.data_ptr())
@@ -489,6 +494,12 @@ class Fit:
                                            int(C_occ.shape[1]), C.c_void_p(KC.data_ptr()), C.byref(ex)),
                "isdf_exchange_occ_ri")
         return KC, ex.value
+
+    def screen_kept(self) -> float:
+        """Kept tile fraction of the last screened occ-RI exchange."""
+        k = C.c_double()
+        _check(load().isdf_fit_screen_stats(self.handle, C.byref(k)), "isdf_fit_screen_stats")
+        return k.value
 
     def exchange_occ_ri_noalloc(self, C_occ, KC):
         """K C through isdf_exchange_occ_ri_noalloc (FP64, workspace in the

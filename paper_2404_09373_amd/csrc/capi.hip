@@ -451,6 +451,11 @@ struct isdf_fit_s {
   DevBuf Kpart, d_yprobs, d_kprobs, d_qprobs;
   int ytiles = 0, ktiles = 0, kparts = 0, qprobs_nocc = -1;
   bool ydense = false;  // Y12, Kpart and their problem tables built
+  // density screening of the occ-RI exchange: tile maxima of |W| (once per
+  // fit), of |E_G| and |E_L|, the tile bounds and masks of Q_GG, Q_GL, Q_LL
+  DevBuf s_wt, s_ng, s_nl, s_bgg, s_bgl, s_bll, s_mgg, s_mgl, s_mll;
+  int s_nt = 0, s_nocc = -1;
+  bool s_ran = false;
   // rows of Q held at once (Q1/Q2 planes or the FP64 Q buffers): N_mu, or a
   // row block of the occ-RI exchange (then QLG holds Q_GL^T's rows)
   int64_t q_rows = 0;
@@ -679,6 +684,10 @@ isdf_status tune_problem(isdf_plan_s* pl, int epi, int tag, const GemmProblem& p
 isdf_status gemm_prof(isdf_plan_s* pl, int fam, int epi, const GemmProblem& p) {
   const int tag = family_tag(fam);
   int shape = -1;
+  if (p.tmask_mode) {  // screening masks are laid out for 64 x 64 tiles
+    ProfScope ps(pl, fam, gemm_bytes(p), gemm_flops(p));
+    return gemm_f64(pl->stream, epi, p, tag, 0);
+  }
   if (pl->tuning || !pl->tune.empty()) {
     const std::string key = gemm_key(epi, tag, p);
     auto it = pl->tune.find(key);
@@ -1687,6 +1696,7 @@ isdf_status run_coulomb(isdf_plan_s* pl, isdf_fit_s* f, DevBuf* scratch = nullpt
     double per_col = 0.0;
     for (int l = 0; l <= lp; ++l) per_col += 8.0 * level_ng(hp, l);
     int64_t w = std::max<int64_t>(2, (int64_t)(v_budget / per_col));
+    if (pl->opts.w_batch > 0) w = std::min<int64_t>(w, std::max(2, pl->opts.w_batch));
     w -= w & 1;
     for (int64_t c0 = lev_begin[lp]; c0 < lev_end[lp]; c0 += w) {
       Chunk c{lp, c0, std::min(c0 + w, lev_end[lp])};
@@ -1708,6 +1718,7 @@ isdf_status run_coulomb(isdf_plan_s* pl, isdf_fit_s* f, DevBuf* scratch = nullpt
   int64_t ngz_max = 0;
   for (auto& c : chunks) ngz_max = std::max(ngz_max, level_ng(hp, c.lp));
   int64_t fft_pairs = std::max<int64_t>(1, (int64_t)(z_budget / (16.0 * ngz_max)));
+  if (pl->opts.w_batch > 0) fft_pairs = std::min<int64_t>(fft_pairs, std::max(1, pl->opts.w_batch / 2));
   // W (FP64), V, zf, zc: carved from the scratch block when it holds them
   const bool w_transient = pl->opts.w_storage == ISDF_W_F32;
   auto a256 = [](size_t b) { return (b + 255) / 256 * 256; };
@@ -2481,8 +2492,10 @@ isdf_status exchange_prepare(isdf_plan_s* plan, isdf_fit_s* fit, int n_occ, bool
     if ((st = fit->ex_out.alloc(sizeof(double))) != ISDF_OK) return st;
   }
   // rows of Q: the dense exchange needs all, occ-RI may run in row blocks
+  // (whole 64-index screening tiles when screening)
   int64_t need_rows = nmu;
   if (ri && fit->q_rows < nmu && (st = ri_q_rows(plan, fit, mixed, &need_rows)) != ISDF_OK) return st;
+  if (ri && plan->opts.ri_screen_tau > 0.0 && need_rows < nmu) need_rows = std::max<int64_t>(64, need_rows / 64 * 64);
   const bool new_q = fit->q_rows < need_rows;
   if (new_q) {
     fit->q_rows = need_rows;
@@ -2613,6 +2626,25 @@ isdf_status exchange_prepare(isdf_plan_s* plan, isdf_fit_s* fit, int n_occ, bool
       if ((st = upload(fit->d_qprobs, qp)) != ISDF_OK) return st;
       fit->qprobs_nocc = n_occ;
     }
+  }
+  if (ri && plan->opts.ri_screen_tau > 0.0 && !mixed && fit->s_nocc != n_occ) {
+    // density screening: tile maxima of |W| once per fit, the rest per n_occ
+    const int64_t nt = (nmu + 63) / 64;
+    if (!fit->s_wt.p) {
+      if ((st = fit->s_wt.alloc(sizeof(double) * nt * nt)) != ISDF_OK) return st;
+      if ((st = launch_tile_absmax_w(plan->stream, fit->w64(), fit->wf32(), nmu, (int)nmu, 64, fit->s_wt.as<double>())) !=
+          ISDF_OK)
+        return st;
+    }
+    for (DevBuf* d : {&fit->s_ng, &fit->s_nl})
+      if ((st = d->alloc(sizeof(double) * nt * std::max(n_occ, 1))) != ISDF_OK) return st;
+    for (DevBuf* d : {&fit->s_bgg, &fit->s_bgl, &fit->s_bll})
+      if ((st = d->alloc(sizeof(double) * nt * nt)) != ISDF_OK) return st;
+    for (DevBuf* d : {&fit->s_mgg, &fit->s_mgl, &fit->s_mll})
+      if ((st = d->alloc(nt * nt)) != ISDF_OK) return st;
+    fit->s_nt = (int)nt;
+    fit->s_nocc = n_occ;
+    fit->drop_graph();
   }
   if (ri && fit->ri_nocc != n_occ) {
     const int m = (int)nmu, n = (int)N, o = n_occ;
@@ -2794,6 +2826,11 @@ struct RiBuffers {
   // each); 0 or N_mu: one block, no QLG
   double* QLG;
   int64_t qrows;
+  // density screening (tau > 0; FP64 path): tile maxima and bounds, masks
+  double tau;
+  const double *wt;
+  double *ng, *nl, *bgg, *bgl, *bll;
+  uint8_t *mgg, *mgl, *mll;
 };
 
 // FP64 occ-RI products into the given workspace (no allocation):
@@ -2813,8 +2850,18 @@ isdf_status ri_fp64_products(isdf_plan_s* plan, isdf_fit_s* fit, const double* C
   const double* XG = fit->XG.as<double>();
   const double* W = fit->w64();
   const float* W32 = fit->wf32();
+  const bool scr = b.tau > 0.0;
+  const int64_t nt = (nmu + 63) / 64;
+  // mask of a product: base, strides of (row tile, column or K tile), mode
+  struct Mask {
+    const uint8_t* base;
+    int64_t s0, s1;
+    int mode;
+  };
+  const Mask none{nullptr, 0, 0, 0};
   auto gemm = [&](int epi, const double* A, int64_t lda, int tA, const double* B, int64_t ldb, int tB,
-                  double* C, int64_t ldc, int M, int Nn, int Kk, double alpha, double beta, int64_t e_row) {
+                  double* C, int64_t ldc, int M, int Nn, int Kk, double alpha, double beta, int64_t e_row,
+                  const Mask& mk) {
     GemmProblem p{};
     p.A = A; p.lda = lda; p.transA = tA;
     p.B = B; p.ldb = ldb; p.transB = tB;
@@ -2826,45 +2873,100 @@ isdf_status ri_fp64_products(isdf_plan_s* plan, isdf_fit_s* fit, const double* C
     p.lde = nmu;
     p.M = M; p.N = Nn; p.K = Kk;
     p.alpha = alpha; p.beta = beta;
+    if (scr && mk.mode) {
+      p.tmask = mk.base;
+      p.tm_s0 = mk.s0;
+      p.tm_s1 = mk.s1;
+      p.tmask_mode = mk.mode;
+    }
     return gemm_prof(plan, ISDF_K_GEMM_EXCHANGE, epi, p);
   };
   isdf_status st;
-  if ((st = gemm(EPI_AXPBY, XG, nmu, 0, Cin, o, 1, b.EG, nmu, m, o, n, 1.0, 0.0, 0)) != ISDF_OK) return st;
-  if ((st = gemm(EPI_AXPBY, XL, nmu, 0, Cin, o, 1, b.EL, nmu, m, o, n, 1.0, 0.0, 0)) != ISDF_OK) return st;
+  if ((st = gemm(EPI_AXPBY, XG, nmu, 0, Cin, o, 1, b.EG, nmu, m, o, n, 1.0, 0.0, 0, none)) != ISDF_OK) return st;
+  if ((st = gemm(EPI_AXPBY, XL, nmu, 0, Cin, o, 1, b.EL, nmu, m, o, n, 1.0, 0.0, 0, none)) != ISDF_OK) return st;
   if ((st = launch_sub(s, b.EG, b.EL, b.EN, nmu * o)) != ISDF_OK) return st;
+  if (scr) {
+    // tile bounds B_ST = Wt o (N_S N_T^T), N_S(b, i) = max over tile b of
+    // |E_S(., i)|, and the masks of the tiles at or above tau
+    if ((st = launch_tile_absmax(s, b.EG, nmu, m, o, 64, b.ng)) != ISDF_OK) return st;
+    if ((st = launch_tile_absmax(s, b.EL, nmu, m, o, 64, b.nl)) != ISDF_OK) return st;
+    const double* NS[3] = {b.ng, b.ng, b.nl};
+    const double* NT[3] = {b.ng, b.nl, b.nl};
+    double* BB[3] = {b.bgg, b.bgl, b.bll};
+    uint8_t* MM[3] = {b.mgg, b.mgl, b.mll};
+    for (int t = 0; t < 3; ++t) {
+      GemmProblem p{};
+      p.A = NS[t]; p.lda = nt;
+      p.B = NT[t]; p.ldb = nt; p.transB = 1;
+      p.C = BB[t]; p.ldc = nt;
+      p.E = b.wt; p.lde = nt;
+      p.M = (int)nt; p.N = (int)nt; p.K = o;
+      p.alpha = 1.0;
+      if ((st = gemm_prof(plan, ISDF_K_GEMM_EXCHANGE, EPI_HADAMARD, p)) != ISDF_OK) return st;
+      if ((st = launch_mask_ge(s, BB[t], nt * nt, b.tau, MM[t])) != ISDF_OK) return st;
+    }
+  }
+  // masks: output tiles (mode 1) of the Q products, K ranges (mode 2) of Z
+  auto out_mask = [&](const uint8_t* mk, int64_t row_tile0) { return Mask{mk + row_tile0, 1, nt, 1}; };
+  auto k_mask = [&](const uint8_t* mk, int64_t row_tile0) { return Mask{mk + row_tile0, 1, nt, 2}; };
   if (b.qrows <= 0 || b.qrows >= nmu) {
-    if ((st = gemm(EPI_HADAMARD, b.EG, nmu, 0, b.EG, nmu, 1, b.QGG, nmu, m, m, o, 1.0, 0.0, 0)) != ISDF_OK) return st;
-    if ((st = gemm(EPI_HADAMARD, b.EG, nmu, 0, b.EL, nmu, 1, b.QGL, nmu, m, m, o, 1.0, 0.0, 0)) != ISDF_OK) return st;
-    if ((st = gemm(EPI_HADAMARD, b.EL, nmu, 0, b.EL, nmu, 1, b.QLL, nmu, m, m, o, 1.0, 0.0, 0)) != ISDF_OK) return st;
-    if ((st = gemm(EPI_AXPBY, b.QGG, nmu, 0, b.EL, nmu, 0, b.Z1, nmu, m, o, m, 1.0, 0.0, 0)) != ISDF_OK) return st;
-    if ((st = gemm(EPI_AXPBY, b.QGL, nmu, 0, b.EN, nmu, 0, b.Z1, nmu, m, o, m, 1.0, 1.0, 0)) != ISDF_OK) return st;
-    if ((st = gemm(EPI_AXPBY, b.QGL, nmu, 1, b.EL, nmu, 0, b.Z2, nmu, m, o, m, 1.0, 0.0, 0)) != ISDF_OK) return st;
-    if ((st = gemm(EPI_AXPBY, b.QLL, nmu, 0, b.EN, nmu, 0, b.Z2, nmu, m, o, m, 1.0, 1.0, 0)) != ISDF_OK) return st;
+    if ((st = gemm(EPI_HADAMARD, b.EG, nmu, 0, b.EG, nmu, 1, b.QGG, nmu, m, m, o, 1.0, 0.0, 0, out_mask(b.mgg, 0))) !=
+        ISDF_OK)
+      return st;
+    if ((st = gemm(EPI_HADAMARD, b.EG, nmu, 0, b.EL, nmu, 1, b.QGL, nmu, m, m, o, 1.0, 0.0, 0, out_mask(b.mgl, 0))) !=
+        ISDF_OK)
+      return st;
+    if ((st = gemm(EPI_HADAMARD, b.EL, nmu, 0, b.EL, nmu, 1, b.QLL, nmu, m, m, o, 1.0, 0.0, 0, out_mask(b.mll, 0))) !=
+        ISDF_OK)
+      return st;
+    if ((st = gemm(EPI_AXPBY, b.QGG, nmu, 0, b.EL, nmu, 0, b.Z1, nmu, m, o, m, 1.0, 0.0, 0, k_mask(b.mgg, 0))) !=
+        ISDF_OK)
+      return st;
+    if ((st = gemm(EPI_AXPBY, b.QGL, nmu, 0, b.EN, nmu, 0, b.Z1, nmu, m, o, m, 1.0, 1.0, 0, k_mask(b.mgl, 0))) !=
+        ISDF_OK)
+      return st;
+    // Q_GL^T: its row tile r, K tile q is Q_GL's tile (q, r)
+    if ((st = gemm(EPI_AXPBY, b.QGL, nmu, 1, b.EL, nmu, 0, b.Z2, nmu, m, o, m, 1.0, 0.0, 0,
+                   Mask{b.mgl, nt, 1, 2})) != ISDF_OK)
+      return st;
+    if ((st = gemm(EPI_AXPBY, b.QLL, nmu, 0, b.EN, nmu, 0, b.Z2, nmu, m, o, m, 1.0, 1.0, 0, k_mask(b.mll, 0))) !=
+        ISDF_OK)
+      return st;
   } else {
     for (int64_t r0 = 0; r0 < nmu; r0 += b.qrows) {
       const int rb = (int)std::min<int64_t>(b.qrows, nmu - r0);
       const int64_t q = b.qrows;  // leading dimension of the block buffers
+      const int64_t t0 = r0 / 64;  // first row tile (row blocks start on tile boundaries)
       // Q_XY(r, :) = W(r, :) o (E_X(r, :) E_Y^T): rows r0.. of W are W + r0 (lde N_mu)
-      if ((st = gemm(EPI_HADAMARD, b.EG + r0, nmu, 0, b.EG, nmu, 1, b.QGG, q, rb, m, o, 1.0, 0.0, r0)) != ISDF_OK)
+      if ((st = gemm(EPI_HADAMARD, b.EG + r0, nmu, 0, b.EG, nmu, 1, b.QGG, q, rb, m, o, 1.0, 0.0, r0,
+                     out_mask(b.mgg, t0))) != ISDF_OK)
         return st;
-      if ((st = gemm(EPI_HADAMARD, b.EG + r0, nmu, 0, b.EL, nmu, 1, b.QGL, q, rb, m, o, 1.0, 0.0, r0)) != ISDF_OK)
+      if ((st = gemm(EPI_HADAMARD, b.EG + r0, nmu, 0, b.EL, nmu, 1, b.QGL, q, rb, m, o, 1.0, 0.0, r0,
+                     out_mask(b.mgl, t0))) != ISDF_OK)
         return st;
-      if ((st = gemm(EPI_HADAMARD, b.EL + r0, nmu, 0, b.EG, nmu, 1, b.QLG, q, rb, m, o, 1.0, 0.0, r0)) != ISDF_OK)
+      // Q_LG = Q_GL^T: its tile (r, c) is Q_GL's tile (c, r)
+      if ((st = gemm(EPI_HADAMARD, b.EL + r0, nmu, 0, b.EG, nmu, 1, b.QLG, q, rb, m, o, 1.0, 0.0, r0,
+                     Mask{b.mgl + t0 * nt, nt, 1, 1})) != ISDF_OK)
         return st;
-      if ((st = gemm(EPI_HADAMARD, b.EL + r0, nmu, 0, b.EL, nmu, 1, b.QLL, q, rb, m, o, 1.0, 0.0, r0)) != ISDF_OK)
+      if ((st = gemm(EPI_HADAMARD, b.EL + r0, nmu, 0, b.EL, nmu, 1, b.QLL, q, rb, m, o, 1.0, 0.0, r0,
+                     out_mask(b.mll, t0))) != ISDF_OK)
         return st;
-      if ((st = gemm(EPI_AXPBY, b.QGG, q, 0, b.EL, nmu, 0, b.Z1 + r0, nmu, rb, o, m, 1.0, 0.0, 0)) != ISDF_OK)
+      if ((st = gemm(EPI_AXPBY, b.QGG, q, 0, b.EL, nmu, 0, b.Z1 + r0, nmu, rb, o, m, 1.0, 0.0, 0,
+                     k_mask(b.mgg, t0))) != ISDF_OK)
         return st;
-      if ((st = gemm(EPI_AXPBY, b.QGL, q, 0, b.EN, nmu, 0, b.Z1 + r0, nmu, rb, o, m, 1.0, 1.0, 0)) != ISDF_OK)
+      if ((st = gemm(EPI_AXPBY, b.QGL, q, 0, b.EN, nmu, 0, b.Z1 + r0, nmu, rb, o, m, 1.0, 1.0, 0,
+                     k_mask(b.mgl, t0))) != ISDF_OK)
         return st;
-      if ((st = gemm(EPI_AXPBY, b.QLG, q, 0, b.EL, nmu, 0, b.Z2 + r0, nmu, rb, o, m, 1.0, 0.0, 0)) != ISDF_OK)
+      if ((st = gemm(EPI_AXPBY, b.QLG, q, 0, b.EL, nmu, 0, b.Z2 + r0, nmu, rb, o, m, 1.0, 0.0, 0,
+                     Mask{b.mgl + t0 * nt, nt, 1, 2})) != ISDF_OK)
         return st;
-      if ((st = gemm(EPI_AXPBY, b.QLL, q, 0, b.EN, nmu, 0, b.Z2 + r0, nmu, rb, o, m, 1.0, 1.0, 0)) != ISDF_OK)
+      if ((st = gemm(EPI_AXPBY, b.QLL, q, 0, b.EN, nmu, 0, b.Z2 + r0, nmu, rb, o, m, 1.0, 1.0, 0,
+                     k_mask(b.mll, t0))) != ISDF_OK)
         return st;
     }
   }
-  if ((st = gemm(EPI_AXPBY, b.Z1, nmu, 1, XL, nmu, 0, KC, o, o, n, m, -1.0, 0.0, 0)) != ISDF_OK) return st;
-  return gemm(EPI_AXPBY, b.Z2, nmu, 1, XN, nmu, 0, KC, o, o, n, m, -1.0, 1.0, 0);
+  if ((st = gemm(EPI_AXPBY, b.Z1, nmu, 1, XL, nmu, 0, KC, o, o, n, m, -1.0, 0.0, 0, none)) != ISDF_OK) return st;
+  return gemm(EPI_AXPBY, b.Z2, nmu, 1, XN, nmu, 0, KC, o, o, n, m, -1.0, 1.0, 0, none);
 }
 
 isdf_status exchange_enqueue_ri(isdf_plan_s* plan, isdf_fit_s* fit, const double* Cin, int n_occ, double* KC,
@@ -2932,8 +3034,21 @@ isdf_status exchange_enqueue_ri(isdf_plan_s* plan, isdf_fit_s* fit, const double
     if ((st = launch_sum_parts(s, fit->KCpart.as<double>(), fit->kcparts, (int64_t)o * n, KC)) != ISDF_OK)
       return st;
   } else {
-    const RiBuffers b{EG,  EL, EN, fit->QGG.as<double>(), fit->QGL.as<double>(), fit->QLL.as<double>(),
-                      Z1,  Z2, fit->QLG.as<double>(), fit->q_rows};
+    RiBuffers b{EG, EL, EN, fit->QGG.as<double>(), fit->QGL.as<double>(), fit->QLL.as<double>(),
+                Z1, Z2, fit->QLG.as<double>(), fit->q_rows};
+    if (plan->opts.ri_screen_tau > 0.0) {
+      b.tau = plan->opts.ri_screen_tau;
+      b.wt = fit->s_wt.as<double>();
+      b.ng = fit->s_ng.as<double>();
+      b.nl = fit->s_nl.as<double>();
+      b.bgg = fit->s_bgg.as<double>();
+      b.bgl = fit->s_bgl.as<double>();
+      b.bll = fit->s_bll.as<double>();
+      b.mgg = fit->s_mgg.as<uint8_t>();
+      b.mgl = fit->s_mgl.as<uint8_t>();
+      b.mll = fit->s_mll.as<uint8_t>();
+      fit->s_ran = true;
+    }
     if ((st = ri_fp64_products(plan, fit, Cin, o, KC, b)) != ISDF_OK) return st;
   }
   if (stage_event) ISDF_HIP_TRY(hipEventRecord(plan->ev[1], s));
@@ -3348,6 +3463,15 @@ isdf_status isdf_plan(const isdf_system* sys, const isdf_options* opts, isdf_pla
     set_error("isdf_plan: universal_tile_mb must not be negative");
     return ISDF_E_ARG;
   }
+  if (!(pl->opts.ri_screen_tau >= 0.0)) {
+    set_error("isdf_plan: ri_screen_tau must be >= 0");
+    return ISDF_E_ARG;
+  }
+  if (pl->opts.ri_screen_tau > 0.0 && pl->opts.precision != ISDF_FP64 &&
+      (pl->opts.mixed_mask == 0 || (pl->opts.mixed_mask & ISDF_MIX_EXCHANGE))) {
+    set_error("isdf_plan: ri_screen_tau needs the FP64 exchange (a mixed plan without mixed_mask bit 2)");
+    return ISDF_E_UNSUPPORTED;
+  }
   if (pl->opts.phi_budget_mb < 0 || pl->opts.ri_rows < 0) {
     set_error("isdf_plan: phi_budget_mb and ri_rows must not be negative");
     return ISDF_E_ARG;
@@ -3742,6 +3866,27 @@ isdf_status isdf_mlp_train(const float* features_dev, const float* labels_dev, i
     if (epoch_loss) epoch_loss[ep] = (float)(tot / (double)n);
   }
   ISDF_HIP_TRY(hipMemcpy(weights, w.p, sizeof(float) * MLP_NPARAM, hipMemcpyDeviceToHost));
+  return ISDF_OK;
+}
+
+isdf_status isdf_fit_screen_stats(isdf_fit_t fit, double* kept_fraction) {
+  if (!fit || !kept_fraction) {
+    set_error("isdf_fit_screen_stats: null argument");
+    return ISDF_E_ARG;
+  }
+  if (!fit->s_ran || fit->s_nt <= 0) {
+    set_error("isdf_fit_screen_stats: no screened exchange has run on this fit");
+    return ISDF_E_STATE;
+  }
+  const size_t nn = (size_t)fit->s_nt * fit->s_nt;
+  std::vector<uint8_t> h(nn);
+  ISDF_HIP_TRY(hipStreamSynchronize(fit->plan->stream));
+  size_t kept = 0;
+  for (DevBuf* d : {&fit->s_mgg, &fit->s_mgl, &fit->s_mll}) {
+    ISDF_HIP_TRY(hipMemcpy(h.data(), d->p, nn, hipMemcpyDeviceToHost));
+    for (uint8_t v : h) kept += v;
+  }
+  *kept_fraction = (double)kept / (3.0 * (double)nn);
   return ISDF_OK;
 }
 

@@ -101,6 +101,14 @@ struct GemmProblem {
   int32_t tile_start;            // first flat tile of this problem in a grouped launch
   int32_t lower;                 // 1: only tiles touching the lower triangle (m >= n)
   const float* E32;              // EPI_HADAMARD: E held in FP32 (read instead of E when set)
+  // Tile masks of density screening (64 x 64 tiles; 64 x 64 tile shape only):
+  // mode 1 leaves out output tile (tm, tn) when tmask[tm s0 + tn s1] == 0
+  // (C = beta C there); mode 2 leaves out the K range [64 q, 64 q + 64) of
+  // output row tile tm when tmask[tm s0 + q s1] == 0 (A is zero there).
+  const uint8_t* tmask;
+  int64_t tm_s0, tm_s1;
+  int32_t tmask_mode;
+  int32_t pad_t;
 };
 
 // Launch one problem or a group (device array of problems, tile_start
@@ -231,6 +239,13 @@ isdf_status launch_gather_x(hipStream_t s, const GatherDom* doms, int ndom, int 
                             double* xrows, double* XL, double* XN, int64_t nmu);
 
 isdf_status launch_fill(hipStream_t s, double* p, int64_t n, double v);
+// Density screening: tile maxima of |A| (nt x n, column-major), of |W| over
+// tiles (nt x nt), and masks B >= tau.
+isdf_status launch_tile_absmax(hipStream_t s, const double* A, int64_t lda, int m, int n, int block,
+                               double* out);
+isdf_status launch_tile_absmax_w(hipStream_t s, const double* W, const float* W32, int64_t ld, int m, int block,
+                                 double* out);
+isdf_status launch_mask_ge(hipStream_t s, const double* B, int64_t n, double tau, uint8_t* mask);
 // p(i, i) = v for i < n (column-major, leading dimension ld)
 isdf_status launch_set_diag(hipStream_t s, double* p, int64_t ld, int n, double v);
 // dst(i, c) = alpha src(idx ? idx[i] : i, c) for i < rows, c < cols (column-major)

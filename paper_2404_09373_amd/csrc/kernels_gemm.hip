@@ -213,6 +213,22 @@ gemm_f64_kernel(GemmProblem single, const GemmProblem* __restrict__ probs, int n
   const int m0 = tm * BM_, n0 = tn * BN_;
   if (n0 >= p.N) return;
   if (p.lower && m0 + BM_ <= n0) return;  // tile strictly above the diagonal
+  if (p.tmask_mode == 1 && !p.tmask[(int64_t)tm * p.tm_s0 + (int64_t)tn * p.tm_s1]) {
+    // a screened-out tile: C = beta C
+    for (int e = (int)threadIdx.x; e < BM_ * BN_; e += 64 * WM_ * WN_) {
+      const int r = e % BM_, c = e / BM_;
+      if (m0 + r < p.M && n0 + c < p.N) {
+        double* cp = p.C + (int64_t)(m0 + r) + (int64_t)(n0 + c) * p.ldc;
+        *cp = p.beta == 0.0 ? 0.0 : p.beta * *cp;
+      }
+    }
+    return;
+  }
+  // mode 2: K ranges of 64 whose A rows of this tile are screened out are
+  // neither loaded nor multiplied (the stage they would fill is not read)
+  auto live = [&](int k) -> bool {
+    return p.tmask_mode != 2 || p.tmask[(int64_t)tm * p.tm_s0 + (int64_t)(k >> 6) * p.tm_s1] != 0;
+  };
 
   // two LDS stages: chunk c is read from stage c & 1 while chunk c + 1 is
   // written to the other, one barrier per chunk
@@ -239,7 +255,7 @@ gemm_f64_kernel(GemmProblem single, const GemmProblem* __restrict__ probs, int n
   TileLoader<BM_, BN_, NT> ld;
   ld.init(p, m0, n0, tid);
   if (p.K > 0) {
-    ld.load(p, 0);
+    if (live(0)) ld.load(p, 0);
     ld.store(p, As[0], Bs[0]);
   }
   __syncthreads();
@@ -248,9 +264,11 @@ gemm_f64_kernel(GemmProblem single, const GemmProblem* __restrict__ probs, int n
     const bool more = k0 + BK < p.K;
     if (more) {
       ld.advance(p);
-      ld.load(p, k0 + BK);  // in flight during the MFMAs below
+      if (live(k0 + BK)) ld.load(p, k0 + BK);  // in flight during the MFMAs below
     }
-    if constexpr (MF4) {
+    if (!live(k0)) {
+      // screened-out K range: nothing to multiply
+    } else if constexpr (MF4) {
       // v_mfma_f64_4x4x4 (4 blocks): one instruction forms rows 0..15 of a
       // 16-row block against 4 columns; its B operand holds those 4 columns
       // once per block (lane 16 k + 4 blk + j: B[k][4 t + j])

@@ -210,6 +210,78 @@ isdf_status launch_scale_rows(hipStream_t s, const double* src, int64_t lds, con
   return ISDF_OK;
 }
 
+// ------------------------------------------------ density screening helpers
+// out(b, j) = max over rows r of tile b (block consecutive rows) of |A(r, j)|
+// (A column-major m x n, lda; out column-major nt x n)
+__global__ void __launch_bounds__(256)
+tile_absmax_kernel(const double* __restrict__ A, int64_t lda, int m, int block, int nt,
+                   double* __restrict__ out) {
+  const int b = blockIdx.x, j = blockIdx.y;
+  const int r0 = b * block, r1 = min(m, r0 + block);
+  __shared__ double red[256];
+  double v = 0.0;
+  for (int r = r0 + (int)threadIdx.x; r < r1; r += 256) v = fmax(v, fabs(A[r + (int64_t)j * lda]));
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[b + (int64_t)j * nt] = red[0];
+}
+isdf_status launch_tile_absmax(hipStream_t s, const double* A, int64_t lda, int m, int n, int block,
+                               double* out) {
+  if (m <= 0 || n <= 0) return ISDF_OK;
+  const int nt = (m + block - 1) / block;
+  hipLaunchKernelGGL(tile_absmax_kernel, dim3(nt, n), dim3(256), 0, s, A, lda, m, block, nt, out);
+  ISDF_HIP_TRY(hipGetLastError());
+  return ISDF_OK;
+}
+
+// out(b, c) = max |W| over tile (b, c) of a symmetric m x m W (FP64 or FP32)
+__global__ void __launch_bounds__(256)
+tile_absmax_w_kernel(const double* __restrict__ W, const float* __restrict__ W32, int64_t ld, int m,
+                     int block, int nt, double* __restrict__ out) {
+  const int b = blockIdx.x, c = blockIdx.y;
+  const int r0 = b * block, r1 = min(m, r0 + block), c0 = c * block, c1 = min(m, c0 + block);
+  const int h = r1 - r0, w = c1 - c0;
+  __shared__ double red[256];
+  double v = 0.0;
+  for (int e = (int)threadIdx.x; e < h * w; e += 256) {
+    const int64_t i = (int64_t)(r0 + e % h) + (int64_t)(c0 + e / h) * ld;
+    v = fmax(v, W32 ? fabs((double)W32[i]) : fabs(W[i]));
+  }
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[b + (int64_t)c * nt] = red[0];
+}
+isdf_status launch_tile_absmax_w(hipStream_t s, const double* W, const float* W32, int64_t ld, int m, int block,
+                                 double* out) {
+  if (m <= 0) return ISDF_OK;
+  const int nt = (m + block - 1) / block;
+  hipLaunchKernelGGL(tile_absmax_w_kernel, dim3(nt, nt), dim3(256), 0, s, W, W32, ld, m, block, nt, out);
+  ISDF_HIP_TRY(hipGetLastError());
+  return ISDF_OK;
+}
+
+// mask[i] = B[i] >= tau
+__global__ void __launch_bounds__(256)
+mask_ge_kernel(const double* __restrict__ B, int64_t n, double tau, uint8_t* __restrict__ mask) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    mask[i] = B[i] >= tau ? 1 : 0;
+}
+isdf_status launch_mask_ge(hipStream_t s, const double* B, int64_t n, double tau, uint8_t* mask) {
+  if (n <= 0) return ISDF_OK;
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(mask_ge_kernel, dim3((unsigned)blocks), dim3(256), 0, s, B, n, tau, mask);
+  ISDF_HIP_TRY(hipGetLastError());
+  return ISDF_OK;
+}
+
 __global__ void add_kernel(const double* a, const double* b, double* c, int64_t n, double sb) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)

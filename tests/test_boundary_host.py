@@ -173,10 +173,16 @@ def test_plan_errors():
     with pytest.raises(binding.IsdfError) as e:
         binding.Plan(tiny_system("one_atom"), w_storage=2)
     assert e.value.status == -1
-    for kw in (dict(phi_budget_mb=-1), dict(ri_rows=-5)):
+    for kw in (dict(phi_budget_mb=-1), dict(ri_rows=-5), dict(ri_screen_tau=-1.0)):
         with pytest.raises(binding.IsdfError) as e:
             binding.Plan(tiny_system("one_atom"), **kw)
         assert e.value.status == -1
+    # density screening runs on the FP64 exchange only
+    with pytest.raises(binding.IsdfError) as e:
+        binding.Plan(tiny_system("one_atom"), precision=binding.MIXED_X6, ri_screen_tau=1e-6)
+    assert e.value.status == -7
+    binding.Plan(tiny_system("one_atom"), precision=binding.MIXED_X6, mixed_mask=binding.MIX_W,
+                 ri_screen_tau=1e-6).close()
     # a workspace needs an aligned pointer and a size (checked on the host)
     import ctypes as C
     s = binding._System()

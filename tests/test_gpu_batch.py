@@ -87,6 +87,37 @@ def test_batch_smallest_cell_matches_oracle(torch, cells):
         p.close()
 
 
+def test_batch_strained_64_atom_cell_matches_oracle(torch):
+    """Cell 3 of the batch (2x2x2, strained and displaced, grids 48^3 / 96^3)
+    fitted in a batch beside two smaller cells, against the stored oracle
+    values of tests/golden/make_cfg3_golden.py: pivots identical, the whole
+    diagonal W block of every window within 1e-9 relative, the whole K within
+    1e-7 Ha, |dE_x| <= 1e-6 Ha/atom."""
+    import os
+
+    g = np.load(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "cfg3_cell3_oracle.npz"))
+    three, small0, small1 = batched_cells(32, cells=[3, 0, 1])
+    plans = [binding.Plan(c) for c in (three, small0, small1)]
+    fits = binding.fit_batch(plans, max_concurrent=3)
+    f = fits[0]
+    assert np.array_equal(f.counts(), g["counts"])
+    piv = np.concatenate([f.get("points", d) for d in range(plans[0].n_domains)])
+    assert np.array_equal(piv, g["pivots"])
+    W = f.get("W")
+    offs = g["W_offsets"]
+    blocks = np.concatenate([W[offs[d]:offs[d + 1], offs[d]:offs[d + 1]].ravel() for d in range(1, len(offs) - 1)])
+    dW = float(np.max(np.abs(blocks - g["W_window_blocks"])) / np.max(np.abs(g["W_window_blocks"])))
+    K, e = _exchange(torch, f, three)
+    dK = float(np.max(np.abs(K - g["K_full"])))
+    dE = abs(e - float(g["E_x"])) / three.n_atoms
+    print(f"[batch vs oracle] cell 3 (64 atoms, strained): W blocks rel {dW:.2e} max|dK| {dK:.2e} |dE|/atom {dE:.2e}")
+    assert dW <= 1e-9 and dK <= 1e-7 and dE <= 1e-6
+    for x in fits:
+        x.close()
+    for p in plans:
+        p.close()
+
+
 def test_batch_rejects_repeated_plan(cells):
     p = binding.Plan(cells[0])
     with pytest.raises(binding.IsdfError):

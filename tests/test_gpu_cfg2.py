@@ -62,6 +62,24 @@ def test_cfg2_metric_samples(run):
     assert np.array_equal(W, W.T)
 
 
+def test_cfg2_whole_k_and_diagonal_w_blocks(run):
+    """The whole K and the whole diagonal W block of every window against the
+    stored oracle values; the universal block on its diagonal and 32 rows."""
+    s, g, plan, fit, K, ex = run
+    dK = float(np.max(np.abs(K - g["K_full"])))
+    W = fit.get("W")
+    offs = g["W_offsets"]
+    blocks = np.concatenate([W[offs[d]:offs[d + 1], offs[d]:offs[d + 1]].ravel() for d in range(1, len(offs) - 1)])
+    dWb = float(np.max(np.abs(blocks - g["W_window_blocks"])) / np.max(np.abs(g["W_window_blocks"])))
+    n0 = int(offs[1])
+    U = W[:n0, :n0]
+    dWu = max(float(np.max(np.abs(np.diag(U) - g["W_univ_diag"]))),
+              float(np.max(np.abs(U[g["W_univ_rows"]] - g["W_univ"])))) / float(np.max(np.abs(g["W_univ"])))
+    print(f"[cfg2] whole K max|dK| {dK:.2e}; window diagonal W blocks rel {dWb:.2e}; universal block rel {dWu:.2e}")
+    assert dK <= 1e-7
+    assert dWb <= 1e-9 and dWu <= 1e-9
+
+
 def test_cfg2_exchange_properties(run):
     s, g, plan, fit, K, ex = run
     assert np.max(np.abs(K - K.T)) <= 1e-12 * np.max(np.abs(K))

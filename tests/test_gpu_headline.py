@@ -7,7 +7,8 @@ captured graph.
 
 The selector is exact, so the pivots equal the oracle's; the energy must agree
 to 1e-6 Ha/atom (the mixed-precision bar of the benchmark; measured ~1e-10),
-and every replay gives the same K."""
+max|dK| stays within 2e-6 Ha (measured 8.1e-7), and every replay gives the
+same K."""
 import os
 
 import numpy as np
@@ -54,6 +55,9 @@ def test_headline_configuration_matches_oracle():
     print(f"[headline] candidates {int(np.sum(info['n_candidates']))}, fallbacks {int(np.sum(info['fallback']))}; "
           f"E_x {energies[-1]:.12f} oracle {float(g['E_x']):.12f} |dE|/atom {dE:.2e} max|dK| {dK:.2e}")
     assert len(set(energies)) == 1
-    assert dE <= 1e-6 and dK <= 1e-5
+    # the gate is |dE| <= 1e-6 Ha/atom; max|dK| is held at about twice its
+    # measured value (8.1e-7: x6 operands carry 24 bits, an FP32-class
+    # relative error per split product on K entries of order 1 Ha)
+    assert dE <= 1e-6 and dK <= 2e-6
     fit.close()
     plan.close()

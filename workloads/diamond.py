@@ -361,7 +361,7 @@ def random_density(S: np.ndarray, n_occ: int, seed: int):
     return C, C @ C.T
 
 
-def bond_orbitals(sysm: "System", hybrid_alpha: float = 0.3):
+def bond_orbitals(sysm: "System", hybrid_alpha: float = 0.3, mix: float = 0.3, seed: int = 0):
     """Localised occupied orbitals of a diamond-like cell: one per bond.
 
     Bonds are the atom pairs closer than 1.2 times the shortest minimum-image
@@ -369,9 +369,12 @@ def bond_orbitals(sysm: "System", hybrid_alpha: float = 0.3):
     closed-shell count).  Orbital b of bond (A, B) starts as the sum of two
     sp3 hybrids, s + sqrt3 (u . p) on A and on B, built from the s and p
     shells whose exponent is closest to `hybrid_alpha`, u the unit vector
-    from the atom to its partner; the set is then made S-orthonormal by
-    C = C0 (C0^T S C0)^(-1/2), the orthonormal set closest to C0 (Loewdin),
-    which keeps it localised.  Returns (C, D = C C^T, bond atom pairs)."""
+    from the atom to its partner, plus `mix` times seeded N(0, 1)
+    coefficients on every function of A and B (so that every shell of the
+    two atoms, sharp ones included, takes part); the set is then made
+    S-orthonormal by C = C0 (C0^T S C0)^(-1/2), the orthonormal set closest
+    to C0 (Loewdin), which keeps it localised.  Returns (C, D = C C^T, bond
+    atom pairs)."""
     lat = np.asarray(sysm.lattice, dtype=np.float64)
     xyz = np.asarray(sysm.xyz, dtype=np.float64)
     n = xyz.shape[0]
@@ -408,10 +411,14 @@ def bond_orbitals(sysm: "System", hybrid_alpha: float = 0.3):
         h[first[p_sh]:first[p_sh] + 3] = np.sqrt(3.0) * u
         return h
 
+    fatom = np.repeat(np.asarray(sysm.shell_atom), 2 * np.asarray(sysm.shell_l) + 1)
+    rng = np.random.default_rng(seed)
     C0 = np.zeros((nb, len(bonds)))
     for k, (a, b) in enumerate(bonds):
         u = vec[(a, b)] / np.linalg.norm(vec[(a, b)])
         C0[:, k] = hybrid(a, u) + hybrid(b, -u)
+        on = np.nonzero((fatom == a) | (fatom == b))[0]
+        C0[on, k] += mix * rng.standard_normal(on.size)
     S = periodic_overlap(lat, xyz, sysm.shell_atom, sysm.shell_l, sysm.shell_alpha)
     G = C0.T @ S @ C0
     w, U = np.linalg.eigh(G)
