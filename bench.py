@@ -483,7 +483,7 @@ def study_batch(torch, binding, log, n_cells=32, max_concurrent=4, repeat=3):
         p.close()
 
 
-def study_screening(torch, binding, log, configs=(2, 4), taus=(1e-10, 1e-8, 1e-6, 1e-4), builds=5):
+def study_screening(torch, binding, log, configs=(2, 4), taus=(1e-8, 1e-6, 1e-4, 1e-2, 1e-1, 1.0), builds=5):
     """Density screening of the occ-RI exchange (FP64 products) with
     localised bond orbitals: per threshold, the kept fraction of the Q tiles,
     the time per K C build (after two warm ones) and the change of E_x and
