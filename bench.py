@@ -613,6 +613,9 @@ def main():
                     help="selector score cutoff (default: 0.001 for the 216-atom cell, 0.05 otherwise; "
                          "swept on each workload for the fastest exact selection)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workspace-margin-gb", type=float, default=6.0,
+                    help="device memory left outside the plans' workspace (GiB); < 0: no workspace "
+                         "(plans allocate and cache their own blocks)")
     ap.add_argument("--exchanges", type=int, default=7)
     ap.add_argument("--paths", choices=["both", "reference", "optimized"], default="both")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -766,20 +769,37 @@ def main():
 
     mlp_cutoff = args.mlp_cutoff if args.mlp_cutoff is not None else (0.001 if args.config >= 4 else 0.05)
     results = {}
-    if args.paths in ("both", "reference"):
-        plan = binding.Plan(s, stream=stream, tune_file=tune)
-        log(f"cfg{args.config}: N={plan.n_basis} N_mu={plan.n_mu} domains={plan.n_domains}")
-        results["reference"] = run_path(plan, "reference", steps=args.ref_steps, warmup=1)
-        plan.close()
     weights, hist = None, None
     if args.paths in ("both", "optimized"):
         weights, hist = train_selector(torch, log)
+    # One caller workspace (isdf_options.workspace) for the plans of the
+    # timed paths, one plan at a time: every device buffer of their fits and
+    # exchanges is carved from it by the plan's allocator, so no fit after
+    # the first calls hipMalloc (a large hipMalloc costs about 29 ms per GB
+    # on this device, more than the kernels that fill it)
+    ws = None
+    if args.workspace_margin_gb >= 0:
+        torch.cuda.empty_cache()
+        free_b, _ = torch.cuda.mem_get_info(dev)
+        ws_bytes = int(free_b - args.workspace_margin_gb * 2 ** 30) // 4096 * 4096
+        ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+        log(f"workspace {ws_bytes / 2 ** 30:.1f} GiB")
+    if args.paths in ("both", "reference"):
+        plan = binding.Plan(s, stream=stream, tune_file=tune, workspace=ws)
+        log(f"cfg{args.config}: N={plan.n_basis} N_mu={plan.n_mu} domains={plan.n_domains}")
+        results["reference"] = run_path(plan, "reference", steps=args.ref_steps, warmup=1)
+        plan.close()
+        plan = None  # releases its hold on the workspace tensor
+    if args.paths in ("both", "optimized"):
         plan = binding.Plan(s, stream=stream, precision=binding.MIXED_X6,
                             selector=binding.SEL_MLP, mlp_weights=weights, mlp_keep=args.mlp_keep,
                             mlp_cutoff=mlp_cutoff, tune_file=tune,
-                            w_storage=binding.W_F32 if args.config == 5 else binding.W_F64)
+                            w_storage=binding.W_F32 if args.config == 5 else binding.W_F64, workspace=ws)
         results["optimized"] = run_path(plan, "optimized", occ=True)
         plan.close()
+        plan = None
+    del ws
+    torch.cuda.empty_cache()
 
     # the method with every universal point a fitting function (the sinc
     # functions of the sparse grid): no selection or fit on the universal
