@@ -42,14 +42,20 @@ __device__ inline int xcd_tile(int b, int nb) {
   const int x = b % NXCD, q = b / NXCD, per = nb / NXCD, rem = nb % NXCD;
   return (x < rem ? x * (per + 1) : rem * (per + 1) + (x - rem) * per) + q;
 }
+// Tile order: groups of G row tiles, the row index running fastest within a
+// group.  The workgroups that run together on one XCD (consecutive tiles)
+// then share each B column panel G ways and keep the group's A row panels in
+// that XCD's L2 across all columns; a plain row-major order read every B
+// panel once per row tile from HBM (measured: exchange products fetching
+// about 12 times their operand bytes).
 __device__ inline void tile_coords(int local, int tilesM, int tilesN, int* tm, int* tn) {
-  if (tilesN <= tilesM) {
-    *tn = local % tilesN;
-    *tm = local / tilesN;
-  } else {
-    *tm = local % tilesM;
-    *tn = local / tilesM;
-  }
+  constexpr int G = 8;
+  const int per_group = G * tilesN;
+  const int g = local / per_group;
+  const int rows = min(G, tilesM - g * G);
+  const int idx = local - g * per_group;
+  *tm = g * G + idx % rows;
+  *tn = idx / rows;
 }
 
 // Element (m, n) of a Hadamard epilogue's E, held in FP64 or FP32.
