@@ -42,9 +42,11 @@ typedef double dv2 __attribute__((ext_vector_type(2)));
 typedef const __attribute__((address_space(1))) double* gdp;
 typedef const __attribute__((address_space(1))) dv2* gd2p;
 typedef const __attribute__((address_space(1))) int32_t* gip;
+typedef const __attribute__((address_space(1))) uint8_t* gbp;
 __device__ inline double gld(const double* p) { return *(gdp)p; }
 __device__ inline dv2 gld2(const double* p) { return *(gd2p)p; }
 __device__ inline int32_t gldi(const int32_t* p) { return *(gip)p; }
+__device__ inline uint8_t gldb(const uint8_t* p) { return *(gbp)p; }
 }  // namespace
 
 // Loads of the large-tile kernel for elements outside a problem read this
@@ -213,7 +215,7 @@ gemm_f64_kernel(GemmProblem single, const GemmProblem* __restrict__ probs, int n
   const int m0 = tm * BM_, n0 = tn * BN_;
   if (n0 >= p.N) return;
   if (p.lower && m0 + BM_ <= n0) return;  // tile strictly above the diagonal
-  if (p.tmask_mode == 1 && !p.tmask[(int64_t)tm * p.tm_s0 + (int64_t)tn * p.tm_s1]) {
+  if (p.tmask_mode == 1 && !gldb(p.tmask + (int64_t)tm * p.tm_s0 + (int64_t)tn * p.tm_s1)) {
     // a screened-out tile: C = beta C
     for (int e = (int)threadIdx.x; e < BM_ * BN_; e += 64 * WM_ * WN_) {
       const int r = e % BM_, c = e / BM_;
@@ -227,7 +229,7 @@ gemm_f64_kernel(GemmProblem single, const GemmProblem* __restrict__ probs, int n
   // mode 2: K ranges of 64 whose A rows of this tile are screened out are
   // neither loaded nor multiplied (the stage they would fill is not read)
   auto live = [&](int k) -> bool {
-    return p.tmask_mode != 2 || p.tmask[(int64_t)tm * p.tm_s0 + (int64_t)(k >> 6) * p.tm_s1] != 0;
+    return p.tmask_mode != 2 || gldb(p.tmask + (int64_t)tm * p.tm_s0 + (int64_t)(k >> 6) * p.tm_s1) != 0;
   };
 
   // two LDS stages: chunk c is read from stage c & 1 while chunk c + 1 is

@@ -58,10 +58,21 @@ __device__ inline void tile_coords(int local, int tilesM, int tilesN, int* tm, i
   *tn = idx / rows;
 }
 
+// Every operand, epilogue input and output lives in device global memory.
+// Reaching it through global-address-space pointers makes the compiler emit
+// global loads and stores instead of flat ones: a flat access also counts
+// against the LDS wait counter, so every wait for LDS fragments would wait
+// for the next chunk's operand prefetch from HBM as well.
+#define GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ inline const GLOBAL T* gro(const T* q) { return (const GLOBAL T*)q; }
+template <class T>
+__device__ inline GLOBAL T* grw(T* q) { return (GLOBAL T*)q; }
+
 // Element (m, n) of a Hadamard epilogue's E, held in FP64 or FP32.
 __device__ inline double mixed_e(const MixedProblem& p, int m, int n) {
   const int64_t i = (int64_t)m + (int64_t)n * p.lde;
-  return p.E32 ? (double)p.E32[i] : p.E[i];
+  return p.E32 ? (double)gro(p.E32)[i] : gro(p.E)[i];
 }
 
 __device__ inline const MixedProblem* find_mixed(const MixedProblem* probs, int nprob, int tile) {
@@ -114,8 +125,8 @@ gemm_mixed_kernel(MixedProblem single, const MixedProblem* __restrict__ probs, i
     if (tile_in && k0 + BK <= p.K) {  // interior: no bounds tests (see the wide kernel)
 #pragma unroll
       for (int s = 0; s < S; ++s) {
-        ra[s] = *reinterpret_cast<const bf8v*>(p.A + s * p.plane_a + (int64_t)(m0 + lr) * p.lda + k0 + lk);
-        rb[s] = *reinterpret_cast<const bf8v*>(p.B + s * p.plane_b + (int64_t)(n0 + lr) * p.ldb + k0 + lk);
+        ra[s] = *reinterpret_cast<const GLOBAL bf8v*>(gro(p.A) + s * p.plane_a + (int64_t)(m0 + lr) * p.lda + k0 + lk);
+        rb[s] = *reinterpret_cast<const GLOBAL bf8v*>(gro(p.B) + s * p.plane_b + (int64_t)(n0 + lr) * p.ldb + k0 + lk);
       }
     } else {
       const int gm = m0 + lr, gk = k0 + lk;
@@ -123,11 +134,11 @@ gemm_mixed_kernel(MixedProblem single, const MixedProblem* __restrict__ probs, i
       for (int s = 0; s < S; ++s) {
         bf8v v;
         if (gm < p.M && gk + 8 <= p.K) {
-          v = *reinterpret_cast<const bf8v*>(p.A + s * p.plane_a + (int64_t)gm * p.lda + gk);
+          v = *reinterpret_cast<const GLOBAL bf8v*>(gro(p.A) + s * p.plane_a + (int64_t)gm * p.lda + gk);
         } else {
 #pragma unroll
           for (int t = 0; t < 8; ++t)
-            v[t] = (gm < p.M && gk + t < p.K) ? p.A[s * p.plane_a + (int64_t)gm * p.lda + gk + t]
+            v[t] = (gm < p.M && gk + t < p.K) ? gro(p.A)[s * p.plane_a + (int64_t)gm * p.lda + gk + t]
                                                : (__bf16)0.0f;
         }
         ra[s] = v;
@@ -137,11 +148,11 @@ gemm_mixed_kernel(MixedProblem single, const MixedProblem* __restrict__ probs, i
       for (int s = 0; s < S; ++s) {
         bf8v v;
         if (gn < p.N && gk + 8 <= p.K) {
-          v = *reinterpret_cast<const bf8v*>(p.B + s * p.plane_b + (int64_t)gn * p.ldb + gk);
+          v = *reinterpret_cast<const GLOBAL bf8v*>(gro(p.B) + s * p.plane_b + (int64_t)gn * p.ldb + gk);
         } else {
 #pragma unroll
           for (int t = 0; t < 8; ++t)
-            v[t] = (gn < p.N && gk + t < p.K) ? p.B[s * p.plane_b + (int64_t)gn * p.ldb + gk + t]
+            v[t] = (gn < p.N && gk + t < p.K) ? gro(p.B)[s * p.plane_b + (int64_t)gn * p.ldb + gk + t]
                                                : (__bf16)0.0f;
         }
         rb[s] = v;
@@ -215,7 +226,7 @@ gemm_mixed_kernel(MixedProblem single, const MixedProblem* __restrict__ probs, i
       for (int v = 0; v < 4; ++v) {
         const int gn = n0 + wn * 32 + b * 16 + 4 * (lane >> 4) + v;
         if (gn >= p.N) continue;
-        double* cp = p.C + (int64_t)gm + (int64_t)gn * p.ldc;
+        GLOBAL double* cp = grw(p.C) + (int64_t)gm + (int64_t)gn * p.ldc;
         const double x = acc[a][b][v];
         if (EPI == EPI_THETA) {
           *cp = x * (x + 2.0 * accN[a][b][v]);
@@ -285,10 +296,10 @@ gemm_mixed_wide_kernel(MixedProblem single, const MixedProblem* __restrict__ pro
   // staging: A rows lr (64 rows), B rows lr and lr + 64; unit lu of 8 k values
   const int lr = tid >> 2, lu = tid & 3;
   bf8v ra[S], rb[S][2];
-  auto fetch = [&](const __bf16* base, int64_t plane, int64_t ld, int rows, int r, int gk) -> bf8v {
+  auto fetch = [&](const GLOBAL __bf16* base, int64_t plane, int64_t ld, int rows, int r, int gk) -> bf8v {
     bf8v v;
     if (r < rows && gk + 8 <= p.K) {
-      v = *reinterpret_cast<const bf8v*>(base + plane + (int64_t)r * ld + gk);
+      v = *reinterpret_cast<const GLOBAL bf8v*>(base + plane + (int64_t)r * ld + gk);
     } else {
 #pragma unroll
       for (int t = 0; t < 8; ++t)
@@ -301,24 +312,24 @@ gemm_mixed_wide_kernel(MixedProblem single, const MixedProblem* __restrict__ pro
   // completion at its branch, and the next chunk would no longer be in
   // flight during the MFMAs.
   const bool tile_in = m0 + WBM <= p.M && n0 + WBN <= p.N;
-  const __bf16* pa = p.A + (int64_t)(m0 + lr) * p.lda + lu * 8;
-  const __bf16* pb0 = p.B + (int64_t)(n0 + lr) * p.ldb + lu * 8;
-  const __bf16* pb1 = pb0 + (int64_t)64 * p.ldb;
+  const GLOBAL __bf16* pa = gro(p.A) + (int64_t)(m0 + lr) * p.lda + lu * 8;
+  const GLOBAL __bf16* pb0 = gro(p.B) + (int64_t)(n0 + lr) * p.ldb + lu * 8;
+  const GLOBAL __bf16* pb1 = pb0 + (int64_t)64 * p.ldb;
   auto load = [&](int k0) {
     if (tile_in && k0 + BK <= p.K) {
 #pragma unroll
       for (int s = 0; s < S; ++s) {
-        ra[s] = *reinterpret_cast<const bf8v*>(pa + s * p.plane_a + k0);
-        rb[s][0] = *reinterpret_cast<const bf8v*>(pb0 + s * p.plane_b + k0);
-        rb[s][1] = *reinterpret_cast<const bf8v*>(pb1 + s * p.plane_b + k0);
+        ra[s] = *reinterpret_cast<const GLOBAL bf8v*>(pa + s * p.plane_a + k0);
+        rb[s][0] = *reinterpret_cast<const GLOBAL bf8v*>(pb0 + s * p.plane_b + k0);
+        rb[s][1] = *reinterpret_cast<const GLOBAL bf8v*>(pb1 + s * p.plane_b + k0);
       }
     } else {
       const int gk = k0 + lu * 8;
 #pragma unroll
       for (int s = 0; s < S; ++s) {
-        ra[s] = fetch(p.A, s * p.plane_a, p.lda, p.M, m0 + lr, gk);
-        rb[s][0] = fetch(p.B, s * p.plane_b, p.ldb, p.N, n0 + lr, gk);
-        rb[s][1] = fetch(p.B, s * p.plane_b, p.ldb, p.N, n0 + lr + 64, gk);
+        ra[s] = fetch(gro(p.A), s * p.plane_a, p.lda, p.M, m0 + lr, gk);
+        rb[s][0] = fetch(gro(p.B), s * p.plane_b, p.ldb, p.N, n0 + lr, gk);
+        rb[s][1] = fetch(gro(p.B), s * p.plane_b, p.ldb, p.N, n0 + lr + 64, gk);
       }
     }
   };
@@ -419,14 +430,14 @@ gemm_mixed_wide_kernel(MixedProblem single, const MixedProblem* __restrict__ pro
     if (vec) {
       for (int e = tid; e < S * WBN * (WBM / 8); e += 256) {
         const int q = e / (WBN * (WBM / 8)), r = (e / (WBM / 8)) % WBN, c8 = (e % (WBM / 8)) * 8;
-        *reinterpret_cast<bf8v*>(p.P + q * p.plane_p + (int64_t)(n0 + r) * p.ldp + p.p_off + m0 + c8) =
+        *reinterpret_cast<GLOBAL bf8v*>(grw(p.P) + q * p.plane_p + (int64_t)(n0 + r) * p.ldp + p.p_off + m0 + c8) =
             *reinterpret_cast<const bf8v*>(&Ps[(q * WBN + r) * WBM + c8]);
       }
     } else {
       for (int e = tid; e < S * WBN * WBM; e += 256) {
         const int q = e / (WBN * WBM), r = (e / WBM) % WBN, c = e % WBM;
         if (n0 + r < p.N && m0 + c < p.M)
-          p.P[q * p.plane_p + (int64_t)(n0 + r) * p.ldp + p.p_off + m0 + c] = Ps[(q * WBN + r) * WBM + c];
+          grw(p.P)[q * p.plane_p + (int64_t)(n0 + r) * p.ldp + p.p_off + m0 + c] = Ps[(q * WBN + r) * WBM + c];
       }
     }
     return;
@@ -442,7 +453,7 @@ gemm_mixed_wide_kernel(MixedProblem single, const MixedProblem* __restrict__ pro
         const int gn = n0 + wn * 64 + b * 16 + 4 * (lane >> 4) + v;
         if (gn >= p.N) continue;
         const double x = acc[a][b][v];
-        double* cp = p.C + (int64_t)gm + (int64_t)gn * p.ldc;
+        GLOBAL double* cp = grw(p.C) + (int64_t)gm + (int64_t)gn * p.ldc;
         double y;
         if (EPI == EPI_HADAMARD)
           y = p.alpha * x * mixed_e(p, gm, gn);
