@@ -345,9 +345,9 @@ gemm_mixed_wide_kernel(MixedProblem single, const MixedProblem* __restrict__ pro
   store(0);
   __syncthreads();
   const int fu = lane >> 4;  // fragment unit: k = 8 fu .. 8 fu + 7
-  for (int k0 = 0, st = 0; k0 < p.K; k0 += BK, st ^= 1) {
-    const bool more = k0 + BK < p.K;
-    if (more) load(k0 + BK);  // in flight during this chunk's MFMAs
+  // fragment reads and MFMAs of the chunk in stage st; the FP32 sums go into
+  // the FP64 accumulators every KFLUSH values of k and after the last chunk
+  auto chunk = [&](int k0, int st, bool last) {
     // planes 0 and 1 first; plane 2 (x6) then reuses plane 1's registers
     bf8v x0[4], y0[2], x1[4], y1[2];
 #pragma unroll
@@ -388,7 +388,7 @@ gemm_mixed_wide_kernel(MixedProblem single, const MixedProblem* __restrict__ pro
           lo[a][b] = l;
         }
     }
-    if (((k0 + BK) % KFLUSH) == 0 || !more) {
+    if (((k0 + BK) % KFLUSH) == 0 || last) {
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -399,14 +399,46 @@ gemm_mixed_wide_kernel(MixedProblem single, const MixedProblem* __restrict__ pro
             hi[a][b][v] = lo[a][b][v] = 0.f;
           }
     }
-    if (more) store(st ^ 1);  // the other stage: its last readers passed the previous barrier
+  };
+  int k0 = 0, st = 0;
+  for (; k0 + BK < p.K; k0 += BK, st ^= 1) {
+    load(k0 + BK);  // in flight during this chunk's MFMAs
+    chunk(k0, st, false);
+    store(st ^ 1);  // the other stage: its last readers passed the previous barrier
     __syncthreads();
   }
+  // The last chunk (peeled).  With the planes epilogue and E in FP32 the
+  // lane's 32 values of E are loaded here, in flight during the chunk's MFMAs,
+  // into registers that the staging loads no longer hold; value (a, b, v)
+  // is word v of ew[4 a + b].  Outside the problem: a valid address, value 0.
+  constexpr bool E_REG = EPI == EPI_HADAMARD_PLANES;
+  const bool ereg = E_REG && p.E32 != nullptr;
+  f4v ew[8];
+  if (ereg) {
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int gm = m0 + wm * 32 + a * 16 + (lane & 15);
+          const int gn = n0 + wn * 64 + b * 16 + 4 * (lane >> 4) + v;
+          const bool ok = gm < p.M && gn < p.N;
+          const float x = gro(p.E32)[ok ? (int64_t)gm + (int64_t)gn * p.lde : 0];
+          ew[a * 4 + b][v] = ok ? x : 0.f;
+        }
+  }
+  chunk(k0, st, true);
+  __syncthreads();
   // lane holds C(m0 + wm*32 + a*16 + lane%16, n0 + wn*64 + b*16 + 4(lane/16) + v)
   if constexpr (EPI == EPI_HADAMARD_PLANES) {
     // The transposed tile's planes go through LDS (the B stages, free now:
-    // S x 128 x 64 values) and out as 16-byte rows of 8 values of m.
+    // S x 128 x 64 values) and out as 16-byte rows of 8 values of m.  Within
+    // row r the four 16-value blocks of m are permuted by (r >> 2) & 3, so
+    // that the four lane groups of a wave, four rows apart, store into four
+    // distinct bank ranges; 8-value runs stay contiguous for the reads.
     __bf16* Ps = &Bs[0][0][0];
+    auto pidx = [](int q, int r, int c) { return (q * WBN + r) * WBM + (c ^ (((r >> 2) & 3) << 4)); };
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
       const int cm = wm * 32 + a * 16 + (lane & 15), gm = m0 + cm;
@@ -415,12 +447,15 @@ gemm_mixed_wide_kernel(MixedProblem single, const MixedProblem* __restrict__ pro
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int rn = wn * 64 + b * 16 + 4 * (lane >> 4) + v, gn = n0 + rn;
-          double y = (gm < p.M && gn < p.N) ? p.alpha * acc[a][b][v] * mixed_e(p, gm, gn)
-                                            : 0.0;
+          double y = 0.0;
+          if (gm < p.M && gn < p.N) {
+            const double e = ereg ? (double)ew[a * 4 + b][v] : mixed_e(p, gm, gn);
+            y = p.alpha * acc[a][b][v] * e;
+          }
 #pragma unroll
           for (int q = 0; q < S; ++q) {
             const __bf16 h = (__bf16)(float)y;
-            Ps[(q * WBN + rn) * WBM + cm] = h;
+            Ps[pidx(q, rn, cm)] = h;
             y -= (double)(float)h;
           }
         }
@@ -431,13 +466,13 @@ gemm_mixed_wide_kernel(MixedProblem single, const MixedProblem* __restrict__ pro
       for (int e = tid; e < S * WBN * (WBM / 8); e += 256) {
         const int q = e / (WBN * (WBM / 8)), r = (e / (WBM / 8)) % WBN, c8 = (e % (WBM / 8)) * 8;
         *reinterpret_cast<GLOBAL bf8v*>(grw(p.P) + q * p.plane_p + (int64_t)(n0 + r) * p.ldp + p.p_off + m0 + c8) =
-            *reinterpret_cast<const bf8v*>(&Ps[(q * WBN + r) * WBM + c8]);
+            *reinterpret_cast<const bf8v*>(&Ps[pidx(q, r, c8)]);
       }
     } else {
       for (int e = tid; e < S * WBN * WBM; e += 256) {
         const int q = e / (WBN * WBM), r = (e / WBM) % WBN, c = e % WBM;
         if (n0 + r < p.N && m0 + c < p.M)
-          grw(p.P)[q * p.plane_p + (int64_t)(n0 + r) * p.ldp + p.p_off + m0 + c] = Ps[(q * WBN + r) * WBM + c];
+          grw(p.P)[q * p.plane_p + (int64_t)(n0 + r) * p.ldp + p.p_off + m0 + c] = Ps[pidx(q, r, c)];
       }
     }
     return;

@@ -39,7 +39,7 @@ def test_roofline_arithmetic(monkeypatch):
     monkeypatch.setattr(bench, "measured_traffic", lambda fam: None)
     # HBM family: 4 launches, 2 ms in all, 4 GB algorithmic -> 1 GB in 0.5 ms = 2000 GB/s
     st = {"ms": 2.0, "launches": 4, "bytes": 4e9, "flops": 0.0}
-    r = bench.roofline(6, st, mixed=False)
+    r = bench.roofline(6, st, mixed=set())
     assert r["bound"] == "hbm" and r["unit"] == "GB/s" and r["family"] == "fft"
     assert r["achieved"] == pytest.approx(2000.0) and r["peak"] == bench.PEAK_HBM_GBS
     assert r["frac"] == pytest.approx(2000.0 / bench.PEAK_HBM_GBS, abs=1e-4)
@@ -47,11 +47,11 @@ def test_roofline_arithmetic(monkeypatch):
     assert r["mfma_issue_frac"] is None
     # GEMM family in FP64: 2 launches, 1 ms, 4e10 flop -> 40 TFLOP/s against the FP64 peak
     st = {"ms": 1.0, "launches": 2, "bytes": 0.0, "flops": 4e10}
-    r = bench.roofline(4, st, mixed=False)
+    r = bench.roofline(4, st, mixed=set())
     assert r["unit"] == "TFLOP/s" and r["peak"] == bench.PEAK_FP64_TFS
     assert r["achieved"] == pytest.approx(40.0)
     # the exchange family in BF16 splits is priced against the BF16 peak, six products per flop
-    r = bench.roofline(5, st, mixed=True)
+    r = bench.roofline(5, st, mixed={5})
     assert r["peak"] == bench.PEAK_BF16_TFS and "gemm_mixed_kernel" in r["kernel"]
     assert r["mfma_issue_frac"] == pytest.approx(6 * 40.0 / bench.PEAK_BF16_TFS, abs=1e-4)
 
