@@ -189,7 +189,7 @@ struct TileLoader {
 // TAG only separates the instantiations per role (selection Gram, Coulomb
 // metric, fit solves, exchange) so that profiles attribute time per role.
 template <int EPI, int TAG, int BM_, int BN_, int WM_, int WN_, int MF4 = 0>
-__global__ void __launch_bounds__(64 * WM_ * WN_, (EPI == EPI_AXPBY && WM_ * WN_ == 8) ? 4 : 1)
+__global__ void __launch_bounds__(64 * WM_ * WN_, (EPI == EPI_AXPBY && WM_ * WN_ == 8) ? 4 : (EPI == EPI_AXPBY && MF4 == 0 && WM_ * WN_ == 4) ? 3 : 1)
 gemm_f64_kernel(GemmProblem single, const GemmProblem* __restrict__ probs, int nprob) {
   constexpr int NT = 64 * WM_ * WN_;
   constexpr int TM = BM_ / WM_, TN = BN_ / WN_;  // wave tile
