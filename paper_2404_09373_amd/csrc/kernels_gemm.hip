@@ -184,12 +184,26 @@ struct TileLoader {
     }
   }
 };
+
+// Waves per SIMD that the register allocation must leave room for (the
+// second launch-bounds argument): two workgroups per CU of the 512-thread
+// AXPBY tile, three of the 256-thread AXPBY tiles and of the 64 x 64 Theta
+// tile, one otherwise.  More resident workgroups keep more operand loads in
+// flight; these bounds cost no spills (a few outside the main loop for the
+// 512-thread tile), tighter ones spill inside it.
+template <int EPI, int BM_, int BN_, int WM_, int WN_, int MF4>
+constexpr int gemm_min_waves() {
+  if (EPI == EPI_AXPBY && WM_ * WN_ == 8) return 4;
+  if (EPI == EPI_AXPBY && MF4 == 0 && WM_ * WN_ == 4) return 3;
+  if (EPI == EPI_THETA && MF4 == 0 && BM_ == 64 && BN_ == 64 && WM_ * WN_ == 4) return 3;
+  return 1;
+}
 }  // namespace
 
 // TAG only separates the instantiations per role (selection Gram, Coulomb
 // metric, fit solves, exchange) so that profiles attribute time per role.
 template <int EPI, int TAG, int BM_, int BN_, int WM_, int WN_, int MF4 = 0>
-__global__ void __launch_bounds__(64 * WM_ * WN_, (EPI == EPI_AXPBY && WM_ * WN_ == 8) ? 4 : (EPI == EPI_AXPBY && MF4 == 0 && WM_ * WN_ == 4) ? 3 : 1)
+__global__ void __launch_bounds__(64 * WM_ * WN_, (gemm_min_waves<EPI, BM_, BN_, WM_, WN_, MF4>()))
 gemm_f64_kernel(GemmProblem single, const GemmProblem* __restrict__ probs, int nprob) {
   constexpr int NT = 64 * WM_ * WN_;
   constexpr int TM = BM_ / WM_, TN = BN_ / WN_;  // wave tile
