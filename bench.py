@@ -91,20 +91,23 @@ def set_profile(plan, mask):
 
 
 # family -> (counter summary under profiles/, kernel source the summary was taken on)
-TRAFFIC = {
-    "fft": ("traffic_fft_cfg2.md", "kernels_fft.hip"),
+TRAFFIC = {  # (family, workload config) -> (counter summary, kernel source it was measured on)
+    ("fft", 2): ("traffic_fft_cfg2.md", "kernels_fft.hip"),
+    ("gemm_exchange", 5): ("traffic_exchange_cfg5.md", "kernels_mixed.hip"),
+    ("gemm_metric", 5): ("traffic_metric_cfg5.md", "kernels_gemm.hip"),
 }
 
 
-def measured_traffic(fam):
-    """HBM bytes per launch of the family from its committed counter summary,
-    or None when there is none or the kernel source changed since."""
+def measured_traffic(fam, config):
+    """HBM bytes per launch of the family on workload `config` from its
+    committed counter summary, or None when there is none or the kernel
+    source changed since."""
     import hashlib
 
-    name = FAMILIES[fam][0]
-    if name not in TRAFFIC:
+    key = (FAMILIES[fam][0], config)
+    if key not in TRAFFIC:
         return None
-    summary, source = TRAFFIC[name]
+    summary, source = TRAFFIC[key]
     path = os.path.join(ROOT, "profiles", summary)
     src = os.path.join(ROOT, "paper_2404_09373_amd", "csrc", source)
     if not os.path.exists(path):
@@ -120,7 +123,7 @@ def measured_traffic(fam):
     return float(vals["traffic_bytes_per_launch"])
 
 
-def roofline(fam, st, mixed):
+def roofline(fam, st, mixed, config=None):
     """Roofline figure of family `fam` from its launches in the timed steps;
     `mixed`: the families whose products ran on the split-BF16 kernels."""
     name, bound, kname = FAMILIES[fam]
@@ -143,7 +146,7 @@ def roofline(fam, st, mixed):
         "peak": peak,
         "unit": unit,
         "frac": round(achieved / peak, 4),
-        "traffic": measured_traffic(fam),
+        "traffic": measured_traffic(fam, config),
         "avg_launch_us": round(avg_s * 1e6, 3),
         "launches": st["launches"],
         "alg_bytes_per_launch": st["bytes"] / n,
@@ -849,7 +852,7 @@ def main():
     # the exchange products run split-BF16 on the optimized path, and so do
     # the metric rows of a fitted universal domain (not the windows' rows)
     mixed_fams = ({5} | (set() if head["univ_all"] else {3})) if use_opt else set()
-    rl = roofline(head["dominant"], head["timed"], mixed=mixed_fams)
+    rl = roofline(head["dominant"], head["timed"], mixed=mixed_fams, config=args.config)
 
     parity = None
     gpath = os.path.join(ROOT, "tests", "golden", f"cfg{args.config}_oracle.npz")

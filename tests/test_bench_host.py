@@ -36,7 +36,7 @@ def test_family_table_matches_header():
 
 
 def test_roofline_arithmetic(monkeypatch):
-    monkeypatch.setattr(bench, "measured_traffic", lambda fam: None)
+    monkeypatch.setattr(bench, "measured_traffic", lambda fam, config: None)
     # HBM family: 4 launches, 2 ms in all, 4 GB algorithmic -> 1 GB in 0.5 ms = 2000 GB/s
     st = {"ms": 2.0, "launches": 4, "bytes": 4e9, "flops": 0.0}
     r = bench.roofline(6, st, mixed=set())
@@ -70,11 +70,13 @@ def test_traffic_figure_needs_the_measured_source(tmp_path, monkeypatch):
     (tmp_path / "profiles" / "traffic_fft_cfg2.md").write_text(
         f"traffic_bytes_per_launch: 2459581000\nkernel_source_sha256: {sha}\n")
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    assert bench.measured_traffic(6) == pytest.approx(2459581000.0)
+    assert bench.measured_traffic(6, 2) == pytest.approx(2459581000.0)
+    # it holds for the workload it was measured on only
+    assert bench.measured_traffic(6, 5) is None
     # a changed source voids it; families without a summary have none
     srcp.write_text(src + "\n// changed\n")
-    assert bench.measured_traffic(6) is None
-    assert bench.measured_traffic(0) is None
+    assert bench.measured_traffic(6, 2) is None
+    assert bench.measured_traffic(0, 2) is None
 
 
 def test_cpu_baseline_both_exchange_forms():
