@@ -297,7 +297,10 @@ sel_column_kernel(const SelDomain* __restrict__ doms, const int32_t* __restrict_
   if (st[dom].done) return;
   const SelDomain D = doms[dom];
   const int lane = threadIdx.x & 63;
-  const int w = threadIdx.x >> 6;
+  // the wave index is uniform within a wave; said so, the pivot-row values
+  // pr[c] below are wave-uniform loads through the scalar cache instead of
+  // one vector load per lane
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int i = (tile - D.tile_off) * SEL_TILE + lane;
   const bool valid = i < D.pts;
   const int ii = valid ? i : 0;
@@ -307,11 +310,14 @@ sel_column_kernel(const SelDomain* __restrict__ doms, const int32_t* __restrict_
   double sL = 0.0, sN = 0.0, sc = 0.0;
   {
     int c = w;
+    // two iterations per trip: eight loads in flight per wave, the same sums
+#pragma unroll 2
     for (; c + 12 < D.nL; c += 16) {
       const double a0 = ph[c * P], a1 = ph[(c + 4) * P], a2 = ph[(c + 8) * P], a3 = ph[(c + 12) * P];
       sL += a0 * pr[c] + a1 * pr[c + 4] + a2 * pr[c + 8] + a3 * pr[c + 12];
     }
     for (; c < D.nL; c += 4) sL += ph[c * P] * pr[c];
+#pragma unroll 2
     for (; c + 12 < D.nG; c += 16) {
       const double a0 = ph[c * P], a1 = ph[(c + 4) * P], a2 = ph[(c + 8) * P], a3 = ph[(c + 12) * P];
       sN += a0 * pr[c] + a1 * pr[c + 4] + a2 * pr[c + 8] + a3 * pr[c + 12];
@@ -320,6 +326,7 @@ sel_column_kernel(const SelDomain* __restrict__ doms, const int32_t* __restrict_
   }
   const double* lf = lfac + D.lfac_off + ii;
   int j = w;
+#pragma unroll 2
   for (; j + 12 < k; j += 16) {
     const double b0 = lf[j * P], b1 = lf[(j + 4) * P], b2 = lf[(j + 8) * P], b3 = lf[(j + 12) * P];
     sc += b0 * pr[D.nG + j] + b1 * pr[D.nG + j + 4] + b2 * pr[D.nG + j + 8] + b3 * pr[D.nG + j + 12];

@@ -102,3 +102,28 @@ def test_cfg2_sampled_windows_stagewise(run):
         assert np.array_equal(fit.get("points", d), piv)
         F, _, _ = isdf.fit_functions(Phi, dom.L.size, piv)
         assert np.max(np.abs(fit.get("F", d) - F)) <= 1e-7 * np.max(np.abs(F))
+
+
+def test_cfg2_mixed_occ_ri_chunked_against_oracle(run):
+    """x6 occ-RI K C on the 64-atom workload, Q held in row blocks of 2048
+    (the last one ragged) and the Z products' 2 N_mu = 13312 columns in two K
+    chunks (8192 and 5120, the second accumulating): against the oracle's
+    whole K times C_occ.  Bound as for the smaller cells' x6 occ-RI: the
+    split-BF16 products carry about 2^-24 relative error per product."""
+    import torch
+
+    s, g, plan, fit, K, ex = run
+    xplan = binding.Plan(s, precision=binding.MIXED_X6, ri_rows=2048,
+                         stream=torch.cuda.current_stream().cuda_stream)
+    xfit = xplan.fit()
+    assert np.array_equal(xfit.counts(), g["counts"])
+    C = torch.tensor(s.C_occ, dtype=torch.float64, device="cuda")
+    KC = torch.empty_like(C)
+    _, e = xfit.exchange_occ_ri(C, KC)
+    ref = g["K_full"] @ s.C_occ
+    dKC = float(np.max(np.abs(KC.cpu().numpy() - ref)))
+    dE = abs(e - float(g["E_x"])) / s.n_atoms
+    print(f"[cfg2 x6 occ-RI chunked] max|dKC| {dKC:.2e} |dE|/atom {dE:.2e}")
+    xfit.close()
+    xplan.close()
+    assert dKC <= 1e-5 and dE <= 1e-6
