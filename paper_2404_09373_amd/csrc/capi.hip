@@ -2686,7 +2686,8 @@ isdf_status exchange_prepare(isdf_plan_s* plan, isdf_fit_s* fit, int n_occ, bool
         }
       }
       if ((st = upload(fit->d_zprobs, zp)) != ISDF_OK) return st;
-      // (K C)^T = -(Z12)(xln)^T over k ranges, partials summed in order
+      // (K C)^T = -(Z12)(xln)^T over k ranges on the wide-tile kernel,
+      // partials summed in order
       const int kc = std::max(32, (2 * m + KSPLIT_RI - 1) / KSPLIT_RI / 32 * 32);
       std::vector<MixedProblem> kp;
       int tiles = 0;
@@ -2696,7 +2697,7 @@ isdf_status exchange_prepare(isdf_plan_s* plan, isdf_fit_s* fit, int n_occ, bool
         q.A += k0;
         q.B += k0;
         q.tile_start = tiles;
-        tiles += mixed_tiles(o, n);
+        tiles += mixed_tiles_wide(o, n);
         kp.push_back(q);
       }
       fit->kcparts = (int)kp.size();
@@ -3043,8 +3044,8 @@ isdf_status exchange_enqueue_ri(isdf_plan_s* plan, isdf_fit_s* fit, const double
     {  // (K C)^T = -(Z12)(xln)^T: partial products over k ranges, then their ordered sum
       ProfScope ps(plan, ISDF_K_GEMM_EXCHANGE, 2.0 * S * (2.0 * m * (o + n)) + 8.0 * fit->kcparts * o * (double)n,
                    2.0 * o * (double)n * 2.0 * m);
-      if ((st = gemm_mixed_grouped(s, EPI_AXPBY, S, fit->d_kcprobs.as<MixedProblem>(), fit->kcparts, fit->kctiles,
-                                   family_tag(ISDF_K_GEMM_EXCHANGE))) != ISDF_OK)
+      if ((st = gemm_mixed_wide_grouped(s, EPI_AXPBY, S, fit->d_kcprobs.as<MixedProblem>(), fit->kcparts,
+                                        fit->kctiles, family_tag(ISDF_K_GEMM_EXCHANGE))) != ISDF_OK)
         return st;
     }
     if ((st = launch_sum_parts(s, fit->KCpart.as<double>(), fit->kcparts, (int64_t)o * n, KC)) != ISDF_OK)
