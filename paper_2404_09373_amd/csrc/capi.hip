@@ -21,7 +21,9 @@
 #include <fstream>
 #include <functional>
 #include <chrono>
+#include <climits>
 #include <map>
+#include <set>
 #include <sstream>
 #include <memory>
 #include <mutex>
@@ -715,6 +717,63 @@ isdf_status fft_prof(isdf_plan_s* pl, double* z, int batch, const int grid[3], i
   return fft3d(pl->stream, z, batch, grid, sign, nullptr);
 }
 
+// Centres of the balls a window domain is made of: every point of the window
+// of atom A lies within r_max of a translate A + T.  The translates are read
+// back from the points (the nearest one to each point, or a neighbour of it),
+// so that the basis kernel can skip the images of a shell that are farther
+// than r_img + r_max from all of them: those fail the cutoff test at every
+// point of the window.  False (every image kept) for the universal domain,
+// whole-grid windows, or a point with no translate in reach.
+bool window_centres(const HostPlan& hp, const HostDomain& D, std::vector<std::array<double, 3>>& ctr) {
+  ctr.clear();
+  if (D.atom < 0 || !std::isfinite(D.r_max)) return false;
+  const int* g = hp.grid[D.level];
+  if ((int64_t)D.points.size() >= (int64_t)g[0] * g[1] * g[2]) return false;
+  const double* a = hp.lattice;
+  const double* inv = hp.inv;
+  const double A[3] = {hp.xyz[3 * D.atom], hp.xyz[3 * D.atom + 1], hp.xyz[3 * D.atom + 2]};
+  const double r2 = D.r_max * D.r_max * (1.0 + 1e-12) + 1e-12;
+  std::set<std::array<int, 3>> Ts;
+  std::array<int, 3> last{INT_MIN, 0, 0};
+  for (int32_t flat : D.points) {
+    const int i1 = flat % g[0], rem = flat / g[0], i2 = rem % g[1], i3 = rem / g[1];
+    const double f[3] = {(double)i1 / g[0], (double)i2 / g[1], (double)i3 / g[2]};
+    double dr[3];
+    for (int q = 0; q < 3; ++q) dr[q] = f[0] * a[q] + f[1] * a[3 + q] + f[2] * a[6 + q] - A[q];
+    auto within = [&](const std::array<int, 3>& T) {
+      double s2 = 0.0;
+      for (int q = 0; q < 3; ++q) {
+        const double v = dr[q] - (T[0] * a[q] + T[1] * a[3 + q] + T[2] * a[6 + q]);
+        s2 += v * v;
+      }
+      return s2 <= r2;
+    };
+    if (last[0] != INT_MIN && within(last)) continue;  // runs of points share a translate
+    std::array<int, 3> base;
+    for (int i = 0; i < 3; ++i)
+      base[i] = (int)std::lround(dr[0] * inv[i] + dr[1] * inv[3 + i] + dr[2] * inv[6 + i]);
+    bool found = false;
+    for (int d0 = -1; d0 <= 1 && !found; ++d0)
+      for (int d1 = -1; d1 <= 1 && !found; ++d1)
+        for (int d2 = -1; d2 <= 1 && !found; ++d2) {
+          const std::array<int, 3> T{base[0] + d0, base[1] + d1, base[2] + d2};
+          if (within(T)) {
+            Ts.insert(T);
+            last = T;
+            found = true;
+          }
+        }
+    if (!found) return false;
+  }
+  for (const auto& T : Ts) {
+    std::array<double, 3> c;
+    for (int q = 0; q < 3; ++q) c[q] = A[q] + T[0] * a[q] + T[1] * a[3 + q] + T[2] * a[6 + q];
+    ctr.push_back(c);
+  }
+  return true;
+}
+
+
 isdf_status upload_plan(isdf_plan_s* pl) {
   if (pl->uploaded) return ISDF_OK;
   HostPlan& hp = pl->hp;
@@ -749,9 +808,27 @@ isdf_status upload_plan(isdf_plan_s* pl) {
     dd.n_mu = D.n_mu;
     dd.level = D.level;
     dd.colshell_off = (int)cols.size();
+    std::vector<std::array<double, 3>> ctr;
+    const bool masked = window_centres(hp, D, ctr);
     for (int c = 0; c < dd.nG;) {
       int s = hp.f_shell[D.funcs[c]];
-      cols.push_back(ColShell{s, c});
+      const int ni = std::min(hp.img_cnt[s], 64);
+      uint64_t mask = ni >= 64 ? ~0ull : (1ull << ni) - 1;  // every image of the shell
+      if (masked) {
+        mask = 0;
+        const double lim = std::sqrt(hp.ln_inv_tau / hp.shell_alpha[s]) + D.r_max + 1e-6;
+        for (int m = 0; m < ni; ++m) {
+          const double* I = &hp.img_xyz[3 * (size_t)(hp.img_off[s] + m)];
+          for (const auto& q : ctr) {
+            const double dx = I[0] - q[0], dy = I[1] - q[1], dz = I[2] - q[2];
+            if (dx * dx + dy * dy + dz * dz <= lim * lim) {
+              mask |= 1ull << m;
+              break;
+            }
+          }
+        }
+      }
+      cols.push_back(ColShell{s, c, mask});
       c += 2 * hp.shell_l[s] + 1;
     }
     dd.colshell_cnt = (int)cols.size() - dd.colshell_off;

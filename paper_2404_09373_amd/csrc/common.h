@@ -44,6 +44,8 @@ struct ShellDev {                // one periodic shell as the basis kernel sees 
 struct ColShell {                // a shell occupying columns [col, col + ncomp) of a domain
   int32_t shell;
   int32_t col;
+  uint64_t imask;                // bit m: image m of the shell can reach a point of the domain
+                                 // (shells with more than 64 images scan them all)
 };
 
 struct HostPlan {

@@ -57,7 +57,15 @@ basis_eval_kernel(LatticeArg lat, const ShellDev* __restrict__ shells,
     // sqrt3 xy, sqrt3 yz, z^2 - (x^2 + y^2)/2, sqrt3 xz, sqrt3/2 (x^2 - y^2)
     double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     const double* c = img + 3 * (int64_t)sh.img_off;
-    for (int m = 0; m < sh.img_cnt; ++m) {
+    // the images that can reach the domain, in ascending order (the others
+    // fail the cutoff test below at every point of the domain); bits at or
+    // above the shell's image count are never set
+    uint64_t todo = sh.img_cnt >= 64 ? cs.imask : cs.imask & ((1ull << sh.img_cnt) - 1);
+    for (int m = 0; sh.img_cnt > 64 ? m < sh.img_cnt : todo != 0; ++m) {
+      if (sh.img_cnt <= 64) {
+        m = __builtin_ctzll(todo);
+        todo &= todo - 1;
+      }
       const double dx = x - c[3 * m], dy = y - c[3 * m + 1], dz = z - c[3 * m + 2];
       const double r2 = dx * dx + dy * dy + dz * dz;
       if (sh.alpha * r2 <= lat.ln_inv_tau) {
