@@ -354,6 +354,8 @@ struct MixedProblem {
   int64_t plane_p, ldp;
   int32_t p_off;
   const float* E32;  // Hadamard epilogues: E held in FP32 (read instead of E when set)
+  int32_t tile_group;  // row tiles per group of the tile order (0: 8)
+  int32_t pad_g;
 };
 isdf_status gemm_mixed(hipStream_t s, int epi, int splits, const MixedProblem& p, int tag = 4);
 // Grouped problems on the wide-tile kernel (tile_start in units of

@@ -42,14 +42,15 @@ __device__ inline int xcd_tile(int b, int nb) {
   const int x = b % NXCD, q = b / NXCD, per = nb / NXCD, rem = nb % NXCD;
   return (x < rem ? x * (per + 1) : rem * (per + 1) + (x - rem) * per) + q;
 }
-// Tile order: groups of G row tiles, the row index running fastest within a
-// group.  The workgroups that run together on one XCD (consecutive tiles)
-// then share each B column panel G ways and keep the group's A row panels in
-// that XCD's L2 across all columns; a plain row-major order read every B
-// panel once per row tile from HBM (measured: exchange products fetching
-// about 12 times their operand bytes).
-__device__ inline void tile_coords(int local, int tilesM, int tilesN, int* tm, int* tn) {
-  constexpr int G = 8;
+// Tile order: groups of G row tiles (the problem's tile_group, 8 when
+// unset), the row index running fastest within a group.  The workgroups that
+// run together on one XCD (consecutive tiles) then share each B column panel
+// G ways and keep the group's A row panels in that XCD's L2 across all
+// columns; a plain row-major order read every B panel once per row tile from
+// HBM (measured: exchange products fetching about 12 times their operand
+// bytes).
+__device__ inline void tile_coords(int local, int tilesM, int tilesN, int group, int* tm, int* tn) {
+  const int G = group > 0 ? group : 8;
   const int per_group = G * tilesN;
   const int g = local / per_group;
   const int rows = min(G, tilesM - g * G);
@@ -92,7 +93,7 @@ gemm_mixed_kernel(MixedProblem single, const MixedProblem* __restrict__ probs, i
   const MixedProblem* pp = probs ? find_mixed(probs, nprob, tile) : &single;
   const MixedProblem p = *pp;
   int tm, tn;
-  tile_coords(tile - p.tile_start, (p.M + BM - 1) / BM, (p.N + BN - 1) / BN, &tm, &tn);
+  tile_coords(tile - p.tile_start, (p.M + BM - 1) / BM, (p.N + BN - 1) / BN, p.tile_group, &tm, &tn);
   const int m0 = tm * BM, n0 = tn * BN;
   if (n0 >= p.N) return;
   if (p.lower && m0 + BM <= n0) return;
@@ -272,7 +273,7 @@ gemm_mixed_wide_kernel(MixedProblem single, const MixedProblem* __restrict__ pro
   const MixedProblem p = !probs ? single : nprob < 0 ? probs[tile % -nprob] : *find_mixed(probs, nprob, tile);
   const int local = !probs ? tile : nprob < 0 ? tile / -nprob : tile - p.tile_start;
   int tm, tn;
-  tile_coords(local, (p.M + WBM - 1) / WBM, (p.N + WBN - 1) / WBN, &tm, &tn);
+  tile_coords(local, (p.M + WBM - 1) / WBM, (p.N + WBN - 1) / WBN, p.tile_group, &tm, &tn);
   const int m0 = tm * WBM, n0 = tn * WBN;
 
   __shared__ __attribute__((aligned(16))) __bf16 As[2][S][WBM * BK];
