@@ -663,6 +663,7 @@ isdf_status tune_problem(isdf_plan_s* pl, int epi, int tag, const GemmProblem& p
   for (int sh = 0; sh < GEMM_NSHAPE; ++sh) {
     if (p.lower && kShapes[sh].bm != kShapes[sh].bn) continue;
     if (p.bidx && kShapes[sh].mf4 == 2) continue;  // the large tiles take no gathered rows
+    if (!p.transA && !gemm_shape_takes_mfast_a(sh)) continue;
     float tmin = 0.f;
     for (int r = 0; r < pl->tune_reps; ++r) {
       if (rd) ISDF_HIP_TRY(hipMemcpyAsync(p.C, save.p, cbytes, hipMemcpyDeviceToDevice, s));
@@ -1873,11 +1874,12 @@ isdf_status run_coulomb(isdf_plan_s* pl, isdf_fit_s* f, DevBuf* scratch = nullpt
         lp_probs.push_back(p);
       }
       // window rows (gathered potentials): tiles 128 columns wide, and tall
-      // enough for the whole row count up to 128, so that the gathered rows
-      // of V are read once per column tile (they dominate the traffic)
+      // enough for the whole row count up to 128 (64, 80 or 128 rows), so
+      // that the gathered rows of V are read once per column tile (they
+      // dominate the traffic)
       auto metric_shape = [](const GemmProblem& p) {
         if (!p.bidx) return gemm_default_shape(EPI_AXPBY, p.M, p.N, p.K);
-        return p.M <= 64 ? 4 : p.M <= 128 ? 2 : gemm_default_shape(EPI_AXPBY, p.M, p.N, p.K);
+        return p.M <= 64 ? 4 : p.M <= 80 ? 12 : p.M <= 128 ? 2 : gemm_default_shape(EPI_AXPBY, p.M, p.N, p.K);
       };
       for (int shape = 0; shape < GEMM_NSHAPE; ++shape) {
         GemmLaunch gl{l, (int)probs.size(), 0, 0, shape, 0.0, 0.0};
@@ -2070,8 +2072,9 @@ isdf_status run_coulomb(isdf_plan_s* pl, isdf_fit_s* f, DevBuf* scratch = nullpt
         continue;
       }
       ProfScope ps(pl, ISDF_K_GEMM_METRIC, gl.bytes, gl.flops);
+      // every window problem reads F transposed (A k-fastest) and V untransposed
       if ((st = gemm_f64_grouped(s, EPI_AXPBY, d_probs.as<GemmProblem>() + gl.off, gl.cnt,
-                                 gl.tiles, family_tag(ISDF_K_GEMM_METRIC), gl.shape)) != ISDF_OK)
+                                 gl.tiles, family_tag(ISDF_K_GEMM_METRIC), gl.shape, 1, 0)) != ISDF_OK)
         return st;
     }
   }

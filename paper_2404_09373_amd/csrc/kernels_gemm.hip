@@ -79,7 +79,12 @@ __device__ inline int xcd_tile(int b, int nb) {
 template <int BM_, int BN_, int NT>
 struct TileLoader {
   static constexpr int NA = BM_ * BK / NT, NB = BN_ * BK / NT;
-  static_assert(NT % BM_ == 0 && NT % BN_ == 0 && NT % BK == 0 && NA >= 1 && NB >= 1, "tile");
+  // A rows: NT % BM_ == 0 for A stored m-fastest; a tile whose rows do not
+  // divide the threads (80 rows) serves only A stored k-fastest (transA),
+  // which the host enforces
+  static constexpr bool A_MFAST = NT % BM_ == 0;
+  static_assert((A_MFAST || (NT / BK) * NA == BM_) && NT % BN_ == 0 && NT % BK == 0 && NA >= 1 && NB >= 1,
+                "tile");
   double ra[NA], rb[NB];
   const double* pa;  // slot r = 0 of A at the current chunk
   const double* pb;  // slot r = 0 of B (rows gathered: column base only)
@@ -91,13 +96,13 @@ struct TileLoader {
 
   __device__ void init(const GemmProblem& p, int m0, int n0, int tid) {
     if (!p.transA) {  // A(m, k) at m + k lda: m fastest
-      am = tid % BM_;
-      ak = tid / BM_;
+      am = A_MFAST ? tid % BM_ : 0;
+      ak = A_MFAST ? tid / BM_ : 0;
       pa = p.A + (int64_t)(m0 + am) + (int64_t)ak * p.lda;
-      sa = (int64_t)(NT / BM_) * p.lda;
+      sa = (int64_t)(A_MFAST ? NT / BM_ : 0) * p.lda;
       ca = (int64_t)BK * p.lda;
 #pragma unroll
-      for (int r = 0; r < NA; ++r) a_ok[r] = m0 + am < p.M;
+      for (int r = 0; r < NA; ++r) a_ok[r] = A_MFAST && m0 + am < p.M;
     } else {  // A(m, k) at k + m lda: k fastest
       ak = tid % BK;
       am = tid / BK;
@@ -133,7 +138,7 @@ struct TileLoader {
     if (!p.transA) {
 #pragma unroll
       for (int r = 0; r < NA; ++r) {
-        const bool ok = a_ok[r] && (kfull || k0 + ak + (NT / BM_) * r < p.K);
+        const bool ok = a_ok[r] && (kfull || k0 + ak + (A_MFAST ? NT / BM_ : 0) * r < p.K);
         ra[r] = ok ? gld(pa + r * sa) : 0.0;
       }
     } else {
@@ -169,8 +174,10 @@ struct TileLoader {
 
   __device__ void store(const GemmProblem& p, double (*As)[BM_ + PAD], double (*Bs)[BN_ + PAD]) const {
     if (!p.transA) {
+      if constexpr (A_MFAST) {
 #pragma unroll
-      for (int r = 0; r < NA; ++r) As[ak + (NT / BM_) * r][am] = ra[r];
+        for (int r = 0; r < NA; ++r) As[ak + (NT / BM_) * r][am] = ra[r];
+      }
     } else {
 #pragma unroll
       for (int r = 0; r < NA; ++r) As[ak][am + (NT / BK) * r] = ra[r];
@@ -194,6 +201,7 @@ struct TileLoader {
 template <int EPI, int BM_, int BN_, int WM_, int WN_, int MF4>
 constexpr int gemm_min_waves() {
   if (EPI == EPI_AXPBY && WM_ * WN_ == 8) return 4;
+  if (BM_ == 80) return 2;  // its 53 KB of LDS allow two workgroups per CU anyway
   if (EPI == EPI_AXPBY && MF4 == 0 && WM_ * WN_ == 4) return 3;
   if (EPI == EPI_THETA && MF4 == 0 && BM_ == 64 && BN_ == 64 && WM_ * WN_ == 4) return 3;
   return 1;
@@ -648,12 +656,15 @@ gemm_big_kernel(GemmProblem single, const GemmProblem* __restrict__ probs, int n
 // Tile shapes (BM x BN, waves WM x WN, instruction).  Shape 0 suits skinny
 // and grouped window problems; the others trade registers per wave against
 // operand reuse; shapes 5-7 use v_mfma_f64_4x4x4 (4 blocks), which issues
-// about 1.5 times the FP64 rate of the 16x16x4 form on this chip; shape 8 is
-// the large-tile kernel above (gemm_big_kernel).
+// about 1.5 times the FP64 rate of the 16x16x4 form on this chip; shapes 8-11
+// are the large-tile kernel above (gemm_big_kernel); shape 12 (80 rows, one
+// wave per row of waves) serves A stored k-fastest only: the 65-row windows
+// of the Coulomb metric without the 63 empty rows of a 128-row tile.
 const GemmShape kShapes[GEMM_NSHAPE] = {
     {64, 64, 2, 2, 0},  {128, 64, 2, 2, 0},  {128, 128, 2, 4, 0}, {128, 128, 4, 4, 0},
     {64, 128, 2, 2, 0}, {64, 64, 2, 2, 1},   {128, 128, 4, 4, 1}, {128, 64, 2, 2, 1},
-    {128, 64, 2, 2, 2},  {128, 128, 2, 4, 2},  {128, 64, 2, 2, 2},  {128, 128, 2, 2, 2}};
+    {128, 64, 2, 2, 2},  {128, 128, 2, 4, 2},  {128, 64, 2, 2, 2},  {128, 128, 2, 2, 2},
+    {80, 128, 1, 4, 0}};
 
 namespace {
 template <int EPI, int TAG, int SH>
@@ -680,6 +691,9 @@ void launch_shape(hipStream_t s, const GemmProblem& single, const GemmProblem* p
   else if constexpr (SH == 6)
     hipLaunchKernelGGL((gemm_f64_kernel<EPI, TAG, 128, 128, 4, 4, 1>), dim3(tiles), dim3(1024), 0,
                        s, single, probs, nprob);
+  else if constexpr (SH == 12)
+    hipLaunchKernelGGL((gemm_f64_kernel<EPI, TAG, 80, 128, 1, 4>), dim3(tiles), dim3(256), 0, s,
+                       single, probs, nprob);
   else
     hipLaunchKernelGGL((gemm_f64_kernel<EPI, TAG, 128, 64, 2, 2, 1>), dim3(tiles), dim3(256), 0, s,
                        single, probs, nprob);
@@ -725,6 +739,7 @@ void launch_epi(hipStream_t s, int shape, const GemmProblem& single, const GemmP
     case 5: launch_shape<EPI, TAG, 5>(s, single, probs, nprob, tiles); break;
     case 6: launch_shape<EPI, TAG, 6>(s, single, probs, nprob, tiles); break;
     case 7: launch_shape<EPI, TAG, 7>(s, single, probs, nprob, tiles); break;
+    case 12: launch_shape<EPI, TAG, 12>(s, single, probs, nprob, tiles); break;
     default: launch_shape<EPI, TAG, 0>(s, single, probs, nprob, tiles); break;
   }
 }
@@ -774,6 +789,11 @@ int gemm_default_shape(int epi, int M, int N, int K, bool lower) {
   return 0;
 }
 
+bool gemm_shape_takes_mfast_a(int shape) {
+  const GemmShape& g = kShapes[shape < 0 || shape >= GEMM_NSHAPE ? 0 : shape];
+  return (64 * g.wm * g.wn) % g.bm == 0;
+}
+
 int gemm_tiles(int M, int N, int shape, bool lower) {
   const GemmShape& g = kShapes[shape < 0 || shape >= GEMM_NSHAPE ? 0 : shape];
   if (lower && g.bm == g.bn) {  // square lower-triangle problems list only tiles with tm >= tn
@@ -809,6 +829,10 @@ isdf_status gemm_f64(hipStream_t s, int epi, const GemmProblem& p, int tag, int 
     set_error("gemm: the large-tile shapes take no gathered rows");
     return ISDF_E_ARG;
   }
+  if (!p.transA && !gemm_shape_takes_mfast_a(shape)) {
+    set_error("gemm: this tile shape takes A stored k-fastest (transA) only");
+    return ISDF_E_ARG;
+  }
   return launch(s, epi, tag, shape, q, nullptr, 1, gemm_tiles(p.M, p.N, shape, p.lower != 0), p.transA,
                 p.transB);
 }
@@ -818,6 +842,10 @@ isdf_status gemm_f64_grouped(hipStream_t s, int epi, const GemmProblem* d_probs,
   if (nprob <= 0) return ISDF_OK;
   if (shape >= 0 && shape < GEMM_NSHAPE && kShapes[shape].mf4 == 2 && (ta < 0 || tb < 0)) {
     set_error("gemm: a grouped large-tile launch needs the problems' shared operand layouts");
+    return ISDF_E_ARG;
+  }
+  if (shape >= 0 && shape < GEMM_NSHAPE && !gemm_shape_takes_mfast_a(shape) && ta != 1) {
+    set_error("gemm: a grouped launch of this tile shape needs problems with A stored k-fastest");
     return ISDF_E_ARG;
   }
   GemmProblem dummy{};

@@ -72,3 +72,41 @@ def test_d_shell_mixed_precision_within_gate(torch):
     dE = abs(ex - ref.E_x) / s.n_atoms
     print(f"[d_two x6] max|dK| {dK:.2e} |dE|/atom {dE:.2e}")
     assert dE <= 1e-6 and dK <= 1e-6
+
+
+@pytest.mark.parametrize("ratio", [13.0, 16.0])
+def test_window_rows_65_to_80_against_oracle(torch, ratio):
+    """Windows of 65 and 80 fitting functions: their rows of W run on the
+    80-row tile of the grouped metric products (the 384-atom workload's
+    finer windows have 65).  Pivots identical and the windows' F to 1e-7
+    against the oracle; W to 1e-9 relative against the oracle's metric of
+    the same fitting functions.  (At these ratios the universal domain takes
+    more points than its pair products have rank, so its F, and the oracle's
+    W built on the oracle's F, carry that conditioning.)"""
+    s = tiny_system("d_two", n_occ=3, n_mu_ratio=ratio)
+    ref = pipeline.run(s)
+    plan = binding.Plan(s)
+    fit = plan.fit()
+    counts = fit.counts()
+    assert list(counts[1:]) == [int(round(5 * ratio))] * 2
+    for d in range(plan.n_domains):
+        assert np.array_equal(fit.get("points", d), ref.pivots[d])
+    from oracle import basis, isdf
+
+    for d in range(1, plan.n_domains):
+        dom = ref.plan.domains[d]
+        F_ref, _, _ = isdf.fit_functions(basis.domain_values(ref.plan, dom), dom.L.size, ref.pivots[d])
+        F = fit.get("F", d)
+        e = float(np.max(np.abs(F - F_ref)) / np.max(np.abs(F_ref)))
+        assert e <= 1e-7, f"F d={d} {e:.2e}"
+    # the metric stage alone: the oracle's W from the fitting functions the
+    # GPU formed (the same input on both sides), whole and window block
+    from oracle import coulomb
+
+    Wr = coulomb.coulomb_metric(ref.plan, [fit.get("F", d) for d in range(plan.n_domains)])
+    W = fit.get("W")
+    n0 = int(counts[0])
+    e_w = float(np.max(np.abs(W - Wr)) / np.max(np.abs(Wr)))
+    e_b = float(np.max(np.abs(W[n0:, n0:] - Wr[n0:, n0:])) / np.max(np.abs(Wr[n0:, n0:])))
+    print(f"[rows {int(5 * ratio)}] W from the GPU's F rel {e_w:.2e}, window block {e_b:.2e}")
+    assert e_w <= 1e-9 and e_b <= 1e-9
