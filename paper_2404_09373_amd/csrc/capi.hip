@@ -1874,12 +1874,13 @@ isdf_status run_coulomb(isdf_plan_s* pl, isdf_fit_s* f, DevBuf* scratch = nullpt
         lp_probs.push_back(p);
       }
       // window rows (gathered potentials): tiles 128 columns wide, and tall
-      // enough for the whole row count up to 128 (64, 80 or 128 rows), so
+      // enough for the whole row count up to 128 (48, 64, 80 or 128 rows), so
       // that the gathered rows of V are read once per column tile (they
       // dominate the traffic)
       auto metric_shape = [](const GemmProblem& p) {
         if (!p.bidx) return gemm_default_shape(EPI_AXPBY, p.M, p.N, p.K);
-        return p.M <= 64 ? 4 : p.M <= 80 ? 12 : p.M <= 128 ? 2 : gemm_default_shape(EPI_AXPBY, p.M, p.N, p.K);
+        return p.M <= 48 ? 13 : p.M <= 64 ? 4 : p.M <= 80 ? 12 : p.M <= 128 ? 2
+                                                               : gemm_default_shape(EPI_AXPBY, p.M, p.N, p.K);
       };
       for (int shape = 0; shape < GEMM_NSHAPE; ++shape) {
         GemmLaunch gl{l, (int)probs.size(), 0, 0, shape, 0.0, 0.0};

@@ -657,14 +657,15 @@ gemm_big_kernel(GemmProblem single, const GemmProblem* __restrict__ probs, int n
 // and grouped window problems; the others trade registers per wave against
 // operand reuse; shapes 5-7 use v_mfma_f64_4x4x4 (4 blocks), which issues
 // about 1.5 times the FP64 rate of the 16x16x4 form on this chip; shapes 8-11
-// are the large-tile kernel above (gemm_big_kernel); shape 12 (80 rows, one
-// wave per row of waves) serves A stored k-fastest only: the 65-row windows
-// of the Coulomb metric without the 63 empty rows of a 128-row tile.
+// are the large-tile kernel above (gemm_big_kernel); shapes 12 and 13 (80
+// and 48 rows, one row of four waves) serve A stored k-fastest only: the 65-
+// and 45-row windows of the Coulomb metric without the empty rows of a 128-
+// or 64-row tile.
 const GemmShape kShapes[GEMM_NSHAPE] = {
     {64, 64, 2, 2, 0},  {128, 64, 2, 2, 0},  {128, 128, 2, 4, 0}, {128, 128, 4, 4, 0},
     {64, 128, 2, 2, 0}, {64, 64, 2, 2, 1},   {128, 128, 4, 4, 1}, {128, 64, 2, 2, 1},
     {128, 64, 2, 2, 2},  {128, 128, 2, 4, 2},  {128, 64, 2, 2, 2},  {128, 128, 2, 2, 2},
-    {80, 128, 1, 4, 0}};
+    {80, 128, 1, 4, 0}, {48, 128, 1, 4, 0}};
 
 namespace {
 template <int EPI, int TAG, int SH>
@@ -693,6 +694,9 @@ void launch_shape(hipStream_t s, const GemmProblem& single, const GemmProblem* p
                        s, single, probs, nprob);
   else if constexpr (SH == 12)
     hipLaunchKernelGGL((gemm_f64_kernel<EPI, TAG, 80, 128, 1, 4>), dim3(tiles), dim3(256), 0, s,
+                       single, probs, nprob);
+  else if constexpr (SH == 13)
+    hipLaunchKernelGGL((gemm_f64_kernel<EPI, TAG, 48, 128, 1, 4>), dim3(tiles), dim3(256), 0, s,
                        single, probs, nprob);
   else
     hipLaunchKernelGGL((gemm_f64_kernel<EPI, TAG, 128, 64, 2, 2, 1>), dim3(tiles), dim3(256), 0, s,
@@ -740,6 +744,7 @@ void launch_epi(hipStream_t s, int shape, const GemmProblem& single, const GemmP
     case 6: launch_shape<EPI, TAG, 6>(s, single, probs, nprob, tiles); break;
     case 7: launch_shape<EPI, TAG, 7>(s, single, probs, nprob, tiles); break;
     case 12: launch_shape<EPI, TAG, 12>(s, single, probs, nprob, tiles); break;
+    case 13: launch_shape<EPI, TAG, 13>(s, single, probs, nprob, tiles); break;
     default: launch_shape<EPI, TAG, 0>(s, single, probs, nprob, tiles); break;
   }
 }

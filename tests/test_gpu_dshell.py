@@ -74,11 +74,11 @@ def test_d_shell_mixed_precision_within_gate(torch):
     assert dE <= 1e-6 and dK <= 1e-6
 
 
-@pytest.mark.parametrize("ratio", [13.0, 16.0])
-def test_window_rows_65_to_80_against_oracle(torch, ratio):
-    """Windows of 65 and 80 fitting functions: their rows of W run on the
-    80-row tile of the grouped metric products (the 384-atom workload's
-    finer windows have 65).  Pivots identical and the windows' F to 1e-7
+@pytest.mark.parametrize("ratio", [9.0, 13.0, 16.0])
+def test_window_rows_45_to_80_against_oracle(torch, ratio):
+    """Windows of 45, 65 and 80 fitting functions: their rows of W run on the
+    48- and 80-row tiles of the grouped metric products (the 384-atom
+    workload's windows have 45 and 65).  Pivots identical and the windows' F to 1e-7
     against the oracle; W to 1e-9 relative against the oracle's metric of
     the same fitting functions.  (At these ratios the universal domain takes
     more points than its pair products have rank, so its F, and the oracle's
