@@ -664,6 +664,7 @@ isdf_status tune_problem(isdf_plan_s* pl, int epi, int tag, const GemmProblem& p
     if (p.lower && kShapes[sh].bm != kShapes[sh].bn) continue;
     if (p.bidx && kShapes[sh].mf4 == 2) continue;  // the large tiles take no gathered rows
     if (!p.transA && !gemm_shape_takes_mfast_a(sh)) continue;
+    if (p.transB && !gemm_shape_takes_nfast_b(sh)) continue;
     float tmin = 0.f;
     for (int r = 0; r < pl->tune_reps; ++r) {
       if (rd) ISDF_HIP_TRY(hipMemcpyAsync(p.C, save.p, cbytes, hipMemcpyDeviceToDevice, s));
@@ -2371,10 +2372,15 @@ isdf_status do_fit(isdf_plan_s* pl, const int64_t* pinned, const int64_t* cand_i
       std::vector<GemmProblem> grouped;
       int tiles[GEMM_NSHAPE] = {}, first[GEMM_NSHAPE] = {}, cnt[GEMM_NSHAPE] = {};
       double by[GEMM_NSHAPE] = {}, fl[GEMM_NSHAPE] = {};
+      // windows with 65-80 fitting functions take the 80-column tile (one
+      // column tile instead of two); the rest the size rule
+      auto theta_shape = [](const GemmProblem& p) {
+        return p.N > 64 && p.N <= 80 && !p.transA && !p.transB ? 14 : gemm_default_shape(EPI_THETA, p.M, p.N, p.K);
+      };
       for (int shape = 0; shape < GEMM_NSHAPE; ++shape) {
         first[shape] = (int)grouped.size();
         for (GemmProblem p : probs) {
-          if (gemm_default_shape(EPI_THETA, p.M, p.N, p.K) != shape) continue;
+          if (theta_shape(p) != shape) continue;
           p.tile_start = tiles[shape];
           tiles[shape] += gemm_tiles(p.M, p.N, shape);
           by[shape] += gemm_bytes(p);
@@ -2390,8 +2396,9 @@ isdf_status do_fit(isdf_plan_s* pl, const int64_t* pinned, const int64_t* cand_i
           if ((st = gemm_prof(pl, ISDF_K_GEMM_FIT, EPI_THETA, grouped[first[shape]])) != ISDF_OK) return st;
         } else if (cnt[shape] > 1) {
           ProfScope ps(pl, ISDF_K_GEMM_FIT, by[shape], fl[shape]);
+          // every problem: Phi m-fastest (A), pivot rows k-fastest (B)
           if ((st = gemm_f64_grouped(s, EPI_THETA, d_probs.as<GemmProblem>() + first[shape], cnt[shape],
-                                     tiles[shape], family_tag(ISDF_K_GEMM_FIT), shape)) != ISDF_OK)
+                                     tiles[shape], family_tag(ISDF_K_GEMM_FIT), shape, 0, 0)) != ISDF_OK)
             return st;
         }
       }

@@ -126,10 +126,12 @@ struct GemmShape {
   int mf4;  // 1: v_mfma_f64_4x4x4 (4 blocks), 0: v_mfma_f64_16x16x4, 2: the large-tile
             // 4x4x4 kernel (gemm_big_kernel)
 };
-constexpr int GEMM_NSHAPE = 14;
+constexpr int GEMM_NSHAPE = 15;
 extern const GemmShape kShapes[GEMM_NSHAPE];
 // False for tile shapes that take A stored k-fastest (transA) only.
 bool gemm_shape_takes_mfast_a(int shape);
+// False for tile shapes that take B stored k-fastest (not transB) only.
+bool gemm_shape_takes_nfast_b(int shape);
 isdf_status gemm_f64(hipStream_t s, int epi, const GemmProblem& p, int tag = 0, int shape = -1);
 // ta, tb: the operand layouts every problem of the group shares (required by
 // the large-tile shapes, whose layouts are compile-time; -1 otherwise).

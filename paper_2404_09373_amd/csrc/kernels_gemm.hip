@@ -80,10 +80,13 @@ template <int BM_, int BN_, int NT>
 struct TileLoader {
   static constexpr int NA = BM_ * BK / NT, NB = BN_ * BK / NT;
   // A rows: NT % BM_ == 0 for A stored m-fastest; a tile whose rows do not
-  // divide the threads (80 rows) serves only A stored k-fastest (transA),
-  // which the host enforces
+  // divide the threads (80 or 48 rows) serves only A stored k-fastest
+  // (transA), which the host enforces.  Likewise for B: NT % BN_ == 0 for B
+  // stored n-fastest, and an 80-column tile takes B stored k-fastest only.
   static constexpr bool A_MFAST = NT % BM_ == 0;
-  static_assert((A_MFAST || (NT / BK) * NA == BM_) && NT % BN_ == 0 && NT % BK == 0 && NA >= 1 && NB >= 1,
+  static constexpr bool B_NFAST = NT % BN_ == 0;
+  static_assert((A_MFAST || (NT / BK) * NA == BM_) && (B_NFAST || (NT / BK) * NB == BN_) && NT % BK == 0 &&
+                    NA >= 1 && NB >= 1,
                 "tile");
   double ra[NA], rb[NB];
   const double* pa;  // slot r = 0 of A at the current chunk
@@ -122,13 +125,13 @@ struct TileLoader {
       for (int r = 0; r < NB; ++r) b_ok[r] = n0 + bn + (NT / BK) * r < p.N;
       nrow = (p.bidx && bk < p.K) ? gldi(p.bidx + bk) : 0;
     } else {  // B(k, n) at n + k ldb: n fastest
-      bn = tid % BN_;
-      bk = tid / BN_;
+      bn = B_NFAST ? tid % BN_ : 0;
+      bk = B_NFAST ? tid / BN_ : 0;
       pb = p.B + (int64_t)(n0 + bn) + (int64_t)bk * p.ldb;
-      sb = (int64_t)(NT / BN_) * p.ldb;
+      sb = (int64_t)(B_NFAST ? NT / BN_ : 0) * p.ldb;
       cb = (int64_t)BK * p.ldb;
 #pragma unroll
-      for (int r = 0; r < NB; ++r) b_ok[r] = n0 + bn < p.N;
+      for (int r = 0; r < NB; ++r) b_ok[r] = B_NFAST && n0 + bn < p.N;
     }
   }
 
@@ -161,7 +164,7 @@ struct TileLoader {
     } else {
 #pragma unroll
       for (int r = 0; r < NB; ++r) {
-        const bool ok = b_ok[r] && (kfull || k0 + bk + (NT / BN_) * r < p.K);
+        const bool ok = b_ok[r] && (kfull || k0 + bk + (B_NFAST ? NT / BN_ : 0) * r < p.K);
         rb[r] = ok ? gld(pb + r * sb) : 0.0;
       }
     }
@@ -186,8 +189,10 @@ struct TileLoader {
 #pragma unroll
       for (int r = 0; r < NB; ++r) Bs[bk][bn + (NT / BK) * r] = rb[r];
     } else {
+      if constexpr (B_NFAST) {
 #pragma unroll
-      for (int r = 0; r < NB; ++r) Bs[bk + (NT / BN_) * r][bn] = rb[r];
+        for (int r = 0; r < NB; ++r) Bs[bk + (NT / BN_) * r][bn] = rb[r];
+      }
     }
   }
 };
@@ -204,6 +209,7 @@ constexpr int gemm_min_waves() {
   if (BM_ == 80) return 2;  // its 53 KB of LDS allow two workgroups per CU anyway
   if (EPI == EPI_AXPBY && MF4 == 0 && WM_ * WN_ == 4) return 3;
   if (EPI == EPI_THETA && MF4 == 0 && BM_ == 64 && BN_ == 64 && WM_ * WN_ == 4) return 3;
+  if (EPI == EPI_THETA && BN_ == 80) return 3;
   return 1;
 }
 }  // namespace
@@ -660,12 +666,14 @@ gemm_big_kernel(GemmProblem single, const GemmProblem* __restrict__ probs, int n
 // are the large-tile kernel above (gemm_big_kernel); shapes 12 and 13 (80
 // and 48 rows, one row of four waves) serve A stored k-fastest only: the 65-
 // and 45-row windows of the Coulomb metric without the empty rows of a 128-
-// or 64-row tile.
+// or 64-row tile; shape 14 (80 columns, one column of four waves) serves B
+// stored k-fastest only: the Theta of windows with 65-80 fitting functions
+// in one column tile instead of two.
 const GemmShape kShapes[GEMM_NSHAPE] = {
     {64, 64, 2, 2, 0},  {128, 64, 2, 2, 0},  {128, 128, 2, 4, 0}, {128, 128, 4, 4, 0},
     {64, 128, 2, 2, 0}, {64, 64, 2, 2, 1},   {128, 128, 4, 4, 1}, {128, 64, 2, 2, 1},
     {128, 64, 2, 2, 2},  {128, 128, 2, 4, 2},  {128, 64, 2, 2, 2},  {128, 128, 2, 2, 2},
-    {80, 128, 1, 4, 0}, {48, 128, 1, 4, 0}};
+    {80, 128, 1, 4, 0}, {48, 128, 1, 4, 0}, {64, 80, 4, 1, 0}};
 
 namespace {
 template <int EPI, int TAG, int SH>
@@ -697,6 +705,9 @@ void launch_shape(hipStream_t s, const GemmProblem& single, const GemmProblem* p
                        single, probs, nprob);
   else if constexpr (SH == 13)
     hipLaunchKernelGGL((gemm_f64_kernel<EPI, TAG, 48, 128, 1, 4>), dim3(tiles), dim3(256), 0, s,
+                       single, probs, nprob);
+  else if constexpr (SH == 14)
+    hipLaunchKernelGGL((gemm_f64_kernel<EPI, TAG, 64, 80, 4, 1>), dim3(tiles), dim3(256), 0, s,
                        single, probs, nprob);
   else
     hipLaunchKernelGGL((gemm_f64_kernel<EPI, TAG, 128, 64, 2, 2, 1>), dim3(tiles), dim3(256), 0, s,
@@ -745,6 +756,7 @@ void launch_epi(hipStream_t s, int shape, const GemmProblem& single, const GemmP
     case 7: launch_shape<EPI, TAG, 7>(s, single, probs, nprob, tiles); break;
     case 12: launch_shape<EPI, TAG, 12>(s, single, probs, nprob, tiles); break;
     case 13: launch_shape<EPI, TAG, 13>(s, single, probs, nprob, tiles); break;
+    case 14: launch_shape<EPI, TAG, 14>(s, single, probs, nprob, tiles); break;
     default: launch_shape<EPI, TAG, 0>(s, single, probs, nprob, tiles); break;
   }
 }
@@ -799,6 +811,11 @@ bool gemm_shape_takes_mfast_a(int shape) {
   return (64 * g.wm * g.wn) % g.bm == 0;
 }
 
+bool gemm_shape_takes_nfast_b(int shape) {
+  const GemmShape& g = kShapes[shape < 0 || shape >= GEMM_NSHAPE ? 0 : shape];
+  return (64 * g.wm * g.wn) % g.bn == 0;
+}
+
 int gemm_tiles(int M, int N, int shape, bool lower) {
   const GemmShape& g = kShapes[shape < 0 || shape >= GEMM_NSHAPE ? 0 : shape];
   if (lower && g.bm == g.bn) {  // square lower-triangle problems list only tiles with tm >= tn
@@ -838,6 +855,10 @@ isdf_status gemm_f64(hipStream_t s, int epi, const GemmProblem& p, int tag, int 
     set_error("gemm: this tile shape takes A stored k-fastest (transA) only");
     return ISDF_E_ARG;
   }
+  if (p.transB && !gemm_shape_takes_nfast_b(shape)) {
+    set_error("gemm: this tile shape takes B stored k-fastest only");
+    return ISDF_E_ARG;
+  }
   return launch(s, epi, tag, shape, q, nullptr, 1, gemm_tiles(p.M, p.N, shape, p.lower != 0), p.transA,
                 p.transB);
 }
@@ -851,6 +872,10 @@ isdf_status gemm_f64_grouped(hipStream_t s, int epi, const GemmProblem* d_probs,
   }
   if (shape >= 0 && shape < GEMM_NSHAPE && !gemm_shape_takes_mfast_a(shape) && ta != 1) {
     set_error("gemm: a grouped launch of this tile shape needs problems with A stored k-fastest");
+    return ISDF_E_ARG;
+  }
+  if (shape >= 0 && shape < GEMM_NSHAPE && !gemm_shape_takes_nfast_b(shape) && tb != 0) {
+    set_error("gemm: a grouped launch of this tile shape needs problems with B stored k-fastest");
     return ISDF_E_ARG;
   }
   GemmProblem dummy{};

@@ -77,10 +77,11 @@ def test_d_shell_mixed_precision_within_gate(torch):
 @pytest.mark.parametrize("ratio", [9.0, 13.0, 16.0])
 def test_window_rows_45_to_80_against_oracle(torch, ratio):
     """Windows of 45, 65 and 80 fitting functions: their rows of W run on the
-    48- and 80-row tiles of the grouped metric products (the 384-atom
-    workload's windows have 45 and 65).  Pivots identical and the windows' F to 1e-7
-    against the oracle; W to 1e-9 relative against the oracle's metric of
-    the same fitting functions.  (At these ratios the universal domain takes
+    48- and 80-row tiles of the grouped metric products, and the Theta of
+    the 65- and 80-function windows on the 80-column tile (the 384-atom
+    workload's windows have 45 and 65).  Pivots identical, the windows'
+    Theta to 1e-11 and F to 1e-7 against the oracle; W to 1e-9 relative
+    against the oracle's metric of the same fitting functions.  (At these ratios the universal domain takes
     more points than its pair products have rank, so its F, and the oracle's
     W built on the oracle's F, carry that conditioning.)"""
     s = tiny_system("d_two", n_occ=3, n_mu_ratio=ratio)
@@ -95,7 +96,10 @@ def test_window_rows_45_to_80_against_oracle(torch, ratio):
 
     for d in range(1, plan.n_domains):
         dom = ref.plan.domains[d]
-        F_ref, _, _ = isdf.fit_functions(basis.domain_values(ref.plan, dom), dom.L.size, ref.pivots[d])
+        F_ref, Theta_ref, _ = isdf.fit_functions(basis.domain_values(ref.plan, dom), dom.L.size, ref.pivots[d])
+        th = fit.get("theta", d)  # 65-80 columns: the 80-column Theta tile
+        e_th = float(np.max(np.abs(th - Theta_ref)) / np.max(np.abs(Theta_ref)))
+        assert e_th <= 1e-11, f"Theta d={d} {e_th:.2e}"
         F = fit.get("F", d)
         e = float(np.max(np.abs(F - F_ref)) / np.max(np.abs(F_ref)))
         assert e <= 1e-7, f"F d={d} {e:.2e}"
