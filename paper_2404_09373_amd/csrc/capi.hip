@@ -2373,9 +2373,12 @@ isdf_status do_fit(isdf_plan_s* pl, const int64_t* pinned, const int64_t* cand_i
       int tiles[GEMM_NSHAPE] = {}, first[GEMM_NSHAPE] = {}, cnt[GEMM_NSHAPE] = {};
       double by[GEMM_NSHAPE] = {}, fl[GEMM_NSHAPE] = {};
       // windows with 65-80 fitting functions take the 80-column tile (one
-      // column tile instead of two); the rest the size rule
+      // column tile instead of two), those with 33-48 the 48-column one; the
+      // rest the size rule
       auto theta_shape = [](const GemmProblem& p) {
-        return p.N > 64 && p.N <= 80 && !p.transA && !p.transB ? 14 : gemm_default_shape(EPI_THETA, p.M, p.N, p.K);
+        if (!p.transA && !p.transB && p.N > 64 && p.N <= 80) return 14;
+        if (!p.transA && !p.transB && p.N > 32 && p.N <= 48) return 15;
+        return gemm_default_shape(EPI_THETA, p.M, p.N, p.K);
       };
       for (int shape = 0; shape < GEMM_NSHAPE; ++shape) {
         first[shape] = (int)grouped.size();

@@ -126,7 +126,7 @@ struct GemmShape {
   int mf4;  // 1: v_mfma_f64_4x4x4 (4 blocks), 0: v_mfma_f64_16x16x4, 2: the large-tile
             // 4x4x4 kernel (gemm_big_kernel)
 };
-constexpr int GEMM_NSHAPE = 15;
+constexpr int GEMM_NSHAPE = 16;
 extern const GemmShape kShapes[GEMM_NSHAPE];
 // False for tile shapes that take A stored k-fastest (transA) only.
 bool gemm_shape_takes_mfast_a(int shape);

@@ -209,7 +209,7 @@ constexpr int gemm_min_waves() {
   if (BM_ == 80) return 2;  // its 53 KB of LDS allow two workgroups per CU anyway
   if (EPI == EPI_AXPBY && MF4 == 0 && WM_ * WN_ == 4) return 3;
   if (EPI == EPI_THETA && MF4 == 0 && BM_ == 64 && BN_ == 64 && WM_ * WN_ == 4) return 3;
-  if (EPI == EPI_THETA && BN_ == 80) return 3;
+  if (EPI == EPI_THETA && (BN_ == 80 || BN_ == 48)) return 3;
   return 1;
 }
 }  // namespace
@@ -666,14 +666,15 @@ gemm_big_kernel(GemmProblem single, const GemmProblem* __restrict__ probs, int n
 // are the large-tile kernel above (gemm_big_kernel); shapes 12 and 13 (80
 // and 48 rows, one row of four waves) serve A stored k-fastest only: the 65-
 // and 45-row windows of the Coulomb metric without the empty rows of a 128-
-// or 64-row tile; shape 14 (80 columns, one column of four waves) serves B
-// stored k-fastest only: the Theta of windows with 65-80 fitting functions
-// in one column tile instead of two.
+// or 64-row tile; shapes 14 and 15 (80 and 48 columns, one column of four
+// waves) serve B stored k-fastest only: the Theta of windows with 65-80
+// fitting functions in one column tile instead of two, and of windows with
+// 33-48 in a 48-column tile.
 const GemmShape kShapes[GEMM_NSHAPE] = {
     {64, 64, 2, 2, 0},  {128, 64, 2, 2, 0},  {128, 128, 2, 4, 0}, {128, 128, 4, 4, 0},
     {64, 128, 2, 2, 0}, {64, 64, 2, 2, 1},   {128, 128, 4, 4, 1}, {128, 64, 2, 2, 1},
     {128, 64, 2, 2, 2},  {128, 128, 2, 4, 2},  {128, 64, 2, 2, 2},  {128, 128, 2, 2, 2},
-    {80, 128, 1, 4, 0}, {48, 128, 1, 4, 0}, {64, 80, 4, 1, 0}};
+    {80, 128, 1, 4, 0}, {48, 128, 1, 4, 0}, {64, 80, 4, 1, 0}, {64, 48, 4, 1, 0}};
 
 namespace {
 template <int EPI, int TAG, int SH>
@@ -708,6 +709,9 @@ void launch_shape(hipStream_t s, const GemmProblem& single, const GemmProblem* p
                        single, probs, nprob);
   else if constexpr (SH == 14)
     hipLaunchKernelGGL((gemm_f64_kernel<EPI, TAG, 64, 80, 4, 1>), dim3(tiles), dim3(256), 0, s,
+                       single, probs, nprob);
+  else if constexpr (SH == 15)
+    hipLaunchKernelGGL((gemm_f64_kernel<EPI, TAG, 64, 48, 4, 1>), dim3(tiles), dim3(256), 0, s,
                        single, probs, nprob);
   else
     hipLaunchKernelGGL((gemm_f64_kernel<EPI, TAG, 128, 64, 2, 2, 1>), dim3(tiles), dim3(256), 0, s,
@@ -757,6 +761,7 @@ void launch_epi(hipStream_t s, int shape, const GemmProblem& single, const GemmP
     case 12: launch_shape<EPI, TAG, 12>(s, single, probs, nprob, tiles); break;
     case 13: launch_shape<EPI, TAG, 13>(s, single, probs, nprob, tiles); break;
     case 14: launch_shape<EPI, TAG, 14>(s, single, probs, nprob, tiles); break;
+    case 15: launch_shape<EPI, TAG, 15>(s, single, probs, nprob, tiles); break;
     default: launch_shape<EPI, TAG, 0>(s, single, probs, nprob, tiles); break;
   }
 }

@@ -77,8 +77,8 @@ def test_d_shell_mixed_precision_within_gate(torch):
 @pytest.mark.parametrize("ratio", [9.0, 13.0, 16.0])
 def test_window_rows_45_to_80_against_oracle(torch, ratio):
     """Windows of 45, 65 and 80 fitting functions: their rows of W run on the
-    48- and 80-row tiles of the grouped metric products, and the Theta of
-    the 65- and 80-function windows on the 80-column tile (the 384-atom
+    48- and 80-row tiles of the grouped metric products, and their Theta on
+    the 48- and 80-column tiles (the 384-atom
     workload's windows have 45 and 65).  Pivots identical, the windows'
     Theta to 1e-11 and F to 1e-7 against the oracle; W to 1e-9 relative
     against the oracle's metric of the same fitting functions.  (At these ratios the universal domain takes
@@ -97,7 +97,7 @@ def test_window_rows_45_to_80_against_oracle(torch, ratio):
     for d in range(1, plan.n_domains):
         dom = ref.plan.domains[d]
         F_ref, Theta_ref, _ = isdf.fit_functions(basis.domain_values(ref.plan, dom), dom.L.size, ref.pivots[d])
-        th = fit.get("theta", d)  # 65-80 columns: the 80-column Theta tile
+        th = fit.get("theta", d)  # 45 / 65-80 columns: the 48- / 80-column Theta tiles
         e_th = float(np.max(np.abs(th - Theta_ref)) / np.max(np.abs(Theta_ref)))
         assert e_th <= 1e-11, f"Theta d={d} {e_th:.2e}"
         F = fit.get("F", d)
